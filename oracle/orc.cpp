@@ -1,0 +1,711 @@
+// orc.cpp -- CPU oracle of the per-frame measure engine.
+//
+// TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+// CPU-baseline leg of the benchmark; never by the product path.  Plain scalar
+// C++17, single-threaded, no intrinsics, built with -O2 -ffp-contract=off so
+// every floating-point expression is evaluated exactly as written.  It shares
+// no code, header, table or helper with the GPU library.
+//
+// What it computes follows Sec. III of the paper (Fassold, arXiv 2502.09202):
+//   - measures AMM, SWR, ACT from a motion field and NCC (Sec. III.A);
+//   - ACT of consecutive frames always, everything else sparse (Sec. III.A);
+//   - measures computed on demand and cached (Sec. III.A, last paragraph);
+//   - shot boundaries by fast check + deep check (Sec. III.B);
+//   - v0, v1, v2 on upper/lower fields, beta = v1/v2 (Sec. III.C);
+//   - dynamic keyframes by accumulated ACT (Sec. III.D).
+// Where the paper is silent the readings are the ones recorded in the design
+// notes (block SAD full search in place of dense optical flow, the 2x2
+// rounding pyramid, the fast/deep-check rules, the sampling vote, ...); each
+// one is stated at the place it is used below.
+#include "orc.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+struct Plane {
+    int w = 0, h = 0;
+    std::vector<int32_t> px;
+    int32_t at(int x, int y) const { return px[(size_t)y * (size_t)w + (size_t)x]; }
+};
+
+// Pyramid geometry.  W_l = floor(W_{l-1}/2).  Working level L is the first
+// level no wider than wmax; fields (alternate rows, Sec. III.C) are taken at
+// Lf = max(0, L - lf_offset); Lcap is the coarsest level that still holds a
+// 2 x 2 grid of blocks (used by the long-range pairs of the deep check).
+struct Geometry {
+    int W = 0, H = 0, L = -1, Lcap = -1, Lf = 0, wf = 0, hf = 0;
+    std::vector<int> wl, hl;
+};
+
+bool make_geometry(int W, int H, const orc_params& p, Geometry& g) {
+    if (W <= 0 || H <= 0 || p.block != 8 || p.wmax < 16) return false;
+    g = Geometry();
+    g.W = W; g.H = H;
+    for (int w = W, h = H; w > 0 && h > 0; w /= 2, h /= 2) { g.wl.push_back(w); g.hl.push_back(h); }
+    const int nl = (int)g.wl.size();
+    for (int l = 0; l < nl; ++l) if (g.wl[l] <= p.wmax) { g.L = l; break; }
+    if (g.L < 0) return false;
+    if (g.wl[g.L] / p.block < 2 || g.hl[g.L] / p.block < 2) return false;
+    g.Lcap = g.L;
+    for (int l = g.L + 1; l < nl; ++l) {
+        if (g.wl[l] / p.block >= 2 && g.hl[l] / p.block >= 2) g.Lcap = l; else break;
+    }
+    g.Lf = std::max(0, g.L - p.lf_offset);
+    g.wf = W; g.hf = H / 2;
+    for (int l = 1; l <= g.Lf; ++l) { g.wf /= 2; g.hf /= 2; }
+    if (g.wf < p.block || g.hf < p.block) return false;
+    return true;
+}
+
+// Level used by a deep-check pair at distance K: L + ceil(log2 K), capped.
+int ceil_log2(int k) { int c = 0; while ((1 << c) < k) ++c; return c; }
+int deep_level(const Geometry& g, int K) { return std::min(g.L + ceil_log2(K), g.Lcap); }
+
+// 2 x 2 box average, rounding half up, applied once per level; a trailing odd
+// row or column is dropped.
+Plane downscale(const Plane& s) {
+    Plane d;
+    d.w = s.w / 2; d.h = s.h / 2;
+    d.px.assign((size_t)d.w * d.h, 0);
+    for (int y = 0; y < d.h; ++y)
+        for (int x = 0; x < d.w; ++x) {
+            int32_t sum = s.at(2 * x, 2 * y) + s.at(2 * x + 1, 2 * y) +
+                          s.at(2 * x, 2 * y + 1) + s.at(2 * x + 1, 2 * y + 1);
+            d.px[(size_t)y * d.w + x] = (sum + 2) >> 2;
+        }
+    return d;
+}
+
+bool load_frame(const void* base, int W, int H, int64_t pitch, int bits, Plane& out) {
+    out.w = W; out.h = H;
+    out.px.assign((size_t)W * H, 0);
+    const unsigned char* b = (const unsigned char*)base;
+    for (int y = 0; y < H; ++y) {
+        const unsigned char* row = b + (size_t)y * (size_t)pitch;
+        for (int x = 0; x < W; ++x) {
+            int32_t v;
+            if (bits == 8) v = row[x];
+            else { uint16_t u; std::memcpy(&u, row + 2 * (size_t)x, 2); v = u; if (v > 1023) return false; }
+            out.px[(size_t)y * W + x] = v;
+        }
+    }
+    return true;
+}
+
+// Upper field = even rows, lower field = odd rows (Sec. III.C; the
+// introduction's "half width" is read as half height).
+Plane field_of(const Plane& f, int parity) {
+    Plane o;
+    o.w = f.w; o.h = f.h / 2;
+    o.px.resize((size_t)o.w * o.h);
+    for (int y = 0; y < o.h; ++y)
+        for (int x = 0; x < o.w; ++x) o.px[(size_t)y * o.w + x] = f.at(x, 2 * y + parity);
+    return o;
+}
+
+struct FrameLevels {
+    std::vector<Plane> lv;   // levels L..Lcap
+    Plane U, D;              // fields at Lf
+};
+
+void build_levels(const Plane& full, const Geometry& g, FrameLevels& fl) {
+    fl.lv.clear();
+    Plane cur = full;
+    if (g.L == 0) fl.lv.push_back(cur);
+    for (int l = 1; l <= g.Lcap; ++l) {
+        cur = downscale(cur);
+        if (l >= g.L) fl.lv.push_back(cur);
+    }
+    fl.U = field_of(full, 0);
+    fl.D = field_of(full, 1);
+    for (int l = 1; l <= g.Lf; ++l) { fl.U = downscale(fl.U); fl.D = downscale(fl.D); }
+}
+
+// Candidate order for ties: by squared length, then dy, then dx.
+std::vector<int> candidate_ranks(int R) {
+    const int n = 2 * R + 1;
+    std::vector<std::tuple<int, int, int>> c;
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) c.emplace_back(dx * dx + dy * dy, dy, dx);
+    std::sort(c.begin(), c.end());
+    std::vector<int> rank((size_t)n * n);
+    for (size_t i = 0; i < c.size(); ++i) {
+        int dy = std::get<1>(c[i]), dx = std::get<2>(c[i]);
+        rank[(size_t)(dy + R) * n + (dx + R)] = (int)i;
+    }
+    return rank;
+}
+
+int64_t isqrt64(int64_t v) {
+    int64_t r = (int64_t)std::sqrt((double)v);
+    while (r > 0 && r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+struct PairOut {
+    int nbx = 0, nby = 0;
+    std::vector<int8_t> mv;
+    std::vector<int32_t> sad;
+    int64_t sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0, n = 0, a = 0, B = 0;
+    bool is_static = false;
+    double ncc = 0, swr = 0, amm = 0, act = 0;
+    bool ok = true;
+};
+
+// NCC, SWR = 1 - NCC, AMM, ACT from the exact integers.  The covariance terms
+// are formed exactly in 64-bit integers; NCC = cov / sqrt(vx * vy) in IEEE
+// double with the operations in this order; the zero-variance cases follow the
+// reading: both constant -> 1, one constant -> 0; the result is clamped to [-1, 1].
+// ACT is the geometric mean of (AMM + a0) and SWR.
+bool finish(int64_t sx, int64_t sy, int64_t sxx, int64_t syy, int64_t sxy, int64_t n,
+            int64_t a, int64_t B, double a0, double out[4]) {
+    if (n <= 0 || B <= 0) return false;
+    int64_t t1, t2, cov, vx, vy;
+    if (__builtin_mul_overflow(n, sxy, &t1) || __builtin_mul_overflow(sx, sy, &t2) ||
+        __builtin_sub_overflow(t1, t2, &cov)) return false;
+    if (__builtin_mul_overflow(n, sxx, &t1) || __builtin_mul_overflow(sx, sx, &t2) ||
+        __builtin_sub_overflow(t1, t2, &vx)) return false;
+    if (__builtin_mul_overflow(n, syy, &t1) || __builtin_mul_overflow(sy, sy, &t2) ||
+        __builtin_sub_overflow(t1, t2, &vy)) return false;
+    double ncc;
+    if (vx == 0 && vy == 0) ncc = 1.0;
+    else if (vx == 0 || vy == 0) ncc = 0.0;
+    else {
+        double x3 = (double)vx * (double)vy;
+        double x4 = std::sqrt(x3);
+        double c = (double)cov / x4;
+        ncc = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    }
+    double swr = 1.0 - ncc;
+    double amm = (double)a / (256.0 * (double)B);
+    double act = std::sqrt((amm + a0) * swr);
+    out[0] = ncc; out[1] = swr; out[2] = amm; out[3] = act;
+    return true;
+}
+
+// The pair measure M(I -> J): for every whole 8 x 8 block of I, the
+// displacement d in [-R, R]^2 minimising the SAD against J (J read with
+// clamp-to-edge), ties broken by the candidate order; J warped block-wise by
+// those vectors; the exact moments of I against warped J over the covered
+// pixels; A = sum over blocks of floor(256 |d|).
+void pair_measure(const Plane& I, const Plane& J, const orc_params& p, bool zero_mv, PairOut& o) {
+    const int w = I.w, h = I.h, R = p.radius;
+    o = PairOut();
+    o.nbx = w / 8; o.nby = h / 8; o.B = (int64_t)o.nbx * o.nby;
+    if (o.B <= 0 || J.w != w || J.h != h || R < 0) { o.ok = false; return; }
+    const std::vector<int> rank = candidate_ranks(R);
+    const int nc = 2 * R + 1;
+    auto cJ = [&](int x, int y) {
+        x = std::min(std::max(x, 0), w - 1);
+        y = std::min(std::max(y, 0), h - 1);
+        return J.at(x, y);
+    };
+    o.mv.assign((size_t)o.B * 2, 0);
+    o.sad.assign((size_t)o.B, 0);
+    for (int by = 0; by < o.nby; ++by)
+        for (int bx = 0; bx < o.nbx; ++bx) {
+            const int x0 = 8 * bx, y0 = 8 * by;
+            int best_sad = -1, best_rank = 0, bdx = 0, bdy = 0;
+            for (int dy = -R; dy <= R; ++dy)
+                for (int dx = -R; dx <= R; ++dx) {
+                    if (zero_mv && (dx != 0 || dy != 0)) continue;
+                    int s = 0;
+                    for (int j = 0; j < 8; ++j)
+                        for (int i = 0; i < 8; ++i)
+                            s += std::abs(I.at(x0 + i, y0 + j) - cJ(x0 + i + dx, y0 + j + dy));
+                    const int r = rank[(size_t)(dy + R) * nc + (dx + R)];
+                    if (best_sad < 0 || s < best_sad || (s == best_sad && r < best_rank)) {
+                        best_sad = s; best_rank = r; bdx = dx; bdy = dy;
+                    }
+                }
+            const size_t b = (size_t)by * o.nbx + bx;
+            o.mv[2 * b] = (int8_t)bdx; o.mv[2 * b + 1] = (int8_t)bdy;
+            o.sad[b] = best_sad;
+            for (int j = 0; j < 8; ++j)
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t x = I.at(x0 + i, y0 + j);
+                    const int64_t y = cJ(x0 + i + bdx, y0 + j + bdy);
+                    o.sx += x; o.sy += y; o.sxx += x * x; o.syy += y * y; o.sxy += x * y;
+                }
+            o.a += isqrt64(65536 * (int64_t)(bdx * bdx + bdy * bdy));
+        }
+    o.n = 64 * o.B;
+    o.is_static = o.a < (int64_t)p.a_static_fx * o.B;
+    double f[4];
+    if (!finish(o.sx, o.sy, o.sxx, o.syy, o.sxy, o.n, o.a, o.B, p.a0, f)) { o.ok = false; return; }
+    o.ncc = f[0]; o.swr = f[1]; o.amm = f[2]; o.act = f[3];
+}
+
+struct Meas { double act = 0, swr = 0; };
+
+// Source of the pair measures used by the sequential pass.
+struct Provider {
+    virtual ~Provider() {}
+    virtual bool consec(int t, orc_frame_rec& r) = 0;        // pair t -> t+1
+    virtual bool field(int t, int which, Meas& m) = 0;        // v0, v1, v2
+    virtual bool deepF(int t, int K, Meas& m) = 0;            // t -> t+K
+    virtual bool deepP(int t, int K, int Kp, Meas& m) = 0;    // t -> t-Kp at the level of K
+    virtual void evict_before(int) {}
+    std::vector<orc_measure_key> log;
+};
+
+// Sampling-structure vote over the analysed frames of one shot (Sec. III.C).
+struct Analysis {
+    bool open = true;
+    int n = 0, nci = 0, s = 0, result = 0, phase = -1;
+    int cm[5] = {0, 0, 0, 0, 0}, np[5] = {0, 0, 0, 0, 0};
+    double sum1 = 0.0, sum2 = 0.0;
+
+    // Two readings of "v0 is not near zero" (Sec. III.C):
+    //  - against the smaller inter-frame field activity: the interlace test.
+    //    In interlaced content v0 and one of v1/v2 span half a frame interval,
+    //    so v0 is comparable to min(v1, v2) even when the other pair moves
+    //    too far for the search range; in progressive content both v1 and v2
+    //    span a full interval and v0 none.
+    //  - against the larger one: the 3:2 pulldown cadence.  Inside a pulldown
+    //    unit one of v1/v2 can itself join two fields of the same film frame,
+    //    so only the larger one is a reliable scale; the frames whose two
+    //    fields come from different film frames are then the combed ones.
+    void add(int ph, double v0, double v1, double v2, const orc_params& p) {
+        const bool comb_min = v0 > p.tau_c * std::min(v1, v2);
+        const bool comb_max = v0 > p.tau_c * std::max(v1, v2);
+        ++n; ++np[ph];
+        if (comb_min) ++nci;
+        if (comb_max) ++cm[ph];
+        if (v1 > v2) ++s; else if (v1 < v2) --s;
+        sum1 = sum1 + v1; sum2 = sum2 + v2;
+    }
+    void decide(const orc_params& p) {
+        open = false;
+        phase = -1;
+        if (n == 0) { result = 0; return; }
+        if (n >= 10) {
+            // 3:2 pulldown: the combed frames sit at two neighbouring positions
+            // of the 5-frame pulldown unit.
+            int mask = 0, cnt = 0;
+            for (int q = 0; q < 5; ++q) if (2 * cm[q] > np[q]) { mask |= 1 << q; ++cnt; }
+            if (cnt == 2) {
+                for (int q = 0; q < 5; ++q) {
+                    if (mask != ((1 << q) | (1 << ((q + 1) % 5)))) continue;
+                    int agree = 0;
+                    for (int r = 0; r < 5; ++r) agree += ((mask >> r) & 1) ? cm[r] : np[r] - cm[r];
+                    if ((double)agree >= p.pd_agree * (double)n) { result = 4; phase = q; return; }
+                }
+            }
+        }
+        bool inter;
+        if ((double)nci <= p.eps * (double)n) inter = false;
+        else if ((double)nci >= (1.0 - p.eps) * (double)n) inter = true;
+        else inter = 2 * nci > n;
+        if (!inter) { result = 1; return; }
+        // Field order from beta = v1 / v2: > 1 upper field first, < 1 lower first.
+        if (s > 0) result = 2;
+        else if (s < 0) result = 3;
+        else result = (sum1 >= sum2) ? 2 : 3;
+    }
+};
+
+// Deep check at frame t (Sec. III.B): a K-frame transition after t is accepted
+// when the activity from t to t+K clearly exceeds the activity from t back to
+// its predecessor at the same distance; K and K+1 must both verify (a single
+// odd frame such as a flash verifies only one); among the candidates the
+// first whose dissimilarity reaches gamma of the largest one is taken.
+bool deep_check(int t, int T, int shot_start, double a_t, double s_t, Provider& pv,
+                const orc_params& p, int& Kstar) {
+    Kstar = 0;
+    const int Kn = std::min(p.k_max + 1, T - 1 - t);
+    std::vector<char> V((size_t)p.k_max + 3, 1);
+    std::vector<double> S((size_t)p.k_max + 3, 0.0);
+    for (int K = 1; K <= Kn; ++K) {
+        Meas f;
+        if (K == 1) { f.act = a_t; f.swr = s_t; }
+        else if (!pv.deepF(t, K, f)) return false;
+        const int Kp = std::min(K, t - shot_start);
+        double pa = 0.0;
+        if (Kp > 0) { Meas b; if (!pv.deepP(t, K, Kp, b)) return false; pa = b.act; }
+        V[K] = f.act > p.rho_d * pa + p.theta_d;
+        S[K] = f.swr;
+    }
+    const int Kc = std::min(p.k_max, Kn);
+    bool any = false;
+    double smax = 0.0;
+    for (int K = 1; K <= Kc; ++K)
+        if (V[K] && V[K + 1]) { if (!any || S[K] > smax) smax = S[K]; any = true; }
+    if (!any) return true;
+    for (int K = 1; K <= Kc; ++K)
+        if (V[K] && V[K + 1] && S[K] >= p.gamma * smax) { Kstar = K; return true; }
+    return true;
+}
+
+void init_record(orc_frame_rec& r, int64_t f) {
+    std::memset(&r, 0, sizeof r);
+    r.frame = f;
+    r.shot_id = -1;
+    const double nan = std::nan("");
+    r.ncc = r.swr = r.amm = r.act = nan;
+    r.v[0] = r.v[1] = r.v[2] = nan;
+}
+
+// The offline sequential pass: one iteration per frame t, jumping over a
+// detected transition.
+int run_pass(int T, Provider& pv, const orc_params& p, bool dense,
+             std::vector<orc_frame_rec>& recs, std::vector<orc_shot_rec>& shots) {
+    recs.assign((size_t)T, orc_frame_rec());
+    for (int f = 0; f < T; ++f) init_record(recs[(size_t)f], f);
+    shots.clear();
+    if (T <= 0) return 0;
+    int done = -1;  // consecutive pairs are computed for every frame, in order
+    auto ensure = [&](int upto) {
+        while (done < upto) { ++done; if (!pv.consec(done, recs[(size_t)done])) return false; }
+        return true;
+    };
+    recs[0].flags |= ORC_F_KEYFRAME | ORC_F_SHOT_START;
+    orc_shot_rec cur;
+    std::memset(&cur, 0, sizeof cur);
+    cur.pulldown_phase = -1;
+    int shot_start = 0, shot_id = 0;
+    std::deque<double> hist;
+    double acc = 0.0;
+    Analysis ss;
+    auto close_shot = [&](int last) {
+        if (ss.open) ss.decide(p);
+        cur.last = last;
+        cur.sampling = ss.result;
+        cur.pulldown_phase = ss.result == 4 ? ss.phase : -1;
+        cur.n_analyzed = ss.n;
+        cur.final_ = 1;
+        shots.push_back(cur);
+    };
+    int t = 0;
+    while (t < T - 1) {
+        pv.evict_before(t - p.k_max - 2);
+        if (!ensure(t)) return -1;
+        orc_frame_rec& r = recs[(size_t)t];
+        const double a = r.act;
+        const bool st = (r.flags & ORC_F_STATIC) != 0;
+        const bool want_fields = ss.open && !st;   // static frames carry no information
+        if (want_fields || dense) {
+            Meas v[3];
+            for (int i = 0; i < 3; ++i) if (!pv.field(t, i, v[i])) return -1;
+            if (want_fields) {
+                for (int i = 0; i < 3; ++i) r.v[i] = v[i].act;
+                r.field_mask = 7;
+                r.flags |= ORC_F_ANALYZED;
+                ss.add((t - shot_start) % 5, v[0].act, v[1].act, v[2].act, p);
+                if (ss.n == p.n_ss) ss.decide(p);
+            }
+        }
+        // Fast check against the recent activity of the current shot.
+        bool fire;
+        if (hist.empty()) fire = a > p.theta_f0;   // no history yet: absolute threshold
+        else {
+            double s = 0.0;
+            for (double x : hist) s = s + x;
+            const double mean = s / (double)hist.size();
+            fire = a > p.rho_f * mean + p.theta_f;
+        }
+        if (fire) r.flags |= ORC_F_FAST_FIRED;
+        int Kstar = 0;
+        if (fire || dense) {
+            if (!ensure(std::min(T - 2, t + p.k_max + 1))) return -1;
+            if (!deep_check(t, T, shot_start, a, r.swr, pv, p, Kstar)) return -1;
+            if (!fire) Kstar = 0;
+        }
+        if (Kstar > 0) {
+            close_shot(t);
+            for (int f = t + 1; f < t + Kstar; ++f) recs[(size_t)f].flags |= ORC_F_IN_TRANSITION;
+            const int b = t + Kstar;
+            orc_frame_rec& rb = recs[(size_t)b];
+            rb.boundary = Kstar == 1 ? 1 : 2;
+            rb.boundary_k = Kstar;
+            rb.flags |= ORC_F_SHOT_START | ORC_F_KEYFRAME;
+            ++shot_id;
+            std::memset(&cur, 0, sizeof cur);
+            cur.shot_id = shot_id;
+            cur.first = b;
+            cur.in_boundary = rb.boundary;
+            cur.in_k = Kstar;
+            cur.pulldown_phase = -1;
+            shot_start = b;
+            hist.clear();
+            acc = 0.0;
+            ss = Analysis();
+            t = b;
+            continue;
+        }
+        hist.push_back(a);
+        if ((int)hist.size() > p.w_hist) hist.pop_front();
+        // Dynamic keyframes: accumulate consecutive-frame activity within the shot.
+        acc = acc + a;
+        if (acc > p.theta_kf) { recs[(size_t)t + 1].flags |= ORC_F_KEYFRAME; acc = 0.0; }
+        ++t;
+    }
+    if (!ensure(T - 2)) return -1;
+    close_shot(T - 1);
+    for (const orc_shot_rec& s : shots)
+        for (int64_t f = s.first; f <= s.last; ++f) recs[(size_t)f].shot_id = s.shot_id;
+    return 0;
+}
+
+void fill_pair_record(orc_frame_rec& r, const PairOut& o) {
+    r.flags |= ORC_F_HAS_PAIR;
+    if (o.is_static) r.flags |= ORC_F_STATIC;
+    r.ncc = o.ncc; r.swr = o.swr; r.amm = o.amm; r.act = o.act;
+    r.mom[0] = o.sx; r.mom[1] = o.sy; r.mom[2] = o.sxx; r.mom[3] = o.syy; r.mom[4] = o.sxy;
+    r.n_pix = o.n; r.amm_num = o.a; r.n_blocks = (int32_t)o.B;
+}
+
+typedef std::tuple<int, int, int, int, int> Key;  // ref, ref_field, oth, oth_field, level
+
+// Measures computed from frames, on demand, each at most once.
+struct FrameProvider : Provider {
+    const unsigned char* base;
+    int T;
+    int64_t pitch, stride;
+    int bits;
+    Geometry g;
+    orc_params p;
+    int8_t* mv_out;
+    std::map<int, FrameLevels> levels;
+    std::map<Key, Meas> cache;
+    bool bad_input = false;
+
+    const FrameLevels* get(int f) {
+        auto it = levels.find(f);
+        if (it != levels.end()) return &it->second;
+        Plane full;
+        if (!load_frame(base + (size_t)f * (size_t)stride, g.W, g.H, pitch, bits, full)) {
+            bad_input = true;
+            return nullptr;
+        }
+        FrameLevels& fl = levels[f];
+        build_levels(full, g, fl);
+        return &fl;
+    }
+    const Plane& plane(const FrameLevels& fl, int field, int level) {
+        if (field == 1) return fl.U;
+        if (field == 2) return fl.D;
+        return fl.lv[(size_t)(level - g.L)];
+    }
+    bool measure(int kind, int ref, int rf, int oth, int of, int level, Meas& m, PairOut* keep) {
+        Key k(ref, rf, oth, of, level);
+        auto it = cache.find(k);
+        if (it != cache.end() && !keep) { m = it->second; return true; }
+        const FrameLevels* a = get(ref);
+        const FrameLevels* b = get(oth);
+        if (!a || !b) return false;
+        PairOut o;
+        pair_measure(plane(*a, rf, level), plane(*b, of, level), p, false, o);
+        if (!o.ok) return false;
+        m.act = o.act; m.swr = o.swr;
+        if (it == cache.end()) {
+            cache[k] = m;
+            log.push_back(orc_measure_key{kind, ref, oth, rf, of, level});
+        }
+        if (keep) *keep = o;
+        return true;
+    }
+    bool consec(int t, orc_frame_rec& r) override {
+        PairOut o;
+        Meas m;
+        if (!measure(0, t, 0, t + 1, 0, g.L, m, &o)) return false;
+        fill_pair_record(r, o);
+        if (mv_out) std::memcpy(mv_out + (size_t)t * o.mv.size(), o.mv.data(), o.mv.size());
+        return true;
+    }
+    bool field(int t, int which, Meas& m) override {
+        // v0: U_t -> D_t, v1: U_t -> D_{t+1}, v2: D_t -> U_{t+1}
+        if (which == 0) return measure(1, t, 1, t, 2, g.Lf, m, nullptr);
+        if (which == 1) return measure(1, t, 1, t + 1, 2, g.Lf, m, nullptr);
+        return measure(1, t, 2, t + 1, 1, g.Lf, m, nullptr);
+    }
+    bool deepF(int t, int K, Meas& m) override {
+        return measure(2, t, 0, t + K, 0, deep_level(g, K), m, nullptr);
+    }
+    bool deepP(int t, int K, int Kp, Meas& m) override {
+        return measure(3, t, 0, t - Kp, 0, deep_level(g, K), m, nullptr);
+    }
+    void evict_before(int f) override {
+        while (!levels.empty() && levels.begin()->first < f) levels.erase(levels.begin());
+    }
+};
+
+// Measures read from injected sequences (decision logic alone).
+struct InjectedProvider : Provider {
+    int T, kw;
+    const double *act, *swr, *v, *F, *S, *P;
+    const uint8_t* stat;
+    bool consec(int t, orc_frame_rec& r) override {
+        r.flags |= ORC_F_HAS_PAIR;
+        if (stat[t]) r.flags |= ORC_F_STATIC;
+        r.act = act[t]; r.swr = swr[t]; r.ncc = 1.0 - swr[t];
+        log.push_back(orc_measure_key{0, t, t + 1, 0, 0, 0});
+        return true;
+    }
+    bool field(int t, int which, Meas& m) override {
+        m.act = v[(size_t)t * 3 + which]; m.swr = 0.0;
+        const int ref_f = which == 2 ? 2 : 1, oth_f = which == 2 ? 1 : 2;
+        log.push_back(orc_measure_key{1, t, which == 0 ? t : t + 1, ref_f, oth_f, -1});
+        return true;
+    }
+    bool deepF(int t, int K, Meas& m) override {
+        m.act = F[(size_t)t * kw + K]; m.swr = S[(size_t)t * kw + K];
+        log.push_back(orc_measure_key{2, t, t + K, 0, 0, ceil_log2(K)});
+        return true;
+    }
+    // The backward pair t -> t-Kp at a given level is one measure, whatever K
+    // asked for it: the first value requested stands (as with real frames).
+    std::map<std::tuple<int, int, int>, double> pcache;
+    bool deepP(int t, int K, int Kp, Meas& m) override {
+        const auto key = std::make_tuple(t, t - Kp, ceil_log2(K));
+        auto it = pcache.find(key);
+        m.swr = 0.0;
+        if (it != pcache.end()) { m.act = it->second; return true; }
+        m.act = P[(size_t)t * kw + K];
+        pcache[key] = m.act;
+        log.push_back(orc_measure_key{3, t, t - Kp, 0, 0, ceil_log2(K)});
+        return true;
+    }
+};
+
+bool params_ok(const orc_params* p) {
+    return p && p->block == 8 && p->radius >= 0 && p->radius <= 16 && p->k_max >= 1 &&
+           p->k_max <= 64 && p->w_hist >= 1 && p->n_ss >= 1 && p->lf_offset >= 0;
+}
+
+int export_results(const std::vector<orc_frame_rec>& recs, const std::vector<orc_shot_rec>& shots,
+                   const std::vector<orc_measure_key>& log, orc_frame_rec* out, orc_shot_rec* sh,
+                   int32_t shots_cap, int32_t* n_shots, orc_measure_key* keys, int32_t keys_cap,
+                   int32_t* n_keys) {
+    if (out && !recs.empty()) std::memcpy(out, recs.data(), recs.size() * sizeof(orc_frame_rec));
+    if (n_shots) *n_shots = (int32_t)shots.size();
+    if (n_keys) *n_keys = (int32_t)log.size();
+    if (sh) {
+        if ((int64_t)shots.size() > shots_cap) return -3;
+        if (!shots.empty()) std::memcpy(sh, shots.data(), shots.size() * sizeof(orc_shot_rec));
+    }
+    if (keys) {
+        if ((int64_t)log.size() > keys_cap) return -3;
+        if (!log.empty()) std::memcpy(keys, log.data(), log.size() * sizeof(orc_measure_key));
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t orc_geometry(int32_t W, int32_t H, const orc_params* p, int32_t* out, int32_t cap) {
+    if (!params_ok(p) || !out) return -1;
+    Geometry g;
+    if (!make_geometry(W, H, *p, g)) return -1;
+    const int need = 4 + 2 * (g.Lcap + 1) + 2;
+    if (cap < need) return -3;
+    out[0] = g.L; out[1] = g.Lcap; out[2] = g.Lf; out[3] = g.Lcap + 1;
+    for (int l = 0; l <= g.Lcap; ++l) { out[4 + 2 * l] = g.wl[l]; out[5 + 2 * l] = g.hl[l]; }
+    out[4 + 2 * (g.Lcap + 1)] = g.wf;
+    out[5 + 2 * (g.Lcap + 1)] = g.hf;
+    return 0;
+}
+
+int32_t orc_downscale(const uint16_t* src, int32_t w, int32_t h, uint16_t* dst) {
+    if (!src || !dst || w < 2 || h < 2) return -1;
+    Plane s;
+    s.w = w; s.h = h;
+    s.px.assign(src, src + (size_t)w * h);
+    Plane d = downscale(s);
+    for (size_t i = 0; i < d.px.size(); ++i) dst[i] = (uint16_t)d.px[i];
+    return 0;
+}
+
+int32_t orc_levels(const void* Y, int32_t W, int32_t H, int64_t pitch_bytes, int32_t bits,
+                   const orc_params* p, uint16_t* out, int64_t cap, int64_t* n_out) {
+    if (!Y || !params_ok(p) || (bits != 8 && bits != 10)) return -1;
+    Geometry g;
+    if (!make_geometry(W, H, *p, g)) return -1;
+    if (pitch_bytes < (int64_t)W * (bits == 8 ? 1 : 2)) return -1;
+    Plane full;
+    if (!load_frame(Y, W, H, pitch_bytes, bits, full)) return -1;
+    FrameLevels fl;
+    build_levels(full, g, fl);
+    int64_t n = 0;
+    for (const Plane& q : fl.lv) n += (int64_t)q.px.size();
+    n += (int64_t)fl.U.px.size() + (int64_t)fl.D.px.size();
+    if (n_out) *n_out = n;
+    if (!out) return 0;
+    if (cap < n) return -3;
+    int64_t k = 0;
+    auto put = [&](const Plane& q) { for (int32_t v : q.px) out[k++] = (uint16_t)v; };
+    for (const Plane& q : fl.lv) put(q);
+    put(fl.U);
+    put(fl.D);
+    return 0;
+}
+
+int32_t orc_pair(const uint16_t* I, const uint16_t* J, int32_t w, int32_t h, const orc_params* p,
+                 int32_t force_zero_mv, int8_t* mv, int32_t* sad, int64_t* ints, double* dbl) {
+    if (!I || !J || !params_ok(p) || w < 8 || h < 8) return -1;
+    Plane a, b;
+    a.w = b.w = w; a.h = b.h = h;
+    a.px.assign(I, I + (size_t)w * h);
+    b.px.assign(J, J + (size_t)w * h);
+    PairOut o;
+    pair_measure(a, b, *p, force_zero_mv != 0, o);
+    if (!o.ok) return -1;
+    if (mv) std::memcpy(mv, o.mv.data(), o.mv.size());
+    if (sad) std::memcpy(sad, o.sad.data(), o.sad.size() * sizeof(int32_t));
+    if (ints) {
+        int64_t v[9] = {o.sx, o.sy, o.sxx, o.syy, o.sxy, o.n, o.a, o.B, o.is_static ? 1 : 0};
+        std::memcpy(ints, v, sizeof v);
+    }
+    if (dbl) { dbl[0] = o.ncc; dbl[1] = o.swr; dbl[2] = o.amm; dbl[3] = o.act; }
+    return 0;
+}
+
+int32_t orc_finish(const int64_t* v, double a0, double* out4) {
+    if (!v || !out4) return -1;
+    return finish(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], a0, out4) ? 0 : -1;
+}
+
+int32_t orc_run_clip(const void* frames, int32_t T, int32_t W, int32_t H, int64_t pitch_bytes,
+                     int64_t frame_stride_bytes, int32_t bits, int32_t dense, const orc_params* p,
+                     orc_frame_rec* recs, orc_shot_rec* shots, int32_t shots_cap, int32_t* n_shots,
+                     orc_measure_key* keys, int32_t keys_cap, int32_t* n_keys, int8_t* mv_out) {
+    if (!frames || T < 1 || !params_ok(p) || (bits != 8 && bits != 10)) return -1;
+    FrameProvider pv;
+    if (!make_geometry(W, H, *p, pv.g)) return -1;
+    const int64_t row = (int64_t)W * (bits == 8 ? 1 : 2);
+    if (pitch_bytes < row || frame_stride_bytes < pitch_bytes * (H - 1) + row) return -1;
+    pv.base = (const unsigned char*)frames;
+    pv.T = T; pv.pitch = pitch_bytes; pv.stride = frame_stride_bytes; pv.bits = bits;
+    pv.p = *p; pv.mv_out = mv_out;
+    std::vector<orc_frame_rec> r;
+    std::vector<orc_shot_rec> s;
+    if (run_pass(T, pv, *p, dense != 0, r, s) != 0) return -1;
+    return export_results(r, s, pv.log, recs, shots, shots_cap, n_shots, keys, keys_cap, n_keys);
+}
+
+int32_t orc_decide_injected(int32_t T, const double* act, const double* swr, const uint8_t* stat,
+                            const double* v, const double* F, const double* S, const double* P,
+                            int32_t dense, const orc_params* p, orc_frame_rec* recs,
+                            orc_shot_rec* shots, int32_t shots_cap, int32_t* n_shots,
+                            orc_measure_key* keys, int32_t keys_cap, int32_t* n_keys) {
+    if (T < 1 || !act || !swr || !stat || !v || !F || !S || !P || !params_ok(p)) return -1;
+    InjectedProvider pv;
+    pv.T = T; pv.kw = p->k_max + 2;
+    pv.act = act; pv.swr = swr; pv.stat = stat; pv.v = v; pv.F = F; pv.S = S; pv.P = P;
+    std::vector<orc_frame_rec> r;
+    std::vector<orc_shot_rec> s;
+    if (run_pass(T, pv, *p, dense != 0, r, s) != 0) return -1;
+    return export_results(r, s, pv.log, recs, shots, shots_cap, n_shots, keys, keys_cap, n_keys);
+}
+
+}  // extern "C"

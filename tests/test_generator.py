@@ -1,0 +1,57 @@
+"""The synthetic input generator: determinism and ground-truth consistency."""
+import numpy as np
+
+import synth
+
+
+def test_c1_shape_and_determinism():
+    a = synth.render(synth.make_c1(T=8))
+    b = synth.render(synth.make_c1(T=8))
+    assert a.shape == (8, 180, 320) and a.dtype == np.uint8
+    assert np.array_equal(a, b)
+    c = synth.render(synth.make_c1(seed=2, T=8))
+    assert not np.array_equal(a, c)
+
+
+def test_c1_truth():
+    t = synth.make_c1().truth()
+    assert t["T"] == 64
+    assert t["boundaries"] == [(31, 32, 1)]
+    assert [s["first"] for s in t["shots"]] == [0, 32]
+
+
+def test_c2_layout_consistent():
+    spec = synth.make_c2(T=1500)
+    t = spec.truth()
+    assert t["T"] == 1500
+    firsts, lasts, bounds = spec.layout()
+    for (lo, fn, k), nxt in zip(bounds, firsts[1:]):
+        assert fn == nxt and fn - lo == k and k in (1, 8)
+    assert lasts[-1] == 1499
+    near = {f for lo, fn, _ in bounds for f in range(lo - 2, fn + 3)}
+    assert not (set(t["flashes"]) & near)
+
+
+def test_translation_is_the_pan():
+    # a progressive shot without rectangles is a pure toroidal translation
+    spec = synth.make_c1(T=4)
+    spec.shots[0].noise_sigma = 0.0
+    f = synth.render(spec, frames=[0, 1])
+    vx, vy = spec.shots[0].pan[0]
+    assert np.array_equal(np.roll(np.roll(f[0], vy, 0), vx, 1)[8:-8, 8:-8], f[1][8:-8, 8:-8])
+
+
+def test_interlaced_fields_half_interval():
+    spec = synth.make_c2(seed=7, T=30, W=512, H=272)
+    r = synth.Renderer(spec)
+    i = next(k for k, s in enumerate(spec.shots) if s.sampling in (2, 3))
+    s = spec.shots[i]
+    s.rects = []
+    s.noise_sigma = 0.0
+    s.flicker = None
+    fr = r.frame(r.firsts[i])
+    early, late = r.scene(i, 0), r.scene(i, 1)
+    if s.sampling == 2:   # top field first: even rows early
+        assert np.array_equal(fr[0::2], early[0::2]) and np.array_equal(fr[1::2], late[1::2])
+    else:
+        assert np.array_equal(fr[1::2], early[1::2]) and np.array_equal(fr[0::2], late[0::2])

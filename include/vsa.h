@@ -1,0 +1,258 @@
+/*
+ * vsa.h -- C ABI of libvsa, the MI355X (gfx950) per-frame video measure engine.
+ *
+ * The engine computes, on the GPU, the measures of Fassold's unified
+ * shot-boundary / sampling-structure / dynamic-keyframe detector
+ * (arXiv 2502.09202, Sec. III) and the cheap decisions on top of them:
+ *
+ *   - a luma pyramid (2x2 rounding box filter, per level) with the upper and
+ *     lower fields (even / odd rows) of every frame (Sec. III.C);
+ *   - an 8x8-block integer motion field by exhaustive SAD search in +-8
+ *     working pixels (stands in for the dense optical flow of Sec. III.A);
+ *   - the exact integer moments of the reference against the motion-
+ *     compensated (warped) image, NCC, SWR = 1 - NCC, AMM (average motion
+ *     magnitude) and ACT (geometric average of AMM and SWR) (Sec. III.A);
+ *   - ACT of consecutive frames always; field measures v0, v1, v2 and the
+ *     deep-check pairs only when the decision logic asks for them (the
+ *     sparse, selective schedule of Sec. III.A), compacted on the device;
+ *   - hardcut / dissolve (fast + deep check, Sec. III.B), progressive /
+ *     interlaced TFF / BFF / 3:2 pulldown per shot (Sec. III.C), dynamic
+ *     keyframes (Sec. III.D).
+ *
+ * Model: open streams (one per video), push one luma plane per stream, call
+ * vsa_step() to process one time step of every stream that has a frame (or is
+ * draining after vsa_stream_end), vsa_sync(), then poll per-frame and per-shot
+ * records.  Records come out in frame order, a bounded number of frames after
+ * the frame was pushed (the deep check looks ahead up to k_max+1 frames); a
+ * shot record is final only once the next boundary (or the end) is known.
+ *
+ * Conventions
+ *   - Every call that can fail returns a vsa_status (0 = VSA_OK, < 0 error);
+ *     no C++ exception crosses this boundary.  vsa_last_error() describes the
+ *     last failure of the calling thread.
+ *   - The engine owns all device memory it allocates.  The caller owns every
+ *     buffer it passes in (frames, output arrays) unless a call says otherwise.
+ *   - Calls on one engine are serialised by an internal mutex; distinct
+ *     engines are independent.
+ *   - Pixel formats: 8-bit luma in uint8, or 10-bit luma in uint16 (values
+ *     <= 1023, little endian).  Only the Y plane is read.
+ */
+#ifndef VSA_H
+#define VSA_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VSA_ABI_VERSION 1
+
+typedef int32_t vsa_status;
+enum {
+    VSA_OK = 0,
+    VSA_E_INVAL = -1,        /* invalid argument (NULL, size, bit depth, pitch, ...)   */
+    VSA_E_NOMEM = -2,        /* device or host allocation failed                        */
+    VSA_E_ADMIT = -3,        /* stream refused: HBM budget or stream slots exhausted    */
+    VSA_E_STATE = -4,        /* call not valid in the stream's state (push after end)   */
+    VSA_E_DEVICE = -5,       /* HIP runtime error; affected streams become FAILED       */
+    VSA_E_AGAIN = -6,        /* stream already holds a frame waiting for a step         */
+    VSA_E_UNSUPPORTED = -7   /* parameters outside what the kernels implement           */
+};
+
+/* Algorithm constants (the paper prints none).  Same meaning as the fields of
+ * the JSON parameter file shipped with the package. */
+typedef struct {
+    int32_t block;        /* block edge; must be 8                                         */
+    int32_t radius;       /* search radius R in working pixels; must be 8                   */
+    int32_t wmax;         /* working level L = first pyramid level with width <= wmax        */
+    int32_t lf_offset;    /* field level Lf = max(0, L - lf_offset); must be 1               */
+    int32_t k_max;        /* default longest transition tested by the deep check (1..15)     */
+    int32_t a_static_fx;  /* pair is STATIC if A < a_static_fx * B (A in 1/256 px)           */
+    int32_t w_hist;       /* fast-check history length (1..32)                               */
+    int32_t n_ss;         /* frames analysed per shot for sampling structure                 */
+    double a0;            /* ACT = sqrt((AMM + a0) * SWR)                                    */
+    double rho_f, theta_f;/* fast check fires if ACT > rho_f * mean(history) + theta_f       */
+    double theta_f0;      /* ... or, with no history in the shot yet, if ACT > theta_f0      */
+    double rho_d, theta_d;/* deep check verifies K if F_K > rho_d * P_K + theta_d            */
+    double gamma;         /* dissolve length: first K with SWR_K >= gamma * max SWR          */
+    double tau_c;         /* combed: v0 > tau_c * min(v1, v2) (interlace vote) and
+                             v0 > tau_c * max(v1, v2) (pulldown cadence vote)                */
+    double eps;           /* progressive if combed <= eps n, interlaced if >= (1 - eps) n     */
+    double pd_agree;      /* pulldown accepted if the cadence explains >= pd_agree n frames  */
+    double theta_kf;      /* keyframe when accumulated ACT exceeds theta_kf                  */
+} vsa_params;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal                                        */
+    int32_t max_streams;       /* stream slots (1..1024)                                    */
+    uint64_t hbm_budget_bytes; /* admission budget; 0 = 90% of free device memory at create */
+    int32_t schedule;          /* VSA_SCHEDULE_SPARSE (the paper's) or VSA_SCHEDULE_DENSE   */
+    int32_t use_graph;         /* 1: replay each time step as a captured HIP graph          */
+    const vsa_params* params;  /* NULL = built-in defaults (vsa_default_params)             */
+    int32_t debug_log;         /* 1: keep a log of every sparse measure computed            */
+    int32_t me_tile;           /* 0 = autotuned / default, else a VSA_ME_TILE_* code        */
+} vsa_engine_config;
+
+enum { VSA_SCHEDULE_SPARSE = 0, VSA_SCHEDULE_DENSE = 1 };
+
+typedef struct {
+    int32_t width, height;     /* full-resolution luma size                                 */
+    int32_t bit_depth;         /* 8 or 10                                                   */
+    int32_t fps_num, fps_den;  /* nominal frame rate (informational)                        */
+    int32_t k_max;             /* 0 = params default, else 1..15                            */
+} vsa_stream_desc;
+
+/* Where vsa_stream_push reads the plane from. */
+enum {
+    VSA_SRC_HOST = 0,          /* host memory; copied into engine-owned pinned memory before the
+                                  call returns; the caller may reuse the buffer at once          */
+    VSA_SRC_DEVICE_COPY = 1,   /* device memory; copied into engine-owned device memory before
+                                  the call returns                                               */
+    VSA_SRC_DEVICE_BORROW = 2  /* device memory read in place by the next vsa_step; the caller
+                                  keeps it valid and unmodified until vsa_sync returns           */
+};
+
+/* Per-frame record.  The pair measures describe (frame -> frame+1) at the
+ * working level; v0..v2 are NaN unless field_mask says they were computed. */
+typedef struct {
+    int64_t frame, pts;
+    int32_t flags;             /* VSA_F_* bits                                              */
+    int32_t shot_id;           /* -1 for frames inside a transition                         */
+    int32_t boundary;          /* 0 none, 1 hardcut, 2 dissolve: set on the first frame of a shot */
+    int32_t boundary_k;        /* K* of that boundary (1 for a hardcut)                     */
+    double ncc, swr, amm, act;
+    int64_t mom[5];            /* Sx, Sy, Sxx, Syy, Sxy over the covered pixels             */
+    int64_t n_pix, amm_num;    /* N = 64 B and A = sum over blocks of floor(256 |d|)        */
+    int32_t n_blocks;
+    uint32_t field_mask;
+    double v[3];               /* v0 = ACT(U_t, D_t), v1 = ACT(U_t, D_t+1), v2 = ACT(D_t, U_t+1) */
+} vsa_frame_result;
+
+enum {
+    VSA_F_HAS_PAIR = 1, VSA_F_STATIC = 2, VSA_F_FAST_FIRED = 4, VSA_F_IN_TRANSITION = 8,
+    VSA_F_KEYFRAME = 16, VSA_F_SHOT_START = 32, VSA_F_ANALYZED = 64
+};
+
+enum { VSA_SAMPLING_UNDETERMINED = 0, VSA_SAMPLING_PROGRESSIVE = 1, VSA_SAMPLING_TFF = 2,
+       VSA_SAMPLING_BFF = 3, VSA_SAMPLING_PULLDOWN32 = 4 };
+
+typedef struct {
+    int32_t shot_id, pad0;
+    int64_t first, last;
+    int32_t in_boundary, in_k;
+    int32_t sampling;          /* VSA_SAMPLING_*                                            */
+    int32_t pulldown_phase;    /* position (mod 5, from the shot start) of the first mixed frame; -1 */
+    int32_t n_analyzed, final_;
+} vsa_shot_result;
+
+typedef struct vsa_engine vsa_engine;
+
+/* ABI version of the loaded library (VSA_ABI_VERSION). */
+int32_t vsa_abi_version(void);
+
+/* Fill *out with the built-in parameter defaults. */
+void vsa_default_params(vsa_params* out);
+
+/* Create an engine on cfg->device; allocates the engine-wide device buffers.
+ * Errors: VSA_E_INVAL (NULL, bad sizes), VSA_E_UNSUPPORTED (params the kernels
+ * do not implement), VSA_E_DEVICE, VSA_E_NOMEM. */
+vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out);
+
+/* Wait for queued work, close every stream and free all device memory.
+ * NULL is a no-op. */
+void vsa_engine_destroy(vsa_engine* e);
+
+/* HBM bytes a stream of this shape holds while open (used for admission);
+ * 0 if the description is invalid. */
+uint64_t vsa_stream_footprint(const vsa_engine* e, const vsa_stream_desc* d);
+
+/* Open a stream.  Frames smaller than a 2 x 2 grid of blocks at the working
+ * level give VSA_E_INVAL; no free slot or not enough budget gives VSA_E_ADMIT. */
+vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid);
+
+/* Hand over the next luma plane of stream sid (see VSA_SRC_*).  pitch_bytes
+ * is the row stride of `luma`.  VSA_E_AGAIN if the previous frame has not been
+ * taken by a vsa_step yet; VSA_E_STATE after vsa_stream_end. */
+vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t pitch_bytes,
+                           int32_t src, int64_t pts);
+
+/* End of stream: later steps drain the look-ahead and close the last shot. */
+vsa_status vsa_stream_end(vsa_engine* e, int32_t sid);
+
+/* 1 once every record of an ended stream has been produced (after vsa_sync),
+ * 0 if not, < 0 on error. */
+int32_t vsa_stream_done(vsa_engine* e, int32_t sid);
+
+/* Enqueue one time step over every open stream.  Asynchronous.  hip_stream
+ * (nullable) is a hipStream_t: the step starts after the work already queued
+ * on it and work queued on it later starts after the step. */
+vsa_status vsa_step(vsa_engine* e, void* hip_stream);
+
+/* Wait for every queued step and publish its records to the host queues. */
+vsa_status vsa_sync(vsa_engine* e);
+
+/* Copy up to cap finished per-frame records of stream sid, in frame order, and
+ * remove them from the queue.  Returns the number copied, or < 0 on error. */
+int32_t vsa_poll_frames(vsa_engine* e, int32_t sid, vsa_frame_result* out, int32_t cap);
+
+/* Same for per-shot records. */
+int32_t vsa_poll_shots(vsa_engine* e, int32_t sid, vsa_shot_result* out, int32_t cap);
+
+/* Motion field of the pair (frame -> frame+1) of stream sid at the working
+ * level, as nby x nbx pairs (dx, dy) of int8, if that frame is still held on
+ * the device (the last 2 k_max + 4 frames).  Synchronises the engine. */
+vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
+                          int32_t cap_blocks, int32_t* nbx, int32_t* nby);
+
+/* Free the slot at once; records not yet polled are dropped. */
+vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
+
+/* Engine counters: out[0] steps, [1] streams open, [2] streams admitted,
+ * [3] admissions refused, [4] HBM bytes held by streams, [5] budget bytes,
+ * [6] sparse pair tasks run, [7] consecutive pair tasks run. */
+vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out8);
+
+/* Thread-local description of the last error; valid until the next call. */
+const char* vsa_last_error(void);
+
+/* ---- test hooks: run one kernel in isolation on host buffers ------------- */
+
+/* Pyramid of one frame: frame levels L..Ltop (Ltop = min(L + 4, Lcap)) then
+ * the upper and lower field at Lf, densely packed as uint16, in that order.
+ * *n_out receives the sample count (call with out = NULL to size). */
+vsa_status vsa_debug_levels(const vsa_params* p, const void* luma, int32_t width, int32_t height,
+                            int64_t pitch_bytes, int32_t bit_depth, uint16_t* out, int64_t cap,
+                            int64_t* n_out);
+
+/* Pair measure of two w x h planes (uint16 samples, densely packed):
+ * mv (B x 2 int8), sad (B int32, nullable), ints (Sx, Sy, Sxx, Syy, Sxy, N, A,
+ * B, STATIC), dbl (NCC, SWR, AMM, ACT).  bit_depth selects the 8-bit or
+ * 10-bit kernel; force_zero_mv uses d = (0, 0) for every block. */
+vsa_status vsa_debug_pair(const vsa_params* p, const uint16_t* I, const uint16_t* J, int32_t w,
+                          int32_t h, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
+                          int32_t* sad, int64_t* ints, double* dbl);
+
+/* The finishing arithmetic on n integer tuples (Sx, Sy, Sxx, Syy, Sxy, N, A, B)
+ * -> n x (NCC, SWR, AMM, ACT), computed by the device. */
+vsa_status vsa_debug_finish(const int64_t* ints, int64_t n, double a0, double* out);
+
+/* Decision logic alone, driven by injected measure sequences instead of
+ * frames (same array layout as the engine's CPU check: act, swr, stat: T;
+ * v: T x 3; F, S, P: T x (k_max + 2)).  Runs the device state machine one
+ * simulated frame arrival at a time.  recs: T records; shots: up to shots_cap;
+ * keys (nullable): up to keys_cap x 6 int32 (kind, ref, oth, ref_field,
+ * oth_field, level) of the sparse measures requested. */
+vsa_status vsa_debug_decide(const vsa_params* p, int32_t k_max, int32_t dense, int32_t T,
+                            const double* act, const double* swr, const uint8_t* stat,
+                            const double* v, const double* F, const double* S, const double* P,
+                            vsa_frame_result* recs, vsa_shot_result* shots, int32_t shots_cap,
+                            int32_t* n_shots, int32_t* keys, int32_t keys_cap, int32_t* n_keys);
+
+/* Sparse measures computed for stream sid (engines created with debug_log):
+ * up to cap x 6 int32 as in vsa_debug_decide; returns the count or < 0. */
+int32_t vsa_debug_measure_log(vsa_engine* e, int32_t sid, int32_t* keys, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,550 @@
+// k_decide.hip -- K6: per-stream decision state machine, sparse-task compaction
+// and record emission.
+//
+// The decisions are those of Sec. III.B-D: a fast check of the consecutive
+// activity against the shot's recent history, a deep check of K-frame
+// transitions (ACT from t to t+K against ACT from t back to its predecessor at
+// the same distance, at a coarser pyramid level for larger K), the sampling
+// structure vote over at most n_ss non-static frames of a shot from the field
+// measures v0, v1, v2 (comb test, 3:2 pulldown cadence, field order from
+// beta = v1/v2), and keyframes from the activity accumulated within a shot.
+//
+// Each stream advances one "iteration" of the offline sequential pass at a
+// time, as soon as the frames it needs are on the device.  An iteration that
+// needs sparse measures (fields of an analysed frame, deep-check pairs after
+// the fast check fired) is planned in one step and committed in the next one,
+// after the step's motion-search launch has computed the requested pairs;
+// iterations that need nothing more are committed at once.  The planned
+// tasks of all streams are compacted into one dense list (per-stream counts,
+// a block-wide exclusive scan built from wave ballots/prefix sums, then each
+// stream writes its tasks at its offset) together with the running tile
+// offsets that the persistent motion-search grid walks.  Finished frames and
+// shots are appended to device output rings in (stream, frame) order.
+//
+// All floating-point comparisons use the operations in the order written,
+// with no contraction (-ffp-contract=off), so that the labels are bitwise
+// reproducible against a scalar CPU implementation.
+#include "vsa_internal.h"
+
+namespace vsa {
+
+namespace {
+
+__device__ __forceinline__ int ceil_log2(int k) {
+    int c = 0;
+    while ((1 << c) < k) ++c;
+    return c;
+}
+
+__device__ __forceinline__ int deep_level(const StreamDesc& sd, int K) {
+    const int l = sd.L + ceil_log2(K);
+    return l < sd.Lcap ? l : sd.Lcap;
+}
+
+__device__ __forceinline__ bool p_dup(const StreamDesc& sd, int K, int d);
+__device__ __forceinline__ int p_rep(const StreamDesc& sd, int K, int d);
+
+__device__ __forceinline__ FrameInfo& info_of(const StreamDesc& sd, int f) { return sd.info[f % sd.rs]; }
+
+__device__ __forceinline__ void ss_reset(Analysis& a) {
+    a.open = 1; a.n = 0; a.nci = 0; a.s = 0; a.result = 0; a.phase = -1;
+    for (int i = 0; i < 5; ++i) { a.cm[i] = 0; a.np[i] = 0; }
+    a.sum1 = 0.0; a.sum2 = 0.0;
+}
+
+// Two comb votes per analysed frame: v0 against the smaller of v1, v2 (the
+// interlace vote: half a frame interval separates v0's fields and one of the
+// inter-frame field pairs) and against the larger one (the pulldown cadence
+// vote: within a pulldown unit one inter-frame field pair may join two fields
+// of the same film frame).
+__device__ __forceinline__ void ss_add(Analysis& a, int ph, double v0, double v1, double v2,
+                                       const DecideParams& dp) {
+    const double mn = v1 < v2 ? v1 : v2;
+    const double mx = v1 > v2 ? v1 : v2;
+    const bool comb_min = v0 > dp.tau_c * mn;
+    const bool comb_max = v0 > dp.tau_c * mx;
+    a.n += 1;
+    a.np[ph] += 1;
+    if (comb_min) a.nci += 1;
+    if (comb_max) a.cm[ph] += 1;
+    if (v1 > v2) a.s += 1; else if (v1 < v2) a.s -= 1;
+    a.sum1 = a.sum1 + v1;
+    a.sum2 = a.sum2 + v2;
+}
+
+__device__ __forceinline__ void ss_decide(Analysis& a, const DecideParams& dp) {
+    a.open = 0;
+    a.phase = -1;
+    if (a.n == 0) { a.result = VSA_SAMPLING_UNDETERMINED; return; }
+    if (a.n >= 10) {
+        int mask = 0, cnt = 0;
+        for (int q = 0; q < 5; ++q)
+            if (2 * a.cm[q] > a.np[q]) { mask |= 1 << q; ++cnt; }
+        if (cnt == 2) {
+            for (int q = 0; q < 5; ++q) {
+                if (mask != ((1 << q) | (1 << ((q + 1) % 5)))) continue;
+                int agree = 0;
+                for (int r = 0; r < 5; ++r) agree += ((mask >> r) & 1) ? a.cm[r] : a.np[r] - a.cm[r];
+                if ((double)agree >= dp.pd_agree * (double)a.n) {
+                    a.result = VSA_SAMPLING_PULLDOWN32;
+                    a.phase = q;
+                    return;
+                }
+            }
+        }
+    }
+    bool inter;
+    if ((double)a.nci <= dp.eps * (double)a.n) inter = false;
+    else if ((double)a.nci >= (1.0 - dp.eps) * (double)a.n) inter = true;
+    else inter = 2 * a.nci > a.n;
+    if (!inter) { a.result = VSA_SAMPLING_PROGRESSIVE; return; }
+    if (a.s > 0) a.result = VSA_SAMPLING_TFF;
+    else if (a.s < 0) a.result = VSA_SAMPLING_BFF;
+    else a.result = (a.sum1 >= a.sum2) ? VSA_SAMPLING_TFF : VSA_SAMPLING_BFF;
+}
+
+__device__ __forceinline__ bool fast_check(const DecideState& st, double a, const DecideParams& dp) {
+    if (st.hist_len == 0) return a > dp.theta_f0;   // no history in the shot yet
+    double s = 0.0;
+    for (int i = 0; i < st.hist_len; ++i) s = s + st.hist[(st.hist_head + i) % dp.w_hist];
+    const double mean = s / (double)st.hist_len;
+    return a > dp.rho_f * mean + dp.theta_f;
+}
+
+__device__ __forceinline__ void hist_push(DecideState& st, double a, const DecideParams& dp) {
+    if (st.hist_len < dp.w_hist) {
+        st.hist[(st.hist_head + st.hist_len) % dp.w_hist] = a;
+        st.hist_len += 1;
+    } else {
+        st.hist[st.hist_head] = a;
+        st.hist_head = (st.hist_head + 1) % dp.w_hist;
+    }
+}
+
+__device__ __forceinline__ void close_shot(DecideState& st, int last, const DecideParams& dp) {
+    if (st.ss.open) ss_decide(st.ss, dp);
+    if (st.n_closed >= 4) return;
+    vsa_shot_result& r = st.closed[st.n_closed++];
+    r.shot_id = st.shot_id;
+    r.pad0 = 0;
+    r.first = st.shot_start;
+    r.last = last;
+    r.in_boundary = st.cur_in_boundary;
+    r.in_k = st.cur_in_k;
+    r.sampling = st.ss.result;
+    r.pulldown_phase = st.ss.result == VSA_SAMPLING_PULLDOWN32 ? st.ss.phase : -1;
+    r.n_analyzed = st.ss.n;
+    r.final_ = 1;
+}
+
+// Deep check of iteration t from the requested results (Sec. III.B).
+__device__ int deep_check(const StreamDesc& sd, const DecideState& st, int t, int Kn, double a_t,
+                          double s_t, const PairResult* res, const DecideParams& dp) {
+    bool V[kMaxKmax + 3];
+    double S[kMaxKmax + 3];
+    for (int K = 0; K < kMaxKmax + 3; ++K) { V[K] = true; S[K] = 0.0; }
+    for (int K = 1; K <= Kn; ++K) {
+        const double f = K == 1 ? a_t : res[kResF + K].act;
+        const double sw = K == 1 ? s_t : res[kResF + K].swr;
+        const int kp = min(K, t - st.shot_start);
+        const double p = kp > 0 ? res[kResP + p_rep(sd, K, t - st.shot_start)].act : 0.0;
+        V[K] = f > dp.rho_d * p + dp.theta_d;
+        S[K] = sw;
+    }
+    const int Kc = min(sd.k_max, Kn);
+    bool any = false;
+    double smax = 0.0;
+    for (int K = 1; K <= Kc; ++K)
+        if (V[K] && V[K + 1]) {
+            if (!any || S[K] > smax) smax = S[K];
+            any = true;
+        }
+    if (!any) return 0;
+    for (int K = 1; K <= Kc; ++K)
+        if (V[K] && V[K + 1] && S[K] >= dp.gamma * smax) return K;
+    return 0;
+}
+
+// Commit iteration t = st.t with the flags it was planned with.
+__device__ void commit(const StreamDesc& sd, DecideState& st, const PairResult* res, const DecideParams& dp,
+                       bool want_fields, bool fire, bool need_deep, int Kn) {
+    const int t = st.t;
+    FrameInfo& fi = info_of(sd, t);
+    const double a = fi.act;
+    if (want_fields) {
+        const double v0 = res[kResFields + 0].act, v1 = res[kResFields + 1].act, v2 = res[kResFields + 2].act;
+        fi.v[0] = v0; fi.v[1] = v1; fi.v[2] = v2;
+        fi.field_mask = 7;
+        fi.flags |= VSA_F_ANALYZED;
+        ss_add(st.ss, (t - st.shot_start) % 5, v0, v1, v2, dp);
+        if (st.ss.n == dp.n_ss) ss_decide(st.ss, dp);
+    }
+    if (fire) fi.flags |= VSA_F_FAST_FIRED;
+    int Kstar = 0;
+    if (need_deep) {
+        Kstar = deep_check(sd, st, t, Kn, a, fi.swr, res, dp);
+        if (!fire) Kstar = 0;
+    }
+    if (Kstar > 0) {
+        fi.shot_id = st.shot_id;
+        close_shot(st, t, dp);
+        for (int f = t + 1; f < t + Kstar; ++f) {
+            FrameInfo& g = info_of(sd, f);
+            g.flags |= VSA_F_IN_TRANSITION;
+            g.shot_id = -1;
+        }
+        const int b = t + Kstar;
+        FrameInfo& fb = info_of(sd, b);
+        fb.boundary = Kstar == 1 ? 1 : 2;
+        fb.boundary_k = Kstar;
+        fb.flags |= VSA_F_SHOT_START | VSA_F_KEYFRAME;
+        st.shot_id += 1;
+        st.cur_in_boundary = fb.boundary;
+        st.cur_in_k = Kstar;
+        st.shot_start = b;
+        st.hist_len = 0;
+        st.hist_head = 0;
+        st.acc = 0.0;
+        ss_reset(st.ss);
+        st.t = b;
+        return;
+    }
+    fi.shot_id = st.shot_id;
+    hist_push(st, a, dp);
+    st.acc = st.acc + a;
+    if (st.acc > dp.theta_kf) {
+        info_of(sd, t + 1).flags |= VSA_F_KEYFRAME;
+        st.acc = 0.0;
+    }
+    st.t = t + 1;
+}
+
+// Backward deep-check pairs: for K beyond the shot start (K' = t - shot_start
+// < K) the pair t -> t-K' repeats; at the same pyramid level it is the same
+// measure, computed once (the first such K) and shared.
+__device__ __forceinline__ bool p_dup(const StreamDesc& sd, int K, int d) {
+    return K > d && K - 1 >= d && deep_level(sd, K - 1) == deep_level(sd, K);
+}
+
+__device__ __forceinline__ int p_rep(const StreamDesc& sd, int K, int d) {
+    while (p_dup(sd, K, d)) --K;
+    return K;
+}
+
+// Sparse tasks of the planned iteration, in a fixed order: v0, v1, v2, then
+// F_K for K = 2..Kn, then the distinct P_K for K = 1..Kn (when t > shot start).
+__device__ __forceinline__ int plan_task_count(const StreamDesc& sd, const DecideState& st) {
+    if (!st.plan) return 0;
+    int n = st.plan_nf ? 3 : 0;
+    if (st.plan_deep) {
+        n += st.plan_kn - 1;
+        const int d = st.t - st.shot_start;
+        if (d > 0)
+            for (int K = 1; K <= st.plan_kn; ++K) n += p_dup(sd, K, d) ? 0 : 1;
+    }
+    return n;
+}
+
+__device__ PairTask plan_task(const StreamDesc& sd, const DecideState& st, int sid, int i) {
+    PairTask k;
+    k.sid = sid;
+    k.flags = 0;
+    k.epoch = sd.epoch;
+    k.tile_prefix = 0;
+    const int t = st.t;
+    if (st.plan_nf) {
+        if (i < 3) {
+            k.kind = MK_FIELD;
+            k.ref = t;
+            k.ref_field = (i == 2) ? PL_LOWER : PL_UPPER;
+            k.oth = (i == 0) ? t : t + 1;
+            k.oth_field = (i == 2) ? PL_UPPER : PL_LOWER;
+            k.level = sd.Lf;
+            k.result = kResFields + i;
+            k.tiles = me_tiles(sd.wf, sd.hf);
+            return k;
+        }
+        i -= 3;
+    }
+    const int nF = st.plan_kn - 1;
+    if (i < nF) {
+        const int K = i + 2;
+        k.kind = MK_DEEP_F;
+        k.ref = t; k.ref_field = PL_FRAME;
+        k.oth = t + K; k.oth_field = PL_FRAME;
+        k.level = deep_level(sd, K);
+        k.result = kResF + K;
+    } else {
+        const int d = t - st.shot_start;
+        int j = i - nF, K = 1;
+        for (;; ++K) {
+            if (!p_dup(sd, K, d)) {
+                if (j == 0) break;
+                --j;
+            }
+        }
+        const int kp = min(K, d);
+        k.kind = MK_DEEP_P;
+        k.ref = t; k.ref_field = PL_FRAME;
+        k.oth = t - kp; k.oth_field = PL_FRAME;
+        k.level = deep_level(sd, K);
+        k.result = kResP + K;
+    }
+    const int dl = k.level - sd.L;
+    k.tiles = me_tiles(sd.wl[dl], sd.hl[dl]);
+    return k;
+}
+
+// Advance one stream as far as the ingested frames allow.
+__device__ void advance(const StreamDesc& sd, DecideState& st, const PairResult* res, const DecideParams& dp,
+                        int has_frame, int frame, int ended_T) {
+    st.n_closed = 0;
+    if (st.done) { st.plan = 0; return; }
+    if (has_frame) st.n = frame;
+    if (ended_T >= 0) st.T_end = ended_T;
+    if (st.plan) {
+        commit(sd, st, res, dp, st.plan_want, st.plan_fire, st.plan_deep, st.plan_kn);
+        st.plan = 0;
+    }
+    for (;;) {
+        const int t = st.t;
+        if (st.T_end >= 0 && t >= st.T_end - 1) {
+            if (st.T_end > 0) {
+                info_of(sd, st.T_end - 1).shot_id = st.shot_id;
+                close_shot(st, st.T_end - 1, dp);
+            }
+            st.t = st.T_end;
+            st.done = 1;
+            break;
+        }
+        if (t + 1 > st.n) break;                  // pair t -> t+1 not finished yet
+        const FrameInfo& fi = info_of(sd, t);
+        const double a = fi.act;
+        const bool stat = (fi.flags & VSA_F_STATIC) != 0;
+        const bool want = st.ss.open && !stat;    // static frames carry no information
+        const bool fire = fast_check(st, a, dp);
+        const bool need_fields = want || dp.dense;
+        const bool need_deep = fire || dp.dense;
+        int Kn = 0;
+        if (need_deep) {
+            if (st.T_end >= 0) Kn = min(sd.k_max + 1, st.T_end - 1 - t);
+            else if (t + sd.k_max + 1 <= st.n) Kn = sd.k_max + 1;
+            else break;                           // wait for the look-ahead frames
+        }
+        st.plan_want = want;
+        st.plan_fire = fire;
+        st.plan_deep = need_deep;
+        st.plan_nf = need_fields;
+        st.plan_kn = Kn;
+        st.plan = 1;
+        if (plan_task_count(sd, st) > 0) break;       // measures requested; commit next step
+        st.plan = 0;
+        commit(sd, st, res, dp, want, fire, need_deep, Kn);
+    }
+}
+
+__device__ void fill_record(vsa_frame_result& r, const FrameInfo& fi) {
+    r.frame = fi.frame;
+    r.pts = fi.pts;
+    r.flags = fi.flags;
+    r.shot_id = fi.shot_id;
+    r.boundary = fi.boundary;
+    r.boundary_k = fi.boundary_k;
+    r.ncc = fi.ncc; r.swr = fi.swr; r.amm = fi.amm; r.act = fi.act;
+    for (int k = 0; k < 5; ++k) r.mom[k] = fi.mom[k];
+    r.n_pix = fi.n_pix;
+    r.amm_num = fi.amm_num;
+    r.n_blocks = fi.n_blocks;
+    r.field_mask = fi.field_mask;
+    r.v[0] = fi.v[0]; r.v[1] = fi.v[1]; r.v[2] = fi.v[2];
+}
+
+__device__ __forceinline__ void log_task(int32_t* log, int64_t cap, DecideState& st, const PairTask& k) {
+    if (log && st.log_count < cap) {
+        int32_t* e = log + 6 * st.log_count;
+        e[0] = k.kind; e[1] = k.ref; e[2] = k.oth; e[3] = k.ref_field; e[4] = k.oth_field; e[5] = k.level;
+    }
+    st.log_count += 1;
+}
+
+// Block-wide exclusive scan of four counters (blockDim.x <= 1024, multiple of 64).
+__device__ int4 block_scan4(int4 v, int4& total, int4* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int4 inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(inc.x, o, 64), y = __shfl_up(inc.y, o, 64);
+        const int z = __shfl_up(inc.z, o, 64), w = __shfl_up(inc.w, o, 64);
+        if (lane >= o) { inc.x += x; inc.y += y; inc.z += z; inc.w += w; }
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int4 run = make_int4(0, 0, 0, 0);
+        for (int i = 0; i < nw; ++i) {
+            const int4 t = lds[i];
+            lds[i] = run;
+            run.x += t.x; run.y += t.y; run.z += t.z; run.w += t.w;
+        }
+        lds[16] = run;
+    }
+    __syncthreads();
+    const int4 wb = lds[wave];
+    total = lds[16];
+    return make_int4(wb.x + inc.x - v.x, wb.y + inc.y - v.y, wb.z + inc.z - v.z, wb.w + inc.w - v.w);
+}
+
+}  // namespace
+
+// One workgroup; thread i handles step entry i (every open stream appears once).
+__global__ void __launch_bounds__(1024) k_decide(const StreamDesc* __restrict__ sds, DecideState* __restrict__ states,
+                                                 const PairResult* __restrict__ results,
+                                                 const StepStream* __restrict__ steps, int32_t n_steps,
+                                                 DecideParams dp, PairTask* __restrict__ sparse_out,
+                                                 DeviceCursors* __restrict__ cur, OutFrame* __restrict__ out_frames,
+                                                 uint64_t frames_cap, OutShot* __restrict__ out_shots,
+                                                 uint64_t shots_cap, int32_t* __restrict__ log, int64_t log_cap) {
+    __shared__ int4 lds[17];
+    __shared__ uint64_t base_frames, base_shots;
+    const int i = threadIdx.x;
+    const bool mine = i < n_steps;
+    int sid = -1;
+    int4 cnt = make_int4(0, 0, 0, 0);
+    if (mine) {
+        const StepStream& ss = steps[i];
+        sid = ss.sid;
+        const StreamDesc& sd = sds[sid];
+        DecideState& st = states[sid];
+        const int e0 = st.emitted;
+        advance(sd, st, results + (int64_t)sid * kResSlots, dp, ss.has_frame, ss.frame, ss.ended_T);
+        const int nt = plan_task_count(sd, st);
+        int tiles = 0;
+        for (int k = 0; k < nt; ++k) tiles += plan_task(sd, st, sid, k).tiles;
+        cnt = make_int4(nt, tiles, st.t - e0, st.n_closed);
+    }
+    if (i == 0) {
+        base_frames = cur->frames_written;
+        base_shots = cur->shots_written;
+    }
+    int4 total;
+    const int4 off = block_scan4(cnt, total, lds);
+    if (mine) {
+        const StreamDesc& sd = sds[sid];
+        DecideState& st = states[sid];
+        int tile = off.y;
+        for (int k = 0; k < cnt.x; ++k) {
+            PairTask t = plan_task(sd, st, sid, k);
+            t.tile_prefix = tile;
+            tile += t.tiles;
+            sparse_out[off.x + k] = t;
+            log_task(log ? log + (int64_t)sid * log_cap * 6 : nullptr, log_cap, st, t);
+        }
+        for (int k = 0; k < cnt.z; ++k) {
+            const int f = st.emitted + k;
+            OutFrame& o = out_frames[(base_frames + (uint64_t)off.z + k) % frames_cap];
+            o.sid = sid;
+            o.pad = 0;
+            fill_record(o.r, info_of(sd, f));
+        }
+        st.emitted += cnt.z;
+        for (int k = 0; k < cnt.w; ++k) {
+            OutShot& o = out_shots[(base_shots + (uint64_t)off.w + k) % shots_cap];
+            o.sid = sid;
+            o.pad = 0;
+            o.r = st.closed[k];
+        }
+    }
+    if (i == 0) {
+        cur->n_sparse = total.x;
+        cur->sparse_tiles = total.y;
+        cur->sparse_run += (uint64_t)total.x;
+        cur->frames_written = base_frames + (uint64_t)total.z;
+        cur->shots_written = base_shots + (uint64_t)total.w;
+    }
+}
+
+// Decision logic alone on injected measures: simulates one frame arrival per
+// step, fills each planned task's result from the injected arrays (as the
+// motion-search launch would), and writes the records and the task log.
+__global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res, DecideParams dp, int32_t T,
+                                const double* act, const double* swr, const uint8_t* stat, const double* v,
+                                const double* F, const double* S, const double* P,
+                                vsa_frame_result* recs, vsa_shot_result* shots, int32_t shots_cap,
+                                int32_t* n_shots, int32_t* log, int32_t log_cap, int32_t* n_log) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DecideState& st = *st_;
+    const int kw = sd.k_max + 2;
+    int ns = 0;
+    int nl = 0;
+    const double nan = __builtin_nan("");
+    for (int step = 0; step < T + 4 * (sd.k_max + 4) && !st.done; ++step) {
+        const int has = step < T;
+        if (has) {
+            FrameInfo& fi = info_of(sd, step);
+            fi.frame = step; fi.pts = step;
+            fi.flags = step == 0 ? (VSA_F_KEYFRAME | VSA_F_SHOT_START) : 0;
+            fi.shot_id = -1; fi.boundary = 0; fi.boundary_k = 0;
+            fi.ncc = fi.swr = fi.amm = fi.act = nan;
+            for (int k = 0; k < 5; ++k) fi.mom[k] = 0;
+            fi.n_pix = 0; fi.amm_num = 0; fi.n_blocks = 0; fi.field_mask = 0;
+            fi.v[0] = fi.v[1] = fi.v[2] = nan;
+            if (step >= 1) {
+                FrameInfo& pi = info_of(sd, step - 1);
+                pi.act = act[step - 1];
+                pi.swr = swr[step - 1];
+                pi.ncc = 1.0 - swr[step - 1];
+                pi.flags |= VSA_F_HAS_PAIR | (stat[step - 1] ? VSA_F_STATIC : 0);
+            }
+        }
+        const int e0 = st.emitted;
+        advance(sd, st, res, dp, has, step, step >= T - 1 ? T : -1);
+        for (int f = e0; f < st.t; ++f) fill_record(recs[f], info_of(sd, f));
+        st.emitted = st.t;
+        for (int k = 0; k < st.n_closed; ++k)
+            if (ns < shots_cap) shots[ns++] = st.closed[k];
+        const int nt = plan_task_count(sd, st);
+        for (int k = 0; k < nt; ++k) {
+            const PairTask t = plan_task(sd, st, 0, k);
+            if (log && nl < log_cap) {
+                int32_t* e = log + 6 * nl;
+                e[0] = t.kind; e[1] = t.ref; e[2] = t.oth; e[3] = t.ref_field; e[4] = t.oth_field;
+                e[5] = t.kind == MK_FIELD ? -1 : t.level - sd.L;
+            }
+            ++nl;
+            const int tt = st.t;
+            PairResult& r = res[t.result];
+            if (t.kind == MK_FIELD) { r.act = v[(int64_t)tt * 3 + (t.result - kResFields)]; r.swr = 0.0; }
+            else if (t.kind == MK_DEEP_F) {
+                const int K = t.result - kResF;
+                r.act = F[(int64_t)tt * kw + K]; r.swr = S[(int64_t)tt * kw + K];
+            } else {
+                const int K = t.result - kResP;
+                r.act = P[(int64_t)tt * kw + K]; r.swr = 0.0;
+            }
+        }
+    }
+    *n_shots = ns;
+    *n_log = nl;
+}
+
+hipError_t launch_decide(const StreamDesc* sds, DecideState* states, const PairResult* results,
+                         const StepStream* steps, int32_t n_steps, const DecideParams& dp, PairTask* sparse_out,
+                         DeviceCursors* cur, OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots,
+                         uint64_t shots_cap, int32_t* log, int64_t log_cap, hipStream_t s) {
+    const int threads = ((n_steps + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(threads < 64 ? 64 : threads), 0, s, sds, states, results, steps,
+                       n_steps, dp, sparse_out, cur, out_frames, frames_cap, out_shots, shots_cap, log, log_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide_replay(const StreamDesc& sd, DecideState* st, PairResult* res, const DecideParams& dp,
+                                int32_t T, const double* act, const double* swr, const uint8_t* stat,
+                                const double* v, const double* F, const double* S, const double* P,
+                                vsa_frame_result* recs, vsa_shot_result* shots, int32_t shots_cap,
+                                int32_t* n_shots, int32_t* log, int32_t log_cap, int32_t* n_log, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide_replay, dim3(1), dim3(64), 0, s, sd, st, res, dp, T, act, swr, stat, v, F, S, P,
+                       recs, shots, shots_cap, n_shots, log, log_cap, n_log);
+    return hipGetLastError();
+}
+
+}  // namespace vsa

@@ -1,0 +1,571 @@
+// k_me.hip -- K2: block motion search + warped moments, K3: pair finish.
+//
+// Pair measure of I -> J at one pyramid level (the reading of Sec. III.A used
+// here): for every whole 8x8 block of I, the displacement d in [-8, 8]^2 with
+// the smallest SAD against J (J read clamp-to-edge); ties go to the candidate
+// first in the order (|d|^2, dy, dx).  J is warped block-wise by d; the exact
+// moments Sx, Sy, Sxx, Syy, Sxy of I against warped J over the covered pixels
+// and A = sum_b floor(256 |d_b|) give NCC, SWR = 1 - NCC, AMM = A / (256 B) and
+// ACT = sqrt((AMM + a0) SWR).
+//
+// K2 layout: one 256-thread workgroup per tile of 8 x 8 blocks (64 x 64
+// pixels of I).  The tile of I and its (64+16) x (64+16) search window of J
+// are staged in LDS once (clamped at the plane edges), so every candidate is
+// read from LDS.  Four lanes share a block: lane q searches dy in
+// [-8+4q, -5+4q] over all dx and one quarter of the dy = +8 row.
+// 8-bit: v_qsad_pk_u16_u8 gives the SADs of four consecutive dx from one
+// aligned 8-byte window (dx groups -8, -4, 0, +4), v_sad_u8 covers dx = +8, so
+// no byte alignment is ever needed in the search loop.  10-bit: v_sad_u16 on
+// pairs of samples with a 2-byte realignment for odd dx.  Each candidate's key
+// is (SAD << 16 | rank) (8-bit) or (SAD << 9 | rank) (10-bit); the minimum
+// key is the unique argmin.  The epilogue reads the warped block from the same
+// LDS window and forms int32 moments per lane, reduced per tile to int64.
+// K3 sums the tile partials of each pair and forms the doubles in a fixed
+// order with no contraction.
+#include "vsa_internal.h"
+
+namespace vsa {
+
+namespace {
+
+// Candidate order used to break SAD ties: rank[(dy+8)*17 + (dx+8)], and its
+// inverse as (dx+8) | (dy+8) << 8.  Built once on the host (see me_rank_tables).
+__constant__ uint16_t c_rank[kCand * kCand];
+__constant__ uint16_t c_unrank[kCand * kCand];
+
+constexpr int kJW8 = 80;   // J window row length (bytes, 8-bit)
+constexpr int kJRows = 80;
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+struct PlaneRef {
+    const uint8_t* base;
+    int w, h, pitch;   // pitch in samples
+};
+
+__device__ __forceinline__ PlaneRef plane_of(const StreamDesc& sd, int frame, int field, int level) {
+    PlaneRef p;
+    const uint8_t* slot = sd.ring + (int64_t)(frame % sd.rs) * sd.slot_bytes;
+    if (field == PL_UPPER || field == PL_LOWER) {
+        p.base = slot + (field == PL_UPPER ? sd.offU : sd.offD);
+        p.w = sd.wf; p.h = sd.hf; p.pitch = sd.pf;
+    } else {
+        const int d = level - sd.L;
+        p.base = slot + sd.off[d];
+        p.w = sd.wl[d]; p.h = sd.hl[d]; p.pitch = sd.pl[d];
+    }
+    return p;
+}
+
+// floor(256 * sqrt(m)) for 0 <= m <= 128, exact.
+__device__ __forceinline__ int amm_fx(int m) {
+    const int v = 65536 * m;
+    int r = (int)__builtin_sqrtf((float)v);
+    while (r > 0 && r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_I(const PlaneRef& P, int bx0, int by0, uint8_t* sI) {
+    // I tile: 64 rows x 64 samples.  The tile origin is a multiple of 64
+    // samples inside the row, so each 16-byte chunk lies within the row pitch;
+    // rows past the plane are clamped (they feed no block).
+    constexpr int B = (int)sizeof(T);
+    constexpr int CH = 64 * B / 16;
+    for (int i = threadIdx.x; i < 64 * CH; i += kMEThreads) {
+        const int r = i / CH, c = i % CH;
+        const int gy = clampi(8 * by0 + r, 0, P.h - 1);
+        const uint4* src = reinterpret_cast<const uint4*>(P.base + ((int64_t)gy * P.pitch + 8 * bx0) * B) + c;
+        reinterpret_cast<uint4*>(sI + r * 64 * B)[c] = *src;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_J(const PlaneRef& P, int bx0, int by0, uint8_t* sJ) {
+    // J window: rows 8*by0-8 .. +80, columns 8*bx0-8 .. +80, clamped to the plane.
+    constexpr int B = (int)sizeof(T);
+    constexpr int CH = kJW8 * B / 8;                 // 8-byte chunks per row
+    const int x0 = 8 * bx0 - 8;
+    for (int i = threadIdx.x; i < kJRows * CH; i += kMEThreads) {
+        const int r = i / CH, c = i % CH;
+        const int gy = clampi(8 * by0 - 8 + r, 0, P.h - 1);
+        const int gx = x0 + c * (8 / B);
+        const T* row = reinterpret_cast<const T*>(P.base + (int64_t)gy * P.pitch * B);
+        uint2 v;
+        if (gx >= 0 && gx + 8 / B <= P.w) {
+            v = *reinterpret_cast<const uint2*>(row + gx);
+        } else {
+            union { T t[8 / B]; uint2 u; } tmp;
+#pragma unroll
+            for (int k = 0; k < 8 / B; ++k) tmp.t[k] = row[clampi(gx + k, 0, P.w - 1)];
+            v = tmp.u;
+        }
+        *reinterpret_cast<uint2*>(sJ + r * kJW8 * B + c * 8) = v;
+    }
+}
+
+__device__ __forceinline__ uint64_t pk64(uint32_t lo, uint32_t hi) {
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// 8-bit search for one lane: returns the best key (SAD << 16 | rank).
+__device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
+    uint32_t r0[8], r1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint2 v = *reinterpret_cast<const uint2*>(sI + (8 * by + j) * 64 + 8 * bx);
+        r0[j] = v.x;
+        r1[j] = v.y;
+    }
+    uint32_t best = 0xffffffffu;
+    // dy = -8+4q .. -5+4q: J rows (window coords) 8*by + 4q + rr, rr = 0..10
+    const int dy0 = -8 + 4 * q;
+    uint64_t acc[4][4];
+    uint32_t acc8[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        acc8[i] = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[i][g] = 0;
+    }
+    const uint8_t* jb = sJ + (8 * by + 4 * q) * kJW8 + 8 * bx;
+#pragma unroll
+    for (int rr = 0; rr < 11; ++rr) {
+        const uint2 a = *reinterpret_cast<const uint2*>(jb + rr * kJW8);
+        const uint2 b = *reinterpret_cast<const uint2*>(jb + rr * kJW8 + 8);
+        const uint2 c = *reinterpret_cast<const uint2*>(jb + rr * kJW8 + 16);
+        const uint32_t d[6] = {a.x, a.y, b.x, b.y, c.x, c.y};   // d[k] = dword at x0-8+4k
+        const uint64_t w01 = pk64(d[0], d[1]), w12 = pk64(d[1], d[2]), w23 = pk64(d[2], d[3]);
+        const uint64_t w34 = pk64(d[3], d[4]), w45 = pk64(d[4], d[5]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = rr - i;
+            if (j < 0 || j > 7) continue;
+            acc[i][0] = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], acc[i][0]);
+            acc[i][0] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], acc[i][0]);
+            acc[i][1] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], acc[i][1]);
+            acc[i][1] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], acc[i][1]);
+            acc[i][2] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r0[j], acc[i][2]);
+            acc[i][2] = __builtin_amdgcn_qsad_pk_u16_u8(w34, r1[j], acc[i][2]);
+            acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w34, r0[j], acc[i][3]);
+            acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w45, r1[j], acc[i][3]);
+            acc8[i] = __builtin_amdgcn_sad_u8(d[4], r0[j], acc8[i]);
+            acc8[i] = __builtin_amdgcn_sad_u8(d[5], r1[j], acc8[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint16_t* rk = c_rank + (dy0 + i + kRadius) * kCand;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t lo = (uint32_t)acc[i][g], hi = (uint32_t)(acc[i][g] >> 32);
+            const uint32_t k0 = (lo << 16) | rk[4 * g + 0];
+            const uint32_t k1 = (lo & 0xffff0000u) | rk[4 * g + 1];
+            const uint32_t k2 = (hi << 16) | rk[4 * g + 2];
+            const uint32_t k3 = (hi & 0xffff0000u) | rk[4 * g + 3];
+            best = min(best, min(k0, k1));
+            best = min(best, min(k2, k3));
+        }
+        best = min(best, (acc8[i] << 16) | rk[16]);
+    }
+    // dy = +8 row, dx group q (dx = -8+4q .. -5+4q); lane q = 3 also dx = +8
+    {
+        uint64_t a4 = 0;
+        uint32_t a8 = 0;
+        const uint8_t* jr = sJ + (8 * by + 16) * kJW8 + 8 * bx + 4 * q;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t e0 = *reinterpret_cast<const uint32_t*>(jr + j * kJW8);
+            const uint32_t e1 = *reinterpret_cast<const uint32_t*>(jr + j * kJW8 + 4);
+            const uint32_t e2 = *reinterpret_cast<const uint32_t*>(jr + j * kJW8 + 8);
+            a4 = __builtin_amdgcn_qsad_pk_u16_u8(pk64(e0, e1), r0[j], a4);
+            a4 = __builtin_amdgcn_qsad_pk_u16_u8(pk64(e1, e2), r1[j], a4);
+            a8 = __builtin_amdgcn_sad_u8(e1, r0[j], a8);
+            a8 = __builtin_amdgcn_sad_u8(e2, r1[j], a8);
+        }
+        const uint16_t* rk = c_rank + (2 * kRadius) * kCand + 4 * q;
+        const uint32_t lo = (uint32_t)a4, hi = (uint32_t)(a4 >> 32);
+        best = min(best, min((lo << 16) | rk[0], (lo & 0xffff0000u) | rk[1]));
+        best = min(best, min((hi << 16) | rk[2], (hi & 0xffff0000u) | rk[3]));
+        if (q == 3) best = min(best, (a8 << 16) | c_rank[(2 * kRadius) * kCand + 16]);
+    }
+    return best;
+}
+
+// 10-bit search for one lane: returns the best key (SAD << 9 | rank).
+__device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
+    // ref block: 8 rows x 4 dwords (2 samples each)
+    uint32_t rf[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint4 v = *reinterpret_cast<const uint4*>(sI + ((8 * by + j) * 64 + 8 * bx) * 2);
+        rf[j][0] = v.x; rf[j][1] = v.y; rf[j][2] = v.z; rf[j][3] = v.w;
+    }
+    uint32_t best = 0xffffffffu;
+    constexpr int RB = kJW8 * 2;   // window row bytes
+    const int ndy = (q == 3) ? 5 : 4;
+    for (int i = 0; i < ndy; ++i) {
+        const int dy = -8 + 4 * q + i;
+        const uint16_t* rk = c_rank + (dy + kRadius) * kCand;
+        uint32_t acc[kCand];
+#pragma unroll
+        for (int k = 0; k < kCand; ++k) acc[k] = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            // samples x0-8 .. x0+15 of window row 8 + 8*by + dy + j: 12 dwords
+            const uint8_t* rowp = sJ + (8 * by + 8 + dy + j) * RB + 8 * bx * 2;
+            uint32_t d[12];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint4 v = *reinterpret_cast<const uint4*>(rowp + 16 * k);
+                d[4 * k] = v.x; d[4 * k + 1] = v.y; d[4 * k + 2] = v.z; d[4 * k + 3] = v.w;
+            }
+#pragma unroll
+            for (int dx = -8; dx <= 8; ++dx) {
+                const int s = dx + 8;       // sample offset of the candidate in the window row
+                uint32_t a = acc[dx + 8];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int so = s + 2 * m;   // sample index of the pair
+                    uint32_t c;
+                    if ((so & 1) == 0) c = d[so >> 1];
+                    else c = __builtin_amdgcn_alignbyte(d[(so >> 1) + 1], d[so >> 1], 2);
+                    a = __builtin_amdgcn_sad_u16(c, rf[j][m], a);
+                }
+                acc[dx + 8] = a;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kCand; ++k) best = min(best, (acc[k] << 9) | rk[k]);
+    }
+    return best;
+}
+
+// Moments of one lane's two rows of the block against the warped J.
+template <typename T>
+__device__ __forceinline__ void moments(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q,
+                                        int dx, int dy, int32_t m[5]) {
+    for (int k = 0; k < 5; ++k) m[k] = 0;
+    if constexpr (sizeof(T) == 1) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int j = 2 * q + jj;
+            const uint2 xv = *reinterpret_cast<const uint2*>(sI + (8 * by + j) * 64 + 8 * bx);
+            const int col = 8 * bx + 8 + dx;     // window byte column of the warped row
+            const uint8_t* jr = sJ + (8 * by + 8 + dy + j) * kJW8 + (col & ~3);
+            const uint32_t w0 = *reinterpret_cast<const uint32_t*>(jr);
+            const uint32_t w1 = *reinterpret_cast<const uint32_t*>(jr + 4);
+            const uint32_t w2 = ((col & 3) != 0) ? *reinterpret_cast<const uint32_t*>(jr + 8) : 0u;
+            const int sh = col & 3;
+            const uint32_t y0 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            const uint32_t y1 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+            m[0] += (int32_t)(__builtin_amdgcn_sad_u8(xv.x, 0u, 0u) + __builtin_amdgcn_sad_u8(xv.y, 0u, 0u));
+            m[1] += (int32_t)(__builtin_amdgcn_sad_u8(y0, 0u, 0u) + __builtin_amdgcn_sad_u8(y1, 0u, 0u));
+            m[2] += (int32_t)__builtin_amdgcn_udot4(xv.y, xv.y, __builtin_amdgcn_udot4(xv.x, xv.x, 0u, false), false);
+            m[3] += (int32_t)__builtin_amdgcn_udot4(y1, y1, __builtin_amdgcn_udot4(y0, y0, 0u, false), false);
+            m[4] += (int32_t)__builtin_amdgcn_udot4(xv.y, y1, __builtin_amdgcn_udot4(xv.x, y0, 0u, false), false);
+        }
+    } else {
+        constexpr int RB = kJW8 * 2;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int j = 2 * q + jj;
+            const uint16_t* xr = reinterpret_cast<const uint16_t*>(sI + ((8 * by + j) * 64 + 8 * bx) * 2);
+            const uint16_t* yr = reinterpret_cast<const uint16_t*>(sJ + (8 * by + 8 + dy + j) * RB) + 8 * bx + 8 + dx;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int32_t x = xr[i], y = yr[i];
+                m[0] += x; m[1] += y; m[2] += x * x; m[3] += y * y; m[4] += x * y;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t wave_sum(int32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Locate the task owning global tile `tile` in a prefix-sorted task list.
+__device__ __forceinline__ int find_task(const PairTask* tasks, int n, int tile) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].tile_prefix <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// SAD of one lane's two block rows at displacement (dx, dy) (debug output only).
+template <typename T>
+__device__ __forceinline__ int32_t rows_sad(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q,
+                                            int dx, int dy) {
+    constexpr int B = (int)sizeof(T);
+    int32_t s = 0;
+    for (int jj = 0; jj < 2; ++jj) {
+        const int j = 2 * q + jj;
+        const T* xr = reinterpret_cast<const T*>(sI + ((8 * by + j) * 64 + 8 * bx) * B);
+        const T* yr = reinterpret_cast<const T*>(sJ + (8 * by + 8 + dy + j) * kJW8 * B) + 8 * bx + 8 + dx;
+        for (int i = 0; i < 8; ++i) s += abs((int)xr[i] - (int)yr[i]);
+    }
+    return s;
+}
+
+template <typename T>
+__device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, TilePartial* part_out,
+                        int8_t* mv_out, int32_t* sad_out, uint8_t* sI, uint8_t* sJ, int64_t* red) {
+    const PlaneRef I = plane_of(sd, tk.ref, tk.ref_field, tk.level);
+    const PlaneRef J = plane_of(sd, tk.oth, tk.oth_field, tk.level);
+    const int nbx = I.w / kBlock, nby = I.h / kBlock;
+    const int tiles_x = div_up(nbx, kTBX);
+    const int bx0 = (local % tiles_x) * kTBX, by0 = (local / tiles_x) * kTBY;
+    stage_I<T>(I, bx0, by0, sI);
+    stage_J<T>(J, bx0, by0, sJ);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    const int b = tid >> 2, q = tid & 3;
+    const int bx = b & (kTBX - 1), by = b >> 3;
+    const bool valid = (bx0 + bx < nbx) && (by0 + by < nby);
+    int dx = 0, dy = 0;
+    if (!(tk.flags & TF_ZERO_MV)) {
+        uint32_t key = 0xffffffffu;
+        if (valid) {
+            if constexpr (sizeof(T) == 1) key = search8(sI, sJ, bx, by, q);
+            else key = search16(sI, sJ, bx, by, q);
+        }
+        key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
+        key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
+        const uint32_t rank = key & (sizeof(T) == 1 ? 0xffffu : 0x1ffu);
+        if (valid) {
+            const uint32_t u = c_unrank[rank];
+            dx = (int)(u & 0xff) - kRadius;
+            dy = (int)(u >> 8) - kRadius;
+        }
+    }
+    int32_t m[5] = {0, 0, 0, 0, 0};
+    int32_t a = 0;
+    if (valid) {
+        moments<T>(sI, sJ, bx, by, q, dx, dy, m);
+        if (q == 0) a = amm_fx(dx * dx + dy * dy);
+    }
+    const int blk = (by0 + by) * nbx + (bx0 + bx);
+    if (sad_out) {
+        int32_t s = valid ? rows_sad<T>(sI, sJ, bx, by, q, dx, dy) : 0;
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (valid && q == 0) sad_out[blk] = s;
+    }
+    if (mv_out && valid && q == 0) {
+        mv_out[2 * blk] = (int8_t)dx;
+        mv_out[2 * blk + 1] = (int8_t)dy;
+    }
+    // per-wave int32 sums are exact for 8- and 10-bit samples (16 blocks per wave)
+    const int32_t w0 = wave_sum(m[0]), w1 = wave_sum(m[1]), w2 = wave_sum(m[2]);
+    const int32_t w3 = wave_sum(m[3]), w4 = wave_sum(m[4]), w5 = wave_sum(a);
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
+        red[wave * 6 + 0] = w0; red[wave * 6 + 1] = w1; red[wave * 6 + 2] = w2;
+        red[wave * 6 + 3] = w3; red[wave * 6 + 4] = w4; red[wave * 6 + 5] = w5;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        TilePartial p;
+        p.sx = red[0] + red[6] + red[12] + red[18];
+        p.sy = red[1] + red[7] + red[13] + red[19];
+        p.sxx = red[2] + red[8] + red[14] + red[20];
+        p.syy = red[3] + red[9] + red[15] + red[21];
+        p.sxy = red[4] + red[10] + red[16] + red[22];
+        p.a = red[5] + red[11] + red[17] + red[23];
+        *part_out = p;
+    }
+    __syncthreads();   // LDS is reused by the next tile
+}
+
+}  // namespace
+
+// Persistent grid over the tiles of the consecutive-pair list (host-built) and
+// the sparse list (built on the device by the previous step's decision kernel).
+// One launch per sample width; tiles of the other width are skipped.
+template <typename T>
+__global__ void __launch_bounds__(kMEThreads) k_me(const StreamDesc* __restrict__ sds,
+                                                   const PairTask* __restrict__ consec, int32_t n_consec,
+                                                   int32_t consec_tiles, const PairTask* __restrict__ sparse,
+                                                   const DeviceCursors* __restrict__ cur,
+                                                   TilePartial* __restrict__ partials, int8_t* dbg_mv,
+                                                   int32_t* dbg_sad) {
+    __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
+    __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
+    __shared__ int64_t red[4 * 6];
+    const int n_sparse = cur ? cur->n_sparse : 0;
+    const int total = consec_tiles + (cur ? cur->sparse_tiles : 0);
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const PairTask* tk;
+        int local;
+        if (tile < consec_tiles) {
+            tk = consec + find_task(consec, n_consec, tile);
+            local = tile - tk->tile_prefix;
+        } else {
+            const int st = tile - consec_tiles;
+            tk = sparse + find_task(sparse, n_sparse, st);
+            local = st - tk->tile_prefix;
+        }
+        const StreamDesc& sd = sds[tk->sid];
+        if (!sd.active || sd.epoch != tk->epoch) continue;   // stream closed since planning
+        if (sd.bits != (sizeof(T) == 1 ? 8 : 10)) continue;
+        int8_t* mv = nullptr;
+        if (tk->flags & TF_MV_RING) mv = sd.mv + (int64_t)(tk->ref % sd.rs) * sd.B_L * 2;
+        else if (tk->flags & TF_DEBUG) mv = dbg_mv;
+        me_tile<T>(sd, *tk, local, partials + tile, mv, (tk->flags & TF_DEBUG) ? dbg_sad : nullptr,
+                   sI, sJ, red);
+    }
+}
+
+// NCC, SWR, AMM, ACT from the exact integers (operations in this order, no
+// contraction: this file is compiled with -ffp-contract=off).
+__device__ __forceinline__ void finish_pair(int64_t sx, int64_t sy, int64_t sxx, int64_t syy, int64_t sxy,
+                                         int64_t n, int64_t a, int64_t B, double a0, double out[4]) {
+    const int64_t cov = n * sxy - sx * sy;
+    const int64_t vx = n * sxx - sx * sx;
+    const int64_t vy = n * syy - sy * sy;
+    double ncc;
+    if (vx == 0 && vy == 0) ncc = 1.0;
+    else if (vx == 0 || vy == 0) ncc = 0.0;
+    else {
+        const double x3 = (double)vx * (double)vy;
+        const double x4 = __builtin_sqrt(x3);
+        const double c = (double)cov / x4;
+        ncc = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    }
+    const double swr = 1.0 - ncc;
+    const double amm = (double)a / (256.0 * (double)B);
+    const double act = __builtin_sqrt((amm + a0) * swr);
+    out[0] = ncc; out[1] = swr; out[2] = amm; out[3] = act;
+}
+
+// One wave per pair task: sum its tile partials and finish it.
+__global__ void __launch_bounds__(256) k_finish(const StreamDesc* __restrict__ sds,
+                                                const PairTask* __restrict__ consec, int32_t n_consec,
+                                                int32_t consec_tiles, const PairTask* __restrict__ sparse,
+                                                const DeviceCursors* __restrict__ cur,
+                                                const TilePartial* __restrict__ partials,
+                                                PairResult* __restrict__ results, DecideParams dp,
+                                                int64_t* dbg_ints, double* dbg_dbl) {
+    const int lane = threadIdx.x & 63;
+    const int total = n_consec + (cur ? cur->n_sparse : 0);
+    for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < total; t += gridDim.x * 4) {
+        const bool is_consec = t < n_consec;
+        const PairTask& tk = is_consec ? consec[t] : sparse[t - n_consec];
+        if (!sds[tk.sid].active || sds[tk.sid].epoch != tk.epoch) continue;
+        const int base = (is_consec ? 0 : consec_tiles) + tk.tile_prefix;
+        int64_t s[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = lane; i < tk.tiles; i += 64) {
+            const TilePartial& p = partials[base + i];
+            s[0] += p.sx; s[1] += p.sy; s[2] += p.sxx; s[3] += p.syy; s[4] += p.sxy; s[5] += p.a;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] = wave_sum64(s[k]);
+        if (lane != 0) continue;
+        const StreamDesc& sd = sds[tk.sid];
+        const PlaneRef P = plane_of(sd, tk.ref, tk.ref_field, tk.level);
+        const int64_t B = (int64_t)(P.w / kBlock) * (P.h / kBlock);
+        const int64_t n = 64 * B;
+        double f[4];
+        finish_pair(s[0], s[1], s[2], s[3], s[4], n, s[5], B, dp.a0, f);
+        if (tk.flags & TF_DEBUG) {
+            if (dbg_ints) {
+                dbg_ints[0] = s[0]; dbg_ints[1] = s[1]; dbg_ints[2] = s[2]; dbg_ints[3] = s[3];
+                dbg_ints[4] = s[4]; dbg_ints[5] = n; dbg_ints[6] = s[5]; dbg_ints[7] = B;
+                dbg_ints[8] = s[5] < (int64_t)dp.a_static_fx * B ? 1 : 0;
+            }
+            if (dbg_dbl) { dbg_dbl[0] = f[0]; dbg_dbl[1] = f[1]; dbg_dbl[2] = f[2]; dbg_dbl[3] = f[3]; }
+        }
+        if (is_consec) {
+            FrameInfo& fi = sd.info[tk.ref % sd.rs];
+            fi.ncc = f[0]; fi.swr = f[1]; fi.amm = f[2]; fi.act = f[3];
+            for (int k = 0; k < 5; ++k) fi.mom[k] = s[k];
+            fi.n_pix = n;
+            fi.amm_num = s[5];
+            fi.n_blocks = (int32_t)B;
+            fi.flags |= VSA_F_HAS_PAIR | (s[5] < (int64_t)dp.a_static_fx * B ? VSA_F_STATIC : 0);
+        } else if (tk.result >= 0) {
+            PairResult& r = results[(int64_t)tk.sid * kResSlots + tk.result];
+            r.act = f[3];
+            r.swr = f[1];
+        }
+    }
+}
+
+// The finishing arithmetic alone on n tuples (bitwise check against the host).
+__global__ void k_finish_debug(const int64_t* __restrict__ ints, int64_t n, double a0, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t* v = ints + 8 * i;
+    double f[4];
+    finish_pair(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], a0, f);
+    out[4 * i] = f[0]; out[4 * i + 1] = f[1]; out[4 * i + 2] = f[2]; out[4 * i + 3] = f[3];
+}
+
+hipError_t me_init_tables() {
+    // rank of (dx, dy) in the order (dx^2 + dy^2, dy, dx)
+    uint16_t rank[kCand * kCand], unrank[kCand * kCand];
+    int order[kCand * kCand];
+    for (int i = 0; i < kCand * kCand; ++i) order[i] = i;
+    auto keyf = [](int i) {
+        const int dx = i % kCand - kRadius, dy = i / kCand - kRadius;
+        return ((dx * dx + dy * dy) * 64 + (dy + kRadius)) * 64 + (dx + kRadius);
+    };
+    for (int i = 1; i < kCand * kCand; ++i) {   // insertion sort, 289 entries
+        const int v = order[i];
+        int j = i - 1;
+        while (j >= 0 && keyf(order[j]) > keyf(v)) { order[j + 1] = order[j]; --j; }
+        order[j + 1] = v;
+    }
+    for (int r = 0; r < kCand * kCand; ++r) {
+        const int i = order[r];
+        rank[i] = (uint16_t)r;
+        unrank[r] = (uint16_t)((i % kCand) | ((i / kCand) << 8));
+    }
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_rank), rank, sizeof rank);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_unrank), unrank, sizeof unrank);
+}
+
+hipError_t launch_me(int bits, const StreamDesc* sds, const PairTask* consec, int32_t n_consec,
+                     int32_t consec_tiles, const PairTask* sparse, const DeviceCursors* cur,
+                     TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (bits == 8)
+        hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
+                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad);
+    else
+        hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
+                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const StreamDesc* sds, const PairTask* consec, int32_t n_consec,
+                         int32_t consec_tiles, const PairTask* sparse, const DeviceCursors* cur,
+                         const TilePartial* partials, PairResult* results, const DecideParams& dp,
+                         int64_t* dbg_ints, double* dbg_dbl, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, s, sds, consec, n_consec, consec_tiles, sparse,
+                       cur, partials, results, dp, dbg_ints, dbg_dbl);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_debug(const int64_t* ints, int64_t n, double a0, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_finish_debug, dim3((unsigned)grid), dim3(256), 0, s, ints, n, a0, out);
+    return hipGetLastError();
+}
+
+}  // namespace vsa

@@ -1,0 +1,290 @@
+// k_pyramid.hip -- K1: luma pyramid and fields of every frame ingested in a step.
+//
+// Each frame level is the 2x2 box average of the level below, rounded half up
+// and applied once per level (a trailing odd row/column is dropped); the upper
+// field holds the even rows and the lower field the odd rows of the frame
+// (Sec. III.C), reduced the same way to the field level Lf = max(0, L-1).
+//
+// One 256-thread workgroup covers a 64 x 16 tile of the working level L.
+// Every thread reads a band of 2^L rows x 4*2^L columns of the luma plane with
+// 16-byte loads (the plane is read exactly once), reduces it level by level in
+// registers to 4 working-level pixels and 8 pixels of each field, and stores
+// them.  The coarser levels L+1..L+4 used by the long-range deep-check pairs
+// are reduced from the 64 x 16 tile held in LDS, so the full-resolution plane
+// is never read again.  The kernel is HBM-bound: bytes moved per frame are the
+// plane plus the levels written.
+#include "vsa_internal.h"
+
+namespace vsa {
+
+namespace {
+
+template <int N>
+struct Row {
+    int v[N];
+};
+
+template <int N>
+__device__ __forceinline__ Row<N / 2> down2(const Row<N>& a, const Row<N>& b) {
+    Row<N / 2> o;
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i)
+        o.v[i] = (a.v[2 * i] + a.v[2 * i + 1] + b.v[2 * i] + b.v[2 * i + 1] + 2) >> 2;
+    return o;
+}
+
+// Load NC samples of one luma row starting at column x0 (zeros past the edge;
+// such samples only feed outputs that are never stored).
+template <typename T, int NC>
+__device__ __forceinline__ void load_row(const uint8_t* rowp, int x0, int W, bool al16,
+                                         Row<NC>& o) {
+    const T* p = reinterpret_cast<const T*>(rowp) + x0;
+    constexpr int BYTES = NC * (int)sizeof(T);
+    if (x0 + NC <= W && al16 && BYTES % 16 == 0) {
+        const uint4* q = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+        for (int k = 0; k < BYTES / 16; ++k) {
+            const uint4 u = q[k];
+            uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (sizeof(T) == 1) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) o.v[16 * k + 4 * m + b] = (w4[m] >> (8 * b)) & 0xff;
+                } else {
+                    o.v[8 * k + 2 * m] = w4[m] & 0xffff;
+                    o.v[8 * k + 2 * m + 1] = w4[m] >> 16;
+                }
+            }
+        }
+    } else if (x0 + NC <= W && al16 && BYTES % 4 == 0) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+        for (int k = 0; k < BYTES / 4; ++k) {
+            uint32_t w = q[k];
+            if (sizeof(T) == 1) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) o.v[4 * k + b] = (w >> (8 * b)) & 0xff;
+            } else {
+                o.v[2 * k] = w & 0xffff;
+                o.v[2 * k + 1] = w >> 16;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) o.v[i] = (x0 + i < W) ? (int)p[i] : 0;
+    }
+}
+
+// Frame row at level l and field rows at level l-1 of a band of 2^l luma rows.
+template <int NC, int l>
+struct Band {
+    Row<(NC >> l)> f;
+    Row<(NC >> (l - 1))> u, d;
+};
+
+template <typename T, int NC, int l>
+__device__ __forceinline__ void build_band(const uint8_t* src, int64_t pitch, int y0, int x0, int W,
+                                           bool al16, Band<NC, l>& out) {
+    if constexpr (l == 1) {
+        Row<NC> a, b;
+        load_row<T, NC>(src + (int64_t)y0 * pitch, x0, W, al16, a);
+        load_row<T, NC>(src + (int64_t)(y0 + 1) * pitch, x0, W, al16, b);
+        out.f = down2<NC>(a, b);
+        out.u = a;
+        out.d = b;
+    } else {
+        Band<NC, l - 1> top, bot;
+        build_band<T, NC, l - 1>(src, pitch, y0, x0, W, al16, top);
+        build_band<T, NC, l - 1>(src, pitch, y0 + (1 << (l - 1)), x0, W, al16, bot);
+        out.f = down2<(NC >> (l - 1))>(top.f, bot.f);
+        out.u = down2<(NC >> (l - 2))>(top.u, bot.u);
+        out.d = down2<(NC >> (l - 2))>(top.d, bot.d);
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_row(uint8_t* dst, int x0, int w, const Row<N>& r) {
+    T* p = reinterpret_cast<T*>(dst) + x0;
+    if (x0 + N <= w) {
+        if constexpr (sizeof(T) == 1 && N == 4) {
+            *reinterpret_cast<uint32_t*>(p) =
+                (uint32_t)r.v[0] | ((uint32_t)r.v[1] << 8) | ((uint32_t)r.v[2] << 16) | ((uint32_t)r.v[3] << 24);
+            return;
+        } else if constexpr (sizeof(T) == 1 && N == 8) {
+            uint2 u;
+            u.x = (uint32_t)r.v[0] | ((uint32_t)r.v[1] << 8) | ((uint32_t)r.v[2] << 16) | ((uint32_t)r.v[3] << 24);
+            u.y = (uint32_t)r.v[4] | ((uint32_t)r.v[5] << 8) | ((uint32_t)r.v[6] << 16) | ((uint32_t)r.v[7] << 24);
+            *reinterpret_cast<uint2*>(p) = u;
+            return;
+        } else if constexpr (sizeof(T) == 2 && N == 4) {
+            uint2 u;
+            u.x = (uint32_t)r.v[0] | ((uint32_t)r.v[1] << 16);
+            u.y = (uint32_t)r.v[2] | ((uint32_t)r.v[3] << 16);
+            *reinterpret_cast<uint2*>(p) = u;
+            return;
+        } else if constexpr (sizeof(T) == 2 && N == 8) {
+            uint4 u;
+            u.x = (uint32_t)r.v[0] | ((uint32_t)r.v[1] << 16);
+            u.y = (uint32_t)r.v[2] | ((uint32_t)r.v[3] << 16);
+            u.z = (uint32_t)r.v[4] | ((uint32_t)r.v[5] << 16);
+            u.w = (uint32_t)r.v[6] | ((uint32_t)r.v[7] << 16);
+            *reinterpret_cast<uint4*>(p) = u;
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (x0 + i < w) p[i] = (T)r.v[i];
+}
+
+__device__ __forceinline__ uint8_t* slot_base(const StreamDesc& sd, int frame) {
+    return sd.ring + (int64_t)(frame % sd.rs) * sd.slot_bytes;
+}
+
+// Pyramid grid width (working-level columns) covering the level and the fields.
+__host__ __device__ inline int pyr_grid_w(const StreamDesc& sd) {
+    const int shift = sd.L - sd.Lf;          // 1 for L >= 1, 0 for L == 0
+    const int gw = (sd.wf + (1 << shift) - 1) >> shift;
+    return gw > sd.wl[0] ? gw : sd.wl[0];
+}
+
+template <typename T, int L>
+__device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int tile, uint16_t* lds) {
+    constexpr int S = 1 << L;
+    constexpr int NC = 4 * S;
+    const int tiles_x = div_up(pyr_grid_w(sd), kPyrTW);
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
+    const int X = tx * kPyrTW + 4 * c;        // first working-level column of this thread
+    const int YL = ty * kPyrTH + r;           // working-level row
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(ss.src);
+    const int64_t pitch = ss.src_pitch;
+    const bool al16 = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)pitch) & 15) == 0;
+    uint8_t* slot = slot_base(sd, ss.frame);
+    const int wL = sd.wl[0], hL = sd.hl[0];
+
+    Row<4> fl;
+    if (YL < sd.hl[0] || (L == 0 && YL < sd.H)) {
+        if constexpr (L == 0) {
+            Row<4> a;
+            load_row<T, 4>(src + (int64_t)YL * pitch, X, sd.W, al16, a);
+            fl = a;
+            // fields at level 0: even rows -> upper, odd rows -> lower
+            const int fy = YL >> 1;
+            if (fy < sd.hf) {
+                uint8_t* dst = slot + ((YL & 1) ? sd.offD : sd.offU) + (int64_t)fy * sd.pf * (int64_t)sizeof(T);
+                store_row<T, 4>(dst, X, sd.wf, a);
+            }
+        } else {
+            Band<NC, L> b;
+            build_band<T, NC, L>(src, pitch, YL * S, X * S, sd.W, al16, b);
+            fl = b.f;
+            if (YL < sd.hf) {
+                const int64_t rowoff = (int64_t)YL * sd.pf * (int64_t)sizeof(T);
+                store_row<T, 8>(slot + sd.offU + rowoff, 2 * X, sd.wf, b.u);
+                store_row<T, 8>(slot + sd.offD + rowoff, 2 * X, sd.wf, b.d);
+            }
+        }
+        if (YL < hL) store_row<T, 4>(slot + sd.off[0] + (int64_t)YL * sd.pl[0] * (int64_t)sizeof(T), X, wL, fl);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fl.v[i] = 0;
+    }
+    if (sd.nlev <= 1) return;
+    // coarser levels from the tile in LDS
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[r * kPyrTW + 4 * c + i] = (uint16_t)fl.v[i];
+    __syncthreads();
+    uint16_t* prev = lds;
+    uint16_t* next = lds + kPyrTW * kPyrTH;
+    int pw = kPyrTW, ph = kPyrTH;
+    for (int d = 1; d < sd.nlev; ++d) {
+        const int cw = pw >> 1, ch = ph >> 1;
+        const int i = threadIdx.x;
+        if (i < cw * ch) {
+            const int x = i % cw, y = i / cw;
+            const int v = (prev[(2 * y) * pw + 2 * x] + prev[(2 * y) * pw + 2 * x + 1] +
+                           prev[(2 * y + 1) * pw + 2 * x] + prev[(2 * y + 1) * pw + 2 * x + 1] + 2) >> 2;
+            next[y * cw + x] = (uint16_t)v;
+            const int gx = tx * (kPyrTW >> d) + x, gy = ty * (kPyrTH >> d) + y;
+            if (gx < sd.wl[d] && gy < sd.hl[d]) {
+                T* dst = reinterpret_cast<T*>(slot + sd.off[d]) + (int64_t)gy * sd.pl[d] + gx;
+                *dst = (T)v;
+            }
+        }
+        __syncthreads();
+        uint16_t* tmp = prev;
+        prev = next;
+        next = tmp;
+        pw = cw;
+        ph = ch;
+    }
+}
+
+}  // namespace
+
+// Grid: one workgroup per pyramid tile over all ingesting streams.
+__global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ sds,
+                                                  const StepStream* __restrict__ steps,
+                                                  const int32_t* __restrict__ k1_list, int32_t n_k1) {
+    __shared__ uint16_t lds[2 * kPyrTW * kPyrTH];
+    const int tile = blockIdx.x;
+    // locate the stream: last list entry whose first tile is <= tile
+    int lo = 0, hi = n_k1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (steps[k1_list[mid]].k1_prefix <= tile) lo = mid; else hi = mid - 1;
+    }
+    const StepStream& ss = steps[k1_list[lo]];
+    const int local = tile - ss.k1_prefix;
+    if (local < 0 || local >= ss.k1_tiles) return;
+    const StreamDesc& sd = sds[ss.sid];
+    if (local == 0 && threadIdx.x == 0) {
+        FrameInfo& fi = sd.info[ss.frame % sd.rs];
+        const double nan = __builtin_nan("");
+        fi.frame = ss.frame;
+        fi.pts = ss.pts;
+        fi.flags = ss.frame == 0 ? (VSA_F_KEYFRAME | VSA_F_SHOT_START) : 0;
+        fi.shot_id = -1;
+        fi.boundary = 0;
+        fi.boundary_k = 0;
+        fi.ncc = fi.swr = fi.amm = fi.act = nan;
+        for (int i = 0; i < 5; ++i) fi.mom[i] = 0;
+        fi.n_pix = 0;
+        fi.amm_num = 0;
+        fi.n_blocks = 0;
+        fi.field_mask = 0;
+        fi.v[0] = fi.v[1] = fi.v[2] = nan;
+    }
+    if (sd.bits == 8) {
+        switch (sd.L) {
+            case 0: pyramid_tile<uint8_t, 0>(sd, ss, local, lds); break;
+            case 1: pyramid_tile<uint8_t, 1>(sd, ss, local, lds); break;
+            case 2: pyramid_tile<uint8_t, 2>(sd, ss, local, lds); break;
+            case 3: pyramid_tile<uint8_t, 3>(sd, ss, local, lds); break;
+            default: pyramid_tile<uint8_t, 4>(sd, ss, local, lds); break;
+        }
+    } else {
+        switch (sd.L) {
+            case 0: pyramid_tile<uint16_t, 0>(sd, ss, local, lds); break;
+            case 1: pyramid_tile<uint16_t, 1>(sd, ss, local, lds); break;
+            case 2: pyramid_tile<uint16_t, 2>(sd, ss, local, lds); break;
+            case 3: pyramid_tile<uint16_t, 3>(sd, ss, local, lds); break;
+            default: pyramid_tile<uint16_t, 4>(sd, ss, local, lds); break;
+        }
+    }
+}
+
+int pyramid_tiles(const StreamDesc& sd) {
+    return div_up(pyr_grid_w(sd), kPyrTW) * div_up(sd.L == 0 ? sd.H : sd.hl[0], kPyrTH);
+}
+
+hipError_t launch_pyramid(const StreamDesc* sds, const StepStream* steps, const int32_t* k1_list,
+                          int32_t n_k1, int32_t total_tiles, hipStream_t s) {
+    if (n_k1 <= 0 || total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pyramid, dim3(total_tiles), dim3(256), 0, s, sds, steps, k1_list, n_k1);
+    return hipGetLastError();
+}
+
+}  // namespace vsa

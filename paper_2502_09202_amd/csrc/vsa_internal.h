@@ -1,0 +1,177 @@
+// vsa_internal.h -- device-side data layout shared by the HIP kernels and the
+// host runtime of libvsa (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vsa.h"
+
+namespace vsa {
+
+constexpr int kBlock = 8;           // block edge (pixels)
+constexpr int kRadius = 8;          // full-search radius (working pixels)
+constexpr int kCand = 2 * kRadius + 1;
+constexpr int kMaxLevels = 5;       // frame levels stored per ring slot: L .. L+4
+constexpr int kMaxKmax = 15;
+constexpr int kMaxHist = 32;
+constexpr int kMaxStreams = 1024;
+
+// Field selector of a plane inside a ring slot.
+enum : int32_t { PL_FRAME = 0, PL_UPPER = 1, PL_LOWER = 2 };
+
+// Measure kinds (also the "kind" of a logged key).
+enum : int32_t { MK_CONSEC = 0, MK_FIELD = 1, MK_DEEP_F = 2, MK_DEEP_P = 3 };
+
+// Geometry and device addresses of one open stream.
+struct StreamDesc {
+    int32_t active;
+    int32_t W, H, bits;
+    int32_t L, Lcap, Lf, ltop;        // frame levels L..ltop are stored
+    int32_t nlev;                     // ltop - L + 1
+    int32_t k_max;
+    int32_t rs;                       // ring slots (frames held)
+    int32_t wl[kMaxLevels], hl[kMaxLevels], pl[kMaxLevels];   // size and pitch (samples) per stored level
+    int64_t off[kMaxLevels];          // byte offset of each stored level in a slot
+    int32_t wf, hf, pf;               // field level size and pitch
+    int64_t offU, offD;               // byte offsets of the fields in a slot
+    int64_t slot_bytes;
+    uint8_t* ring;                    // rs slots
+    struct FrameInfo* info;           // rs entries
+    int8_t* mv;                       // rs x (B_L x 2)
+    int32_t B_L;                      // blocks at the working level
+    int32_t epoch;                    // bumped each time the slot is (re)opened
+};
+
+// Per-frame record under construction (one per ring slot).
+struct FrameInfo {
+    int64_t frame, pts;
+    int32_t flags, shot_id, boundary, boundary_k;
+    double ncc, swr, amm, act;
+    int64_t mom[5];
+    int64_t n_pix, amm_num;
+    int32_t n_blocks;
+    uint32_t field_mask;
+    double v[3];
+};
+
+// One pair measure to compute: ref -> oth planes of stream `sid`.
+struct PairTask {
+    int32_t sid;
+    int32_t kind;                     // MK_*
+    int32_t ref, oth;                 // frame indices
+    int32_t ref_field, oth_field;     // PL_*
+    int32_t level;                    // absolute pyramid level
+    int32_t result;                   // index into the stream's sparse result slots (-1: consecutive)
+    int32_t tiles;                    // ME tiles of the pair
+    int32_t tile_prefix;              // first tile of the pair within its list
+    int32_t flags;                    // TF_*
+    int32_t epoch;                    // StreamDesc::epoch when planned; stale tasks are skipped
+};
+
+enum : int32_t {
+    TF_MV_RING = 1,    // store the motion field in the stream's MV ring (consecutive pairs)
+    TF_DEBUG = 2,      // store motion field, SADs and integers in the debug buffers
+    TF_ZERO_MV = 4     // use d = (0, 0) for every block (no search)
+};
+
+// Result of a sparse pair measure.
+struct PairResult {
+    double act, swr;
+};
+
+// Sparse result slots of a stream: fields (3), deep forward F_K and deep
+// backward P_K for K = 1..kMaxKmax+1.
+constexpr int kResFields = 0;
+constexpr int kResF = 3;
+constexpr int kResP = kResF + kMaxKmax + 2;
+constexpr int kResSlots = kResP + kMaxKmax + 2;
+
+// Sampling-structure analysis of the open shot.
+struct Analysis {
+    int32_t open, n, nci, s, result, phase;
+    int32_t cm[5], np[5];
+    double sum1, sum2;
+};
+
+// Decision state of one stream.
+struct DecideState {
+    int32_t t;                  // next iteration of the sequential pass
+    int32_t n;                  // newest frame index ingested (-1: none)
+    int32_t T_end;              // total frames once the stream has ended, else -1
+    int32_t emitted;            // frames [0, emitted) have been written out
+    int32_t shot_start, shot_id;
+    int32_t hist_len, hist_head;
+    double hist[kMaxHist];
+    double acc;                 // keyframe accumulator
+    Analysis ss;
+    int32_t cur_in_boundary, cur_in_k;   // how the current shot began
+    // iteration planned in the previous step (its sparse measures are computed
+    // by this step's motion-search launch)
+    int32_t plan, plan_want, plan_fire, plan_deep, plan_nf, plan_kn;
+    int32_t done;               // end of stream fully processed
+    int32_t n_closed;           // shots closed by the last advance
+    int64_t log_count;          // sparse measures logged
+    vsa_shot_result closed[4];  // at most 3 per advance: a planned boundary, one
+                                // immediate boundary at the clip end, the last shot
+};
+
+// Engine-wide constants for the decision kernel.
+struct DecideParams {
+    int32_t w_hist, n_ss, dense, a_static_fx;
+    double a0, rho_f, theta_f, theta_f0, rho_d, theta_d, gamma, tau_c, eps, pd_agree, theta_kf;
+};
+
+// Per-step view of one stream (host -> device each step).
+struct StepStream {
+    int32_t sid;
+    int32_t has_frame;          // a frame was pushed for this step
+    int32_t frame;              // its index
+    int32_t ended_T;            // total frame count if the stream has ended, else -1
+    int64_t pts;
+    const void* src;            // plane to ingest
+    int64_t src_pitch;          // bytes
+    int32_t k1_tiles;           // pyramid tiles of this stream
+    int32_t k1_prefix;          // first pyramid tile
+    int32_t consec_tiles;       // ME tiles of its consecutive pair (0 if none)
+    int32_t consec_prefix;
+};
+
+// Output ring entries (device -> host).
+struct OutFrame {
+    int32_t sid, pad;
+    vsa_frame_result r;
+};
+struct OutShot {
+    int32_t sid, pad;
+    vsa_shot_result r;
+};
+
+// Counters and cursors in device memory.
+struct DeviceCursors {
+    uint64_t frames_written;     // monotonically increasing write cursor (OutFrame ring)
+    uint64_t shots_written;
+    int32_t n_sparse;            // sparse tasks planned for the next step
+    int32_t sparse_tiles;
+    uint64_t sparse_run;         // total sparse tasks planned
+};
+
+// ME tiling: a tile is TBX x TBY blocks, one 256-thread workgroup.
+constexpr int kTBX = 8;
+constexpr int kTBY = 8;
+constexpr int kMEThreads = 256;
+
+inline __host__ __device__ int div_up(int a, int b) { return (a + b - 1) / b; }
+inline __host__ __device__ int me_tiles(int w, int h) {
+    return div_up(w / kBlock, kTBX) * div_up(h / kBlock, kTBY);
+}
+
+// Per-tile partial sums of a pair (exact integers).
+struct TilePartial {
+    int64_t sx, sy, sxx, syy, sxy, a;
+};
+
+// Pyramid tile: TW x TH pixels of the working level, 256 threads.
+constexpr int kPyrTW = 64;
+constexpr int kPyrTH = 16;
+
+}  // namespace vsa

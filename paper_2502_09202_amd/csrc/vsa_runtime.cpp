@@ -1,0 +1,1060 @@
+// vsa_runtime.cpp -- host runtime and C ABI of libvsa (see include/vsa.h).
+//
+// One engine = one HIP stream of work on one device.  Every open stream owns
+// one device allocation: a ring of 2 k_max + 4 frame slots (working level,
+// the coarser levels used by the deep check and the two fields), the
+// per-frame records under construction, the motion fields of the
+// consecutive pairs, and two staging planes for copied input.  The engine
+// owns the tables shared by all streams (stream descriptors, decision state,
+// sparse results, the device-built sparse task list, tile partials and the
+// output rings).
+//
+// A time step (vsa_step) enqueues, in order on the engine stream:
+//   H2D   the step descriptor (which streams ingest which plane, the
+//         consecutive-pair tasks) and any host-sourced planes;
+//   K1    pyramid + fields of every ingested frame (one launch);
+//   K2    motion search + moments over the consecutive pairs of this step
+//         and the sparse pairs planned by the previous step (one persistent
+//         launch per sample width);
+//   K3    finish of every pair (NCC, SWR, AMM, ACT);
+//   K6    decisions, sparse-task compaction for the next step, records.
+// Nothing is copied back until vsa_sync, which drains the device output rings.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "vsa_internal.h"
+
+namespace vsa {
+hipError_t launch_pyramid(const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t, hipStream_t);
+int pyramid_tiles(const StreamDesc& sd);
+hipError_t me_init_tables();
+hipError_t launch_me(int bits, const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
+                     const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t);
+hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
+                         const DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
+                         double*, int grid, hipStream_t);
+hipError_t launch_finish_debug(const int64_t*, int64_t, double, double*, hipStream_t);
+hipError_t launch_decide(const StreamDesc*, DecideState*, const PairResult*, const StepStream*, int32_t,
+                         const DecideParams&, PairTask*, DeviceCursors*, OutFrame*, uint64_t, OutShot*, uint64_t,
+                         int32_t*, int64_t, hipStream_t);
+hipError_t launch_decide_replay(const StreamDesc&, DecideState*, PairResult*, const DecideParams&, int32_t,
+                                const double*, const double*, const uint8_t*, const double*, const double*,
+                                const double*, const double*, vsa_frame_result*, vsa_shot_result*, int32_t,
+                                int32_t*, int32_t*, int32_t, int32_t*, hipStream_t);
+}  // namespace vsa
+
+using namespace vsa;
+
+namespace {
+
+thread_local std::string g_err;
+
+vsa_status fail(vsa_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+vsa_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return VSA_E_DEVICE;
+}
+
+#define HIPCK(x, what)                                  \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr int kMaxTasksPerStream = 3 + 2 * (kMaxKmax + 1);
+constexpr uint64_t kFramesCap = 1u << 16;
+constexpr uint64_t kShotsCap = 1u << 14;
+constexpr int kDescRing = 8;
+constexpr int64_t kLogCapPerStream = 1 << 16;
+
+int ceil_log2(int k) {
+    int c = 0;
+    while ((1 << c) < k) ++c;
+    return c;
+}
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Geometry of a W x H stream (same definitions as the decision kernel uses).
+struct Geo {
+    int L = -1, Lcap = -1, Lf = 0, ltop = 0, nlev = 0;
+    int wl[kMaxLevels] = {0}, hl[kMaxLevels] = {0};
+    int wf = 0, hf = 0;
+};
+
+vsa_status make_geo(int W, int H, const vsa_params& p, int kmax, Geo& g) {
+    if (W <= 0 || H <= 0) return fail(VSA_E_INVAL, "frame size must be positive");
+    std::vector<int> ws, hs;
+    for (int w = W, h = H; w > 0 && h > 0; w /= 2, h /= 2) { ws.push_back(w); hs.push_back(h); }
+    g.L = -1;
+    for (size_t l = 0; l < ws.size(); ++l)
+        if (ws[l] <= p.wmax) { g.L = (int)l; break; }
+    if (g.L < 0 || ws[g.L] / 8 < 2 || hs[g.L] / 8 < 2)
+        return fail(VSA_E_INVAL, "working level smaller than a 2x2 grid of 8x8 blocks");
+    if (g.L > 4) return fail(VSA_E_UNSUPPORTED, "frames wider than 16 x wmax are not supported");
+    g.Lcap = g.L;
+    for (size_t l = g.L + 1; l < ws.size(); ++l) {
+        if (ws[l] / 8 >= 2 && hs[l] / 8 >= 2) g.Lcap = (int)l; else break;
+    }
+    g.Lf = std::max(0, g.L - 1);
+    g.wf = W >> g.Lf;
+    g.hf = (H / 2) >> g.Lf;
+    if (g.wf < 8 || g.hf < 8) return fail(VSA_E_INVAL, "field level smaller than one block");
+    g.ltop = std::min(g.L + ceil_log2(kmax + 1), g.Lcap);
+    g.nlev = g.ltop - g.L + 1;
+    if (g.nlev > kMaxLevels) return fail(VSA_E_UNSUPPORTED, "k_max too large");
+    for (int d = 0; d < g.nlev; ++d) { g.wl[d] = ws[g.L + d]; g.hl[d] = hs[g.L + d]; }
+    return VSA_OK;
+}
+
+vsa_status check_params(const vsa_params& p) {
+    if (p.block != 8 || p.radius != 8) return fail(VSA_E_UNSUPPORTED, "block must be 8 and radius 8");
+    if (p.lf_offset != 1) return fail(VSA_E_UNSUPPORTED, "lf_offset must be 1");
+    if (p.wmax < 16) return fail(VSA_E_INVAL, "wmax must be >= 16");
+    if (p.k_max < 1 || p.k_max > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
+    if (p.w_hist < 1 || p.w_hist > kMaxHist) return fail(VSA_E_INVAL, "w_hist must be in 1..32");
+    if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
+    return VSA_OK;
+}
+
+DecideParams decide_params(const vsa_params& p, int dense) {
+    DecideParams d;
+    d.w_hist = p.w_hist; d.n_ss = p.n_ss; d.dense = dense; d.a_static_fx = p.a_static_fx;
+    d.a0 = p.a0; d.rho_f = p.rho_f; d.theta_f = p.theta_f; d.theta_f0 = p.theta_f0; d.rho_d = p.rho_d; d.theta_d = p.theta_d;
+    d.gamma = p.gamma; d.tau_c = p.tau_c; d.eps = p.eps; d.pd_agree = p.pd_agree; d.theta_kf = p.theta_kf;
+    return d;
+}
+
+// Lay out one ring slot and fill the device descriptor (addresses excluded).
+void layout(const Geo& g, int W, int H, int bits, int kmax, StreamDesc& sd) {
+    std::memset(&sd, 0, sizeof sd);
+    const int b = bits == 8 ? 1 : 2;
+    sd.active = 1;
+    sd.W = W; sd.H = H; sd.bits = bits;
+    sd.L = g.L; sd.Lcap = g.Lcap; sd.Lf = g.Lf; sd.ltop = g.ltop; sd.nlev = g.nlev;
+    sd.k_max = kmax;
+    sd.rs = 2 * kmax + 4;
+    int64_t off = 0;
+    for (int d = 0; d < g.nlev; ++d) {
+        sd.wl[d] = g.wl[d]; sd.hl[d] = g.hl[d];
+        sd.pl[d] = (int)round_up(g.wl[d], 64);
+        sd.off[d] = off;
+        off = round_up(off + (int64_t)sd.pl[d] * g.hl[d] * b, 256);
+    }
+    sd.wf = g.wf; sd.hf = g.hf; sd.pf = (int)round_up(g.wf, 64);
+    sd.offU = off;
+    off = round_up(off + (int64_t)sd.pf * g.hf * b, 256);
+    sd.offD = off;
+    off = round_up(off + (int64_t)sd.pf * g.hf * b, 256);
+    sd.slot_bytes = off;
+    sd.B_L = (g.wl[0] / 8) * (g.hl[0] / 8);
+}
+
+int max_sparse_tiles(const StreamDesc& sd) {
+    int n = 3 * me_tiles(sd.wf, sd.hf);
+    for (int K = 1; K <= sd.k_max + 1; ++K) {
+        const int l = std::min(sd.L + ceil_log2(K), sd.Lcap);
+        const int d = l - sd.L;
+        n += (K >= 2 ? 2 : 1) * me_tiles(sd.wl[d], sd.hl[d]);
+    }
+    return n;
+}
+
+struct HostStream {
+    bool open = false;
+    vsa_stream_desc desc{};
+    StreamDesc sd{};
+    Geo geo;
+    uint8_t* mem = nullptr;
+    uint64_t bytes = 0;
+    uint8_t* staging_dev[2] = {nullptr, nullptr};
+    int64_t staging_pitch = 0;
+    int next_frame = 0;        // frames pushed
+    bool pending = false;      // a pushed frame waits for a step
+    int pend_mode = 0;
+    const void* pend_src = nullptr;
+    int64_t pend_pitch = 0;
+    int64_t pend_pts = 0;
+    bool ended = false;
+    int T_end = -1;
+    int frames_out = 0;
+    bool done = false;
+    int consec_tiles = 0;
+    int sparse_tiles_max = 0;
+    int epoch = 0;
+    std::deque<vsa_frame_result> fq;
+    std::deque<vsa_shot_result> sq;
+};
+
+}  // namespace
+
+struct vsa_engine {
+    std::mutex mu;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    vsa_params params{};
+    DecideParams dp{};
+    int schedule = 0;
+    int max_streams = 0;
+    uint64_t budget = 0, used = 0;
+    int debug_log = 0;
+    std::vector<HostStream> streams;
+    std::vector<int> slot_epoch;
+    // engine-wide device tables
+    StreamDesc* d_sds = nullptr;
+    DecideState* d_states = nullptr;
+    PairResult* d_results = nullptr;
+    PairTask* d_sparse = nullptr;
+    DeviceCursors* d_cur = nullptr;
+    OutFrame* d_out_frames = nullptr;
+    OutShot* d_out_shots = nullptr;
+    TilePartial* d_partials = nullptr;
+    int64_t partials_cap = 0;
+    int32_t* d_log = nullptr;
+    // step descriptors: device buffer + pinned host ring
+    uint8_t* d_desc = nullptr;
+    uint8_t* h_desc[kDescRing] = {nullptr};
+    hipEvent_t desc_ev[kDescRing] = {nullptr};
+    int desc_i = 0;
+    size_t desc_bytes = 0;
+    // host staging for VSA_SRC_HOST planes (per stream, 2 slots)
+    std::vector<uint8_t*> h_stage;
+    std::vector<hipEvent_t> stage_ev;
+    // output drain
+    uint64_t frames_read = 0, shots_read = 0;
+    OutFrame* h_out_frames = nullptr;
+    OutShot* h_out_shots = nullptr;
+    uint64_t emit_bound = 0;     // upper bound of frames emitted since the last sync
+    uint64_t shot_bound = 0;
+    int has10 = 0;
+    int me_grid = 0;
+    uint64_t counters[8] = {0};
+};
+
+namespace {
+
+size_t desc_size(int max_streams) {
+    return round_up(sizeof(StepStream) * max_streams, 256) + round_up(sizeof(int32_t) * max_streams, 256) +
+           round_up(sizeof(PairTask) * max_streams, 256);
+}
+
+vsa_status ensure_partials(vsa_engine* e) {
+    int64_t need = 0;
+    for (const HostStream& s : e->streams)
+        if (s.open) need += s.consec_tiles + s.sparse_tiles_max;
+    if (need <= e->partials_cap) return VSA_OK;
+    HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    if (e->d_partials) HIPCK(hipFree(e->d_partials), "hipFree");
+    e->d_partials = nullptr;
+    const int64_t cap = std::max<int64_t>(need * 2, 4096);
+    if (hipMalloc(&e->d_partials, sizeof(TilePartial) * cap) != hipSuccess) {
+        e->partials_cap = 0;
+        return fail(VSA_E_NOMEM, "tile partial buffer");
+    }
+    e->partials_cap = cap;
+    return VSA_OK;
+}
+
+uint64_t stream_bytes(const StreamDesc& sd, int64_t staging_pitch) {
+    const int64_t info = round_up((int64_t)sizeof(FrameInfo) * sd.rs, 256);
+    const int64_t mv = round_up((int64_t)sd.rs * sd.B_L * 2, 256);
+    const int64_t stage = 2 * round_up(staging_pitch * sd.H, 256);
+    return (uint64_t)(sd.slot_bytes * sd.rs + info + mv + stage);
+}
+
+vsa_status drain(vsa_engine* e) {
+    HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    DeviceCursors c;
+    HIPCK(hipMemcpy(&c, e->d_cur, sizeof c, hipMemcpyDeviceToHost), "read cursors");
+    auto copy_ring = [&](auto* d_ring, auto* h_buf, uint64_t cap, uint64_t from, uint64_t to) -> hipError_t {
+        using Elem = std::remove_pointer_t<decltype(d_ring)>;
+        uint64_t n = to - from;
+        uint64_t a = from % cap;
+        uint64_t first = std::min(n, cap - a);
+        hipError_t err = hipSuccess;
+        if (first) err = hipMemcpy(h_buf, d_ring + a, first * sizeof(Elem), hipMemcpyDeviceToHost);
+        if (err == hipSuccess && n > first)
+            err = hipMemcpy(h_buf + first, d_ring, (n - first) * sizeof(Elem), hipMemcpyDeviceToHost);
+        return err;
+    };
+    if (c.frames_written > e->frames_read) {
+        if (c.frames_written - e->frames_read > kFramesCap) return fail(VSA_E_DEVICE, "frame ring overflow");
+        HIPCK(copy_ring(e->d_out_frames, e->h_out_frames, kFramesCap, e->frames_read, c.frames_written), "drain frames");
+        for (uint64_t i = 0; i < c.frames_written - e->frames_read; ++i) {
+            const OutFrame& o = e->h_out_frames[i];
+            HostStream& s = e->streams[o.sid];
+            if (!s.open) continue;
+            s.fq.push_back(o.r);
+            s.frames_out += 1;
+        }
+        e->frames_read = c.frames_written;
+    }
+    if (c.shots_written > e->shots_read) {
+        if (c.shots_written - e->shots_read > kShotsCap) return fail(VSA_E_DEVICE, "shot ring overflow");
+        HIPCK(copy_ring(e->d_out_shots, e->h_out_shots, kShotsCap, e->shots_read, c.shots_written), "drain shots");
+        for (uint64_t i = 0; i < c.shots_written - e->shots_read; ++i) {
+            const OutShot& o = e->h_out_shots[i];
+            HostStream& s = e->streams[o.sid];
+            if (!s.open) continue;
+            s.sq.push_back(o.r);
+        }
+        e->shots_read = c.shots_written;
+    }
+    for (HostStream& s : e->streams)
+        if (s.open && s.ended && s.frames_out >= s.T_end) s.done = true;
+    e->emit_bound = 0;
+    e->shot_bound = 0;
+    e->counters[6] = c.sparse_run;
+    return VSA_OK;
+}
+
+void free_stream(vsa_engine* e, int sid) {
+    HostStream& s = e->streams[sid];
+    if (s.mem) (void)hipFree(s.mem);
+    e->used -= s.bytes;
+    s = HostStream();
+    StreamDesc z;
+    std::memset(&z, 0, sizeof z);
+    (void)hipMemcpy(e->d_sds + sid, &z, sizeof z, hipMemcpyHostToDevice);
+}
+
+void init_state(DecideState& st) {
+    std::memset(&st, 0, sizeof st);
+    st.t = 0;
+    st.n = -1;
+    st.T_end = -1;
+    st.ss.open = 1;
+    st.ss.phase = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vsa_abi_version(void) { return VSA_ABI_VERSION; }
+
+const char* vsa_last_error(void) { return g_err.c_str(); }
+
+void vsa_default_params(vsa_params* p) {
+    if (!p) return;
+    p->block = 8; p->radius = 8; p->wmax = 512; p->lf_offset = 1; p->k_max = 4;
+    p->a_static_fx = 64; p->w_hist = 8; p->n_ss = 20;
+    p->a0 = 1.0; p->rho_f = 2.0; p->theta_f = 0.10; p->theta_f0 = 1.0; p->rho_d = 3.0; p->theta_d = 0.20;
+    p->gamma = 0.90; p->tau_c = 0.5; p->eps = 0.2; p->pd_agree = 0.8; p->theta_kf = 3.0;
+}
+
+vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
+    if (!cfg || !out) return fail(VSA_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (cfg->max_streams < 1 || cfg->max_streams > kMaxStreams)
+        return fail(VSA_E_INVAL, "max_streams must be in 1..1024");
+    if (cfg->schedule != VSA_SCHEDULE_SPARSE && cfg->schedule != VSA_SCHEDULE_DENSE)
+        return fail(VSA_E_INVAL, "unknown schedule");
+    vsa_params p;
+    if (cfg->params) p = *cfg->params; else vsa_default_params(&p);
+    vsa_status st = check_params(p);
+    if (st != VSA_OK) return st;
+    int ndev = 0;
+    HIPCK(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(VSA_E_INVAL, "no such device");
+    HIPCK(hipSetDevice(cfg->device), "hipSetDevice");
+    HIPCK(me_init_tables(), "motion-search tables");
+    vsa_engine* e = new vsa_engine();
+    e->device = cfg->device;
+    e->params = p;
+    e->schedule = cfg->schedule;
+    e->dp = decide_params(p, cfg->schedule == VSA_SCHEDULE_DENSE);
+    e->max_streams = cfg->max_streams;
+    e->debug_log = cfg->debug_log;
+    e->streams.resize(cfg->max_streams);
+    e->slot_epoch.assign(cfg->max_streams, 0);
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    e->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    e->me_grid = cus * 8;
+    const int M = cfg->max_streams;
+    auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
+    bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && dalloc((void**)&e->d_sds, sizeof(StreamDesc) * M);
+    ok = ok && dalloc((void**)&e->d_states, sizeof(DecideState) * M);
+    ok = ok && dalloc((void**)&e->d_results, sizeof(PairResult) * M * kResSlots);
+    ok = ok && dalloc((void**)&e->d_sparse, sizeof(PairTask) * M * kMaxTasksPerStream);
+    ok = ok && dalloc((void**)&e->d_cur, sizeof(DeviceCursors));
+    ok = ok && dalloc((void**)&e->d_out_frames, sizeof(OutFrame) * kFramesCap);
+    ok = ok && dalloc((void**)&e->d_out_shots, sizeof(OutShot) * kShotsCap);
+    e->desc_bytes = desc_size(M);
+    ok = ok && dalloc((void**)&e->d_desc, e->desc_bytes);
+    for (int i = 0; ok && i < kDescRing; ++i) {
+        ok = hipHostMalloc((void**)&e->h_desc[i], e->desc_bytes, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&e->desc_ev[i], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipHostMalloc((void**)&e->h_out_frames, sizeof(OutFrame) * kFramesCap, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&e->h_out_shots, sizeof(OutShot) * kShotsCap, hipHostMallocDefault) == hipSuccess;
+    if (ok && e->debug_log) ok = dalloc((void**)&e->d_log, sizeof(int32_t) * 6 * kLogCapPerStream * M);
+    if (ok) {
+        ok = hipMemset(e->d_sds, 0, sizeof(StreamDesc) * M) == hipSuccess &&
+             hipMemset(e->d_cur, 0, sizeof(DeviceCursors)) == hipSuccess &&
+             hipMemset(e->d_results, 0, sizeof(PairResult) * M * kResSlots) == hipSuccess;
+    }
+    e->h_stage.assign(2 * M, nullptr);
+    e->stage_ev.assign(2 * M, nullptr);
+    if (!ok) {
+        vsa_engine_destroy(e);
+        return fail(VSA_E_NOMEM, "engine allocation failed");
+    }
+    *out = e;
+    return VSA_OK;
+}
+
+void vsa_engine_destroy(vsa_engine* e) {
+    if (!e) return;
+    (void)hipSetDevice(e->device);
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    for (size_t i = 0; i < e->streams.size(); ++i)
+        if (e->streams[i].mem) (void)hipFree(e->streams[i].mem);
+    for (uint8_t* h : e->h_stage) if (h) (void)hipHostFree(h);
+    for (hipEvent_t ev : e->stage_ev) if (ev) (void)hipEventDestroy(ev);
+    void* dev[] = {e->d_sds, e->d_states, e->d_results, e->d_sparse, e->d_cur, e->d_out_frames,
+                   e->d_out_shots, e->d_partials, e->d_log, e->d_desc};
+    for (void* p : dev) if (p) (void)hipFree(p);
+    for (int i = 0; i < kDescRing; ++i) {
+        if (e->h_desc[i]) (void)hipHostFree(e->h_desc[i]);
+        if (e->desc_ev[i]) (void)hipEventDestroy(e->desc_ev[i]);
+    }
+    if (e->h_out_frames) (void)hipHostFree(e->h_out_frames);
+    if (e->h_out_shots) (void)hipHostFree(e->h_out_shots);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+static vsa_status prepare_stream(const vsa_engine* e, const vsa_stream_desc* d, StreamDesc& sd, Geo& g,
+                                 int64_t& staging_pitch, uint64_t& bytes) {
+    if (!d) return fail(VSA_E_INVAL, "NULL stream description");
+    if (d->bit_depth != 8 && d->bit_depth != 10) return fail(VSA_E_INVAL, "bit_depth must be 8 or 10");
+    const int kmax = d->k_max ? d->k_max : e->params.k_max;
+    if (kmax < 1 || kmax > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
+    vsa_status st = make_geo(d->width, d->height, e->params, kmax, g);
+    if (st != VSA_OK) return st;
+    layout(g, d->width, d->height, d->bit_depth, kmax, sd);
+    // exact int64 covariance terms need N (Sxx) products to stay below 2^63
+    const int64_t maxv = d->bit_depth == 8 ? 255 : 1023;
+    const int64_t nmax = 64LL * std::max<int64_t>((int64_t)(sd.wf / 8) * (sd.hf / 8), sd.B_L);
+    if ((double)nmax * (double)nmax * (double)(maxv * maxv) >= 9.2e18)
+        return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit moments");
+    staging_pitch = round_up((int64_t)d->width * (d->bit_depth == 8 ? 1 : 2), 256);
+    bytes = stream_bytes(sd, staging_pitch);
+    return VSA_OK;
+}
+
+uint64_t vsa_stream_footprint(const vsa_engine* e, const vsa_stream_desc* d) {
+    if (!e) return 0;
+    StreamDesc sd;
+    Geo g;
+    int64_t sp;
+    uint64_t bytes;
+    if (prepare_stream(e, d, sd, g, sp, bytes) != VSA_OK) return 0;
+    return bytes + (uint64_t)(me_tiles(sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
+}
+
+vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid) {
+    if (!e || !sid) return fail(VSA_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    StreamDesc sd;
+    Geo g;
+    int64_t sp;
+    uint64_t bytes;
+    vsa_status st = prepare_stream(e, d, sd, g, sp, bytes);
+    if (st != VSA_OK) return st;
+    int slot = -1;
+    for (int i = 0; i < e->max_streams; ++i)
+        if (!e->streams[i].open) { slot = i; break; }
+    const uint64_t part = (uint64_t)(me_tiles(sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
+    if (slot < 0 || e->used + bytes + part > e->budget) {
+        e->counters[3] += 1;
+        return fail(VSA_E_ADMIT, slot < 0 ? "no free stream slot" : "HBM budget exhausted");
+    }
+    HostStream& s = e->streams[slot];
+    const int epoch = e->slot_epoch[slot] + 1;
+    e->slot_epoch[slot] = epoch;
+    sd.epoch = epoch;
+    uint8_t* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        e->counters[3] += 1;
+        return fail(VSA_E_ADMIT, "device allocation for the stream failed");
+    }
+    int64_t off = sd.slot_bytes * sd.rs;
+    sd.ring = mem;
+    sd.info = reinterpret_cast<FrameInfo*>(mem + off);
+    off += round_up((int64_t)sizeof(FrameInfo) * sd.rs, 256);
+    sd.mv = reinterpret_cast<int8_t*>(mem + off);
+    off += round_up((int64_t)sd.rs * sd.B_L * 2, 256);
+    s = HostStream();
+    s.open = true;
+    s.desc = *d;
+    s.sd = sd;
+    s.geo = g;
+    s.mem = mem;
+    s.bytes = bytes + part;
+    s.staging_pitch = sp;
+    s.staging_dev[0] = mem + off;
+    s.staging_dev[1] = mem + off + round_up(sp * sd.H, 256);
+    s.consec_tiles = me_tiles(sd.wl[0], sd.hl[0]);
+    s.sparse_tiles_max = max_sparse_tiles(sd);
+    s.epoch = epoch;
+    e->used += s.bytes;
+    DecideState ds;
+    init_state(ds);
+    hipError_t err = hipMemcpy(e->d_sds + slot, &sd, sizeof sd, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(e->d_states + slot, &ds, sizeof ds, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemset(sd.info, 0, sizeof(FrameInfo) * sd.rs);
+    if (err != hipSuccess) { free_stream(e, slot); return hip_fail(err, "stream init"); }
+    st = ensure_partials(e);
+    if (st != VSA_OK) { free_stream(e, slot); return st; }
+    if (sd.bits == 10) e->has10 = 1;
+    e->counters[2] += 1;
+    *sid = slot;
+    return VSA_OK;
+}
+
+static HostStream* get_stream(vsa_engine* e, int32_t sid) {
+    if (!e || sid < 0 || sid >= e->max_streams || !e->streams[sid].open) return nullptr;
+    return &e->streams[sid];
+}
+
+vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t pitch, int32_t src, int64_t pts) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    if (!luma) return fail(VSA_E_INVAL, "NULL plane");
+    const int64_t row = (int64_t)s->sd.W * (s->sd.bits == 8 ? 1 : 2);
+    if (pitch < row) return fail(VSA_E_INVAL, "pitch smaller than a row");
+    if (s->ended) return fail(VSA_E_STATE, "push after end of stream");
+    if (s->pending) return fail(VSA_E_AGAIN, "a frame is already waiting for a step");
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    const int slot = s->next_frame & 1;
+    if (src == VSA_SRC_HOST) {
+        const int k = 2 * sid + slot;
+        if (!e->h_stage[k]) {
+            HIPCK(hipHostMalloc((void**)&e->h_stage[k], s->staging_pitch * s->sd.H, hipHostMallocDefault), "pinned staging");
+            HIPCK(hipEventCreateWithFlags(&e->stage_ev[k], hipEventDisableTiming), "event");
+        } else {
+            HIPCK(hipEventSynchronize(e->stage_ev[k]), "staging reuse");
+        }
+        const uint8_t* p = static_cast<const uint8_t*>(luma);
+        for (int y = 0; y < s->sd.H; ++y) std::memcpy(e->h_stage[k] + y * s->staging_pitch, p + y * pitch, row);
+        s->pend_src = e->h_stage[k];
+        s->pend_pitch = s->staging_pitch;
+    } else if (src == VSA_SRC_DEVICE_COPY) {
+        HIPCK(hipMemcpy2DAsync(s->staging_dev[slot], s->staging_pitch, luma, pitch, row, s->sd.H,
+                               hipMemcpyDeviceToDevice, e->stream), "device copy");
+        HIPCK(hipStreamSynchronize(e->stream), "device copy");
+        s->pend_src = s->staging_dev[slot];
+        s->pend_pitch = s->staging_pitch;
+    } else if (src == VSA_SRC_DEVICE_BORROW) {
+        s->pend_src = luma;
+        s->pend_pitch = pitch;
+    } else {
+        return fail(VSA_E_INVAL, "unknown source kind");
+    }
+    s->pend_mode = src;
+    s->pend_pts = pts;
+    s->pending = true;
+    return VSA_OK;
+}
+
+vsa_status vsa_stream_end(vsa_engine* e, int32_t sid) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    if (s->ended) return fail(VSA_E_STATE, "stream already ended");
+    s->ended = true;
+    s->T_end = s->next_frame + (s->pending ? 1 : 0);
+    if (s->T_end == 0) s->done = true;
+    return VSA_OK;
+}
+
+int32_t vsa_stream_done(vsa_engine* e, int32_t sid) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    return s->done ? 1 : 0;
+}
+
+vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    hipStream_t user = static_cast<hipStream_t>(hip_stream);
+    // bound the output produced between syncs by the ring capacities
+    uint64_t step_frames = 0, step_shots = 0;
+    int n_open = 0;
+    for (const HostStream& s : e->streams)
+        if (s.open && !s.done) { step_frames += s.sd.rs; step_shots += 4; ++n_open; }
+    if (n_open == 0) return VSA_OK;
+    if (e->emit_bound + step_frames > kFramesCap || e->shot_bound + step_shots > kShotsCap) {
+        vsa_status st = drain(e);
+        if (st != VSA_OK) return st;
+    }
+    // step descriptor in a pinned ring slot
+    const int di = e->desc_i;
+    e->desc_i = (e->desc_i + 1) % kDescRing;
+    HIPCK(hipEventSynchronize(e->desc_ev[di]), "descriptor reuse");
+    uint8_t* h = e->h_desc[di];
+    const int M = e->max_streams;
+    StepStream* steps = reinterpret_cast<StepStream*>(h);
+    int32_t* k1 = reinterpret_cast<int32_t*>(h + round_up(sizeof(StepStream) * M, 256));
+    PairTask* consec = reinterpret_cast<PairTask*>(h + round_up(sizeof(StepStream) * M, 256) +
+                                                    round_up(sizeof(int32_t) * M, 256));
+    int n_steps = 0, n_k1 = 0, k1_tiles = 0, n_consec = 0, consec_tiles = 0;
+    for (int sid = 0; sid < M; ++sid) {
+        HostStream& s = e->streams[sid];
+        if (!s.open || s.done) continue;
+        StepStream& ss = steps[n_steps];
+        std::memset(&ss, 0, sizeof ss);
+        ss.sid = sid;
+        ss.has_frame = s.pending ? 1 : 0;
+        ss.frame = s.pending ? s.next_frame : -1;
+        ss.ended_T = s.ended ? s.T_end : -1;
+        ss.pts = s.pend_pts;
+        if (s.pending) {
+            const int slot = s.next_frame & 1;
+            if (s.pend_mode == VSA_SRC_HOST) {
+                HIPCK(hipMemcpyAsync(s.staging_dev[slot], s.pend_src, s.staging_pitch * s.sd.H,
+                                     hipMemcpyHostToDevice, e->stream), "plane upload");
+                HIPCK(hipEventRecord(e->stage_ev[2 * sid + slot], e->stream), "event");
+                ss.src = s.staging_dev[slot];
+            } else {
+                ss.src = s.pend_src;
+            }
+            ss.src_pitch = s.pend_pitch;
+            ss.k1_tiles = pyramid_tiles(s.sd);
+            ss.k1_prefix = k1_tiles;
+            k1_tiles += ss.k1_tiles;
+            k1[n_k1++] = n_steps;
+            if (s.next_frame >= 1) {
+                PairTask& t = consec[n_consec++];
+                std::memset(&t, 0, sizeof t);
+                t.sid = sid;
+                t.kind = MK_CONSEC;
+                t.ref = s.next_frame - 1;
+                t.oth = s.next_frame;
+                t.ref_field = t.oth_field = PL_FRAME;
+                t.level = s.sd.L;
+                t.result = -1;
+                t.tiles = s.consec_tiles;
+                t.tile_prefix = consec_tiles;
+                t.flags = TF_MV_RING;
+                t.epoch = s.sd.epoch;
+                consec_tiles += t.tiles;
+                ss.consec_tiles = t.tiles;
+                ss.consec_prefix = t.tile_prefix;
+            }
+        }
+        ++n_steps;
+    }
+    const size_t off_k1 = round_up(sizeof(StepStream) * M, 256);
+    const size_t off_consec = off_k1 + round_up(sizeof(int32_t) * M, 256);
+    if (user) {
+        hipEvent_t ev;
+        HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        HIPCK(hipEventRecord(ev, user), "event");
+        HIPCK(hipStreamWaitEvent(e->stream, ev, 0), "wait");
+        (void)hipEventDestroy(ev);
+    }
+    HIPCK(hipMemcpyAsync(e->d_desc, h, off_consec + sizeof(PairTask) * std::max(n_consec, 1),
+                         hipMemcpyHostToDevice, e->stream), "descriptor upload");
+    HIPCK(hipEventRecord(e->desc_ev[di], e->stream), "event");
+    const StepStream* d_steps = reinterpret_cast<const StepStream*>(e->d_desc);
+    const int32_t* d_k1 = reinterpret_cast<const int32_t*>(e->d_desc + off_k1);
+    const PairTask* d_consec = reinterpret_cast<const PairTask*>(e->d_desc + off_consec);
+    HIPCK(launch_pyramid(e->d_sds, d_steps, d_k1, n_k1, k1_tiles, e->stream), "pyramid launch");
+    // persistent motion-search grid: enough workgroups for the largest possible step
+    int64_t max_tiles = consec_tiles;
+    for (const HostStream& s : e->streams) if (s.open && !s.done) max_tiles += s.sparse_tiles_max;
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), e->me_grid);
+    HIPCK(launch_me(8, e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials, nullptr,
+                    nullptr, grid, e->stream), "motion search launch");
+    if (e->has10)
+        HIPCK(launch_me(10, e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials,
+                        nullptr, nullptr, grid, e->stream), "motion search launch");
+    const int max_tasks = n_consec + n_steps * kMaxTasksPerStream;
+    const int fgrid = std::min(std::max((max_tasks + 3) / 4, 1), 1024);
+    HIPCK(launch_finish(e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials,
+                        e->d_results, e->dp, nullptr, nullptr, fgrid, e->stream), "finish launch");
+    HIPCK(launch_decide(e->d_sds, e->d_states, e->d_results, d_steps, n_steps, e->dp, e->d_sparse, e->d_cur,
+                        e->d_out_frames, kFramesCap, e->d_out_shots, kShotsCap, e->d_log, kLogCapPerStream,
+                        e->stream), "decide launch");
+    if (user) {
+        hipEvent_t ev;
+        HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        HIPCK(hipEventRecord(ev, e->stream), "event");
+        HIPCK(hipStreamWaitEvent(user, ev, 0), "wait");
+        (void)hipEventDestroy(ev);
+    }
+    for (HostStream& s : e->streams)
+        if (s.open && s.pending) { s.pending = false; s.next_frame += 1; }
+    e->emit_bound += step_frames;
+    e->shot_bound += step_shots;
+    e->counters[0] += 1;
+    e->counters[7] += (uint64_t)n_consec;
+    return VSA_OK;
+}
+
+vsa_status vsa_sync(vsa_engine* e) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    return drain(e);
+}
+
+int32_t vsa_poll_frames(vsa_engine* e, int32_t sid, vsa_frame_result* out, int32_t cap) {
+    if (!e || (!out && cap > 0) || cap < 0) return fail(VSA_E_INVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    int32_t n = 0;
+    while (n < cap && !s->fq.empty()) { out[n++] = s->fq.front(); s->fq.pop_front(); }
+    return n;
+}
+
+int32_t vsa_poll_shots(vsa_engine* e, int32_t sid, vsa_shot_result* out, int32_t cap) {
+    if (!e || (!out && cap > 0) || cap < 0) return fail(VSA_E_INVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    int32_t n = 0;
+    while (n < cap && !s->sq.empty()) { out[n++] = s->sq.front(); s->sq.pop_front(); }
+    return n;
+}
+
+vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv, int32_t cap_blocks,
+                          int32_t* nbx, int32_t* nby) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    const int bx = s->sd.wl[0] / 8, by = s->sd.hl[0] / 8;
+    if (nbx) *nbx = bx;
+    if (nby) *nby = by;
+    if (!mv) return VSA_OK;
+    if (cap_blocks < bx * by) return fail(VSA_E_INVAL, "output too small");
+    // pair (frame -> frame+1) exists once frame+1 has been stepped and is still in the ring
+    if (frame < 0 || frame + 1 >= s->next_frame || frame < s->next_frame - s->sd.rs)
+        return fail(VSA_E_INVAL, "frame not held on the device");
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream), "sync");
+    HIPCK(hipMemcpy(mv, s->sd.mv + (frame % s->sd.rs) * s->sd.B_L * 2, (size_t)s->sd.B_L * 2,
+                    hipMemcpyDeviceToHost), "motion copy");
+    return VSA_OK;
+}
+
+vsa_status vsa_stream_close(vsa_engine* e, int32_t sid) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream), "sync");
+    // records of this stream still in the device ring are dropped at the next drain
+    vsa_status st = drain(e);
+    free_stream(e, sid);
+    bool any10 = false;
+    for (const HostStream& o : e->streams) if (o.open && o.sd.bits == 10) any10 = true;
+    e->has10 = any10;
+    return st;
+}
+
+vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out8) {
+    if (!e || !out8) return fail(VSA_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    int open = 0;
+    for (const HostStream& s : e->streams) if (s.open) ++open;
+    e->counters[1] = (uint64_t)open;
+    e->counters[4] = e->used;
+    e->counters[5] = e->budget;
+    std::memcpy(out8, e->counters, sizeof e->counters);
+    return VSA_OK;
+}
+
+int32_t vsa_debug_measure_log(vsa_engine* e, int32_t sid, int32_t* keys, int32_t cap) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    if (!e->d_log) return fail(VSA_E_STATE, "engine created without debug_log");
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream), "sync");
+    DecideState st;
+    HIPCK(hipMemcpy(&st, e->d_states + sid, sizeof st, hipMemcpyDeviceToHost), "state");
+    const int64_t n = std::min<int64_t>(st.log_count, kLogCapPerStream);
+    if (keys && cap > 0) {
+        const int64_t m = std::min<int64_t>(n, cap);
+        HIPCK(hipMemcpy(keys, e->d_log + (int64_t)sid * kLogCapPerStream * 6, sizeof(int32_t) * 6 * m,
+                        hipMemcpyDeviceToHost), "log");
+    }
+    return (int32_t)n;
+}
+
+// ---- test hooks -------------------------------------------------------------
+
+vsa_status vsa_debug_levels(const vsa_params* pp, const void* luma, int32_t W, int32_t H, int64_t pitch,
+                            int32_t bits, uint16_t* out, int64_t cap, int64_t* n_out) {
+    if (!luma || (bits != 8 && bits != 10)) return fail(VSA_E_INVAL, "bad argument");
+    vsa_params p;
+    if (pp) p = *pp; else vsa_default_params(&p);
+    vsa_status st = check_params(p);
+    if (st != VSA_OK) return st;
+    Geo g;
+    st = make_geo(W, H, p, kMaxKmax, g);
+    if (st != VSA_OK) return st;
+    const int b = bits == 8 ? 1 : 2;
+    if (pitch < (int64_t)W * b) return fail(VSA_E_INVAL, "pitch smaller than a row");
+    StreamDesc sd;
+    layout(g, W, H, bits, kMaxKmax, sd);
+    sd.rs = 1;
+    int64_t n = 0;
+    for (int d = 0; d < sd.nlev; ++d) n += (int64_t)sd.wl[d] * sd.hl[d];
+    n += 2 * (int64_t)sd.wf * sd.hf;
+    if (n_out) *n_out = n;
+    if (!out) return VSA_OK;
+    if (cap < n) return fail(VSA_E_INVAL, "output too small");
+    uint8_t *ring = nullptr, *plane = nullptr, *dsd = nullptr, *ddesc = nullptr;
+    FrameInfo* info = nullptr;
+    std::vector<uint8_t> host(sd.slot_bytes);
+    hipError_t err = hipMalloc(&ring, sd.slot_bytes);
+    if (err == hipSuccess) err = hipMalloc(&plane, pitch * H);
+    if (err == hipSuccess) err = hipMalloc(&info, sizeof(FrameInfo));
+    if (err == hipSuccess) err = hipMalloc(&dsd, sizeof(StreamDesc));
+    if (err == hipSuccess) err = hipMalloc(&ddesc, sizeof(StepStream) + 256);
+    if (err == hipSuccess) err = hipMemset(ring, 0, sd.slot_bytes);
+    if (err == hipSuccess) err = hipMemcpy(plane, luma, pitch * H, hipMemcpyHostToDevice);
+    sd.ring = ring;
+    sd.info = info;
+    StepStream ss;
+    std::memset(&ss, 0, sizeof ss);
+    ss.sid = 0; ss.has_frame = 1; ss.frame = 0; ss.ended_T = -1;
+    ss.src = plane; ss.src_pitch = pitch;
+    ss.k1_tiles = pyramid_tiles(sd);
+    ss.k1_prefix = 0;
+    int32_t k1idx = 0;
+    if (err == hipSuccess) err = hipMemcpy(dsd, &sd, sizeof sd, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(ddesc, &ss, sizeof ss, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(ddesc + 256, &k1idx, sizeof k1idx, hipMemcpyHostToDevice);
+    if (err == hipSuccess)
+        err = launch_pyramid(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<StepStream*>(ddesc),
+                             reinterpret_cast<int32_t*>(ddesc + 256), 1, ss.k1_tiles, nullptr);
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    if (err == hipSuccess) err = hipMemcpy(host.data(), ring, sd.slot_bytes, hipMemcpyDeviceToHost);
+    for (void* q : {(void*)ring, (void*)plane, (void*)info, (void*)dsd, (void*)ddesc}) if (q) (void)hipFree(q);
+    if (err != hipSuccess) return hip_fail(err, "debug levels");
+    int64_t k = 0;
+    auto put = [&](int64_t off, int w, int h, int pitch_s) {
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x) {
+                const int64_t o = off + ((int64_t)y * pitch_s + x) * b;
+                out[k++] = b == 1 ? host[o] : (uint16_t)(host[o] | (host[o + 1] << 8));
+            }
+    };
+    for (int d = 0; d < sd.nlev; ++d) put(sd.off[d], sd.wl[d], sd.hl[d], sd.pl[d]);
+    put(sd.offU, sd.wf, sd.hf, sd.pf);
+    put(sd.offD, sd.wf, sd.hf, sd.pf);
+    return VSA_OK;
+}
+
+vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_t* J, int32_t w, int32_t h,
+                          int32_t bits, int32_t force_zero_mv, int8_t* mv, int32_t* sad, int64_t* ints,
+                          double* dbl) {
+    if (!I || !J || (bits != 8 && bits != 10) || w < 8 || h < 8) return fail(VSA_E_INVAL, "bad argument");
+    vsa_params p;
+    if (pp) p = *pp; else vsa_default_params(&p);
+    vsa_status st = check_params(p);
+    if (st != VSA_OK) return st;
+    const int b = bits == 8 ? 1 : 2;
+    const int maxv = bits == 8 ? 255 : 1023;
+    for (int64_t i = 0; i < (int64_t)w * h; ++i)
+        if (I[i] > maxv || J[i] > maxv) return fail(VSA_E_INVAL, "sample out of range");
+    HIPCK(me_init_tables(), "motion-search tables");
+    StreamDesc sd;
+    std::memset(&sd, 0, sizeof sd);
+    sd.active = 1; sd.W = w; sd.H = h; sd.bits = bits; sd.L = 0; sd.Lcap = 0; sd.Lf = 0; sd.ltop = 0;
+    sd.nlev = 1; sd.k_max = 1; sd.rs = 2;
+    sd.wl[0] = w; sd.hl[0] = h; sd.pl[0] = (int)round_up(w, 64); sd.off[0] = 0;
+    sd.wf = w; sd.hf = h; sd.pf = sd.pl[0]; sd.offU = sd.offD = 0;
+    sd.slot_bytes = round_up((int64_t)sd.pl[0] * h * b, 256);
+    sd.B_L = (w / 8) * (h / 8);
+    std::vector<uint8_t> host(2 * sd.slot_bytes, 0);
+    for (int s = 0; s < 2; ++s) {
+        const uint16_t* src = s == 0 ? I : J;
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x) {
+                const int64_t o = s * sd.slot_bytes + ((int64_t)y * sd.pl[0] + x) * b;
+                host[o] = (uint8_t)(src[(int64_t)y * w + x] & 0xff);
+                if (b == 2) host[o + 1] = (uint8_t)(src[(int64_t)y * w + x] >> 8);
+            }
+    }
+    PairTask t;
+    std::memset(&t, 0, sizeof t);
+    t.sid = 0; t.kind = MK_CONSEC; t.ref = 0; t.oth = 1; t.level = 0; t.result = -1;
+    t.tiles = me_tiles(w, h); t.tile_prefix = 0;
+    t.flags = TF_DEBUG | (force_zero_mv ? TF_ZERO_MV : 0);
+    uint8_t *ring = nullptr, *dsd = nullptr, *dt = nullptr;
+    FrameInfo* info = nullptr;
+    TilePartial* part = nullptr;
+    int8_t* dmv = nullptr;
+    int32_t* dsad = nullptr;
+    int64_t* dints = nullptr;
+    double* ddbl = nullptr;
+    const int B = sd.B_L;
+    hipError_t err = hipMalloc(&ring, host.size());
+    if (err == hipSuccess) err = hipMalloc(&dsd, sizeof sd);
+    if (err == hipSuccess) err = hipMalloc(&dt, sizeof t);
+    if (err == hipSuccess) err = hipMalloc(&info, 2 * sizeof(FrameInfo));
+    if (err == hipSuccess) err = hipMalloc(&part, sizeof(TilePartial) * t.tiles);
+    if (err == hipSuccess) err = hipMalloc(&dmv, 2 * (size_t)B);
+    if (err == hipSuccess) err = hipMalloc(&dsad, sizeof(int32_t) * B);
+    if (err == hipSuccess) err = hipMalloc(&dints, sizeof(int64_t) * 9);
+    if (err == hipSuccess) err = hipMalloc(&ddbl, sizeof(double) * 4);
+    sd.ring = ring;
+    sd.info = info;
+    if (err == hipSuccess) err = hipMemcpy(ring, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(dsd, &sd, sizeof sd, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(dt, &t, sizeof t, hipMemcpyHostToDevice);
+    const DecideParams dp = decide_params(p, 0);
+    if (err == hipSuccess)
+        err = launch_me(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
+                        nullptr, nullptr, part, dmv, dsad, std::min(t.tiles, 1024), nullptr);
+    if (err == hipSuccess)
+        err = launch_finish(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
+                            nullptr, nullptr, part, nullptr, dp, dints, ddbl, 1, nullptr);
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    if (err == hipSuccess && mv) err = hipMemcpy(mv, dmv, 2 * (size_t)B, hipMemcpyDeviceToHost);
+    if (err == hipSuccess && sad) err = hipMemcpy(sad, dsad, sizeof(int32_t) * B, hipMemcpyDeviceToHost);
+    if (err == hipSuccess && ints) err = hipMemcpy(ints, dints, sizeof(int64_t) * 9, hipMemcpyDeviceToHost);
+    if (err == hipSuccess && dbl) err = hipMemcpy(dbl, ddbl, sizeof(double) * 4, hipMemcpyDeviceToHost);
+    for (void* q : {(void*)ring, (void*)dsd, (void*)dt, (void*)info, (void*)part, (void*)dmv, (void*)dsad,
+                    (void*)dints, (void*)ddbl})
+        if (q) (void)hipFree(q);
+    if (err != hipSuccess) return hip_fail(err, "debug pair");
+    return VSA_OK;
+}
+
+vsa_status vsa_debug_finish(const int64_t* ints, int64_t n, double a0, double* out) {
+    if (!ints || !out || n < 0) return fail(VSA_E_INVAL, "bad argument");
+    if (n == 0) return VSA_OK;
+    for (int64_t i = 0; i < n; ++i)
+        if (ints[8 * i + 5] <= 0 || ints[8 * i + 7] <= 0) return fail(VSA_E_INVAL, "N and B must be positive");
+    int64_t* di = nullptr;
+    double* dd = nullptr;
+    hipError_t err = hipMalloc(&di, sizeof(int64_t) * 8 * n);
+    if (err == hipSuccess) err = hipMalloc(&dd, sizeof(double) * 4 * n);
+    if (err == hipSuccess) err = hipMemcpy(di, ints, sizeof(int64_t) * 8 * n, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = launch_finish_debug(di, n, a0, dd, nullptr);
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    if (err == hipSuccess) err = hipMemcpy(out, dd, sizeof(double) * 4 * n, hipMemcpyDeviceToHost);
+    if (di) (void)hipFree(di);
+    if (dd) (void)hipFree(dd);
+    if (err != hipSuccess) return hip_fail(err, "debug finish");
+    return VSA_OK;
+}
+
+vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, int32_t T, const double* act,
+                            const double* swr, const uint8_t* stat, const double* v, const double* F,
+                            const double* S, const double* P, vsa_frame_result* recs, vsa_shot_result* shots,
+                            int32_t shots_cap, int32_t* n_shots, int32_t* keys, int32_t keys_cap,
+                            int32_t* n_keys) {
+    if (T < 1 || !act || !swr || !stat || !v || !F || !S || !P || !recs || (!shots && shots_cap > 0))
+        return fail(VSA_E_INVAL, "bad argument");
+    vsa_params p;
+    if (pp) p = *pp; else vsa_default_params(&p);
+    vsa_status st = check_params(p);
+    if (st != VSA_OK) return st;
+    const int kmax = k_max ? k_max : p.k_max;
+    if (kmax < 1 || kmax > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
+    StreamDesc sd;
+    std::memset(&sd, 0, sizeof sd);
+    sd.active = 1; sd.k_max = kmax; sd.rs = 2 * kmax + 4; sd.L = 0; sd.Lcap = kMaxLevels - 1;
+    sd.ltop = kMaxLevels - 1; sd.nlev = kMaxLevels; sd.Lf = 0;
+    for (int d = 0; d < kMaxLevels; ++d) { sd.wl[d] = 16; sd.hl[d] = 16; }
+    sd.wf = 16; sd.hf = 16;
+    const int kw = kmax + 2;
+    const size_t nT = (size_t)T;
+    DecideState ds;
+    init_state(ds);
+    const DecideParams dp = decide_params(p, dense);
+    uint8_t* mem = nullptr;
+    size_t off[16];
+    size_t sz = 0;
+    auto reserve = [&](int i, size_t bytes) { off[i] = sz; sz += round_up(bytes, 256); };
+    reserve(0, sizeof(FrameInfo) * sd.rs);
+    reserve(1, sizeof(DecideState));
+    reserve(2, sizeof(PairResult) * kResSlots);
+    reserve(3, sizeof(double) * nT);
+    reserve(4, sizeof(double) * nT);
+    reserve(5, nT);
+    reserve(6, sizeof(double) * 3 * nT);
+    reserve(7, sizeof(double) * kw * nT);
+    reserve(8, sizeof(double) * kw * nT);
+    reserve(9, sizeof(double) * kw * nT);
+    reserve(10, sizeof(vsa_frame_result) * nT);
+    reserve(11, sizeof(vsa_shot_result) * std::max(shots_cap, 1));
+    reserve(12, sizeof(int32_t) * 2);
+    const int log_cap = std::max(keys_cap, 0);
+    reserve(13, sizeof(int32_t) * 6 * std::max(log_cap, 1));
+    hipError_t err = hipMalloc(&mem, sz);
+    if (err != hipSuccess) return hip_fail(err, "debug decide");
+    auto at = [&](int i) { return mem + off[i]; };
+    sd.info = reinterpret_cast<FrameInfo*>(at(0));
+    err = hipMemset(mem, 0, sz);
+    if (err == hipSuccess) err = hipMemcpy(at(1), &ds, sizeof ds, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(3), act, sizeof(double) * nT, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(4), swr, sizeof(double) * nT, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(5), stat, nT, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(6), v, sizeof(double) * 3 * nT, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(7), F, sizeof(double) * kw * nT, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(8), S, sizeof(double) * kw * nT, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(at(9), P, sizeof(double) * kw * nT, hipMemcpyHostToDevice);
+    int32_t counts[2] = {0, 0};
+    if (err == hipSuccess)
+        err = launch_decide_replay(sd, reinterpret_cast<DecideState*>(at(1)), reinterpret_cast<PairResult*>(at(2)),
+                                   dp, T, reinterpret_cast<double*>(at(3)), reinterpret_cast<double*>(at(4)),
+                                   reinterpret_cast<uint8_t*>(at(5)), reinterpret_cast<double*>(at(6)),
+                                   reinterpret_cast<double*>(at(7)), reinterpret_cast<double*>(at(8)),
+                                   reinterpret_cast<double*>(at(9)), reinterpret_cast<vsa_frame_result*>(at(10)),
+                                   reinterpret_cast<vsa_shot_result*>(at(11)), shots_cap,
+                                   reinterpret_cast<int32_t*>(at(12)), keys ? reinterpret_cast<int32_t*>(at(13)) : nullptr,
+                                   log_cap, reinterpret_cast<int32_t*>(at(12)) + 1, nullptr);
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    if (err == hipSuccess) err = hipMemcpy(recs, at(10), sizeof(vsa_frame_result) * nT, hipMemcpyDeviceToHost);
+    if (err == hipSuccess) err = hipMemcpy(counts, at(12), sizeof counts, hipMemcpyDeviceToHost);
+    if (err == hipSuccess && shots && shots_cap > 0)
+        err = hipMemcpy(shots, at(11), sizeof(vsa_shot_result) * std::min(counts[0], shots_cap), hipMemcpyDeviceToHost);
+    if (err == hipSuccess && keys && log_cap > 0)
+        err = hipMemcpy(keys, at(13), sizeof(int32_t) * 6 * std::min(counts[1], log_cap), hipMemcpyDeviceToHost);
+    (void)hipFree(mem);
+    if (err != hipSuccess) return hip_fail(err, "debug decide");
+    if (n_shots) *n_shots = counts[0];
+    if (n_keys) *n_keys = counts[1];
+    return VSA_OK;
+}
+
+}  // extern "C"

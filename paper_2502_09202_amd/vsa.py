@@ -1,0 +1,369 @@
+"""Python binding of libvsa (argument marshalling only).
+
+Every function here forwards to the C ABI of the same name in
+``include/vsa.h`` (``vsa_<name>``).  All computation runs in the library's
+HIP kernels; if the library is missing this module raises instead of falling
+back to anything else.  PyTorch is optional: device planes can be handed over
+as raw device pointers, or as CUDA tensors through :func:`stream_push_tensor`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvsa.so")
+DEFAULT_PARAMS_JSON = os.path.join(HERE, "params", "default.json")
+
+OK, E_INVAL, E_NOMEM, E_ADMIT, E_STATE, E_DEVICE, E_AGAIN, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+SCHEDULE_SPARSE, SCHEDULE_DENSE = 0, 1
+SRC_HOST, SRC_DEVICE_COPY, SRC_DEVICE_BORROW = 0, 1, 2
+F_HAS_PAIR, F_STATIC, F_FAST_FIRED, F_IN_TRANSITION = 1, 2, 4, 8
+F_KEYFRAME, F_SHOT_START, F_ANALYZED = 16, 32, 64
+SAMPLING_NAMES = {0: "undetermined", 1: "progressive", 2: "tff", 3: "bff", 4: "pulldown32"}
+
+
+class VsaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vsa error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("block", C.c_int32), ("radius", C.c_int32), ("wmax", C.c_int32),
+        ("lf_offset", C.c_int32), ("k_max", C.c_int32), ("a_static_fx", C.c_int32),
+        ("w_hist", C.c_int32), ("n_ss", C.c_int32),
+        ("a0", C.c_double), ("rho_f", C.c_double), ("theta_f", C.c_double), ("theta_f0", C.c_double),
+        ("rho_d", C.c_double), ("theta_d", C.c_double), ("gamma", C.c_double),
+        ("tau_c", C.c_double), ("eps", C.c_double), ("pd_agree", C.c_double),
+        ("theta_kf", C.c_double),
+    ]
+
+
+class EngineConfig(C.Structure):
+    _fields_ = [
+        ("device", C.c_int32), ("max_streams", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
+        ("schedule", C.c_int32), ("use_graph", C.c_int32), ("params", C.POINTER(Params)),
+        ("debug_log", C.c_int32), ("me_tile", C.c_int32),
+    ]
+
+
+class StreamDesc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bit_depth", C.c_int32),
+                ("fps_num", C.c_int32), ("fps_den", C.c_int32), ("k_max", C.c_int32)]
+
+
+FRAME_DTYPE = np.dtype([
+    ("frame", "<i8"), ("pts", "<i8"), ("flags", "<i4"), ("shot_id", "<i4"), ("boundary", "<i4"),
+    ("boundary_k", "<i4"), ("ncc", "<f8"), ("swr", "<f8"), ("amm", "<f8"), ("act", "<f8"),
+    ("mom", "<i8", (5,)), ("n_pix", "<i8"), ("amm_num", "<i8"), ("n_blocks", "<i4"),
+    ("field_mask", "<u4"), ("v", "<f8", (3,)),
+])
+SHOT_DTYPE = np.dtype([
+    ("shot_id", "<i4"), ("pad0", "<i4"), ("first", "<i8"), ("last", "<i8"),
+    ("in_boundary", "<i4"), ("in_k", "<i4"), ("sampling", "<i4"), ("pulldown_phase", "<i4"),
+    ("n_analyzed", "<i4"), ("final", "<i4"),
+])
+KEY_DTYPE = np.dtype([("kind", "<i4"), ("ref", "<i4"), ("oth", "<i4"), ("ref_field", "<i4"),
+                      ("oth_field", "<i4"), ("level", "<i4")])
+
+# every symbol the header declares
+SYMBOLS = [
+    "vsa_abi_version", "vsa_default_params", "vsa_engine_create", "vsa_engine_destroy",
+    "vsa_stream_footprint", "vsa_stream_open", "vsa_stream_push", "vsa_stream_end",
+    "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
+    "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_last_error",
+    "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
+    "vsa_debug_measure_log",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libvsa.so (built in-tree by paper_2502_09202_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2502_09202_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32, i64, u64 = C.c_int32, C.c_int64, C.c_uint64
+    sig = {
+        "vsa_abi_version": (i32, []),
+        "vsa_default_params": (None, [C.POINTER(Params)]),
+        "vsa_engine_create": (i32, [C.POINTER(EngineConfig), C.POINTER(P)]),
+        "vsa_engine_destroy": (None, [P]),
+        "vsa_stream_footprint": (u64, [P, C.POINTER(StreamDesc)]),
+        "vsa_stream_open": (i32, [P, C.POINTER(StreamDesc), C.POINTER(i32)]),
+        "vsa_stream_push": (i32, [P, i32, P, i64, i32, i64]),
+        "vsa_stream_end": (i32, [P, i32]),
+        "vsa_stream_done": (i32, [P, i32]),
+        "vsa_step": (i32, [P, P]),
+        "vsa_sync": (i32, [P]),
+        "vsa_poll_frames": (i32, [P, i32, P, i32]),
+        "vsa_poll_shots": (i32, [P, i32, P, i32]),
+        "vsa_get_motion": (i32, [P, i32, i64, P, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "vsa_stream_close": (i32, [P, i32]),
+        "vsa_engine_counters": (i32, [P, P]),
+        "vsa_last_error": (C.c_char_p, []),
+        "vsa_debug_levels": (i32, [C.POINTER(Params), P, i32, i32, i64, i32, P, i64, C.POINTER(i64)]),
+        "vsa_debug_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i32, i32, P, P, P, P]),
+        "vsa_debug_finish": (i32, [P, i64, C.c_double, P]),
+        "vsa_debug_decide": (i32, [C.POINTER(Params), i32, i32, i32, P, P, P, P, P, P, P, P, P, i32,
+                                   C.POINTER(i32), P, i32, C.POINTER(i32)]),
+        "vsa_debug_measure_log": (i32, [P, i32, P, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().vsa_last_error().decode(errors="replace")
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise VsaError(rc, f"{what}: {last_error()}")
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def abi_version() -> int:
+    return lib().vsa_abi_version()
+
+
+def default_params() -> dict:
+    p = Params()
+    lib().vsa_default_params(C.byref(p))
+    return {k: getattr(p, k) for k, _ in Params._fields_}
+
+
+def load_params(path: Optional[str] = None) -> dict:
+    with open(path or DEFAULT_PARAMS_JSON) as f:
+        return json.load(f)
+
+
+def make_params(d: Optional[dict]) -> Params:
+    p = Params()
+    lib().vsa_default_params(C.byref(p))
+    for k, v in (d or {}).items():
+        setattr(p, k, v)
+    return p
+
+
+class Engine:
+    """An engine handle; see vsa_engine_create."""
+
+    def __init__(self, device: int = 0, max_streams: int = 64, hbm_budget_bytes: int = 0,
+                 schedule: int = SCHEDULE_SPARSE, use_graph: int = 0, params: Optional[dict] = None,
+                 debug_log: int = 0):
+        self._params = make_params(params)
+        cfg = EngineConfig(device=device, max_streams=max_streams, hbm_budget_bytes=hbm_budget_bytes,
+                           schedule=schedule, use_graph=use_graph,
+                           params=C.pointer(self._params), debug_log=debug_log, me_tile=0)
+        h = C.c_void_p()
+        _check(lib().vsa_engine_create(C.byref(cfg), C.byref(h)), "engine_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().vsa_engine_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- streams
+    def footprint(self, width, height, bit_depth=8, k_max=0, fps=(25, 1)) -> int:
+        d = StreamDesc(width, height, bit_depth, fps[0], fps[1], k_max)
+        return int(lib().vsa_stream_footprint(self.h, C.byref(d)))
+
+    def stream_open(self, width, height, bit_depth=8, k_max=0, fps=(25, 1)) -> int:
+        d = StreamDesc(width, height, bit_depth, fps[0], fps[1], k_max)
+        sid = C.c_int32(-1)
+        _check(lib().vsa_stream_open(self.h, C.byref(d), C.byref(sid)), "stream_open")
+        return sid.value
+
+    def stream_push(self, sid: int, plane, pts: int = 0) -> int:
+        """Push a host numpy plane (uint8 / uint16), copied before return."""
+        a = np.ascontiguousarray(plane)
+        return lib().vsa_stream_push(self.h, sid, _ptr(a), a.strides[0], SRC_HOST, pts)
+
+    def stream_push_device(self, sid: int, dev_ptr: int, pitch_bytes: int, mode: int = SRC_DEVICE_BORROW,
+                           pts: int = 0) -> int:
+        return lib().vsa_stream_push(self.h, sid, C.c_void_p(dev_ptr), pitch_bytes, mode, pts)
+
+    def stream_push_tensor(self, sid: int, t, mode: int = SRC_DEVICE_BORROW, pts: int = 0) -> int:
+        """Push a 2-D CUDA tensor (uint8 / int16 / uint16 samples) by device pointer."""
+        assert t.dim() == 2 and t.is_cuda and t.stride(1) == 1
+        return self.stream_push_device(sid, t.data_ptr(), t.stride(0) * t.element_size(), mode, pts)
+
+    def stream_end(self, sid: int):
+        _check(lib().vsa_stream_end(self.h, sid), "stream_end")
+
+    def stream_done(self, sid: int) -> bool:
+        return bool(_check(lib().vsa_stream_done(self.h, sid), "stream_done"))
+
+    def stream_close(self, sid: int):
+        _check(lib().vsa_stream_close(self.h, sid), "stream_close")
+
+    # -- steps
+    def step(self, hip_stream: Optional[int] = None):
+        _check(lib().vsa_step(self.h, C.c_void_p(hip_stream) if hip_stream else None), "step")
+
+    def sync(self):
+        _check(lib().vsa_sync(self.h), "sync")
+
+    def poll_frames(self, sid: int, cap: int = 4096) -> np.ndarray:
+        out = np.zeros(cap, FRAME_DTYPE)
+        n = _check(lib().vsa_poll_frames(self.h, sid, _ptr(out), cap), "poll_frames")
+        return out[:n].copy()
+
+    def poll_shots(self, sid: int, cap: int = 1024) -> np.ndarray:
+        out = np.zeros(cap, SHOT_DTYPE)
+        n = _check(lib().vsa_poll_shots(self.h, sid, _ptr(out), cap), "poll_shots")
+        return out[:n].copy()
+
+    def get_motion(self, sid: int, frame: int) -> np.ndarray:
+        nbx, nby = C.c_int32(0), C.c_int32(0)
+        _check(lib().vsa_get_motion(self.h, sid, frame, None, 0, C.byref(nbx), C.byref(nby)), "get_motion")
+        mv = np.zeros((nby.value, nbx.value, 2), np.int8)
+        _check(lib().vsa_get_motion(self.h, sid, frame, _ptr(mv), nbx.value * nby.value,
+                                    C.byref(nbx), C.byref(nby)), "get_motion")
+        return mv
+
+    def counters(self) -> dict:
+        out = np.zeros(8, np.uint64)
+        _check(lib().vsa_engine_counters(self.h, _ptr(out)), "engine_counters")
+        keys = ("steps", "streams_open", "admitted", "refused", "bytes_in_use", "budget",
+                "sparse_tasks", "consecutive_tasks")
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def measure_log(self, sid: int) -> np.ndarray:
+        n = _check(lib().vsa_debug_measure_log(self.h, sid, None, 0), "debug_measure_log")
+        out = np.zeros(max(n, 1), KEY_DTYPE)
+        _check(lib().vsa_debug_measure_log(self.h, sid, _ptr(out), n), "debug_measure_log")
+        return out[:n].copy()
+
+
+def run_clip(frames: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8, dense: bool = False,
+             k_max: int = 0, device: int = 0, debug_log: bool = False, want_mv: bool = False):
+    """Push a whole host clip [T, H, W] through one stream; returns records and shots."""
+    T, H, W = frames.shape
+    with Engine(device=device, max_streams=1, params=params,
+                schedule=SCHEDULE_DENSE if dense else SCHEDULE_SPARSE, debug_log=int(debug_log)) as e:
+        sid = e.stream_open(W, H, bit_depth, k_max)
+        recs, shots, mvs = [], [], []
+        for t in range(T):
+            _check(e.stream_push(sid, frames[t], pts=t), "stream_push")
+            if t == T - 1:
+                e.stream_end(sid)
+            e.step()
+            if want_mv and t >= 1:
+                e.sync()
+                mvs.append(e.get_motion(sid, t - 1))
+        guard = 0
+        while not e.stream_done(sid):
+            e.step()
+            e.sync()
+            guard += 1
+            if guard > 4 * (T + 64):
+                raise VsaError(E_STATE, "stream did not finish")
+        e.sync()
+        recs.append(e.poll_frames(sid, T + 16))
+        shots.append(e.poll_shots(sid, T + 16))
+        out = {"frames": np.concatenate(recs), "shots": np.concatenate(shots)}
+        if debug_log:
+            out["keys"] = e.measure_log(sid)
+        if want_mv:
+            out["mv"] = np.stack(mvs) if mvs else np.zeros((0,), np.int8)
+        return out
+
+
+# -- test hooks ---------------------------------------------------------------
+
+def debug_levels(plane: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8) -> np.ndarray:
+    a = np.ascontiguousarray(plane)
+    H, W = a.shape
+    p = make_params(params)
+    n = C.c_int64(0)
+    _check(lib().vsa_debug_levels(C.byref(p), _ptr(a), W, H, a.strides[0], bit_depth, None, 0, C.byref(n)),
+           "debug_levels")
+    out = np.zeros(n.value, np.uint16)
+    _check(lib().vsa_debug_levels(C.byref(p), _ptr(a), W, H, a.strides[0], bit_depth, _ptr(out), out.size,
+                                  C.byref(n)), "debug_levels")
+    return out
+
+
+def debug_pair(I: np.ndarray, J: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8,
+               force_zero_mv: bool = False) -> dict:
+    I = np.ascontiguousarray(I, dtype=np.uint16)
+    J = np.ascontiguousarray(J, dtype=np.uint16)
+    h, w = I.shape
+    B = (w // 8) * (h // 8)
+    mv = np.zeros((max(B, 1), 2), np.int8)
+    sad = np.zeros(max(B, 1), np.int32)
+    ints = np.zeros(9, np.int64)
+    dbl = np.zeros(4, np.float64)
+    p = make_params(params)
+    _check(lib().vsa_debug_pair(C.byref(p), _ptr(I), _ptr(J), w, h, bit_depth, int(force_zero_mv), _ptr(mv),
+                                _ptr(sad), _ptr(ints), _ptr(dbl)), "debug_pair")
+    keys = ("sx", "sy", "sxx", "syy", "sxy", "n", "a", "B", "static")
+    out = {k: int(v) for k, v in zip(keys, ints)}
+    out.update(ncc=float(dbl[0]), swr=float(dbl[1]), amm=float(dbl[2]), act=float(dbl[3]))
+    out["mv"] = mv[:B].reshape(h // 8, w // 8, 2)
+    out["sad"] = sad[:B].reshape(h // 8, w // 8)
+    return out
+
+
+def debug_finish(ints: np.ndarray, a0: float) -> np.ndarray:
+    v = np.ascontiguousarray(ints, dtype=np.int64).reshape(-1, 8)
+    out = np.zeros((v.shape[0], 4), np.float64)
+    _check(lib().vsa_debug_finish(_ptr(v), v.shape[0], float(a0), _ptr(out)), "debug_finish")
+    return out
+
+
+def debug_decide(seq: dict, params: Optional[dict] = None, dense: bool = False, k_max: int = 0) -> dict:
+    p = make_params(params)
+    km = k_max or p.k_max
+    T = len(seq["act"])
+    kw = km + 2
+    act = np.ascontiguousarray(seq["act"], np.float64)
+    swr = np.ascontiguousarray(seq["swr"], np.float64)
+    stat = np.ascontiguousarray(seq["static"], np.uint8)
+    v = np.ascontiguousarray(seq["v"], np.float64).reshape(T, 3)
+    F = np.ascontiguousarray(seq["F"], np.float64).reshape(T, kw)
+    S = np.ascontiguousarray(seq["S"], np.float64).reshape(T, kw)
+    P = np.ascontiguousarray(seq["P"], np.float64).reshape(T, kw)
+    recs = np.zeros(T, FRAME_DTYPE)
+    shots = np.zeros(T + 1, SHOT_DTYPE)
+    kcap = T * (4 + 2 * kw) + 16
+    keys = np.zeros(kcap, KEY_DTYPE)
+    ns, nk = C.c_int32(0), C.c_int32(0)
+    _check(lib().vsa_debug_decide(C.byref(p), km, int(dense), T, _ptr(act), _ptr(swr), _ptr(stat), _ptr(v),
+                                  _ptr(F), _ptr(S), _ptr(P), _ptr(recs), _ptr(shots), shots.size, C.byref(ns),
+                                  _ptr(keys), kcap, C.byref(nk)), "debug_decide")
+    return {"frames": recs, "shots": shots[:ns.value].copy(), "keys": keys[:nk.value].copy()}

@@ -1,0 +1,63 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol include/vsa.h
+declares, its built-in defaults equal the shipped parameter file, and calls
+fail cleanly (status codes, no crash) where no GPU is present."""
+import ctypes as C
+import json
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "vsa.h")).read()
+    decl = re.findall(r"^(?:const\s+)?[A-Za-z_0-9]+\s*\*?\s*(vsa_[a-z_0-9]+)\(", text, re.M)
+    return sorted(set(decl))
+
+
+def test_header_declares_binding_symbols(vsa):
+    assert declared_symbols() == sorted(vsa.SYMBOLS)
+
+
+def test_library_exports_every_symbol(vsa):
+    lib = vsa.lib()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", vsa.LIB_PATH], capture_output=True, text=True).stdout
+    for name in declared_symbols():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_abi_version(vsa):
+    assert vsa.abi_version() == 1
+
+
+def test_defaults_match_parameter_file(vsa, params):
+    d = vsa.default_params()
+    assert set(d) == set(params)
+    for k, v in params.items():
+        assert d[k] == v, k
+
+
+def test_errors_without_device(vsa):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(vsa.VsaError) as ei:
+        vsa.Engine()
+    assert ei.value.code in (vsa.E_DEVICE, vsa.E_INVAL)
+    assert vsa.last_error()
+
+
+def test_null_arguments(vsa):
+    lib = vsa.lib()
+    assert lib.vsa_engine_create(None, None) == vsa.E_INVAL
+    lib.vsa_engine_destroy(None)   # no-op
+    assert lib.vsa_step(None, None) == vsa.E_INVAL
+    assert lib.vsa_sync(None) == vsa.E_INVAL
+    assert lib.vsa_poll_frames(None, 0, None, 0) == vsa.E_INVAL
+    assert lib.vsa_stream_footprint(None, None) == 0
+    assert lib.vsa_debug_finish(None, 1, C.c_double(1.0), None) == vsa.E_INVAL

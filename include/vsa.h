@@ -68,7 +68,7 @@ typedef struct {
     int32_t lf_offset;    /* field level Lf = max(0, L - lf_offset); must be 1               */
     int32_t k_max;        /* default longest transition tested by the deep check (1..15)     */
     int32_t a_static_fx;  /* pair is STATIC if A < a_static_fx * B (A in 1/256 px)           */
-    int32_t w_hist;       /* fast-check history length (1..32)                               */
+    int32_t w_hist;       /* fast-check history length (1..16)                               */
     int32_t n_ss;         /* frames analysed per shot for sampling structure                 */
     double a0;            /* ACT = sqrt((AMM + a0) * SWR)                                    */
     double rho_f, theta_f;/* fast check fires if ACT > rho_f * mean(history) + theta_f       */
@@ -90,7 +90,10 @@ typedef struct {
     int32_t use_graph;         /* 1: replay each time step as a captured HIP graph          */
     const vsa_params* params;  /* NULL = built-in defaults (vsa_default_params)             */
     int32_t debug_log;         /* 1: keep a log of every sparse measure computed            */
-    int32_t me_tile;           /* 0 = autotuned / default, else a VSA_ME_TILE_* code        */
+    int32_t me_tile;           /* reserved, must be 0                                       */
+    int32_t profile;           /* time kernel launches with HIP events (see
+                                  vsa_engine_kernel_times): 1 pyramid and motion search,
+                                  2 every kernel and the whole step; 0 off                   */
 } vsa_engine_config;
 
 enum { VSA_SCHEDULE_SPARSE = 0, VSA_SCHEDULE_DENSE = 1 };
@@ -176,6 +179,12 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
 vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t pitch_bytes,
                            int32_t src, int64_t pts);
 
+/* Push one plane to each of n streams in one call (same rules as
+ * vsa_stream_push for each).  status (nullable) receives the n individual
+ * results; the call returns VSA_OK if all succeeded, else the first error. */
+vsa_status vsa_stream_push_batch(vsa_engine* e, int32_t n, const int32_t* sids, const void* const* planes,
+                                 const int64_t* pitches, int32_t src, const int64_t* pts, int32_t* status);
+
 /* End of stream: later steps drain the look-ahead and close the last shot. */
 vsa_status vsa_stream_end(vsa_engine* e, int32_t sid);
 
@@ -200,17 +209,27 @@ int32_t vsa_poll_shots(vsa_engine* e, int32_t sid, vsa_shot_result* out, int32_t
 
 /* Motion field of the pair (frame -> frame+1) of stream sid at the working
  * level, as nby x nbx pairs (dx, dy) of int8, if that frame is still held on
- * the device (the last 2 k_max + 4 frames).  Synchronises the engine. */
+ * the device (the last 2 k_max + 5 frames).  Synchronises the engine. */
 vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
                           int32_t cap_blocks, int32_t* nbx, int32_t* nby);
 
 /* Free the slot at once; records not yet polled are dropped. */
 vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
 
-/* Engine counters: out[0] steps, [1] streams open, [2] streams admitted,
- * [3] admissions refused, [4] HBM bytes held by streams, [5] budget bytes,
- * [6] sparse pair tasks run, [7] consecutive pair tasks run. */
-vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out8);
+/* Engine counters, the first n of: [0] steps, [1] streams open, [2] streams
+ * admitted, [3] admissions refused, [4] HBM bytes held by streams, [5] budget
+ * bytes, [6] sparse pair tasks planned, [7] consecutive pair tasks run,
+ * [8] blocks of the consecutive pairs, [9] blocks of the sparse pairs
+ * (device-side figures as of the last vsa_sync). */
+vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n);
+
+/* Accumulated device time per kernel of engines created with profile = 1,
+ * measured with HIP events on the engine stream, for the steps completed by
+ * the last vsa_sync: ms[i] total milliseconds and launches[i] launch count of
+ * i = 0 pyramid (K1), 1 motion search 8-bit (K2), 2 motion search 10-bit,
+ * 3 pair finish (K3), 4 decisions (K6), 5 whole step (descriptor upload to
+ * end of K6).  Either pointer may be NULL; reset = 1 clears the totals. */
+vsa_status vsa_engine_kernel_times(vsa_engine* e, double* ms, uint64_t* launches, int32_t reset);
 
 /* Thread-local description of the last error; valid until the next call. */
 const char* vsa_last_error(void);

@@ -64,9 +64,13 @@ __device__ __forceinline__ void ss_add(Analysis& a, int ph, double v0, double v1
     const bool comb_min = v0 > dp.tau_c * mn;
     const bool comb_max = v0 > dp.tau_c * mx;
     a.n += 1;
-    a.np[ph] += 1;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        if (q == ph) {
+            a.np[q] += 1;
+            if (comb_max) a.cm[q] += 1;
+        }
     if (comb_min) a.nci += 1;
-    if (comb_max) a.cm[ph] += 1;
     if (v1 > v2) a.s += 1; else if (v1 < v2) a.s -= 1;
     a.sum1 = a.sum1 + v1;
     a.sum2 = a.sum2 + v2;
@@ -106,25 +110,25 @@ __device__ __forceinline__ void ss_decide(Analysis& a, const DecideParams& dp) {
 __device__ __forceinline__ bool fast_check(const DecideState& st, double a, const DecideParams& dp) {
     if (st.hist_len == 0) return a > dp.theta_f0;   // no history in the shot yet
     double s = 0.0;
-    for (int i = 0; i < st.hist_len; ++i) s = s + st.hist[(st.hist_head + i) % dp.w_hist];
+#pragma unroll
+    for (int i = 0; i < kMaxHist; ++i)              // oldest to newest
+        if (i >= kMaxHist - st.hist_len) s = s + st.hist[i];
     const double mean = s / (double)st.hist_len;
     return a > dp.rho_f * mean + dp.theta_f;
 }
 
 __device__ __forceinline__ void hist_push(DecideState& st, double a, const DecideParams& dp) {
-    if (st.hist_len < dp.w_hist) {
-        st.hist[(st.hist_head + st.hist_len) % dp.w_hist] = a;
-        st.hist_len += 1;
-    } else {
-        st.hist[st.hist_head] = a;
-        st.hist_head = (st.hist_head + 1) % dp.w_hist;
-    }
+#pragma unroll
+    for (int i = 0; i < kMaxHist - 1; ++i) st.hist[i] = st.hist[i + 1];
+    st.hist[kMaxHist - 1] = a;
+    if (st.hist_len < dp.w_hist) st.hist_len += 1;
 }
 
-__device__ __forceinline__ void close_shot(DecideState& st, int last, const DecideParams& dp) {
+__device__ __forceinline__ void close_shot(DecideState& st, vsa_shot_result* closed, int last,
+                                           const DecideParams& dp) {
     if (st.ss.open) ss_decide(st.ss, dp);
-    if (st.n_closed >= 4) return;
-    vsa_shot_result& r = st.closed[st.n_closed++];
+    if (st.n_closed >= kMaxClosed) return;
+    vsa_shot_result& r = closed[st.n_closed++];
     r.shot_id = st.shot_id;
     r.pad0 = 0;
     r.first = st.shot_start;
@@ -166,8 +170,8 @@ __device__ int deep_check(const StreamDesc& sd, const DecideState& st, int t, in
 }
 
 // Commit iteration t = st.t with the flags it was planned with.
-__device__ void commit(const StreamDesc& sd, DecideState& st, const PairResult* res, const DecideParams& dp,
-                       bool want_fields, bool fire, bool need_deep, int Kn) {
+__device__ void commit(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, const PairResult* res,
+                       const DecideParams& dp, bool want_fields, bool fire, bool need_deep, int Kn) {
     const int t = st.t;
     FrameInfo& fi = info_of(sd, t);
     const double a = fi.act;
@@ -187,7 +191,7 @@ __device__ void commit(const StreamDesc& sd, DecideState& st, const PairResult* 
     }
     if (Kstar > 0) {
         fi.shot_id = st.shot_id;
-        close_shot(st, t, dp);
+        close_shot(st, closed, t, dp);
         for (int f = t + 1; f < t + Kstar; ++f) {
             FrameInfo& g = info_of(sd, f);
             g.flags |= VSA_F_IN_TRANSITION;
@@ -203,7 +207,6 @@ __device__ void commit(const StreamDesc& sd, DecideState& st, const PairResult* 
         st.cur_in_k = Kstar;
         st.shot_start = b;
         st.hist_len = 0;
-        st.hist_head = 0;
         st.acc = 0.0;
         ss_reset(st.ss);
         st.t = b;
@@ -295,15 +298,23 @@ __device__ PairTask plan_task(const StreamDesc& sd, const DecideState& st, int s
     return k;
 }
 
+struct PlaneDims { int w, h; };
+
+__device__ __forceinline__ PlaneDims plane_dims(const StreamDesc& sd, const PairTask& t) {
+    if (t.ref_field != PL_FRAME) return PlaneDims{sd.wf, sd.hf};
+    const int d = t.level - sd.L;
+    return PlaneDims{sd.wl[d], sd.hl[d]};
+}
+
 // Advance one stream as far as the ingested frames allow.
-__device__ void advance(const StreamDesc& sd, DecideState& st, const PairResult* res, const DecideParams& dp,
-                        int has_frame, int frame, int ended_T) {
+__device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, const PairResult* res,
+                        const DecideParams& dp, int has_frame, int frame, int ended_T) {
     st.n_closed = 0;
     if (st.done) { st.plan = 0; return; }
     if (has_frame) st.n = frame;
     if (ended_T >= 0) st.T_end = ended_T;
     if (st.plan) {
-        commit(sd, st, res, dp, st.plan_want, st.plan_fire, st.plan_deep, st.plan_kn);
+        commit(sd, st, closed, res, dp, st.plan_want, st.plan_fire, st.plan_deep, st.plan_kn);
         st.plan = 0;
     }
     for (;;) {
@@ -311,7 +322,7 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, const PairResult*
         if (st.T_end >= 0 && t >= st.T_end - 1) {
             if (st.T_end > 0) {
                 info_of(sd, st.T_end - 1).shot_id = st.shot_id;
-                close_shot(st, st.T_end - 1, dp);
+                close_shot(st, closed, st.T_end - 1, dp);
             }
             st.t = st.T_end;
             st.done = 1;
@@ -339,7 +350,7 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, const PairResult*
         st.plan = 1;
         if (plan_task_count(sd, st) > 0) break;       // measures requested; commit next step
         st.plan = 0;
-        commit(sd, st, res, dp, want, fire, need_deep, Kn);
+        commit(sd, st, closed, res, dp, want, fire, need_deep, Kn);
     }
 }
 
@@ -367,99 +378,84 @@ __device__ __forceinline__ void log_task(int32_t* log, int64_t cap, DecideState&
     st.log_count += 1;
 }
 
-// Block-wide exclusive scan of four counters (blockDim.x <= 1024, multiple of 64).
-__device__ int4 block_scan4(int4 v, int4& total, int4* lds) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int4 inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int x = __shfl_up(inc.x, o, 64), y = __shfl_up(inc.y, o, 64);
-        const int z = __shfl_up(inc.z, o, 64), w = __shfl_up(inc.w, o, 64);
-        if (lane >= o) { inc.x += x; inc.y += y; inc.z += z; inc.w += w; }
-    }
-    if (lane == 63) lds[wave] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int4 run = make_int4(0, 0, 0, 0);
-        for (int i = 0; i < nw; ++i) {
-            const int4 t = lds[i];
-            lds[i] = run;
-            run.x += t.x; run.y += t.y; run.z += t.z; run.w += t.w;
-        }
-        lds[16] = run;
-    }
-    __syncthreads();
-    const int4 wb = lds[wave];
-    total = lds[16];
-    return make_int4(wb.x + inc.x - v.x, wb.y + inc.y - v.y, wb.z + inc.z - v.z, wb.w + inc.w - v.w);
-}
-
 }  // namespace
 
-// One workgroup; thread i handles step entry i (every open stream appears once).
-__global__ void __launch_bounds__(1024) k_decide(const StreamDesc* __restrict__ sds, DecideState* __restrict__ states,
-                                                 const PairResult* __restrict__ results,
-                                                 const StepStream* __restrict__ steps, int32_t n_steps,
-                                                 DecideParams dp, PairTask* __restrict__ sparse_out,
-                                                 DeviceCursors* __restrict__ cur, OutFrame* __restrict__ out_frames,
-                                                 uint64_t frames_cap, OutShot* __restrict__ out_shots,
-                                                 uint64_t shots_cap, int32_t* __restrict__ log, int64_t log_cap) {
-    __shared__ int4 lds[17];
-    __shared__ uint64_t base_frames, base_shots;
-    const int i = threadIdx.x;
-    const bool mine = i < n_steps;
-    int sid = -1;
-    int4 cnt = make_int4(0, 0, 0, 0);
-    if (mine) {
-        const StepStream& ss = steps[i];
-        sid = ss.sid;
-        const StreamDesc& sd = sds[sid];
-        DecideState& st = states[sid];
+// One wavefront per stream (four per workgroup).  Lane 0 advances the
+// stream's state machine with its descriptor and state in registers, reserves
+// its slice of the next step's sparse task list (tasks and tiles from one
+// 64-bit atomic, so tile offsets grow with task order) and of the output
+// rings, and writes its tasks; then the whole wave copies the finished frame
+// and shot records out in parallel.  Streams never share a wave, so their
+// different control paths do not serialise each other.
+__global__ void __launch_bounds__(256) k_decide(
+    const StreamDesc* __restrict__ sds, DecideState* __restrict__ states, const PairResult* __restrict__ results,
+    const StepStream* __restrict__ steps, int32_t n_steps, DecideParams dp, PairTask* __restrict__ sparse_out,
+    DeviceCursors* __restrict__ cur, OutFrame* __restrict__ out_frames, uint64_t frames_cap,
+    OutShot* __restrict__ out_shots, uint64_t shots_cap, int32_t* __restrict__ log, int64_t log_cap,
+    vsa_shot_result* __restrict__ closed_buf, int32_t par) {
+    struct Bcast {
+        FrameInfo* info;
+        int32_t rs, sid, e0, nframes, nshots, pad;
+        uint64_t fbase, sbase;
+    };
+    __shared__ Bcast bc[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wave;
+    const bool active = i < n_steps;
+    if (active && lane == 0) {
+        const StepStream ss = steps[i];
+        const int sid = ss.sid;
+        const StreamDesc sd = sds[sid];
+        DecideState st = states[sid];
+        vsa_shot_result* closed = closed_buf + (int64_t)sid * kMaxClosed;
         const int e0 = st.emitted;
-        advance(sd, st, results + (int64_t)sid * kResSlots, dp, ss.has_frame, ss.frame, ss.ended_T);
+        advance(sd, st, closed, results + (int64_t)sid * kResSlots, dp, ss.has_frame, ss.frame, ss.ended_T);
         const int nt = plan_task_count(sd, st);
-        int tiles = 0;
-        for (int k = 0; k < nt; ++k) tiles += plan_task(sd, st, sid, k).tiles;
-        cnt = make_int4(nt, tiles, st.t - e0, st.n_closed);
-    }
-    if (i == 0) {
-        base_frames = cur->frames_written;
-        base_shots = cur->shots_written;
-    }
-    int4 total;
-    const int4 off = block_scan4(cnt, total, lds);
-    if (mine) {
-        const StreamDesc& sd = sds[sid];
-        DecideState& st = states[sid];
-        int tile = off.y;
-        for (int k = 0; k < cnt.x; ++k) {
-            PairTask t = plan_task(sd, st, sid, k);
+        int tiles = 0, blocks = 0;
+        for (int q = 0; q < nt; ++q) {
+            const PairTask pt = plan_task(sd, st, sid, q);
+            tiles += pt.tiles;
+            const PlaneDims pd = plane_dims(sd, pt);
+            blocks += (pd.w / kBlock) * (pd.h / kBlock);
+        }
+        const int nframes = st.t - e0;
+        const unsigned long long res =
+            nt ? atomicAdd(&cur->sparse_tt[par], ((unsigned long long)nt << 32) | (unsigned long long)tiles) : 0ull;
+        const uint64_t fbase = nframes ? atomicAdd((unsigned long long*)&cur->frames_written,
+                                                   (unsigned long long)nframes) : 0ull;
+        const uint64_t sbase = st.n_closed ? atomicAdd((unsigned long long*)&cur->shots_written,
+                                                       (unsigned long long)st.n_closed) : 0ull;
+        if (nt) {
+            atomicAdd((unsigned long long*)&cur->sparse_run, (unsigned long long)nt);
+            atomicAdd((unsigned long long*)&cur->sparse_blocks, (unsigned long long)blocks);
+        }
+        int32_t* slog = log ? log + (int64_t)sid * log_cap * 6 : nullptr;
+        int task = tt_tasks(res), tile = tt_tiles(res);
+        for (int q = 0; q < nt; ++q) {
+            PairTask t = plan_task(sd, st, sid, q);
             t.tile_prefix = tile;
             tile += t.tiles;
-            sparse_out[off.x + k] = t;
-            log_task(log ? log + (int64_t)sid * log_cap * 6 : nullptr, log_cap, st, t);
+            sparse_out[task + q] = t;
+            log_task(slog, log_cap, st, t);
         }
-        for (int k = 0; k < cnt.z; ++k) {
-            const int f = st.emitted + k;
-            OutFrame& o = out_frames[(base_frames + (uint64_t)off.z + k) % frames_cap];
-            o.sid = sid;
-            o.pad = 0;
-            fill_record(o.r, info_of(sd, f));
-        }
-        st.emitted += cnt.z;
-        for (int k = 0; k < cnt.w; ++k) {
-            OutShot& o = out_shots[(base_shots + (uint64_t)off.w + k) % shots_cap];
-            o.sid = sid;
-            o.pad = 0;
-            o.r = st.closed[k];
-        }
+        st.emitted = st.t;
+        states[sid] = st;
+        bc[wave] = Bcast{sd.info, sd.rs, sid, e0, nframes, st.n_closed, 0, fbase, sbase};
     }
-    if (i == 0) {
-        cur->n_sparse = total.x;
-        cur->sparse_tiles = total.y;
-        cur->sparse_run += (uint64_t)total.x;
-        cur->frames_written = base_frames + (uint64_t)total.z;
-        cur->shots_written = base_shots + (uint64_t)total.w;
+    __syncthreads();
+    if (!active) return;
+    const Bcast b = bc[wave];
+    for (int q = lane; q < b.nframes; q += 64) {
+        OutFrame& o = out_frames[(b.fbase + (uint64_t)q) % frames_cap];
+        o.sid = b.sid;
+        o.pad = 0;
+        fill_record(o.r, b.info[(b.e0 + q) % b.rs]);
+    }
+    if (lane < b.nshots) {
+        OutShot& o = out_shots[(b.sbase + (uint64_t)lane) % shots_cap];
+        o.sid = b.sid;
+        o.pad = 0;
+        o.r = closed_buf[(int64_t)b.sid * kMaxClosed + lane];
     }
 }
 
@@ -472,7 +468,8 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
                                 vsa_frame_result* recs, vsa_shot_result* shots, int32_t shots_cap,
                                 int32_t* n_shots, int32_t* log, int32_t log_cap, int32_t* n_log) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    DecideState& st = *st_;
+    DecideState st = *st_;
+    vsa_shot_result closed[kMaxClosed];
     const int kw = sd.k_max + 2;
     int ns = 0;
     int nl = 0;
@@ -497,11 +494,11 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
             }
         }
         const int e0 = st.emitted;
-        advance(sd, st, res, dp, has, step, step >= T - 1 ? T : -1);
+        advance(sd, st, closed, res, dp, has, step, step >= T - 1 ? T : -1);
         for (int f = e0; f < st.t; ++f) fill_record(recs[f], info_of(sd, f));
         st.emitted = st.t;
         for (int k = 0; k < st.n_closed; ++k)
-            if (ns < shots_cap) shots[ns++] = st.closed[k];
+            if (ns < shots_cap) shots[ns++] = closed[k];
         const int nt = plan_task_count(sd, st);
         for (int k = 0; k < nt; ++k) {
             const PairTask t = plan_task(sd, st, 0, k);
@@ -525,15 +522,18 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
     }
     *n_shots = ns;
     *n_log = nl;
+    *st_ = st;
 }
 
 hipError_t launch_decide(const StreamDesc* sds, DecideState* states, const PairResult* results,
                          const StepStream* steps, int32_t n_steps, const DecideParams& dp, PairTask* sparse_out,
                          DeviceCursors* cur, OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots,
-                         uint64_t shots_cap, int32_t* log, int64_t log_cap, hipStream_t s) {
-    const int threads = ((n_steps + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(threads < 64 ? 64 : threads), 0, s, sds, states, results, steps,
-                       n_steps, dp, sparse_out, cur, out_frames, frames_cap, out_shots, shots_cap, log, log_cap);
+                         uint64_t shots_cap, int32_t* log, int64_t log_cap, vsa_shot_result* closed_buf,
+                         int32_t par, hipStream_t s) {
+    if (n_steps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_decide, dim3((n_steps + 3) / 4), dim3(256), 0, s, sds, states, results, steps,
+                       n_steps, dp, sparse_out, cur, out_frames, frames_cap, out_shots, shots_cap, log, log_cap,
+                       closed_buf, par);
     return hipGetLastError();
 }
 

@@ -110,7 +110,8 @@ __device__ __forceinline__ uint64_t pk64(uint32_t lo, uint32_t hi) {
 }
 
 // 8-bit search for one lane: returns the best key (SAD << 16 | rank).
-__device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
+__device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, const uint16_t* rank, int bx,
+                                            int by, int q) {
     uint32_t r0[8], r1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -156,7 +157,7 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const uint16_t* rk = c_rank + (dy0 + i + kRadius) * kCand;
+        const uint16_t* rk = rank + (dy0 + i + kRadius) * kCand;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const uint32_t lo = (uint32_t)acc[i][g], hi = (uint32_t)(acc[i][g] >> 32);
@@ -184,17 +185,18 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
             a8 = __builtin_amdgcn_sad_u8(e1, r0[j], a8);
             a8 = __builtin_amdgcn_sad_u8(e2, r1[j], a8);
         }
-        const uint16_t* rk = c_rank + (2 * kRadius) * kCand + 4 * q;
+        const uint16_t* rk = rank + (2 * kRadius) * kCand + 4 * q;
         const uint32_t lo = (uint32_t)a4, hi = (uint32_t)(a4 >> 32);
         best = min(best, min((lo << 16) | rk[0], (lo & 0xffff0000u) | rk[1]));
         best = min(best, min((hi << 16) | rk[2], (hi & 0xffff0000u) | rk[3]));
-        if (q == 3) best = min(best, (a8 << 16) | c_rank[(2 * kRadius) * kCand + 16]);
+        if (q == 3) best = min(best, (a8 << 16) | rank[(2 * kRadius) * kCand + 16]);
     }
     return best;
 }
 
 // 10-bit search for one lane: returns the best key (SAD << 9 | rank).
-__device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
+__device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* sJ, const uint16_t* rank, int bx,
+                                             int by, int q) {
     // ref block: 8 rows x 4 dwords (2 samples each)
     uint32_t rf[8][4];
 #pragma unroll
@@ -207,7 +209,7 @@ __device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* s
     const int ndy = (q == 3) ? 5 : 4;
     for (int i = 0; i < ndy; ++i) {
         const int dy = -8 + 4 * q + i;
-        const uint16_t* rk = c_rank + (dy + kRadius) * kCand;
+        const uint16_t* rk = rank + (dy + kRadius) * kCand;
         uint32_t acc[kCand];
 #pragma unroll
         for (int k = 0; k < kCand; ++k) acc[k] = 0;
@@ -321,7 +323,8 @@ __device__ __forceinline__ int32_t rows_sad(const uint8_t* sI, const uint8_t* sJ
 
 template <typename T>
 __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, TilePartial* part_out,
-                        int8_t* mv_out, int32_t* sad_out, uint8_t* sI, uint8_t* sJ, int64_t* red) {
+                        int8_t* mv_out, int32_t* sad_out, uint8_t* sI, uint8_t* sJ, const uint16_t* rank,
+                        int64_t* red) {
     const PlaneRef I = plane_of(sd, tk.ref, tk.ref_field, tk.level);
     const PlaneRef J = plane_of(sd, tk.oth, tk.oth_field, tk.level);
     const int nbx = I.w / kBlock, nby = I.h / kBlock;
@@ -338,8 +341,8 @@ __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, Til
     if (!(tk.flags & TF_ZERO_MV)) {
         uint32_t key = 0xffffffffu;
         if (valid) {
-            if constexpr (sizeof(T) == 1) key = search8(sI, sJ, bx, by, q);
-            else key = search16(sI, sJ, bx, by, q);
+            if constexpr (sizeof(T) == 1) key = search8(sI, sJ, rank, bx, by, q);
+            else key = search16(sI, sJ, rank, bx, by, q);
         }
         key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
         key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
@@ -400,12 +403,16 @@ __global__ void __launch_bounds__(kMEThreads) k_me(const StreamDesc* __restrict_
                                                    int32_t consec_tiles, const PairTask* __restrict__ sparse,
                                                    const DeviceCursors* __restrict__ cur,
                                                    TilePartial* __restrict__ partials, int8_t* dbg_mv,
-                                                   int32_t* dbg_sad) {
+                                                   int32_t* dbg_sad, int32_t par_prev) {
     __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
     __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
     __shared__ int64_t red[4 * 6];
-    const int n_sparse = cur ? cur->n_sparse : 0;
-    const int total = consec_tiles + (cur ? cur->sparse_tiles : 0);
+    __shared__ uint16_t rank[kCand * kCand];
+    for (int i = threadIdx.x; i < kCand * kCand; i += kMEThreads) rank[i] = c_rank[i];
+    __syncthreads();
+    const unsigned long long tt = cur ? cur->sparse_tt[par_prev] : 0ull;
+    const int n_sparse = tt_tasks(tt);
+    const int total = consec_tiles + tt_tiles(tt);
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const PairTask* tk;
         int local;
@@ -424,7 +431,7 @@ __global__ void __launch_bounds__(kMEThreads) k_me(const StreamDesc* __restrict_
         if (tk->flags & TF_MV_RING) mv = sd.mv + (int64_t)(tk->ref % sd.rs) * sd.B_L * 2;
         else if (tk->flags & TF_DEBUG) mv = dbg_mv;
         me_tile<T>(sd, *tk, local, partials + tile, mv, (tk->flags & TF_DEBUG) ? dbg_sad : nullptr,
-                   sI, sJ, red);
+                   sI, sJ, rank, red);
     }
 }
 
@@ -457,9 +464,12 @@ __global__ void __launch_bounds__(256) k_finish(const StreamDesc* __restrict__ s
                                                 const DeviceCursors* __restrict__ cur,
                                                 const TilePartial* __restrict__ partials,
                                                 PairResult* __restrict__ results, DecideParams dp,
-                                                int64_t* dbg_ints, double* dbg_dbl) {
+                                                int64_t* dbg_ints, double* dbg_dbl, int32_t par_prev,
+                                                DeviceCursors* __restrict__ cur_w) {
     const int lane = threadIdx.x & 63;
-    const int total = n_consec + (cur ? cur->n_sparse : 0);
+    const int total = n_consec + (cur ? tt_tasks(cur->sparse_tt[par_prev]) : 0);
+    // clear this step's planning counter before the decision kernel adds to it
+    if (cur_w && blockIdx.x == 0 && threadIdx.x == 0) cur_w->sparse_tt[par_prev ^ 1] = 0ull;
     for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < total; t += gridDim.x * 4) {
         const bool is_consec = t < n_consec;
         const PairTask& tk = is_consec ? consec[t] : sparse[t - n_consec];
@@ -540,24 +550,25 @@ hipError_t me_init_tables() {
 
 hipError_t launch_me(int bits, const StreamDesc* sds, const PairTask* consec, int32_t n_consec,
                      int32_t consec_tiles, const PairTask* sparse, const DeviceCursors* cur,
-                     TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid, hipStream_t s) {
+                     TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid, int32_t par_prev,
+                     hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     if (bits == 8)
         hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
-                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad);
+                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev);
     else
         hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
-                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad);
+                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev);
     return hipGetLastError();
 }
 
 hipError_t launch_finish(const StreamDesc* sds, const PairTask* consec, int32_t n_consec,
-                         int32_t consec_tiles, const PairTask* sparse, const DeviceCursors* cur,
+                         int32_t consec_tiles, const PairTask* sparse, DeviceCursors* cur,
                          const TilePartial* partials, PairResult* results, const DecideParams& dp,
-                         int64_t* dbg_ints, double* dbg_dbl, int grid, hipStream_t s) {
+                         int64_t* dbg_ints, double* dbg_dbl, int grid, int32_t par_prev, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, s, sds, consec, n_consec, consec_tiles, sparse,
-                       cur, partials, results, dp, dbg_ints, dbg_dbl);
+                       cur, partials, results, dp, dbg_ints, dbg_dbl, par_prev, cur);
     return hipGetLastError();
 }
 

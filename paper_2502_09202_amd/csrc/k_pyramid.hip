@@ -117,6 +117,12 @@ __device__ __forceinline__ void store_row(uint8_t* dst, int x0, int w, const Row
             u.y = (uint32_t)r.v[4] | ((uint32_t)r.v[5] << 8) | ((uint32_t)r.v[6] << 16) | ((uint32_t)r.v[7] << 24);
             *reinterpret_cast<uint2*>(p) = u;
             return;
+        } else if constexpr (sizeof(T) == 1 && N == 2) {
+            *reinterpret_cast<uint16_t*>(p) = (uint16_t)(r.v[0] | (r.v[1] << 8));
+            return;
+        } else if constexpr (sizeof(T) == 2 && N == 2) {
+            *reinterpret_cast<uint32_t*>(p) = (uint32_t)r.v[0] | ((uint32_t)r.v[1] << 16);
+            return;
         } else if constexpr (sizeof(T) == 2 && N == 4) {
             uint2 u;
             u.x = (uint32_t)r.v[0] | ((uint32_t)r.v[1] << 16);
@@ -142,6 +148,16 @@ __device__ __forceinline__ uint8_t* slot_base(const StreamDesc& sd, int frame) {
     return sd.ring + (int64_t)(frame % sd.rs) * sd.slot_bytes;
 }
 
+// Working-level columns per thread: 4 up to L = 2, fewer for larger L so that
+// the per-thread band (2^L rows x CW 2^L columns) stays small in registers.
+template <int L>
+struct PyrShape {
+    static constexpr int CW = L <= 2 ? 4 : (L == 3 ? 2 : 1);
+    static constexpr int TW = 16 * CW;     // tile width (working-level pixels)
+};
+
+__host__ __device__ inline int pyr_cw(int L) { return L <= 2 ? 4 : (L == 3 ? 2 : 1); }
+
 // Pyramid grid width (working-level columns) covering the level and the fields.
 __host__ __device__ inline int pyr_grid_w(const StreamDesc& sd) {
     const int shift = sd.L - sd.Lf;          // 1 for L >= 1, 0 for L == 0
@@ -152,11 +168,13 @@ __host__ __device__ inline int pyr_grid_w(const StreamDesc& sd) {
 template <typename T, int L>
 __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int tile, uint16_t* lds) {
     constexpr int S = 1 << L;
-    constexpr int NC = 4 * S;
-    const int tiles_x = div_up(pyr_grid_w(sd), kPyrTW);
+    constexpr int CW = PyrShape<L>::CW;
+    constexpr int TW = PyrShape<L>::TW;
+    constexpr int NC = CW * S;
+    const int tiles_x = div_up(pyr_grid_w(sd), TW);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
-    const int X = tx * kPyrTW + 4 * c;        // first working-level column of this thread
+    const int X = tx * TW + CW * c;           // first working-level column of this thread
     const int YL = ty * kPyrTH + r;           // working-level row
     const uint8_t* src = reinterpret_cast<const uint8_t*>(ss.src);
     const int64_t pitch = ss.src_pitch;
@@ -164,17 +182,17 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
     uint8_t* slot = slot_base(sd, ss.frame);
     const int wL = sd.wl[0], hL = sd.hl[0];
 
-    Row<4> fl;
-    if (YL < sd.hl[0] || (L == 0 && YL < sd.H)) {
+    Row<CW> fl;
+    if (YL < hL) {
         if constexpr (L == 0) {
-            Row<4> a;
-            load_row<T, 4>(src + (int64_t)YL * pitch, X, sd.W, al16, a);
+            Row<CW> a;
+            load_row<T, CW>(src + (int64_t)YL * pitch, X, sd.W, al16, a);
             fl = a;
             // fields at level 0: even rows -> upper, odd rows -> lower
             const int fy = YL >> 1;
             if (fy < sd.hf) {
                 uint8_t* dst = slot + ((YL & 1) ? sd.offD : sd.offU) + (int64_t)fy * sd.pf * (int64_t)sizeof(T);
-                store_row<T, 4>(dst, X, sd.wf, a);
+                store_row<T, CW>(dst, X, sd.wf, a);
             }
         } else {
             Band<NC, L> b;
@@ -182,23 +200,23 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
             fl = b.f;
             if (YL < sd.hf) {
                 const int64_t rowoff = (int64_t)YL * sd.pf * (int64_t)sizeof(T);
-                store_row<T, 8>(slot + sd.offU + rowoff, 2 * X, sd.wf, b.u);
-                store_row<T, 8>(slot + sd.offD + rowoff, 2 * X, sd.wf, b.d);
+                store_row<T, 2 * CW>(slot + sd.offU + rowoff, 2 * X, sd.wf, b.u);
+                store_row<T, 2 * CW>(slot + sd.offD + rowoff, 2 * X, sd.wf, b.d);
             }
         }
-        if (YL < hL) store_row<T, 4>(slot + sd.off[0] + (int64_t)YL * sd.pl[0] * (int64_t)sizeof(T), X, wL, fl);
+        store_row<T, CW>(slot + sd.off[0] + (int64_t)YL * sd.pl[0] * (int64_t)sizeof(T), X, wL, fl);
     } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) fl.v[i] = 0;
+        for (int i = 0; i < CW; ++i) fl.v[i] = 0;
     }
     if (sd.nlev <= 1) return;
     // coarser levels from the tile in LDS
 #pragma unroll
-    for (int i = 0; i < 4; ++i) lds[r * kPyrTW + 4 * c + i] = (uint16_t)fl.v[i];
+    for (int i = 0; i < CW; ++i) lds[r * TW + CW * c + i] = (uint16_t)fl.v[i];
     __syncthreads();
     uint16_t* prev = lds;
     uint16_t* next = lds + kPyrTW * kPyrTH;
-    int pw = kPyrTW, ph = kPyrTH;
+    int pw = TW, ph = kPyrTH;
     for (int d = 1; d < sd.nlev; ++d) {
         const int cw = pw >> 1, ch = ph >> 1;
         const int i = threadIdx.x;
@@ -207,7 +225,7 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
             const int v = (prev[(2 * y) * pw + 2 * x] + prev[(2 * y) * pw + 2 * x + 1] +
                            prev[(2 * y + 1) * pw + 2 * x] + prev[(2 * y + 1) * pw + 2 * x + 1] + 2) >> 2;
             next[y * cw + x] = (uint16_t)v;
-            const int gx = tx * (kPyrTW >> d) + x, gy = ty * (kPyrTH >> d) + y;
+            const int gx = tx * (TW >> d) + x, gy = ty * (kPyrTH >> d) + y;
             if (gx < sd.wl[d] && gy < sd.hl[d]) {
                 T* dst = reinterpret_cast<T*>(slot + sd.off[d]) + (int64_t)gy * sd.pl[d] + gx;
                 *dst = (T)v;
@@ -222,9 +240,30 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
     }
 }
 
+__device__ __forceinline__ void init_frame_info(const StreamDesc& sd, const StepStream& ss) {
+    FrameInfo& fi = sd.info[ss.frame % sd.rs];
+    const double nan = __builtin_nan("");
+    fi.frame = ss.frame;
+    fi.pts = ss.pts;
+    fi.flags = ss.frame == 0 ? (VSA_F_KEYFRAME | VSA_F_SHOT_START) : 0;
+    fi.shot_id = -1;
+    fi.boundary = 0;
+    fi.boundary_k = 0;
+    fi.ncc = fi.swr = fi.amm = fi.act = nan;
+    for (int i = 0; i < 5; ++i) fi.mom[i] = 0;
+    fi.n_pix = 0;
+    fi.amm_num = 0;
+    fi.n_blocks = 0;
+    fi.field_mask = 0;
+    fi.v[0] = fi.v[1] = fi.v[2] = nan;
+}
+
 }  // namespace
 
-// Grid: one workgroup per pyramid tile over all ingesting streams.
+// Grid: one workgroup per pyramid tile over the ingesting streams of one
+// (sample width, working level) group; each group is its own instantiation so
+// that registers are sized for that shape only.
+template <typename T, int L>
 __global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ sds,
                                                   const StepStream* __restrict__ steps,
                                                   const int32_t* __restrict__ k1_list, int32_t n_k1) {
@@ -240,50 +279,38 @@ __global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ 
     const int local = tile - ss.k1_prefix;
     if (local < 0 || local >= ss.k1_tiles) return;
     const StreamDesc& sd = sds[ss.sid];
-    if (local == 0 && threadIdx.x == 0) {
-        FrameInfo& fi = sd.info[ss.frame % sd.rs];
-        const double nan = __builtin_nan("");
-        fi.frame = ss.frame;
-        fi.pts = ss.pts;
-        fi.flags = ss.frame == 0 ? (VSA_F_KEYFRAME | VSA_F_SHOT_START) : 0;
-        fi.shot_id = -1;
-        fi.boundary = 0;
-        fi.boundary_k = 0;
-        fi.ncc = fi.swr = fi.amm = fi.act = nan;
-        for (int i = 0; i < 5; ++i) fi.mom[i] = 0;
-        fi.n_pix = 0;
-        fi.amm_num = 0;
-        fi.n_blocks = 0;
-        fi.field_mask = 0;
-        fi.v[0] = fi.v[1] = fi.v[2] = nan;
-    }
-    if (sd.bits == 8) {
-        switch (sd.L) {
-            case 0: pyramid_tile<uint8_t, 0>(sd, ss, local, lds); break;
-            case 1: pyramid_tile<uint8_t, 1>(sd, ss, local, lds); break;
-            case 2: pyramid_tile<uint8_t, 2>(sd, ss, local, lds); break;
-            case 3: pyramid_tile<uint8_t, 3>(sd, ss, local, lds); break;
-            default: pyramid_tile<uint8_t, 4>(sd, ss, local, lds); break;
-        }
-    } else {
-        switch (sd.L) {
-            case 0: pyramid_tile<uint16_t, 0>(sd, ss, local, lds); break;
-            case 1: pyramid_tile<uint16_t, 1>(sd, ss, local, lds); break;
-            case 2: pyramid_tile<uint16_t, 2>(sd, ss, local, lds); break;
-            case 3: pyramid_tile<uint16_t, 3>(sd, ss, local, lds); break;
-            default: pyramid_tile<uint16_t, 4>(sd, ss, local, lds); break;
-        }
-    }
+    if (local == 0 && threadIdx.x == 0) init_frame_info(sd, ss);
+    pyramid_tile<T, L>(sd, ss, local, lds);
 }
 
 int pyramid_tiles(const StreamDesc& sd) {
-    return div_up(pyr_grid_w(sd), kPyrTW) * div_up(sd.L == 0 ? sd.H : sd.hl[0], kPyrTH);
+    return div_up(pyr_grid_w(sd), 16 * pyr_cw(sd.L)) * div_up(sd.hl[0], kPyrTH);
 }
 
-hipError_t launch_pyramid(const StreamDesc* sds, const StepStream* steps, const int32_t* k1_list,
+// Launch the pyramid for one group of streams sharing sample width and L.
+hipError_t launch_pyramid(int bits, int L, const StreamDesc* sds, const StepStream* steps, const int32_t* k1_list,
                           int32_t n_k1, int32_t total_tiles, hipStream_t s) {
     if (n_k1 <= 0 || total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pyramid, dim3(total_tiles), dim3(256), 0, s, sds, steps, k1_list, n_k1);
+    const dim3 g(total_tiles), b(256);
+#define VSA_PYR(TT, LL) hipLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, sds, steps, k1_list, n_k1)
+    if (bits == 8) {
+        switch (L) {
+            case 0: VSA_PYR(uint8_t, 0); break;
+            case 1: VSA_PYR(uint8_t, 1); break;
+            case 2: VSA_PYR(uint8_t, 2); break;
+            case 3: VSA_PYR(uint8_t, 3); break;
+            default: VSA_PYR(uint8_t, 4); break;
+        }
+    } else {
+        switch (L) {
+            case 0: VSA_PYR(uint16_t, 0); break;
+            case 1: VSA_PYR(uint16_t, 1); break;
+            case 2: VSA_PYR(uint16_t, 2); break;
+            case 3: VSA_PYR(uint16_t, 3); break;
+            default: VSA_PYR(uint16_t, 4); break;
+        }
+    }
+#undef VSA_PYR
     return hipGetLastError();
 }
 

@@ -13,8 +13,9 @@ constexpr int kRadius = 8;          // full-search radius (working pixels)
 constexpr int kCand = 2 * kRadius + 1;
 constexpr int kMaxLevels = 5;       // frame levels stored per ring slot: L .. L+4
 constexpr int kMaxKmax = 15;
-constexpr int kMaxHist = 32;
+constexpr int kMaxHist = 16;
 constexpr int kMaxStreams = 1024;
+constexpr int kDecideThreads = 256;     // decision kernel: one workgroup, up to 4 streams per thread
 
 // Field selector of a plane inside a ring slot.
 enum : int32_t { PL_FRAME = 0, PL_UPPER = 1, PL_LOWER = 2 };
@@ -89,7 +90,7 @@ constexpr int kResSlots = kResP + kMaxKmax + 2;
 // Sampling-structure analysis of the open shot.
 struct Analysis {
     int32_t open, n, nci, s, result, phase;
-    int32_t cm[5], np[5];
+    int32_t cm[5], np[5];       // per phase of the 5-frame unit
     double sum1, sum2;
 };
 
@@ -100,8 +101,8 @@ struct DecideState {
     int32_t T_end;              // total frames once the stream has ended, else -1
     int32_t emitted;            // frames [0, emitted) have been written out
     int32_t shot_start, shot_id;
-    int32_t hist_len, hist_head;
-    double hist[kMaxHist];
+    int32_t hist_len, hist_pad;
+    double hist[kMaxHist];      // the last hist_len values end at index kMaxHist-1 (oldest first)
     double acc;                 // keyframe accumulator
     Analysis ss;
     int32_t cur_in_boundary, cur_in_k;   // how the current shot began
@@ -111,9 +112,11 @@ struct DecideState {
     int32_t done;               // end of stream fully processed
     int32_t n_closed;           // shots closed by the last advance
     int64_t log_count;          // sparse measures logged
-    vsa_shot_result closed[4];  // at most 3 per advance: a planned boundary, one
-                                // immediate boundary at the clip end, the last shot
 };
+
+// Shots closed by one advance of a stream: at most 3 (a planned boundary, one
+// immediate boundary at the clip end, the last shot).
+constexpr int kMaxClosed = 4;
 
 // Engine-wide constants for the decision kernel.
 struct DecideParams {
@@ -150,10 +153,16 @@ struct OutShot {
 struct DeviceCursors {
     uint64_t frames_written;     // monotonically increasing write cursor (OutFrame ring)
     uint64_t shots_written;
-    int32_t n_sparse;            // sparse tasks planned for the next step
-    int32_t sparse_tiles;
+    // sparse tasks planned by the decision kernel of steps of parity p, packed
+    // as (tasks << 32 | tiles); the next step's motion search reads it and its
+    // finish kernel clears the other entry before that step's decisions add to it
+    unsigned long long sparse_tt[2];
     uint64_t sparse_run;         // total sparse tasks planned
+    uint64_t sparse_blocks;      // total 8x8 blocks of those tasks
 };
+
+__host__ __device__ inline int tt_tasks(unsigned long long v) { return (int)(v >> 32); }
+__host__ __device__ inline int tt_tiles(unsigned long long v) { return (int)(v & 0xffffffffu); }
 
 // ME tiling: a tile is TBX x TBY blocks, one 256-thread workgroup.
 constexpr int kTBX = 8;

@@ -1,7 +1,7 @@
 // vsa_runtime.cpp -- host runtime and C ABI of libvsa (see include/vsa.h).
 //
 // One engine = one HIP stream of work on one device.  Every open stream owns
-// one device allocation: a ring of 2 k_max + 4 frame slots (working level,
+// one device allocation: a ring of 2 k_max + 5 frame slots (working level,
 // the coarser levels used by the deep check and the two fields), the
 // per-frame records under construction, the motion fields of the
 // consecutive pairs, and two staging planes for copied input.  The engine
@@ -18,6 +18,11 @@
 //         launch per sample width);
 //   K3    finish of every pair (NCC, SWR, AMM, ACT);
 //   K6    decisions, sparse-task compaction for the next step, records.
+// K1 and the uploads run on a second HIP stream ("ingest"); the rest on the
+// main stream.  Step s's pyramid may run while step s-1's motion search and
+// decisions are still executing (the ring holds one extra slot for that), but
+// never ahead of step s-2.  The two kernels stress different units (HBM vs
+// VALU/latency), so they overlap well.
 // Nothing is copied back until vsa_sync, which drains the device output rings.
 #include <hip/hip_runtime.h>
 
@@ -35,18 +40,19 @@
 #include "vsa_internal.h"
 
 namespace vsa {
-hipError_t launch_pyramid(const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t, hipStream_t);
+hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
+                          hipStream_t);
 int pyramid_tiles(const StreamDesc& sd);
 hipError_t me_init_tables();
 hipError_t launch_me(int bits, const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
-                     const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t);
+                     const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid, int32_t par_prev, hipStream_t);
 hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
-                         const DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
-                         double*, int grid, hipStream_t);
+                         DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
+                         double*, int grid, int32_t par_prev, hipStream_t);
 hipError_t launch_finish_debug(const int64_t*, int64_t, double, double*, hipStream_t);
 hipError_t launch_decide(const StreamDesc*, DecideState*, const PairResult*, const StepStream*, int32_t,
                          const DecideParams&, PairTask*, DeviceCursors*, OutFrame*, uint64_t, OutShot*, uint64_t,
-                         int32_t*, int64_t, hipStream_t);
+                         int32_t*, int64_t, vsa_shot_result*, int32_t, hipStream_t);
 hipError_t launch_decide_replay(const StreamDesc&, DecideState*, PairResult*, const DecideParams&, int32_t,
                                 const double*, const double*, const uint8_t*, const double*, const double*,
                                 const double*, const double*, vsa_frame_result*, vsa_shot_result*, int32_t,
@@ -77,7 +83,9 @@ vsa_status hip_fail(hipError_t e, const char* what) {
 
 constexpr int kMaxTasksPerStream = 3 + 2 * (kMaxKmax + 1);
 constexpr uint64_t kFramesCap = 1u << 16;
-constexpr uint64_t kShotsCap = 1u << 14;
+constexpr uint64_t kShotsCap = 1u << 16;
+constexpr int kProfRing = 64;
+constexpr int kProfKinds = 6;
 constexpr int kDescRing = 8;
 constexpr int64_t kLogCapPerStream = 1 << 16;
 
@@ -126,7 +134,7 @@ vsa_status check_params(const vsa_params& p) {
     if (p.lf_offset != 1) return fail(VSA_E_UNSUPPORTED, "lf_offset must be 1");
     if (p.wmax < 16) return fail(VSA_E_INVAL, "wmax must be >= 16");
     if (p.k_max < 1 || p.k_max > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
-    if (p.w_hist < 1 || p.w_hist > kMaxHist) return fail(VSA_E_INVAL, "w_hist must be in 1..32");
+    if (p.w_hist < 1 || p.w_hist > kMaxHist) return fail(VSA_E_INVAL, "w_hist must be in 1..16");
     if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
     return VSA_OK;
 }
@@ -147,7 +155,7 @@ void layout(const Geo& g, int W, int H, int bits, int kmax, StreamDesc& sd) {
     sd.W = W; sd.H = H; sd.bits = bits;
     sd.L = g.L; sd.Lcap = g.Lcap; sd.Lf = g.Lf; sd.ltop = g.ltop; sd.nlev = g.nlev;
     sd.k_max = kmax;
-    sd.rs = 2 * kmax + 4;
+    sd.rs = 2 * kmax + 5;   // look-back + look-ahead of the deep check, + 1 for the next step's pyramid
     int64_t off = 0;
     for (int d = 0; d < g.nlev; ++d) {
         sd.wl[d] = g.wl[d]; sd.hl[d] = g.hl[d];
@@ -205,7 +213,10 @@ struct HostStream {
 struct vsa_engine {
     std::mutex mu;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // motion search, finish, decisions
+    hipStream_t stream_b = nullptr;    // uploads and pyramid (one step ahead at most)
+    hipEvent_t ev_a[2] = {nullptr, nullptr}, ev_b[2] = {nullptr, nullptr};
+    int64_t step_no = 0;
     vsa_params params{};
     DecideParams dp{};
     int schedule = 0;
@@ -217,6 +228,7 @@ struct vsa_engine {
     // engine-wide device tables
     StreamDesc* d_sds = nullptr;
     DecideState* d_states = nullptr;
+    vsa_shot_result* d_closed = nullptr;
     PairResult* d_results = nullptr;
     PairTask* d_sparse = nullptr;
     DeviceCursors* d_cur = nullptr;
@@ -226,7 +238,7 @@ struct vsa_engine {
     int64_t partials_cap = 0;
     int32_t* d_log = nullptr;
     // step descriptors: device buffer + pinned host ring
-    uint8_t* d_desc = nullptr;
+    uint8_t* d_desc = nullptr;     // two step descriptors (alternating steps)
     uint8_t* h_desc[kDescRing] = {nullptr};
     hipEvent_t desc_ev[kDescRing] = {nullptr};
     int desc_i = 0;
@@ -238,11 +250,17 @@ struct vsa_engine {
     uint64_t frames_read = 0, shots_read = 0;
     OutFrame* h_out_frames = nullptr;
     OutShot* h_out_shots = nullptr;
-    uint64_t emit_bound = 0;     // upper bound of frames emitted since the last sync
-    uint64_t shot_bound = 0;
+    uint64_t pushed_since_drain = 0;   // frames ingested since the last drain
+    // per-kernel timing (profile = 1): a ring of event pairs per step
+    int profile = 0;
+    hipEvent_t prof_ev[kProfRing][kProfKinds][2] = {};
+    int prof_used[kProfRing][kProfKinds] = {};
+    int64_t prof_step = 0;
+    double prof_ms[kProfKinds] = {0};
+    uint64_t prof_n[kProfKinds] = {0};
     int has10 = 0;
     int me_grid = 0;
-    uint64_t counters[8] = {0};
+    uint64_t counters[10] = {0};
 };
 
 namespace {
@@ -257,6 +275,7 @@ vsa_status ensure_partials(vsa_engine* e) {
     for (const HostStream& s : e->streams)
         if (s.open) need += s.consec_tiles + s.sparse_tiles_max;
     if (need <= e->partials_cap) return VSA_OK;
+    HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     if (e->d_partials) HIPCK(hipFree(e->d_partials), "hipFree");
     e->d_partials = nullptr;
@@ -276,7 +295,28 @@ uint64_t stream_bytes(const StreamDesc& sd, int64_t staging_pitch) {
     return (uint64_t)(sd.slot_bytes * sd.rs + info + mv + stage);
 }
 
+// Add the elapsed time of a recorded event pair to the totals (stream already
+// synchronised, or the pair is old enough to have completed).
+void prof_collect(vsa_engine* e, int slot) {
+    for (int k = 0; k < kProfKinds; ++k) {
+        if (!e->prof_used[slot][k]) continue;
+        float ms = 0.f;
+        if (hipEventSynchronize(e->prof_ev[slot][k][1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, e->prof_ev[slot][k][0], e->prof_ev[slot][k][1]) == hipSuccess) {
+            e->prof_ms[k] += ms;
+            e->prof_n[k] += 1;
+        }
+        e->prof_used[slot][k] = 0;
+    }
+}
+
+void prof_collect_all(vsa_engine* e) {
+    if (!e->profile) return;
+    for (int i = 0; i < kProfRing; ++i) prof_collect(e, i);
+}
+
 vsa_status drain(vsa_engine* e) {
+    HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     DeviceCursors c;
     HIPCK(hipMemcpy(&c, e->d_cur, sizeof c, hipMemcpyDeviceToHost), "read cursors");
@@ -316,9 +356,10 @@ vsa_status drain(vsa_engine* e) {
     }
     for (HostStream& s : e->streams)
         if (s.open && s.ended && s.frames_out >= s.T_end) s.done = true;
-    e->emit_bound = 0;
-    e->shot_bound = 0;
+    e->pushed_since_drain = 0;
     e->counters[6] = c.sparse_run;
+    e->counters[9] = c.sparse_blocks;
+    prof_collect_all(e);
     return VSA_OK;
 }
 
@@ -391,15 +432,20 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     const int M = cfg->max_streams;
     auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&e->stream_b, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < 2; ++i)
+        ok = hipEventCreateWithFlags(&e->ev_a[i], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&e->ev_b[i], hipEventDisableTiming) == hipSuccess;
     ok = ok && dalloc((void**)&e->d_sds, sizeof(StreamDesc) * M);
     ok = ok && dalloc((void**)&e->d_states, sizeof(DecideState) * M);
+    ok = ok && dalloc((void**)&e->d_closed, sizeof(vsa_shot_result) * kMaxClosed * M);
     ok = ok && dalloc((void**)&e->d_results, sizeof(PairResult) * M * kResSlots);
     ok = ok && dalloc((void**)&e->d_sparse, sizeof(PairTask) * M * kMaxTasksPerStream);
     ok = ok && dalloc((void**)&e->d_cur, sizeof(DeviceCursors));
     ok = ok && dalloc((void**)&e->d_out_frames, sizeof(OutFrame) * kFramesCap);
     ok = ok && dalloc((void**)&e->d_out_shots, sizeof(OutShot) * kShotsCap);
     e->desc_bytes = desc_size(M);
-    ok = ok && dalloc((void**)&e->d_desc, e->desc_bytes);
+    ok = ok && dalloc((void**)&e->d_desc, 2 * e->desc_bytes);
     for (int i = 0; ok && i < kDescRing; ++i) {
         ok = hipHostMalloc((void**)&e->h_desc[i], e->desc_bytes, hipHostMallocDefault) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&e->desc_ev[i], hipEventDisableTiming) == hipSuccess;
@@ -412,6 +458,11 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
              hipMemset(e->d_cur, 0, sizeof(DeviceCursors)) == hipSuccess &&
              hipMemset(e->d_results, 0, sizeof(PairResult) * M * kResSlots) == hipSuccess;
     }
+    e->profile = cfg->profile < 0 ? 0 : (cfg->profile > 2 ? 2 : cfg->profile);
+    for (int i = 0; ok && e->profile && i < kProfRing; ++i)
+        for (int k = 0; ok && k < kProfKinds; ++k)
+            for (int j = 0; ok && j < 2; ++j)
+                ok = hipEventCreate(&e->prof_ev[i][k][j]) == hipSuccess;
     e->h_stage.assign(2 * M, nullptr);
     e->stage_ev.assign(2 * M, nullptr);
     if (!ok) {
@@ -425,12 +476,13 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
 void vsa_engine_destroy(vsa_engine* e) {
     if (!e) return;
     (void)hipSetDevice(e->device);
+    if (e->stream_b) (void)hipStreamSynchronize(e->stream_b);
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     for (size_t i = 0; i < e->streams.size(); ++i)
         if (e->streams[i].mem) (void)hipFree(e->streams[i].mem);
     for (uint8_t* h : e->h_stage) if (h) (void)hipHostFree(h);
     for (hipEvent_t ev : e->stage_ev) if (ev) (void)hipEventDestroy(ev);
-    void* dev[] = {e->d_sds, e->d_states, e->d_results, e->d_sparse, e->d_cur, e->d_out_frames,
+    void* dev[] = {e->d_sds, e->d_states, e->d_closed, e->d_results, e->d_sparse, e->d_cur, e->d_out_frames,
                    e->d_out_shots, e->d_partials, e->d_log, e->d_desc};
     for (void* p : dev) if (p) (void)hipFree(p);
     for (int i = 0; i < kDescRing; ++i) {
@@ -439,6 +491,15 @@ void vsa_engine_destroy(vsa_engine* e) {
     }
     if (e->h_out_frames) (void)hipHostFree(e->h_out_frames);
     if (e->h_out_shots) (void)hipHostFree(e->h_out_shots);
+    for (int i = 0; i < kProfRing; ++i)
+        for (int k = 0; k < kProfKinds; ++k)
+            for (int j = 0; j < 2; ++j)
+                if (e->prof_ev[i][k][j]) (void)hipEventDestroy(e->prof_ev[i][k][j]);
+    for (int i = 0; i < 2; ++i) {
+        if (e->ev_a[i]) (void)hipEventDestroy(e->ev_a[i]);
+        if (e->ev_b[i]) (void)hipEventDestroy(e->ev_b[i]);
+    }
+    if (e->stream_b) (void)hipStreamDestroy(e->stream_b);
     if (e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -564,8 +625,8 @@ vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t
         s->pend_pitch = s->staging_pitch;
     } else if (src == VSA_SRC_DEVICE_COPY) {
         HIPCK(hipMemcpy2DAsync(s->staging_dev[slot], s->staging_pitch, luma, pitch, row, s->sd.H,
-                               hipMemcpyDeviceToDevice, e->stream), "device copy");
-        HIPCK(hipStreamSynchronize(e->stream), "device copy");
+                               hipMemcpyDeviceToDevice, e->stream_b), "device copy");
+        HIPCK(hipStreamSynchronize(e->stream_b), "device copy");
         s->pend_src = s->staging_dev[slot];
         s->pend_pitch = s->staging_pitch;
     } else if (src == VSA_SRC_DEVICE_BORROW) {
@@ -577,6 +638,30 @@ vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t
     s->pend_mode = src;
     s->pend_pts = pts;
     s->pending = true;
+    return VSA_OK;
+}
+
+vsa_status vsa_stream_push_batch(vsa_engine* e, int32_t n, const int32_t* sids, const void* const* planes,
+                                 const int64_t* pitches, int32_t src, const int64_t* pts, int32_t* status) {
+    if (!e || n < 0 || (n > 0 && (!sids || !planes || !pitches))) return fail(VSA_E_INVAL, "bad argument");
+    vsa_status first = VSA_OK;
+    for (int32_t i = 0; i < n; ++i) {
+        const vsa_status st = vsa_stream_push(e, sids[i], planes[i], pitches[i], src, pts ? pts[i] : 0);
+        if (status) status[i] = st;
+        if (st != VSA_OK && first == VSA_OK) first = st;
+    }
+    return first;
+}
+
+vsa_status vsa_engine_kernel_times(vsa_engine* e, double* ms, uint64_t* launches, int32_t reset) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!e->profile) return fail(VSA_E_STATE, "engine created without profile");
+    for (int k = 0; k < kProfKinds; ++k) {
+        if (ms) ms[k] = e->prof_ms[k];
+        if (launches) launches[k] = e->prof_n[k];
+        if (reset) { e->prof_ms[k] = 0.0; e->prof_n[k] = 0; }
+    }
     return VSA_OK;
 }
 
@@ -606,15 +691,29 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
     hipStream_t user = static_cast<hipStream_t>(hip_stream);
     // bound the output produced between syncs by the ring capacities
-    uint64_t step_frames = 0, step_shots = 0;
+    // A stream emits, between two drains, at most the frames it ingested plus
+    // the backlog it held (< rs) plus one; shots never outnumber frames + 3.
+    uint64_t backlog = 0, step_push = 0;
     int n_open = 0;
     for (const HostStream& s : e->streams)
-        if (s.open && !s.done) { step_frames += s.sd.rs; step_shots += 4; ++n_open; }
+        if (s.open && !s.done) { backlog += s.sd.rs + 4; step_push += s.pending ? 1 : 0; ++n_open; }
     if (n_open == 0) return VSA_OK;
-    if (e->emit_bound + step_frames > kFramesCap || e->shot_bound + step_shots > kShotsCap) {
+    if (e->pushed_since_drain + step_push + backlog > std::min(kFramesCap, kShotsCap)) {
         vsa_status st = drain(e);
         if (st != VSA_OK) return st;
     }
+    const int ps = (int)(e->prof_step % kProfRing);
+    if (e->profile) prof_collect(e, ps);
+    auto prof = [&](int k, int j, hipStream_t st) {
+        // profile 1: the pyramid and motion-search launches only; 2: every kernel
+        if (!e->profile || (e->profile == 1 && k > 2)) return;
+        (void)hipEventRecord(e->prof_ev[ps][k][j], st);
+        if (j == 1) e->prof_used[ps][k] = 1;
+    };
+    const int par = (int)(e->step_no & 1);
+    hipStream_t A = e->stream, Bs = e->stream_b;
+    // the ingest stream never runs more than one step ahead of the main stream
+    HIPCK(hipStreamWaitEvent(Bs, e->ev_a[par], 0), "wait");
     // step descriptor in a pinned ring slot
     const int di = e->desc_i;
     e->desc_i = (e->desc_i + 1) % kDescRing;
@@ -625,7 +724,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     int32_t* k1 = reinterpret_cast<int32_t*>(h + round_up(sizeof(StepStream) * M, 256));
     PairTask* consec = reinterpret_cast<PairTask*>(h + round_up(sizeof(StepStream) * M, 256) +
                                                     round_up(sizeof(int32_t) * M, 256));
-    int n_steps = 0, n_k1 = 0, k1_tiles = 0, n_consec = 0, consec_tiles = 0;
+    int n_steps = 0, n_k1 = 0, n_consec = 0, consec_tiles = 0;
     for (int sid = 0; sid < M; ++sid) {
         HostStream& s = e->streams[sid];
         if (!s.open || s.done) continue;
@@ -640,16 +739,14 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
             const int slot = s.next_frame & 1;
             if (s.pend_mode == VSA_SRC_HOST) {
                 HIPCK(hipMemcpyAsync(s.staging_dev[slot], s.pend_src, s.staging_pitch * s.sd.H,
-                                     hipMemcpyHostToDevice, e->stream), "plane upload");
-                HIPCK(hipEventRecord(e->stage_ev[2 * sid + slot], e->stream), "event");
+                                     hipMemcpyHostToDevice, Bs), "plane upload");
+                HIPCK(hipEventRecord(e->stage_ev[2 * sid + slot], Bs), "event");
                 ss.src = s.staging_dev[slot];
             } else {
                 ss.src = s.pend_src;
             }
             ss.src_pitch = s.pend_pitch;
             ss.k1_tiles = pyramid_tiles(s.sd);
-            ss.k1_prefix = k1_tiles;
-            k1_tiles += ss.k1_tiles;
             k1[n_k1++] = n_steps;
             if (s.next_frame >= 1) {
                 PairTask& t = consec[n_consec++];
@@ -672,51 +769,92 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         }
         ++n_steps;
     }
+    // group the pyramid work by (sample width, working level): one launch per group
+    struct K1Group { int bits, L, first, count, tiles; };
+    K1Group groups[10];
+    int n_groups = 0;
+    {
+        std::stable_sort(k1, k1 + n_k1, [&](int a, int b) {
+            const StreamDesc& sa = e->streams[steps[a].sid].sd;
+            const StreamDesc& sb = e->streams[steps[b].sid].sd;
+            return sa.bits * 8 + sa.L < sb.bits * 8 + sb.L;
+        });
+        for (int i = 0; i < n_k1; ++i) {
+            StepStream& ss = steps[k1[i]];
+            const StreamDesc& sd = e->streams[ss.sid].sd;
+            if (n_groups == 0 || groups[n_groups - 1].bits != sd.bits || groups[n_groups - 1].L != sd.L)
+                groups[n_groups++] = K1Group{sd.bits, sd.L, i, 0, 0};
+            K1Group& gr = groups[n_groups - 1];
+            ss.k1_prefix = gr.tiles;
+            gr.tiles += ss.k1_tiles;
+            gr.count += 1;
+        }
+    }
     const size_t off_k1 = round_up(sizeof(StepStream) * M, 256);
     const size_t off_consec = off_k1 + round_up(sizeof(int32_t) * M, 256);
     if (user) {
         hipEvent_t ev;
         HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
         HIPCK(hipEventRecord(ev, user), "event");
-        HIPCK(hipStreamWaitEvent(e->stream, ev, 0), "wait");
+        HIPCK(hipStreamWaitEvent(Bs, ev, 0), "wait");
+        HIPCK(hipStreamWaitEvent(A, ev, 0), "wait");
         (void)hipEventDestroy(ev);
     }
-    HIPCK(hipMemcpyAsync(e->d_desc, h, off_consec + sizeof(PairTask) * std::max(n_consec, 1),
-                         hipMemcpyHostToDevice, e->stream), "descriptor upload");
-    HIPCK(hipEventRecord(e->desc_ev[di], e->stream), "event");
-    const StepStream* d_steps = reinterpret_cast<const StepStream*>(e->d_desc);
-    const int32_t* d_k1 = reinterpret_cast<const int32_t*>(e->d_desc + off_k1);
-    const PairTask* d_consec = reinterpret_cast<const PairTask*>(e->d_desc + off_consec);
-    HIPCK(launch_pyramid(e->d_sds, d_steps, d_k1, n_k1, k1_tiles, e->stream), "pyramid launch");
+    uint8_t* ddesc = e->d_desc + par * e->desc_bytes;
+    prof(5, 0, Bs);
+    HIPCK(hipMemcpyAsync(ddesc, h, off_consec + sizeof(PairTask) * std::max(n_consec, 1),
+                         hipMemcpyHostToDevice, Bs), "descriptor upload");
+    HIPCK(hipEventRecord(e->desc_ev[di], Bs), "event");
+    const StepStream* d_steps = reinterpret_cast<const StepStream*>(ddesc);
+    const int32_t* d_k1 = reinterpret_cast<const int32_t*>(ddesc + off_k1);
+    const PairTask* d_consec = reinterpret_cast<const PairTask*>(ddesc + off_consec);
+    if (n_k1 > 0) {
+        prof(0, 0, Bs);
+        for (int gi = 0; gi < n_groups; ++gi) {
+            const K1Group& gr = groups[gi];
+            HIPCK(launch_pyramid(gr.bits, gr.L, e->d_sds, d_steps, d_k1 + gr.first, gr.count, gr.tiles, Bs),
+                  "pyramid launch");
+        }
+        prof(0, 1, Bs);
+    }
+    HIPCK(hipEventRecord(e->ev_b[par], Bs), "event");
+    HIPCK(hipStreamWaitEvent(A, e->ev_b[par], 0), "wait");
     // persistent motion-search grid: enough workgroups for the largest possible step
     int64_t max_tiles = consec_tiles;
     for (const HostStream& s : e->streams) if (s.open && !s.done) max_tiles += s.sparse_tiles_max;
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), e->me_grid);
+    prof(1, 0, A);
     HIPCK(launch_me(8, e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials, nullptr,
-                    nullptr, grid, e->stream), "motion search launch");
-    if (e->has10)
+                    nullptr, grid, par ^ 1, A), "motion search launch");
+    prof(1, 1, A);
+    if (e->has10) {
+        prof(2, 0, A);
         HIPCK(launch_me(10, e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials,
-                        nullptr, nullptr, grid, e->stream), "motion search launch");
+                        nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
+        prof(2, 1, A);
+    }
     const int max_tasks = n_consec + n_steps * kMaxTasksPerStream;
     const int fgrid = std::min(std::max((max_tasks + 3) / 4, 1), 1024);
+    prof(3, 0, A);
     HIPCK(launch_finish(e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials,
-                        e->d_results, e->dp, nullptr, nullptr, fgrid, e->stream), "finish launch");
+                        e->d_results, e->dp, nullptr, nullptr, fgrid, par ^ 1, A), "finish launch");
+    prof(3, 1, A);
+    prof(4, 0, A);
     HIPCK(launch_decide(e->d_sds, e->d_states, e->d_results, d_steps, n_steps, e->dp, e->d_sparse, e->d_cur,
                         e->d_out_frames, kFramesCap, e->d_out_shots, kShotsCap, e->d_log, kLogCapPerStream,
-                        e->stream), "decide launch");
-    if (user) {
-        hipEvent_t ev;
-        HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
-        HIPCK(hipEventRecord(ev, e->stream), "event");
-        HIPCK(hipStreamWaitEvent(user, ev, 0), "wait");
-        (void)hipEventDestroy(ev);
-    }
+                        e->d_closed, par, A), "decide launch");
+    prof(4, 1, A);
+    prof(5, 1, A);
+    HIPCK(hipEventRecord(e->ev_a[par], A), "event");
+    e->prof_step += 1;
+    e->step_no += 1;
+    if (user) HIPCK(hipStreamWaitEvent(user, e->ev_a[par], 0), "wait");
     for (HostStream& s : e->streams)
         if (s.open && s.pending) { s.pending = false; s.next_frame += 1; }
-    e->emit_bound += step_frames;
-    e->shot_bound += step_shots;
+    e->pushed_since_drain += step_push;
     e->counters[0] += 1;
     e->counters[7] += (uint64_t)n_consec;
+    for (int i = 0; i < n_consec; ++i) e->counters[8] += (uint64_t)(consec[i].tiles >= 0 ? e->streams[consec[i].sid].sd.B_L : 0);
     return VSA_OK;
 }
 
@@ -762,6 +900,7 @@ vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv,
     if (frame < 0 || frame + 1 >= s->next_frame || frame < s->next_frame - s->sd.rs)
         return fail(VSA_E_INVAL, "frame not held on the device");
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream_b), "sync");
     HIPCK(hipStreamSynchronize(e->stream), "sync");
     HIPCK(hipMemcpy(mv, s->sd.mv + (frame % s->sd.rs) * s->sd.B_L * 2, (size_t)s->sd.B_L * 2,
                     hipMemcpyDeviceToHost), "motion copy");
@@ -774,6 +913,7 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid) {
     HostStream* s = get_stream(e, sid);
     if (!s) return fail(VSA_E_INVAL, "no such stream");
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream_b), "sync");
     HIPCK(hipStreamSynchronize(e->stream), "sync");
     // records of this stream still in the device ring are dropped at the next drain
     vsa_status st = drain(e);
@@ -784,15 +924,15 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid) {
     return st;
 }
 
-vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out8) {
-    if (!e || !out8) return fail(VSA_E_INVAL, "NULL argument");
+vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n) {
+    if (!e || !out || n < 0) return fail(VSA_E_INVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(e->mu);
     int open = 0;
     for (const HostStream& s : e->streams) if (s.open) ++open;
     e->counters[1] = (uint64_t)open;
     e->counters[4] = e->used;
     e->counters[5] = e->budget;
-    std::memcpy(out8, e->counters, sizeof e->counters);
+    for (int32_t i = 0; i < n && i < 10; ++i) out[i] = e->counters[i];
     return VSA_OK;
 }
 
@@ -803,6 +943,7 @@ int32_t vsa_debug_measure_log(vsa_engine* e, int32_t sid, int32_t* keys, int32_t
     if (!s) return fail(VSA_E_INVAL, "no such stream");
     if (!e->d_log) return fail(VSA_E_STATE, "engine created without debug_log");
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream_b), "sync");
     HIPCK(hipStreamSynchronize(e->stream), "sync");
     DecideState st;
     HIPCK(hipMemcpy(&st, e->d_states + sid, sizeof st, hipMemcpyDeviceToHost), "state");
@@ -861,7 +1002,7 @@ vsa_status vsa_debug_levels(const vsa_params* pp, const void* luma, int32_t W, i
     if (err == hipSuccess) err = hipMemcpy(ddesc, &ss, sizeof ss, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(ddesc + 256, &k1idx, sizeof k1idx, hipMemcpyHostToDevice);
     if (err == hipSuccess)
-        err = launch_pyramid(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<StepStream*>(ddesc),
+        err = launch_pyramid(bits, sd.L, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<StepStream*>(ddesc),
                              reinterpret_cast<int32_t*>(ddesc + 256), 1, ss.k1_tiles, nullptr);
     if (err == hipSuccess) err = hipDeviceSynchronize();
     if (err == hipSuccess) err = hipMemcpy(host.data(), ring, sd.slot_bytes, hipMemcpyDeviceToHost);
@@ -942,10 +1083,10 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     const DecideParams dp = decide_params(p, 0);
     if (err == hipSuccess)
         err = launch_me(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
-                        nullptr, nullptr, part, dmv, dsad, std::min(t.tiles, 1024), nullptr);
+                        nullptr, nullptr, part, dmv, dsad, std::min(t.tiles, 1024), 0, nullptr);
     if (err == hipSuccess)
         err = launch_finish(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
-                            nullptr, nullptr, part, nullptr, dp, dints, ddbl, 1, nullptr);
+                            nullptr, nullptr, part, nullptr, dp, dints, ddbl, 1, 0, nullptr);
     if (err == hipSuccess) err = hipDeviceSynchronize();
     if (err == hipSuccess && mv) err = hipMemcpy(mv, dmv, 2 * (size_t)B, hipMemcpyDeviceToHost);
     if (err == hipSuccess && sad) err = hipMemcpy(sad, dsad, sizeof(int32_t) * B, hipMemcpyDeviceToHost);
@@ -992,7 +1133,7 @@ vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, 
     if (kmax < 1 || kmax > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
     StreamDesc sd;
     std::memset(&sd, 0, sizeof sd);
-    sd.active = 1; sd.k_max = kmax; sd.rs = 2 * kmax + 4; sd.L = 0; sd.Lcap = kMaxLevels - 1;
+    sd.active = 1; sd.k_max = kmax; sd.rs = 2 * kmax + 5; sd.L = 0; sd.Lcap = kMaxLevels - 1;
     sd.ltop = kMaxLevels - 1; sd.nlev = kMaxLevels; sd.Lf = 0;
     for (int d = 0; d < kMaxLevels; ++d) { sd.wl[d] = 16; sd.hl[d] = 16; }
     sd.wf = 16; sd.hf = 16;

@@ -49,7 +49,7 @@ class EngineConfig(C.Structure):
     _fields_ = [
         ("device", C.c_int32), ("max_streams", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
         ("schedule", C.c_int32), ("use_graph", C.c_int32), ("params", C.POINTER(Params)),
-        ("debug_log", C.c_int32), ("me_tile", C.c_int32),
+        ("debug_log", C.c_int32), ("me_tile", C.c_int32), ("profile", C.c_int32),
     ]
 
 
@@ -79,7 +79,7 @@ SYMBOLS = [
     "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
     "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
-    "vsa_debug_measure_log",
+    "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times",
 ]
 
 _lib = None
@@ -111,7 +111,7 @@ def lib():
         "vsa_poll_shots": (i32, [P, i32, P, i32]),
         "vsa_get_motion": (i32, [P, i32, i64, P, i32, C.POINTER(i32), C.POINTER(i32)]),
         "vsa_stream_close": (i32, [P, i32]),
-        "vsa_engine_counters": (i32, [P, P]),
+        "vsa_engine_counters": (i32, [P, P, i32]),
         "vsa_last_error": (C.c_char_p, []),
         "vsa_debug_levels": (i32, [C.POINTER(Params), P, i32, i32, i64, i32, P, i64, C.POINTER(i64)]),
         "vsa_debug_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i32, i32, P, P, P, P]),
@@ -119,6 +119,8 @@ def lib():
         "vsa_debug_decide": (i32, [C.POINTER(Params), i32, i32, i32, P, P, P, P, P, P, P, P, P, i32,
                                    C.POINTER(i32), P, i32, C.POINTER(i32)]),
         "vsa_debug_measure_log": (i32, [P, i32, P, i32]),
+        "vsa_stream_push_batch": (i32, [P, i32, P, P, P, i32, P, P]),
+        "vsa_engine_kernel_times": (i32, [P, P, P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -170,11 +172,12 @@ class Engine:
 
     def __init__(self, device: int = 0, max_streams: int = 64, hbm_budget_bytes: int = 0,
                  schedule: int = SCHEDULE_SPARSE, use_graph: int = 0, params: Optional[dict] = None,
-                 debug_log: int = 0):
+                 debug_log: int = 0, profile: int = 0):
         self._params = make_params(params)
         cfg = EngineConfig(device=device, max_streams=max_streams, hbm_budget_bytes=hbm_budget_bytes,
                            schedule=schedule, use_graph=use_graph,
-                           params=C.pointer(self._params), debug_log=debug_log, me_tile=0)
+                           params=C.pointer(self._params), debug_log=debug_log, me_tile=0,
+                           profile=profile)
         h = C.c_void_p()
         _check(lib().vsa_engine_create(C.byref(cfg), C.byref(h)), "engine_create")
         self.h = h
@@ -221,6 +224,21 @@ class Engine:
         assert t.dim() == 2 and t.is_cuda and t.stride(1) == 1
         return self.stream_push_device(sid, t.data_ptr(), t.stride(0) * t.element_size(), mode, pts)
 
+    def stream_push_batch(self, sids: np.ndarray, ptrs: np.ndarray, pitches: np.ndarray,
+                          mode: int = SRC_DEVICE_BORROW, pts: Optional[np.ndarray] = None) -> int:
+        """One call for many streams: sids int32[n], ptrs uint64[n] (host or device
+        addresses per mode), pitches int64[n] bytes, pts int64[n] (optional)."""
+        n = len(sids)
+        return lib().vsa_stream_push_batch(self.h, n, _ptr(sids), _ptr(ptrs), _ptr(pitches), mode,
+                                           _ptr(pts), None)
+
+    def kernel_times(self, reset: bool = False) -> dict:
+        ms = np.zeros(6, np.float64)
+        n = np.zeros(6, np.uint64)
+        _check(lib().vsa_engine_kernel_times(self.h, _ptr(ms), _ptr(n), int(reset)), "engine_kernel_times")
+        names = ("pyramid", "me8", "me10", "finish", "decide", "step")
+        return {k: (float(m), int(c)) for k, m, c in zip(names, ms, n)}
+
     def stream_end(self, sid: int):
         _check(lib().vsa_stream_end(self.h, sid), "stream_end")
 
@@ -256,10 +274,10 @@ class Engine:
         return mv
 
     def counters(self) -> dict:
-        out = np.zeros(8, np.uint64)
-        _check(lib().vsa_engine_counters(self.h, _ptr(out)), "engine_counters")
+        out = np.zeros(10, np.uint64)
+        _check(lib().vsa_engine_counters(self.h, _ptr(out), 10), "engine_counters")
         keys = ("steps", "streams_open", "admitted", "refused", "bytes_in_use", "budget",
-                "sparse_tasks", "consecutive_tasks")
+                "sparse_tasks", "consecutive_tasks", "consecutive_blocks", "sparse_blocks")
         return {k: int(v) for k, v in zip(keys, out)}
 
     def measure_log(self, sid: int) -> np.ndarray:

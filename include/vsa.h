@@ -209,7 +209,7 @@ int32_t vsa_poll_shots(vsa_engine* e, int32_t sid, vsa_shot_result* out, int32_t
 
 /* Motion field of the pair (frame -> frame+1) of stream sid at the working
  * level, as nby x nbx pairs (dx, dy) of int8, if that frame is still held on
- * the device (the last 2 k_max + 5 frames).  Synchronises the engine. */
+ * the device (the last 2 k_max + 7 frames).  Synchronises the engine. */
 vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
                           int32_t cap_blocks, int32_t* nbx, int32_t* nby);
 
@@ -220,7 +220,9 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
  * admitted, [3] admissions refused, [4] HBM bytes held by streams, [5] budget
  * bytes, [6] sparse pair tasks planned, [7] consecutive pair tasks run,
  * [8] blocks of the consecutive pairs, [9] blocks of the sparse pairs
- * (device-side figures as of the last vsa_sync). */
+ * (device-side figures as of the last vsa_sync), and host nanoseconds spent
+ * in vsa_step: [10] building step descriptors, [11] uploads, [12] kernel
+ * launches and stream ordering, [13] in total. */
 vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n);
 
 /* Accumulated device time per kernel of engines created with profile = 1,

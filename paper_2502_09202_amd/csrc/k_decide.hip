@@ -25,6 +25,7 @@
 // with no contraction (-ffp-contract=off), so that the labels are bitwise
 // reproducible against a scalar CPU implementation.
 #include "vsa_internal.h"
+#include "pair_finish.h"
 
 namespace vsa {
 
@@ -380,36 +381,124 @@ __device__ __forceinline__ void log_task(int32_t* log, int64_t cap, DecideState&
 
 }  // namespace
 
-// One wavefront per stream (four per workgroup).  Lane 0 advances the
-// stream's state machine with its descriptor and state in registers, reserves
-// its slice of the next step's sparse task list (tasks and tiles from one
-// 64-bit atomic, so tile offsets grow with task order) and of the output
-// rings, and writes its tasks; then the whole wave copies the finished frame
-// and shot records out in parallel.  Streams never share a wave, so their
-// different control paths do not serialise each other.
-__global__ void __launch_bounds__(256) k_decide(
-    const StreamDesc* __restrict__ sds, DecideState* __restrict__ states, const PairResult* __restrict__ results,
-    const StepStream* __restrict__ steps, int32_t n_steps, DecideParams dp, PairTask* __restrict__ sparse_out,
-    DeviceCursors* __restrict__ cur, OutFrame* __restrict__ out_frames, uint64_t frames_cap,
-    OutShot* __restrict__ out_shots, uint64_t shots_cap, int32_t* __restrict__ log, int64_t log_cap,
-    vsa_shot_result* __restrict__ closed_buf, int32_t par) {
+__device__ __forceinline__ int64_t wsum64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wavefront per stream (eight per workgroup), after the step's motion search:
+//  1. the wave sums the tile partials of the stream's consecutive pair and
+//     lane 0 finishes it (NCC, SWR, AMM, ACT) into the frame's record;
+//  2. likewise for each sparse pair the stream planned last step, into the
+//     wave's result slots in LDS;
+//  3. lane 0 advances the stream's state machine with descriptor and state in
+//     registers, reserves its slice of the next step's sparse task list (tasks
+//     and tiles from one 64-bit atomic, so tile offsets grow with task order)
+//     and of the output rings, and writes its tasks;
+//  4. the wave copies the finished frame and shot records out in parallel.
+// Streams never share a wave, so their control paths do not serialise.
+__global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
+    const StreamDesc* __restrict__ sds, DecideState* __restrict__ states, const StepStream* __restrict__ steps,
+    int32_t n_steps, DecideParams dp, const TilePartial* __restrict__ partials, int32_t consec_tiles,
+    const PairTask* __restrict__ sparse_prev, PairTask* __restrict__ sparse_next, DeviceCursors* __restrict__ cur,
+    OutFrame* __restrict__ out_frames, uint64_t frames_cap, OutShot* __restrict__ out_shots, uint64_t shots_cap,
+    int32_t* __restrict__ log, int64_t log_cap, vsa_shot_result* __restrict__ closed_buf, int32_t par) {
     struct Bcast {
         FrameInfo* info;
-        int32_t rs, sid, e0, nframes, nshots, pad;
+        int32_t rs, sid, e0, nframes, nshots, ntasks, tiles, blocks;
         uint64_t fbase, sbase;
+        int32_t task, tile;
     };
-    __shared__ Bcast bc[4];
+    __shared__ Bcast bc[kDecideWaves];
+    __shared__ PairResult res[kDecideWaves][kResSlots];
+    constexpr int kMaxT = 3 + 2 * (kMaxKmax + 1);
+    __shared__ int32_t tpre[kDecideWaves][kMaxT];
+    __shared__ int64_t acc[kDecideWaves][kMaxT][6];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + wave;
+    const int i = blockIdx.x * kDecideWaves + wave;
     const bool active = i < n_steps;
+    StepStream ss;
+    int sid = -1;
+    if (active) {
+        ss = steps[i];
+        sid = ss.sid;
+        const StreamDesc& sd = sds[sid];
+        // 1. consecutive pair (frame-1 -> frame) of this step: lanes stride over its tiles
+        if (ss.has_frame && ss.consec_tiles > 0) {
+            int64_t a[6] = {0, 0, 0, 0, 0, 0};
+            for (int q = lane; q < ss.consec_tiles; q += 64) {
+                const TilePartial& p = partials[ss.consec_prefix + q];
+                a[0] += p.sx; a[1] += p.sy; a[2] += p.sxx; a[3] += p.syy; a[4] += p.sxy; a[5] += p.a;
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a[k] = wsum64(a[k]);
+            if (lane == 0) {
+                const int64_t B = sd.B_L, n = 64 * B;
+                double f[4];
+                finish_pair(a[0], a[1], a[2], a[3], a[4], n, a[5], B, dp.a0, f);
+                FrameInfo& fi = sd.info[(ss.frame - 1) % sd.rs];
+                fi.ncc = f[0]; fi.swr = f[1]; fi.amm = f[2]; fi.act = f[3];
+                for (int k = 0; k < 5; ++k) fi.mom[k] = a[k];
+                fi.n_pix = n;
+                fi.amm_num = a[5];
+                fi.n_blocks = (int32_t)B;
+                fi.flags |= VSA_F_HAS_PAIR | (a[5] < (int64_t)dp.a_static_fx * B ? VSA_F_STATIC : 0);
+            }
+        }
+        // 2. sparse pairs planned by the previous step.  A stream's tasks are
+        //    contiguous in the list and so are their tiles: the lanes stride
+        //    over the whole tile range once, add each partial to its task's
+        //    LDS accumulators, and lane j then finishes task j.
+        const int spb = states[sid].sp_base, spc = states[sid].sp_count;
+        PairTask mine;
+        mine.tiles = 0;
+        if (lane < spc) {
+            mine = sparse_prev[spb + lane];
+            tpre[wave][lane] = mine.tile_prefix;
+            for (int k = 0; k < 6; ++k) acc[wave][lane][k] = 0;
+        }
+        if (spc > 0) {
+            const int t0 = __shfl(mine.tile_prefix, 0, 64);
+            const int t_last = __shfl(mine.tile_prefix + mine.tiles, spc - 1, 64);
+            for (int q = t0 + lane; q < t_last; q += 64) {
+                int lo = 0, hi = spc - 1;       // last task whose first tile is <= q
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (tpre[wave][mid] <= q) lo = mid; else hi = mid - 1;
+                }
+                const TilePartial& p = partials[consec_tiles + q];
+                unsigned long long* acc_t = reinterpret_cast<unsigned long long*>(acc[wave][lo]);
+                atomicAdd(acc_t + 0, (unsigned long long)p.sx);
+                atomicAdd(acc_t + 1, (unsigned long long)p.sy);
+                atomicAdd(acc_t + 2, (unsigned long long)p.sxx);
+                atomicAdd(acc_t + 3, (unsigned long long)p.syy);
+                atomicAdd(acc_t + 4, (unsigned long long)p.sxy);
+                atomicAdd(acc_t + 5, (unsigned long long)p.a);
+            }
+        }
+        if (lane < spc && mine.epoch == sd.epoch && mine.result >= 0) {
+            const int64_t* a = acc[wave][lane];
+            int w, h;
+            if (mine.ref_field != PL_FRAME) { w = sd.wf; h = sd.hf; }
+            else { w = sd.wl[mine.level - sd.L]; h = sd.hl[mine.level - sd.L]; }
+            const int64_t B = (int64_t)(w / kBlock) * (h / kBlock), n = 64 * B;
+            double f[4];
+            finish_pair(a[0], a[1], a[2], a[3], a[4], n, a[5], B, dp.a0, f);
+            res[wave][mine.result].act = f[3];
+            res[wave][mine.result].swr = f[1];
+        }
+    }
+    __syncthreads();
+    // 3. decisions (lane 0 of each wave), counts of what the stream produces
+    StreamDesc sd;
+    DecideState st;
     if (active && lane == 0) {
-        const StepStream ss = steps[i];
-        const int sid = ss.sid;
-        const StreamDesc sd = sds[sid];
-        DecideState st = states[sid];
+        sd = sds[sid];
+        st = states[sid];
         vsa_shot_result* closed = closed_buf + (int64_t)sid * kMaxClosed;
         const int e0 = st.emitted;
-        advance(sd, st, closed, results + (int64_t)sid * kResSlots, dp, ss.has_frame, ss.frame, ss.ended_T);
+        advance(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T);
         const int nt = plan_task_count(sd, st);
         int tiles = 0, blocks = 0;
         for (int q = 0; q < nt; ++q) {
@@ -418,33 +507,55 @@ __global__ void __launch_bounds__(256) k_decide(
             const PlaneDims pd = plane_dims(sd, pt);
             blocks += (pd.w / kBlock) * (pd.h / kBlock);
         }
-        const int nframes = st.t - e0;
-        const unsigned long long res =
-            nt ? atomicAdd(&cur->sparse_tt[par], ((unsigned long long)nt << 32) | (unsigned long long)tiles) : 0ull;
-        const uint64_t fbase = nframes ? atomicAdd((unsigned long long*)&cur->frames_written,
-                                                   (unsigned long long)nframes) : 0ull;
-        const uint64_t sbase = st.n_closed ? atomicAdd((unsigned long long*)&cur->shots_written,
-                                                       (unsigned long long)st.n_closed) : 0ull;
-        if (nt) {
-            atomicAdd((unsigned long long*)&cur->sparse_run, (unsigned long long)nt);
-            atomicAdd((unsigned long long*)&cur->sparse_blocks, (unsigned long long)blocks);
+        Bcast& b = bc[wave];
+        b.info = sd.info; b.rs = sd.rs; b.sid = sid; b.e0 = e0; b.nframes = st.t - e0; b.nshots = st.n_closed;
+        b.ntasks = nt; b.tiles = tiles; b.blocks = blocks;
+    } else if (lane == 0) {
+        Bcast& b = bc[wave];
+        b.nframes = 0; b.nshots = 0; b.ntasks = 0; b.tiles = 0; b.blocks = 0;
+    }
+    __syncthreads();
+    // one reservation per counter for the whole workgroup
+    if (threadIdx.x == 0) {
+        int nt = 0, ti = 0, nf = 0, ns = 0, bl = 0;
+        for (int w = 0; w < kDecideWaves; ++w) {
+            nt += bc[w].ntasks; ti += bc[w].tiles; nf += bc[w].nframes; ns += bc[w].nshots; bl += bc[w].blocks;
         }
+        const unsigned long long rsv =
+            nt ? atomicAdd(&cur->sparse_tt[par].v, ((unsigned long long)nt << 32) | (unsigned long long)ti) : 0ull;
+        const unsigned long long fb = nf ? atomicAdd(&cur->frames_written.v, (unsigned long long)nf) : 0ull;
+        const unsigned long long sb = ns ? atomicAdd(&cur->shots_written.v, (unsigned long long)ns) : 0ull;
+        if (nt) {
+            atomicAdd(&cur->sparse_run.v, (unsigned long long)nt);
+            atomicAdd(&cur->sparse_blocks.v, (unsigned long long)bl);
+        }
+        int task = tt_tasks(rsv), tile = tt_tiles(rsv);
+        uint64_t f = fb, s2 = sb;
+        for (int w = 0; w < kDecideWaves; ++w) {
+            bc[w].task = task; bc[w].tile = tile; bc[w].fbase = f; bc[w].sbase = s2;
+            task += bc[w].ntasks; tile += bc[w].tiles; f += bc[w].nframes; s2 += bc[w].nshots;
+        }
+    }
+    __syncthreads();
+    if (active && lane == 0) {
+        const Bcast& b = bc[wave];
         int32_t* slog = log ? log + (int64_t)sid * log_cap * 6 : nullptr;
-        int task = tt_tasks(res), tile = tt_tiles(res);
-        for (int q = 0; q < nt; ++q) {
+        int tile = b.tile;
+        for (int q = 0; q < b.ntasks; ++q) {
             PairTask t = plan_task(sd, st, sid, q);
             t.tile_prefix = tile;
             tile += t.tiles;
-            sparse_out[task + q] = t;
+            sparse_next[b.task + q] = t;
             log_task(slog, log_cap, st, t);
         }
+        st.sp_base = b.task;
+        st.sp_count = b.ntasks;
         st.emitted = st.t;
         states[sid] = st;
-        bc[wave] = Bcast{sd.info, sd.rs, sid, e0, nframes, st.n_closed, 0, fbase, sbase};
     }
-    __syncthreads();
     if (!active) return;
-    const Bcast b = bc[wave];
+    // 4. records out, the whole wave
+    const Bcast& b = bc[wave];
     for (int q = lane; q < b.nframes; q += 64) {
         OutFrame& o = out_frames[(b.fbase + (uint64_t)q) % frames_cap];
         o.sid = b.sid;
@@ -525,15 +636,17 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
     *st_ = st;
 }
 
-hipError_t launch_decide(const StreamDesc* sds, DecideState* states, const PairResult* results,
-                         const StepStream* steps, int32_t n_steps, const DecideParams& dp, PairTask* sparse_out,
-                         DeviceCursors* cur, OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots,
-                         uint64_t shots_cap, int32_t* log, int64_t log_cap, vsa_shot_result* closed_buf,
-                         int32_t par, hipStream_t s) {
+hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, const StepStream* steps, int32_t n_steps,
+                                const DecideParams& dp, const TilePartial* partials, int32_t consec_tiles,
+                                const PairTask* sparse_prev, PairTask* sparse_next, DeviceCursors* cur,
+                                OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots, uint64_t shots_cap,
+                                int32_t* log, int64_t log_cap, vsa_shot_result* closed_buf, int32_t par,
+                                hipStream_t s) {
     if (n_steps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_decide, dim3((n_steps + 3) / 4), dim3(256), 0, s, sds, states, results, steps,
-                       n_steps, dp, sparse_out, cur, out_frames, frames_cap, out_shots, shots_cap, log, log_cap,
-                       closed_buf, par);
+    hipLaunchKernelGGL(k_finish_decide, dim3((n_steps + kDecideWaves - 1) / kDecideWaves), dim3(64 * kDecideWaves), 0,
+                       s, sds, states, steps, n_steps, dp,
+                       partials, consec_tiles, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
+                       shots_cap, log, log_cap, closed_buf, par);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 // K3 sums the tile partials of each pair and forms the doubles in a fixed
 // order with no contraction.
 #include "vsa_internal.h"
+#include "pair_finish.h"
 
 namespace vsa {
 
@@ -110,6 +111,9 @@ __device__ __forceinline__ uint64_t pk64(uint32_t lo, uint32_t hi) {
 }
 
 // 8-bit search for one lane: returns the best key (SAD << 16 | rank).
+// The lane's four dy rows are visited one at a time (eight J rows each, read
+// from LDS), which keeps only five accumulators live; register pressure, not
+// LDS bandwidth, is what limits this kernel's occupancy.
 __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, const uint16_t* rank, int bx,
                                             int by, int q) {
     uint32_t r0[8], r1[8];
@@ -120,47 +124,36 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
         r1[j] = v.y;
     }
     uint32_t best = 0xffffffffu;
-    // dy = -8+4q .. -5+4q: J rows (window coords) 8*by + 4q + rr, rr = 0..10
     const int dy0 = -8 + 4 * q;
-    uint64_t acc[4][4];
-    uint32_t acc8[4];
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < 4; ++i) {
-        acc8[i] = 0;
+        // J rows (window coords) 8*by + 4q + i + j, j = 0..7
+        const uint8_t* jb = sJ + (8 * by + 4 * q + i) * kJW8 + 8 * bx;
+        uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        uint32_t a8 = 0;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) acc[i][g] = 0;
-    }
-    const uint8_t* jb = sJ + (8 * by + 4 * q) * kJW8 + 8 * bx;
-#pragma unroll
-    for (int rr = 0; rr < 11; ++rr) {
-        const uint2 a = *reinterpret_cast<const uint2*>(jb + rr * kJW8);
-        const uint2 b = *reinterpret_cast<const uint2*>(jb + rr * kJW8 + 8);
-        const uint2 c = *reinterpret_cast<const uint2*>(jb + rr * kJW8 + 16);
-        const uint32_t d[6] = {a.x, a.y, b.x, b.y, c.x, c.y};   // d[k] = dword at x0-8+4k
-        const uint64_t w01 = pk64(d[0], d[1]), w12 = pk64(d[1], d[2]), w23 = pk64(d[2], d[3]);
-        const uint64_t w34 = pk64(d[3], d[4]), w45 = pk64(d[4], d[5]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = rr - i;
-            if (j < 0 || j > 7) continue;
-            acc[i][0] = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], acc[i][0]);
-            acc[i][0] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], acc[i][0]);
-            acc[i][1] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], acc[i][1]);
-            acc[i][1] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], acc[i][1]);
-            acc[i][2] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r0[j], acc[i][2]);
-            acc[i][2] = __builtin_amdgcn_qsad_pk_u16_u8(w34, r1[j], acc[i][2]);
-            acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w34, r0[j], acc[i][3]);
-            acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w45, r1[j], acc[i][3]);
-            acc8[i] = __builtin_amdgcn_sad_u8(d[4], r0[j], acc8[i]);
-            acc8[i] = __builtin_amdgcn_sad_u8(d[5], r1[j], acc8[i]);
+        for (int j = 0; j < 8; ++j) {
+            const uint2 a = *reinterpret_cast<const uint2*>(jb + j * kJW8);
+            const uint2 b = *reinterpret_cast<const uint2*>(jb + j * kJW8 + 8);
+            const uint2 c = *reinterpret_cast<const uint2*>(jb + j * kJW8 + 16);
+            const uint64_t w01 = pk64(a.x, a.y), w12 = pk64(a.y, b.x), w23 = pk64(b.x, b.y);
+            const uint64_t w34 = pk64(b.y, c.x), w45 = pk64(c.x, c.y);
+            a0 = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], a0);
+            a0 = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], a0);
+            a1 = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], a1);
+            a1 = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], a1);
+            a2 = __builtin_amdgcn_qsad_pk_u16_u8(w23, r0[j], a2);
+            a2 = __builtin_amdgcn_qsad_pk_u16_u8(w34, r1[j], a2);
+            a3 = __builtin_amdgcn_qsad_pk_u16_u8(w34, r0[j], a3);
+            a3 = __builtin_amdgcn_qsad_pk_u16_u8(w45, r1[j], a3);
+            a8 = __builtin_amdgcn_sad_u8(c.x, r0[j], a8);
+            a8 = __builtin_amdgcn_sad_u8(c.y, r1[j], a8);
         }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
         const uint16_t* rk = rank + (dy0 + i + kRadius) * kCand;
+        const uint64_t acc[4] = {a0, a1, a2, a3};
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const uint32_t lo = (uint32_t)acc[i][g], hi = (uint32_t)(acc[i][g] >> 32);
+            const uint32_t lo = (uint32_t)acc[g], hi = (uint32_t)(acc[g] >> 32);
             const uint32_t k0 = (lo << 16) | rk[4 * g + 0];
             const uint32_t k1 = (lo & 0xffff0000u) | rk[4 * g + 1];
             const uint32_t k2 = (hi << 16) | rk[4 * g + 2];
@@ -168,7 +161,7 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
             best = min(best, min(k0, k1));
             best = min(best, min(k2, k3));
         }
-        best = min(best, (acc8[i] << 16) | rk[16]);
+        best = min(best, (a8 << 16) | rk[16]);
     }
     // dy = +8 row, dx group q (dx = -8+4q .. -5+4q); lane q = 3 also dx = +8
     {
@@ -398,19 +391,22 @@ __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, Til
 // the sparse list (built on the device by the previous step's decision kernel).
 // One launch per sample width; tiles of the other width are skipped.
 template <typename T>
-__global__ void __launch_bounds__(kMEThreads) k_me(const StreamDesc* __restrict__ sds,
+__global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restrict__ sds,
                                                    const PairTask* __restrict__ consec, int32_t n_consec,
                                                    int32_t consec_tiles, const PairTask* __restrict__ sparse,
                                                    const DeviceCursors* __restrict__ cur,
                                                    TilePartial* __restrict__ partials, int8_t* dbg_mv,
-                                                   int32_t* dbg_sad, int32_t par_prev) {
+                                                   int32_t* dbg_sad, int32_t par_prev,
+                                                   unsigned long long* __restrict__ clear_tt) {
+    // clear this step's planning counter before the decision kernel adds to it
+    if (clear_tt && blockIdx.x == 0 && threadIdx.x == 0) *clear_tt = 0ull;
     __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
     __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
     __shared__ int64_t red[4 * 6];
     __shared__ uint16_t rank[kCand * kCand];
     for (int i = threadIdx.x; i < kCand * kCand; i += kMEThreads) rank[i] = c_rank[i];
     __syncthreads();
-    const unsigned long long tt = cur ? cur->sparse_tt[par_prev] : 0ull;
+    const unsigned long long tt = cur ? cur->sparse_tt[par_prev].v : 0ull;
     const int n_sparse = tt_tasks(tt);
     const int total = consec_tiles + tt_tiles(tt);
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -435,28 +431,6 @@ __global__ void __launch_bounds__(kMEThreads) k_me(const StreamDesc* __restrict_
     }
 }
 
-// NCC, SWR, AMM, ACT from the exact integers (operations in this order, no
-// contraction: this file is compiled with -ffp-contract=off).
-__device__ __forceinline__ void finish_pair(int64_t sx, int64_t sy, int64_t sxx, int64_t syy, int64_t sxy,
-                                         int64_t n, int64_t a, int64_t B, double a0, double out[4]) {
-    const int64_t cov = n * sxy - sx * sy;
-    const int64_t vx = n * sxx - sx * sx;
-    const int64_t vy = n * syy - sy * sy;
-    double ncc;
-    if (vx == 0 && vy == 0) ncc = 1.0;
-    else if (vx == 0 || vy == 0) ncc = 0.0;
-    else {
-        const double x3 = (double)vx * (double)vy;
-        const double x4 = __builtin_sqrt(x3);
-        const double c = (double)cov / x4;
-        ncc = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-    }
-    const double swr = 1.0 - ncc;
-    const double amm = (double)a / (256.0 * (double)B);
-    const double act = __builtin_sqrt((amm + a0) * swr);
-    out[0] = ncc; out[1] = swr; out[2] = amm; out[3] = act;
-}
-
 // One wave per pair task: sum its tile partials and finish it.
 __global__ void __launch_bounds__(256) k_finish(const StreamDesc* __restrict__ sds,
                                                 const PairTask* __restrict__ consec, int32_t n_consec,
@@ -467,9 +441,9 @@ __global__ void __launch_bounds__(256) k_finish(const StreamDesc* __restrict__ s
                                                 int64_t* dbg_ints, double* dbg_dbl, int32_t par_prev,
                                                 DeviceCursors* __restrict__ cur_w) {
     const int lane = threadIdx.x & 63;
-    const int total = n_consec + (cur ? tt_tasks(cur->sparse_tt[par_prev]) : 0);
+    const int total = n_consec + (cur ? tt_tasks(cur->sparse_tt[par_prev].v) : 0);
     // clear this step's planning counter before the decision kernel adds to it
-    if (cur_w && blockIdx.x == 0 && threadIdx.x == 0) cur_w->sparse_tt[par_prev ^ 1] = 0ull;
+    if (cur_w && blockIdx.x == 0 && threadIdx.x == 0) cur_w->sparse_tt[par_prev ^ 1].v = 0ull;
     for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < total; t += gridDim.x * 4) {
         const bool is_consec = t < n_consec;
         const PairTask& tk = is_consec ? consec[t] : sparse[t - n_consec];
@@ -553,12 +527,14 @@ hipError_t launch_me(int bits, const StreamDesc* sds, const PairTask* consec, in
                      TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid, int32_t par_prev,
                      hipStream_t s) {
     if (grid <= 0) return hipSuccess;
+    unsigned long long* clear_tt =
+        cur ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
     if (bits == 8)
         hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
-                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev);
+                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
     else
         hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
-                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev);
+                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
     return hipGetLastError();
 }
 

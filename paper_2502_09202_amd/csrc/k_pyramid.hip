@@ -15,6 +15,8 @@
 // plane plus the levels written.
 #include "vsa_internal.h"
 
+#include <algorithm>
+
 namespace vsa {
 
 namespace {
@@ -285,6 +287,21 @@ __global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ 
 
 int pyramid_tiles(const StreamDesc& sd) {
     return div_up(pyr_grid_w(sd), 16 * pyr_cw(sd.L)) * div_up(sd.hl[0], kPyrTH);
+}
+
+// Copy the step descriptor from mapped pinned host memory to device memory
+// (one pass, 16-byte words); cheaper to enqueue than an API copy of the same size.
+__global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+    const int64_t n = (bytes + 15) / 16;
+    if (n <= 0) return hipSuccess;
+    const int64_t grid = std::min<int64_t>((n + 255) / 256, 64);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)grid), dim3(256), 0, s, reinterpret_cast<const uint4*>(src),
+                       reinterpret_cast<uint4*>(dst), n);
+    return hipGetLastError();
 }
 
 // Launch the pyramid for one group of streams sharing sample width and L.

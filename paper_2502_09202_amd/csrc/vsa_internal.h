@@ -15,7 +15,7 @@ constexpr int kMaxLevels = 5;       // frame levels stored per ring slot: L .. L
 constexpr int kMaxKmax = 15;
 constexpr int kMaxHist = 16;
 constexpr int kMaxStreams = 1024;
-constexpr int kDecideThreads = 256;     // decision kernel: one workgroup, up to 4 streams per thread
+constexpr int kDecideWaves = 8;         // decision kernel: one wavefront per stream, 8 per workgroup
 
 // Field selector of a plane inside a ring slot.
 enum : int32_t { PL_FRAME = 0, PL_UPPER = 1, PL_LOWER = 2 };
@@ -111,6 +111,7 @@ struct DecideState {
     int32_t plan, plan_want, plan_fire, plan_deep, plan_nf, plan_kn;
     int32_t done;               // end of stream fully processed
     int32_t n_closed;           // shots closed by the last advance
+    int32_t sp_base, sp_count;  // where the planned tasks sit in that step's sparse list
     int64_t log_count;          // sparse measures logged
 };
 
@@ -136,7 +137,7 @@ struct StepStream {
     int32_t k1_tiles;           // pyramid tiles of this stream
     int32_t k1_prefix;          // first pyramid tile
     int32_t consec_tiles;       // ME tiles of its consecutive pair (0 if none)
-    int32_t consec_prefix;
+    int32_t consec_prefix;      // first tile (and partial) of that pair
 };
 
 // Output ring entries (device -> host).
@@ -150,15 +151,22 @@ struct OutShot {
 };
 
 // Counters and cursors in device memory.
+// Each counter sits on its own 128-byte line so that concurrent atomics on
+// different counters do not serialise on one line.
+struct alignas(128) DeviceCounter {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
+
 struct DeviceCursors {
-    uint64_t frames_written;     // monotonically increasing write cursor (OutFrame ring)
-    uint64_t shots_written;
+    DeviceCounter frames_written;    // monotonically increasing write cursor (OutFrame ring)
+    DeviceCounter shots_written;
     // sparse tasks planned by the decision kernel of steps of parity p, packed
-    // as (tasks << 32 | tiles); the next step's motion search reads it and its
-    // finish kernel clears the other entry before that step's decisions add to it
-    unsigned long long sparse_tt[2];
-    uint64_t sparse_run;         // total sparse tasks planned
-    uint64_t sparse_blocks;      // total 8x8 blocks of those tasks
+    // as (tasks << 32 | tiles); the next step's motion search reads it (and
+    // clears the other entry before that step's decisions add to it)
+    DeviceCounter sparse_tt[2];
+    DeviceCounter sparse_run;        // total sparse tasks planned
+    DeviceCounter sparse_blocks;     // total 8x8 blocks of those tasks
 };
 
 __host__ __device__ inline int tt_tasks(unsigned long long v) { return (int)(v >> 32); }

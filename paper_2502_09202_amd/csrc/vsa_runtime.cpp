@@ -1,7 +1,7 @@
 // vsa_runtime.cpp -- host runtime and C ABI of libvsa (see include/vsa.h).
 //
 // One engine = one HIP stream of work on one device.  Every open stream owns
-// one device allocation: a ring of 2 k_max + 5 frame slots (working level,
+// one device allocation: a ring of 2 k_max + 7 frame slots (working level,
 // the coarser levels used by the deep check and the two fields), the
 // per-frame records under construction, the motion fields of the
 // consecutive pairs, and two staging planes for copied input.  The engine
@@ -19,14 +19,16 @@
 //   K3    finish of every pair (NCC, SWR, AMM, ACT);
 //   K6    decisions, sparse-task compaction for the next step, records.
 // K1 and the uploads run on a second HIP stream ("ingest"); the rest on the
-// main stream.  Step s's pyramid may run while step s-1's motion search and
-// decisions are still executing (the ring holds one extra slot for that), but
-// never ahead of step s-2.  The two kernels stress different units (HBM vs
-// VALU/latency), so they overlap well.
+// main stream.  Step s's pyramid may run while steps s-3..s-1 are still in
+// their motion search and decisions (the ring holds three extra slots and the
+// step descriptor four copies for that), never further ahead.  The kernels
+// stress different units (HBM vs VALU/latency), so they overlap well, and the
+// main stream's wait for a pyramid is usually already satisfied.
 // Nothing is copied back until vsa_sync, which drains the device output rings.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -40,6 +42,7 @@
 #include "vsa_internal.h"
 
 namespace vsa {
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
 hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
                           hipStream_t);
 int pyramid_tiles(const StreamDesc& sd);
@@ -50,9 +53,10 @@ hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, c
                          DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
                          double*, int grid, int32_t par_prev, hipStream_t);
 hipError_t launch_finish_debug(const int64_t*, int64_t, double, double*, hipStream_t);
-hipError_t launch_decide(const StreamDesc*, DecideState*, const PairResult*, const StepStream*, int32_t,
-                         const DecideParams&, PairTask*, DeviceCursors*, OutFrame*, uint64_t, OutShot*, uint64_t,
-                         int32_t*, int64_t, vsa_shot_result*, int32_t, hipStream_t);
+hipError_t launch_finish_decide(const StreamDesc*, DecideState*, const StepStream*, int32_t, const DecideParams&,
+                                const TilePartial*, int32_t, const PairTask*, PairTask*, DeviceCursors*, OutFrame*,
+                                uint64_t, OutShot*, uint64_t, int32_t*, int64_t, vsa_shot_result*, int32_t,
+                                hipStream_t);
 hipError_t launch_decide_replay(const StreamDesc&, DecideState*, PairResult*, const DecideParams&, int32_t,
                                 const double*, const double*, const uint8_t*, const double*, const double*,
                                 const double*, const double*, vsa_frame_result*, vsa_shot_result*, int32_t,
@@ -85,6 +89,8 @@ constexpr int kMaxTasksPerStream = 3 + 2 * (kMaxKmax + 1);
 constexpr uint64_t kFramesCap = 1u << 16;
 constexpr uint64_t kShotsCap = 1u << 16;
 constexpr int kProfRing = 64;
+// The ingest stream may run up to kAhead steps ahead of the main stream.
+constexpr int kAhead = 3;
 constexpr int kProfKinds = 6;
 constexpr int kDescRing = 8;
 constexpr int64_t kLogCapPerStream = 1 << 16;
@@ -155,7 +161,7 @@ void layout(const Geo& g, int W, int H, int bits, int kmax, StreamDesc& sd) {
     sd.W = W; sd.H = H; sd.bits = bits;
     sd.L = g.L; sd.Lcap = g.Lcap; sd.Lf = g.Lf; sd.ltop = g.ltop; sd.nlev = g.nlev;
     sd.k_max = kmax;
-    sd.rs = 2 * kmax + 5;   // look-back + look-ahead of the deep check, + 1 for the next step's pyramid
+    sd.rs = 2 * kmax + 4 + kAhead;   // deep-check look-back + look-ahead, + the pyramids running ahead
     int64_t off = 0;
     for (int d = 0; d < g.nlev; ++d) {
         sd.wl[d] = g.wl[d]; sd.hl[d] = g.hl[d];
@@ -215,7 +221,7 @@ struct vsa_engine {
     int device = 0;
     hipStream_t stream = nullptr;      // motion search, finish, decisions
     hipStream_t stream_b = nullptr;    // uploads and pyramid (one step ahead at most)
-    hipEvent_t ev_a[2] = {nullptr, nullptr}, ev_b[2] = {nullptr, nullptr};
+    hipEvent_t ev_a[kAhead + 1] = {}, ev_b[kAhead + 1] = {};
     int64_t step_no = 0;
     vsa_params params{};
     DecideParams dp{};
@@ -239,7 +245,9 @@ struct vsa_engine {
     int32_t* d_log = nullptr;
     // step descriptors: device buffer + pinned host ring
     uint8_t* d_desc = nullptr;     // two step descriptors (alternating steps)
-    uint8_t* h_desc[kDescRing] = {nullptr};
+    uint8_t* h_desc[kDescRing] = {nullptr};       // pinned, mapped
+    void* h_desc_dev[kDescRing] = {nullptr};      // device addresses of the same
+    std::vector<uint8_t> desc_build;              // descriptors are built here (cached memory)
     hipEvent_t desc_ev[kDescRing] = {nullptr};
     int desc_i = 0;
     size_t desc_bytes = 0;
@@ -260,7 +268,7 @@ struct vsa_engine {
     uint64_t prof_n[kProfKinds] = {0};
     int has10 = 0;
     int me_grid = 0;
-    uint64_t counters[10] = {0};
+    uint64_t counters[14] = {0};   // [10..13] host ns in vsa_step: descriptors, uploads, launches, total
 };
 
 namespace {
@@ -331,34 +339,34 @@ vsa_status drain(vsa_engine* e) {
             err = hipMemcpy(h_buf + first, d_ring, (n - first) * sizeof(Elem), hipMemcpyDeviceToHost);
         return err;
     };
-    if (c.frames_written > e->frames_read) {
-        if (c.frames_written - e->frames_read > kFramesCap) return fail(VSA_E_DEVICE, "frame ring overflow");
-        HIPCK(copy_ring(e->d_out_frames, e->h_out_frames, kFramesCap, e->frames_read, c.frames_written), "drain frames");
-        for (uint64_t i = 0; i < c.frames_written - e->frames_read; ++i) {
+    if (c.frames_written.v > e->frames_read) {
+        if (c.frames_written.v - e->frames_read > kFramesCap) return fail(VSA_E_DEVICE, "frame ring overflow");
+        HIPCK(copy_ring(e->d_out_frames, e->h_out_frames, kFramesCap, e->frames_read, c.frames_written.v), "drain frames");
+        for (uint64_t i = 0; i < c.frames_written.v - e->frames_read; ++i) {
             const OutFrame& o = e->h_out_frames[i];
             HostStream& s = e->streams[o.sid];
             if (!s.open) continue;
             s.fq.push_back(o.r);
             s.frames_out += 1;
         }
-        e->frames_read = c.frames_written;
+        e->frames_read = c.frames_written.v;
     }
-    if (c.shots_written > e->shots_read) {
-        if (c.shots_written - e->shots_read > kShotsCap) return fail(VSA_E_DEVICE, "shot ring overflow");
-        HIPCK(copy_ring(e->d_out_shots, e->h_out_shots, kShotsCap, e->shots_read, c.shots_written), "drain shots");
-        for (uint64_t i = 0; i < c.shots_written - e->shots_read; ++i) {
+    if (c.shots_written.v > e->shots_read) {
+        if (c.shots_written.v - e->shots_read > kShotsCap) return fail(VSA_E_DEVICE, "shot ring overflow");
+        HIPCK(copy_ring(e->d_out_shots, e->h_out_shots, kShotsCap, e->shots_read, c.shots_written.v), "drain shots");
+        for (uint64_t i = 0; i < c.shots_written.v - e->shots_read; ++i) {
             const OutShot& o = e->h_out_shots[i];
             HostStream& s = e->streams[o.sid];
             if (!s.open) continue;
             s.sq.push_back(o.r);
         }
-        e->shots_read = c.shots_written;
+        e->shots_read = c.shots_written.v;
     }
     for (HostStream& s : e->streams)
         if (s.open && s.ended && s.frames_out >= s.T_end) s.done = true;
     e->pushed_since_drain = 0;
-    e->counters[6] = c.sparse_run;
-    e->counters[9] = c.sparse_blocks;
+    e->counters[6] = c.sparse_run.v;
+    e->counters[9] = c.sparse_blocks.v;
     prof_collect_all(e);
     return VSA_OK;
 }
@@ -433,21 +441,23 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&e->stream_b, hipStreamNonBlocking) == hipSuccess;
-    for (int i = 0; ok && i < 2; ++i)
+    for (int i = 0; ok && i <= kAhead; ++i)
         ok = hipEventCreateWithFlags(&e->ev_a[i], hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&e->ev_b[i], hipEventDisableTiming) == hipSuccess;
     ok = ok && dalloc((void**)&e->d_sds, sizeof(StreamDesc) * M);
     ok = ok && dalloc((void**)&e->d_states, sizeof(DecideState) * M);
     ok = ok && dalloc((void**)&e->d_closed, sizeof(vsa_shot_result) * kMaxClosed * M);
     ok = ok && dalloc((void**)&e->d_results, sizeof(PairResult) * M * kResSlots);
-    ok = ok && dalloc((void**)&e->d_sparse, sizeof(PairTask) * M * kMaxTasksPerStream);
+    ok = ok && dalloc((void**)&e->d_sparse, 2 * sizeof(PairTask) * M * kMaxTasksPerStream);
     ok = ok && dalloc((void**)&e->d_cur, sizeof(DeviceCursors));
     ok = ok && dalloc((void**)&e->d_out_frames, sizeof(OutFrame) * kFramesCap);
     ok = ok && dalloc((void**)&e->d_out_shots, sizeof(OutShot) * kShotsCap);
     e->desc_bytes = desc_size(M);
-    ok = ok && dalloc((void**)&e->d_desc, 2 * e->desc_bytes);
+    e->desc_build.assign(e->desc_bytes, 0);
+    ok = ok && dalloc((void**)&e->d_desc, (kAhead + 1) * e->desc_bytes);
     for (int i = 0; ok && i < kDescRing; ++i) {
-        ok = hipHostMalloc((void**)&e->h_desc[i], e->desc_bytes, hipHostMallocDefault) == hipSuccess;
+        ok = hipHostMalloc((void**)&e->h_desc[i], e->desc_bytes, hipHostMallocMapped) == hipSuccess &&
+             hipHostGetDevicePointer(&e->h_desc_dev[i], e->h_desc[i], 0) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&e->desc_ev[i], hipEventDisableTiming) == hipSuccess;
     }
     ok = ok && hipHostMalloc((void**)&e->h_out_frames, sizeof(OutFrame) * kFramesCap, hipHostMallocDefault) == hipSuccess;
@@ -495,7 +505,7 @@ void vsa_engine_destroy(vsa_engine* e) {
         for (int k = 0; k < kProfKinds; ++k)
             for (int j = 0; j < 2; ++j)
                 if (e->prof_ev[i][k][j]) (void)hipEventDestroy(e->prof_ev[i][k][j]);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i <= kAhead; ++i) {
         if (e->ev_a[i]) (void)hipEventDestroy(e->ev_a[i]);
         if (e->ev_b[i]) (void)hipEventDestroy(e->ev_b[i]);
     }
@@ -685,9 +695,15 @@ int32_t vsa_stream_done(vsa_engine* e, int32_t sid) {
     return s->done ? 1 : 0;
 }
 
+static inline uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     if (!e) return fail(VSA_E_INVAL, "NULL engine");
     std::lock_guard<std::mutex> lk(e->mu);
+    const uint64_t t_start = now_ns();
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
     hipStream_t user = static_cast<hipStream_t>(hip_stream);
     // bound the output produced between syncs by the ring capacities
@@ -711,14 +727,16 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         if (j == 1) e->prof_used[ps][k] = 1;
     };
     const int par = (int)(e->step_no & 1);
+    const int slot_s = (int)(e->step_no % (kAhead + 1));
     hipStream_t A = e->stream, Bs = e->stream_b;
-    // the ingest stream never runs more than one step ahead of the main stream
-    HIPCK(hipStreamWaitEvent(Bs, e->ev_a[par], 0), "wait");
+    // the ingest stream never runs more than kAhead steps ahead of the main
+    // stream: before step s it waits for the main stream's step s - kAhead - 1
+    // (recorded in the same event slot)
+    HIPCK(hipStreamWaitEvent(Bs, e->ev_a[slot_s], 0), "wait");
     // step descriptor in a pinned ring slot
     const int di = e->desc_i;
     e->desc_i = (e->desc_i + 1) % kDescRing;
-    HIPCK(hipEventSynchronize(e->desc_ev[di]), "descriptor reuse");
-    uint8_t* h = e->h_desc[di];
+    uint8_t* h = e->desc_build.data();
     const int M = e->max_streams;
     StepStream* steps = reinterpret_cast<StepStream*>(h);
     int32_t* k1 = reinterpret_cast<int32_t*>(h + round_up(sizeof(StepStream) * M, 256));
@@ -792,6 +810,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     }
     const size_t off_k1 = round_up(sizeof(StepStream) * M, 256);
     const size_t off_consec = off_k1 + round_up(sizeof(int32_t) * M, 256);
+    const uint64_t t_built = now_ns();
     if (user) {
         hipEvent_t ev;
         HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
@@ -800,11 +819,18 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         HIPCK(hipStreamWaitEvent(A, ev, 0), "wait");
         (void)hipEventDestroy(ev);
     }
-    uint8_t* ddesc = e->d_desc + par * e->desc_bytes;
+    uint8_t* ddesc = e->d_desc + (size_t)slot_s * e->desc_bytes;
     prof(5, 0, Bs);
-    HIPCK(hipMemcpyAsync(ddesc, h, off_consec + sizeof(PairTask) * std::max(n_consec, 1),
-                         hipMemcpyHostToDevice, Bs), "descriptor upload");
+    {
+        // one sequential write into the pinned slot (after the device has read
+        // its previous contents), then a copy kernel on the ingest stream
+        const size_t used = off_consec + sizeof(PairTask) * std::max(n_consec, 1);
+        HIPCK(hipEventSynchronize(e->desc_ev[di]), "descriptor reuse");
+        std::memcpy(e->h_desc[di], h, used);
+        HIPCK(launch_copy16(e->h_desc_dev[di], ddesc, (int64_t)used, Bs), "descriptor upload");
+    }
     HIPCK(hipEventRecord(e->desc_ev[di], Bs), "event");
+    const uint64_t t_upload = now_ns();
     const StepStream* d_steps = reinterpret_cast<const StepStream*>(ddesc);
     const int32_t* d_k1 = reinterpret_cast<const int32_t*>(ddesc + off_k1);
     const PairTask* d_consec = reinterpret_cast<const PairTask*>(ddesc + off_consec);
@@ -817,41 +843,44 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         }
         prof(0, 1, Bs);
     }
-    HIPCK(hipEventRecord(e->ev_b[par], Bs), "event");
-    HIPCK(hipStreamWaitEvent(A, e->ev_b[par], 0), "wait");
+    HIPCK(hipEventRecord(e->ev_b[slot_s], Bs), "event");
+    HIPCK(hipStreamWaitEvent(A, e->ev_b[slot_s], 0), "wait");
     // persistent motion-search grid: enough workgroups for the largest possible step
     int64_t max_tiles = consec_tiles;
     for (const HostStream& s : e->streams) if (s.open && !s.done) max_tiles += s.sparse_tiles_max;
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), e->me_grid);
+    // sparse task lists alternate between steps: read the previous one, write the next
+    const size_t sp_cap = (size_t)M * kMaxTasksPerStream;
+    PairTask* sparse_prev = e->d_sparse + (size_t)(par ^ 1) * sp_cap;
+    PairTask* sparse_next = e->d_sparse + (size_t)par * sp_cap;
     prof(1, 0, A);
-    HIPCK(launch_me(8, e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials, nullptr,
+    HIPCK(launch_me(8, e->d_sds, d_consec, n_consec, consec_tiles, sparse_prev, e->d_cur, e->d_partials, nullptr,
                     nullptr, grid, par ^ 1, A), "motion search launch");
     prof(1, 1, A);
     if (e->has10) {
         prof(2, 0, A);
-        HIPCK(launch_me(10, e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials,
+        HIPCK(launch_me(10, e->d_sds, d_consec, n_consec, consec_tiles, sparse_prev, e->d_cur, e->d_partials,
                         nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
         prof(2, 1, A);
     }
-    const int max_tasks = n_consec + n_steps * kMaxTasksPerStream;
-    const int fgrid = std::min(std::max((max_tasks + 3) / 4, 1), 1024);
-    prof(3, 0, A);
-    HIPCK(launch_finish(e->d_sds, d_consec, n_consec, consec_tiles, e->d_sparse, e->d_cur, e->d_partials,
-                        e->d_results, e->dp, nullptr, nullptr, fgrid, par ^ 1, A), "finish launch");
-    prof(3, 1, A);
     prof(4, 0, A);
-    HIPCK(launch_decide(e->d_sds, e->d_states, e->d_results, d_steps, n_steps, e->dp, e->d_sparse, e->d_cur,
-                        e->d_out_frames, kFramesCap, e->d_out_shots, kShotsCap, e->d_log, kLogCapPerStream,
-                        e->d_closed, par, A), "decide launch");
+    HIPCK(launch_finish_decide(e->d_sds, e->d_states, d_steps, n_steps, e->dp, e->d_partials, consec_tiles,
+                               sparse_prev, sparse_next, e->d_cur, e->d_out_frames, kFramesCap, e->d_out_shots,
+                               kShotsCap, e->d_log, kLogCapPerStream, e->d_closed, par, A), "decide launch");
     prof(4, 1, A);
     prof(5, 1, A);
-    HIPCK(hipEventRecord(e->ev_a[par], A), "event");
+    HIPCK(hipEventRecord(e->ev_a[slot_s], A), "event");
     e->prof_step += 1;
     e->step_no += 1;
-    if (user) HIPCK(hipStreamWaitEvent(user, e->ev_a[par], 0), "wait");
+    if (user) HIPCK(hipStreamWaitEvent(user, e->ev_a[slot_s], 0), "wait");
     for (HostStream& s : e->streams)
         if (s.open && s.pending) { s.pending = false; s.next_frame += 1; }
     e->pushed_since_drain += step_push;
+    const uint64_t t_end = now_ns();
+    e->counters[10] += t_built - t_start;
+    e->counters[11] += t_upload - t_built;
+    e->counters[12] += t_end - t_upload;
+    e->counters[13] += t_end - t_start;
     e->counters[0] += 1;
     e->counters[7] += (uint64_t)n_consec;
     for (int i = 0; i < n_consec; ++i) e->counters[8] += (uint64_t)(consec[i].tiles >= 0 ? e->streams[consec[i].sid].sd.B_L : 0);
@@ -932,7 +961,7 @@ vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n) {
     e->counters[1] = (uint64_t)open;
     e->counters[4] = e->used;
     e->counters[5] = e->budget;
-    for (int32_t i = 0; i < n && i < 10; ++i) out[i] = e->counters[i];
+    for (int32_t i = 0; i < n && i < 14; ++i) out[i] = e->counters[i];
     return VSA_OK;
 }
 
@@ -1133,7 +1162,7 @@ vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, 
     if (kmax < 1 || kmax > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
     StreamDesc sd;
     std::memset(&sd, 0, sizeof sd);
-    sd.active = 1; sd.k_max = kmax; sd.rs = 2 * kmax + 5; sd.L = 0; sd.Lcap = kMaxLevels - 1;
+    sd.active = 1; sd.k_max = kmax; sd.rs = 2 * kmax + 4 + kAhead; sd.L = 0; sd.Lcap = kMaxLevels - 1;
     sd.ltop = kMaxLevels - 1; sd.nlev = kMaxLevels; sd.Lf = 0;
     for (int d = 0; d < kMaxLevels; ++d) { sd.wl[d] = 16; sd.hl[d] = 16; }
     sd.wf = 16; sd.hf = 16;

@@ -274,10 +274,11 @@ class Engine:
         return mv
 
     def counters(self) -> dict:
-        out = np.zeros(10, np.uint64)
-        _check(lib().vsa_engine_counters(self.h, _ptr(out), 10), "engine_counters")
+        out = np.zeros(14, np.uint64)
+        _check(lib().vsa_engine_counters(self.h, _ptr(out), 14), "engine_counters")
         keys = ("steps", "streams_open", "admitted", "refused", "bytes_in_use", "budget",
-                "sparse_tasks", "consecutive_tasks", "consecutive_blocks", "sparse_blocks")
+                "sparse_tasks", "consecutive_tasks", "consecutive_blocks", "sparse_blocks",
+                "host_ns_build", "host_ns_upload", "host_ns_launch", "host_ns_step")
         return {k: int(v) for k, v in zip(keys, out)}
 
     def measure_log(self, sid: int) -> np.ndarray:

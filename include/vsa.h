@@ -74,11 +74,11 @@ typedef struct {
     double rho_f, theta_f;/* fast check fires if ACT > rho_f * mean(history) + theta_f       */
     double theta_f0;      /* ... or, with no history in the shot yet, if ACT > theta_f0      */
     double rho_d, theta_d;/* deep check verifies K if F_K > rho_d * P_K + theta_d            */
-    double gamma;         /* dissolve length: first K with SWR_K >= gamma * max SWR          */
-    double tau_c;         /* combed: v0 > tau_c * min(v1, v2) (interlace vote) and
-                             v0 > tau_c * max(v1, v2) (pulldown cadence vote)                */
+    double gamma;         /* transition length: first K with F_K - P_K >= gamma * max of them  */
+    double tau_c;         /* interlace vote: frame combed if v0 > tau_c * min(v1, v2)         */
     double eps;           /* progressive if combed <= eps n, interlaced if >= (1 - eps) n     */
-    double pd_agree;      /* pulldown accepted if the cadence explains >= pd_agree n frames  */
+    double tau_p;         /* 3:2 pulldown if the mean v0 at two neighbouring positions of the
+                             5-frame unit exceeds tau_p times the mean at each other one     */
     double theta_kf;      /* keyframe when accumulated ACT exceeds theta_kf                  */
 } vsa_params;
 

@@ -42,7 +42,7 @@ class Params(C.Structure):
         ("w_hist", C.c_int32), ("n_ss", C.c_int32),
         ("a0", C.c_double), ("rho_f", C.c_double), ("theta_f", C.c_double), ("theta_f0", C.c_double),
         ("rho_d", C.c_double), ("theta_d", C.c_double), ("gamma", C.c_double),
-        ("tau_c", C.c_double), ("eps", C.c_double), ("pd_agree", C.c_double),
+        ("tau_c", C.c_double), ("eps", C.c_double), ("tau_p", C.c_double),
         ("theta_kf", C.c_double),
     ]
 
@@ -126,7 +126,8 @@ def downscale(plane):
 
 
 def levels(Y, params, bits=8):
-    """Frame levels L..Lcap and the two fields at Lf, as a dict of uint16 planes."""
+    """Frame levels L..Lcap, the two fields at Lf and the lower field on the
+    upper field's rows ("Dc", what field pairs read), as a dict of uint16 planes."""
     Y = np.ascontiguousarray(Y)
     H, W = Y.shape
     g = geometry(W, H, params)
@@ -146,6 +147,8 @@ def levels(Y, params, bits=8):
     res[("U", g["Lf"])] = out[k:k + wf * hf].reshape(hf, wf)
     k += wf * hf
     res[("D", g["Lf"])] = out[k:k + wf * hf].reshape(hf, wf)
+    k += wf * hf
+    res[("Dc", g["Lf"])] = out[k:k + wf * hf].reshape(hf, wf)
     return res
 
 

@@ -110,9 +110,32 @@ Plane field_of(const Plane& f, int parity) {
     return o;
 }
 
+// The lower field resampled to the rows of the upper field.  At field level
+// Lf both fields have a row pitch of p = 2^(Lf+1) full-resolution rows and
+// the lower field's rows sit one full-resolution row below the upper field's,
+// so the value at upper-field row y lies 1/p of the way from D[y] to D[y-1]:
+// ((p-1) D[y] + D[y-1] + p/2) / p, rounded down, D[-1] read as D[0].  Field
+// pairs compare the upper field with this plane: an integer motion field can
+// not absorb the sub-row offset between the two fields, which would otherwise
+// make v0 of progressive content as large as an inter-frame activity
+// (Sec. III.C expects it near zero).
+Plane cosite_lower(const Plane& D, int Lf) {
+    const int s = Lf + 1, p = 1 << s;
+    Plane o;
+    o.w = D.w; o.h = D.h;
+    o.px.resize(D.px.size());
+    for (int y = 0; y < D.h; ++y)
+        for (int x = 0; x < D.w; ++x) {
+            const int32_t a = D.at(x, y), b = D.at(x, y > 0 ? y - 1 : 0);
+            o.px[(size_t)y * o.w + x] = ((p - 1) * a + b + p / 2) >> s;
+        }
+    return o;
+}
+
 struct FrameLevels {
     std::vector<Plane> lv;   // levels L..Lcap
     Plane U, D;              // fields at Lf
+    Plane Dc;                // D on the rows of U (what field pairs read)
 };
 
 void build_levels(const Plane& full, const Geometry& g, FrameLevels& fl) {
@@ -126,6 +149,7 @@ void build_levels(const Plane& full, const Geometry& g, FrameLevels& fl) {
     fl.U = field_of(full, 0);
     fl.D = field_of(full, 1);
     for (int l = 1; l <= g.Lf; ++l) { fl.U = downscale(fl.U); fl.D = downscale(fl.D); }
+    fl.Dc = cosite_lower(fl.D, g.Lf);
 }
 
 // Candidate order for ties: by squared length, then dy, then dx.
@@ -261,44 +285,46 @@ struct Provider {
 struct Analysis {
     bool open = true;
     int n = 0, nci = 0, s = 0, result = 0, phase = -1;
-    int cm[5] = {0, 0, 0, 0, 0}, np[5] = {0, 0, 0, 0, 0};
+    int np[5] = {0, 0, 0, 0, 0};
+    double s0[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double sum1 = 0.0, sum2 = 0.0;
 
-    // Two readings of "v0 is not near zero" (Sec. III.C):
-    //  - against the smaller inter-frame field activity: the interlace test.
-    //    In interlaced content v0 and one of v1/v2 span half a frame interval,
-    //    so v0 is comparable to min(v1, v2) even when the other pair moves
-    //    too far for the search range; in progressive content both v1 and v2
-    //    span a full interval and v0 none.
-    //  - against the larger one: the 3:2 pulldown cadence.  Inside a pulldown
-    //    unit one of v1/v2 can itself join two fields of the same film frame,
-    //    so only the larger one is a reliable scale; the frames whose two
-    //    fields come from different film frames are then the combed ones.
+    // Interlace vote, one reading of "v0 is not near zero" (Sec. III.C): v0
+    // against the smaller inter-frame field activity.  In interlaced content
+    // v0 and one of v1/v2 span half a frame interval, so v0 is comparable to
+    // min(v1, v2) even when the other pair moves too far for the search
+    // range; in progressive content v1 and v2 span a full interval and v0
+    // none.  For the 3:2 pulldown cadence v0 is summed per position of the
+    // 5-frame pulldown unit (phase = frame index in the shot mod 5).
     void add(int ph, double v0, double v1, double v2, const orc_params& p) {
         const bool comb_min = v0 > p.tau_c * std::min(v1, v2);
-        const bool comb_max = v0 > p.tau_c * std::max(v1, v2);
         ++n; ++np[ph];
         if (comb_min) ++nci;
-        if (comb_max) ++cm[ph];
+        s0[ph] = s0[ph] + v0;
         if (v1 > v2) ++s; else if (v1 < v2) --s;
         sum1 = sum1 + v1; sum2 = sum2 + v2;
+    }
+    // Mean v0 at position a exceeds tau_p times the mean at position r
+    // (cross-multiplied, so no division is rounded).
+    bool dominates(int a, int r, const orc_params& p) const {
+        return s0[a] * (double)np[r] > p.tau_p * (s0[r] * (double)np[a]);
     }
     void decide(const orc_params& p) {
         open = false;
         phase = -1;
         if (n == 0) { result = 0; return; }
-        if (n >= 10) {
-            // 3:2 pulldown: the combed frames sit at two neighbouring positions
-            // of the 5-frame pulldown unit.
-            int mask = 0, cnt = 0;
-            for (int q = 0; q < 5; ++q) if (2 * cm[q] > np[q]) { mask |= 1 << q; ++cnt; }
-            if (cnt == 2) {
-                for (int q = 0; q < 5; ++q) {
-                    if (mask != ((1 << q) | (1 << ((q + 1) % 5)))) continue;
-                    int agree = 0;
-                    for (int r = 0; r < 5; ++r) agree += ((mask >> r) & 1) ? cm[r] : np[r] - cm[r];
-                    if ((double)agree >= p.pd_agree * (double)n) { result = 4; phase = q; return; }
-                }
+        if (n >= 10 && np[0] && np[1] && np[2] && np[3] && np[4]) {
+            // 3:2 pulldown: the frames whose two fields come from different
+            // film frames (the combed ones) sit at two neighbouring positions
+            // q, q+1 of the unit; their mean v0 exceeds tau_p times the mean
+            // at each of the other three positions.  With tau_p >= 1 at most
+            // one q qualifies.
+            for (int q = 0; q < 5; ++q) {
+                const int a = q, b = (q + 1) % 5;
+                bool ok = true;
+                for (int r = 0; r < 5 && ok; ++r)
+                    if (r != a && r != b) ok = dominates(a, r, p) && dominates(b, r, p);
+                if (ok) { result = 4; phase = q; return; }
             }
         }
         bool inter;
@@ -316,8 +342,11 @@ struct Analysis {
 // Deep check at frame t (Sec. III.B): a K-frame transition after t is accepted
 // when the activity from t to t+K clearly exceeds the activity from t back to
 // its predecessor at the same distance; K and K+1 must both verify (a single
-// odd frame such as a flash verifies only one); among the candidates the
-// first whose dissimilarity reaches gamma of the largest one is taken.
+// odd frame such as a flash verifies only one).  Among the candidates the
+// first whose excess activity E_K = ACT(t, t+K) - ACT(t, t-K) reaches gamma
+// of the largest one is taken: both activities are measured at the same
+// distance and pyramid level, so E_K stops growing once t+K lies in the new
+// shot, where a plain dissimilarity keeps growing with K.
 bool deep_check(int t, int T, int shot_start, double a_t, double s_t, Provider& pv,
                 const orc_params& p, int& Kstar) {
     Kstar = 0;
@@ -332,7 +361,7 @@ bool deep_check(int t, int T, int shot_start, double a_t, double s_t, Provider& 
         double pa = 0.0;
         if (Kp > 0) { Meas b; if (!pv.deepP(t, K, Kp, b)) return false; pa = b.act; }
         V[K] = f.act > p.rho_d * pa + p.theta_d;
-        S[K] = f.swr;
+        S[K] = f.act - pa;
     }
     const int Kc = std::min(p.k_max, Kn);
     bool any = false;
@@ -404,14 +433,15 @@ int run_pass(int T, Provider& pv, const orc_params& p, bool dense,
             }
         }
         // Fast check against the recent activity of the current shot.
-        bool fire;
-        if (hist.empty()) fire = a > p.theta_f0;   // no history yet: absolute threshold
+        double thr;
+        if (hist.empty()) thr = p.theta_f0;       // no history yet: absolute threshold
         else {
             double s = 0.0;
             for (double x : hist) s = s + x;
             const double mean = s / (double)hist.size();
-            fire = a > p.rho_f * mean + p.theta_f;
+            thr = p.rho_f * mean + p.theta_f;
         }
+        const bool fire = a > thr;
         if (fire) r.flags |= ORC_F_FAST_FIRED;
         int Kstar = 0;
         if (fire || dense) {
@@ -441,7 +471,9 @@ int run_pass(int T, Provider& pv, const orc_params& p, bool dense,
             t = b;
             continue;
         }
-        hist.push_back(a);
+        // The history takes the activity capped at the threshold, so that a
+        // flash or other one-off spike does not mask what follows it.
+        hist.push_back(fire ? thr : a);
         if ((int)hist.size() > p.w_hist) hist.pop_front();
         // Dynamic keyframes: accumulate consecutive-frame activity within the shot.
         acc = acc + a;
@@ -492,7 +524,7 @@ struct FrameProvider : Provider {
     }
     const Plane& plane(const FrameLevels& fl, int field, int level) {
         if (field == 1) return fl.U;
-        if (field == 2) return fl.D;
+        if (field == 2) return fl.Dc;
         return fl.lv[(size_t)(level - g.L)];
     }
     bool measure(int kind, int ref, int rf, int oth, int of, int level, Meas& m, PairOut* keep) {
@@ -578,7 +610,7 @@ struct InjectedProvider : Provider {
 
 bool params_ok(const orc_params* p) {
     return p && p->block == 8 && p->radius >= 0 && p->radius <= 16 && p->k_max >= 1 &&
-           p->k_max <= 64 && p->w_hist >= 1 && p->n_ss >= 1 && p->lf_offset >= 0;
+           p->k_max <= 64 && p->w_hist >= 1 && p->n_ss >= 1 && p->lf_offset >= 0 && p->tau_p >= 1.0;
 }
 
 int export_results(const std::vector<orc_frame_rec>& recs, const std::vector<orc_shot_rec>& shots,
@@ -638,7 +670,7 @@ int32_t orc_levels(const void* Y, int32_t W, int32_t H, int64_t pitch_bytes, int
     build_levels(full, g, fl);
     int64_t n = 0;
     for (const Plane& q : fl.lv) n += (int64_t)q.px.size();
-    n += (int64_t)fl.U.px.size() + (int64_t)fl.D.px.size();
+    n += (int64_t)fl.U.px.size() + (int64_t)fl.D.px.size() + (int64_t)fl.Dc.px.size();
     if (n_out) *n_out = n;
     if (!out) return 0;
     if (cap < n) return -3;
@@ -647,6 +679,7 @@ int32_t orc_levels(const void* Y, int32_t W, int32_t H, int64_t pitch_bytes, int
     for (const Plane& q : fl.lv) put(q);
     put(fl.U);
     put(fl.D);
+    put(fl.Dc);
     return 0;
 }
 

@@ -39,7 +39,7 @@ typedef struct {
     double tau_c;         /* comb tests: v0 > tau_c * min(v1, v2) (interlace) and
                              v0 > tau_c * max(v1, v2) (pulldown cadence)      */
     double eps;           /* class fraction margin                             */
-    double pd_agree;      /* pulldown agreement fraction                       */
+    double tau_p;         /* pulldown: combed positions' mean v0 ratio          */
     double theta_kf;      /* keyframe threshold on accumulated ACT             */
 } orc_params;
 
@@ -86,9 +86,10 @@ int32_t orc_geometry(int32_t W, int32_t H, const orc_params* p, int32_t* out, in
 /* One 2x2 rounding downscale step of a w x h plane (uint16 samples). */
 int32_t orc_downscale(const uint16_t* src, int32_t w, int32_t h, uint16_t* dst);
 
-/* All levels of one frame, as uint16: frame levels L..Lcap, then U_Lf, D_Lf,
- * concatenated, each densely packed (pitch = width). Returns the number of
- * samples written in *n_out. */
+/* All levels of one frame, as uint16: frame levels L..Lcap, then U_Lf, D_Lf
+ * and the lower field resampled to the upper field's rows (the plane field
+ * pairs read), concatenated, each densely packed (pitch = width). Returns the
+ * number of samples written in *n_out. */
 int32_t orc_levels(const void* Y, int32_t W, int32_t H, int64_t pitch_bytes, int32_t bits,
                    const orc_params* p, uint16_t* out, int64_t cap, int64_t* n_out);
 

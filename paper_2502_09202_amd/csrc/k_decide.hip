@@ -49,27 +49,23 @@ __device__ __forceinline__ FrameInfo& info_of(const StreamDesc& sd, int f) { ret
 
 __device__ __forceinline__ void ss_reset(Analysis& a) {
     a.open = 1; a.n = 0; a.nci = 0; a.s = 0; a.result = 0; a.phase = -1;
-    for (int i = 0; i < 5; ++i) { a.cm[i] = 0; a.np[i] = 0; }
+    for (int i = 0; i < 5; ++i) { a.np[i] = 0; a.s0[i] = 0.0; }
     a.sum1 = 0.0; a.sum2 = 0.0;
 }
 
-// Two comb votes per analysed frame: v0 against the smaller of v1, v2 (the
-// interlace vote: half a frame interval separates v0's fields and one of the
-// inter-frame field pairs) and against the larger one (the pulldown cadence
-// vote: within a pulldown unit one inter-frame field pair may join two fields
-// of the same film frame).
+// Per analysed frame: the interlace vote (v0 against the smaller of v1, v2:
+// half a frame interval separates v0's fields and one of the inter-frame field
+// pairs) and v0 summed per position of the 5-frame pulldown unit.
 __device__ __forceinline__ void ss_add(Analysis& a, int ph, double v0, double v1, double v2,
                                        const DecideParams& dp) {
     const double mn = v1 < v2 ? v1 : v2;
-    const double mx = v1 > v2 ? v1 : v2;
     const bool comb_min = v0 > dp.tau_c * mn;
-    const bool comb_max = v0 > dp.tau_c * mx;
     a.n += 1;
 #pragma unroll
     for (int q = 0; q < 5; ++q)
         if (q == ph) {
             a.np[q] += 1;
-            if (comb_max) a.cm[q] += 1;
+            a.s0[q] = a.s0[q] + v0;
         }
     if (comb_min) a.nci += 1;
     if (v1 > v2) a.s += 1; else if (v1 < v2) a.s -= 1;
@@ -81,20 +77,21 @@ __device__ __forceinline__ void ss_decide(Analysis& a, const DecideParams& dp) {
     a.open = 0;
     a.phase = -1;
     if (a.n == 0) { a.result = VSA_SAMPLING_UNDETERMINED; return; }
-    if (a.n >= 10) {
-        int mask = 0, cnt = 0;
-        for (int q = 0; q < 5; ++q)
-            if (2 * a.cm[q] > a.np[q]) { mask |= 1 << q; ++cnt; }
-        if (cnt == 2) {
-            for (int q = 0; q < 5; ++q) {
-                if (mask != ((1 << q) | (1 << ((q + 1) % 5)))) continue;
-                int agree = 0;
-                for (int r = 0; r < 5; ++r) agree += ((mask >> r) & 1) ? a.cm[r] : a.np[r] - a.cm[r];
-                if ((double)agree >= dp.pd_agree * (double)a.n) {
-                    a.result = VSA_SAMPLING_PULLDOWN32;
-                    a.phase = q;
-                    return;
-                }
+    if (a.n >= 10 && a.np[0] && a.np[1] && a.np[2] && a.np[3] && a.np[4]) {
+        // 3:2 pulldown: mean v0 at positions q, q+1 above tau_p times the mean
+        // at each other position (cross-multiplied; at most one q qualifies)
+        for (int q = 0; q < 5; ++q) {
+            const int b = q == 4 ? 0 : q + 1;
+            bool ok = true;
+            for (int r = 0; r < 5; ++r) {
+                if (r == q || r == b) continue;
+                const double rq = a.s0[r] * (double)a.np[q], rb = a.s0[r] * (double)a.np[b];
+                ok = ok && (a.s0[q] * (double)a.np[r] > dp.tau_p * rq) && (a.s0[b] * (double)a.np[r] > dp.tau_p * rb);
+            }
+            if (ok) {
+                a.result = VSA_SAMPLING_PULLDOWN32;
+                a.phase = q;
+                return;
             }
         }
     }
@@ -108,14 +105,20 @@ __device__ __forceinline__ void ss_decide(Analysis& a, const DecideParams& dp) {
     else a.result = (a.sum1 >= a.sum2) ? VSA_SAMPLING_TFF : VSA_SAMPLING_BFF;
 }
 
-__device__ __forceinline__ bool fast_check(const DecideState& st, double a, const DecideParams& dp) {
-    if (st.hist_len == 0) return a > dp.theta_f0;   // no history in the shot yet
+// Fast-check threshold from the recent activity of the shot (W_hist values,
+// each capped at the threshold in force when it was pushed).
+__device__ __forceinline__ double fast_thr(const DecideState& st, const DecideParams& dp) {
+    if (st.hist_len == 0) return dp.theta_f0;       // no history in the shot yet
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxHist; ++i)              // oldest to newest
         if (i >= kMaxHist - st.hist_len) s = s + st.hist[i];
     const double mean = s / (double)st.hist_len;
-    return a > dp.rho_f * mean + dp.theta_f;
+    return dp.rho_f * mean + dp.theta_f;
+}
+
+__device__ __forceinline__ bool fast_check(const DecideState& st, double a, const DecideParams& dp) {
+    return a > fast_thr(st, dp);
 }
 
 __device__ __forceinline__ void hist_push(DecideState& st, double a, const DecideParams& dp) {
@@ -142,19 +145,21 @@ __device__ __forceinline__ void close_shot(DecideState& st, vsa_shot_result* clo
     r.final_ = 1;
 }
 
-// Deep check of iteration t from the requested results (Sec. III.B).
+// Deep check of iteration t from the requested results (Sec. III.B): K verifies
+// when ACT(t, t+K) > rho_d * ACT(t, t-K) + theta_d; among the K with K and K+1
+// verified, the first whose excess ACT(t, t+K) - ACT(t, t-K) reaches gamma of
+// the largest excess is taken.
 __device__ int deep_check(const StreamDesc& sd, const DecideState& st, int t, int Kn, double a_t,
-                          double s_t, const PairResult* res, const DecideParams& dp) {
+                          const PairResult* res, const DecideParams& dp) {
     bool V[kMaxKmax + 3];
     double S[kMaxKmax + 3];
     for (int K = 0; K < kMaxKmax + 3; ++K) { V[K] = true; S[K] = 0.0; }
     for (int K = 1; K <= Kn; ++K) {
         const double f = K == 1 ? a_t : res[kResF + K].act;
-        const double sw = K == 1 ? s_t : res[kResF + K].swr;
         const int kp = min(K, t - st.shot_start);
         const double p = kp > 0 ? res[kResP + p_rep(sd, K, t - st.shot_start)].act : 0.0;
         V[K] = f > dp.rho_d * p + dp.theta_d;
-        S[K] = sw;
+        S[K] = f - p;
     }
     const int Kc = min(sd.k_max, Kn);
     bool any = false;
@@ -187,7 +192,7 @@ __device__ void commit(const StreamDesc& sd, DecideState& st, vsa_shot_result* c
     if (fire) fi.flags |= VSA_F_FAST_FIRED;
     int Kstar = 0;
     if (need_deep) {
-        Kstar = deep_check(sd, st, t, Kn, a, fi.swr, res, dp);
+        Kstar = deep_check(sd, st, t, Kn, a, res, dp);
         if (!fire) Kstar = 0;
     }
     if (Kstar > 0) {
@@ -214,7 +219,7 @@ __device__ void commit(const StreamDesc& sd, DecideState& st, vsa_shot_result* c
         return;
     }
     fi.shot_id = st.shot_id;
-    hist_push(st, a, dp);
+    hist_push(st, fire ? fast_thr(st, dp) : a, dp);
     st.acc = st.acc + a;
     if (st.acc > dp.theta_kf) {
         info_of(sd, t + 1).flags |= VSA_F_KEYFRAME;

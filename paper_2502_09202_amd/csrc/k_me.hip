@@ -42,6 +42,7 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 struct PlaneRef {
     const uint8_t* base;
     int w, h, pitch;   // pitch in samples
+    int cosite;        // 0, or s = Lf + 1: read the lower field on the upper field's rows
 };
 
 __device__ __forceinline__ PlaneRef plane_of(const StreamDesc& sd, int frame, int field, int level) {
@@ -50,10 +51,12 @@ __device__ __forceinline__ PlaneRef plane_of(const StreamDesc& sd, int frame, in
     if (field == PL_UPPER || field == PL_LOWER) {
         p.base = slot + (field == PL_UPPER ? sd.offU : sd.offD);
         p.w = sd.wf; p.h = sd.hf; p.pitch = sd.pf;
+        p.cosite = field == PL_LOWER ? sd.Lf + 1 : 0;
     } else {
         const int d = level - sd.L;
         p.base = slot + sd.off[d];
         p.w = sd.wl[d]; p.h = sd.hl[d]; p.pitch = sd.pl[d];
+        p.cosite = 0;
     }
     return p;
 }
@@ -67,6 +70,25 @@ __device__ __forceinline__ int amm_fx(int m) {
     return r;
 }
 
+// The lower field on the upper field's rows.  Both fields have a row pitch of
+// p = 2^s full-resolution rows (s = Lf + 1) and the lower field lies one
+// full-resolution row lower, so row y of the resampled plane is
+// ((p-1) D[y] + D[y-1] + p/2) >> s, with D[-1] read as D[0].  Field pairs read
+// the lower field only through this (an integer motion field cannot absorb
+// the sub-row offset between the fields).
+template <typename T, typename V>
+__device__ __forceinline__ V cosite_vec(V a, V b, int s) {
+    constexpr int N = (int)(sizeof(V) / sizeof(T));
+    union U { V v; T t[N]; };
+    U ua, ub, uo;
+    ua.v = a;
+    ub.v = b;
+    const int p = 1 << s;
+#pragma unroll
+    for (int k = 0; k < N; ++k) uo.t[k] = (T)(((p - 1) * (int)ua.t[k] + (int)ub.t[k] + (p >> 1)) >> s);
+    return uo.v;
+}
+
 template <typename T>
 __device__ __forceinline__ void stage_I(const PlaneRef& P, int bx0, int by0, uint8_t* sI) {
     // I tile: 64 rows x 64 samples.  The tile origin is a multiple of 64
@@ -78,7 +100,13 @@ __device__ __forceinline__ void stage_I(const PlaneRef& P, int bx0, int by0, uin
         const int r = i / CH, c = i % CH;
         const int gy = clampi(8 * by0 + r, 0, P.h - 1);
         const uint4* src = reinterpret_cast<const uint4*>(P.base + ((int64_t)gy * P.pitch + 8 * bx0) * B) + c;
-        reinterpret_cast<uint4*>(sI + r * 64 * B)[c] = *src;
+        uint4 v = *src;
+        if (P.cosite) {
+            const int gp = gy > 0 ? gy - 1 : 0;
+            const uint4* prv = reinterpret_cast<const uint4*>(P.base + ((int64_t)gp * P.pitch + 8 * bx0) * B) + c;
+            v = cosite_vec<T, uint4>(v, *prv, P.cosite);
+        }
+        reinterpret_cast<uint4*>(sI + r * 64 * B)[c] = v;
     }
 }
 
@@ -93,15 +121,22 @@ __device__ __forceinline__ void stage_J(const PlaneRef& P, int bx0, int by0, uin
         const int gy = clampi(8 * by0 - 8 + r, 0, P.h - 1);
         const int gx = x0 + c * (8 / B);
         const T* row = reinterpret_cast<const T*>(P.base + (int64_t)gy * P.pitch * B);
-        uint2 v;
+        const T* prv = reinterpret_cast<const T*>(P.base + (int64_t)(gy > 0 ? gy - 1 : 0) * P.pitch * B);
+        uint2 v, w = make_uint2(0u, 0u);
         if (gx >= 0 && gx + 8 / B <= P.w) {
             v = *reinterpret_cast<const uint2*>(row + gx);
+            if (P.cosite) w = *reinterpret_cast<const uint2*>(prv + gx);
         } else {
-            union { T t[8 / B]; uint2 u; } tmp;
+            union { T t[8 / B]; uint2 u; } tmp, tmq;
 #pragma unroll
-            for (int k = 0; k < 8 / B; ++k) tmp.t[k] = row[clampi(gx + k, 0, P.w - 1)];
+            for (int k = 0; k < 8 / B; ++k) {
+                tmp.t[k] = row[clampi(gx + k, 0, P.w - 1)];
+                tmq.t[k] = P.cosite ? prv[clampi(gx + k, 0, P.w - 1)] : (T)0;
+            }
             v = tmp.u;
+            w = tmq.u;
         }
+        if (P.cosite) v = cosite_vec<T, uint2>(v, w, P.cosite);
         *reinterpret_cast<uint2*>(sJ + r * kJW8 * B + c * 8) = v;
     }
 }

@@ -90,7 +90,8 @@ constexpr int kResSlots = kResP + kMaxKmax + 2;
 // Sampling-structure analysis of the open shot.
 struct Analysis {
     int32_t open, n, nci, s, result, phase;
-    int32_t cm[5], np[5];       // per phase of the 5-frame unit
+    int32_t np[5], pad;         // analysed frames per position of the 5-frame unit
+    double s0[5];               // sum of v0 per position
     double sum1, sum2;
 };
 
@@ -122,7 +123,7 @@ constexpr int kMaxClosed = 4;
 // Engine-wide constants for the decision kernel.
 struct DecideParams {
     int32_t w_hist, n_ss, dense, a_static_fx;
-    double a0, rho_f, theta_f, theta_f0, rho_d, theta_d, gamma, tau_c, eps, pd_agree, theta_kf;
+    double a0, rho_f, theta_f, theta_f0, rho_d, theta_d, gamma, tau_c, eps, tau_p, theta_kf;
 };
 
 // Per-step view of one stream (host -> device each step).

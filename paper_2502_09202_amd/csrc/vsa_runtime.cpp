@@ -142,6 +142,7 @@ vsa_status check_params(const vsa_params& p) {
     if (p.k_max < 1 || p.k_max > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
     if (p.w_hist < 1 || p.w_hist > kMaxHist) return fail(VSA_E_INVAL, "w_hist must be in 1..16");
     if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
+    if (!(p.tau_p >= 1.0)) return fail(VSA_E_INVAL, "tau_p must be >= 1");
     return VSA_OK;
 }
 
@@ -149,7 +150,7 @@ DecideParams decide_params(const vsa_params& p, int dense) {
     DecideParams d;
     d.w_hist = p.w_hist; d.n_ss = p.n_ss; d.dense = dense; d.a_static_fx = p.a_static_fx;
     d.a0 = p.a0; d.rho_f = p.rho_f; d.theta_f = p.theta_f; d.theta_f0 = p.theta_f0; d.rho_d = p.rho_d; d.theta_d = p.theta_d;
-    d.gamma = p.gamma; d.tau_c = p.tau_c; d.eps = p.eps; d.pd_agree = p.pd_agree; d.theta_kf = p.theta_kf;
+    d.gamma = p.gamma; d.tau_c = p.tau_c; d.eps = p.eps; d.tau_p = p.tau_p; d.theta_kf = p.theta_kf;
     return d;
 }
 
@@ -402,8 +403,8 @@ void vsa_default_params(vsa_params* p) {
     if (!p) return;
     p->block = 8; p->radius = 8; p->wmax = 512; p->lf_offset = 1; p->k_max = 4;
     p->a_static_fx = 64; p->w_hist = 8; p->n_ss = 20;
-    p->a0 = 1.0; p->rho_f = 2.0; p->theta_f = 0.10; p->theta_f0 = 1.0; p->rho_d = 3.0; p->theta_d = 0.20;
-    p->gamma = 0.90; p->tau_c = 0.5; p->eps = 0.2; p->pd_agree = 0.8; p->theta_kf = 3.0;
+    p->a0 = 1.0; p->rho_f = 1.5; p->theta_f = 0.05; p->theta_f0 = 1.0; p->rho_d = 1.3; p->theta_d = 0.4;
+    p->gamma = 0.5; p->tau_c = 0.65; p->eps = 0.2; p->tau_p = 2.0; p->theta_kf = 3.0;
 }
 
 vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {

@@ -40,7 +40,7 @@ class Params(C.Structure):
         ("w_hist", C.c_int32), ("n_ss", C.c_int32),
         ("a0", C.c_double), ("rho_f", C.c_double), ("theta_f", C.c_double), ("theta_f0", C.c_double),
         ("rho_d", C.c_double), ("theta_d", C.c_double), ("gamma", C.c_double),
-        ("tau_c", C.c_double), ("eps", C.c_double), ("pd_agree", C.c_double),
+        ("tau_c", C.c_double), ("eps", C.c_double), ("tau_p", C.c_double),
         ("theta_kf", C.c_double),
     ]
 

@@ -42,6 +42,7 @@ def test_keyframe_spacing_closed_form(orc, params):
 
 
 def test_hardcut(orc, params):
+    # every K verifies with the same excess: the first (K = 1) is taken
     T, c = 80, 30
     s = seq(T, 4)
     s["act"][c] = 2.0
@@ -75,19 +76,29 @@ def test_one_frame_flash_is_not_a_boundary(orc, params):
 
 
 def test_dissolve_plateau(orc, params):
+    # A 3-frame dissolve after t while the shot drifts: the backward activity
+    # P_K grows with the distance K, and so does the forward activity F_K
+    # past the end of the transition.  The excess E_K = F_K - P_K climbs over
+    # the transition and then stays flat; the plain dissimilarity S_K keeps
+    # growing, so a plateau on S would pick K = 4.
     T, t = 90, 50
     s = seq(T, 4, a=0.2)
-    s["act"][t] = 0.8
-    s["F"][t, 2:6] = [0.8, 1.2, 1.6, 2.0]     # K = 2..5
-    s["S"][t, 2:6] = [0.4, 0.6, 0.8, 0.8]
-    s["P"][t, :] = 0.2
-    r = run(orc, params, s)
+    s["act"][t] = 0.6
+    s["F"][t, 1:6] = [0.6, 1.4, 2.2, 2.4, 2.6]          # K = 1..5
+    s["P"][t, 1:6] = [0.2, 0.4, 0.6, 0.8, 1.0]
+    s["S"][t, 1:6] = [0.1, 0.2, 0.4, 0.8, 0.9]
+    s["swr"][t] = 0.1
+    r = run(orc, params, s, rho_d=1.5, theta_d=0.4, gamma=0.8)
     f = r["frames"]
-    # V_1 (0.8 > 0.8) and V_2 (0.8 > 0.8) fail; 3, 4, 5 verify; first S >= 0.9 max -> K = 4
-    assert f["boundary"][t + 4] == 2 and f["boundary_k"][t + 4] == 4
-    assert np.all(f["flags"][t + 1:t + 4] & F_TRANS)
-    assert np.all(f["shot_id"][t + 1:t + 4] == -1)
-    assert r["shots"][1]["first"] == t + 4 and r["shots"][0]["last"] == t
+    # V_1: 0.6 > 0.7 fails; V_2..V_5 hold, so C = {2, 3, 4}; E = 1.0, 1.6, 1.6;
+    # the first E >= 0.8 * 1.6 is K = 3
+    assert f["boundary"][t + 3] == 2 and f["boundary_k"][t + 3] == 3
+    assert np.all(f["flags"][t + 1:t + 3] & F_TRANS)
+    assert np.all(f["shot_id"][t + 1:t + 3] == -1)
+    assert r["shots"][1]["first"] == t + 3 and r["shots"][0]["last"] == t
+    # gamma = 0 takes the shortest verified transition
+    r0 = run(orc, params, s, rho_d=1.5, theta_d=0.4, gamma=0.0)
+    assert r0["frames"]["boundary_k"][t + 2] == 2
 
 
 def _sampling(orc, params, v_of_phase, T=40, **kw):

@@ -117,3 +117,44 @@ def test_too_small_rejected(orc, params):
         orc.geometry(15, 100, params)
     with pytest.raises(ValueError):
         orc.geometry(100, 15, params)
+
+
+def test_cosited_lower_field_on_vertical_ramp_lf0(orc, params):
+    # 320x180: Lf = 0, fields are rows 2y (U) and 2y+1 (D).  On a vertical ramp
+    # Y[r] = r the lower field halfway between rows 2y-1 and 2y+1 is row 2y,
+    # i.e. the upper field itself (row 0 reads D[-1] as D[0]).
+    Y = np.repeat(np.arange(180, dtype=np.uint8)[:, None], 320, axis=1)
+    lv = orc.levels(Y, params)
+    U, D, Dc = lv[("U", 0)], lv[("D", 0)], lv[("Dc", 0)]
+    assert np.all(U[:, 0] == 2 * np.arange(90)) and np.all(D[:, 0] == 2 * np.arange(90) + 1)
+    assert np.array_equal(Dc[1:], U[1:])
+    assert np.array_equal(Dc[0], D[0])
+
+
+def test_cosited_lower_field_on_vertical_ramp_lf1(orc, params):
+    # 1280x720 10-bit: L = 2, Lf = 1.  U_1[y] averages rows 4y, 4y+2 (centre
+    # 4y+1), D_1[y] rows 4y+1, 4y+3 (centre 4y+2); on Y[r] = r the lower field
+    # moved up by one full-resolution row is again the upper field:
+    # (3 (4y+2) + (4y-2) + 2) >> 2 = 4y+1.
+    Y = np.repeat(np.arange(720, dtype=np.uint16)[:, None], 1280, axis=1)
+    lv = orc.levels(Y, params, bits=10)
+    U, D, Dc = lv[("U", 1)], lv[("D", 1)], lv[("Dc", 1)]
+    y = np.arange(180)
+    assert np.all(U[:, 5] == 4 * y + 1) and np.all(D[:, 5] == 4 * y + 2)
+    assert np.array_equal(Dc[1:], U[1:])
+
+
+def test_cosited_lower_field_weights(orc, params):
+    # Row y of the resampled plane lies 1/p of a field row above D[y]
+    # (p = 2^(Lf+1) full-resolution rows per field row), rounded half up;
+    # checked at sampled points on random frames at Lf = 0, 1, 2.
+    rng = np.random.default_rng(11)
+    for W, H, bits, Lf in ((320, 180, 8, 0), (2048, 1080, 8, 1), (3840, 2160, 10, 2)):
+        Y = rng.integers(0, (1 << bits), size=(H, W)).astype(np.uint8 if bits == 8 else np.uint16)
+        lv = orc.levels(Y, params, bits=bits)
+        D = lv[("D", Lf)].astype(np.int64)
+        Dc = lv[("Dc", Lf)].astype(np.int64)
+        p = 2 << Lf
+        for (yy, xx) in [(0, 0), (1, 3), (50, 100), (D.shape[0] - 1, D.shape[1] - 1)]:
+            prev = D[max(yy - 1, 0), xx]
+            assert Dc[yy, xx] == ((p - 1) * D[yy, xx] + prev + p // 2) // p

@@ -19,6 +19,7 @@ Printed JSON also carries:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
@@ -35,6 +36,40 @@ HBM_PEAK_GBS = 8000.0
 # differences into one full-rate lane-op (v_qsad_pk_u16_u8: 16 at quarter rate)
 AD_PEAK_T = 256 * 64 * 2.4e9 * 4 / 1e12
 RT_FPS = 25.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pyramid_2k_b64_traffic.txt")
+K1_SOURCE = os.path.join(ROOT, "paper_2502_09202_amd", "csrc", "k_pyramid.hip")
+
+
+def k1_traffic(streams):
+    """HBM bytes per pyramid launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the copy-kernel factor),
+    or None if the kernel source has changed since the counters were taken or
+    they were taken at another batch size."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(K1_SOURCE, "rb").read()).hexdigest()
+        if kv.get("k_pyramid.hip sha256") != sha or int(kv.get("streams", -1)) != streams:
+            return None
+        return float(kv["hbm bytes per launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_only(nbytes, reps):
+    """A plain device copy of known size: the calibration run for the HBM byte
+    counters (FETCH_SIZE / WRITE_SIZE of one dispatch vs nbytes)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
 
 
 def _render_range(args):
@@ -146,12 +181,20 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-stream comparison run")
+    ap.add_argument("--no-diag", action="store_true", help="skip the all-kernel timing run")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); streams shard across "
               "GPUs with no exchange, so run one process per GPU", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_only:
+        copy_only(args.copy_only, 5)
+        return
 
     import torch
     import oracle  # noqa: F401  (cpu baseline only)
@@ -171,11 +214,15 @@ def main():
     fps = args.streams * args.steps / dt
     print(f"[bench] batched B={args.streams}: {fps:.0f} frames/s, {1e3 * dt / args.steps:.3f} ms/step, "
           f"{nout} records", file=sys.stderr, flush=True)
-    pdt, _, _, _, _ = run_engine(vsa, dev, params, 1, args.plain_steps, 20, 0, torch)
-    plain_fps = args.plain_steps / pdt
-    # untimed diagnostic: every kernel timed, for the per-kernel breakdown
-    _, kt_all, _, _, _ = run_engine(vsa, dev, params, args.streams, min(args.steps, 200), 20, 2, torch)
-    print(f"[bench] plain 1 stream: {plain_fps:.0f} frames/s", file=sys.stderr, flush=True)
+    plain_fps = None
+    if not args.no_plain and args.plain_steps > 0:
+        pdt, _, _, _, _ = run_engine(vsa, dev, params, 1, args.plain_steps, 20, 0, torch)
+        plain_fps = args.plain_steps / pdt
+        print(f"[bench] plain 1 stream: {plain_fps:.0f} frames/s", file=sys.stderr, flush=True)
+    kt_all = None
+    if not args.no_diag:
+        # untimed diagnostic: every kernel timed, for the per-kernel breakdown
+        _, kt_all, _, _, _ = run_engine(vsa, dev, params, args.streams, min(args.steps, 200), 20, 2, torch)
 
     g = oracle.geometry(W, H, params)
     k1b = k1_bytes_per_frame(g, W, H, params["k_max"])
@@ -190,15 +237,18 @@ def main():
         blocks = (c1["consecutive_blocks"] - c0["consecutive_blocks"]) + (c1["sparse_blocks"] - c0["sparse_blocks"])
         ad = blocks * 289 * 64
         me_tads = ad / (me_ms * 1e-3) / 1e12 if me_ms > 0 else 0.0
+        traffic = k1_traffic(args.streams)
         hbm = {"bound": "hbm", "kernel": "k_pyramid", "achieved": round(k1_gbs, 1), "peak": HBM_PEAK_GBS,
-               "unit": "GB/s", "frac": round(k1_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+               "unit": "GB/s", "frac": round(k1_gbs / HBM_PEAK_GBS, 4),
+               "traffic": None if traffic is None else int(traffic),
                "avg_launch_us": round(k1_avg * 1e3, 3), "bytes_per_launch": args.streams * k1b}
         alu = {"bound": "alu", "kernel": "k_me<uint8_t>", "achieved": round(me_tads, 2), "peak": round(AD_PEAK_T, 1),
                "unit": "T absdiff/s", "frac": round(me_tads / AD_PEAK_T, 4), "traffic": None,
                "avg_launch_us": round(me_ms / max(me_n, 1) * 1e3, 3), "ad_per_launch": ad / max(me_n, 1)}
         roof, other = (hbm, alu) if k1_ms >= me_ms else (alu, hbm)
         extra["roofline_other"] = other
-        extra["kernel_ms_per_step"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in kt_all.items() if v[1]}
+        if kt_all:
+            extra["kernel_ms_per_step"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in kt_all.items() if v[1]}
         extra["step_hbm_frac"] = round(args.streams * k1b / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
     cpu = None
     if not args.no_cpu_baseline:
@@ -221,8 +271,8 @@ def main():
                                f"{args.frames}-frame seeded clip resident in HBM, k_max 8, sparse schedule",
                    "streams": args.streams, "width": W, "height": H, "bit_depth": 8},
         "x_realtime": round(fps / RT_FPS, 1),
-        "plain_fps": round(plain_fps, 1),
-        "plain_x_realtime": round(plain_fps / RT_FPS, 1),
+        "plain_fps": None if plain_fps is None else round(plain_fps, 1),
+        "plain_x_realtime": None if plain_fps is None else round(plain_fps / RT_FPS, 1),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -35,6 +35,7 @@ __constant__ uint16_t c_rank[kCand * kCand];
 __constant__ uint16_t c_unrank[kCand * kCand];
 
 constexpr int kJW8 = 80;   // J window row length (bytes, 8-bit)
+constexpr int kXcd = 8;    // accelerator complex dies, one L2 each
 constexpr int kJRows = 80;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -444,7 +445,22 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
     const unsigned long long tt = cur ? cur->sparse_tt[par_prev].v : 0ull;
     const int n_sparse = tt_tasks(tt);
     const int total = consec_tiles + tt_tiles(tt);
-    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    // Workgroups are dispatched round-robin over the XCDs, each with its own
+    // L2: workgroup b runs on XCD b % kXcd.  Each XCD walks one contiguous
+    // slice of the tile list, so neighbouring tiles of a pair (which share
+    // cache lines of I and of the J halo) are fetched into the same L2.
+    int lo = 0, hi = total, first = blockIdx.x, stride = gridDim.x;
+    if (gridDim.x >= kXcd) {
+        const int groups = gridDim.x / kXcd;      // the host launches a multiple of kXcd
+        const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+        if (j >= groups) return;
+        const int per = (total + kXcd - 1) / kXcd;
+        lo = x * per;
+        hi = min(total, lo + per);
+        first = lo + j;
+        stride = groups;
+    }
+    for (int tile = first; tile < hi; tile += stride) {
         const PairTask* tk;
         int local;
         if (tile < consec_tiles) {

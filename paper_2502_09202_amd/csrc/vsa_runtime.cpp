@@ -849,7 +849,8 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     // persistent motion-search grid: enough workgroups for the largest possible step
     int64_t max_tiles = consec_tiles;
     for (const HostStream& s : e->streams) if (s.open && !s.done) max_tiles += s.sparse_tiles_max;
-    const int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), e->me_grid);
+    int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), e->me_grid);
+    if (grid >= 8) grid -= grid % 8;   // whole groups of one workgroup per XCD
     // sparse task lists alternate between steps: read the previous one, write the next
     const size_t sp_cap = (size_t)M * kMaxTasksPerStream;
     PairTask* sparse_prev = e->d_sparse + (size_t)(par ^ 1) * sp_cap;

@@ -72,14 +72,23 @@ def copy_only(nbytes, reps):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
 
 
+def _spec(kind):
+    import synth
+    if kind[0] == "c2":
+        _, seed, T, W, H = kind
+        return synth.make_c2(seed=seed, T=T, W=W, H=H, k_dis=8)
+    _, i, seed, T = kind                      # clip i of the uneven mix
+    return synth.make_mix_clip(i, seed=seed, T=T)
+
+
 def _render_range(args):
-    seed, T, W, H, lo, hi, shm_name = args
+    kind, n, lo, hi, shm_name = args
     from multiprocessing import shared_memory
     import synth
-    spec = synth.make_c2(seed=seed, T=T, W=W, H=H, k_dis=8)
+    spec = _spec(kind)
     r = synth.Renderer(spec)
     shm = shared_memory.SharedMemory(name=shm_name)
-    out = np.ndarray((T, H, W), np.uint8, buffer=shm.buf)
+    out = np.ndarray((n, spec.H, spec.W), np.uint8, buffer=shm.buf)
     for t in range(lo, hi):
         out[t] = r.frame(t)
     del out
@@ -87,20 +96,84 @@ def _render_range(args):
     return hi - lo
 
 
-def render_clip(seed, T, W, H, workers):
+def render_frames(kind, n, W, H, workers):
+    """Frames 0..n-1 of a seeded clip, rendered in parallel processes."""
     from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(create=True, size=T * H * W)
+    shm = shared_memory.SharedMemory(create=True, size=n * H * W)
     try:
-        chunks = np.linspace(0, T, workers * 4 + 1).astype(int)
-        jobs = [(seed, T, W, H, int(a), int(b), shm.name) for a, b in zip(chunks[:-1], chunks[1:]) if b > a]
+        chunks = np.linspace(0, n, workers * 4 + 1).astype(int)
+        jobs = [(kind, n, int(a), int(b), shm.name) for a, b in zip(chunks[:-1], chunks[1:]) if b > a]
         with mp.get_context("spawn").Pool(workers) as pool:
             done = sum(pool.map(_render_range, jobs))
-        assert done == T
-        frames = np.ndarray((T, H, W), np.uint8, buffer=shm.buf).copy()
+        assert done == n
+        frames = np.ndarray((n, H, W), np.uint8, buffer=shm.buf).copy()
     finally:
         shm.close()
         shm.unlink()
     return frames
+
+
+def render_clip(seed, T, W, H, workers):
+    return render_frames(("c2", seed, T, W, H), T, W, H, workers)
+
+
+def mix_pools(n, workers, torch):
+    """The first n frames of one clip per format of the uneven mix, on the device."""
+    import synth
+    pools = []
+    for i, (W, H, _, _) in enumerate(synth.MIX_FORMATS):
+        fr = render_frames(("mix", i, 3, 3000), n, W, H, workers)
+        pools.append(torch.from_numpy(fr).to("cuda:0"))
+    torch.cuda.synchronize()
+    return pools
+
+
+def run_mix(vsa, pools, params, B, steps, warmup, torch):
+    """B clips of the uneven mix in one engine (clip i: format i mod 6), every
+    clip stepping together; returns frames/s and the per-kernel times."""
+    e = vsa.Engine(device=0, max_streams=B, params=params, profile=2)
+    sids, bases, pitches, planes, nsrc = [], [], [], [], []
+    for i in range(B):
+        src = pools[i % len(pools)]
+        F, H, W = src.shape
+        sids.append(e.stream_open(W, H, 8))
+        bases.append(src.data_ptr()); pitches.append(W); planes.append(H * W); nsrc.append(F)
+    sids = np.array(sids, np.int32)
+    bases = np.array(bases, np.uint64); pitches = np.array(pitches, np.int64)
+    planes = np.array(planes, np.uint64); nsrc = np.array(nsrc, np.int64)
+    offs = np.arange(B) * 7
+
+    def do_step(s):
+        ptrs = bases + ((offs + s) % nsrc).astype(np.uint64) * planes
+        if e.stream_push_batch(sids, ptrs, pitches, vsa.SRC_DEVICE_BORROW, None) != 0:
+            raise RuntimeError(vsa.last_error())
+        e.step()
+
+    for s in range(warmup):
+        do_step(s)
+    e.sync()
+    e.kernel_times(reset=True)
+    t0 = time.perf_counter()
+    for s in range(warmup, warmup + steps):
+        do_step(s)
+    e.sync()
+    dt = time.perf_counter() - t0
+    kt = e.kernel_times()
+    e.close()
+    return B * steps / dt, {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}
+
+
+def serve_requests(serve, pools, n, rate, seed, lengths=(200, 3000)):
+    """Clips of the uneven mix arriving as a Poisson process: format uniform,
+    length U{lengths}, each reading its format's frame pool from a random start."""
+    rng = np.random.default_rng(seed)
+    arr = serve.poisson_arrivals(rate, n, seed) if rate > 0 else np.zeros(n)
+    reqs = []
+    for cid in range(n):
+        src = pools[int(rng.integers(0, len(pools)))]
+        reqs.append(serve.ClipRequest(cid, float(arr[cid]), src, int(rng.integers(0, src.shape[0])),
+                                      int(rng.integers(lengths[0], lengths[1] + 1)), 8))
+    return reqs
 
 
 def k1_bytes_per_frame(g, W, H, k_max):
@@ -183,6 +256,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-stream comparison run")
     ap.add_argument("--no-diag", action="store_true", help="skip the all-kernel timing run")
+    ap.add_argument("--no-mix", action="store_true", help="skip the uneven-mix batched run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served runs")
+    ap.add_argument("--serve-clips", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
@@ -250,6 +327,37 @@ def main():
         if kt_all:
             extra["kernel_ms_per_step"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in kt_all.items() if v[1]}
         extra["step_hbm_frac"] = round(args.streams * k1b / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
+    pools = None
+    if not (args.no_mix and args.no_serve):
+        t1 = time.perf_counter()
+        pools = mix_pools(64, args.workers, torch)
+        print(f"[bench] mix frame pools rendered in {time.perf_counter() - t1:.1f}s", file=sys.stderr, flush=True)
+    if not args.no_mix:
+        mfps, mkt = run_mix(vsa, pools, dict(params, k_max=8), 64, 300, 30, torch)
+        extra["mix"] = {"workload": "64 clips of the uneven mix in one engine (720x576i, 1280x720p, "
+                                    "1920x1080p, 1920x1080i, 2048x1080p, 3840x2160p; 8-bit), one frame "
+                                    "each per step", "fps": round(mfps, 1), "kernel_ms_per_step": mkt}
+        print(f"[bench] mix 64 clips: {mfps:.0f} frames/s", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        from paper_2502_09202_amd import serve
+        sv = {}
+        p8 = dict(params, k_max=8)
+        for name, rate in (("poisson", args.serve_rate), ("archive", 0.0)):
+            for path in ("batched", "plain"):
+                reqs = serve_requests(serve, pools, args.serve_clips, rate, 4)
+                S = serve.Server if path == "batched" else serve.PlainServer
+                srv = S(max_streams=256, params=p8)
+                try:
+                    rep_ = srv.run(reqs, keep_records=False)
+                finally:
+                    srv.close()
+                sv[f"{name}_{path}"] = rep_.summary()
+                print(f"[bench] serve {name} {path}: {rep_.fps:.0f} frames/s, frame p50/p99 "
+                      f"{sv[f'{name}_{path}']['frame_latency_ms_p50']:.2f}/"
+                      f"{sv[f'{name}_{path}']['frame_latency_ms_p99']:.2f} ms", file=sys.stderr, flush=True)
+        extra["serve"] = {"workload": f"{args.serve_clips} clips of the uneven mix, length U{{200..3000}}, "
+                                      f"Poisson arrivals at {args.serve_rate}/s (poisson) or all at once "
+                                      "(archive); budget 90% of free HBM, 256 slots", **sv}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(frames, params, args.cpu_seconds)

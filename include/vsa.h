@@ -112,7 +112,8 @@ enum {
     VSA_SRC_DEVICE_COPY = 1,   /* device memory; copied into engine-owned device memory before
                                   the call returns                                               */
     VSA_SRC_DEVICE_BORROW = 2  /* device memory read in place by the next vsa_step; the caller
-                                  keeps it valid and unmodified until vsa_sync returns           */
+                                  keeps it valid and unmodified until that step has completed:
+                                  vsa_sync has returned, or vsa_collect counts it as published  */
 };
 
 /* Per-frame record.  The pair measures describe (frame -> frame+1) at the
@@ -188,8 +189,8 @@ vsa_status vsa_stream_push_batch(vsa_engine* e, int32_t n, const int32_t* sids, 
 /* End of stream: later steps drain the look-ahead and close the last shot. */
 vsa_status vsa_stream_end(vsa_engine* e, int32_t sid);
 
-/* 1 once every record of an ended stream has been produced (after vsa_sync),
- * 0 if not, < 0 on error. */
+/* 1 once every record of an ended stream has been published (by vsa_sync or
+ * vsa_collect), 0 if not, < 0 on error. */
 int32_t vsa_stream_done(vsa_engine* e, int32_t sid);
 
 /* Enqueue one time step over every open stream.  Asynchronous.  hip_stream
@@ -200,6 +201,14 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream);
 /* Wait for every queued step and publish its records to the host queues. */
 vsa_status vsa_sync(vsa_engine* e);
 
+/* Publish, without waiting, the records of every step the device has already
+ * completed (each step snapshots the output cursors after its decisions), so
+ * that vsa_poll_* return them; the non-blocking form of vsa_sync for serving
+ * loops.  *steps_published (nullable) receives the number of steps, counted
+ * from the engine's first, whose records are published.  Errors:
+ * VSA_E_INVAL, VSA_E_DEVICE. */
+vsa_status vsa_collect(vsa_engine* e, int64_t* steps_published);
+
 /* Copy up to cap finished per-frame records of stream sid, in frame order, and
  * remove them from the queue.  Returns the number copied, or < 0 on error. */
 int32_t vsa_poll_frames(vsa_engine* e, int32_t sid, vsa_frame_result* out, int32_t cap);
@@ -207,13 +216,20 @@ int32_t vsa_poll_frames(vsa_engine* e, int32_t sid, vsa_frame_result* out, int32
 /* Same for per-shot records. */
 int32_t vsa_poll_shots(vsa_engine* e, int32_t sid, vsa_shot_result* out, int32_t cap);
 
+/* Per-frame records of every stream in one call: up to cap records, each
+ * stream's in frame order, with sids[i] the stream of out[i].  Returns the
+ * number copied, or < 0 on error.  For serving loops over many streams. */
+int32_t vsa_poll_frames_all(vsa_engine* e, int32_t* sids, vsa_frame_result* out, int32_t cap);
+
 /* Motion field of the pair (frame -> frame+1) of stream sid at the working
  * level, as nby x nbx pairs (dx, dy) of int8, if that frame is still held on
  * the device (the last 2 k_max + 7 frames).  Synchronises the engine. */
 vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
                           int32_t cap_blocks, int32_t* nbx, int32_t* nby);
 
-/* Free the slot at once; records not yet polled are dropped. */
+/* Free the slot at once, without waiting for the device: records not yet
+ * polled are dropped, and the stream's device memory is reused only after the
+ * queued steps that read it have completed. */
 vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
 
 /* Engine counters, the first n of: [0] steps, [1] streams open, [2] streams

@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     int32_t* __restrict__ log, int64_t log_cap, vsa_shot_result* __restrict__ closed_buf, int32_t par) {
     struct Bcast {
         FrameInfo* info;
-        int32_t rs, sid, e0, nframes, nshots, ntasks, tiles, blocks;
+        int32_t rs, sid, epoch, e0, nframes, nshots, ntasks, tiles, blocks;
         uint64_t fbase, sbase;
         int32_t task, tile;
     };
@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
             blocks += (pd.w / kBlock) * (pd.h / kBlock);
         }
         Bcast& b = bc[wave];
-        b.info = sd.info; b.rs = sd.rs; b.sid = sid; b.e0 = e0; b.nframes = st.t - e0; b.nshots = st.n_closed;
+        b.info = sd.info; b.rs = sd.rs; b.sid = sid; b.epoch = sd.epoch; b.e0 = e0; b.nframes = st.t - e0; b.nshots = st.n_closed;
         b.ntasks = nt; b.tiles = tiles; b.blocks = blocks;
     } else if (lane == 0) {
         Bcast& b = bc[wave];
@@ -564,13 +564,13 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     for (int q = lane; q < b.nframes; q += 64) {
         OutFrame& o = out_frames[(b.fbase + (uint64_t)q) % frames_cap];
         o.sid = b.sid;
-        o.pad = 0;
+        o.pad = b.epoch;   // lets the host drop records of a slot's earlier stream
         fill_record(o.r, b.info[(b.e0 + q) % b.rs]);
     }
     if (lane < b.nshots) {
         OutShot& o = out_shots[(b.sbase + (uint64_t)lane) % shots_cap];
         o.sid = b.sid;
-        o.pad = 0;
+        o.pad = b.epoch;   // lets the host drop records of a slot's earlier stream
         o.r = closed_buf[(int64_t)b.sid * kMaxClosed + lane];
     }
 }

@@ -93,6 +93,9 @@ constexpr int kProfRing = 64;
 constexpr int kAhead = 3;
 constexpr int kProfKinds = 6;
 constexpr int kDescRing = 8;
+// Cursor snapshots, one per step (a ring): the host may run at most kDescRing
+// steps ahead of the device, so a snapshot is never rewritten while it is read.
+constexpr int kSnap = 64;
 constexpr int64_t kLogCapPerStream = 1 << 16;
 
 int ceil_log2(int k) {
@@ -195,7 +198,8 @@ struct HostStream {
     StreamDesc sd{};
     Geo geo;
     uint8_t* mem = nullptr;
-    uint64_t bytes = 0;
+    uint64_t mem_bytes = 0;    // size of mem
+    uint64_t bytes = 0;        // budget charged (mem + tile partials)
     uint8_t* staging_dev[2] = {nullptr, nullptr};
     int64_t staging_pitch = 0;
     int next_frame = 0;        // frames pushed
@@ -254,12 +258,27 @@ struct vsa_engine {
     size_t desc_bytes = 0;
     // host staging for VSA_SRC_HOST planes (per stream, 2 slots)
     std::vector<uint8_t*> h_stage;
+    std::vector<int64_t> h_stage_bytes;
     std::vector<hipEvent_t> stage_ev;
     // output drain
     uint64_t frames_read = 0, shots_read = 0;
-    OutFrame* h_out_frames = nullptr;
-    OutShot* h_out_shots = nullptr;
-    uint64_t pushed_since_drain = 0;   // frames ingested since the last drain
+    OutFrame* h_out_frames = nullptr;  // output rings in mapped pinned memory; the
+    OutShot* h_out_shots = nullptr;    // decision kernel writes them through d_out_*
+    uint64_t pushed_since_drain = 0;   // frames ingested after the newest published step
+    // non-blocking publication: after its decisions each step copies the
+    // cursors into h_snap[step % kSnap] and records pub_ev of that slot
+    DeviceCursors* h_snap = nullptr;
+    hipEvent_t pub_ev[kSnap] = {};
+    uint64_t pushed_cum[kSnap] = {};   // frames ingested up to and including each step
+    uint64_t pushed_total = 0;
+    int64_t pub_step = -1;             // newest step whose records are published
+    // memory of closed streams, reusable once the device is past its last use
+    struct PoolBlock { uint8_t* mem; uint64_t bytes; hipEvent_t ev; };
+    std::vector<PoolBlock> pool;
+    // pinned sources of the stream-ordered descriptor / state writes of open and close
+    uint8_t* h_init = nullptr;
+    size_t init_stride = 0;
+    std::vector<hipEvent_t> init_ev;
     // per-kernel timing (profile = 1): a ring of event pairs per step
     int profile = 0;
     hipEvent_t prof_ev[kProfRing][kProfKinds][2] = {};
@@ -324,29 +343,16 @@ void prof_collect_all(vsa_engine* e) {
     for (int i = 0; i < kProfRing; ++i) prof_collect(e, i);
 }
 
-vsa_status drain(vsa_engine* e) {
-    HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
-    HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-    DeviceCursors c;
-    HIPCK(hipMemcpy(&c, e->d_cur, sizeof c, hipMemcpyDeviceToHost), "read cursors");
-    auto copy_ring = [&](auto* d_ring, auto* h_buf, uint64_t cap, uint64_t from, uint64_t to) -> hipError_t {
-        using Elem = std::remove_pointer_t<decltype(d_ring)>;
-        uint64_t n = to - from;
-        uint64_t a = from % cap;
-        uint64_t first = std::min(n, cap - a);
-        hipError_t err = hipSuccess;
-        if (first) err = hipMemcpy(h_buf, d_ring + a, first * sizeof(Elem), hipMemcpyDeviceToHost);
-        if (err == hipSuccess && n > first)
-            err = hipMemcpy(h_buf + first, d_ring, (n - first) * sizeof(Elem), hipMemcpyDeviceToHost);
-        return err;
-    };
+// Move the records up to the cursors c (all written by completed steps) from
+// the mapped output rings into the per-stream queues.  Records of a stream
+// closed since they were written carry an older epoch and are dropped.
+vsa_status publish(vsa_engine* e, const DeviceCursors& c) {
     if (c.frames_written.v > e->frames_read) {
         if (c.frames_written.v - e->frames_read > kFramesCap) return fail(VSA_E_DEVICE, "frame ring overflow");
-        HIPCK(copy_ring(e->d_out_frames, e->h_out_frames, kFramesCap, e->frames_read, c.frames_written.v), "drain frames");
-        for (uint64_t i = 0; i < c.frames_written.v - e->frames_read; ++i) {
-            const OutFrame& o = e->h_out_frames[i];
+        for (uint64_t i = e->frames_read; i < c.frames_written.v; ++i) {
+            const OutFrame& o = e->h_out_frames[i % kFramesCap];
             HostStream& s = e->streams[o.sid];
-            if (!s.open) continue;
+            if (!s.open || o.pad != s.epoch) continue;
             s.fq.push_back(o.r);
             s.frames_out += 1;
         }
@@ -354,32 +360,106 @@ vsa_status drain(vsa_engine* e) {
     }
     if (c.shots_written.v > e->shots_read) {
         if (c.shots_written.v - e->shots_read > kShotsCap) return fail(VSA_E_DEVICE, "shot ring overflow");
-        HIPCK(copy_ring(e->d_out_shots, e->h_out_shots, kShotsCap, e->shots_read, c.shots_written.v), "drain shots");
-        for (uint64_t i = 0; i < c.shots_written.v - e->shots_read; ++i) {
-            const OutShot& o = e->h_out_shots[i];
+        for (uint64_t i = e->shots_read; i < c.shots_written.v; ++i) {
+            const OutShot& o = e->h_out_shots[i % kShotsCap];
             HostStream& s = e->streams[o.sid];
-            if (!s.open) continue;
+            if (!s.open || o.pad != s.epoch) continue;
             s.sq.push_back(o.r);
         }
         e->shots_read = c.shots_written.v;
     }
     for (HostStream& s : e->streams)
         if (s.open && s.ended && s.frames_out >= s.T_end) s.done = true;
-    e->pushed_since_drain = 0;
     e->counters[6] = c.sparse_run.v;
     e->counters[9] = c.sparse_blocks.v;
+    return VSA_OK;
+}
+
+// Wait for every queued step, then publish.
+vsa_status drain(vsa_engine* e) {
+    HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
+    HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    DeviceCursors c;
+    HIPCK(hipMemcpy(&c, e->d_cur, sizeof c, hipMemcpyDeviceToHost), "read cursors");
+    vsa_status st = publish(e, c);
+    if (st != VSA_OK) return st;
+    e->pub_step = e->step_no - 1;
+    e->pushed_since_drain = 0;
     prof_collect_all(e);
     return VSA_OK;
 }
 
+// Publish the steps the device has completed, without waiting.
+vsa_status collect(vsa_engine* e) {
+    int64_t s = e->pub_step + 1;
+    while (s < e->step_no) {
+        const hipError_t q = hipEventQuery(e->pub_ev[s % kSnap]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return hip_fail(q, "step completion query");
+        ++s;
+    }
+    const int64_t last = s - 1;
+    if (last <= e->pub_step) return VSA_OK;
+    vsa_status st = publish(e, e->h_snap[last % kSnap]);
+    if (st != VSA_OK) return st;
+    e->pub_step = last;
+    e->pushed_since_drain = e->pushed_total - e->pushed_cum[last % kSnap];
+    return VSA_OK;
+}
+
+// Release a stream slot without waiting for the device: its descriptor is
+// zeroed on the main stream (after every queued step that may read it) and
+// its memory joins the pool once that point of the main stream is reached.
 void free_stream(vsa_engine* e, int sid) {
     HostStream& s = e->streams[sid];
-    if (s.mem) (void)hipFree(s.mem);
+    hipEvent_t ev = nullptr;
+    const uint8_t* zero = e->h_init + e->init_stride * (size_t)e->max_streams;
+    bool ordered = hipMemcpyAsync(e->d_sds + sid, zero, sizeof(StreamDesc), hipMemcpyHostToDevice, e->stream) ==
+                   hipSuccess;
+    ordered = ordered && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+              hipEventRecord(ev, e->stream) == hipSuccess;
+    // the ingest stream may run ahead of the main stream: it must not see the
+    // slot again before the zeroing
+    ordered = ordered && hipStreamWaitEvent(e->stream_b, ev, 0) == hipSuccess;
+    if (s.mem) {
+        if (ordered) {
+            e->pool.push_back({s.mem, s.mem_bytes, ev});
+            ev = nullptr;
+        } else {
+            (void)hipStreamSynchronize(e->stream_b);
+            (void)hipStreamSynchronize(e->stream);
+            (void)hipFree(s.mem);
+        }
+    }
+    if (ev) (void)hipEventDestroy(ev);
     e->used -= s.bytes;
     s = HostStream();
-    StreamDesc z;
-    std::memset(&z, 0, sizeof z);
-    (void)hipMemcpy(e->d_sds + sid, &z, sizeof z, hipMemcpyHostToDevice);
+}
+
+// Device memory for a new stream: a pooled block of the same size whose last
+// use has completed, else a fresh allocation (the pool is released first if
+// that fails).
+uint8_t* stream_alloc(vsa_engine* e, uint64_t bytes) {
+    for (size_t i = 0; i < e->pool.size(); ++i) {
+        auto& b = e->pool[i];
+        if (b.bytes != bytes || hipEventQuery(b.ev) != hipSuccess) continue;
+        uint8_t* m = b.mem;
+        (void)hipEventDestroy(b.ev);
+        e->pool.erase(e->pool.begin() + (long)i);
+        return m;
+    }
+    uint8_t* m = nullptr;
+    if (hipMalloc(&m, bytes) == hipSuccess) return m;
+    (void)hipStreamSynchronize(e->stream_b);
+    (void)hipStreamSynchronize(e->stream);
+    for (auto& b : e->pool) {
+        (void)hipFree(b.mem);
+        (void)hipEventDestroy(b.ev);
+    }
+    e->pool.clear();
+    m = nullptr;
+    if (hipMalloc(&m, bytes) == hipSuccess) return m;
+    return nullptr;
 }
 
 void init_state(DecideState& st) {
@@ -451,8 +531,6 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     ok = ok && dalloc((void**)&e->d_results, sizeof(PairResult) * M * kResSlots);
     ok = ok && dalloc((void**)&e->d_sparse, 2 * sizeof(PairTask) * M * kMaxTasksPerStream);
     ok = ok && dalloc((void**)&e->d_cur, sizeof(DeviceCursors));
-    ok = ok && dalloc((void**)&e->d_out_frames, sizeof(OutFrame) * kFramesCap);
-    ok = ok && dalloc((void**)&e->d_out_shots, sizeof(OutShot) * kShotsCap);
     e->desc_bytes = desc_size(M);
     e->desc_build.assign(e->desc_bytes, 0);
     ok = ok && dalloc((void**)&e->d_desc, (kAhead + 1) * e->desc_bytes);
@@ -461,8 +539,20 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
              hipHostGetDevicePointer(&e->h_desc_dev[i], e->h_desc[i], 0) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&e->desc_ev[i], hipEventDisableTiming) == hipSuccess;
     }
-    ok = ok && hipHostMalloc((void**)&e->h_out_frames, sizeof(OutFrame) * kFramesCap, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&e->h_out_shots, sizeof(OutShot) * kShotsCap, hipHostMallocDefault) == hipSuccess;
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
+    ok = ok && hipHostMalloc((void**)&e->h_out_frames, sizeof(OutFrame) * kFramesCap, mapped) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&e->d_out_frames, e->h_out_frames, 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&e->h_out_shots, sizeof(OutShot) * kShotsCap, mapped) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&e->d_out_shots, e->h_out_shots, 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&e->h_snap, sizeof(DeviceCursors) * kSnap, hipHostMallocDefault) == hipSuccess;
+    for (int i = 0; ok && i < kSnap; ++i)
+        ok = hipEventCreateWithFlags(&e->pub_ev[i], hipEventDisableTiming) == hipSuccess;
+    e->init_stride = round_up(sizeof(StreamDesc) + sizeof(DecideState), 256);
+    ok = ok && hipHostMalloc((void**)&e->h_init, e->init_stride * (M + 1), hipHostMallocDefault) == hipSuccess;
+    if (ok) std::memset(e->h_init, 0, e->init_stride * (M + 1));   // the last entry stays zero
+    e->init_ev.assign(M, nullptr);
+    for (int i = 0; ok && i < M; ++i)
+        ok = hipEventCreateWithFlags(&e->init_ev[i], hipEventDisableTiming) == hipSuccess;
     if (ok && e->debug_log) ok = dalloc((void**)&e->d_log, sizeof(int32_t) * 6 * kLogCapPerStream * M);
     if (ok) {
         ok = hipMemset(e->d_sds, 0, sizeof(StreamDesc) * M) == hipSuccess &&
@@ -475,6 +565,7 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
             for (int j = 0; ok && j < 2; ++j)
                 ok = hipEventCreate(&e->prof_ev[i][k][j]) == hipSuccess;
     e->h_stage.assign(2 * M, nullptr);
+    e->h_stage_bytes.assign(2 * M, 0);
     e->stage_ev.assign(2 * M, nullptr);
     if (!ok) {
         vsa_engine_destroy(e);
@@ -491,10 +582,18 @@ void vsa_engine_destroy(vsa_engine* e) {
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     for (size_t i = 0; i < e->streams.size(); ++i)
         if (e->streams[i].mem) (void)hipFree(e->streams[i].mem);
+    for (const auto& b : e->pool) {
+        (void)hipFree(b.mem);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+    }
+    for (hipEvent_t ev : e->init_ev) if (ev) (void)hipEventDestroy(ev);
+    if (e->h_init) (void)hipHostFree(e->h_init);
+    for (int i = 0; i < kSnap; ++i) if (e->pub_ev[i]) (void)hipEventDestroy(e->pub_ev[i]);
+    if (e->h_snap) (void)hipHostFree(e->h_snap);
     for (uint8_t* h : e->h_stage) if (h) (void)hipHostFree(h);
     for (hipEvent_t ev : e->stage_ev) if (ev) (void)hipEventDestroy(ev);
-    void* dev[] = {e->d_sds, e->d_states, e->d_closed, e->d_results, e->d_sparse, e->d_cur, e->d_out_frames,
-                   e->d_out_shots, e->d_partials, e->d_log, e->d_desc};
+    void* dev[] = {e->d_sds, e->d_states, e->d_closed, e->d_results, e->d_sparse, e->d_cur,
+                   e->d_partials, e->d_log, e->d_desc};
     for (void* p : dev) if (p) (void)hipFree(p);
     for (int i = 0; i < kDescRing; ++i) {
         if (e->h_desc[i]) (void)hipHostFree(e->h_desc[i]);
@@ -566,8 +665,8 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     const int epoch = e->slot_epoch[slot] + 1;
     e->slot_epoch[slot] = epoch;
     sd.epoch = epoch;
-    uint8_t* mem = nullptr;
-    if (hipMalloc(&mem, bytes) != hipSuccess) {
+    uint8_t* mem = stream_alloc(e, bytes);
+    if (!mem) {
         e->counters[3] += 1;
         return fail(VSA_E_ADMIT, "device allocation for the stream failed");
     }
@@ -583,6 +682,7 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     s.sd = sd;
     s.geo = g;
     s.mem = mem;
+    s.mem_bytes = bytes;
     s.bytes = bytes + part;
     s.staging_pitch = sp;
     s.staging_dev[0] = mem + off;
@@ -591,11 +691,24 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     s.sparse_tiles_max = max_sparse_tiles(sd);
     s.epoch = epoch;
     e->used += s.bytes;
+    // descriptor, decision state and frame records are initialised on the
+    // main stream, after every queued step (which may still use this slot's
+    // previous stream); the ingest stream waits for it before its next step
     DecideState ds;
     init_state(ds);
-    hipError_t err = hipMemcpy(e->d_sds + slot, &sd, sizeof sd, hipMemcpyHostToDevice);
-    if (err == hipSuccess) err = hipMemcpy(e->d_states + slot, &ds, sizeof ds, hipMemcpyHostToDevice);
-    if (err == hipSuccess) err = hipMemset(sd.info, 0, sizeof(FrameInfo) * sd.rs);
+    uint8_t* src = e->h_init + e->init_stride * (size_t)slot;
+    hipError_t err = hipEventSynchronize(e->init_ev[slot]);   // the previous open's copies
+    if (err == hipSuccess) {
+        std::memcpy(src, &sd, sizeof sd);
+        std::memcpy(src + sizeof(StreamDesc), &ds, sizeof ds);
+        err = hipMemcpyAsync(e->d_sds + slot, src, sizeof sd, hipMemcpyHostToDevice, e->stream);
+    }
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->d_states + slot, src + sizeof(StreamDesc), sizeof ds, hipMemcpyHostToDevice,
+                             e->stream);
+    if (err == hipSuccess) err = hipMemsetAsync(sd.info, 0, sizeof(FrameInfo) * sd.rs, e->stream);
+    if (err == hipSuccess) err = hipEventRecord(e->init_ev[slot], e->stream);
+    if (err == hipSuccess) err = hipStreamWaitEvent(e->stream_b, e->init_ev[slot], 0);
     if (err != hipSuccess) { free_stream(e, slot); return hip_fail(err, "stream init"); }
     st = ensure_partials(e);
     if (st != VSA_OK) { free_stream(e, slot); return st; }
@@ -624,11 +737,15 @@ vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t
     const int slot = s->next_frame & 1;
     if (src == VSA_SRC_HOST) {
         const int k = 2 * sid + slot;
-        if (!e->h_stage[k]) {
-            HIPCK(hipHostMalloc((void**)&e->h_stage[k], s->staging_pitch * s->sd.H, hipHostMallocDefault), "pinned staging");
-            HIPCK(hipEventCreateWithFlags(&e->stage_ev[k], hipEventDisableTiming), "event");
-        } else {
-            HIPCK(hipEventSynchronize(e->stage_ev[k]), "staging reuse");
+        const int64_t need = s->staging_pitch * s->sd.H;
+        if (e->stage_ev[k]) HIPCK(hipEventSynchronize(e->stage_ev[k]), "staging reuse");
+        else HIPCK(hipEventCreateWithFlags(&e->stage_ev[k], hipEventDisableTiming), "event");
+        if (e->h_stage_bytes[k] < need) {   // a slot may be reused by a larger format
+            if (e->h_stage[k]) HIPCK(hipHostFree(e->h_stage[k]), "pinned staging");
+            e->h_stage[k] = nullptr;
+            e->h_stage_bytes[k] = 0;
+            HIPCK(hipHostMalloc((void**)&e->h_stage[k], need, hipHostMallocDefault), "pinned staging");
+            e->h_stage_bytes[k] = need;
         }
         const uint8_t* p = static_cast<const uint8_t*>(luma);
         for (int y = 0; y < s->sd.H; ++y) std::memcpy(e->h_stage[k] + y * s->staging_pitch, p + y * pitch, row);
@@ -716,7 +833,9 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         if (s.open && !s.done) { backlog += s.sd.rs + 4; step_push += s.pending ? 1 : 0; ++n_open; }
     if (n_open == 0) return VSA_OK;
     if (e->pushed_since_drain + step_push + backlog > std::min(kFramesCap, kShotsCap)) {
-        vsa_status st = drain(e);
+        vsa_status st = collect(e);
+        if (st == VSA_OK && e->pushed_since_drain + step_push + backlog > std::min(kFramesCap, kShotsCap))
+            st = drain(e);
         if (st != VSA_OK) return st;
     }
     const int ps = (int)(e->prof_step % kProfRing);
@@ -871,6 +990,11 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
                                kShotsCap, e->d_log, kLogCapPerStream, e->d_closed, par, A), "decide launch");
     prof(4, 1, A);
     prof(5, 1, A);
+    // cursor snapshot of this step, read by vsa_collect once pub_ev completes
+    const int sn = (int)(e->step_no % kSnap);
+    HIPCK(hipMemcpyAsync(e->h_snap + sn, e->d_cur, sizeof(DeviceCursors), hipMemcpyDeviceToHost, A),
+          "cursor snapshot");
+    HIPCK(hipEventRecord(e->pub_ev[sn], A), "event");
     HIPCK(hipEventRecord(e->ev_a[slot_s], A), "event");
     e->prof_step += 1;
     e->step_no += 1;
@@ -878,6 +1002,8 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     for (HostStream& s : e->streams)
         if (s.open && s.pending) { s.pending = false; s.next_frame += 1; }
     e->pushed_since_drain += step_push;
+    e->pushed_total += step_push;
+    e->pushed_cum[sn] = e->pushed_total;
     const uint64_t t_end = now_ns();
     e->counters[10] += t_built - t_start;
     e->counters[11] += t_upload - t_built;
@@ -894,6 +1020,31 @@ vsa_status vsa_sync(vsa_engine* e) {
     std::lock_guard<std::mutex> lk(e->mu);
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
     return drain(e);
+}
+
+vsa_status vsa_collect(vsa_engine* e, int64_t* steps_published) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    vsa_status st = collect(e);
+    if (steps_published) *steps_published = e->pub_step + 1;
+    return st;
+}
+
+int32_t vsa_poll_frames_all(vsa_engine* e, int32_t* sids, vsa_frame_result* out, int32_t cap) {
+    if (!e || ((!out || !sids) && cap > 0) || cap < 0) return fail(VSA_E_INVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    int32_t n = 0;
+    for (int sid = 0; sid < e->max_streams && n < cap; ++sid) {
+        HostStream& s = e->streams[sid];
+        if (!s.open) continue;
+        while (n < cap && !s.fq.empty()) {
+            sids[n] = sid;
+            out[n++] = s.fq.front();
+            s.fq.pop_front();
+        }
+    }
+    return n;
 }
 
 int32_t vsa_poll_frames(vsa_engine* e, int32_t sid, vsa_frame_result* out, int32_t cap) {
@@ -944,15 +1095,14 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid) {
     HostStream* s = get_stream(e, sid);
     if (!s) return fail(VSA_E_INVAL, "no such stream");
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
-    HIPCK(hipStreamSynchronize(e->stream_b), "sync");
-    HIPCK(hipStreamSynchronize(e->stream), "sync");
-    // records of this stream still in the device ring are dropped at the next drain
-    vsa_status st = drain(e);
+    // records of this stream still in flight carry its epoch and are dropped
+    // when published; queued steps still read its memory, so the memory is
+    // only reused once the main stream has passed them
     free_stream(e, sid);
     bool any10 = false;
     for (const HostStream& o : e->streams) if (o.open && o.sd.bits == 10) any10 = true;
     e->has10 = any10;
-    return st;
+    return VSA_OK;
 }
 
 vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n) {

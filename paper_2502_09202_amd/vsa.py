@@ -79,7 +79,8 @@ SYMBOLS = [
     "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
     "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
-    "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times",
+    "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
+    "vsa_poll_frames_all",
 ]
 
 _lib = None
@@ -92,6 +93,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2502_09202_amd/build.py")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading it first
+    # makes libvsa bind to that one, so a process that also uses torch (for
+    # device buffers and streams) holds a single HIP runtime; loaded the other
+    # way round, torch would bring a second runtime that then finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     i32, i64, u64 = C.c_int32, C.c_int64, C.c_uint64
@@ -107,8 +116,10 @@ def lib():
         "vsa_stream_done": (i32, [P, i32]),
         "vsa_step": (i32, [P, P]),
         "vsa_sync": (i32, [P]),
+        "vsa_collect": (i32, [P, C.POINTER(i64)]),
         "vsa_poll_frames": (i32, [P, i32, P, i32]),
         "vsa_poll_shots": (i32, [P, i32, P, i32]),
+        "vsa_poll_frames_all": (i32, [P, P, P, i32]),
         "vsa_get_motion": (i32, [P, i32, i64, P, i32, C.POINTER(i32), C.POINTER(i32)]),
         "vsa_stream_close": (i32, [P, i32]),
         "vsa_engine_counters": (i32, [P, P, i32]),
@@ -255,10 +266,24 @@ class Engine:
     def sync(self):
         _check(lib().vsa_sync(self.h), "sync")
 
+    def collect(self) -> int:
+        """Publish the records of the steps the device has completed, without
+        waiting; returns the number of published steps."""
+        n = C.c_int64(0)
+        _check(lib().vsa_collect(self.h, C.byref(n)), "collect")
+        return n.value
+
     def poll_frames(self, sid: int, cap: int = 4096) -> np.ndarray:
         out = np.zeros(cap, FRAME_DTYPE)
         n = _check(lib().vsa_poll_frames(self.h, sid, _ptr(out), cap), "poll_frames")
         return out[:n].copy()
+
+    def poll_frames_all(self, cap: int = 1 << 16):
+        """Records of every stream: (sids int32[n], records FRAME_DTYPE[n])."""
+        sids = np.zeros(cap, np.int32)
+        out = np.zeros(cap, FRAME_DTYPE)
+        n = _check(lib().vsa_poll_frames_all(self.h, _ptr(sids), _ptr(out), cap), "poll_frames_all")
+        return sids[:n].copy(), out[:n].copy()
 
     def poll_shots(self, sid: int, cap: int = 1024) -> np.ndarray:
         out = np.zeros(cap, SHOT_DTYPE)

@@ -186,7 +186,7 @@ class Server:
             e.step()
             step += 1
             e.collect()
-            sids, recs = e.poll_frames_all()
+            sids, recs = e.poll_frames_all(max(4096, 8 * len(active)))
             t_poll = clock() - t0
             if len(recs):
                 frames_total += len(recs)

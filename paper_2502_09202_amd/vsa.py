@@ -278,10 +278,14 @@ class Engine:
         n = _check(lib().vsa_poll_frames(self.h, sid, _ptr(out), cap), "poll_frames")
         return out[:n].copy()
 
-    def poll_frames_all(self, cap: int = 1 << 16):
-        """Records of every stream: (sids int32[n], records FRAME_DTYPE[n])."""
-        sids = np.zeros(cap, np.int32)
-        out = np.zeros(cap, FRAME_DTYPE)
+    def poll_frames_all(self, cap: int = 4096):
+        """Records of every stream: (sids int32[n], records FRAME_DTYPE[n]), at
+        most cap per call (the receive buffers are reused between calls)."""
+        buf = getattr(self, "_poll_buf", None)
+        if buf is None or buf[0].size < cap:
+            buf = (np.zeros(cap, np.int32), np.zeros(cap, FRAME_DTYPE))
+            self._poll_buf = buf
+        sids, out = buf
         n = _check(lib().vsa_poll_frames_all(self.h, _ptr(sids), _ptr(out), cap), "poll_frames_all")
         return sids[:n].copy(), out[:n].copy()
 

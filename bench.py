@@ -77,6 +77,9 @@ def _spec(kind):
     if kind[0] == "c2":
         _, seed, T, W, H = kind
         return synth.make_c2(seed=seed, T=T, W=W, H=H, k_dis=8)
+    if kind[0] == "c5":
+        _, seed, T, W, H = kind
+        return synth.make_c5(seed=seed, T=T, W=W, H=H)
     _, i, seed, T = kind                      # clip i of the uneven mix
     return synth.make_mix_clip(i, seed=seed, T=T)
 
@@ -88,7 +91,7 @@ def _render_range(args):
     spec = _spec(kind)
     r = synth.Renderer(spec)
     shm = shared_memory.SharedMemory(name=shm_name)
-    out = np.ndarray((n, spec.H, spec.W), np.uint8, buffer=shm.buf)
+    out = np.ndarray((n, spec.H, spec.W), np.uint8 if spec.bits == 8 else np.uint16, buffer=shm.buf)
     for t in range(lo, hi):
         out[t] = r.frame(t)
     del out
@@ -96,17 +99,18 @@ def _render_range(args):
     return hi - lo
 
 
-def render_frames(kind, n, W, H, workers):
+def render_frames(kind, n, W, H, workers, bits=8):
     """Frames 0..n-1 of a seeded clip, rendered in parallel processes."""
     from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(create=True, size=n * H * W)
+    dt = np.uint8 if bits == 8 else np.uint16
+    shm = shared_memory.SharedMemory(create=True, size=n * H * W * np.dtype(dt).itemsize)
     try:
         chunks = np.linspace(0, n, workers * 4 + 1).astype(int)
         jobs = [(kind, n, int(a), int(b), shm.name) for a, b in zip(chunks[:-1], chunks[1:]) if b > a]
         with mp.get_context("spawn").Pool(workers) as pool:
             done = sum(pool.map(_render_range, jobs))
         assert done == n
-        frames = np.ndarray((n, H, W), np.uint8, buffer=shm.buf).copy()
+        frames = np.ndarray((n, H, W), dt, buffer=shm.buf).copy()
     finally:
         shm.close()
         shm.unlink()
@@ -161,6 +165,42 @@ def run_mix(vsa, pools, params, B, steps, warmup, torch):
     kt = e.kernel_times()
     e.close()
     return B * steps / dt, {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}
+
+
+def run_stress(vsa, frames, params, B, steps, warmup, dense, torch):
+    """B streams of 3840x2160 10-bit (uint16) in one engine, sparse or dense
+    schedule; returns frames/s, AD per frame and the per-kernel times."""
+    F, H, W = frames.shape
+    e = vsa.Engine(device=0, max_streams=B, params=params, profile=2,
+                   schedule=vsa.SCHEDULE_DENSE if dense else vsa.SCHEDULE_SPARSE)
+    sids = np.array([e.stream_open(W, H, 10) for _ in range(B)], np.int32)
+    base = frames.data_ptr()
+    plane = H * W * 2
+    offs = (np.arange(B) * (F // B)) % F
+    pitches = np.full(B, W * 2, np.int64)
+
+    def do_step(s):
+        ptrs = (base + ((offs + s) % F).astype(np.uint64) * plane).astype(np.uint64)
+        if e.stream_push_batch(sids, ptrs, pitches, vsa.SRC_DEVICE_BORROW, None) != 0:
+            raise RuntimeError(vsa.last_error())
+        e.step()
+
+    for s in range(warmup):
+        do_step(s)
+    e.sync()
+    e.kernel_times(reset=True)
+    c0 = e.counters()
+    t0 = time.perf_counter()
+    for s in range(warmup, warmup + steps):
+        do_step(s)
+    e.sync()
+    dt = time.perf_counter() - t0
+    c1 = e.counters()
+    kt = e.kernel_times()
+    e.close()
+    blocks = (c1["consecutive_blocks"] - c0["consecutive_blocks"]) + (c1["sparse_blocks"] - c0["sparse_blocks"])
+    return (B * steps / dt, blocks * 289 * 64 / (B * steps),
+            {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]})
 
 
 def serve_requests(serve, pools, n, rate, seed, lengths=(200, 3000)):
@@ -259,6 +299,7 @@ def main():
     ap.add_argument("--no-mix", action="store_true", help="skip the uneven-mix batched run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served runs")
     ap.add_argument("--serve-clips", type=int, default=32)
+    ap.add_argument("--no-stress", action="store_true", help="skip the 4K 10-bit sparse/dense runs")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
@@ -358,6 +399,22 @@ def main():
         extra["serve"] = {"workload": f"{args.serve_clips} clips of the uneven mix, length U{{200..3000}}, "
                                       f"Poisson arrivals at {args.serve_rate}/s (poisson) or all at once "
                                       "(archive); budget 90% of free HBM, 256 slots", **sv}
+    if not args.no_stress:
+        t1 = time.perf_counter()
+        c5 = torch.from_numpy(render_frames(("c5", 5, 600, 3840, 2160), 32, 3840, 2160, args.workers,
+                                            bits=10).astype(np.int16)).to("cuda:0")
+        torch.cuda.synchronize()
+        print(f"[bench] 4K 10-bit frames rendered in {time.perf_counter() - t1:.1f}s", file=sys.stderr, flush=True)
+        st = {"workload": "8 streams of 3840x2160 10-bit (uint16) 50i, low contrast, pans up to 64 px/frame, "
+                          "noise sigma 12, flashes every ~25 frames, k_max 4"}
+        for dense in (False, True):
+            sfps, adpf, skt = run_stress(vsa, c5, dict(params, k_max=4), 8, 200, 20, dense, torch)
+            st["dense" if dense else "sparse"] = {"fps": round(sfps, 1), "x_realtime": round(sfps / RT_FPS, 1),
+                                                  "absdiff_per_frame": round(adpf), "kernel_ms_per_step": skt}
+            print(f"[bench] 4K 10-bit {'dense' if dense else 'sparse'}: {sfps:.0f} frames/s, "
+                  f"{adpf / 1e6:.1f} M AD/frame", file=sys.stderr, flush=True)
+        extra["stress_10bit"] = st
+        del c5
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(frames, params, args.cpu_seconds)

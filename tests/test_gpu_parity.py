@@ -277,3 +277,43 @@ def test_engine_batched_mixed(vsa, orc, params):
         _cmp_records(e.poll_frames(s, 1000), r["frames"])
         _cmp_shots(e.poll_shots(s, 1000), r["shots"])
     e.close()
+
+
+def test_engine_2k_bench_config(vsa, orc, params):
+    """Full size, in the launch configuration the benchmark times: 64 streams of
+    2048x1080 8-bit in one engine, k_max 8, frames borrowed from device memory.
+    Three sampled streams are compared record by record with the oracle on the
+    same frame sequences (the oracle takes seconds per 2K stream)."""
+    import torch
+    import bench
+    F, B, S = 96, 64, 40
+    W, H = 2048, 1080
+    frames = bench.render_frames(("c2", 2, 1500, W, H), F, W, H, 16)
+    print("engine 2K x 64 streams", frames.shape, flush=True)
+    dev = torch.from_numpy(frames).to("cuda:0")
+    torch.cuda.synchronize()
+    p = dict(params, k_max=8)
+    e = vsa.Engine(max_streams=B, params=p)
+    sids = np.array([e.stream_open(W, H, 8) for _ in range(B)], np.int32)
+    offs = (np.arange(B) * 37) % F
+    base = np.uint64(dev.data_ptr())
+    pitches = np.full(B, W, np.int64)
+    for s in range(S):
+        ptrs = base + ((offs + s) % F).astype(np.uint64) * np.uint64(W * H)
+        assert e.stream_push_batch(sids, ptrs, pitches, vsa.SRC_DEVICE_BORROW, None) == 0
+        if s == S - 1:
+            for sid in sids:
+                e.stream_end(int(sid))
+        e.step()
+    guard = 0
+    while not all(e.stream_done(int(sid)) for sid in sids):
+        e.step()
+        e.sync()
+        guard += 1
+        assert guard < 100
+    for i in (0, 13, 63):
+        seq = np.ascontiguousarray(frames[(offs[i] + np.arange(S)) % F])
+        ref = orc.run_clip(seq, p)
+        _cmp_records(e.poll_frames(int(sids[i]), 1000), ref["frames"])
+        _cmp_shots(e.poll_shots(int(sids[i]), 1000), ref["shots"])
+    e.close()

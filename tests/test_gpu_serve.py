@@ -60,7 +60,8 @@ def test_served_mix_equals_alone(vsa, params, plain):
         F = dev.shape[0]
         length = int(rng.integers(12, 90))
         start = int(rng.integers(0, F))
-        reqs.append((serve.ClipRequest(cid, 0.002 * cid, dev, start, length, bits), host))
+        arrival = 0.0 if cid < 10 else 0.01     # most at once (they must queue), two mid-flight
+        reqs.append((serve.ClipRequest(cid, arrival, dev, start, length, bits), host))
     p = dict(params)
     # room for about three of the larger streams at once, and four slots
     big = vsa.Engine(max_streams=1, params=p)

@@ -15,10 +15,12 @@
 // [-8+4q, -5+4q] over all dx and one quarter of the dy = +8 row.
 // 8-bit: v_qsad_pk_u16_u8 gives the SADs of four consecutive dx from one
 // aligned 8-byte window (dx groups -8, -4, 0, +4), v_sad_u8 covers dx = +8, so
-// no byte alignment is ever needed in the search loop.  10-bit: v_sad_u16 on
+// no byte alignment is ever needed in the search loop; each J row a lane needs
+// is read from LDS once and used for all four of its dy.  10-bit: v_sad_u16 on
 // pairs of samples with a 2-byte realignment for odd dx.  Each candidate's key
-// is (SAD << 16 | rank) (8-bit) or (SAD << 9 | rank) (10-bit); the minimum
-// key is the unique argmin.  The epilogue reads the warped block from the same
+// is (SAD << 16) + code(dx, dy), where the code is strictly increasing in the
+// candidate order (|d|^2, dy, dx) and below 2^16, so the minimum key is the
+// unique argmin; the code is arithmetic, no table is read.  The epilogue reads the warped block from the same
 // LDS window and forms int32 moments per lane, reduced per tile to int64.
 // K3 sums the tile partials of each pair and forms the doubles in a fixed
 // order with no contraction.
@@ -29,10 +31,13 @@ namespace vsa {
 
 namespace {
 
-// Candidate order used to break SAD ties: rank[(dy+8)*17 + (dx+8)], and its
-// inverse as (dx+8) | (dy+8) << 8.  Built once on the host (see me_rank_tables).
-__constant__ uint16_t c_rank[kCand * kCand];
-__constant__ uint16_t c_unrank[kCand * kCand];
+// Tie-break code of candidate (dx, dy): ((dx^2 + dy^2) * 17 + dy + 8) * 17 +
+// dx + 8, the candidate's position in mixed radix, so codes increase strictly
+// in the order (|d|^2, dy, dx); at most 128 * 289 + 288 < 2^16.  Split into a
+// dx part and a dy part that add up to it.
+__host__ __device__ constexpr uint32_t code_dx(int dx) { return (uint32_t)(dx * dx * 289 + dx + 8); }
+__host__ __device__ constexpr uint32_t code_dy(int dy) { return (uint32_t)(dy * dy * 289 + (dy + 8) * 17); }
+static_assert(code_dx(8) + code_dy(8) < 65536u, "candidate code must fit 16 bits");
 
 constexpr int kJW8 = 80;   // J window row length (bytes, 8-bit)
 constexpr int kXcd = 8;    // accelerator complex dies, one L2 each
@@ -146,12 +151,11 @@ __device__ __forceinline__ uint64_t pk64(uint32_t lo, uint32_t hi) {
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
-// 8-bit search for one lane: returns the best key (SAD << 16 | rank).
+// 8-bit search for one lane: returns the best key (SAD << 16) + code(dx, dy).
 // The lane's four dy rows are visited one at a time (eight J rows each, read
 // from LDS), which keeps only five accumulators live; register pressure, not
 // LDS bandwidth, is what limits this kernel's occupancy.
-__device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, const uint16_t* rank, int bx,
-                                            int by, int q) {
+__device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
     uint32_t r0[8], r1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -160,49 +164,60 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
         r1[j] = v.y;
     }
     uint32_t best = 0xffffffffu;
-    const int dy0 = -8 + 4 * q;
+    // Two passes of two dy each (dy = -8+4q+i0+i, i = 0, 1): the nine J rows
+    // of a pass are each read from LDS once and used for both of its dy.
 #pragma unroll 1
-    for (int i = 0; i < 4; ++i) {
-        // J rows (window coords) 8*by + 4q + i + j, j = 0..7
-        const uint8_t* jb = sJ + (8 * by + 4 * q + i) * kJW8 + 8 * bx;
-        uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        uint32_t a8 = 0;
+    for (int i0 = 0; i0 < 4; i0 += 2) {
+        // acc[i][g]: four packed SADs of dx = -8+4g .. -5+4g; a8[i]: dx = +8
+        uint64_t acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+        uint32_t a8[2] = {0, 0};
+        const uint8_t* jb = sJ + (8 * by + 4 * q + i0) * kJW8 + 8 * bx;
+        uint32_t off = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint2 a = *reinterpret_cast<const uint2*>(jb + j * kJW8);
-            const uint2 b = *reinterpret_cast<const uint2*>(jb + j * kJW8 + 8);
-            const uint2 c = *reinterpret_cast<const uint2*>(jb + j * kJW8 + 16);
+        for (int u = 0; u < 9; ++u) {      // J row u pairs with block row j = u - i
+            // the row's address passes through an empty asm that reads the
+            // previous row's sum, so later rows are not hoisted into registers
+            if (u > 0) asm volatile("" : "+v"(off) : "v"(a8[0]));
+            const uint2 a = *reinterpret_cast<const uint2*>(jb + off);
+            const uint2 b = *reinterpret_cast<const uint2*>(jb + off + 8);
+            const uint2 c = *reinterpret_cast<const uint2*>(jb + off + 16);
+            off += kJW8;
             const uint64_t w01 = pk64(a.x, a.y), w12 = pk64(a.y, b.x), w23 = pk64(b.x, b.y);
             const uint64_t w34 = pk64(b.y, c.x), w45 = pk64(c.x, c.y);
-            a0 = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], a0);
-            a0 = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], a0);
-            a1 = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], a1);
-            a1 = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], a1);
-            a2 = __builtin_amdgcn_qsad_pk_u16_u8(w23, r0[j], a2);
-            a2 = __builtin_amdgcn_qsad_pk_u16_u8(w34, r1[j], a2);
-            a3 = __builtin_amdgcn_qsad_pk_u16_u8(w34, r0[j], a3);
-            a3 = __builtin_amdgcn_qsad_pk_u16_u8(w45, r1[j], a3);
-            a8 = __builtin_amdgcn_sad_u8(c.x, r0[j], a8);
-            a8 = __builtin_amdgcn_sad_u8(c.y, r1[j], a8);
-        }
-        const uint16_t* rk = rank + (dy0 + i + kRadius) * kCand;
-        const uint64_t acc[4] = {a0, a1, a2, a3};
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const uint32_t lo = (uint32_t)acc[g], hi = (uint32_t)(acc[g] >> 32);
-            const uint32_t k0 = (lo << 16) | rk[4 * g + 0];
-            const uint32_t k1 = (lo & 0xffff0000u) | rk[4 * g + 1];
-            const uint32_t k2 = (hi << 16) | rk[4 * g + 2];
-            const uint32_t k3 = (hi & 0xffff0000u) | rk[4 * g + 3];
-            best = min(best, min(k0, k1));
-            best = min(best, min(k2, k3));
+            for (int i = 0; i < 2; ++i) {
+                const int j = u - i;
+                if (j < 0 || j > 7) continue;
+                acc[i][0] = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], acc[i][0]);
+                acc[i][0] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], acc[i][0]);
+                acc[i][1] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], acc[i][1]);
+                acc[i][1] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], acc[i][1]);
+                acc[i][2] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r0[j], acc[i][2]);
+                acc[i][2] = __builtin_amdgcn_qsad_pk_u16_u8(w34, r1[j], acc[i][2]);
+                acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w34, r0[j], acc[i][3]);
+                acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w45, r1[j], acc[i][3]);
+                a8[i] = __builtin_amdgcn_sad_u8(c.x, r0[j], a8[i]);
+                a8[i] = __builtin_amdgcn_sad_u8(c.y, r1[j], a8[i]);
+            }
         }
-        best = min(best, (a8 << 16) | rk[16]);
+        // keys: the dx part of the code is a constant per candidate, the dy
+        // part is added once per row (adding a constant keeps the row's argmin)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            uint32_t rb = (a8[i] << 16) + code_dx(8);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const uint32_t lo = (uint32_t)acc[i][g], hi = (uint32_t)(acc[i][g] >> 32);
+                rb = min(rb, min((lo << 16) + code_dx(-8 + 4 * g), (lo & 0xffff0000u) + code_dx(-7 + 4 * g)));
+                rb = min(rb, min((hi << 16) + code_dx(-6 + 4 * g), (hi & 0xffff0000u) + code_dx(-5 + 4 * g)));
+            }
+            best = min(best, rb + code_dy(-8 + 4 * q + i0 + i));
+        }
     }
     // dy = +8 row, dx group q (dx = -8+4q .. -5+4q); lane q = 3 also dx = +8
     {
         uint64_t a4 = 0;
-        uint32_t a8 = 0;
+        uint32_t e8 = 0;
         const uint8_t* jr = sJ + (8 * by + 16) * kJW8 + 8 * bx + 4 * q;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -211,21 +226,21 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
             const uint32_t e2 = *reinterpret_cast<const uint32_t*>(jr + j * kJW8 + 8);
             a4 = __builtin_amdgcn_qsad_pk_u16_u8(pk64(e0, e1), r0[j], a4);
             a4 = __builtin_amdgcn_qsad_pk_u16_u8(pk64(e1, e2), r1[j], a4);
-            a8 = __builtin_amdgcn_sad_u8(e1, r0[j], a8);
-            a8 = __builtin_amdgcn_sad_u8(e2, r1[j], a8);
+            e8 = __builtin_amdgcn_sad_u8(e1, r0[j], e8);
+            e8 = __builtin_amdgcn_sad_u8(e2, r1[j], e8);
         }
-        const uint16_t* rk = rank + (2 * kRadius) * kCand + 4 * q;
+        const int dx0 = -8 + 4 * q;
         const uint32_t lo = (uint32_t)a4, hi = (uint32_t)(a4 >> 32);
-        best = min(best, min((lo << 16) | rk[0], (lo & 0xffff0000u) | rk[1]));
-        best = min(best, min((hi << 16) | rk[2], (hi & 0xffff0000u) | rk[3]));
-        if (q == 3) best = min(best, (a8 << 16) | rank[(2 * kRadius) * kCand + 16]);
+        uint32_t rb = min((lo << 16) + code_dx(dx0), (lo & 0xffff0000u) + code_dx(dx0 + 1));
+        rb = min(rb, min((hi << 16) + code_dx(dx0 + 2), (hi & 0xffff0000u) + code_dx(dx0 + 3)));
+        if (q == 3) rb = min(rb, (e8 << 16) + code_dx(8));
+        best = min(best, rb + code_dy(8));
     }
     return best;
 }
 
-// 10-bit search for one lane: returns the best key (SAD << 9 | rank).
-__device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* sJ, const uint16_t* rank, int bx,
-                                             int by, int q) {
+// 10-bit search for one lane: returns the best key (SAD << 16) + code(dx, dy).
+__device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
     // ref block: 8 rows x 4 dwords (2 samples each)
     uint32_t rf[8][4];
 #pragma unroll
@@ -238,7 +253,6 @@ __device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* s
     const int ndy = (q == 3) ? 5 : 4;
     for (int i = 0; i < ndy; ++i) {
         const int dy = -8 + 4 * q + i;
-        const uint16_t* rk = rank + (dy + kRadius) * kCand;
         uint32_t acc[kCand];
 #pragma unroll
         for (int k = 0; k < kCand; ++k) acc[k] = 0;
@@ -267,8 +281,10 @@ __device__ __forceinline__ uint32_t search16(const uint8_t* sI, const uint8_t* s
                 acc[dx + 8] = a;
             }
         }
+        uint32_t rb = 0xffffffffu;
 #pragma unroll
-        for (int k = 0; k < kCand; ++k) best = min(best, (acc[k] << 9) | rk[k]);
+        for (int k = 0; k < kCand; ++k) rb = min(rb, (acc[k] << 16) + code_dx(k - kRadius));
+        best = min(best, rb + code_dy(dy));
     }
     return best;
 }
@@ -352,8 +368,7 @@ __device__ __forceinline__ int32_t rows_sad(const uint8_t* sI, const uint8_t* sJ
 
 template <typename T>
 __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, TilePartial* part_out,
-                        int8_t* mv_out, int32_t* sad_out, uint8_t* sI, uint8_t* sJ, const uint16_t* rank,
-                        int64_t* red) {
+                        int8_t* mv_out, int32_t* sad_out, uint8_t* sI, uint8_t* sJ, int64_t* red) {
     const PlaneRef I = plane_of(sd, tk.ref, tk.ref_field, tk.level);
     const PlaneRef J = plane_of(sd, tk.oth, tk.oth_field, tk.level);
     const int nbx = I.w / kBlock, nby = I.h / kBlock;
@@ -370,16 +385,15 @@ __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, Til
     if (!(tk.flags & TF_ZERO_MV)) {
         uint32_t key = 0xffffffffu;
         if (valid) {
-            if constexpr (sizeof(T) == 1) key = search8(sI, sJ, rank, bx, by, q);
-            else key = search16(sI, sJ, rank, bx, by, q);
+            if constexpr (sizeof(T) == 1) key = search8(sI, sJ, bx, by, q);
+            else key = search16(sI, sJ, bx, by, q);
         }
         key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
         key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
-        const uint32_t rank = key & (sizeof(T) == 1 ? 0xffffu : 0x1ffu);
         if (valid) {
-            const uint32_t u = c_unrank[rank];
-            dx = (int)(u & 0xff) - kRadius;
-            dy = (int)(u >> 8) - kRadius;
+            const uint32_t cell = (key & 0xffffu) % (uint32_t)(kCand * kCand);   // (dy+8)*17 + dx+8
+            dx = (int)(cell % kCand) - kRadius;
+            dy = (int)(cell / kCand) - kRadius;
         }
     }
     int32_t m[5] = {0, 0, 0, 0, 0};
@@ -439,9 +453,6 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
     __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
     __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
     __shared__ int64_t red[4 * 6];
-    __shared__ uint16_t rank[kCand * kCand];
-    for (int i = threadIdx.x; i < kCand * kCand; i += kMEThreads) rank[i] = c_rank[i];
-    __syncthreads();
     const unsigned long long tt = cur ? cur->sparse_tt[par_prev].v : 0ull;
     const int n_sparse = tt_tasks(tt);
     const int total = consec_tiles + tt_tiles(tt);
@@ -478,7 +489,7 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
         if (tk->flags & TF_MV_RING) mv = sd.mv + (int64_t)(tk->ref % sd.rs) * sd.B_L * 2;
         else if (tk->flags & TF_DEBUG) mv = dbg_mv;
         me_tile<T>(sd, *tk, local, partials + tile, mv, (tk->flags & TF_DEBUG) ? dbg_sad : nullptr,
-                   sI, sJ, rank, red);
+                   sI, sJ, red);
     }
 }
 
@@ -546,31 +557,6 @@ __global__ void k_finish_debug(const int64_t* __restrict__ ints, int64_t n, doub
     double f[4];
     finish_pair(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], a0, f);
     out[4 * i] = f[0]; out[4 * i + 1] = f[1]; out[4 * i + 2] = f[2]; out[4 * i + 3] = f[3];
-}
-
-hipError_t me_init_tables() {
-    // rank of (dx, dy) in the order (dx^2 + dy^2, dy, dx)
-    uint16_t rank[kCand * kCand], unrank[kCand * kCand];
-    int order[kCand * kCand];
-    for (int i = 0; i < kCand * kCand; ++i) order[i] = i;
-    auto keyf = [](int i) {
-        const int dx = i % kCand - kRadius, dy = i / kCand - kRadius;
-        return ((dx * dx + dy * dy) * 64 + (dy + kRadius)) * 64 + (dx + kRadius);
-    };
-    for (int i = 1; i < kCand * kCand; ++i) {   // insertion sort, 289 entries
-        const int v = order[i];
-        int j = i - 1;
-        while (j >= 0 && keyf(order[j]) > keyf(v)) { order[j + 1] = order[j]; --j; }
-        order[j + 1] = v;
-    }
-    for (int r = 0; r < kCand * kCand; ++r) {
-        const int i = order[r];
-        rank[i] = (uint16_t)r;
-        unrank[r] = (uint16_t)((i % kCand) | ((i / kCand) << 8));
-    }
-    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_rank), rank, sizeof rank);
-    if (e != hipSuccess) return e;
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_unrank), unrank, sizeof unrank);
 }
 
 hipError_t launch_me(int bits, const StreamDesc* sds, const PairTask* consec, int32_t n_consec,

@@ -46,7 +46,6 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t 
 hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
                           hipStream_t);
 int pyramid_tiles(const StreamDesc& sd);
-hipError_t me_init_tables();
 hipError_t launch_me(int bits, const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
                      const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid, int32_t par_prev, hipStream_t);
 hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
@@ -502,7 +501,6 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     HIPCK(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
     if (cfg->device < 0 || cfg->device >= ndev) return fail(VSA_E_INVAL, "no such device");
     HIPCK(hipSetDevice(cfg->device), "hipSetDevice");
-    HIPCK(me_init_tables(), "motion-search tables");
     vsa_engine* e = new vsa_engine();
     e->device = cfg->device;
     e->params = p;
@@ -1215,7 +1213,6 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     const int maxv = bits == 8 ? 255 : 1023;
     for (int64_t i = 0; i < (int64_t)w * h; ++i)
         if (I[i] > maxv || J[i] > maxv) return fail(VSA_E_INVAL, "sample out of range");
-    HIPCK(me_init_tables(), "motion-search tables");
     StreamDesc sd;
     std::memset(&sd, 0, sizeof sd);
     sd.active = 1; sd.W = w; sd.H = h; sd.bits = bits; sd.L = 0; sd.Lcap = 0; sd.Lf = 0; sd.ltop = 0;

@@ -87,10 +87,13 @@ typedef struct {
     int32_t max_streams;       /* stream slots (1..1024)                                    */
     uint64_t hbm_budget_bytes; /* admission budget; 0 = 90% of free device memory at create */
     int32_t schedule;          /* VSA_SCHEDULE_SPARSE (the paper's) or VSA_SCHEDULE_DENSE   */
-    int32_t use_graph;         /* 1: replay each time step as a captured HIP graph          */
+    int32_t use_graph;         /* must be 0: a captured HIP graph of a step costs more host
+                                  time per replay than its direct launches (VSA_E_UNSUPPORTED) */
     const vsa_params* params;  /* NULL = built-in defaults (vsa_default_params)             */
     int32_t debug_log;         /* 1: keep a log of every sparse measure computed            */
-    int32_t me_tile;           /* reserved, must be 0                                       */
+    int32_t me_wgs_per_cu;     /* persistent motion-search workgroups per compute unit:
+                                  0 = autotuned per step size, else 1..8 (results do not
+                                  depend on it)                                              */
     int32_t profile;           /* time kernel launches with HIP events (see
                                   vsa_engine_kernel_times): 1 pyramid and motion search,
                                   2 every kernel and the whole step; 0 off                   */

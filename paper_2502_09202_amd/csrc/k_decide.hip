@@ -408,7 +408,8 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     int32_t n_steps, DecideParams dp, const TilePartial* __restrict__ partials, int32_t consec_tiles,
     const PairTask* __restrict__ sparse_prev, PairTask* __restrict__ sparse_next, DeviceCursors* __restrict__ cur,
     OutFrame* __restrict__ out_frames, uint64_t frames_cap, OutShot* __restrict__ out_shots, uint64_t shots_cap,
-    int32_t* __restrict__ log, int64_t log_cap, vsa_shot_result* __restrict__ closed_buf, int32_t par) {
+    int32_t* __restrict__ log, int64_t log_cap, vsa_shot_result* __restrict__ closed_buf, int32_t par,
+    PubSnap* __restrict__ snap, TileJob* __restrict__ sjobs_next, int32_t* __restrict__ smap_next) {
     struct Bcast {
         FrameInfo* info;
         int32_t rs, sid, epoch, e0, nframes, nshots, ntasks, tiles, blocks;
@@ -551,6 +552,9 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
             t.tile_prefix = tile;
             tile += t.tiles;
             sparse_next[b.task + q] = t;
+            // the next step's motion search finds the task's tiles through these
+            sjobs_next[b.task + q] = make_tile_job(sd, t, nullptr);
+            for (int k = 0; k < t.tiles; ++k) smap_next[t.tile_prefix + k] = b.task + q;
             log_task(slog, log_cap, st, t);
         }
         st.sp_base = b.task;
@@ -558,20 +562,38 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         st.emitted = st.t;
         states[sid] = st;
     }
-    if (!active) return;
     // 4. records out, the whole wave
-    const Bcast& b = bc[wave];
-    for (int q = lane; q < b.nframes; q += 64) {
-        OutFrame& o = out_frames[(b.fbase + (uint64_t)q) % frames_cap];
-        o.sid = b.sid;
-        o.pad = b.epoch;   // lets the host drop records of a slot's earlier stream
-        fill_record(o.r, b.info[(b.e0 + q) % b.rs]);
+    if (active) {
+        const Bcast& b = bc[wave];
+        for (int q = lane; q < b.nframes; q += 64) {
+            OutFrame& o = out_frames[(b.fbase + (uint64_t)q) % frames_cap];
+            o.sid = b.sid;
+            o.pad = b.epoch;   // lets the host drop records of a slot's earlier stream
+            fill_record(o.r, b.info[(b.e0 + q) % b.rs]);
+        }
+        if (lane < b.nshots) {
+            OutShot& o = out_shots[(b.sbase + (uint64_t)lane) % shots_cap];
+            o.sid = b.sid;
+            o.pad = b.epoch;   // lets the host drop records of a slot's earlier stream
+            o.r = closed_buf[(int64_t)b.sid * kMaxClosed + lane];
+        }
     }
-    if (lane < b.nshots) {
-        OutShot& o = out_shots[(b.sbase + (uint64_t)lane) % shots_cap];
-        o.sid = b.sid;
-        o.pad = b.epoch;   // lets the host drop records of a slot's earlier stream
-        o.r = closed_buf[(int64_t)b.sid * kMaxClosed + lane];
+    // 5. the last workgroup to finish publishes the step's cursors: every
+    //    reservation (and every record) of the step precedes its count
+    __syncthreads();
+    if (snap && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long done = atomicAdd(&cur->blocks_done.v, 1ull);
+        if (done == (unsigned long long)gridDim.x - 1) {
+            __threadfence();
+            PubSnap p;
+            p.frames_written = atomicAdd(&cur->frames_written.v, 0ull);
+            p.shots_written = atomicAdd(&cur->shots_written.v, 0ull);
+            p.sparse_run = atomicAdd(&cur->sparse_run.v, 0ull);
+            p.sparse_blocks = atomicAdd(&cur->sparse_blocks.v, 0ull);
+            *snap = p;
+            atomicExch(&cur->blocks_done.v, 0ull);
+        }
     }
 }
 
@@ -646,12 +668,12 @@ hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, cons
                                 const PairTask* sparse_prev, PairTask* sparse_next, DeviceCursors* cur,
                                 OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots, uint64_t shots_cap,
                                 int32_t* log, int64_t log_cap, vsa_shot_result* closed_buf, int32_t par,
-                                hipStream_t s) {
+                                PubSnap* snap, TileJob* sjobs_next, int32_t* smap_next, hipStream_t s) {
     if (n_steps <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish_decide, dim3((n_steps + kDecideWaves - 1) / kDecideWaves), dim3(64 * kDecideWaves), 0,
                        s, sds, states, steps, n_steps, dp,
                        partials, consec_tiles, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
-                       shots_cap, log, log_cap, closed_buf, par);
+                       shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
     return hipGetLastError();
 }
 

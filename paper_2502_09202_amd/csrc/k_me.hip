@@ -342,15 +342,6 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 }
 
 // Locate the task owning global tile `tile` in a prefix-sorted task list.
-__device__ __forceinline__ int find_task(const PairTask* tasks, int n, int tile) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tasks[mid].tile_prefix <= tile) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // SAD of one lane's two block rows at displacement (dx, dy) (debug output only).
 template <typename T>
 __device__ __forceinline__ int32_t rows_sad(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q,
@@ -367,12 +358,12 @@ __device__ __forceinline__ int32_t rows_sad(const uint8_t* sI, const uint8_t* sJ
 }
 
 template <typename T>
-__device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, TilePartial* part_out,
-                        int8_t* mv_out, int32_t* sad_out, uint8_t* sI, uint8_t* sJ, int64_t* red) {
-    const PlaneRef I = plane_of(sd, tk.ref, tk.ref_field, tk.level);
-    const PlaneRef J = plane_of(sd, tk.oth, tk.oth_field, tk.level);
+__device__ void me_tile(const TileJob& jb, int local, TilePartial* part_out, int8_t* mv_out, int32_t* sad_out,
+                        uint8_t* sI, uint8_t* sJ, int64_t* red) {
+    const PlaneRef I{jb.I, jb.w, jb.h, jb.pitch, jb.cos_I};
+    const PlaneRef J{jb.J, jb.w, jb.h, jb.pitch, jb.cos_J};
     const int nbx = I.w / kBlock, nby = I.h / kBlock;
-    const int tiles_x = div_up(nbx, kTBX);
+    const int tiles_x = jb.tiles_x;
     const int bx0 = (local % tiles_x) * kTBX, by0 = (local / tiles_x) * kTBY;
     stage_I<T>(I, bx0, by0, sI);
     stage_J<T>(J, bx0, by0, sJ);
@@ -382,7 +373,7 @@ __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, Til
     const int bx = b & (kTBX - 1), by = b >> 3;
     const bool valid = (bx0 + bx < nbx) && (by0 + by < nby);
     int dx = 0, dy = 0;
-    if (!(tk.flags & TF_ZERO_MV)) {
+    if (!(jb.flags & TF_ZERO_MV)) {
         uint32_t key = 0xffffffffu;
         if (valid) {
             if constexpr (sizeof(T) == 1) key = search8(sI, sJ, bx, by, q);
@@ -442,8 +433,10 @@ __device__ void me_tile(const StreamDesc& sd, const PairTask& tk, int local, Til
 // One launch per sample width; tiles of the other width are skipped.
 template <typename T>
 __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restrict__ sds,
-                                                   const PairTask* __restrict__ consec, int32_t n_consec,
-                                                   int32_t consec_tiles, const PairTask* __restrict__ sparse,
+                                                   const TileJob* __restrict__ cjobs, int32_t n_cjobs,
+                                                   const int32_t* __restrict__ cmap, int32_t consec_tiles,
+                                                   const TileJob* __restrict__ sjobs, int32_t n_sjobs,
+                                                   const int32_t* __restrict__ smap,
                                                    const DeviceCursors* __restrict__ cur,
                                                    TilePartial* __restrict__ partials, int8_t* dbg_mv,
                                                    int32_t* dbg_sad, int32_t par_prev,
@@ -454,7 +447,6 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
     __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
     __shared__ int64_t red[4 * 6];
     const unsigned long long tt = cur ? cur->sparse_tt[par_prev].v : 0ull;
-    const int n_sparse = tt_tasks(tt);
     const int total = consec_tiles + tt_tiles(tt);
     // Workgroups are dispatched round-robin over the XCDs, each with its own
     // L2: workgroup b runs on XCD b % kXcd.  Each XCD walks one contiguous
@@ -471,25 +463,27 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
         first = lo + j;
         stride = groups;
     }
+    // A tile's job: map entry, then the job (the next tile's map entry is
+    // loaded one iteration ahead).  Consecutive pairs come first in the tile
+    // list, their jobs built by this step's pyramid kernel; the sparse pairs'
+    // jobs were built by the previous step's decision kernel.
+    int idx_next = 0;
+    if (first < hi) idx_next = first < consec_tiles ? cmap[first] : smap[first - consec_tiles];
     for (int tile = first; tile < hi; tile += stride) {
-        const PairTask* tk;
-        int local;
-        if (tile < consec_tiles) {
-            tk = consec + find_task(consec, n_consec, tile);
-            local = tile - tk->tile_prefix;
-        } else {
-            const int st = tile - consec_tiles;
-            tk = sparse + find_task(sparse, n_sparse, st);
-            local = st - tk->tile_prefix;
+        const int idx = idx_next;
+        const int nt = tile + stride;
+        if (nt < hi) idx_next = nt < consec_tiles ? cmap[nt] : smap[nt - consec_tiles];
+        const bool consec = tile < consec_tiles;
+        if (idx < 0 || idx >= (consec ? n_cjobs : n_sjobs)) continue;   // never expected; keeps reads in bounds
+        const TileJob& jb = consec ? cjobs[idx] : sjobs[idx];
+        const int local = (consec ? tile : tile - consec_tiles) - jb.tile_prefix;
+        if (jb.bits != (sizeof(T) == 1 ? 8 : 10)) continue;
+        if (!consec) {
+            const StreamDesc& sd = sds[jb.sid];
+            if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
         }
-        const StreamDesc& sd = sds[tk->sid];
-        if (!sd.active || sd.epoch != tk->epoch) continue;   // stream closed since planning
-        if (sd.bits != (sizeof(T) == 1 ? 8 : 10)) continue;
-        int8_t* mv = nullptr;
-        if (tk->flags & TF_MV_RING) mv = sd.mv + (int64_t)(tk->ref % sd.rs) * sd.B_L * 2;
-        else if (tk->flags & TF_DEBUG) mv = dbg_mv;
-        me_tile<T>(sd, *tk, local, partials + tile, mv, (tk->flags & TF_DEBUG) ? dbg_sad : nullptr,
-                   sI, sJ, red);
+        const bool dbg = (jb.flags & TF_DEBUG) != 0;
+        me_tile<T>(jb, local, partials + tile, dbg ? dbg_mv : jb.mv, dbg ? dbg_sad : nullptr, sI, sJ, red);
     }
 }
 
@@ -559,19 +553,19 @@ __global__ void k_finish_debug(const int64_t* __restrict__ ints, int64_t n, doub
     out[4 * i] = f[0]; out[4 * i + 1] = f[1]; out[4 * i + 2] = f[2]; out[4 * i + 3] = f[3];
 }
 
-hipError_t launch_me(int bits, const StreamDesc* sds, const PairTask* consec, int32_t n_consec,
-                     int32_t consec_tiles, const PairTask* sparse, const DeviceCursors* cur,
-                     TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid, int32_t par_prev,
-                     hipStream_t s) {
+hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* cjobs, int32_t n_cjobs, const int32_t* cmap,
+                     int32_t consec_tiles, const TileJob* sjobs, int32_t n_sjobs, const int32_t* smap,
+                     const DeviceCursors* cur, TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid,
+                     int32_t par_prev, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     unsigned long long* clear_tt =
         cur ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
     if (bits == 8)
-        hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
-                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
+        hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, cjobs, n_cjobs, cmap, consec_tiles,
+                           sjobs, n_sjobs, smap, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
     else
-        hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, consec, n_consec,
-                           consec_tiles, sparse, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
+        hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, cjobs, n_cjobs, cmap, consec_tiles,
+                           sjobs, n_sjobs, smap, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
     return hipGetLastError();
 }
 

@@ -268,7 +268,8 @@ __device__ __forceinline__ void init_frame_info(const StreamDesc& sd, const Step
 template <typename T, int L>
 __global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ sds,
                                                   const StepStream* __restrict__ steps,
-                                                  const int32_t* __restrict__ k1_list, int32_t n_k1) {
+                                                  const int32_t* __restrict__ k1_list, int32_t n_k1,
+                                                  TileJob* __restrict__ cjobs, int32_t* __restrict__ cmap) {
     __shared__ uint16_t lds[2 * kPyrTW * kPyrTH];
     const int tile = blockIdx.x;
     // locate the stream: last list entry whose first tile is <= tile
@@ -281,7 +282,23 @@ __global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ 
     const int local = tile - ss.k1_prefix;
     if (local < 0 || local >= ss.k1_tiles) return;
     const StreamDesc& sd = sds[ss.sid];
-    if (local == 0 && threadIdx.x == 0) init_frame_info(sd, ss);
+    if (local == 0) {
+        if (threadIdx.x == 0) init_frame_info(sd, ss);
+        // the motion-search job of this step's consecutive pair (frame-1 ->
+        // frame) and the map from its tiles to that job
+        if (cjobs && ss.has_frame && ss.consec_tiles > 0) {
+            const int i = k1_list[lo];
+            if (threadIdx.x == 0) {
+                PairTask t;
+                t.sid = ss.sid; t.kind = MK_CONSEC; t.ref = ss.frame - 1; t.oth = ss.frame;
+                t.ref_field = t.oth_field = PL_FRAME; t.level = sd.L; t.result = -1;
+                t.tiles = ss.consec_tiles; t.tile_prefix = ss.consec_prefix; t.flags = TF_MV_RING;
+                t.epoch = sd.epoch;
+                cjobs[i] = make_tile_job(sd, t, sd.mv + (int64_t)(t.ref % sd.rs) * sd.B_L * 2);
+            }
+            for (int k = threadIdx.x; k < ss.consec_tiles; k += 256) cmap[ss.consec_prefix + k] = i;
+        }
+    }
     pyramid_tile<T, L>(sd, ss, local, lds);
 }
 
@@ -306,10 +323,10 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t 
 
 // Launch the pyramid for one group of streams sharing sample width and L.
 hipError_t launch_pyramid(int bits, int L, const StreamDesc* sds, const StepStream* steps, const int32_t* k1_list,
-                          int32_t n_k1, int32_t total_tiles, hipStream_t s) {
+                          int32_t n_k1, int32_t total_tiles, TileJob* cjobs, int32_t* cmap, hipStream_t s) {
     if (n_k1 <= 0 || total_tiles <= 0) return hipSuccess;
     const dim3 g(total_tiles), b(256);
-#define VSA_PYR(TT, LL) hipLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, sds, steps, k1_list, n_k1)
+#define VSA_PYR(TT, LL) hipLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, sds, steps, k1_list, n_k1, cjobs, cmap)
     if (bits == 8) {
         switch (L) {
             case 0: VSA_PYR(uint8_t, 0); break;

@@ -168,6 +168,13 @@ struct DeviceCursors {
     DeviceCounter sparse_tt[2];
     DeviceCounter sparse_run;        // total sparse tasks planned
     DeviceCounter sparse_blocks;     // total 8x8 blocks of those tasks
+    DeviceCounter blocks_done;       // workgroups of the running decision kernel that finished
+};
+
+// Output cursors as of the end of one step, written by the last workgroup of
+// the step's decision kernel into mapped host memory (what vsa_collect reads).
+struct PubSnap {
+    uint64_t frames_written, shots_written, sparse_run, sparse_blocks;
 };
 
 __host__ __device__ inline int tt_tasks(unsigned long long v) { return (int)(v >> 32); }
@@ -181,6 +188,53 @@ constexpr int kMEThreads = 256;
 inline __host__ __device__ int div_up(int a, int b) { return (a + b - 1) / b; }
 inline __host__ __device__ int me_tiles(int w, int h) {
     return div_up(w / kBlock, kTBX) * div_up(h / kBlock, kTBY);
+}
+
+// Everything a motion-search tile needs from its pair, resolved once per pair
+// by the pair's producer (the pyramid kernel for the consecutive pair of a
+// step, the decision kernel for the sparse pairs it plans), so that a tile is
+// found with two loads: the tile's job index from a per-tile map, then the job.
+struct TileJob {
+    const uint8_t* I;                 // reference plane (its blocks tile the search)
+    const uint8_t* J;                 // searched plane
+    int8_t* mv;                       // motion-field destination, or null
+    int32_t w, h, pitch;              // plane size and row pitch (samples), same for I and J
+    int32_t cos_I, cos_J;             // 0, or Lf + 1: the lower field read on the upper field's rows
+    int32_t tiles_x;                  // tiles per row of the plane
+    int32_t tile_prefix;              // first tile of the pair within its list
+    int32_t flags;                    // TF_*
+    int32_t sid, epoch;               // stream and its epoch when planned
+    int32_t bits;                     // 8 or 10
+};
+
+// Job of pair t of stream sd (mv: the motion-field destination).
+inline __host__ __device__ TileJob make_tile_job(const StreamDesc& sd, const PairTask& t, int8_t* mv) {
+    TileJob j;
+    const int64_t sref = (int64_t)(t.ref % sd.rs) * sd.slot_bytes;
+    const int64_t soth = (int64_t)(t.oth % sd.rs) * sd.slot_bytes;
+    if (t.ref_field != PL_FRAME) {
+        const int64_t oref = t.ref_field == PL_UPPER ? sd.offU : sd.offD;
+        const int64_t ooth = t.oth_field == PL_UPPER ? sd.offU : sd.offD;
+        j.I = sd.ring + sref + oref;
+        j.J = sd.ring + soth + ooth;
+        j.w = sd.wf; j.h = sd.hf; j.pitch = sd.pf;
+        j.cos_I = t.ref_field == PL_LOWER ? sd.Lf + 1 : 0;
+        j.cos_J = t.oth_field == PL_LOWER ? sd.Lf + 1 : 0;
+    } else {
+        const int d = t.level - sd.L;
+        j.I = sd.ring + sref + sd.off[d];
+        j.J = sd.ring + soth + sd.off[d];
+        j.w = sd.wl[d]; j.h = sd.hl[d]; j.pitch = sd.pl[d];
+        j.cos_I = j.cos_J = 0;
+    }
+    j.mv = mv;
+    j.tiles_x = div_up(j.w / kBlock, kTBX);
+    j.tile_prefix = t.tile_prefix;
+    j.flags = t.flags;
+    j.sid = t.sid;
+    j.epoch = t.epoch;
+    j.bits = sd.bits;
+    return j;
 }
 
 // Per-tile partial sums of a pair (exact integers).

@@ -44,10 +44,11 @@
 namespace vsa {
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
 hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
-                          hipStream_t);
+                          TileJob*, int32_t*, hipStream_t);
 int pyramid_tiles(const StreamDesc& sd);
-hipError_t launch_me(int bits, const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
-                     const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid, int32_t par_prev, hipStream_t);
+hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t, const TileJob*,
+                     int32_t, const int32_t*, const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid,
+                     int32_t par_prev, hipStream_t);
 hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
                          DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
                          double*, int grid, int32_t par_prev, hipStream_t);
@@ -55,7 +56,7 @@ hipError_t launch_finish_debug(const int64_t*, int64_t, double, double*, hipStre
 hipError_t launch_finish_decide(const StreamDesc*, DecideState*, const StepStream*, int32_t, const DecideParams&,
                                 const TilePartial*, int32_t, const PairTask*, PairTask*, DeviceCursors*, OutFrame*,
                                 uint64_t, OutShot*, uint64_t, int32_t*, int64_t, vsa_shot_result*, int32_t,
-                                hipStream_t);
+                                PubSnap*, TileJob*, int32_t*, hipStream_t);
 hipError_t launch_decide_replay(const StreamDesc&, DecideState*, PairResult*, const DecideParams&, int32_t,
                                 const double*, const double*, const uint8_t*, const double*, const double*,
                                 const double*, const double*, vsa_frame_result*, vsa_shot_result*, int32_t,
@@ -95,6 +96,10 @@ constexpr int kDescRing = 8;
 // Cursor snapshots, one per step (a ring): the host may run at most kDescRing
 // steps ahead of the device, so a snapshot is never rewritten while it is read.
 constexpr int kSnap = 64;
+constexpr int kTuneN = 5;
+constexpr int kTuneWgs[kTuneN] = {2, 3, 4, 6, 8};
+constexpr int kTuneSamples = 4;
+constexpr int kTuneRing = 16;
 constexpr int64_t kLogCapPerStream = 1 << 16;
 
 int ceil_log2(int k) {
@@ -246,6 +251,13 @@ struct vsa_engine {
     OutShot* d_out_shots = nullptr;
     TilePartial* d_partials = nullptr;
     int64_t partials_cap = 0;
+    // motion-search jobs and tile maps: the consecutive pairs' per step slot
+    // (written by the pyramid kernel), the sparse pairs' per step parity
+    // (written by the decision kernel); maps hold partials_cap entries each
+    TileJob* d_cjobs = nullptr;        // (kAhead + 1) x max_streams
+    TileJob* d_sjobs = nullptr;        // 2 x max_streams x kMaxTasksPerStream
+    int32_t* d_cmap = nullptr;         // (kAhead + 1) x partials_cap
+    int32_t* d_smap = nullptr;         // 2 x partials_cap
     int32_t* d_log = nullptr;
     // step descriptors: device buffer + pinned host ring
     uint8_t* d_desc = nullptr;     // two step descriptors (alternating steps)
@@ -264,9 +276,11 @@ struct vsa_engine {
     OutFrame* h_out_frames = nullptr;  // output rings in mapped pinned memory; the
     OutShot* h_out_shots = nullptr;    // decision kernel writes them through d_out_*
     uint64_t pushed_since_drain = 0;   // frames ingested after the newest published step
-    // non-blocking publication: after its decisions each step copies the
-    // cursors into h_snap[step % kSnap] and records pub_ev of that slot
-    DeviceCursors* h_snap = nullptr;
+    // non-blocking publication: the decision kernel of each step writes the
+    // output cursors into h_snap[step % kSnap] (mapped pinned memory, through
+    // d_snap) and pub_ev of that slot is recorded after it
+    PubSnap* h_snap = nullptr;
+    PubSnap* d_snap = nullptr;
     hipEvent_t pub_ev[kSnap] = {};
     uint64_t pushed_cum[kSnap] = {};   // frames ingested up to and including each step
     uint64_t pushed_total = 0;
@@ -287,6 +301,17 @@ struct vsa_engine {
     uint64_t prof_n[kProfKinds] = {0};
     int has10 = 0;
     int me_grid = 0;
+    int cus = 256;
+    // Motion-search launch autotuner: the persistent grid is kTuneWgs[c] x CUs
+    // workgroups.  Per size bucket (log2 of the step's tile bound), candidates
+    // are tried in turn on live steps, timed with an event pair around the
+    // launch, until each has kTuneSamples timings; the fastest mean is kept.
+    int me_fixed = 0;                  // > 0: fixed workgroups per CU, no tuning
+    struct TuneBucket { double ms[kTuneN] = {}; int n[kTuneN] = {}; int best = -1; };
+    TuneBucket tune[32];
+    struct TunePending { hipEvent_t ev0 = nullptr, ev1 = nullptr; int bucket = -1, cand = -1; };
+    TunePending tune_ring[kTuneRing];
+    int tune_head = 0;
     uint64_t counters[14] = {0};   // [10..13] host ns in vsa_step: descriptors, uploads, launches, total
 };
 
@@ -304,10 +329,25 @@ vsa_status ensure_partials(vsa_engine* e) {
     if (need <= e->partials_cap) return VSA_OK;
     HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    // the sparse tile maps planned by the last decision kernel are still to be
+    // read by the next motion search: they move to the new allocation
+    const int64_t old_cap = e->partials_cap;
+    int32_t* old_smap = e->d_smap;
     if (e->d_partials) HIPCK(hipFree(e->d_partials), "hipFree");
+    if (e->d_cmap) HIPCK(hipFree(e->d_cmap), "hipFree");
     e->d_partials = nullptr;
+    e->d_cmap = e->d_smap = nullptr;
     const int64_t cap = std::max<int64_t>(need * 2, 4096);
-    if (hipMalloc(&e->d_partials, sizeof(TilePartial) * cap) != hipSuccess) {
+    bool ok = hipMalloc(&e->d_partials, sizeof(TilePartial) * cap) == hipSuccess &&
+              hipMalloc(&e->d_cmap, sizeof(int32_t) * cap * (kAhead + 1)) == hipSuccess &&
+              hipMalloc(&e->d_smap, sizeof(int32_t) * cap * 2) == hipSuccess;
+    if (ok && old_smap) {
+        for (int par = 0; ok && par < 2; ++par)
+            ok = hipMemcpy(e->d_smap + par * cap, old_smap + par * old_cap, sizeof(int32_t) * old_cap,
+                           hipMemcpyDeviceToDevice) == hipSuccess;
+    }
+    if (old_smap) (void)hipFree(old_smap);
+    if (!ok) {
         e->partials_cap = 0;
         return fail(VSA_E_NOMEM, "tile partial buffer");
     }
@@ -345,32 +385,32 @@ void prof_collect_all(vsa_engine* e) {
 // Move the records up to the cursors c (all written by completed steps) from
 // the mapped output rings into the per-stream queues.  Records of a stream
 // closed since they were written carry an older epoch and are dropped.
-vsa_status publish(vsa_engine* e, const DeviceCursors& c) {
-    if (c.frames_written.v > e->frames_read) {
-        if (c.frames_written.v - e->frames_read > kFramesCap) return fail(VSA_E_DEVICE, "frame ring overflow");
-        for (uint64_t i = e->frames_read; i < c.frames_written.v; ++i) {
+vsa_status publish(vsa_engine* e, const PubSnap& c) {
+    if (c.frames_written > e->frames_read) {
+        if (c.frames_written - e->frames_read > kFramesCap) return fail(VSA_E_DEVICE, "frame ring overflow");
+        for (uint64_t i = e->frames_read; i < c.frames_written; ++i) {
             const OutFrame& o = e->h_out_frames[i % kFramesCap];
             HostStream& s = e->streams[o.sid];
             if (!s.open || o.pad != s.epoch) continue;
             s.fq.push_back(o.r);
             s.frames_out += 1;
         }
-        e->frames_read = c.frames_written.v;
+        e->frames_read = c.frames_written;
     }
-    if (c.shots_written.v > e->shots_read) {
-        if (c.shots_written.v - e->shots_read > kShotsCap) return fail(VSA_E_DEVICE, "shot ring overflow");
-        for (uint64_t i = e->shots_read; i < c.shots_written.v; ++i) {
+    if (c.shots_written > e->shots_read) {
+        if (c.shots_written - e->shots_read > kShotsCap) return fail(VSA_E_DEVICE, "shot ring overflow");
+        for (uint64_t i = e->shots_read; i < c.shots_written; ++i) {
             const OutShot& o = e->h_out_shots[i % kShotsCap];
             HostStream& s = e->streams[o.sid];
             if (!s.open || o.pad != s.epoch) continue;
             s.sq.push_back(o.r);
         }
-        e->shots_read = c.shots_written.v;
+        e->shots_read = c.shots_written;
     }
     for (HostStream& s : e->streams)
         if (s.open && s.ended && s.frames_out >= s.T_end) s.done = true;
-    e->counters[6] = c.sparse_run.v;
-    e->counters[9] = c.sparse_blocks.v;
+    e->counters[6] = c.sparse_run;
+    e->counters[9] = c.sparse_blocks;
     return VSA_OK;
 }
 
@@ -380,7 +420,8 @@ vsa_status drain(vsa_engine* e) {
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     DeviceCursors c;
     HIPCK(hipMemcpy(&c, e->d_cur, sizeof c, hipMemcpyDeviceToHost), "read cursors");
-    vsa_status st = publish(e, c);
+    const PubSnap ps{c.frames_written.v, c.shots_written.v, c.sparse_run.v, c.sparse_blocks.v};
+    vsa_status st = publish(e, ps);
     if (st != VSA_OK) return st;
     e->pub_step = e->step_no - 1;
     e->pushed_since_drain = 0;
@@ -493,6 +534,11 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
         return fail(VSA_E_INVAL, "max_streams must be in 1..1024");
     if (cfg->schedule != VSA_SCHEDULE_SPARSE && cfg->schedule != VSA_SCHEDULE_DENSE)
         return fail(VSA_E_INVAL, "unknown schedule");
+    if (cfg->use_graph)
+        return fail(VSA_E_UNSUPPORTED, "use_graph: a captured step graph costs more host time per replay than "
+                                       "its direct launches");
+    if (cfg->me_wgs_per_cu < 0 || cfg->me_wgs_per_cu > 8)
+        return fail(VSA_E_INVAL, "me_wgs_per_cu must be in 0..8");
     vsa_params p;
     if (cfg->params) p = *cfg->params; else vsa_default_params(&p);
     vsa_status st = check_params(p);
@@ -515,7 +561,9 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     e->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    e->cus = cus;
     e->me_grid = cus * 8;
+    e->me_fixed = cfg->me_wgs_per_cu;
     const int M = cfg->max_streams;
     auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
@@ -528,6 +576,8 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     ok = ok && dalloc((void**)&e->d_closed, sizeof(vsa_shot_result) * kMaxClosed * M);
     ok = ok && dalloc((void**)&e->d_results, sizeof(PairResult) * M * kResSlots);
     ok = ok && dalloc((void**)&e->d_sparse, 2 * sizeof(PairTask) * M * kMaxTasksPerStream);
+    ok = ok && dalloc((void**)&e->d_sjobs, 2 * sizeof(TileJob) * M * kMaxTasksPerStream);
+    ok = ok && dalloc((void**)&e->d_cjobs, (kAhead + 1) * sizeof(TileJob) * M);
     ok = ok && dalloc((void**)&e->d_cur, sizeof(DeviceCursors));
     e->desc_bytes = desc_size(M);
     e->desc_build.assign(e->desc_bytes, 0);
@@ -542,9 +592,12 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
          hipHostGetDevicePointer((void**)&e->d_out_frames, e->h_out_frames, 0) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&e->h_out_shots, sizeof(OutShot) * kShotsCap, mapped) == hipSuccess &&
          hipHostGetDevicePointer((void**)&e->d_out_shots, e->h_out_shots, 0) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&e->h_snap, sizeof(DeviceCursors) * kSnap, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&e->h_snap, sizeof(PubSnap) * kSnap, mapped) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&e->d_snap, e->h_snap, 0) == hipSuccess;
     for (int i = 0; ok && i < kSnap; ++i)
         ok = hipEventCreateWithFlags(&e->pub_ev[i], hipEventDisableTiming) == hipSuccess;
+    for (auto& t : e->tune_ring)
+        ok = ok && hipEventCreate(&t.ev0) == hipSuccess && hipEventCreate(&t.ev1) == hipSuccess;
     e->init_stride = round_up(sizeof(StreamDesc) + sizeof(DecideState), 256);
     ok = ok && hipHostMalloc((void**)&e->h_init, e->init_stride * (M + 1), hipHostMallocDefault) == hipSuccess;
     if (ok) std::memset(e->h_init, 0, e->init_stride * (M + 1));   // the last entry stays zero
@@ -587,11 +640,15 @@ void vsa_engine_destroy(vsa_engine* e) {
     for (hipEvent_t ev : e->init_ev) if (ev) (void)hipEventDestroy(ev);
     if (e->h_init) (void)hipHostFree(e->h_init);
     for (int i = 0; i < kSnap; ++i) if (e->pub_ev[i]) (void)hipEventDestroy(e->pub_ev[i]);
+    for (auto& t : e->tune_ring) {
+        if (t.ev0) (void)hipEventDestroy(t.ev0);
+        if (t.ev1) (void)hipEventDestroy(t.ev1);
+    }
     if (e->h_snap) (void)hipHostFree(e->h_snap);
     for (uint8_t* h : e->h_stage) if (h) (void)hipHostFree(h);
     for (hipEvent_t ev : e->stage_ev) if (ev) (void)hipEventDestroy(ev);
     void* dev[] = {e->d_sds, e->d_states, e->d_closed, e->d_results, e->d_sparse, e->d_cur,
-                   e->d_partials, e->d_log, e->d_desc};
+                   e->d_partials, e->d_log, e->d_desc, e->d_sjobs, e->d_cjobs, e->d_cmap, e->d_smap};
     for (void* p : dev) if (p) (void)hipFree(p);
     for (int i = 0; i < kDescRing; ++i) {
         if (e->h_desc[i]) (void)hipHostFree(e->h_desc[i]);
@@ -816,6 +873,44 @@ static inline uint64_t now_ns() {
                std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Add a finished timing to its bucket; once every candidate has kTuneSamples
+// timings the bucket keeps the fastest.  With wait, block for the timing.
+void tune_harvest(vsa_engine* e, vsa_engine::TunePending& t, bool wait) {
+    if (t.bucket < 0) return;
+    if (!wait && hipEventQuery(t.ev1) != hipSuccess) return;
+    if (wait) (void)hipEventSynchronize(t.ev1);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev0, t.ev1) == hipSuccess) {
+        auto& b = e->tune[t.bucket];
+        if (b.best < 0) {
+            b.ms[t.cand] += ms;
+            b.n[t.cand] += 1;
+            bool all = true;
+            for (int c = 0; c < kTuneN; ++c) all = all && b.n[c] >= kTuneSamples;
+            if (all) {
+                int best = 0;
+                for (int c = 1; c < kTuneN; ++c)
+                    if (b.ms[c] / b.n[c] < b.ms[best] / b.n[best]) best = c;
+                b.best = best;
+            }
+        }
+    }
+    t.bucket = -1;
+}
+
+// Candidate for this step's motion-search launch: the bucket's choice once
+// tuned, else the candidate with the fewest timings (finished timings of
+// earlier steps are collected first, without waiting).
+int me_candidate(vsa_engine* e, int bucket) {
+    if (e->me_fixed) return 0;
+    for (auto& t : e->tune_ring) tune_harvest(e, t, false);
+    auto& b = e->tune[bucket];
+    if (b.best >= 0) return b.best;
+    int c = 0;
+    for (int k = 1; k < kTuneN; ++k) if (b.n[k] < b.n[c]) c = k;
+    return c;
+}
+
 vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     if (!e) return fail(VSA_E_INVAL, "NULL engine");
     std::lock_guard<std::mutex> lk(e->mu);
@@ -950,13 +1045,16 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     HIPCK(hipEventRecord(e->desc_ev[di], Bs), "event");
     const uint64_t t_upload = now_ns();
     const StepStream* d_steps = reinterpret_cast<const StepStream*>(ddesc);
+    TileJob* cjobs = e->d_cjobs + (size_t)slot_s * M;
+    int32_t* cmap = e->d_cmap + (size_t)slot_s * e->partials_cap;
     const int32_t* d_k1 = reinterpret_cast<const int32_t*>(ddesc + off_k1);
     const PairTask* d_consec = reinterpret_cast<const PairTask*>(ddesc + off_consec);
     if (n_k1 > 0) {
         prof(0, 0, Bs);
         for (int gi = 0; gi < n_groups; ++gi) {
             const K1Group& gr = groups[gi];
-            HIPCK(launch_pyramid(gr.bits, gr.L, e->d_sds, d_steps, d_k1 + gr.first, gr.count, gr.tiles, Bs),
+            HIPCK(launch_pyramid(gr.bits, gr.L, e->d_sds, d_steps, d_k1 + gr.first, gr.count, gr.tiles, cjobs, cmap,
+                                 Bs),
                   "pyramid launch");
         }
         prof(0, 1, Bs);
@@ -966,32 +1064,51 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     // persistent motion-search grid: enough workgroups for the largest possible step
     int64_t max_tiles = consec_tiles;
     for (const HostStream& s : e->streams) if (s.open && !s.done) max_tiles += s.sparse_tiles_max;
-    int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), e->me_grid);
+    int bucket = 0;
+    while (bucket < 31 && (int64_t(1) << (bucket + 1)) <= max_tiles) ++bucket;
+    const int cand = me_candidate(e, bucket);
+    const int wgs = e->me_fixed ? e->me_fixed : kTuneWgs[cand];
+    int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), (int64_t)wgs * e->cus);
     if (grid >= 8) grid -= grid % 8;   // whole groups of one workgroup per XCD
+    vsa_engine::TunePending* tp = nullptr;
+    if (!e->me_fixed && e->tune[bucket].best < 0) {
+        tp = &e->tune_ring[e->tune_head];
+        e->tune_head = (e->tune_head + 1) % kTuneRing;
+        if (tp->bucket >= 0) tune_harvest(e, *tp, true);   // the slot's previous timing
+        tp->bucket = bucket;
+        tp->cand = cand;
+        HIPCK(hipEventRecord(tp->ev0, A), "event");
+    }
     // sparse task lists alternate between steps: read the previous one, write the next
     const size_t sp_cap = (size_t)M * kMaxTasksPerStream;
     PairTask* sparse_prev = e->d_sparse + (size_t)(par ^ 1) * sp_cap;
     PairTask* sparse_next = e->d_sparse + (size_t)par * sp_cap;
     prof(1, 0, A);
-    HIPCK(launch_me(8, e->d_sds, d_consec, n_consec, consec_tiles, sparse_prev, e->d_cur, e->d_partials, nullptr,
-                    nullptr, grid, par ^ 1, A), "motion search launch");
+    TileJob* sjobs_prev = e->d_sjobs + (size_t)(par ^ 1) * sp_cap;
+    TileJob* sjobs_next = e->d_sjobs + (size_t)par * sp_cap;
+    int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
+    int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
+    HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, sjobs_prev, (int32_t)sp_cap, smap_prev, e->d_cur,
+                    e->d_partials, nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
     prof(1, 1, A);
+    if (tp && !e->has10) HIPCK(hipEventRecord(tp->ev1, A), "event");
     if (e->has10) {
         prof(2, 0, A);
-        HIPCK(launch_me(10, e->d_sds, d_consec, n_consec, consec_tiles, sparse_prev, e->d_cur, e->d_partials,
-                        nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
+        HIPCK(launch_me(10, e->d_sds, cjobs, M, cmap, consec_tiles, sjobs_prev, (int32_t)sp_cap, smap_prev, e->d_cur,
+                        e->d_partials, nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
         prof(2, 1, A);
+        if (tp) HIPCK(hipEventRecord(tp->ev1, A), "event");
     }
     prof(4, 0, A);
+    const int sn = (int)(e->step_no % kSnap);
     HIPCK(launch_finish_decide(e->d_sds, e->d_states, d_steps, n_steps, e->dp, e->d_partials, consec_tiles,
                                sparse_prev, sparse_next, e->d_cur, e->d_out_frames, kFramesCap, e->d_out_shots,
-                               kShotsCap, e->d_log, kLogCapPerStream, e->d_closed, par, A), "decide launch");
+                               kShotsCap, e->d_log, kLogCapPerStream, e->d_closed, par, e->d_snap + sn,
+                               sjobs_next, smap_next, A), "decide launch");
     prof(4, 1, A);
     prof(5, 1, A);
-    // cursor snapshot of this step, read by vsa_collect once pub_ev completes
-    const int sn = (int)(e->step_no % kSnap);
-    HIPCK(hipMemcpyAsync(e->h_snap + sn, e->d_cur, sizeof(DeviceCursors), hipMemcpyDeviceToHost, A),
-          "cursor snapshot");
+    // the decision kernel wrote this step's cursors into h_snap[sn]; vsa_collect
+    // reads them once pub_ev[sn] has completed
     HIPCK(hipEventRecord(e->pub_ev[sn], A), "event");
     HIPCK(hipEventRecord(e->ev_a[slot_s], A), "event");
     e->prof_step += 1;
@@ -1182,7 +1299,7 @@ vsa_status vsa_debug_levels(const vsa_params* pp, const void* luma, int32_t W, i
     if (err == hipSuccess) err = hipMemcpy(ddesc + 256, &k1idx, sizeof k1idx, hipMemcpyHostToDevice);
     if (err == hipSuccess)
         err = launch_pyramid(bits, sd.L, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<StepStream*>(ddesc),
-                             reinterpret_cast<int32_t*>(ddesc + 256), 1, ss.k1_tiles, nullptr);
+                             reinterpret_cast<int32_t*>(ddesc + 256), 1, ss.k1_tiles, nullptr, nullptr, nullptr);
     if (err == hipSuccess) err = hipDeviceSynchronize();
     if (err == hipSuccess) err = hipMemcpy(host.data(), ring, sd.slot_bytes, hipMemcpyDeviceToHost);
     for (void* q : {(void*)ring, (void*)plane, (void*)info, (void*)dsd, (void*)ddesc}) if (q) (void)hipFree(q);
@@ -1236,7 +1353,8 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     t.sid = 0; t.kind = MK_CONSEC; t.ref = 0; t.oth = 1; t.level = 0; t.result = -1;
     t.tiles = me_tiles(w, h); t.tile_prefix = 0;
     t.flags = TF_DEBUG | (force_zero_mv ? TF_ZERO_MV : 0);
-    uint8_t *ring = nullptr, *dsd = nullptr, *dt = nullptr;
+    uint8_t *ring = nullptr, *dsd = nullptr, *dt = nullptr, *djob = nullptr;
+    int32_t* dmap = nullptr;
     FrameInfo* info = nullptr;
     TilePartial* part = nullptr;
     int8_t* dmv = nullptr;
@@ -1247,6 +1365,9 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     hipError_t err = hipMalloc(&ring, host.size());
     if (err == hipSuccess) err = hipMalloc(&dsd, sizeof sd);
     if (err == hipSuccess) err = hipMalloc(&dt, sizeof t);
+    if (err == hipSuccess) err = hipMalloc(&djob, sizeof(TileJob));
+    if (err == hipSuccess) err = hipMalloc(&dmap, sizeof(int32_t) * t.tiles);
+    if (err == hipSuccess) err = hipMemset(dmap, 0, sizeof(int32_t) * t.tiles);   // every tile: job 0
     if (err == hipSuccess) err = hipMalloc(&info, 2 * sizeof(FrameInfo));
     if (err == hipSuccess) err = hipMalloc(&part, sizeof(TilePartial) * t.tiles);
     if (err == hipSuccess) err = hipMalloc(&dmv, 2 * (size_t)B);
@@ -1258,10 +1379,12 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     if (err == hipSuccess) err = hipMemcpy(ring, host.data(), host.size(), hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(dsd, &sd, sizeof sd, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(dt, &t, sizeof t, hipMemcpyHostToDevice);
+    const TileJob job = make_tile_job(sd, t, nullptr);
+    if (err == hipSuccess) err = hipMemcpy(djob, &job, sizeof job, hipMemcpyHostToDevice);
     const DecideParams dp = decide_params(p, 0);
     if (err == hipSuccess)
-        err = launch_me(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
-                        nullptr, nullptr, part, dmv, dsad, std::min(t.tiles, 1024), 0, nullptr);
+        err = launch_me(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<TileJob*>(djob), 1, dmap, t.tiles,
+                        nullptr, 0, nullptr, nullptr, part, dmv, dsad, std::min(t.tiles, 1024), 0, nullptr);
     if (err == hipSuccess)
         err = launch_finish(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
                             nullptr, nullptr, part, nullptr, dp, dints, ddbl, 1, 0, nullptr);
@@ -1271,7 +1394,7 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     if (err == hipSuccess && ints) err = hipMemcpy(ints, dints, sizeof(int64_t) * 9, hipMemcpyDeviceToHost);
     if (err == hipSuccess && dbl) err = hipMemcpy(dbl, ddbl, sizeof(double) * 4, hipMemcpyDeviceToHost);
     for (void* q : {(void*)ring, (void*)dsd, (void*)dt, (void*)info, (void*)part, (void*)dmv, (void*)dsad,
-                    (void*)dints, (void*)ddbl})
+                    (void*)dints, (void*)ddbl, (void*)djob, (void*)dmap})
         if (q) (void)hipFree(q);
     if (err != hipSuccess) return hip_fail(err, "debug pair");
     return VSA_OK;

@@ -61,3 +61,17 @@ def test_null_arguments(vsa):
     assert lib.vsa_poll_frames(None, 0, None, 0) == vsa.E_INVAL
     assert lib.vsa_stream_footprint(None, None) == 0
     assert lib.vsa_debug_finish(None, 1, C.c_double(1.0), None) == vsa.E_INVAL
+
+
+def test_engine_config_checks(vsa):
+    # checked before any device call, so they run without a GPU
+    with pytest.raises(vsa.VsaError) as ei:
+        vsa.Engine(use_graph=1)
+    assert ei.value.code == vsa.E_UNSUPPORTED and "graph" in vsa.last_error()
+    for bad in (-1, 9):
+        with pytest.raises(vsa.VsaError) as ei:
+            vsa.Engine(me_wgs_per_cu=bad)
+        assert ei.value.code == vsa.E_INVAL
+    lib = vsa.lib()
+    assert lib.vsa_collect(None, None) == vsa.E_INVAL
+    assert lib.vsa_poll_frames_all(None, None, None, 0) == vsa.E_INVAL

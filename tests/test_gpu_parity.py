@@ -317,3 +317,24 @@ def test_engine_2k_bench_config(vsa, orc, params):
         _cmp_records(e.poll_frames(int(sids[i]), 1000), ref["frames"])
         _cmp_shots(e.poll_shots(int(sids[i]), 1000), ref["shots"])
     e.close()
+
+
+@pytest.mark.parametrize("wgs", [1, 3, 8])
+def test_engine_fixed_launch_schedules(vsa, orc, params, wgs):
+    """The motion-search launch schedule (persistent workgroups per CU, fixed
+    or autotuned) changes no output: each equals the oracle."""
+    frames = synth.render(synth.make_c2(seed=41, T=30, W=720, H=576))
+    ref = orc.run_clip(frames, params)
+    e = vsa.Engine(max_streams=2, params=params, me_wgs_per_cu=wgs)
+    sid = e.stream_open(720, 576, 8)
+    for t in range(len(frames)):
+        assert e.stream_push(sid, frames[t], pts=t) == 0
+        if t == len(frames) - 1:
+            e.stream_end(sid)
+        e.step()
+    while not e.stream_done(sid):
+        e.step()
+        e.sync()
+    _cmp_records(e.poll_frames(sid, 100), ref["frames"])
+    _cmp_shots(e.poll_shots(sid, 100), ref["shots"])
+    e.close()

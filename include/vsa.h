@@ -54,7 +54,7 @@ enum {
     VSA_E_NOMEM = -2,        /* device or host allocation failed                        */
     VSA_E_ADMIT = -3,        /* stream refused: HBM budget or stream slots exhausted    */
     VSA_E_STATE = -4,        /* call not valid in the stream's state (push after end)   */
-    VSA_E_DEVICE = -5,       /* HIP runtime error; affected streams become FAILED       */
+    VSA_E_DEVICE = -5,       /* HIP runtime error (the engine should be destroyed)     */
     VSA_E_AGAIN = -6,        /* stream already holds a frame waiting for a step         */
     VSA_E_UNSUPPORTED = -7   /* parameters outside what the kernels implement           */
 };
@@ -173,13 +173,19 @@ void vsa_engine_destroy(vsa_engine* e);
  * 0 if the description is invalid. */
 uint64_t vsa_stream_footprint(const vsa_engine* e, const vsa_stream_desc* d);
 
-/* Open a stream.  Frames smaller than a 2 x 2 grid of blocks at the working
- * level give VSA_E_INVAL; no free slot or not enough budget gives VSA_E_ADMIT. */
+/* Open a stream: one video analysed by the method of Sec. III, with its own
+ * pyramid ring, measure history and decision state in device memory.  *sid
+ * receives the stream id.  Frames smaller than a 2 x 2 grid of blocks at the
+ * working level give VSA_E_INVAL; no free slot or not enough budget gives
+ * VSA_E_ADMIT (admission by HBM budget). */
 vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid);
 
-/* Hand over the next luma plane of stream sid (see VSA_SRC_*).  pitch_bytes
- * is the row stride of `luma`.  VSA_E_AGAIN if the previous frame has not been
- * taken by a vsa_step yet; VSA_E_STATE after vsa_stream_end. */
+/* Hand over the next frame of stream sid: its luma plane only (the measures
+ * of Sec. III.A work on intensity), W x H samples with rows pitch_bytes apart,
+ * read from host or device memory as `src` says (VSA_SRC_*; ownership there).
+ * pts is carried into the frame's record.  VSA_E_AGAIN if the previous frame
+ * has not been taken by a vsa_step yet; VSA_E_STATE after vsa_stream_end;
+ * VSA_E_INVAL for a NULL plane or a pitch below one row. */
 vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t pitch_bytes,
                            int32_t src, int64_t pts);
 
@@ -196,12 +202,18 @@ vsa_status vsa_stream_end(vsa_engine* e, int32_t sid);
  * vsa_collect), 0 if not, < 0 on error. */
 int32_t vsa_stream_done(vsa_engine* e, int32_t sid);
 
-/* Enqueue one time step over every open stream.  Asynchronous.  hip_stream
+/* Enqueue one time step over every open stream: the pyramid and fields of
+ * each new frame (Sec. III.C), the consecutive pair's motion field and
+ * measures (Sec. III.A), the sparse pairs the decision logic requested in the
+ * previous step (fields Sec. III.C, deep check Sec. III.B), and one advance of
+ * each stream's sequential pass (Sec. III.B-D).  Asynchronous.  hip_stream
  * (nullable) is a hipStream_t: the step starts after the work already queued
- * on it and work queued on it later starts after the step. */
+ * on it and work queued on it later starts after the step.  Errors:
+ * VSA_E_INVAL, VSA_E_DEVICE. */
 vsa_status vsa_step(vsa_engine* e, void* hip_stream);
 
-/* Wait for every queued step and publish its records to the host queues. */
+/* Wait for every queued step and publish its records to the host queues.
+ * Errors: VSA_E_INVAL, VSA_E_DEVICE. */
 vsa_status vsa_sync(vsa_engine* e);
 
 /* Publish, without waiting, the records of every step the device has already
@@ -212,21 +224,29 @@ vsa_status vsa_sync(vsa_engine* e);
  * VSA_E_INVAL, VSA_E_DEVICE. */
 vsa_status vsa_collect(vsa_engine* e, int64_t* steps_published);
 
-/* Copy up to cap finished per-frame records of stream sid, in frame order, and
- * remove them from the queue.  Returns the number copied, or < 0 on error. */
+/* Copy up to cap published per-frame records of stream sid into out (the
+ * caller's array), in frame order, and remove them from the queue: the
+ * frame's pair measures (Sec. III.A), field measures when computed
+ * (Sec. III.C) and its labels: boundary, transition, shot, keyframe
+ * (Sec. III.B, III.D).  Returns the number copied, or < 0 on error. */
 int32_t vsa_poll_frames(vsa_engine* e, int32_t sid, vsa_frame_result* out, int32_t cap);
 
-/* Same for per-shot records. */
+/* Same for per-shot records: each shot between two boundaries (Sec. III.B)
+ * with its sampling structure, field order and pulldown phase (Sec. III.C);
+ * a shot is reported once the next boundary or the end is known. */
 int32_t vsa_poll_shots(vsa_engine* e, int32_t sid, vsa_shot_result* out, int32_t cap);
 
-/* Per-frame records of every stream in one call: up to cap records, each
- * stream's in frame order, with sids[i] the stream of out[i].  Returns the
- * number copied, or < 0 on error.  For serving loops over many streams. */
+/* Per-frame records of every stream in one call (serving interface, not in
+ * the paper): up to cap records, each stream's in frame order, with sids[i]
+ * the stream of out[i]; both arrays are the caller's.  Returns the number
+ * copied, or < 0 on error. */
 int32_t vsa_poll_frames_all(vsa_engine* e, int32_t* sids, vsa_frame_result* out, int32_t cap);
 
-/* Motion field of the pair (frame -> frame+1) of stream sid at the working
- * level, as nby x nbx pairs (dx, dy) of int8, if that frame is still held on
- * the device (the last 2 k_max + 7 frames).  Synchronises the engine. */
+/* Motion field (Sec. III.A; here 8x8 block matching) of the pair
+ * (frame -> frame+1) of stream sid at the working level, as nby x nbx pairs
+ * (dx, dy) of int8 written to mv_xy (cap_blocks pairs, the caller's array;
+ * NULL to query nbx, nby), if that frame is still held on the device (the
+ * last 2 k_max + 7 frames).  Synchronises the engine.  VSA_E_INVAL otherwise. */
 vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
                           int32_t cap_blocks, int32_t* nbx, int32_t* nby);
 
@@ -235,7 +255,7 @@ vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_
  * queued steps that read it have completed. */
 vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
 
-/* Engine counters, the first n of: [0] steps, [1] streams open, [2] streams
+/* Instrumentation (not in the paper).  Engine counters, the first n of: [0] steps, [1] streams open, [2] streams
  * admitted, [3] admissions refused, [4] HBM bytes held by streams, [5] budget
  * bytes, [6] sparse pair tasks planned, [7] consecutive pair tasks run,
  * [8] blocks of the consecutive pairs, [9] blocks of the sparse pairs
@@ -257,14 +277,15 @@ const char* vsa_last_error(void);
 
 /* ---- test hooks: run one kernel in isolation on host buffers ------------- */
 
-/* Pyramid of one frame: frame levels L..Ltop (Ltop = min(L + 4, Lcap)) then
+/* Pyramid and fields of one frame (Sec. III.C): frame levels L..Ltop
+ * (Ltop = min(L + 4, Lcap)) then
  * the upper and lower field at Lf, densely packed as uint16, in that order.
  * *n_out receives the sample count (call with out = NULL to size). */
 vsa_status vsa_debug_levels(const vsa_params* p, const void* luma, int32_t width, int32_t height,
                             int64_t pitch_bytes, int32_t bit_depth, uint16_t* out, int64_t cap,
                             int64_t* n_out);
 
-/* Pair measure of two w x h planes (uint16 samples, densely packed):
+/* Pair measure (Sec. III.A) of two w x h planes (uint16 samples, densely packed):
  * mv (B x 2 int8), sad (B int32, nullable), ints (Sx, Sy, Sxx, Syy, Sxy, N, A,
  * B, STATIC), dbl (NCC, SWR, AMM, ACT).  bit_depth selects the 8-bit or
  * 10-bit kernel; force_zero_mv uses d = (0, 0) for every block. */
@@ -272,13 +293,15 @@ vsa_status vsa_debug_pair(const vsa_params* p, const uint16_t* I, const uint16_t
                           int32_t h, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
                           int32_t* sad, int64_t* ints, double* dbl);
 
-/* The finishing arithmetic on n integer tuples (Sx, Sy, Sxx, Syy, Sxy, N, A, B)
- * -> n x (NCC, SWR, AMM, ACT), computed by the device. */
+/* The finishing arithmetic of Sec. III.A on n integer tuples
+ * (Sx, Sy, Sxx, Syy, Sxy, N, A, B) -> n x (NCC, SWR, AMM, ACT), computed by the
+ * device (ints: n x 8 int64; out: n x 4 double; both the caller's). */
 vsa_status vsa_debug_finish(const int64_t* ints, int64_t n, double a0, double* out);
 
-/* Decision logic alone, driven by injected measure sequences instead of
- * frames (same array layout as the engine's CPU check: act, swr, stat: T;
- * v: T x 3; F, S, P: T x (k_max + 2)).  Runs the device state machine one
+/* Decision logic alone (Sec. III.B-D), driven by injected measure sequences
+ * instead of frames (act, swr, stat: T; v: T x 3 (v0, v1, v2); F, S, P:
+ * T x (k_max + 2), column K the forward ACT, its SWR and the backward ACT at
+ * distance K).  Runs the device state machine one
  * simulated frame arrival at a time.  recs: T records; shots: up to shots_cap;
  * keys (nullable): up to keys_cap x 6 int32 (kind, ref, oth, ref_field,
  * oth_field, level) of the sparse measures requested. */

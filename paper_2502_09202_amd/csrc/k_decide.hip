@@ -420,6 +420,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     __shared__ PairResult res[kDecideWaves][kResSlots];
     constexpr int kMaxT = 3 + 2 * (kMaxKmax + 1);
     __shared__ int32_t tpre[kDecideWaves][kMaxT];
+    __shared__ int32_t npre[kDecideWaves][kMaxT + 1];   // first tile of each planned task, then the end
     __shared__ int64_t acc[kDecideWaves][kMaxT][6];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * kDecideWaves + wave;
@@ -552,19 +553,30 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
             t.tile_prefix = tile;
             tile += t.tiles;
             sparse_next[b.task + q] = t;
-            // the next step's motion search finds the task's tiles through these
+            // the next step's motion search finds the task's tiles through the
+            // job and the tile map (filled by the whole wave below)
             sjobs_next[b.task + q] = make_tile_job(sd, t, nullptr);
-            for (int k = 0; k < t.tiles; ++k) smap_next[t.tile_prefix + k] = b.task + q;
+            npre[wave][q] = t.tile_prefix;
             log_task(slog, log_cap, st, t);
         }
+        npre[wave][b.ntasks] = tile;
         st.sp_base = b.task;
         st.sp_count = b.ntasks;
         st.emitted = st.t;
         states[sid] = st;
     }
-    // 4. records out, the whole wave
+    __syncthreads();
+    // 4. tile map of the planned tasks and records out, the whole wave
     if (active) {
         const Bcast& b = bc[wave];
+        if (b.ntasks > 0) {
+            const int t_end = npre[wave][b.ntasks];
+            int q = 0;
+            for (int tt = b.tile + lane; tt < t_end; tt += 64) {
+                while (q + 1 < b.ntasks && npre[wave][q + 1] <= tt) ++q;   // tiles ascend with the lane stride
+                smap_next[tt] = b.task + q;
+            }
+        }
         for (int q = lane; q < b.nframes; q += 64) {
             OutFrame& o = out_frames[(b.fbase + (uint64_t)q) % frames_cap];
             o.sid = b.sid;

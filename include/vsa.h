@@ -264,12 +264,14 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
  * launches and stream ordering, [13] in total. */
 vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n);
 
-/* Accumulated device time per kernel of engines created with profile = 1,
- * measured with HIP events on the engine stream, for the steps completed by
- * the last vsa_sync: ms[i] total milliseconds and launches[i] launch count of
- * i = 0 pyramid (K1), 1 motion search 8-bit (K2), 2 motion search 10-bit,
- * 3 pair finish (K3), 4 decisions (K6), 5 whole step (descriptor upload to
- * end of K6).  Either pointer may be NULL; reset = 1 clears the totals. */
+/* Accumulated device time per kernel of engines created with profile = 1
+ * (slots 0-3) or 2 (all), measured with HIP events on the stream each runs
+ * on, for the steps completed by the last vsa_sync: ms[i] total milliseconds
+ * and launches[i] launch count of i = 0 pyramid (K1), 1 motion search of the
+ * consecutive pairs, 8-bit, 2 the same, 10-bit, 3 motion search of the
+ * sparse pairs (both depths), 4 decisions (K6), 5 whole step (descriptor
+ * upload to end of K6).  Either pointer may be NULL; reset = 1 clears the
+ * totals. */
 vsa_status vsa_engine_kernel_times(vsa_engine* e, double* ms, uint64_t* launches, int32_t reset);
 
 /* Thread-local description of the last error; valid until the next call. */

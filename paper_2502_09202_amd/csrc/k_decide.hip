@@ -405,7 +405,7 @@ __device__ __forceinline__ int64_t wsum64(int64_t v) {
 // Streams never share a wave, so their control paths do not serialise.
 __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     const StreamDesc* __restrict__ sds, DecideState* __restrict__ states, const StepStream* __restrict__ steps,
-    int32_t n_steps, DecideParams dp, const TilePartial* __restrict__ partials, int32_t consec_tiles,
+    int32_t n_steps, DecideParams dp, const TilePartial* __restrict__ cpart, const TilePartial* __restrict__ spart,
     const PairTask* __restrict__ sparse_prev, PairTask* __restrict__ sparse_next, DeviceCursors* __restrict__ cur,
     OutFrame* __restrict__ out_frames, uint64_t frames_cap, OutShot* __restrict__ out_shots, uint64_t shots_cap,
     int32_t* __restrict__ log, int64_t log_cap, vsa_shot_result* __restrict__ closed_buf, int32_t par,
@@ -421,6 +421,9 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     constexpr int kMaxT = 3 + 2 * (kMaxKmax + 1);
     __shared__ int32_t tpre[kDecideWaves][kMaxT];
     __shared__ int32_t npre[kDecideWaves][kMaxT + 1];   // first tile of each planned task, then the end
+    // the decisions are on the critical path of every step while other
+    // streams' motion search shares the CUs: their waves issue first
+    __builtin_amdgcn_s_setprio(3);
     __shared__ int64_t acc[kDecideWaves][kMaxT][6];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * kDecideWaves + wave;
@@ -435,7 +438,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         if (ss.has_frame && ss.consec_tiles > 0) {
             int64_t a[6] = {0, 0, 0, 0, 0, 0};
             for (int q = lane; q < ss.consec_tiles; q += 64) {
-                const TilePartial& p = partials[ss.consec_prefix + q];
+                const TilePartial& p = cpart[ss.consec_prefix + q];
                 a[0] += p.sx; a[1] += p.sy; a[2] += p.sxx; a[3] += p.syy; a[4] += p.sxy; a[5] += p.a;
             }
 #pragma unroll
@@ -474,7 +477,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
                     const int mid = (lo + hi + 1) >> 1;
                     if (tpre[wave][mid] <= q) lo = mid; else hi = mid - 1;
                 }
-                const TilePartial& p = partials[consec_tiles + q];
+                const TilePartial& p = spart[q];
                 unsigned long long* acc_t = reinterpret_cast<unsigned long long*>(acc[wave][lo]);
                 atomicAdd(acc_t + 0, (unsigned long long)p.sx);
                 atomicAdd(acc_t + 1, (unsigned long long)p.sy);
@@ -676,7 +679,7 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
 }
 
 hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, const StepStream* steps, int32_t n_steps,
-                                const DecideParams& dp, const TilePartial* partials, int32_t consec_tiles,
+                                const DecideParams& dp, const TilePartial* cpart, const TilePartial* spart,
                                 const PairTask* sparse_prev, PairTask* sparse_next, DeviceCursors* cur,
                                 OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots, uint64_t shots_cap,
                                 int32_t* log, int64_t log_cap, vsa_shot_result* closed_buf, int32_t par,
@@ -684,7 +687,7 @@ hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, cons
     if (n_steps <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish_decide, dim3((n_steps + kDecideWaves - 1) / kDecideWaves), dim3(64 * kDecideWaves), 0,
                        s, sds, states, steps, n_steps, dp,
-                       partials, consec_tiles, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
+                       cpart, spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
                        shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
     return hipGetLastError();
 }

@@ -432,22 +432,25 @@ __device__ void me_tile(const TileJob& jb, int local, TilePartial* part_out, int
 // the sparse list (built on the device by the previous step's decision kernel).
 // One launch per sample width; tiles of the other width are skipped.
 template <typename T>
+// One launch walks one tile list: the consecutive pairs of a step (n_tiles
+// known to the host), or, with cur set, the sparse pairs planned by the
+// previous step's decisions (their tile count read from cur->sparse_tt).
 __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restrict__ sds,
-                                                   const TileJob* __restrict__ cjobs, int32_t n_cjobs,
-                                                   const int32_t* __restrict__ cmap, int32_t consec_tiles,
-                                                   const TileJob* __restrict__ sjobs, int32_t n_sjobs,
-                                                   const int32_t* __restrict__ smap,
-                                                   const DeviceCursors* __restrict__ cur,
+                                                   const TileJob* __restrict__ jobs, int32_t n_jobs,
+                                                   const int32_t* __restrict__ map, int32_t n_tiles,
+                                                   const DeviceCursors* __restrict__ cur, int32_t par_prev,
                                                    TilePartial* __restrict__ partials, int8_t* dbg_mv,
-                                                   int32_t* dbg_sad, int32_t par_prev,
-                                                   unsigned long long* __restrict__ clear_tt) {
+                                                   int32_t* dbg_sad, unsigned long long* __restrict__ clear_tt) {
     // clear this step's planning counter before the decision kernel adds to it
     if (clear_tt && blockIdx.x == 0 && threadIdx.x == 0) *clear_tt = 0ull;
     __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
     __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
     __shared__ int64_t red[4 * 6];
-    const unsigned long long tt = cur ? cur->sparse_tt[par_prev].v : 0ull;
-    const int total = consec_tiles + tt_tiles(tt);
+    const bool sparse = cur != nullptr;
+    // the sparse pairs precede the step's decisions on the critical path;
+    // their waves issue before those of the next step's consecutive pairs
+    if (sparse) __builtin_amdgcn_s_setprio(2);
+    const int total = sparse ? tt_tiles(cur->sparse_tt[par_prev].v) : n_tiles;
     // Workgroups are dispatched round-robin over the XCDs, each with its own
     // L2: workgroup b runs on XCD b % kXcd.  Each XCD walks one contiguous
     // slice of the tile list, so neighbouring tiles of a pair (which share
@@ -464,21 +467,19 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
         stride = groups;
     }
     // A tile's job: map entry, then the job (the next tile's map entry is
-    // loaded one iteration ahead).  Consecutive pairs come first in the tile
-    // list, their jobs built by this step's pyramid kernel; the sparse pairs'
-    // jobs were built by the previous step's decision kernel.
-    int idx_next = 0;
-    if (first < hi) idx_next = first < consec_tiles ? cmap[first] : smap[first - consec_tiles];
+    // loaded one iteration ahead).  The consecutive pairs' jobs are built by
+    // this step's pyramid kernel, the sparse pairs' by the previous step's
+    // decision kernel.
+    int idx_next = first < hi ? map[first] : 0;
     for (int tile = first; tile < hi; tile += stride) {
         const int idx = idx_next;
         const int nt = tile + stride;
-        if (nt < hi) idx_next = nt < consec_tiles ? cmap[nt] : smap[nt - consec_tiles];
-        const bool consec = tile < consec_tiles;
-        if (idx < 0 || idx >= (consec ? n_cjobs : n_sjobs)) continue;   // never expected; keeps reads in bounds
-        const TileJob& jb = consec ? cjobs[idx] : sjobs[idx];
-        const int local = (consec ? tile : tile - consec_tiles) - jb.tile_prefix;
+        if (nt < hi) idx_next = map[nt];
+        if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
+        const TileJob& jb = jobs[idx];
+        const int local = tile - jb.tile_prefix;
         if (jb.bits != (sizeof(T) == 1 ? 8 : 10)) continue;
-        if (!consec) {
+        if (sparse) {
             const StreamDesc& sd = sds[jb.sid];
             if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
         }
@@ -553,19 +554,20 @@ __global__ void k_finish_debug(const int64_t* __restrict__ ints, int64_t n, doub
     out[4 * i] = f[0]; out[4 * i + 1] = f[1]; out[4 * i + 2] = f[2]; out[4 * i + 3] = f[3];
 }
 
-hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* cjobs, int32_t n_cjobs, const int32_t* cmap,
-                     int32_t consec_tiles, const TileJob* sjobs, int32_t n_sjobs, const int32_t* smap,
-                     const DeviceCursors* cur, TilePartial* partials, int8_t* dbg_mv, int32_t* dbg_sad, int grid,
-                     int32_t par_prev, hipStream_t s) {
+hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* jobs, int32_t n_jobs, const int32_t* map,
+                     int32_t n_tiles, const DeviceCursors* cur, int32_t par_prev, bool clear_next, TilePartial* partials,
+                     int8_t* dbg_mv, int32_t* dbg_sad, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
+    // the sparse launch of a step clears the planning counter the step's
+    // decision kernel adds to (the other parity)
     unsigned long long* clear_tt =
-        cur ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
+        (cur && clear_next) ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
     if (bits == 8)
-        hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, cjobs, n_cjobs, cmap, consec_tiles,
-                           sjobs, n_sjobs, smap, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
+        hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
+                           par_prev, partials, dbg_mv, dbg_sad, clear_tt);
     else
-        hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, cjobs, n_cjobs, cmap, consec_tiles,
-                           sjobs, n_sjobs, smap, cur, partials, dbg_mv, dbg_sad, par_prev, clear_tt);
+        hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
+                           par_prev, partials, dbg_mv, dbg_sad, clear_tt);
     return hipGetLastError();
 }
 

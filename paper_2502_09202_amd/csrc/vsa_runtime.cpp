@@ -46,15 +46,15 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t 
 hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
                           TileJob*, int32_t*, hipStream_t);
 int pyramid_tiles(const StreamDesc& sd);
-hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t, const TileJob*,
-                     int32_t, const int32_t*, const DeviceCursors*, TilePartial*, int8_t*, int32_t*, int grid,
-                     int32_t par_prev, hipStream_t);
+hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
+                     const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t);
 hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
                          DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
                          double*, int grid, int32_t par_prev, hipStream_t);
 hipError_t launch_finish_debug(const int64_t*, int64_t, double, double*, hipStream_t);
 hipError_t launch_finish_decide(const StreamDesc*, DecideState*, const StepStream*, int32_t, const DecideParams&,
-                                const TilePartial*, int32_t, const PairTask*, PairTask*, DeviceCursors*, OutFrame*,
+                                const TilePartial*, const TilePartial*, const PairTask*, PairTask*, DeviceCursors*,
+                                OutFrame*,
                                 uint64_t, OutShot*, uint64_t, int32_t*, int64_t, vsa_shot_result*, int32_t,
                                 PubSnap*, TileJob*, int32_t*, hipStream_t);
 hipError_t launch_decide_replay(const StreamDesc&, DecideState*, PairResult*, const DecideParams&, int32_t,
@@ -230,6 +230,8 @@ struct vsa_engine {
     int device = 0;
     hipStream_t stream = nullptr;      // motion search, finish, decisions
     hipStream_t stream_b = nullptr;    // uploads and pyramid (one step ahead at most)
+    hipStream_t stream_c = nullptr;    // motion search of the consecutive pairs
+    hipEvent_t ev_c[kAhead + 1] = {};
     hipEvent_t ev_a[kAhead + 1] = {}, ev_b[kAhead + 1] = {};
     int64_t step_no = 0;
     vsa_params params{};
@@ -328,6 +330,7 @@ vsa_status ensure_partials(vsa_engine* e) {
         if (s.open) need += s.consec_tiles + s.sparse_tiles_max;
     if (need <= e->partials_cap) return VSA_OK;
     HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
+    HIPCK(hipStreamSynchronize(e->stream_c), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     // the sparse tile maps planned by the last decision kernel are still to be
     // read by the next motion search: they move to the new allocation
@@ -338,7 +341,8 @@ vsa_status ensure_partials(vsa_engine* e) {
     e->d_partials = nullptr;
     e->d_cmap = e->d_smap = nullptr;
     const int64_t cap = std::max<int64_t>(need * 2, 4096);
-    bool ok = hipMalloc(&e->d_partials, sizeof(TilePartial) * cap) == hipSuccess &&
+    // partials: consecutive pairs of even and odd steps, then the sparse pairs
+    bool ok = hipMalloc(&e->d_partials, sizeof(TilePartial) * cap * 3) == hipSuccess &&
               hipMalloc(&e->d_cmap, sizeof(int32_t) * cap * (kAhead + 1)) == hipSuccess &&
               hipMalloc(&e->d_smap, sizeof(int32_t) * cap * 2) == hipSuccess;
     if (ok && old_smap) {
@@ -417,6 +421,7 @@ vsa_status publish(vsa_engine* e, const PubSnap& c) {
 // Wait for every queued step, then publish.
 vsa_status drain(vsa_engine* e) {
     HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
+    HIPCK(hipStreamSynchronize(e->stream_c), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     DeviceCursors c;
     HIPCK(hipMemcpy(&c, e->d_cur, sizeof c, hipMemcpyDeviceToHost), "read cursors");
@@ -467,6 +472,7 @@ void free_stream(vsa_engine* e, int sid) {
             ev = nullptr;
         } else {
             (void)hipStreamSynchronize(e->stream_b);
+            (void)hipStreamSynchronize(e->stream_c);
             (void)hipStreamSynchronize(e->stream);
             (void)hipFree(s.mem);
         }
@@ -491,6 +497,7 @@ uint8_t* stream_alloc(vsa_engine* e, uint64_t bytes) {
     uint8_t* m = nullptr;
     if (hipMalloc(&m, bytes) == hipSuccess) return m;
     (void)hipStreamSynchronize(e->stream_b);
+    (void)hipStreamSynchronize(e->stream_c);
     (void)hipStreamSynchronize(e->stream);
     for (auto& b : e->pool) {
         (void)hipFree(b.mem);
@@ -568,9 +575,11 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&e->stream_b, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&e->stream_c, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i <= kAhead; ++i)
         ok = hipEventCreateWithFlags(&e->ev_a[i], hipEventDisableTiming) == hipSuccess &&
-             hipEventCreateWithFlags(&e->ev_b[i], hipEventDisableTiming) == hipSuccess;
+             hipEventCreateWithFlags(&e->ev_b[i], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&e->ev_c[i], hipEventDisableTiming) == hipSuccess;
     ok = ok && dalloc((void**)&e->d_sds, sizeof(StreamDesc) * M);
     ok = ok && dalloc((void**)&e->d_states, sizeof(DecideState) * M);
     ok = ok && dalloc((void**)&e->d_closed, sizeof(vsa_shot_result) * kMaxClosed * M);
@@ -630,6 +639,7 @@ void vsa_engine_destroy(vsa_engine* e) {
     if (!e) return;
     (void)hipSetDevice(e->device);
     if (e->stream_b) (void)hipStreamSynchronize(e->stream_b);
+    if (e->stream_c) (void)hipStreamSynchronize(e->stream_c);
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     for (size_t i = 0; i < e->streams.size(); ++i)
         if (e->streams[i].mem) (void)hipFree(e->streams[i].mem);
@@ -663,7 +673,9 @@ void vsa_engine_destroy(vsa_engine* e) {
     for (int i = 0; i <= kAhead; ++i) {
         if (e->ev_a[i]) (void)hipEventDestroy(e->ev_a[i]);
         if (e->ev_b[i]) (void)hipEventDestroy(e->ev_b[i]);
+        if (e->ev_c[i]) (void)hipEventDestroy(e->ev_c[i]);
     }
+    if (e->stream_c) (void)hipStreamDestroy(e->stream_c);
     if (e->stream_b) (void)hipStreamDestroy(e->stream_b);
     if (e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
@@ -935,7 +947,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     if (e->profile) prof_collect(e, ps);
     auto prof = [&](int k, int j, hipStream_t st) {
         // profile 1: the pyramid and motion-search launches only; 2: every kernel
-        if (!e->profile || (e->profile == 1 && k > 2)) return;
+        if (!e->profile || (e->profile == 1 && k > 3)) return;
         (void)hipEventRecord(e->prof_ev[ps][k][j], st);
         if (j == 1) e->prof_used[ps][k] = 1;
     };
@@ -1029,6 +1041,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
         HIPCK(hipEventRecord(ev, user), "event");
         HIPCK(hipStreamWaitEvent(Bs, ev, 0), "wait");
+        HIPCK(hipStreamWaitEvent(e->stream_c, ev, 0), "wait");
         HIPCK(hipStreamWaitEvent(A, ev, 0), "wait");
         (void)hipEventDestroy(ev);
     }
@@ -1060,48 +1073,72 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         prof(0, 1, Bs);
     }
     HIPCK(hipEventRecord(e->ev_b[slot_s], Bs), "event");
-    HIPCK(hipStreamWaitEvent(A, e->ev_b[slot_s], 0), "wait");
-    // persistent motion-search grid: enough workgroups for the largest possible step
-    int64_t max_tiles = consec_tiles;
-    for (const HostStream& s : e->streams) if (s.open && !s.done) max_tiles += s.sparse_tiles_max;
+    // Consecutive pairs run on the search stream C once this step's pyramids
+    // are done and the decisions of step s-2 (which read the consecutive
+    // partials of this parity) have finished, so they overlap the decisions
+    // of step s-1.  Sparse pairs (planned by step s-1) and the decisions run
+    // on the main stream A, the decisions after C's consecutive pairs.
+    hipStream_t Cs = e->stream_c;
+    HIPCK(hipStreamWaitEvent(Cs, e->ev_b[slot_s], 0), "wait");
+    if (e->step_no >= 2) HIPCK(hipStreamWaitEvent(Cs, e->pub_ev[(e->step_no - 2) % kSnap], 0), "wait");
+    // persistent motion-search grids, autotuned on the consecutive launch
+    int64_t sparse_max = 0;
+    for (const HostStream& s : e->streams) if (s.open && !s.done) sparse_max += s.sparse_tiles_max;
     int bucket = 0;
-    while (bucket < 31 && (int64_t(1) << (bucket + 1)) <= max_tiles) ++bucket;
+    while (bucket < 31 && (int64_t(1) << (bucket + 1)) <= consec_tiles) ++bucket;
     const int cand = me_candidate(e, bucket);
     const int wgs = e->me_fixed ? e->me_fixed : kTuneWgs[cand];
-    int grid = (int)std::min<int64_t>(std::max<int64_t>(max_tiles, 1), (int64_t)wgs * e->cus);
-    if (grid >= 8) grid -= grid % 8;   // whole groups of one workgroup per XCD
+    auto me_grid = [&](int64_t tiles) {
+        int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)wgs * e->cus);
+        if (g >= 8) g -= g % 8;   // whole groups of one workgroup per XCD
+        return g;
+    };
+    const int grid_c = me_grid(consec_tiles), grid_s = me_grid(sparse_max);
     vsa_engine::TunePending* tp = nullptr;
-    if (!e->me_fixed && e->tune[bucket].best < 0) {
+    if (!e->me_fixed && e->tune[bucket].best < 0 && consec_tiles > 0) {
         tp = &e->tune_ring[e->tune_head];
         e->tune_head = (e->tune_head + 1) % kTuneRing;
         if (tp->bucket >= 0) tune_harvest(e, *tp, true);   // the slot's previous timing
         tp->bucket = bucket;
         tp->cand = cand;
-        HIPCK(hipEventRecord(tp->ev0, A), "event");
+        HIPCK(hipEventRecord(tp->ev0, Cs), "event");
     }
-    // sparse task lists alternate between steps: read the previous one, write the next
+    // consecutive partials alternate by step parity; sparse task lists, jobs
+    // and maps too (read the previous step's, write the next)
+    TilePartial* cpart = e->d_partials + (size_t)par * e->partials_cap;
+    TilePartial* spart = e->d_partials + (size_t)2 * e->partials_cap;
     const size_t sp_cap = (size_t)M * kMaxTasksPerStream;
     PairTask* sparse_prev = e->d_sparse + (size_t)(par ^ 1) * sp_cap;
     PairTask* sparse_next = e->d_sparse + (size_t)par * sp_cap;
-    prof(1, 0, A);
     TileJob* sjobs_prev = e->d_sjobs + (size_t)(par ^ 1) * sp_cap;
     TileJob* sjobs_next = e->d_sjobs + (size_t)par * sp_cap;
     int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
     int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
-    HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, sjobs_prev, (int32_t)sp_cap, smap_prev, e->d_cur,
-                    e->d_partials, nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
-    prof(1, 1, A);
-    if (tp && !e->has10) HIPCK(hipEventRecord(tp->ev1, A), "event");
-    if (e->has10) {
-        prof(2, 0, A);
-        HIPCK(launch_me(10, e->d_sds, cjobs, M, cmap, consec_tiles, sjobs_prev, (int32_t)sp_cap, smap_prev, e->d_cur,
-                        e->d_partials, nullptr, nullptr, grid, par ^ 1, A), "motion search launch");
-        prof(2, 1, A);
-        if (tp) HIPCK(hipEventRecord(tp->ev1, A), "event");
+    if (consec_tiles > 0) {
+        prof(1, 0, Cs);
+        HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
+                        grid_c, Cs), "motion search launch");
+        prof(1, 1, Cs);
+        if (e->has10) {
+            prof(2, 0, Cs);
+            HIPCK(launch_me(10, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
+                            grid_c, Cs), "motion search launch");
+            prof(2, 1, Cs);
+        }
+        if (tp) HIPCK(hipEventRecord(tp->ev1, Cs), "event");
     }
+    HIPCK(hipEventRecord(e->ev_c[slot_s], Cs), "event");
+    prof(3, 0, A);
+    HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart, nullptr,
+                    nullptr, grid_s, A), "motion search launch");
+    if (e->has10)
+        HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, false, spart,
+                        nullptr, nullptr, grid_s, A), "motion search launch");
+    prof(3, 1, A);
+    HIPCK(hipStreamWaitEvent(A, e->ev_c[slot_s], 0), "wait");
     prof(4, 0, A);
     const int sn = (int)(e->step_no % kSnap);
-    HIPCK(launch_finish_decide(e->d_sds, e->d_states, d_steps, n_steps, e->dp, e->d_partials, consec_tiles,
+    HIPCK(launch_finish_decide(e->d_sds, e->d_states, d_steps, n_steps, e->dp, cpart, spart,
                                sparse_prev, sparse_next, e->d_cur, e->d_out_frames, kFramesCap, e->d_out_shots,
                                kShotsCap, e->d_log, kLogCapPerStream, e->d_closed, par, e->d_snap + sn,
                                sjobs_next, smap_next, A), "decide launch");
@@ -1198,6 +1235,7 @@ vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv,
         return fail(VSA_E_INVAL, "frame not held on the device");
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
     HIPCK(hipStreamSynchronize(e->stream_b), "sync");
+    HIPCK(hipStreamSynchronize(e->stream_c), "sync");
     HIPCK(hipStreamSynchronize(e->stream), "sync");
     HIPCK(hipMemcpy(mv, s->sd.mv + (frame % s->sd.rs) * s->sd.B_L * 2, (size_t)s->sd.B_L * 2,
                     hipMemcpyDeviceToHost), "motion copy");
@@ -1240,6 +1278,7 @@ int32_t vsa_debug_measure_log(vsa_engine* e, int32_t sid, int32_t* keys, int32_t
     if (!e->d_log) return fail(VSA_E_STATE, "engine created without debug_log");
     HIPCK(hipSetDevice(e->device), "hipSetDevice");
     HIPCK(hipStreamSynchronize(e->stream_b), "sync");
+    HIPCK(hipStreamSynchronize(e->stream_c), "sync");
     HIPCK(hipStreamSynchronize(e->stream), "sync");
     DecideState st;
     HIPCK(hipMemcpy(&st, e->d_states + sid, sizeof st, hipMemcpyDeviceToHost), "state");
@@ -1384,7 +1423,7 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     const DecideParams dp = decide_params(p, 0);
     if (err == hipSuccess)
         err = launch_me(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<TileJob*>(djob), 1, dmap, t.tiles,
-                        nullptr, 0, nullptr, nullptr, part, dmv, dsad, std::min(t.tiles, 1024), 0, nullptr);
+                        nullptr, 0, false, part, dmv, dsad, std::min(t.tiles, 1024), nullptr);
     if (err == hipSuccess)
         err = launch_finish(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
                             nullptr, nullptr, part, nullptr, dp, dints, ddbl, 1, 0, nullptr);

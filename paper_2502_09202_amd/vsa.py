@@ -247,7 +247,7 @@ class Engine:
         ms = np.zeros(6, np.float64)
         n = np.zeros(6, np.uint64)
         _check(lib().vsa_engine_kernel_times(self.h, _ptr(ms), _ptr(n), int(reset)), "engine_kernel_times")
-        names = ("pyramid", "me8", "me10", "finish", "decide", "step")
+        names = ("pyramid", "me8", "me10", "me_sparse", "decide", "step")
         return {k: (float(m), int(c)) for k, m, c in zip(names, ms, n)}
 
     def stream_end(self, sid: int):

@@ -264,6 +264,18 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid);
  * launches and stream ordering, [13] in total. */
 vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n);
 
+/* Instrumentation (not in the paper).  State of the motion-search launch
+ * autotuner for size bucket `bucket` (0..31, floor(log2) of a step's
+ * consecutive-pair tiles): *best is the chosen candidate, or -1 while the
+ * bucket is being tuned (or pinned by me_wgs_per_cu).  For the first min(cap,
+ * count) candidates, wgs[2c], wgs[2c+1] are its workgroups per CU of the
+ * consecutive and the sparse grid, windows[c] its finished timing windows and
+ * step_ms[c] the step period of its fastest window (0 without any).  Any of the
+ * arrays may be NULL when cap is 0.  Returns the candidate count, or a
+ * negative vsa_status (bad engine or bucket, or cap < 0). */
+int32_t vsa_engine_tuning(vsa_engine* e, int32_t bucket, int32_t* best, int32_t* wgs, int32_t* windows,
+                          double* step_ms, int32_t cap);
+
 /* Accumulated device time per kernel of engines created with profile = 1
  * (slots 0-3) or 2 (all), measured with HIP events on the stream each runs
  * on, for the steps completed by the last vsa_sync: ms[i] total milliseconds

@@ -683,12 +683,13 @@ hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, cons
                                 const PairTask* sparse_prev, PairTask* sparse_next, DeviceCursors* cur,
                                 OutFrame* out_frames, uint64_t frames_cap, OutShot* out_shots, uint64_t shots_cap,
                                 int32_t* log, int64_t log_cap, vsa_shot_result* closed_buf, int32_t par,
-                                PubSnap* snap, TileJob* sjobs_next, int32_t* smap_next, hipStream_t s) {
+                                PubSnap* snap, TileJob* sjobs_next, int32_t* smap_next, hipStream_t s,
+                                LaunchTiming tm) {
     if (n_steps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finish_decide, dim3((n_steps + kDecideWaves - 1) / kDecideWaves), dim3(64 * kDecideWaves), 0,
-                       s, sds, states, steps, n_steps, dp,
-                       cpart, spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
-                       shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
+    hipExtLaunchKernelGGL(k_finish_decide, dim3((n_steps + kDecideWaves - 1) / kDecideWaves),
+                          dim3(64 * kDecideWaves), 0, s, tm.start, tm.stop, 0, sds, states, steps, n_steps, dp,
+                          cpart, spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
+                          shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
     return hipGetLastError();
 }
 

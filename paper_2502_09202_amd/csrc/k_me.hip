@@ -556,18 +556,18 @@ __global__ void k_finish_debug(const int64_t* __restrict__ ints, int64_t n, doub
 
 hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* jobs, int32_t n_jobs, const int32_t* map,
                      int32_t n_tiles, const DeviceCursors* cur, int32_t par_prev, bool clear_next, TilePartial* partials,
-                     int8_t* dbg_mv, int32_t* dbg_sad, int grid, hipStream_t s) {
+                     int8_t* dbg_mv, int32_t* dbg_sad, int grid, hipStream_t s, LaunchTiming tm) {
     if (grid <= 0) return hipSuccess;
     // the sparse launch of a step clears the planning counter the step's
     // decision kernel adds to (the other parity)
     unsigned long long* clear_tt =
         (cur && clear_next) ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
     if (bits == 8)
-        hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
-                           par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+        hipExtLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds, jobs,
+                              n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
     else
-        hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
-                           par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+        hipExtLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds, jobs,
+                              n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
     return hipGetLastError();
 }
 

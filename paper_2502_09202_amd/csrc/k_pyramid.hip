@@ -323,10 +323,12 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t 
 
 // Launch the pyramid for one group of streams sharing sample width and L.
 hipError_t launch_pyramid(int bits, int L, const StreamDesc* sds, const StepStream* steps, const int32_t* k1_list,
-                          int32_t n_k1, int32_t total_tiles, TileJob* cjobs, int32_t* cmap, hipStream_t s) {
+                          int32_t n_k1, int32_t total_tiles, TileJob* cjobs, int32_t* cmap, hipStream_t s,
+                          LaunchTiming tm) {
     if (n_k1 <= 0 || total_tiles <= 0) return hipSuccess;
     const dim3 g(total_tiles), b(256);
-#define VSA_PYR(TT, LL) hipLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, sds, steps, k1_list, n_k1, cjobs, cmap)
+#define VSA_PYR(TT, LL) \
+    hipExtLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, tm.start, tm.stop, 0, sds, steps, k1_list, n_k1, cjobs, cmap)
     if (bits == 8) {
         switch (L) {
             case 0: VSA_PYR(uint8_t, 0); break;

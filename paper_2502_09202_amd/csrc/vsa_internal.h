@@ -2,6 +2,7 @@
 // host runtime of libvsa (not part of the public ABI).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "../../include/vsa.h"
@@ -173,6 +174,14 @@ struct DeviceCursors {
 
 // Output cursors as of the end of one step, written by the last workgroup of
 // the step's decision kernel into mapped host memory (what vsa_collect reads).
+// Optional event pair of a kernel launch (hipExtLaunchKernel): start is
+// stamped when the kernel begins, stop when it ends, from the dispatch itself
+// rather than from separate marker packets.  Either may be null.
+struct LaunchTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 struct PubSnap {
     uint64_t frames_written, shots_written, sparse_run, sparse_blocks;
 };

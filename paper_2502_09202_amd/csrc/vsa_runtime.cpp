@@ -44,10 +44,11 @@
 namespace vsa {
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
 hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
-                          TileJob*, int32_t*, hipStream_t);
+                          TileJob*, int32_t*, hipStream_t, LaunchTiming = {});
 int pyramid_tiles(const StreamDesc& sd);
 hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
-                     const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t);
+                     const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
+                     LaunchTiming = {});
 hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
                          DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
                          double*, int grid, int32_t par_prev, hipStream_t);
@@ -56,7 +57,7 @@ hipError_t launch_finish_decide(const StreamDesc*, DecideState*, const StepStrea
                                 const TilePartial*, const TilePartial*, const PairTask*, PairTask*, DeviceCursors*,
                                 OutFrame*,
                                 uint64_t, OutShot*, uint64_t, int32_t*, int64_t, vsa_shot_result*, int32_t,
-                                PubSnap*, TileJob*, int32_t*, hipStream_t);
+                                PubSnap*, TileJob*, int32_t*, hipStream_t, LaunchTiming = {});
 hipError_t launch_decide_replay(const StreamDesc&, DecideState*, PairResult*, const DecideParams&, int32_t,
                                 const double*, const double*, const uint8_t*, const double*, const double*,
                                 const double*, const double*, vsa_frame_result*, vsa_shot_result*, int32_t,
@@ -96,9 +97,17 @@ constexpr int kDescRing = 8;
 // Cursor snapshots, one per step (a ring): the host may run at most kDescRing
 // steps ahead of the device, so a snapshot is never rewritten while it is read.
 constexpr int kSnap = 64;
-constexpr int kTuneN = 5;
-constexpr int kTuneWgs[kTuneN] = {2, 3, 4, 6, 8};
-constexpr int kTuneSamples = 4;
+// Motion-search launch candidates: workgroups per CU of the persistent grid
+// of the consecutive pairs and of the sparse pairs.
+struct TuneCand { int consec, sparse; };
+constexpr int kTuneN = 4;
+constexpr TuneCand kTuneCands[kTuneN] = {{1, 4}, {2, 3}, {2, 4}, {4, 4}};
+constexpr int kTuneSamples = 3;
+constexpr int kTuneWindow = 8;     // steps per timing window
+// Windows start only after this many steps of an engine: the first steps
+// are not representative (every stream opens a shot at once and asks for the
+// fields of its first analysed frames; buffers grow).
+constexpr int kTuneStart = 64;
 constexpr int kTuneRing = 16;
 constexpr int64_t kLogCapPerStream = 1 << 16;
 
@@ -304,16 +313,24 @@ struct vsa_engine {
     int has10 = 0;
     int me_grid = 0;
     int cus = 256;
-    // Motion-search launch autotuner: the persistent grid is kTuneWgs[c] x CUs
-    // workgroups.  Per size bucket (log2 of the step's tile bound), candidates
-    // are tried in turn on live steps, timed with an event pair around the
-    // launch, until each has kTuneSamples timings; the fastest mean is kept.
+    // Motion-search launch autotuner.  The two motion-search launches of a
+    // step share the GPU with the pyramids of the next step and the decisions
+    // of the previous one, so a launch's own duration is not what to minimise:
+    // a wider consecutive grid finishes sooner but starves the sparse pairs and
+    // the decisions, which are the step's critical path.  Per size bucket
+    // (log2 of the step's consecutive tiles) each candidate runs in turn for a
+    // window of kTuneWindow live steps, timed between two events on the main
+    // stream (the end of the step before the window, the end of its last
+    // step), until each has kTuneSamples windows; the candidate with the
+    // shortest window is kept (host-side hiccups only lengthen a window).
     int me_fixed = 0;                  // > 0: fixed workgroups per CU, no tuning
-    struct TuneBucket { double ms[kTuneN] = {}; int n[kTuneN] = {}; int best = -1; };
+    struct TuneBucket { double ms[kTuneN] = {}; int n[kTuneN] = {}; int best = -1; };   // ms: shortest window
     TuneBucket tune[32];
     struct TunePending { hipEvent_t ev0 = nullptr, ev1 = nullptr; int bucket = -1, cand = -1; };
     TunePending tune_ring[kTuneRing];
     int tune_head = 0;
+    TunePending* tune_win = nullptr;   // the window in progress (its ev1 not yet recorded)
+    int tune_left = 0;                 // steps left in it
     uint64_t counters[14] = {0};   // [10..13] host ns in vsa_step: descriptors, uploads, launches, total
 };
 
@@ -885,24 +902,24 @@ static inline uint64_t now_ns() {
                std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Add a finished timing to its bucket; once every candidate has kTuneSamples
-// timings the bucket keeps the fastest.  With wait, block for the timing.
+// Add a finished window to its bucket; once every candidate has kTuneSamples
+// windows the bucket keeps the fastest.  With wait, block for the timing.
 void tune_harvest(vsa_engine* e, vsa_engine::TunePending& t, bool wait) {
-    if (t.bucket < 0) return;
+    if (t.bucket < 0 || &t == e->tune_win) return;
     if (!wait && hipEventQuery(t.ev1) != hipSuccess) return;
     if (wait) (void)hipEventSynchronize(t.ev1);
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.ev0, t.ev1) == hipSuccess) {
         auto& b = e->tune[t.bucket];
         if (b.best < 0) {
-            b.ms[t.cand] += ms;
+            b.ms[t.cand] = b.n[t.cand] ? std::min<double>(b.ms[t.cand], ms) : ms;
             b.n[t.cand] += 1;
             bool all = true;
             for (int c = 0; c < kTuneN; ++c) all = all && b.n[c] >= kTuneSamples;
             if (all) {
                 int best = 0;
                 for (int c = 1; c < kTuneN; ++c)
-                    if (b.ms[c] / b.n[c] < b.ms[best] / b.n[best]) best = c;
+                    if (b.ms[c] < b.ms[best]) best = c;
                 b.best = best;
             }
         }
@@ -910,16 +927,19 @@ void tune_harvest(vsa_engine* e, vsa_engine::TunePending& t, bool wait) {
     t.bucket = -1;
 }
 
-// Candidate for this step's motion-search launch: the bucket's choice once
-// tuned, else the candidate with the fewest timings (finished timings of
+// Candidate for the next motion-search window: the bucket's choice once
+// tuned, else the candidate with the fewest windows (finished windows of
 // earlier steps are collected first, without waiting).
 int me_candidate(vsa_engine* e, int bucket) {
     if (e->me_fixed) return 0;
     for (auto& t : e->tune_ring) tune_harvest(e, t, false);
     auto& b = e->tune[bucket];
     if (b.best >= 0) return b.best;
+    int n[kTuneN];                     // windows per candidate, finished or in flight
+    for (int k = 0; k < kTuneN; ++k) n[k] = b.n[k];
+    for (const auto& t : e->tune_ring) if (t.bucket == bucket) n[t.cand] += 1;
     int c = 0;
-    for (int k = 1; k < kTuneN; ++k) if (b.n[k] < b.n[c]) c = k;
+    for (int k = 1; k < kTuneN; ++k) if (n[k] < n[c]) c = k;
     return c;
 }
 
@@ -945,9 +965,23 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     }
     const int ps = (int)(e->prof_step % kProfRing);
     if (e->profile) prof_collect(e, ps);
+    // profile 1: the pyramid and motion-search launches only; 2: every kernel.
+    // Kernels are timed by events stamped from their own dispatch (the first
+    // launch of a kind starts the pair, the last one stops it); the whole step
+    // by recorded events.
+    auto profiled = [&](int k) { return e->profile && !(e->profile == 1 && k > 3); };
+    auto timing = [&](int k, bool first, bool last) {
+        LaunchTiming t;
+        if (!profiled(k)) return t;
+        if (first) t.start = e->prof_ev[ps][k][0];
+        if (last) {
+            t.stop = e->prof_ev[ps][k][1];
+            e->prof_used[ps][k] = 1;
+        }
+        return t;
+    };
     auto prof = [&](int k, int j, hipStream_t st) {
-        // profile 1: the pyramid and motion-search launches only; 2: every kernel
-        if (!e->profile || (e->profile == 1 && k > 3)) return;
+        if (!profiled(k)) return;
         (void)hipEventRecord(e->prof_ev[ps][k][j], st);
         if (j == 1) e->prof_used[ps][k] = 1;
     };
@@ -1063,14 +1097,12 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     const int32_t* d_k1 = reinterpret_cast<const int32_t*>(ddesc + off_k1);
     const PairTask* d_consec = reinterpret_cast<const PairTask*>(ddesc + off_consec);
     if (n_k1 > 0) {
-        prof(0, 0, Bs);
         for (int gi = 0; gi < n_groups; ++gi) {
             const K1Group& gr = groups[gi];
             HIPCK(launch_pyramid(gr.bits, gr.L, e->d_sds, d_steps, d_k1 + gr.first, gr.count, gr.tiles, cjobs, cmap,
-                                 Bs),
+                                 Bs, timing(0, gi == 0, gi == n_groups - 1)),
                   "pyramid launch");
         }
-        prof(0, 1, Bs);
     }
     HIPCK(hipEventRecord(e->ev_b[slot_s], Bs), "event");
     // Consecutive pairs run on the search stream C once this step's pyramids
@@ -1086,23 +1118,37 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     for (const HostStream& s : e->streams) if (s.open && !s.done) sparse_max += s.sparse_tiles_max;
     int bucket = 0;
     while (bucket < 31 && (int64_t(1) << (bucket + 1)) <= consec_tiles) ++bucket;
-    const int cand = me_candidate(e, bucket);
-    const int wgs = e->me_fixed ? e->me_fixed : kTuneWgs[cand];
-    auto me_grid = [&](int64_t tiles) {
-        int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)wgs * e->cus);
+    TuneCand wgs{e->me_fixed, e->me_fixed};
+    if (!e->me_fixed) {
+        if (e->tune_win && e->tune_win->bucket != bucket) {   // the bucket changed: drop the window
+            e->tune_win->bucket = -1;
+            e->tune_win = nullptr;
+        }
+        int cand;
+        if (e->tune_win) {
+            cand = e->tune_win->cand;
+        } else {
+            cand = me_candidate(e, bucket);
+            // windows start once the pipeline is full
+            if (e->tune[bucket].best < 0 && consec_tiles > 0 && e->step_no >= kTuneStart) {
+                vsa_engine::TunePending* tp = &e->tune_ring[e->tune_head];
+                e->tune_head = (e->tune_head + 1) % kTuneRing;
+                if (tp->bucket >= 0) tune_harvest(e, *tp, true);   // the slot's previous window
+                tp->bucket = bucket;
+                tp->cand = cand;
+                HIPCK(hipEventRecord(tp->ev0, A), "event");      // A holds only earlier steps' work here
+                e->tune_win = tp;
+                e->tune_left = kTuneWindow;
+            }
+        }
+        wgs = kTuneCands[cand];
+    }
+    auto me_grid = [&](int64_t tiles, int w) {
+        int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)w * e->cus);
         if (g >= 8) g -= g % 8;   // whole groups of one workgroup per XCD
         return g;
     };
-    const int grid_c = me_grid(consec_tiles), grid_s = me_grid(sparse_max);
-    vsa_engine::TunePending* tp = nullptr;
-    if (!e->me_fixed && e->tune[bucket].best < 0 && consec_tiles > 0) {
-        tp = &e->tune_ring[e->tune_head];
-        e->tune_head = (e->tune_head + 1) % kTuneRing;
-        if (tp->bucket >= 0) tune_harvest(e, *tp, true);   // the slot's previous timing
-        tp->bucket = bucket;
-        tp->cand = cand;
-        HIPCK(hipEventRecord(tp->ev0, Cs), "event");
-    }
+    const int grid_c = me_grid(consec_tiles, wgs.consec), grid_s = me_grid(sparse_max, wgs.sparse);
     // consecutive partials alternate by step parity; sparse task lists, jobs
     // and maps too (read the previous step's, write the next)
     TilePartial* cpart = e->d_partials + (size_t)par * e->partials_cap;
@@ -1115,39 +1161,34 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
     int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
     if (consec_tiles > 0) {
-        prof(1, 0, Cs);
         HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
-                        grid_c, Cs), "motion search launch");
-        prof(1, 1, Cs);
-        if (e->has10) {
-            prof(2, 0, Cs);
+                        grid_c, Cs, timing(1, true, true)), "motion search launch");
+        if (e->has10)
             HIPCK(launch_me(10, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
-                            grid_c, Cs), "motion search launch");
-            prof(2, 1, Cs);
-        }
-        if (tp) HIPCK(hipEventRecord(tp->ev1, Cs), "event");
+                            grid_c, Cs, timing(2, true, true)), "motion search launch");
     }
     HIPCK(hipEventRecord(e->ev_c[slot_s], Cs), "event");
-    prof(3, 0, A);
     HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart, nullptr,
-                    nullptr, grid_s, A), "motion search launch");
+                    nullptr, grid_s, A, timing(3, true, !e->has10)), "motion search launch");
     if (e->has10)
         HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, false, spart,
-                        nullptr, nullptr, grid_s, A), "motion search launch");
-    prof(3, 1, A);
+                        nullptr, nullptr, grid_s, A, timing(3, false, true)), "motion search launch");
     HIPCK(hipStreamWaitEvent(A, e->ev_c[slot_s], 0), "wait");
-    prof(4, 0, A);
     const int sn = (int)(e->step_no % kSnap);
     HIPCK(launch_finish_decide(e->d_sds, e->d_states, d_steps, n_steps, e->dp, cpart, spart,
                                sparse_prev, sparse_next, e->d_cur, e->d_out_frames, kFramesCap, e->d_out_shots,
                                kShotsCap, e->d_log, kLogCapPerStream, e->d_closed, par, e->d_snap + sn,
-                               sjobs_next, smap_next, A), "decide launch");
-    prof(4, 1, A);
+                               sjobs_next, smap_next, A, n_steps > 0 ? timing(4, true, true) : LaunchTiming{}),
+          "decide launch");
     prof(5, 1, A);
     // the decision kernel wrote this step's cursors into h_snap[sn]; vsa_collect
     // reads them once pub_ev[sn] has completed
     HIPCK(hipEventRecord(e->pub_ev[sn], A), "event");
     HIPCK(hipEventRecord(e->ev_a[slot_s], A), "event");
+    if (e->tune_win && --e->tune_left == 0) {
+        HIPCK(hipEventRecord(e->tune_win->ev1, A), "event");
+        e->tune_win = nullptr;
+    }
     e->prof_step += 1;
     e->step_no += 1;
     if (user) HIPCK(hipStreamWaitEvent(user, e->ev_a[slot_s], 0), "wait");
@@ -1268,6 +1309,22 @@ vsa_status vsa_engine_counters(vsa_engine* e, uint64_t* out, int32_t n) {
     e->counters[5] = e->budget;
     for (int32_t i = 0; i < n && i < 14; ++i) out[i] = e->counters[i];
     return VSA_OK;
+}
+
+int32_t vsa_engine_tuning(vsa_engine* e, int32_t bucket, int32_t* best, int32_t* wgs, int32_t* windows,
+                          double* step_ms, int32_t cap) {
+    if (!e || bucket < 0 || bucket >= 32 || cap < 0) return fail(VSA_E_INVAL, "bad argument");
+    if (cap > 0 && (!best || !wgs || !windows || !step_ms)) return fail(VSA_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    const auto& b = e->tune[bucket];
+    if (best) *best = b.best;
+    for (int c = 0; c < kTuneN && c < cap; ++c) {
+        wgs[2 * c] = kTuneCands[c].consec;
+        wgs[2 * c + 1] = kTuneCands[c].sparse;
+        windows[c] = b.n[c];
+        step_ms[c] = b.n[c] ? b.ms[c] / kTuneWindow : 0.0;
+    }
+    return kTuneN;
 }
 
 int32_t vsa_debug_measure_log(vsa_engine* e, int32_t sid, int32_t* keys, int32_t cap) {

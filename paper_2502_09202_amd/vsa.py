@@ -77,7 +77,7 @@ SYMBOLS = [
     "vsa_abi_version", "vsa_default_params", "vsa_engine_create", "vsa_engine_destroy",
     "vsa_stream_footprint", "vsa_stream_open", "vsa_stream_push", "vsa_stream_end",
     "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
-    "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_last_error",
+    "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
     "vsa_poll_frames_all",
@@ -132,6 +132,7 @@ def lib():
         "vsa_debug_measure_log": (i32, [P, i32, P, i32]),
         "vsa_stream_push_batch": (i32, [P, i32, P, P, P, i32, P, P]),
         "vsa_engine_kernel_times": (i32, [P, P, P, i32]),
+        "vsa_engine_tuning": (i32, [P, i32, P, P, P, P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -309,6 +310,24 @@ class Engine:
                 "sparse_tasks", "consecutive_tasks", "consecutive_blocks", "sparse_blocks",
                 "host_ns_build", "host_ns_upload", "host_ns_launch", "host_ns_step")
         return {k: int(v) for k, v in zip(keys, out)}
+
+    def tuning(self) -> dict:
+        """Launch autotuner state per size bucket that has timings: the chosen
+        candidate (-1 while tuning) and each candidate's grids, windows and
+        step period in ms (fastest window)."""
+        out = {}
+        for bucket in range(32):
+            best = C.c_int32(-1)
+            wgs = np.zeros((8, 2), np.int32)
+            win = np.zeros(8, np.int32)
+            ms = np.zeros(8, np.float64)
+            n = _check(lib().vsa_engine_tuning(self.h, bucket, C.byref(best), _ptr(wgs), _ptr(win), _ptr(ms), 8),
+                       "engine_tuning")
+            if best.value >= 0 or win[:n].any():
+                out[bucket] = {"best": best.value,
+                               "candidates": [{"wgs": tuple(int(x) for x in wgs[c]), "windows": int(win[c]),
+                                               "step_ms": round(float(ms[c]), 4)} for c in range(n)]}
+        return out
 
     def measure_log(self, sid: int) -> np.ndarray:
         n = _check(lib().vsa_debug_measure_log(self.h, sid, None, 0), "debug_measure_log")

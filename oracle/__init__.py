@@ -51,7 +51,7 @@ FRAME_DTYPE = np.dtype([
     ("frame", "<i8"), ("flags", "<i4"), ("shot_id", "<i4"), ("boundary", "<i4"),
     ("boundary_k", "<i4"), ("ncc", "<f8"), ("swr", "<f8"), ("amm", "<f8"), ("act", "<f8"),
     ("mom", "<i8", (5,)), ("n_pix", "<i8"), ("amm_num", "<i8"), ("n_blocks", "<i4"),
-    ("field_mask", "<u4"), ("v", "<f8", (3,)),
+    ("field_mask", "<u4"), ("v", "<f8", (3,)), ("h_mean", "<f8"), ("h_std", "<f8"), ("h_mad", "<f8"),
 ])
 SHOT_DTYPE = np.dtype([
     ("shot_id", "<i4"), ("pad0", "<i4"), ("first", "<i8"), ("last", "<i8"),
@@ -78,6 +78,7 @@ def lib():
         L.orc_pair.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(Params), C.c_int32,
                                P, P, P, P]
         L.orc_finish.argtypes = [P, C.c_double, P]
+        L.orc_intensity.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.orc_run_clip.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
                                    C.c_int32, C.c_int32, C.POINTER(Params), P, P, C.c_int32,
                                    C.POINTER(C.c_int32), P, C.c_int32, C.POINTER(C.c_int32), P]
@@ -86,7 +87,7 @@ def lib():
                                           C.POINTER(C.c_int32), P, C.c_int32,
                                           C.POINTER(C.c_int32)]
         for f in ("orc_geometry", "orc_downscale", "orc_levels", "orc_pair", "orc_finish",
-                  "orc_run_clip", "orc_decide_injected"):
+                  "orc_intensity", "orc_run_clip", "orc_decide_injected"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -169,6 +170,18 @@ def pair(I, J, params, force_zero_mv=False):
     out["mv"] = mv[:B].reshape(h // 8, w // 8, 2)
     out["sad"] = sad[:B].reshape(h // 8, w // 8)
     return out
+
+
+def intensity(plane, bits=8):
+    """Sec. III.A unary measure of one plane: (histogram int64[2^bits],
+    {"n", "s1", "s2", "m"}, (mean, std, mad))."""
+    q = np.ascontiguousarray(plane, dtype=np.uint16)
+    h, w = q.shape
+    hist = np.zeros(1 << bits, np.int64)
+    ints = np.zeros(4, np.int64)
+    out = np.zeros(3, np.float64)
+    _check(lib().orc_intensity(_ptr(q), w, h, bits, _ptr(hist), _ptr(ints), _ptr(out)), "orc_intensity")
+    return hist, dict(zip(("n", "s1", "s2", "m"), (int(v) for v in ints))), tuple(float(v) for v in out)
 
 
 def finish(ints8, a0):

@@ -381,6 +381,39 @@ void init_record(orc_frame_rec& r, int64_t f) {
     const double nan = std::nan("");
     r.ncc = r.swr = r.amm = r.act = nan;
     r.v[0] = r.v[1] = r.v[2] = nan;
+    r.h_mean = r.h_std = r.h_mad = nan;
+}
+
+// Sec. III.A: H(t), the intensity histogram of a frame, and its mean,
+// standard deviation and mean absolute deviation.  The sums are exact
+// integers; each measure is rounded once:
+//   mean = S1 / N,  std = sqrt(N S2 - S1^2) / N,  mad = sum_v h[v] |N v - S1| / N^2,
+// which are sum(x)/N, sqrt(sum((x - mean)^2) / N) and sum(|x - mean|) / N
+// with the sums taken exactly.
+struct Intensity {
+    std::vector<int64_t> h;
+    int64_t n = 0, s1 = 0, s2 = 0, m = 0;
+    double mean = 0, sd = 0, mad = 0;
+};
+
+Intensity intensity(const Plane& q, int bits) {
+    Intensity o;
+    o.h.assign((size_t)1 << bits, 0);
+    for (int32_t v : q.px) o.h[(size_t)v] += 1;
+    for (size_t v = 0; v < o.h.size(); ++v) {
+        o.n += o.h[v];
+        o.s1 += (int64_t)v * o.h[v];
+        o.s2 += (int64_t)v * (int64_t)v * o.h[v];
+    }
+    for (size_t v = 0; v < o.h.size(); ++v) {
+        const int64_t d = o.n * (int64_t)v - o.s1;
+        o.m += o.h[v] * (d < 0 ? -d : d);
+    }
+    const __int128 var_n2 = (__int128)o.n * o.s2 - (__int128)o.s1 * o.s1;   // N^2 times the variance
+    o.mean = (double)o.s1 / (double)o.n;
+    o.sd = std::sqrt((double)var_n2) / (double)o.n;
+    o.mad = (double)o.m / ((double)o.n * (double)o.n);
+    return o;
 }
 
 // The offline sequential pass: one iteration per frame t, jumping over a
@@ -723,7 +756,30 @@ int32_t orc_run_clip(const void* frames, int32_t T, int32_t W, int32_t H, int64_
     std::vector<orc_frame_rec> r;
     std::vector<orc_shot_rec> s;
     if (run_pass(T, pv, *p, dense != 0, r, s) != 0) return -1;
+    // the unary measure of every frame, over its working-level image
+    for (int t = 0; t < T; ++t) {
+        const FrameLevels* fl = pv.get(t);
+        if (!fl) return -1;
+        const Intensity in = intensity(fl->lv[0], bits);
+        r[(size_t)t].h_mean = in.mean;
+        r[(size_t)t].h_std = in.sd;
+        r[(size_t)t].h_mad = in.mad;
+    }
     return export_results(r, s, pv.log, recs, shots, shots_cap, n_shots, keys, keys_cap, n_keys);
+}
+
+int32_t orc_intensity(const uint16_t* px, int32_t w, int32_t h, int32_t bits, int64_t* hist, int64_t* ints,
+                      double* out3) {
+    if (!px || w < 1 || h < 1 || (bits != 8 && bits != 10)) return -1;
+    Plane q;
+    q.w = w; q.h = h;
+    q.px.assign(px, px + (size_t)w * h);
+    for (int32_t v : q.px) if (v >= (1 << bits)) return -1;
+    const Intensity in = intensity(q, bits);
+    if (hist) std::memcpy(hist, in.h.data(), in.h.size() * sizeof(int64_t));
+    if (ints) { ints[0] = in.n; ints[1] = in.s1; ints[2] = in.s2; ints[3] = in.m; }
+    if (out3) { out3[0] = in.mean; out3[1] = in.sd; out3[2] = in.mad; }
+    return 0;
 }
 
 int32_t orc_decide_injected(int32_t T, const double* act, const double* swr, const uint8_t* stat,

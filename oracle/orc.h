@@ -56,6 +56,7 @@ typedef struct {
     int32_t n_blocks;
     uint32_t field_mask;            /* bit i set if v_i was computed           */
     double v[3];                    /* v0, v1, v2 (NaN if not computed)        */
+    double h_mean, h_std, h_mad;    /* intensity measures of the frame (working level) */
 } orc_frame_rec;
 
 enum {
@@ -72,6 +73,14 @@ typedef struct {
     int32_t pulldown_phase; /* -1 unless pulldown                               */
     int32_t n_analyzed, final_;
 } orc_shot_rec;
+
+/* Sec. III.A, the unary intensity measure H(t): the histogram of a plane
+ * (w x h samples, row-major, values < 2^bits) and the mean, the standard
+ * deviation and the mean absolute deviation (about the mean) taken from it.
+ * hist: 2^bits counts; ints: N, S1 = sum v h[v], S2 = sum v^2 h[v],
+ * M = sum h[v] |N v - S1|; out3: mean, std, mad.  Any output may be NULL. */
+int32_t orc_intensity(const uint16_t* px, int32_t w, int32_t h, int32_t bits, int64_t* hist, int64_t* ints,
+                      double* out3);
 
 /* Key of one computed pair measure: ref -> oth, each a frame (field 0),
  * its upper field (1) or its lower field (2), at pyramid level `level`.

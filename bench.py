@@ -229,9 +229,9 @@ def k1_bytes_per_frame(g, W, H, k_max):
     return b + 2 * wf * hf
 
 
-def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch):
+def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, **engine_kw):
     F, H, W = dev_frames.shape
-    e = vsa.Engine(device=0, max_streams=max(B, 1), params=params, profile=int(profile))
+    e = vsa.Engine(device=0, max_streams=max(B, 1), params=params, profile=int(profile), **engine_kw)
     sids = np.array([e.stream_open(W, H, 8) for _ in range(B)], np.int32)
     base = dev_frames.data_ptr()
     fbytes = H * W
@@ -299,6 +299,8 @@ def main():
                     help="untimed steps of a separate engine before the timed run (clocks, code objects)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-stream comparison run")
     ap.add_argument("--no-diag", action="store_true", help="skip the all-kernel timing run")
+    ap.add_argument("--no-intensity-leg", action="store_true",
+                    help="skip the batched run without the unary intensity measure")
     ap.add_argument("--no-mix", action="store_true", help="skip the uneven-mix batched run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served runs")
     ap.add_argument("--serve-clips", type=int, default=32)
@@ -346,6 +348,14 @@ def main():
                                                          "ms_per_step": round(1e3 * adt / args.steps, 4)}
         print(f"[bench] batched B={args.also_streams}: {args.also_streams * args.steps / adt:.0f} frames/s",
               file=sys.stderr, flush=True)
+    if not args.no_intensity_leg:
+        # the same batched run without the unary intensity measure (no decision uses it)
+        ndt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,
+                                     no_intensity=1)
+        extra["batched_no_intensity"] = {"fps": round(args.streams * args.steps / ndt, 1),
+                                         "ms_per_step": round(1e3 * ndt / args.steps, 4)}
+        print(f"[bench] batched B={args.streams} without the intensity measure: "
+              f"{args.streams * args.steps / ndt:.0f} frames/s", file=sys.stderr, flush=True)
     plain_fps = None
     if not args.no_plain and args.plain_steps > 0:
         pdt, _, _, _, _ = run_engine(vsa, dev, params, 1, args.plain_steps, 20, 0, torch)

@@ -97,6 +97,9 @@ typedef struct {
     int32_t profile;           /* time kernel launches with HIP events (see
                                   vsa_engine_kernel_times): 1 pyramid and motion search,
                                   2 every kernel and the whole step; 0 off                   */
+    int32_t no_intensity;      /* 1: skip the unary intensity measure H(t) (Sec. III.A; no
+                                  decision uses it): h_mean/h_std/h_mad are NaN and
+                                  vsa_get_histogram fails with VSA_E_STATE; 0: computed      */
 } vsa_engine_config;
 
 enum { VSA_SCHEDULE_SPARSE = 0, VSA_SCHEDULE_DENSE = 1 };
@@ -133,6 +136,9 @@ typedef struct {
     int32_t n_blocks;
     uint32_t field_mask;
     double v[3];               /* v0 = ACT(U_t, D_t), v1 = ACT(U_t, D_t+1), v2 = ACT(D_t, U_t+1) */
+    double h_mean, h_std, h_mad; /* Sec. III.A unary measure H(t) over the working-level image:
+                                  mean, standard deviation (population) and mean absolute
+                                  deviation about the mean of its intensity histogram      */
 } vsa_frame_result;
 
 enum {
@@ -249,6 +255,17 @@ int32_t vsa_poll_frames_all(vsa_engine* e, int32_t* sids, vsa_frame_result* out,
  * last 2 k_max + 7 frames).  Synchronises the engine.  VSA_E_INVAL otherwise. */
 vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
                           int32_t cap_blocks, int32_t* nbx, int32_t* nby);
+
+/* Sec. III.A: the intensity histogram H(t) of frame `frame` over its
+ * working-level image: bins[v] = pixels with value v, v < 2^bit_depth (the
+ * frame's h_mean, h_std and h_mad are taken from it).  Held for the last rs
+ * frames stepped (the stream's ring).  *nbins (if not NULL) receives
+ * 2^bit_depth; with bins NULL only that count is returned.  The caller owns
+ * bins (cap entries).  Waits for the engine's queued work.  VSA_E_INVAL: no
+ * such stream, cap < 2^bit_depth, or the frame is not held on the device;
+ * VSA_E_STATE: the engine was created with no_intensity. */
+vsa_status vsa_get_histogram(vsa_engine* e, int32_t sid, int64_t frame, uint32_t* bins, int32_t cap,
+                             int32_t* nbins);
 
 /* Free the slot at once, without waiting for the device: records not yet
  * polled are dropped, and the stream's device memory is reused only after the

@@ -374,6 +374,7 @@ __device__ void fill_record(vsa_frame_result& r, const FrameInfo& fi) {
     r.n_blocks = fi.n_blocks;
     r.field_mask = fi.field_mask;
     r.v[0] = fi.v[0]; r.v[1] = fi.v[1]; r.v[2] = fi.v[2];
+    r.h_mean = fi.h_mean; r.h_std = fi.h_std; r.h_mad = fi.h_mad;
 }
 
 __device__ __forceinline__ void log_task(int32_t* log, int64_t cap, DecideState& st, const PairTask& k) {

@@ -13,6 +13,16 @@
 // are reduced from the 64 x 16 tile held in LDS, so the full-resolution plane
 // is never read again.  The kernel is HBM-bound: bytes moved per frame are the
 // plane plus the levels written.
+//
+// The same pass counts the working-level pixels of each tile into an LDS
+// histogram and writes it out, for the unary intensity measure of Sec. III.A;
+// k_intensity (queued right after, one workgroup per frame) sums the tile
+// histograms, stores the frame histogram in the ring slot and forms the mean,
+// standard deviation and mean absolute deviation from exact integer sums
+// (mean = S1/N, std = sqrt(N S2 - S1^2)/N, mad = sum h[v] |N v - S1| / N^2),
+// each rounded once.  (A last-tile-of-the-frame reduction inside this kernel
+// would need a device-scope release per workgroup, which writes back the
+// XCD's L2 each time.)
 #include "vsa_internal.h"
 
 #include <algorithm>
@@ -168,7 +178,7 @@ __host__ __device__ inline int pyr_grid_w(const StreamDesc& sd) {
 }
 
 template <typename T, int L>
-__device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int tile, uint16_t* lds) {
+__device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int tile, uint16_t* lds, uint32_t* hist) {
     constexpr int S = 1 << L;
     constexpr int CW = PyrShape<L>::CW;
     constexpr int TW = PyrShape<L>::TW;
@@ -207,6 +217,24 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
             }
         }
         store_row<T, CW>(slot + sd.off[0] + (int64_t)YL * sd.pl[0] * (int64_t)sizeof(T), X, wL, fl);
+        if (hist && X < wL) {
+            // a run of equal adjacent values is one atomic (fewer lanes of a
+            // wave on one LDS address in smooth regions)
+            int cur = fl.v[0];
+            uint32_t cnt = 1;
+#pragma unroll
+            for (int i = 1; i < CW; ++i) {
+                if (X + i >= wL) break;
+                if (fl.v[i] == cur) {
+                    ++cnt;
+                } else {
+                    atomicAdd(&hist[cur], cnt);
+                    cur = fl.v[i];
+                    cnt = 1;
+                }
+            }
+            atomicAdd(&hist[cur], cnt);
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < CW; ++i) fl.v[i] = 0;
@@ -242,6 +270,16 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
     }
 }
 
+// After the tile's pixels are counted in `hist`: store the tile histogram
+// (at most 64 x 16 pixels per tile: the counts fit 16 bits).
+template <typename T>
+__device__ void store_tile_hist(const StreamDesc& sd, int tile, const uint32_t* hist) {
+    constexpr int NB = sizeof(T) == 1 ? 256 : 1024;
+    __syncthreads();                               // every count of the tile is in
+    uint16_t* th = sd.tileh + (int64_t)tile * NB;
+    for (int v = threadIdx.x; v < NB; v += 256) th[v] = (uint16_t)hist[v];
+}
+
 __device__ __forceinline__ void init_frame_info(const StreamDesc& sd, const StepStream& ss) {
     FrameInfo& fi = sd.info[ss.frame % sd.rs];
     const double nan = __builtin_nan("");
@@ -258,6 +296,7 @@ __device__ __forceinline__ void init_frame_info(const StreamDesc& sd, const Step
     fi.n_blocks = 0;
     fi.field_mask = 0;
     fi.v[0] = fi.v[1] = fi.v[2] = nan;
+    fi.h_mean = fi.h_std = fi.h_mad = nan;
 }
 
 }  // namespace
@@ -266,11 +305,12 @@ __device__ __forceinline__ void init_frame_info(const StreamDesc& sd, const Step
 // (sample width, working level) group; each group is its own instantiation so
 // that registers are sized for that shape only.
 template <typename T, int L>
-__global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ sds,
+__global__ void __launch_bounds__(256, (sizeof(T) == 1 && L <= 2) ? 7 : 1) k_pyramid(const StreamDesc* __restrict__ sds,
                                                   const StepStream* __restrict__ steps,
                                                   const int32_t* __restrict__ k1_list, int32_t n_k1,
                                                   TileJob* __restrict__ cjobs, int32_t* __restrict__ cmap) {
     __shared__ uint16_t lds[2 * kPyrTW * kPyrTH];
+    __shared__ uint32_t hist[sizeof(T) == 1 ? 256 : 1024];
     const int tile = blockIdx.x;
     // locate the stream: last list entry whose first tile is <= tile
     int lo = 0, hi = n_k1 - 1;
@@ -299,7 +339,94 @@ __global__ void __launch_bounds__(256) k_pyramid(const StreamDesc* __restrict__ 
             for (int k = threadIdx.x; k < ss.consec_tiles; k += 256) cmap[ss.consec_prefix + k] = i;
         }
     }
-    pyramid_tile<T, L>(sd, ss, local, lds);
+    const bool unary = sd.tileh != nullptr;
+    if (unary) {
+        for (int v = threadIdx.x; v < (sizeof(T) == 1 ? 256 : 1024); v += 256) hist[v] = 0u;
+        __syncthreads();
+    }
+    pyramid_tile<T, L>(sd, ss, local, lds, unary ? hist : nullptr);
+    if (unary) store_tile_hist<T>(sd, local, hist);
+}
+
+// Unary intensity measure of each frame pyramided in the step (one 256-thread
+// workgroup per frame, after k_pyramid): the frame histogram is the sum of its
+// tile histograms (each thread adds 16-byte chunks of 8 bins over a strided
+// subset of the tiles; the partial sums meet in LDS); then the exact sums and
+// the three measures.  The workgroup is kept small (8 KB of LDS) so that it is
+// placed at once next to the persistent motion-search grids: the ingest
+// stream's next pyramid waits behind it.
+constexpr int kIntThreads = 256;
+
+__device__ __forceinline__ int64_t block_sum64_1024(int64_t v, int64_t* red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();                               // red is free
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kIntThreads / 64; ++w) t += red[w];
+    return t;
+}
+
+__global__ void __launch_bounds__(kIntThreads) k_intensity(const StreamDesc* __restrict__ sds,
+                                                          const StepStream* __restrict__ steps,
+                                                          const int32_t* __restrict__ k1_list, int32_t n_k1) {
+    __shared__ uint32_t part[8 * 256];             // [groups][bins]: 8 x 256 (8-bit) or 2 x 1024 (10-bit)
+    __shared__ int64_t red[kIntThreads / 64];
+    if ((int)blockIdx.x >= n_k1) return;
+    const StepStream& ss = steps[k1_list[blockIdx.x]];
+    const StreamDesc& sd = sds[ss.sid];
+    if (!sd.tileh) return;
+    const int nb = 1 << sd.bits, nt = ss.k1_tiles, tid = threadIdx.x;
+    const int per = nb / 8, groups = kIntThreads / per;
+    const int c = tid % per, g = tid / per;
+    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = g; t < nt; t += groups) {
+        const uint4 q = reinterpret_cast<const uint4*>(sd.tileh + (int64_t)t * nb)[c];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc[2 * k] += w[k] & 0xffffu;
+            acc[2 * k + 1] += w[k] >> 16;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[g * nb + 8 * c + k] = acc[k];
+    __syncthreads();
+    uint32_t* fh = reinterpret_cast<uint32_t*>(slot_base(sd, ss.frame) + sd.offH);
+    int64_t n = 0, s1 = 0, s2 = 0;
+    for (int v = tid; v < nb; v += kIntThreads) {
+        uint32_t cnt = 0;
+        for (int gg = 0; gg < groups; ++gg) cnt += part[gg * nb + v];
+        part[v] = cnt;                             // group 0's row now holds the frame histogram
+        fh[v] = cnt;
+        n += cnt;
+        s1 += (int64_t)v * cnt;
+        s2 += (int64_t)v * v * cnt;
+    }
+    n = block_sum64_1024(n, red);
+    s1 = block_sum64_1024(s1, red);
+    s2 = block_sum64_1024(s2, red);
+    int64_t m = 0;
+    for (int v = tid; v < nb; v += kIntThreads) {
+        const int64_t d = n * v - s1;
+        m += (int64_t)part[v] * (d < 0 ? -d : d);
+    }
+    m = block_sum64_1024(m, red);
+    if (tid == 0) {
+        FrameInfo& fi = sd.info[ss.frame % sd.rs];
+        fi.h_mean = (double)s1 / (double)n;
+        fi.h_std = __builtin_sqrt((double)(n * s2 - s1 * s1)) / (double)n;
+        fi.h_mad = (double)m / ((double)n * (double)n);
+    }
+}
+
+hipError_t launch_intensity(const StreamDesc* sds, const StepStream* steps, const int32_t* k1_list, int32_t n_k1,
+                            hipStream_t s) {
+    if (n_k1 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_intensity, dim3((unsigned)n_k1), dim3(kIntThreads), 0, s, sds, steps, k1_list, n_k1);
+    return hipGetLastError();
 }
 
 int pyramid_tiles(const StreamDesc& sd) {

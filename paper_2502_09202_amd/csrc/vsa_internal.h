@@ -16,7 +16,9 @@ constexpr int kMaxLevels = 5;       // frame levels stored per ring slot: L .. L
 constexpr int kMaxKmax = 15;
 constexpr int kMaxHist = 16;
 constexpr int kMaxStreams = 1024;
-constexpr int kDecideWaves = 8;         // decision kernel: one wavefront per stream, 8 per workgroup
+constexpr int kDecideWaves = 1;         // decision kernel: one wavefront per stream and per workgroup
+                                        // (small workgroups are placed at once beside the persistent
+                                        // motion-search grids; 8-wave ones waited for room)
 
 // Field selector of a plane inside a ring slot.
 enum : int32_t { PL_FRAME = 0, PL_UPPER = 1, PL_LOWER = 2 };
@@ -36,10 +38,12 @@ struct StreamDesc {
     int64_t off[kMaxLevels];          // byte offset of each stored level in a slot
     int32_t wf, hf, pf;               // field level size and pitch
     int64_t offU, offD;               // byte offsets of the fields in a slot
+    int64_t offH;                     // byte offset of the frame's intensity histogram (2^bits uint32)
     int64_t slot_bytes;
     uint8_t* ring;                    // rs slots
     struct FrameInfo* info;           // rs entries
     int8_t* mv;                       // rs x (B_L x 2)
+    uint16_t* tileh;                  // per pyramid tile: its working-level histogram (2^bits counts)
     int32_t B_L;                      // blocks at the working level
     int32_t epoch;                    // bumped each time the slot is (re)opened
 };
@@ -54,6 +58,7 @@ struct FrameInfo {
     int32_t n_blocks;
     uint32_t field_mask;
     double v[3];
+    double h_mean, h_std, h_mad;      // intensity measures of the frame (working level)
 };
 
 // One pair measure to compute: ref -> oth planes of stream `sid`.

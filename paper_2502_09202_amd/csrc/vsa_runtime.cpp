@@ -46,6 +46,7 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t 
 hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*, const int32_t*, int32_t, int32_t,
                           TileJob*, int32_t*, hipStream_t, LaunchTiming = {});
 int pyramid_tiles(const StreamDesc& sd);
+hipError_t launch_intensity(const StreamDesc*, const StepStream*, const int32_t*, int32_t, hipStream_t);
 hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
                      const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                      LaunchTiming = {});
@@ -191,6 +192,8 @@ void layout(const Geo& g, int W, int H, int bits, int kmax, StreamDesc& sd) {
     off = round_up(off + (int64_t)sd.pf * g.hf * b, 256);
     sd.offD = off;
     off = round_up(off + (int64_t)sd.pf * g.hf * b, 256);
+    sd.offH = off;
+    off = round_up(off + (int64_t)sizeof(uint32_t) * (1 << bits), 256);
     sd.slot_bytes = off;
     sd.B_L = (g.wl[0] / 8) * (g.hl[0] / 8);
 }
@@ -242,6 +245,7 @@ struct vsa_engine {
     hipStream_t stream_c = nullptr;    // motion search of the consecutive pairs
     hipEvent_t ev_c[kAhead + 1] = {};
     hipEvent_t ev_a[kAhead + 1] = {}, ev_b[kAhead + 1] = {};
+    hipEvent_t ev_h[kAhead + 1] = {};   // the step's intensity measures are in the frame records
     int64_t step_no = 0;
     vsa_params params{};
     DecideParams dp{};
@@ -324,6 +328,7 @@ struct vsa_engine {
     // step), until each has kTuneSamples windows; the candidate with the
     // shortest window is kept (host-side hiccups only lengthen a window).
     int me_fixed = 0;                  // > 0: fixed workgroups per CU, no tuning
+    bool no_intensity = false;         // skip the unary intensity measure
     struct TuneBucket { double ms[kTuneN] = {}; int n[kTuneN] = {}; int best = -1; };   // ms: shortest window
     TuneBucket tune[32];
     struct TunePending { hipEvent_t ev0 = nullptr, ev1 = nullptr; int bucket = -1, cand = -1; };
@@ -376,11 +381,18 @@ vsa_status ensure_partials(vsa_engine* e) {
     return VSA_OK;
 }
 
-uint64_t stream_bytes(const StreamDesc& sd, int64_t staging_pitch) {
+// Tile histograms of one frame (written by each pyramid tile, summed by
+// k_intensity).
+int64_t tile_hist_bytes(const StreamDesc& sd, bool intensity) {
+    if (!intensity) return 0;
+    return round_up((int64_t)pyramid_tiles(sd) * (1 << sd.bits) * (int64_t)sizeof(uint16_t), 256);
+}
+
+uint64_t stream_bytes(const StreamDesc& sd, int64_t staging_pitch, bool intensity) {
     const int64_t info = round_up((int64_t)sizeof(FrameInfo) * sd.rs, 256);
     const int64_t mv = round_up((int64_t)sd.rs * sd.B_L * 2, 256);
     const int64_t stage = 2 * round_up(staging_pitch * sd.H, 256);
-    return (uint64_t)(sd.slot_bytes * sd.rs + info + mv + stage);
+    return (uint64_t)(sd.slot_bytes * sd.rs + info + mv + tile_hist_bytes(sd, intensity) + stage);
 }
 
 // Add the elapsed time of a recorded event pair to the totals (stream already
@@ -588,6 +600,7 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     e->cus = cus;
     e->me_grid = cus * 8;
     e->me_fixed = cfg->me_wgs_per_cu;
+    e->no_intensity = cfg->no_intensity != 0;
     const int M = cfg->max_streams;
     auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
@@ -596,7 +609,8 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     for (int i = 0; ok && i <= kAhead; ++i)
         ok = hipEventCreateWithFlags(&e->ev_a[i], hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&e->ev_b[i], hipEventDisableTiming) == hipSuccess &&
-             hipEventCreateWithFlags(&e->ev_c[i], hipEventDisableTiming) == hipSuccess;
+             hipEventCreateWithFlags(&e->ev_c[i], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&e->ev_h[i], hipEventDisableTiming) == hipSuccess;
     ok = ok && dalloc((void**)&e->d_sds, sizeof(StreamDesc) * M);
     ok = ok && dalloc((void**)&e->d_states, sizeof(DecideState) * M);
     ok = ok && dalloc((void**)&e->d_closed, sizeof(vsa_shot_result) * kMaxClosed * M);
@@ -691,6 +705,7 @@ void vsa_engine_destroy(vsa_engine* e) {
         if (e->ev_a[i]) (void)hipEventDestroy(e->ev_a[i]);
         if (e->ev_b[i]) (void)hipEventDestroy(e->ev_b[i]);
         if (e->ev_c[i]) (void)hipEventDestroy(e->ev_c[i]);
+        if (e->ev_h[i]) (void)hipEventDestroy(e->ev_h[i]);
     }
     if (e->stream_c) (void)hipStreamDestroy(e->stream_c);
     if (e->stream_b) (void)hipStreamDestroy(e->stream_b);
@@ -712,8 +727,12 @@ static vsa_status prepare_stream(const vsa_engine* e, const vsa_stream_desc* d, 
     const int64_t nmax = 64LL * std::max<int64_t>((int64_t)(sd.wf / 8) * (sd.hf / 8), sd.B_L);
     if ((double)nmax * (double)nmax * (double)(maxv * maxv) >= 9.2e18)
         return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit moments");
+    // and the intensity sums over the working level (N S2 < 2^63)
+    const double npx = (double)sd.wl[0] * (double)sd.hl[0];
+    if (npx * npx * (double)(maxv * maxv) >= 9.2e18)
+        return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit intensity sums");
     staging_pitch = round_up((int64_t)d->width * (d->bit_depth == 8 ? 1 : 2), 256);
-    bytes = stream_bytes(sd, staging_pitch);
+    bytes = stream_bytes(sd, staging_pitch, !e->no_intensity);
     return VSA_OK;
 }
 
@@ -760,6 +779,8 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     off += round_up((int64_t)sizeof(FrameInfo) * sd.rs, 256);
     sd.mv = reinterpret_cast<int8_t*>(mem + off);
     off += round_up((int64_t)sd.rs * sd.B_L * 2, 256);
+    sd.tileh = e->no_intensity ? nullptr : reinterpret_cast<uint16_t*>(mem + off);
+    off += tile_hist_bytes(sd, !e->no_intensity);
     s = HostStream();
     s.open = true;
     s.desc = *d;
@@ -1105,6 +1126,12 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         }
     }
     HIPCK(hipEventRecord(e->ev_b[slot_s], Bs), "event");
+    // the frames' intensity measures from the tile histograms: off the search
+    // stream's path; the decisions (which may emit this step's records) wait
+    if (!e->no_intensity) {
+        HIPCK(launch_intensity(e->d_sds, d_steps, d_k1, n_k1, Bs), "intensity launch");
+        HIPCK(hipEventRecord(e->ev_h[slot_s], Bs), "event");
+    }
     // Consecutive pairs run on the search stream C once this step's pyramids
     // are done and the decisions of step s-2 (which read the consecutive
     // partials of this parity) have finished, so they overlap the decisions
@@ -1174,6 +1201,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, false, spart,
                         nullptr, nullptr, grid_s, A, timing(3, false, true)), "motion search launch");
     HIPCK(hipStreamWaitEvent(A, e->ev_c[slot_s], 0), "wait");
+    if (!e->no_intensity) HIPCK(hipStreamWaitEvent(A, e->ev_h[slot_s], 0), "wait");
     const int sn = (int)(e->step_no % kSnap);
     HIPCK(launch_finish_decide(e->d_sds, e->d_states, d_steps, n_steps, e->dp, cpart, spart,
                                sparse_prev, sparse_next, e->d_cur, e->d_out_frames, kFramesCap, e->d_out_shots,
@@ -1280,6 +1308,28 @@ vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv,
     HIPCK(hipStreamSynchronize(e->stream), "sync");
     HIPCK(hipMemcpy(mv, s->sd.mv + (frame % s->sd.rs) * s->sd.B_L * 2, (size_t)s->sd.B_L * 2,
                     hipMemcpyDeviceToHost), "motion copy");
+    return VSA_OK;
+}
+
+vsa_status vsa_get_histogram(vsa_engine* e, int32_t sid, int64_t frame, uint32_t* bins, int32_t cap,
+                             int32_t* nbins) {
+    if (!e) return fail(VSA_E_INVAL, "NULL engine");
+    std::lock_guard<std::mutex> lk(e->mu);
+    HostStream* s = get_stream(e, sid);
+    if (!s) return fail(VSA_E_INVAL, "no such stream");
+    const int nb = 1 << s->sd.bits;
+    if (nbins) *nbins = nb;
+    if (!s->sd.tileh) return fail(VSA_E_STATE, "the engine was created with no_intensity");
+    if (!bins) return VSA_OK;
+    if (cap < nb) return fail(VSA_E_INVAL, "output too small");
+    if (frame < 0 || frame >= s->next_frame || frame < s->next_frame - s->sd.rs)
+        return fail(VSA_E_INVAL, "frame not held on the device");
+    HIPCK(hipSetDevice(e->device), "hipSetDevice");
+    HIPCK(hipStreamSynchronize(e->stream_b), "sync");
+    HIPCK(hipStreamSynchronize(e->stream_c), "sync");
+    HIPCK(hipStreamSynchronize(e->stream), "sync");
+    HIPCK(hipMemcpy(bins, s->sd.ring + (frame % s->sd.rs) * s->sd.slot_bytes + s->sd.offH,
+                    sizeof(uint32_t) * nb, hipMemcpyDeviceToHost), "histogram copy");
     return VSA_OK;
 }
 

@@ -50,6 +50,7 @@ class EngineConfig(C.Structure):
         ("device", C.c_int32), ("max_streams", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
         ("schedule", C.c_int32), ("use_graph", C.c_int32), ("params", C.POINTER(Params)),
         ("debug_log", C.c_int32), ("me_wgs_per_cu", C.c_int32), ("profile", C.c_int32),
+        ("no_intensity", C.c_int32),
     ]
 
 
@@ -62,7 +63,7 @@ FRAME_DTYPE = np.dtype([
     ("frame", "<i8"), ("pts", "<i8"), ("flags", "<i4"), ("shot_id", "<i4"), ("boundary", "<i4"),
     ("boundary_k", "<i4"), ("ncc", "<f8"), ("swr", "<f8"), ("amm", "<f8"), ("act", "<f8"),
     ("mom", "<i8", (5,)), ("n_pix", "<i8"), ("amm_num", "<i8"), ("n_blocks", "<i4"),
-    ("field_mask", "<u4"), ("v", "<f8", (3,)),
+    ("field_mask", "<u4"), ("v", "<f8", (3,)), ("h_mean", "<f8"), ("h_std", "<f8"), ("h_mad", "<f8"),
 ])
 SHOT_DTYPE = np.dtype([
     ("shot_id", "<i4"), ("pad0", "<i4"), ("first", "<i8"), ("last", "<i8"),
@@ -77,7 +78,7 @@ SYMBOLS = [
     "vsa_abi_version", "vsa_default_params", "vsa_engine_create", "vsa_engine_destroy",
     "vsa_stream_footprint", "vsa_stream_open", "vsa_stream_push", "vsa_stream_end",
     "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
-    "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_last_error",
+    "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_get_histogram", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
     "vsa_poll_frames_all",
@@ -133,6 +134,7 @@ def lib():
         "vsa_stream_push_batch": (i32, [P, i32, P, P, P, i32, P, P]),
         "vsa_engine_kernel_times": (i32, [P, P, P, i32]),
         "vsa_engine_tuning": (i32, [P, i32, P, P, P, P, i32]),
+        "vsa_get_histogram": (i32, [P, i32, i64, P, i32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -184,12 +186,12 @@ class Engine:
 
     def __init__(self, device: int = 0, max_streams: int = 64, hbm_budget_bytes: int = 0,
                  schedule: int = SCHEDULE_SPARSE, use_graph: int = 0, params: Optional[dict] = None,
-                 debug_log: int = 0, profile: int = 0, me_wgs_per_cu: int = 0):
+                 debug_log: int = 0, profile: int = 0, me_wgs_per_cu: int = 0, no_intensity: int = 0):
         self._params = make_params(params)
         cfg = EngineConfig(device=device, max_streams=max_streams, hbm_budget_bytes=hbm_budget_bytes,
                            schedule=schedule, use_graph=use_graph,
                            params=C.pointer(self._params), debug_log=debug_log, me_wgs_per_cu=me_wgs_per_cu,
-                           profile=profile)
+                           profile=profile, no_intensity=no_intensity)
         h = C.c_void_p()
         _check(lib().vsa_engine_create(C.byref(cfg), C.byref(h)), "engine_create")
         self.h = h
@@ -310,6 +312,15 @@ class Engine:
                 "sparse_tasks", "consecutive_tasks", "consecutive_blocks", "sparse_blocks",
                 "host_ns_build", "host_ns_upload", "host_ns_launch", "host_ns_step")
         return {k: int(v) for k, v in zip(keys, out)}
+
+    def histogram(self, sid: int, frame: int) -> np.ndarray:
+        """Intensity histogram H(t) of a frame still held on the device
+        (working-level image, 2^bit_depth bins)."""
+        nb = C.c_int32(0)
+        _check(lib().vsa_get_histogram(self.h, sid, frame, None, 0, C.byref(nb)), "get_histogram")
+        out = np.zeros(nb.value, np.uint32)
+        _check(lib().vsa_get_histogram(self.h, sid, frame, _ptr(out), nb.value, C.byref(nb)), "get_histogram")
+        return out
 
     def tuning(self) -> dict:
         """Launch autotuner state per size bucket that has timings: the chosen

@@ -177,6 +177,8 @@ def _cmp_records(got, ref, check_pair=True):
     if check_pair:
         for name in ("mom", "n_pix", "amm_num", "n_blocks"):
             assert np.array_equal(got[name], ref[name]), name
+        for name in ("h_mean", "h_std", "h_mad"):     # exact sums, one rounding each: bitwise
+            assert np.array_equal(got[name].view(np.uint64), ref[name].view(np.uint64)), name
         for name in ("ncc", "swr", "amm", "act"):
             g, r = got[name], ref[name]
             assert np.array_equal(np.isnan(g), np.isnan(r)), name

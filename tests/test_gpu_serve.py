@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 INT_FIELDS = ("frame", "flags", "shot_id", "boundary", "boundary_k", "mom", "n_pix", "amm_num", "n_blocks",
               "field_mask")
-DBL_FIELDS = ("ncc", "swr", "amm", "act", "v")
+DBL_FIELDS = ("ncc", "swr", "amm", "act", "v", "h_mean", "h_std", "h_mad")
 
 
 def _sources(torch):

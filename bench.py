@@ -216,9 +216,23 @@ def serve_requests(serve, pools, n, rate, seed, lengths=(200, 3000)):
     return reqs
 
 
-def k1_bytes_per_frame(g, W, H, k_max):
-    """Algorithmic bytes of the pyramid kernel for one frame: the luma plane
-    read once, the stored levels L..L+ceil(log2(k_max+1)) and both fields written."""
+def k1_tiles(g):
+    """Pyramid tiles of one frame (64 x 16 working-level pixels up to L = 2,
+    32 x 16 at L = 3, 16 x 16 beyond; the grid also covers the fields)."""
+    L, Lf = g["L"], g["Lf"]
+    wl, hl = g["dims"][L]
+    wf, _ = g["field"]
+    shift = L - Lf
+    gw = max((wf + (1 << shift) - 1) >> shift, wl)
+    tw = 16 * (4 if L <= 2 else (2 if L == 3 else 1))
+    return -(-gw // tw) * -(-hl // 16)
+
+
+def k1_bytes_per_frame(g, W, H, k_max, intensity=True):
+    """Algorithmic bytes of the pyramid kernel for one 8-bit frame: the luma
+    plane read once, the stored levels L..L+ceil(log2(k_max+1)) and both fields
+    written, and (with the intensity measure) one 256-bin uint16 histogram
+    written per tile."""
     L, Lcap = g["L"], g["Lcap"]
     ltop = min(L + int(np.ceil(np.log2(k_max + 1))), Lcap)
     b = W * H
@@ -226,7 +240,7 @@ def k1_bytes_per_frame(g, W, H, k_max):
         w, h = g["dims"][l]
         b += w * h
     wf, hf = g["field"]
-    return b + 2 * wf * hf
+    return b + 2 * wf * hf + (k1_tiles(g) * 256 * 2 if intensity else 0)
 
 
 def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, **engine_kw):

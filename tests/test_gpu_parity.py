@@ -282,13 +282,14 @@ def test_engine_batched_mixed(vsa, orc, params):
 
 
 def test_engine_2k_bench_config(vsa, orc, params):
-    """Full size, in the launch configuration the benchmark times: 64 streams of
-    2048x1080 8-bit in one engine, k_max 8, frames borrowed from device memory.
-    Three sampled streams are compared record by record with the oracle on the
-    same frame sequences (the oracle takes seconds per 2K stream)."""
+    """Full size, in the launch configuration the benchmark times: 256 streams
+    of 2048x1080 8-bit in one engine, k_max 8, autotuned motion-search grids,
+    the intensity measure on, frames borrowed from device memory.  Three
+    sampled streams are compared record by record with the oracle on the same
+    frame sequences (the oracle takes seconds per 2K stream)."""
     import torch
     import bench
-    F, B, S = 96, 64, 40
+    F, B, S = 96, 256, 40
     W, H = 2048, 1080
     frames = bench.render_frames(("c2", 2, 1500, W, H), F, W, H, 16)
     print("engine 2K x 64 streams", frames.shape, flush=True)
@@ -313,7 +314,7 @@ def test_engine_2k_bench_config(vsa, orc, params):
         e.sync()
         guard += 1
         assert guard < 100
-    for i in (0, 13, 63):
+    for i in (0, 131, 255):
         seq = np.ascontiguousarray(frames[(offs[i] + np.arange(S)) % F])
         ref = orc.run_clip(seq, p)
         _cmp_records(e.poll_frames(int(sids[i]), 1000), ref["frames"])

@@ -687,10 +687,15 @@ hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, cons
                                 PubSnap* snap, TileJob* sjobs_next, int32_t* smap_next, hipStream_t s,
                                 LaunchTiming tm) {
     if (n_steps <= 0) return hipSuccess;
-    hipExtLaunchKernelGGL(k_finish_decide, dim3((n_steps + kDecideWaves - 1) / kDecideWaves),
-                          dim3(64 * kDecideWaves), 0, s, tm.start, tm.stop, 0, sds, states, steps, n_steps, dp,
-                          cpart, spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
-                          shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
+    const dim3 g((n_steps + kDecideWaves - 1) / kDecideWaves), b(64 * kDecideWaves);
+    if (tm.any())
+        hipExtLaunchKernelGGL(k_finish_decide, g, b, 0, s, tm.start, tm.stop, 0, sds, states, steps, n_steps, dp,
+                              cpart, spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
+                              shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
+    else
+        hipLaunchKernelGGL(k_finish_decide, g, b, 0, s, sds, states, steps, n_steps, dp, cpart, spart, sparse_prev,
+                           sparse_next, cur, out_frames, frames_cap, out_shots, shots_cap, log, log_cap, closed_buf,
+                           par, snap, sjobs_next, smap_next);
     return hipGetLastError();
 }
 

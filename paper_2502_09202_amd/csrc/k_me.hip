@@ -562,12 +562,21 @@ hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* jobs, int32
     // decision kernel adds to (the other parity)
     unsigned long long* clear_tt =
         (cur && clear_next) ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
-    if (bits == 8)
-        hipExtLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds, jobs,
-                              n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
-    else
-        hipExtLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds, jobs,
-                              n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+    if (bits == 8) {
+        if (tm.any())
+            hipExtLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds,
+                                  jobs, n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+        else
+            hipLaunchKernelGGL(k_me<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles,
+                               cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+    } else {
+        if (tm.any())
+            hipExtLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds,
+                                  jobs, n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+        else
+            hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles,
+                               cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+    }
     return hipGetLastError();
 }
 

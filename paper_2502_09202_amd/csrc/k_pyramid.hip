@@ -454,8 +454,14 @@ hipError_t launch_pyramid(int bits, int L, const StreamDesc* sds, const StepStre
                           LaunchTiming tm) {
     if (n_k1 <= 0 || total_tiles <= 0) return hipSuccess;
     const dim3 g(total_tiles), b(256);
-#define VSA_PYR(TT, LL) \
-    hipExtLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, tm.start, tm.stop, 0, sds, steps, k1_list, n_k1, cjobs, cmap)
+#define VSA_PYR(TT, LL)                                                                                      \
+    do {                                                                                                     \
+        if (tm.any())                                                                                        \
+            hipExtLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, tm.start, tm.stop, 0, sds, steps, k1_list, \
+                                  n_k1, cjobs, cmap);                                                        \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_pyramid<TT, LL>), g, b, 0, s, sds, steps, k1_list, n_k1, cjobs, cmap);     \
+    } while (0)
     if (bits == 8) {
         switch (L) {
             case 0: VSA_PYR(uint8_t, 0); break;

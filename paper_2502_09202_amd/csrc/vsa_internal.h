@@ -181,10 +181,12 @@ struct DeviceCursors {
 // the step's decision kernel into mapped host memory (what vsa_collect reads).
 // Optional event pair of a kernel launch (hipExtLaunchKernel): start is
 // stamped when the kernel begins, stop when it ends, from the dispatch itself
-// rather than from separate marker packets.  Either may be null.
+// rather than from separate marker packets.  Either may be null; with both
+// null the launch takes the plain (cheaper on the host) path.
 struct LaunchTiming {
     hipEvent_t start = nullptr;
     hipEvent_t stop = nullptr;
+    bool any() const { return start != nullptr || stop != nullptr; }
 };
 
 struct PubSnap {

@@ -115,6 +115,55 @@ __device__ __forceinline__ void build_band(const uint8_t* src, int64_t pitch, in
     }
 }
 
+// 8-bit, L = 2, a band of 4 full-resolution rows x 16 columns inside the
+// plane: the 2x2 box sums straight from the packed bytes, with dot products
+// against a byte mask (v_dot4_u32_u8 adds two bytes of each of two rows into
+// an accumulator that starts at the rounding constant 2), instead of
+// unpacking every byte.  Same arithmetic as down2, level by level.
+__device__ __forceinline__ uint32_t box2(uint32_t a, uint32_t b, uint32_t mask) {
+    return __builtin_amdgcn_udot4(a, mask, __builtin_amdgcn_udot4(b, mask, 2u, false), false) >> 2;
+}
+
+// Columns past the plane's width W read as 0 (they only feed outputs that are
+// never stored), as in load_row.
+__device__ __forceinline__ void band_l2_u8(const uint8_t* src, int64_t pitch, int y0, int x0, int W, bool al16,
+                                           Row<4>& f, Row<8>& u, Row<8>& d) {
+    constexpr uint32_t LO = 0x00000101u, HI = 0x01010000u;   // bytes 0,1 and bytes 2,3 of a word
+    uint32_t w[4][4];
+    if (al16 && x0 + 16 <= W) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint4 q = *reinterpret_cast<const uint4*>(src + (int64_t)(y0 + r) * pitch + x0);
+            w[r][0] = q.x; w[r][1] = q.y; w[r][2] = q.z; w[r][3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint8_t* p = src + (int64_t)(y0 + r) * pitch + x0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (x0 + 4 * k + b < W) v |= (uint32_t)p[4 * k + b] << (8 * b);
+                w[r][k] = v;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {                  // word k: columns 4k..4k+3
+        // level 1 of rows (0,1) and (2,3), then level 2
+        const uint32_t a0 = box2(w[0][k], w[1][k], LO), a1 = box2(w[0][k], w[1][k], HI);
+        const uint32_t b0 = box2(w[2][k], w[3][k], LO), b1 = box2(w[2][k], w[3][k], HI);
+        f.v[k] = (int)((a0 + a1 + b0 + b1 + 2u) >> 2);
+        // fields at level 1: rows (0,2) and (1,3)
+        u.v[2 * k] = (int)box2(w[0][k], w[2][k], LO);
+        u.v[2 * k + 1] = (int)box2(w[0][k], w[2][k], HI);
+        d.v[2 * k] = (int)box2(w[1][k], w[3][k], LO);
+        d.v[2 * k + 1] = (int)box2(w[1][k], w[3][k], HI);
+    }
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void store_row(uint8_t* dst, int x0, int w, const Row<N>& r) {
     T* p = reinterpret_cast<T*>(dst) + x0;
@@ -208,7 +257,11 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
             }
         } else {
             Band<NC, L> b;
-            build_band<T, NC, L>(src, pitch, YL * S, X * S, sd.W, al16, b);
+            if constexpr (sizeof(T) == 1 && L == 2) {
+                band_l2_u8(src, pitch, YL * S, X * S, sd.W, al16, b.f, b.u, b.d);
+            } else {
+                build_band<T, NC, L>(src, pitch, YL * S, X * S, sd.W, al16, b);
+            }
             fl = b.f;
             if (YL < sd.hf) {
                 const int64_t rowoff = (int64_t)YL * sd.pf * (int64_t)sizeof(T);

@@ -329,10 +329,10 @@ __device__ __forceinline__ void moments(const uint8_t* sI, const uint8_t* sJ, in
     }
 }
 
+// Wavefront sum through the device library's reduction (DPP lane moves, no
+// LDS crossbar round trips); every lane gets the total.
 __device__ __forceinline__ int32_t wave_sum(int32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return __reduce_add_sync(~0ull, v);
 }
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {

@@ -314,7 +314,7 @@ struct vsa_engine {
     int64_t prof_step = 0;
     double prof_ms[kProfKinds] = {0};
     uint64_t prof_n[kProfKinds] = {0};
-    int has10 = 0;
+    int has8 = 0, has10 = 0;           // an open stream of that sample width (its launches run)
     int me_grid = 0;
     int cus = 256;
     // Motion-search launch autotuner.  The two motion-search launches of a
@@ -818,6 +818,7 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     st = ensure_partials(e);
     if (st != VSA_OK) { free_stream(e, slot); return st; }
     if (sd.bits == 10) e->has10 = 1;
+    else e->has8 = 1;
     e->counters[2] += 1;
     *sid = slot;
     return VSA_OK;
@@ -1187,19 +1188,25 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     TileJob* sjobs_next = e->d_sjobs + (size_t)par * sp_cap;
     int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
     int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
+    // one launch per sample width that an open stream has
     if (consec_tiles > 0) {
-        HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
-                        grid_c, Cs, timing(1, true, true)), "motion search launch");
+        if (e->has8)
+            HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
+                            grid_c, Cs, timing(1, true, true)), "motion search launch");
         if (e->has10)
             HIPCK(launch_me(10, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
                             grid_c, Cs, timing(2, true, true)), "motion search launch");
     }
     HIPCK(hipEventRecord(e->ev_c[slot_s], Cs), "event");
-    HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart, nullptr,
-                    nullptr, grid_s, A, timing(3, true, !e->has10)), "motion search launch");
+    // the first sparse launch also clears the counter this step's decisions
+    // plan into: the 8-bit one runs unless only 10-bit streams are open
+    const bool sparse8 = e->has8 || !e->has10;
+    if (sparse8)
+        HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart,
+                        nullptr, nullptr, grid_s, A, timing(3, true, !e->has10)), "motion search launch");
     if (e->has10)
-        HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, false, spart,
-                        nullptr, nullptr, grid_s, A, timing(3, false, true)), "motion search launch");
+        HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, !sparse8, spart,
+                        nullptr, nullptr, grid_s, A, timing(3, !sparse8, true)), "motion search launch");
     HIPCK(hipStreamWaitEvent(A, e->ev_c[slot_s], 0), "wait");
     if (!e->no_intensity) HIPCK(hipStreamWaitEvent(A, e->ev_h[slot_s], 0), "wait");
     const int sn = (int)(e->step_no % kSnap);
@@ -1343,8 +1350,12 @@ vsa_status vsa_stream_close(vsa_engine* e, int32_t sid) {
     // when published; queued steps still read its memory, so the memory is
     // only reused once the main stream has passed them
     free_stream(e, sid);
-    bool any10 = false;
-    for (const HostStream& o : e->streams) if (o.open && o.sd.bits == 10) any10 = true;
+    bool any8 = false, any10 = false;
+    for (const HostStream& o : e->streams) {
+        if (o.open && o.sd.bits == 10) any10 = true;
+        if (o.open && o.sd.bits == 8) any8 = true;
+    }
+    e->has8 = any8;
     e->has10 = any10;
     return VSA_OK;
 }

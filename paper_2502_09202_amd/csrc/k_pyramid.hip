@@ -115,52 +115,117 @@ __device__ __forceinline__ void build_band(const uint8_t* src, int64_t pitch, in
     }
 }
 
-// 8-bit, L = 2, a band of 4 full-resolution rows x 16 columns inside the
-// plane: the 2x2 box sums straight from the packed bytes, with dot products
-// against a byte mask (v_dot4_u32_u8 adds two bytes of each of two rows into
-// an accumulator that starts at the rounding constant 2), instead of
-// unpacking every byte.  Same arithmetic as down2, level by level.
-__device__ __forceinline__ uint32_t box2(uint32_t a, uint32_t b, uint32_t mask) {
-    return __builtin_amdgcn_udot4(a, mask, __builtin_amdgcn_udot4(b, mask, 2u, false), false) >> 2;
-}
+// Working levels 2 and 3: the 2x2 box sums straight from packed samples, with
+// dot products against a mask (v_dot4_u32_u8 adds two bytes of a word,
+// v_dot2_u32_u16 the two samples of a word; two rows accumulate onto the
+// rounding constant 2), instead of unpacking every sample.  Same arithmetic
+// as down2, level by level.  Words past the plane's width read as 0 (they
+// only feed outputs that are never stored), as in load_row.
+typedef unsigned short pk_us2 __attribute__((ext_vector_type(2)));
 
-// Columns past the plane's width W read as 0 (they only feed outputs that are
-// never stored), as in load_row.
-__device__ __forceinline__ void band_l2_u8(const uint8_t* src, int64_t pitch, int y0, int x0, int W, bool al16,
-                                           Row<4>& f, Row<8>& u, Row<8>& d) {
-    constexpr uint32_t LO = 0x00000101u, HI = 0x01010000u;   // bytes 0,1 and bytes 2,3 of a word
-    uint32_t w[4][4];
-    if (al16 && x0 + 16 <= W) {
+template <typename T> struct Pk;
+template <> struct Pk<uint8_t> {
+    static constexpr int E = 4;   // samples per 32-bit word
+    static constexpr int C = 2;   // level-1 columns per word
+    static __device__ __forceinline__ uint32_t box(uint32_t a, uint32_t b, int h) {
+        const uint32_t m = h ? 0x01010000u : 0x00000101u;
+        return __builtin_amdgcn_udot4(a, m, __builtin_amdgcn_udot4(b, m, 2u, false), false) >> 2;
+    }
+};
+template <> struct Pk<uint16_t> {
+    static constexpr int E = 2;
+    static constexpr int C = 1;
+    static __device__ __forceinline__ uint32_t box(uint32_t a, uint32_t b, int) {
+        const pk_us2 one = {1, 1};
+        return __builtin_amdgcn_udot2(__builtin_bit_cast(pk_us2, a), one,
+                                      __builtin_amdgcn_udot2(__builtin_bit_cast(pk_us2, b), one, 2u, false),
+                                      false) >> 2;
+    }
+};
+
+// NW words of one row starting at sample x0.
+template <typename T, int NW>
+__device__ __forceinline__ void load_words(const uint8_t* rowp, int x0, int W, bool fast, uint32_t (&w)[NW]) {
+    constexpr int E = Pk<T>::E;
+    const T* p = reinterpret_cast<const T*>(rowp) + x0;
+    if (fast) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint4 q = *reinterpret_cast<const uint4*>(src + (int64_t)(y0 + r) * pitch + x0);
-            w[r][0] = q.x; w[r][1] = q.y; w[r][2] = q.z; w[r][3] = q.w;
+        for (int k = 0; k < NW / 4; ++k) {
+            const uint4 q = reinterpret_cast<const uint4*>(p)[k];
+            w[4 * k] = q.x; w[4 * k + 1] = q.y; w[4 * k + 2] = q.z; w[4 * k + 3] = q.w;
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint8_t* p = src + (int64_t)(y0 + r) * pitch + x0;
+        for (int k = 0; k < NW; ++k) {
+            uint32_t v = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                uint32_t v = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (x0 + 4 * k + b < W) v |= (uint32_t)p[4 * k + b] << (8 * b);
-                w[r][k] = v;
-            }
+            for (int e = 0; e < E; ++e)
+                if (x0 + E * k + e < W) v |= (uint32_t)p[E * k + e] << ((32 / E) * e);
+            w[k] = v;
         }
     }
+}
+
+// Level-1 column j of rows (a, b): word j / C, pair j % C.
+template <typename T, int NW>
+__device__ __forceinline__ int l1col(const uint32_t (&a)[NW], const uint32_t (&b)[NW], int j) {
+    return (int)Pk<T>::box(a[j / Pk<T>::C], b[j / Pk<T>::C], j % Pk<T>::C);
+}
+
+// A band of 2^L rows x NC samples (L = 2: 16 = 4 x 4; L = 3: 16 = 2 x 8): the
+// frame value(s) at level L and both fields at level L-1.
+template <typename T, int L, int NC>
+__device__ __forceinline__ void band_dot(const uint8_t* src, int64_t pitch, int y0, int x0, int W, bool al16,
+                                         Row<(NC >> L)>& f, Row<(NC >> (L - 1))>& u, Row<(NC >> (L - 1))>& d) {
+    constexpr int NW = NC / Pk<T>::E;
+    const bool fast = al16 && x0 + NC <= W;
+    if constexpr (L == 2) {
+        uint32_t w0[NW], w1[NW], w2[NW], w3[NW];
+        load_words<T, NW>(src + (int64_t)(y0 + 0) * pitch, x0, W, fast, w0);
+        load_words<T, NW>(src + (int64_t)(y0 + 1) * pitch, x0, W, fast, w1);
+        load_words<T, NW>(src + (int64_t)(y0 + 2) * pitch, x0, W, fast, w2);
+        load_words<T, NW>(src + (int64_t)(y0 + 3) * pitch, x0, W, fast, w3);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {                  // word k: columns 4k..4k+3
-        // level 1 of rows (0,1) and (2,3), then level 2
-        const uint32_t a0 = box2(w[0][k], w[1][k], LO), a1 = box2(w[0][k], w[1][k], HI);
-        const uint32_t b0 = box2(w[2][k], w[3][k], LO), b1 = box2(w[2][k], w[3][k], HI);
-        f.v[k] = (int)((a0 + a1 + b0 + b1 + 2u) >> 2);
-        // fields at level 1: rows (0,2) and (1,3)
-        u.v[2 * k] = (int)box2(w[0][k], w[2][k], LO);
-        u.v[2 * k + 1] = (int)box2(w[0][k], w[2][k], HI);
-        d.v[2 * k] = (int)box2(w[1][k], w[3][k], LO);
-        d.v[2 * k + 1] = (int)box2(w[1][k], w[3][k], HI);
+        for (int i = 0; i < (NC >> 2); ++i) {   // level 1 of rows (0,1) and (2,3), then level 2
+            const int a0 = l1col<T>(w0, w1, 2 * i), a1 = l1col<T>(w0, w1, 2 * i + 1);
+            const int b0 = l1col<T>(w2, w3, 2 * i), b1 = l1col<T>(w2, w3, 2 * i + 1);
+            f.v[i] = (a0 + a1 + b0 + b1 + 2) >> 2;
+        }
+#pragma unroll
+        for (int j = 0; j < (NC >> 1); ++j) {   // fields at level 1: rows (0,2) and (1,3)
+            u.v[j] = l1col<T>(w0, w2, j);
+            d.v[j] = l1col<T>(w1, w3, j);
+        }
+    } else {
+        static_assert(L == 3, "working levels 2 and 3");
+        int l2[2][NC >> 2], uf[2][NC >> 1], df[2][NC >> 1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {           // rows 4h .. 4h+3
+            uint32_t w0[NW], w1[NW], w2[NW], w3[NW];
+            load_words<T, NW>(src + (int64_t)(y0 + 4 * h + 0) * pitch, x0, W, fast, w0);
+            load_words<T, NW>(src + (int64_t)(y0 + 4 * h + 1) * pitch, x0, W, fast, w1);
+            load_words<T, NW>(src + (int64_t)(y0 + 4 * h + 2) * pitch, x0, W, fast, w2);
+            load_words<T, NW>(src + (int64_t)(y0 + 4 * h + 3) * pitch, x0, W, fast, w3);
+#pragma unroll
+            for (int k = 0; k < (NC >> 2); ++k) {
+                const int a0 = l1col<T>(w0, w1, 2 * k), a1 = l1col<T>(w0, w1, 2 * k + 1);
+                const int b0 = l1col<T>(w2, w3, 2 * k), b1 = l1col<T>(w2, w3, 2 * k + 1);
+                l2[h][k] = (a0 + a1 + b0 + b1 + 2) >> 2;
+            }
+#pragma unroll
+            for (int j = 0; j < (NC >> 1); ++j) {   // fields at level 1: rows (4h, 4h+2), (4h+1, 4h+3)
+                uf[h][j] = l1col<T>(w0, w2, j);
+                df[h][j] = l1col<T>(w1, w3, j);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < (NC >> 3); ++i)
+            f.v[i] = (l2[0][2 * i] + l2[0][2 * i + 1] + l2[1][2 * i] + l2[1][2 * i + 1] + 2) >> 2;
+#pragma unroll
+        for (int k = 0; k < (NC >> 2); ++k) {   // fields at level 2
+            u.v[k] = (uf[0][2 * k] + uf[0][2 * k + 1] + uf[1][2 * k] + uf[1][2 * k + 1] + 2) >> 2;
+            d.v[k] = (df[0][2 * k] + df[0][2 * k + 1] + df[1][2 * k] + df[1][2 * k + 1] + 2) >> 2;
+        }
     }
 }
 
@@ -257,8 +322,8 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
             }
         } else {
             Band<NC, L> b;
-            if constexpr (sizeof(T) == 1 && L == 2) {
-                band_l2_u8(src, pitch, YL * S, X * S, sd.W, al16, b.f, b.u, b.d);
+            if constexpr (L == 2 || L == 3) {
+                band_dot<T, L, NC>(src, pitch, YL * S, X * S, sd.W, al16, b.f, b.u, b.d);
             } else {
                 build_band<T, NC, L>(src, pitch, YL * S, X * S, sd.W, al16, b);
             }

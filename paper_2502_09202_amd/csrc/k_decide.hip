@@ -15,11 +15,12 @@
 // the fast check fired) is planned in one step and committed in the next one,
 // after the step's motion-search launch has computed the requested pairs;
 // iterations that need nothing more are committed at once.  The planned
-// tasks of all streams are compacted into one dense list (per-stream counts,
-// a block-wide exclusive scan built from wave ballots/prefix sums, then each
-// stream writes its tasks at its offset) together with the running tile
-// offsets that the persistent motion-search grid walks.  Finished frames and
-// shots are appended to device output rings in (stream, frame) order.
+// tasks of all streams are compacted into one dense list: each workgroup sums
+// its streams' task and tile counts, reserves its slice of the list and of the
+// tile range with one packed 64-bit atomic, hands each stream its offsets (a
+// running sum over the workgroup's waves), and each stream writes its tasks
+// there, with the running tile offsets that the persistent motion-search grid
+// walks.  Finished frames and shots are appended to device output rings.
 //
 // All floating-point comparisons use the operations in the order written,
 // with no contraction (-ffp-contract=off), so that the labels are bitwise

@@ -303,6 +303,59 @@ int32_t vsa_engine_tuning(vsa_engine* e, int32_t bucket, int32_t* best, int32_t*
  * totals. */
 vsa_status vsa_engine_kernel_times(vsa_engine* e, double* ms, uint64_t* launches, int32_t reset);
 
+/* ---- offline form: one whole clip, look-ahead batched --------------------- */
+
+/* The same analysis as a stream of the engine (Sec. III: identical records and
+ * shots), for one clip whose frames are all at hand.  Instead of one frame per
+ * step, `chunk` frames at a time go through the pyramid and the consecutive
+ * pairs' motion search in one launch each; the sequential pass (Sec. III.B-D)
+ * then runs over them, with rounds of sparse pairs (Sec. III.A's selective
+ * schedule) wherever it asks for measures, before the next chunk.  A lone
+ * clip thus fills the GPU without other streams beside it. */
+typedef struct vsa_clip vsa_clip;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal                                        */
+    int32_t width, height;     /* full-resolution luma size of every frame                  */
+    int32_t bit_depth;         /* 8 or 10                                                   */
+    int32_t k_max;             /* 0 = params default, else 1..15                            */
+    int32_t chunk;             /* frames per chunk, 1..4096; 0 = 256.  Device memory grows
+                                  with it (a ring of chunk + 2 k_max + 8 frame slots)        */
+    int32_t schedule;          /* VSA_SCHEDULE_SPARSE (the paper's) or VSA_SCHEDULE_DENSE   */
+    int32_t no_intensity;      /* 1: skip H(t) (h_mean/h_std/h_mad are NaN)                 */
+    int32_t me_wgs_per_cu;     /* persistent motion-search workgroups per CU, 0 = default   */
+    const vsa_params* params;  /* NULL = built-in defaults                                  */
+} vsa_clip_config;
+
+/* Create a clip analyser on cfg->device and allocate its device memory (sized
+ * by frame size, k_max and chunk).  Errors as vsa_engine_create, and
+ * VSA_E_INVAL for a frame smaller than a 2 x 2 grid of blocks at the working
+ * level or a chunk outside 1..4096. */
+vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out);
+
+/* Wait for the analyser's work and free it.  NULL is a no-op. */
+void vsa_clip_destroy(vsa_clip* c);
+
+/* Analyse the n_frames frames of one clip; returns when every record is out.
+ * Frame i is the plane at frames + i * frame_stride_bytes with rows
+ * pitch_bytes apart, in host memory (src = VSA_SRC_HOST: uploaded chunk by
+ * chunk) or device memory (VSA_SRC_DEVICE_BORROW: read in place; the caller
+ * keeps it valid until the call returns).  out_frames receives n_frames
+ * records in frame order (pts = frame index); out_shots the first shots_cap
+ * shot records, and *n_shots (nullable) the clip's shot count, which may
+ * exceed shots_cap (n_frames + 1 always suffices).  Both arrays are the
+ * caller's.  n_frames = 0 gives no records and no shots.  Errors: VSA_E_INVAL
+ * (NULL, pitch below a row, stride below a frame, bad src), VSA_E_NOMEM,
+ * VSA_E_DEVICE.  Calls on one analyser are serialised. */
+vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_bytes, int64_t pitch_bytes,
+                        int32_t n_frames, int32_t src, vsa_frame_result* out_frames,
+                        vsa_shot_result* out_shots, int32_t shots_cap, int32_t* n_shots);
+
+/* Instrumentation (not in the paper): the first n of [0] chunks processed,
+ * [1] decision launches (one per chunk plus one per round), [2] host waits,
+ * [3] sparse pair tasks computed, summed over the analyser's runs. */
+vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n);
+
 /* Thread-local description of the last error; valid until the next call. */
 const char* vsa_last_error(void);
 

@@ -34,6 +34,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -196,6 +197,21 @@ void layout(const Geo& g, int W, int H, int bits, int kmax, StreamDesc& sd) {
     off = round_up(off + (int64_t)sizeof(uint32_t) * (1 << bits), 256);
     sd.slot_bytes = off;
     sd.B_L = (g.wl[0] / 8) * (g.hl[0] / 8);
+}
+
+// The moments and the intensity sums are exact 64-bit integers: refuse
+// frames whose sums could overflow.
+vsa_status check_exact_sums(const StreamDesc& sd) {
+    // covariance terms need N (Sxx) products to stay below 2^63
+    const int64_t maxv = sd.bits == 8 ? 255 : 1023;
+    const int64_t nmax = 64LL * std::max<int64_t>((int64_t)(sd.wf / 8) * (sd.hf / 8), sd.B_L);
+    if ((double)nmax * (double)nmax * (double)(maxv * maxv) >= 9.2e18)
+        return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit moments");
+    // and the intensity sums over the working level (N S2 < 2^63)
+    const double npx = (double)sd.wl[0] * (double)sd.hl[0];
+    if (npx * npx * (double)(maxv * maxv) >= 9.2e18)
+        return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit intensity sums");
+    return VSA_OK;
 }
 
 int max_sparse_tiles(const StreamDesc& sd) {
@@ -722,15 +738,8 @@ static vsa_status prepare_stream(const vsa_engine* e, const vsa_stream_desc* d, 
     vsa_status st = make_geo(d->width, d->height, e->params, kmax, g);
     if (st != VSA_OK) return st;
     layout(g, d->width, d->height, d->bit_depth, kmax, sd);
-    // exact int64 covariance terms need N (Sxx) products to stay below 2^63
-    const int64_t maxv = d->bit_depth == 8 ? 255 : 1023;
-    const int64_t nmax = 64LL * std::max<int64_t>((int64_t)(sd.wf / 8) * (sd.hf / 8), sd.B_L);
-    if ((double)nmax * (double)nmax * (double)(maxv * maxv) >= 9.2e18)
-        return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit moments");
-    // and the intensity sums over the working level (N S2 < 2^63)
-    const double npx = (double)sd.wl[0] * (double)sd.hl[0];
-    if (npx * npx * (double)(maxv * maxv) >= 9.2e18)
-        return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit intensity sums");
+    st = check_exact_sums(sd);
+    if (st != VSA_OK) return st;
     staging_pitch = round_up((int64_t)d->width * (d->bit_depth == 8 ? 1 : 2), 256);
     bytes = stream_bytes(sd, staging_pitch, !e->no_intensity);
     return VSA_OK;
@@ -1117,7 +1126,6 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     TileJob* cjobs = e->d_cjobs + (size_t)slot_s * M;
     int32_t* cmap = e->d_cmap + (size_t)slot_s * e->partials_cap;
     const int32_t* d_k1 = reinterpret_cast<const int32_t*>(ddesc + off_k1);
-    const PairTask* d_consec = reinterpret_cast<const PairTask*>(ddesc + off_consec);
     if (n_k1 > 0) {
         for (int gi = 0; gi < n_groups; ++gi) {
             const K1Group& gr = groups[gi];
@@ -1653,6 +1661,384 @@ vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, 
     if (err != hipSuccess) return hip_fail(err, "debug decide");
     if (n_shots) *n_shots = counts[0];
     if (n_keys) *n_keys = counts[1];
+    return VSA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Offline form: one whole clip with temporal look-ahead batching.
+//
+// The streaming engine advances each stream by one frame per step, so a lone
+// stream pays a step's launches and host work for every frame.  Here all
+// frames of the clip are at hand and are taken `chunk` at a time; per chunk,
+// on one HIP stream:
+//   K1  pyramid, fields and intensity measure of every frame of the chunk
+//       (one launch);
+//   K2  motion search of every consecutive pair that ends in the chunk (one
+//       persistent launch), then the pairs' finishing arithmetic (k_finish);
+//   K6  the sequential pass over the new frames until it asks for sparse
+//       measures, then rounds of (K2 over the requested pairs, K6) until it
+//       waits for frames of the next chunk or, at the end of the clip, has
+//       closed the last shot.
+// Each frame of a chunk is a pyramid entry of its own: the chunk's stream
+// descriptors are copies of the clip's, sharing its ring, motion fields and
+// frame records, each with its own tile histograms.  The ring holds the chunk
+// plus the deep check's look-back and look-ahead, so a chunk never overwrites
+// a frame that the pass can still read.  The host learns whether another
+// round is needed from the cursor snapshot each decision launch writes into
+// mapped memory: it enqueues as many rounds as the previous chunk took before
+// it first waits, then four at a time.
+struct vsa_clip {
+    std::mutex mu;
+    int device = 0;
+    DecideParams dp{};
+    bool no_intensity = false;
+    int C = 0;                     // frames per chunk
+    StreamDesc sd{};               // the clip's descriptor (ring of C + 2 k_max + 8 slots)
+    int pyr_tiles = 0;             // pyramid tiles per frame
+    int pair_tiles = 0;            // motion-search tiles of a consecutive pair
+    int sparse_tiles = 0;          // most tiles one round's sparse pairs can have
+    int grid_c = 0, grid_s = 0;    // persistent motion-search grids
+    hipStream_t s = nullptr;
+    uint8_t* mem = nullptr;        // ring, frame records, motion fields, tile histograms
+    StreamDesc* d_sds = nullptr;   // C descriptors (entry i: frame i of the chunk)
+    DecideState* d_state = nullptr;
+    DeviceCursors* d_cur = nullptr;
+    vsa_shot_result* d_closed = nullptr;
+    uint8_t* d_desc = nullptr;     // StepStream[C + 2], pyramid list[C], consecutive tasks[C]
+    uint8_t* h_desc = nullptr;     // its pinned source
+    size_t desc_bytes = 0, off_k1 = 0, off_cons = 0;
+    DecideState* h_init = nullptr; // pinned source of the decision state's reset
+    TileJob* d_cjobs = nullptr;    // C
+    int32_t* d_cmap = nullptr;     // C x pair_tiles
+    TilePartial* d_part = nullptr; // C x pair_tiles (consecutive), then sparse_tiles
+    PairTask* d_sparse = nullptr;  // 2 x kMaxTasksPerStream (by decision-launch parity)
+    TileJob* d_sjobs = nullptr;    // 2 x kMaxTasksPerStream
+    int32_t* d_smap = nullptr;     // 2 x sparse_tiles
+    OutFrame* h_out_frames = nullptr;
+    OutFrame* d_out_frames = nullptr;
+    OutShot* h_out_shots = nullptr;
+    OutShot* d_out_shots = nullptr;
+    uint64_t out_cap = 0;
+    PubSnap* h_snap = nullptr;     // [2], by decision-launch parity
+    PubSnap* d_snap = nullptr;
+    uint8_t* d_stage = nullptr;    // host-sourced frames of one chunk
+    int64_t stage_pitch = 0, stage_bytes = 0;
+    int64_t dec_no = 0;            // decision launches in the current run
+    int est_rounds = 8;            // rounds enqueued before the first wait of a chunk
+    uint64_t counters[4] = {0};    // chunks, decision launches, host waits, sparse tasks
+};
+
+namespace {
+
+int64_t clip_info_offset(const StreamDesc& sd) { return sd.slot_bytes * sd.rs; }
+int64_t clip_mv_offset(const StreamDesc& sd) {
+    return clip_info_offset(sd) + round_up((int64_t)sizeof(FrameInfo) * sd.rs, 256);
+}
+int64_t clip_tileh_offset(const StreamDesc& sd) { return clip_mv_offset(sd) + round_up((int64_t)sd.rs * sd.B_L * 2, 256); }
+
+// Everything the sequential pass and the sparse pairs of one decision launch
+// need: the sparse K2 over the tasks the previous launch planned (it also
+// clears the counter this launch plans into), then K6 for the clip's entry.
+vsa_status clip_decide(vsa_clip* c, const StepStream* d_entry) {
+    const int par = (int)(c->dec_no & 1);
+    const size_t tc = kMaxTasksPerStream;
+    PairTask* sp_prev = c->d_sparse + (size_t)(par ^ 1) * tc;
+    PairTask* sp_next = c->d_sparse + (size_t)par * tc;
+    TileJob* sj_prev = c->d_sjobs + (size_t)(par ^ 1) * tc;
+    TileJob* sj_next = c->d_sjobs + (size_t)par * tc;
+    int32_t* sm_prev = c->d_smap + (size_t)(par ^ 1) * c->sparse_tiles;
+    int32_t* sm_next = c->d_smap + (size_t)par * c->sparse_tiles;
+    TilePartial* spart = c->d_part + (size_t)c->C * c->pair_tiles;
+    HIPCK(launch_me(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, spart, nullptr,
+                    nullptr, c->grid_s, c->s),
+          "motion search launch");
+    HIPCK(launch_finish_decide(c->d_sds, c->d_state, d_entry, 1, c->dp, c->d_part, spart, sp_prev, sp_next, c->d_cur,
+                               c->d_out_frames, c->out_cap, c->d_out_shots, c->out_cap, nullptr, 0, c->d_closed, par,
+                               c->d_snap + par, sj_next, sm_next, c->s),
+          "decide launch");
+    c->dec_no += 1;
+    c->counters[1] += 1;
+    return VSA_OK;
+}
+
+// Whether the last decision launch planned sparse tasks (after a wait).
+bool clip_pending(const vsa_clip* c) {
+    const int64_t j = c->dec_no - 1;
+    const uint64_t now = c->h_snap[j & 1].sparse_run;
+    const uint64_t before = j >= 1 ? c->h_snap[(j - 1) & 1].sparse_run : 0;
+    return now != before;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vsa_clip_destroy(vsa_clip* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->s) (void)hipStreamSynchronize(c->s);
+    void* dev[] = {c->mem, c->d_sds, c->d_state, c->d_cur, c->d_closed, c->d_desc, c->d_cjobs, c->d_cmap,
+                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    void* host[] = {c->h_desc, c->h_init, c->h_out_frames, c->h_out_shots, c->h_snap};
+    for (void* p : host)
+        if (p) (void)hipHostFree(p);
+    if (c->s) (void)hipStreamDestroy(c->s);
+    delete c;
+}
+
+vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
+    if (!cfg || !out) return fail(VSA_E_INVAL, "NULL argument");
+    *out = nullptr;
+    vsa_params p;
+    if (cfg->params) p = *cfg->params;
+    else vsa_default_params(&p);
+    vsa_status st = check_params(p);
+    if (st != VSA_OK) return st;
+    if (cfg->bit_depth != 8 && cfg->bit_depth != 10) return fail(VSA_E_INVAL, "bit_depth must be 8 or 10");
+    const int kmax = cfg->k_max ? cfg->k_max : p.k_max;
+    if (kmax < 1 || kmax > kMaxKmax) return fail(VSA_E_INVAL, "k_max must be in 1..15");
+    if (cfg->schedule != VSA_SCHEDULE_SPARSE && cfg->schedule != VSA_SCHEDULE_DENSE)
+        return fail(VSA_E_INVAL, "unknown schedule");
+    const int C = cfg->chunk ? cfg->chunk : 256;
+    if (C < 1 || C > 4096) return fail(VSA_E_INVAL, "chunk must be in 1..4096");
+    if (cfg->me_wgs_per_cu < 0 || cfg->me_wgs_per_cu > 8) return fail(VSA_E_INVAL, "me_wgs_per_cu must be in 0..8");
+    Geo g;
+    st = make_geo(cfg->width, cfg->height, p, kmax, g);
+    if (st != VSA_OK) return st;
+    StreamDesc sd;
+    layout(g, cfg->width, cfg->height, cfg->bit_depth, kmax, sd);
+    st = check_exact_sums(sd);
+    if (st != VSA_OK) return st;
+    // the chunk being ingested, the deep check's look-back (k_max + 1) and
+    // look-ahead (k_max + 1) behind it, and slack
+    sd.rs = C + 2 * kmax + 8;
+    sd.epoch = 1;
+    HIPCK(hipSetDevice(cfg->device), "hipSetDevice");
+    vsa_clip* c = new vsa_clip;
+    std::unique_ptr<vsa_clip, void (*)(vsa_clip*)> guard(c, vsa_clip_destroy);
+    c->device = cfg->device;
+    c->dp = decide_params(p, cfg->schedule == VSA_SCHEDULE_DENSE);
+    c->no_intensity = cfg->no_intensity != 0;
+    c->C = C;
+    c->pyr_tiles = pyramid_tiles(sd);
+    c->pair_tiles = me_tiles(sd.wl[0], sd.hl[0]);
+    c->sparse_tiles = max_sparse_tiles(sd);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    auto grid = [&](int64_t tiles, int w) {
+        int gsz = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)w * cus);
+        if (gsz >= 8) gsz -= gsz % 8;   // whole groups of one workgroup per XCD
+        return gsz;
+    };
+    const int wgs = cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2;
+    c->grid_c = grid((int64_t)C * c->pair_tiles, wgs);
+    c->grid_s = grid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
+    HIPCK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking), "hipStreamCreate");
+    const int64_t thb = tile_hist_bytes(sd, !c->no_intensity);
+    const int64_t mem_bytes = clip_tileh_offset(sd) + thb * C;
+    auto dalloc = [](void** p_, size_t n) { return hipMalloc(p_, std::max<size_t>(n, 256)) == hipSuccess; };
+    c->desc_bytes = round_up(sizeof(StepStream) * (C + 2), 256);
+    c->off_k1 = c->desc_bytes;
+    c->desc_bytes += round_up(sizeof(int32_t) * C, 256);
+    c->off_cons = c->desc_bytes;
+    c->desc_bytes += round_up(sizeof(PairTask) * C, 256);
+    const size_t tc = kMaxTasksPerStream;
+    bool ok = dalloc((void**)&c->mem, mem_bytes) && dalloc((void**)&c->d_sds, sizeof(StreamDesc) * C) &&
+              dalloc((void**)&c->d_state, sizeof(DecideState)) && dalloc((void**)&c->d_cur, sizeof(DeviceCursors)) &&
+              dalloc((void**)&c->d_closed, sizeof(vsa_shot_result) * kMaxClosed) &&
+              dalloc((void**)&c->d_desc, c->desc_bytes) && dalloc((void**)&c->d_cjobs, sizeof(TileJob) * C) &&
+              dalloc((void**)&c->d_cmap, sizeof(int32_t) * C * c->pair_tiles) &&
+              dalloc((void**)&c->d_part, sizeof(TilePartial) * ((size_t)C * c->pair_tiles + c->sparse_tiles)) &&
+              dalloc((void**)&c->d_sparse, 2 * sizeof(PairTask) * tc) &&
+              dalloc((void**)&c->d_sjobs, 2 * sizeof(TileJob) * tc) &&
+              dalloc((void**)&c->d_smap, 2 * sizeof(int32_t) * c->sparse_tiles);
+    if (!ok) return fail(VSA_E_NOMEM, "clip device buffers");
+    // records out: a chunk emits at most its frames plus the backlog the pass
+    // held (< rs); shots never outnumber frames + 3
+    c->out_cap = (uint64_t)(2 * (C + sd.rs) + 64);
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
+    ok = hipHostMalloc((void**)&c->h_desc, c->desc_bytes, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_init, sizeof(DecideState), hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_out_frames, sizeof(OutFrame) * c->out_cap, mapped) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->d_out_frames, c->h_out_frames, 0) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_out_shots, sizeof(OutShot) * c->out_cap, mapped) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->d_out_shots, c->h_out_shots, 0) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_snap, 2 * sizeof(PubSnap), mapped) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->d_snap, c->h_snap, 0) == hipSuccess;
+    if (!ok) return fail(VSA_E_NOMEM, "clip pinned buffers");
+    sd.ring = c->mem;
+    sd.info = reinterpret_cast<FrameInfo*>(c->mem + clip_info_offset(sd));
+    sd.mv = reinterpret_cast<int8_t*>(c->mem + clip_mv_offset(sd));
+    c->sd = sd;
+    std::vector<StreamDesc> sds(C, sd);
+    for (int i = 0; i < C; ++i)
+        sds[i].tileh = c->no_intensity ? nullptr
+                                       : reinterpret_cast<uint16_t*>(c->mem + clip_tileh_offset(sd) + thb * i);
+    c->sd.tileh = sds[0].tileh;
+    HIPCK(hipMemcpy(c->d_sds, sds.data(), sizeof(StreamDesc) * C, hipMemcpyHostToDevice), "descriptor upload");
+    *out = guard.release();
+    return VSA_OK;
+}
+
+vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_bytes, int64_t pitch_bytes,
+                        int32_t n_frames, int32_t src, vsa_frame_result* out_frames, vsa_shot_result* out_shots,
+                        int32_t shots_cap, int32_t* n_shots) {
+    if (!c) return fail(VSA_E_INVAL, "NULL clip");
+    if (n_frames < 0) return fail(VSA_E_INVAL, "negative frame count");
+    if (n_frames > 0 && (!frames || !out_frames)) return fail(VSA_E_INVAL, "NULL frames or records");
+    if (shots_cap < 0 || (shots_cap > 0 && !out_shots)) return fail(VSA_E_INVAL, "bad shot array");
+    if (src != VSA_SRC_HOST && src != VSA_SRC_DEVICE_BORROW) return fail(VSA_E_INVAL, "src must be host or device");
+    if (n_shots) *n_shots = 0;
+    if (n_frames == 0) return VSA_OK;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const StreamDesc& sd = c->sd;
+    const int64_t row = (int64_t)sd.W * (sd.bits == 8 ? 1 : 2);
+    if (pitch_bytes < row) return fail(VSA_E_INVAL, "pitch smaller than a row");
+    if (n_frames > 1 && frame_stride_bytes < pitch_bytes * (sd.H - 1) + row)
+        return fail(VSA_E_INVAL, "frame stride smaller than a frame");
+    HIPCK(hipSetDevice(c->device), "hipSetDevice");
+    const int C = c->C, T = n_frames;
+    if (src == VSA_SRC_HOST && !c->d_stage) {
+        c->stage_pitch = round_up(row, 256);
+        c->stage_bytes = round_up(c->stage_pitch * sd.H, 256);
+        if (hipMalloc((void**)&c->d_stage, (size_t)c->stage_bytes * C) != hipSuccess) {
+            c->d_stage = nullptr;
+            return fail(VSA_E_NOMEM, "clip staging");
+        }
+    }
+    // a fresh pass: decision state, cursors, frame records and snapshots
+    init_state(*c->h_init);
+    HIPCK(hipMemcpyAsync(c->d_state, c->h_init, sizeof(DecideState), hipMemcpyHostToDevice, c->s), "state reset");
+    HIPCK(hipMemsetAsync(c->d_cur, 0, sizeof(DeviceCursors), c->s), "cursor reset");
+    HIPCK(hipMemsetAsync(sd.info, 0, sizeof(FrameInfo) * sd.rs, c->s), "record reset");
+    HIPCK(hipStreamSynchronize(c->s), "reset");
+    std::memset(c->h_snap, 0, 2 * sizeof(PubSnap));
+    c->dec_no = 0;
+    uint64_t frames_read = 0, shots_read = 0, run_tasks = 0;
+    const uint8_t* base = static_cast<const uint8_t*>(frames);
+    StepStream* steps = reinterpret_cast<StepStream*>(c->h_desc);
+    int32_t* k1 = reinterpret_cast<int32_t*>(c->h_desc + c->off_k1);
+    PairTask* cons = reinterpret_cast<PairTask*>(c->h_desc + c->off_cons);
+    const StepStream* d_steps = reinterpret_cast<const StepStream*>(c->d_desc);
+    const int32_t* d_k1 = reinterpret_cast<const int32_t*>(c->d_desc + c->off_k1);
+    const PairTask* d_cons = reinterpret_cast<const PairTask*>(c->d_desc + c->off_cons);
+    for (int f0 = 0; f0 < T; f0 += C) {
+        const int n = std::min(C, T - f0);
+        const bool last = f0 + n == T;
+        if (src == VSA_SRC_HOST)
+            for (int i = 0; i < n; ++i)
+                HIPCK(hipMemcpy2DAsync(c->d_stage + (int64_t)i * c->stage_bytes, c->stage_pitch,
+                                       base + (int64_t)(f0 + i) * frame_stride_bytes, pitch_bytes, row, sd.H,
+                                       hipMemcpyHostToDevice, c->s),
+                      "plane upload");
+        int n_cons = 0, ctiles = 0;
+        for (int i = 0; i < n; ++i) {
+            StepStream& ss = steps[i];
+            std::memset(&ss, 0, sizeof ss);
+            ss.sid = i;
+            ss.has_frame = 1;
+            ss.frame = f0 + i;
+            ss.ended_T = -1;
+            ss.pts = f0 + i;
+            if (src == VSA_SRC_HOST) {
+                ss.src = c->d_stage + (int64_t)i * c->stage_bytes;
+                ss.src_pitch = c->stage_pitch;
+            } else {
+                ss.src = base + (int64_t)(f0 + i) * frame_stride_bytes;
+                ss.src_pitch = pitch_bytes;
+            }
+            ss.k1_tiles = c->pyr_tiles;
+            ss.k1_prefix = i * c->pyr_tiles;
+            k1[i] = i;
+            if (f0 + i >= 1) {
+                PairTask& t = cons[n_cons++];
+                std::memset(&t, 0, sizeof t);
+                t.sid = i;
+                t.kind = MK_CONSEC;
+                t.ref = f0 + i - 1;
+                t.oth = f0 + i;
+                t.ref_field = t.oth_field = PL_FRAME;
+                t.level = sd.L;
+                t.result = -1;
+                t.tiles = c->pair_tiles;
+                t.tile_prefix = ctiles;
+                t.flags = TF_MV_RING;
+                t.epoch = sd.epoch;
+                ss.consec_tiles = c->pair_tiles;
+                ss.consec_prefix = ctiles;
+                ctiles += c->pair_tiles;
+            }
+        }
+        // the decision entries: the chunk's arrival, then the rounds after it
+        for (int k = 0; k < 2; ++k) {
+            StepStream& ss = steps[C + k];
+            std::memset(&ss, 0, sizeof ss);
+            ss.sid = 0;
+            ss.has_frame = k == 0;
+            ss.frame = k == 0 ? f0 + n - 1 : -1;
+            ss.ended_T = last ? T : -1;
+        }
+        HIPCK(hipMemcpyAsync(c->d_desc, c->h_desc, c->desc_bytes, hipMemcpyHostToDevice, c->s), "descriptor upload");
+        HIPCK(launch_pyramid(sd.bits, sd.L, c->d_sds, d_steps, d_k1, n, n * c->pyr_tiles, c->d_cjobs, c->d_cmap, c->s),
+              "pyramid launch");
+        if (!c->no_intensity) HIPCK(launch_intensity(c->d_sds, d_steps, d_k1, n, c->s), "intensity launch");
+        if (ctiles > 0) {
+            int gc = std::min(c->grid_c, ctiles);
+            if (gc >= 8) gc -= gc % 8;
+            HIPCK(launch_me(sd.bits, c->d_sds, c->d_cjobs, C, c->d_cmap, ctiles, nullptr, 0, false, c->d_part, nullptr,
+                            nullptr, gc, c->s),
+                  "motion search launch");
+            HIPCK(launch_finish(c->d_sds, d_cons, n_cons, ctiles, nullptr, nullptr, c->d_part, nullptr, c->dp, nullptr,
+                                nullptr, (n_cons + 3) / 4, 0, c->s),
+                  "finish launch");
+        }
+        vsa_status st = clip_decide(c, d_steps + C);
+        if (st != VSA_OK) return st;
+        // each round commits at least one iteration of the pass
+        const int limit = 4 * (n + sd.rs) + 64;
+        int rounds = 0, batch = c->est_rounds;
+        for (;;) {
+            for (int r = 0; r < batch; ++r, ++rounds) {
+                st = clip_decide(c, d_steps + C + 1);
+                if (st != VSA_OK) return st;
+            }
+            HIPCK(hipStreamSynchronize(c->s), "clip chunk");
+            c->counters[2] += 1;
+            if (!clip_pending(c)) break;
+            if (rounds > limit) return fail(VSA_E_DEVICE, "decision pass did not settle");
+            batch = 4;
+        }
+        c->est_rounds = std::min(rounds, 32);
+        c->counters[0] += 1;
+        // records of this chunk (mapped memory, complete after the wait)
+        const PubSnap ps = c->h_snap[(c->dec_no - 1) & 1];
+        if (ps.frames_written - frames_read > c->out_cap || ps.shots_written - shots_read > c->out_cap)
+            return fail(VSA_E_DEVICE, "clip record ring overflow");
+        for (uint64_t i = frames_read; i < ps.frames_written; ++i) {
+            const OutFrame& o = c->h_out_frames[i % c->out_cap];
+            if (o.r.frame != (int64_t)i || i >= (uint64_t)T) return fail(VSA_E_DEVICE, "clip records out of order");
+            out_frames[i] = o.r;
+        }
+        for (uint64_t i = shots_read; i < ps.shots_written; ++i)
+            if (i < (uint64_t)shots_cap) out_shots[i] = c->h_out_shots[i % c->out_cap].r;
+        frames_read = ps.frames_written;
+        shots_read = ps.shots_written;
+        run_tasks = ps.sparse_run;
+    }
+    c->counters[3] += run_tasks;
+    if (frames_read != (uint64_t)T) return fail(VSA_E_DEVICE, "clip ended with frames missing");
+    if (n_shots) *n_shots = (int32_t)shots_read;
+    return VSA_OK;
+}
+
+vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n) {
+    if (!c || !out || n < 0) return fail(VSA_E_INVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (int i = 0; i < n && i < 4; ++i) out[i] = c->counters[i];
     return VSA_OK;
 }
 

@@ -54,6 +54,12 @@ class EngineConfig(C.Structure):
     ]
 
 
+class ClipConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("bit_depth", C.c_int32),
+                ("k_max", C.c_int32), ("chunk", C.c_int32), ("schedule", C.c_int32), ("no_intensity", C.c_int32),
+                ("me_wgs_per_cu", C.c_int32), ("params", C.POINTER(Params))]
+
+
 class StreamDesc(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bit_depth", C.c_int32),
                 ("fps_num", C.c_int32), ("fps_den", C.c_int32), ("k_max", C.c_int32)]
@@ -81,7 +87,7 @@ SYMBOLS = [
     "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_get_histogram", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
-    "vsa_poll_frames_all",
+    "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters",
 ]
 
 _lib = None
@@ -135,6 +141,10 @@ def lib():
         "vsa_engine_kernel_times": (i32, [P, P, P, i32]),
         "vsa_engine_tuning": (i32, [P, i32, P, P, P, P, i32]),
         "vsa_get_histogram": (i32, [P, i32, i64, P, i32, P]),
+        "vsa_clip_create": (i32, [C.POINTER(ClipConfig), C.POINTER(P)]),
+        "vsa_clip_destroy": (None, [P]),
+        "vsa_clip_run": (i32, [P, P, i64, i64, i32, i32, P, P, i32, C.POINTER(i32)]),
+        "vsa_clip_counters": (i32, [P, P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -345,6 +355,68 @@ class Engine:
         out = np.zeros(max(n, 1), KEY_DTYPE)
         _check(lib().vsa_debug_measure_log(self.h, sid, _ptr(out), n), "debug_measure_log")
         return out[:n].copy()
+
+
+class Clip:
+    """An offline clip analyser; see vsa_clip_create (one clip at a time, all
+    its frames at hand, processed `chunk` frames per launch)."""
+
+    def __init__(self, width: int, height: int, bit_depth: int = 8, k_max: int = 0, chunk: int = 0,
+                 dense: bool = False, params: Optional[dict] = None, no_intensity: int = 0,
+                 me_wgs_per_cu: int = 0, device: int = 0):
+        self._params = make_params(params)
+        cfg = ClipConfig(device=device, width=width, height=height, bit_depth=bit_depth, k_max=k_max, chunk=chunk,
+                         schedule=SCHEDULE_DENSE if dense else SCHEDULE_SPARSE, no_intensity=no_intensity,
+                         me_wgs_per_cu=me_wgs_per_cu, params=C.pointer(self._params))
+        h = C.c_void_p()
+        _check(lib().vsa_clip_create(C.byref(cfg), C.byref(h)), "clip_create")
+        self.h = h
+        self.shape = (height, width)
+        self.bit_depth = bit_depth
+
+    def close(self):
+        if self.h:
+            lib().vsa_clip_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run(self, ptr, stride, pitch, T, src):
+        recs = np.zeros(T, FRAME_DTYPE)
+        shots = np.zeros(T + 1, SHOT_DTYPE)
+        ns = C.c_int32(0)
+        _check(lib().vsa_clip_run(self.h, ptr, stride, pitch, T, src, _ptr(recs), _ptr(shots), shots.size,
+                                  C.byref(ns)), "clip_run")
+        return {"frames": recs, "shots": shots[:ns.value].copy()}
+
+    def run(self, frames: np.ndarray) -> dict:
+        """Analyse a host clip [T, H, W] (uint8, or uint16 for 10 bits)."""
+        a = np.ascontiguousarray(frames)
+        assert a.ndim == 3 and a.shape[1:] == self.shape
+        pitch = a.shape[2] * a.itemsize          # (an empty array's strides may read 0)
+        return self._run(_ptr(a), pitch * a.shape[1], pitch, a.shape[0], SRC_HOST)
+
+    def run_tensor(self, t) -> dict:
+        """Analyse a CUDA tensor [T, H, W] read in place (rows contiguous)."""
+        assert t.dim() == 3 and t.is_cuda and t.stride(2) == 1 and tuple(t.shape[1:]) == self.shape
+        es = t.element_size()
+        return self._run(C.c_void_p(t.data_ptr()), t.stride(0) * es, t.stride(1) * es, t.shape[0],
+                         SRC_DEVICE_BORROW)
+
+    def counters(self) -> dict:
+        out = np.zeros(4, np.uint64)
+        _check(lib().vsa_clip_counters(self.h, _ptr(out), 4), "clip_counters")
+        return dict(zip(("chunks", "decision_launches", "waits", "sparse_tasks"), (int(x) for x in out)))
 
 
 def run_clip(frames: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8, dense: bool = False,

@@ -75,3 +75,20 @@ def test_engine_config_checks(vsa):
     lib = vsa.lib()
     assert lib.vsa_collect(None, None) == vsa.E_INVAL
     assert lib.vsa_poll_frames_all(None, None, None, 0) == vsa.E_INVAL
+
+
+def test_clip_config_checks(vsa):
+    # checked before any device call, so they run without a GPU
+    for kw in (dict(chunk=-1), dict(chunk=4097), dict(bit_depth=9), dict(k_max=16), dict(me_wgs_per_cu=9)):
+        with pytest.raises(vsa.VsaError) as ei:
+            vsa.Clip(64, 32, **kw)
+        assert ei.value.code == vsa.E_INVAL, kw
+    for w, h in ((15, 16), (16, 15), (0, 16)):
+        with pytest.raises(vsa.VsaError) as ei:
+            vsa.Clip(w, h)
+        assert ei.value.code == vsa.E_INVAL
+    lib = vsa.lib()
+    assert lib.vsa_clip_create(None, None) == vsa.E_INVAL
+    lib.vsa_clip_destroy(None)   # no-op
+    assert lib.vsa_clip_run(None, None, 0, 0, 0, 0, None, None, 0, None) == vsa.E_INVAL
+    assert lib.vsa_clip_counters(None, None, 0) == vsa.E_INVAL

@@ -1671,48 +1671,57 @@ vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, 
 //
 // The streaming engine advances each stream by one frame per step, so a lone
 // stream pays a step's launches and host work for every frame.  Here all
-// frames of the clip are at hand and are taken `chunk` at a time; per chunk,
-// on one HIP stream:
-//   K1  pyramid, fields and intensity measure of every frame of the chunk
-//       (one launch);
-//   K2  motion search of every consecutive pair that ends in the chunk (one
-//       persistent launch), then the pairs' finishing arithmetic (k_finish);
-//   K6  the sequential pass over the new frames until it asks for sparse
-//       measures, then rounds of (K2 over the requested pairs, K6) until it
-//       waits for frames of the next chunk or, at the end of the clip, has
-//       closed the last shot.
-// Each frame of a chunk is a pyramid entry of its own: the chunk's stream
-// descriptors are copies of the clip's, sharing its ring, motion fields and
-// frame records, each with its own tile histograms.  The ring holds the chunk
-// plus the deep check's look-back and look-ahead, so a chunk never overwrites
-// a frame that the pass can still read.  The host learns whether another
-// round is needed from the cursor snapshot each decision launch writes into
-// mapped memory: it enqueues as many rounds as the previous chunk took before
-// it first waits, then four at a time.
+// frames of the clip are at hand and are taken `chunk` at a time:
+//   ingest stream (P), per chunk:
+//     K1  pyramid, fields and intensity measure of every frame of the chunk
+//         (one launch);
+//     K2  motion search of every consecutive pair that ends in the chunk
+//         (one persistent launch);
+//   decision stream (D), per chunk, once P has finished it:
+//     the pairs' finishing arithmetic into the frame records (k_finish);
+//     K6, the sequential pass over the new frames until it asks for sparse
+//     measures, then rounds of (K2 over the requested pairs, K6) until it
+//     waits for frames of the next chunk or, at the end of the clip, has
+//     closed the last shot.
+// P ingests chunk c+1 while D runs the rounds of chunk c.  The finishing
+// arithmetic stays on D: it writes the record of the chunk's first pair,
+// whose reference frame is the previous chunk's last, which that chunk's
+// decisions may still be labelling.  Each frame of a chunk is a pyramid entry
+// of its own: the chunk's stream descriptors are copies of the clip's,
+// sharing its ring, motion fields and frame records, each with its own tile
+// histograms.  Descriptors, jobs, tile maps, partials and tile histograms are
+// double-buffered by chunk parity.  The ring holds two chunks plus the deep
+// check's look-back and look-ahead, so an ingested chunk never overwrites a
+// frame that the pass can still read.  The host learns whether another round
+// is needed from the cursor snapshot each decision launch writes into mapped
+// memory: it enqueues as many rounds as the previous chunk took before it
+// first waits, then four at a time.
 struct vsa_clip {
     std::mutex mu;
     int device = 0;
     DecideParams dp{};
     bool no_intensity = false;
     int C = 0;                     // frames per chunk
-    StreamDesc sd{};               // the clip's descriptor (ring of C + 2 k_max + 8 slots)
+    StreamDesc sd{};               // the clip's descriptor (ring of 2 chunk + 2 k_max + 8 slots)
     int pyr_tiles = 0;             // pyramid tiles per frame
     int pair_tiles = 0;            // motion-search tiles of a consecutive pair
     int sparse_tiles = 0;          // most tiles one round's sparse pairs can have
     int grid_c = 0, grid_s = 0;    // persistent motion-search grids
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;       // decisions (D)
+    hipStream_t sp = nullptr;      // ingest (P)
+    hipEvent_t ev_p[2] = {};       // P has finished the chunk of that parity
     uint8_t* mem = nullptr;        // ring, frame records, motion fields, tile histograms
-    StreamDesc* d_sds = nullptr;   // C descriptors (entry i: frame i of the chunk)
+    StreamDesc* d_sds = nullptr;   // 2 x C descriptors (entry q C + i: frame i of a chunk of parity q)
     DecideState* d_state = nullptr;
     DeviceCursors* d_cur = nullptr;
     vsa_shot_result* d_closed = nullptr;
-    uint8_t* d_desc = nullptr;     // StepStream[C + 2], pyramid list[C], consecutive tasks[C]
-    uint8_t* h_desc = nullptr;     // its pinned source
+    uint8_t* d_desc = nullptr;     // per parity: StepStream[C + 2], pyramid list[C], consecutive tasks[C]
+    uint8_t* h_desc = nullptr;     // its pinned source (per parity)
     size_t desc_bytes = 0, off_k1 = 0, off_cons = 0;
     DecideState* h_init = nullptr; // pinned source of the decision state's reset
-    TileJob* d_cjobs = nullptr;    // C
-    int32_t* d_cmap = nullptr;     // C x pair_tiles
-    TilePartial* d_part = nullptr; // C x pair_tiles (consecutive), then sparse_tiles
+    TileJob* d_cjobs = nullptr;    // 2 x C
+    int32_t* d_cmap = nullptr;     // 2 x C x pair_tiles
+    TilePartial* d_part = nullptr; // 2 x C x pair_tiles (consecutive), then sparse_tiles
     PairTask* d_sparse = nullptr;  // 2 x kMaxTasksPerStream (by decision-launch parity)
     TileJob* d_sjobs = nullptr;    // 2 x kMaxTasksPerStream
     int32_t* d_smap = nullptr;     // 2 x sparse_tiles
@@ -1723,7 +1732,7 @@ struct vsa_clip {
     uint64_t out_cap = 0;
     PubSnap* h_snap = nullptr;     // [2], by decision-launch parity
     PubSnap* d_snap = nullptr;
-    uint8_t* d_stage = nullptr;    // host-sourced frames of one chunk
+    uint8_t* d_stage = nullptr;    // host-sourced frames of two chunks
     int64_t stage_pitch = 0, stage_bytes = 0;
     int64_t dec_no = 0;            // decision launches in the current run
     int est_rounds = 8;            // rounds enqueued before the first wait of a chunk
@@ -1750,7 +1759,7 @@ vsa_status clip_decide(vsa_clip* c, const StepStream* d_entry) {
     TileJob* sj_next = c->d_sjobs + (size_t)par * tc;
     int32_t* sm_prev = c->d_smap + (size_t)(par ^ 1) * c->sparse_tiles;
     int32_t* sm_next = c->d_smap + (size_t)par * c->sparse_tiles;
-    TilePartial* spart = c->d_part + (size_t)c->C * c->pair_tiles;
+    TilePartial* spart = c->d_part + (size_t)2 * c->C * c->pair_tiles;
     HIPCK(launch_me(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, spart, nullptr,
                     nullptr, c->grid_s, c->s),
           "motion search launch");
@@ -1771,6 +1780,103 @@ bool clip_pending(const vsa_clip* c) {
     return now != before;
 }
 
+// Where the frames of one run come from.
+struct ClipSource {
+    const uint8_t* base;
+    int64_t stride, pitch;
+    int32_t T, src;
+};
+
+// Fill the descriptors of chunk ch (parity ch & 1) and enqueue its ingest on
+// P: host-sourced planes, descriptor upload, K1 (+ intensity), consecutive
+// K2; then record ev_p of its parity.  *n_cons receives its consecutive pairs.
+vsa_status clip_ingest(vsa_clip* c, const ClipSource& in, int ch, int* n_cons_out, int* ctiles_out) {
+    const StreamDesc& sd = c->sd;
+    const int C = c->C, q = ch & 1;
+    const int f0 = ch * C, n = std::min(C, in.T - f0);
+    const bool last = f0 + n == in.T;
+    const int64_t row = (int64_t)sd.W * (sd.bits == 8 ? 1 : 2);
+    uint8_t* h = c->h_desc + (size_t)q * c->desc_bytes;
+    uint8_t* dd = c->d_desc + (size_t)q * c->desc_bytes;
+    StepStream* steps = reinterpret_cast<StepStream*>(h);
+    int32_t* k1 = reinterpret_cast<int32_t*>(h + c->off_k1);
+    PairTask* cons = reinterpret_cast<PairTask*>(h + c->off_cons);
+    uint8_t* stage = c->d_stage ? c->d_stage + (int64_t)q * C * c->stage_bytes : nullptr;
+    if (in.src == VSA_SRC_HOST)
+        for (int i = 0; i < n; ++i)
+            HIPCK(hipMemcpy2DAsync(stage + (int64_t)i * c->stage_bytes, c->stage_pitch,
+                                   in.base + (int64_t)(f0 + i) * in.stride, in.pitch, row, sd.H,
+                                   hipMemcpyHostToDevice, c->sp),
+                  "plane upload");
+    int n_cons = 0, ctiles = 0;
+    for (int i = 0; i < n; ++i) {
+        StepStream& ss = steps[i];
+        std::memset(&ss, 0, sizeof ss);
+        ss.sid = q * C + i;
+        ss.has_frame = 1;
+        ss.frame = f0 + i;
+        ss.ended_T = -1;
+        ss.pts = f0 + i;
+        if (in.src == VSA_SRC_HOST) {
+            ss.src = stage + (int64_t)i * c->stage_bytes;
+            ss.src_pitch = c->stage_pitch;
+        } else {
+            ss.src = in.base + (int64_t)(f0 + i) * in.stride;
+            ss.src_pitch = in.pitch;
+        }
+        ss.k1_tiles = c->pyr_tiles;
+        ss.k1_prefix = i * c->pyr_tiles;
+        k1[i] = i;
+        if (f0 + i >= 1) {
+            PairTask& t = cons[n_cons++];
+            std::memset(&t, 0, sizeof t);
+            t.sid = q * C + i;
+            t.kind = MK_CONSEC;
+            t.ref = f0 + i - 1;
+            t.oth = f0 + i;
+            t.ref_field = t.oth_field = PL_FRAME;
+            t.level = sd.L;
+            t.result = -1;
+            t.tiles = c->pair_tiles;
+            t.tile_prefix = ctiles;
+            t.flags = TF_MV_RING;
+            t.epoch = sd.epoch;
+            ss.consec_tiles = c->pair_tiles;
+            ss.consec_prefix = ctiles;
+            ctiles += c->pair_tiles;
+        }
+    }
+    // the decision entries: the chunk's arrival, then the rounds after it
+    for (int k = 0; k < 2; ++k) {
+        StepStream& ss = steps[C + k];
+        std::memset(&ss, 0, sizeof ss);
+        ss.sid = 0;
+        ss.has_frame = k == 0;
+        ss.frame = k == 0 ? f0 + n - 1 : -1;
+        ss.ended_T = last ? in.T : -1;
+    }
+    HIPCK(hipMemcpyAsync(dd, h, c->desc_bytes, hipMemcpyHostToDevice, c->sp), "descriptor upload");
+    const StepStream* d_steps = reinterpret_cast<const StepStream*>(dd);
+    const int32_t* d_k1 = reinterpret_cast<const int32_t*>(dd + c->off_k1);
+    TileJob* cjobs = c->d_cjobs + (size_t)q * C;
+    int32_t* cmap = c->d_cmap + (size_t)q * C * c->pair_tiles;
+    TilePartial* cpart = c->d_part + (size_t)q * C * c->pair_tiles;
+    HIPCK(launch_pyramid(sd.bits, sd.L, c->d_sds, d_steps, d_k1, n, n * c->pyr_tiles, cjobs, cmap, c->sp),
+          "pyramid launch");
+    if (!c->no_intensity) HIPCK(launch_intensity(c->d_sds, d_steps, d_k1, n, c->sp), "intensity launch");
+    if (ctiles > 0) {
+        int gc = std::min(c->grid_c, ctiles);
+        if (gc >= 8) gc -= gc % 8;
+        HIPCK(launch_me(sd.bits, c->d_sds, cjobs, C, cmap, ctiles, nullptr, 0, false, cpart, nullptr, nullptr, gc,
+                        c->sp),
+              "motion search launch");
+    }
+    HIPCK(hipEventRecord(c->ev_p[q], c->sp), "event");
+    *n_cons_out = n_cons;
+    *ctiles_out = ctiles;
+    return VSA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1778,6 +1884,7 @@ extern "C" {
 void vsa_clip_destroy(vsa_clip* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    if (c->sp) (void)hipStreamSynchronize(c->sp);
     if (c->s) (void)hipStreamSynchronize(c->s);
     void* dev[] = {c->mem, c->d_sds, c->d_state, c->d_cur, c->d_closed, c->d_desc, c->d_cjobs, c->d_cmap,
                    c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage};
@@ -1786,6 +1893,9 @@ void vsa_clip_destroy(vsa_clip* c) {
     void* host[] = {c->h_desc, c->h_init, c->h_out_frames, c->h_out_shots, c->h_snap};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
+    for (hipEvent_t ev : c->ev_p)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->sp) (void)hipStreamDestroy(c->sp);
     if (c->s) (void)hipStreamDestroy(c->s);
     delete c;
 }
@@ -1813,9 +1923,9 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     layout(g, cfg->width, cfg->height, cfg->bit_depth, kmax, sd);
     st = check_exact_sums(sd);
     if (st != VSA_OK) return st;
-    // the chunk being ingested, the deep check's look-back (k_max + 1) and
-    // look-ahead (k_max + 1) behind it, and slack
-    sd.rs = C + 2 * kmax + 8;
+    // the chunk being decided, the chunk being ingested beside it, the deep
+    // check's look-back (k_max + 1) and look-ahead (k_max + 1), and slack
+    sd.rs = 2 * C + 2 * kmax + 8;
     sd.epoch = 1;
     HIPCK(hipSetDevice(cfg->device), "hipSetDevice");
     vsa_clip* c = new vsa_clip;
@@ -1834,12 +1944,13 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
         if (gsz >= 8) gsz -= gsz % 8;   // whole groups of one workgroup per XCD
         return gsz;
     };
-    const int wgs = cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2;
-    c->grid_c = grid((int64_t)C * c->pair_tiles, wgs);
+    c->grid_c = grid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2);
     c->grid_s = grid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
     HIPCK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking), "hipStreamCreate");
+    HIPCK(hipStreamCreateWithFlags(&c->sp, hipStreamNonBlocking), "hipStreamCreate");
+    for (hipEvent_t& ev : c->ev_p) HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
     const int64_t thb = tile_hist_bytes(sd, !c->no_intensity);
-    const int64_t mem_bytes = clip_tileh_offset(sd) + thb * C;
+    const int64_t mem_bytes = clip_tileh_offset(sd) + thb * 2 * C;
     auto dalloc = [](void** p_, size_t n) { return hipMalloc(p_, std::max<size_t>(n, 256)) == hipSuccess; };
     c->desc_bytes = round_up(sizeof(StepStream) * (C + 2), 256);
     c->off_k1 = c->desc_bytes;
@@ -1847,12 +1958,13 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     c->off_cons = c->desc_bytes;
     c->desc_bytes += round_up(sizeof(PairTask) * C, 256);
     const size_t tc = kMaxTasksPerStream;
-    bool ok = dalloc((void**)&c->mem, mem_bytes) && dalloc((void**)&c->d_sds, sizeof(StreamDesc) * C) &&
+    const size_t cpt = (size_t)C * c->pair_tiles;
+    bool ok = dalloc((void**)&c->mem, mem_bytes) && dalloc((void**)&c->d_sds, sizeof(StreamDesc) * 2 * C) &&
               dalloc((void**)&c->d_state, sizeof(DecideState)) && dalloc((void**)&c->d_cur, sizeof(DeviceCursors)) &&
               dalloc((void**)&c->d_closed, sizeof(vsa_shot_result) * kMaxClosed) &&
-              dalloc((void**)&c->d_desc, c->desc_bytes) && dalloc((void**)&c->d_cjobs, sizeof(TileJob) * C) &&
-              dalloc((void**)&c->d_cmap, sizeof(int32_t) * C * c->pair_tiles) &&
-              dalloc((void**)&c->d_part, sizeof(TilePartial) * ((size_t)C * c->pair_tiles + c->sparse_tiles)) &&
+              dalloc((void**)&c->d_desc, 2 * c->desc_bytes) && dalloc((void**)&c->d_cjobs, sizeof(TileJob) * 2 * C) &&
+              dalloc((void**)&c->d_cmap, sizeof(int32_t) * 2 * cpt) &&
+              dalloc((void**)&c->d_part, sizeof(TilePartial) * (2 * cpt + c->sparse_tiles)) &&
               dalloc((void**)&c->d_sparse, 2 * sizeof(PairTask) * tc) &&
               dalloc((void**)&c->d_sjobs, 2 * sizeof(TileJob) * tc) &&
               dalloc((void**)&c->d_smap, 2 * sizeof(int32_t) * c->sparse_tiles);
@@ -1861,7 +1973,7 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     // held (< rs); shots never outnumber frames + 3
     c->out_cap = (uint64_t)(2 * (C + sd.rs) + 64);
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
-    ok = hipHostMalloc((void**)&c->h_desc, c->desc_bytes, hipHostMallocDefault) == hipSuccess &&
+    ok = hipHostMalloc((void**)&c->h_desc, 2 * c->desc_bytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void**)&c->h_init, sizeof(DecideState), hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void**)&c->h_out_frames, sizeof(OutFrame) * c->out_cap, mapped) == hipSuccess &&
          hipHostGetDevicePointer((void**)&c->d_out_frames, c->h_out_frames, 0) == hipSuccess &&
@@ -1873,13 +1985,13 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     sd.ring = c->mem;
     sd.info = reinterpret_cast<FrameInfo*>(c->mem + clip_info_offset(sd));
     sd.mv = reinterpret_cast<int8_t*>(c->mem + clip_mv_offset(sd));
-    c->sd = sd;
-    std::vector<StreamDesc> sds(C, sd);
-    for (int i = 0; i < C; ++i)
+    std::vector<StreamDesc> sds(2 * C, sd);
+    for (int i = 0; i < 2 * C; ++i)
         sds[i].tileh = c->no_intensity ? nullptr
                                        : reinterpret_cast<uint16_t*>(c->mem + clip_tileh_offset(sd) + thb * i);
-    c->sd.tileh = sds[0].tileh;
-    HIPCK(hipMemcpy(c->d_sds, sds.data(), sizeof(StreamDesc) * C, hipMemcpyHostToDevice), "descriptor upload");
+    sd.tileh = sds[0].tileh;
+    c->sd = sd;
+    HIPCK(hipMemcpy(c->d_sds, sds.data(), sizeof(StreamDesc) * 2 * C, hipMemcpyHostToDevice), "descriptor upload");
     *out = guard.release();
     return VSA_OK;
 }
@@ -1905,7 +2017,7 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
     if (src == VSA_SRC_HOST && !c->d_stage) {
         c->stage_pitch = round_up(row, 256);
         c->stage_bytes = round_up(c->stage_pitch * sd.H, 256);
-        if (hipMalloc((void**)&c->d_stage, (size_t)c->stage_bytes * C) != hipSuccess) {
+        if (hipMalloc((void**)&c->d_stage, (size_t)c->stage_bytes * 2 * C) != hipSuccess) {
             c->d_stage = nullptr;
             return fail(VSA_E_NOMEM, "clip staging");
         }
@@ -1918,88 +2030,34 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
     HIPCK(hipStreamSynchronize(c->s), "reset");
     std::memset(c->h_snap, 0, 2 * sizeof(PubSnap));
     c->dec_no = 0;
+    const ClipSource in{static_cast<const uint8_t*>(frames), frame_stride_bytes, pitch_bytes, T, src};
+    const int n_chunks = (T + C - 1) / C;
+    int n_cons[2] = {0, 0}, ctiles[2] = {0, 0};
+    vsa_status st = clip_ingest(c, in, 0, &n_cons[0], &ctiles[0]);
+    if (st != VSA_OK) return st;
     uint64_t frames_read = 0, shots_read = 0, run_tasks = 0;
-    const uint8_t* base = static_cast<const uint8_t*>(frames);
-    StepStream* steps = reinterpret_cast<StepStream*>(c->h_desc);
-    int32_t* k1 = reinterpret_cast<int32_t*>(c->h_desc + c->off_k1);
-    PairTask* cons = reinterpret_cast<PairTask*>(c->h_desc + c->off_cons);
-    const StepStream* d_steps = reinterpret_cast<const StepStream*>(c->d_desc);
-    const int32_t* d_k1 = reinterpret_cast<const int32_t*>(c->d_desc + c->off_k1);
-    const PairTask* d_cons = reinterpret_cast<const PairTask*>(c->d_desc + c->off_cons);
-    for (int f0 = 0; f0 < T; f0 += C) {
-        const int n = std::min(C, T - f0);
-        const bool last = f0 + n == T;
-        if (src == VSA_SRC_HOST)
-            for (int i = 0; i < n; ++i)
-                HIPCK(hipMemcpy2DAsync(c->d_stage + (int64_t)i * c->stage_bytes, c->stage_pitch,
-                                       base + (int64_t)(f0 + i) * frame_stride_bytes, pitch_bytes, row, sd.H,
-                                       hipMemcpyHostToDevice, c->s),
-                      "plane upload");
-        int n_cons = 0, ctiles = 0;
-        for (int i = 0; i < n; ++i) {
-            StepStream& ss = steps[i];
-            std::memset(&ss, 0, sizeof ss);
-            ss.sid = i;
-            ss.has_frame = 1;
-            ss.frame = f0 + i;
-            ss.ended_T = -1;
-            ss.pts = f0 + i;
-            if (src == VSA_SRC_HOST) {
-                ss.src = c->d_stage + (int64_t)i * c->stage_bytes;
-                ss.src_pitch = c->stage_pitch;
-            } else {
-                ss.src = base + (int64_t)(f0 + i) * frame_stride_bytes;
-                ss.src_pitch = pitch_bytes;
-            }
-            ss.k1_tiles = c->pyr_tiles;
-            ss.k1_prefix = i * c->pyr_tiles;
-            k1[i] = i;
-            if (f0 + i >= 1) {
-                PairTask& t = cons[n_cons++];
-                std::memset(&t, 0, sizeof t);
-                t.sid = i;
-                t.kind = MK_CONSEC;
-                t.ref = f0 + i - 1;
-                t.oth = f0 + i;
-                t.ref_field = t.oth_field = PL_FRAME;
-                t.level = sd.L;
-                t.result = -1;
-                t.tiles = c->pair_tiles;
-                t.tile_prefix = ctiles;
-                t.flags = TF_MV_RING;
-                t.epoch = sd.epoch;
-                ss.consec_tiles = c->pair_tiles;
-                ss.consec_prefix = ctiles;
-                ctiles += c->pair_tiles;
-            }
-        }
-        // the decision entries: the chunk's arrival, then the rounds after it
-        for (int k = 0; k < 2; ++k) {
-            StepStream& ss = steps[C + k];
-            std::memset(&ss, 0, sizeof ss);
-            ss.sid = 0;
-            ss.has_frame = k == 0;
-            ss.frame = k == 0 ? f0 + n - 1 : -1;
-            ss.ended_T = last ? T : -1;
-        }
-        HIPCK(hipMemcpyAsync(c->d_desc, c->h_desc, c->desc_bytes, hipMemcpyHostToDevice, c->s), "descriptor upload");
-        HIPCK(launch_pyramid(sd.bits, sd.L, c->d_sds, d_steps, d_k1, n, n * c->pyr_tiles, c->d_cjobs, c->d_cmap, c->s),
-              "pyramid launch");
-        if (!c->no_intensity) HIPCK(launch_intensity(c->d_sds, d_steps, d_k1, n, c->s), "intensity launch");
-        if (ctiles > 0) {
-            int gc = std::min(c->grid_c, ctiles);
-            if (gc >= 8) gc -= gc % 8;
-            HIPCK(launch_me(sd.bits, c->d_sds, c->d_cjobs, C, c->d_cmap, ctiles, nullptr, 0, false, c->d_part, nullptr,
-                            nullptr, gc, c->s),
-                  "motion search launch");
-            HIPCK(launch_finish(c->d_sds, d_cons, n_cons, ctiles, nullptr, nullptr, c->d_part, nullptr, c->dp, nullptr,
-                                nullptr, (n_cons + 3) / 4, 0, c->s),
+    for (int ch = 0; ch < n_chunks; ++ch) {
+        const int q = ch & 1;
+        const uint8_t* dd = c->d_desc + (size_t)q * c->desc_bytes;
+        const StepStream* d_steps = reinterpret_cast<const StepStream*>(dd);
+        // the chunk's pairs into the frame records, then its first decisions
+        HIPCK(hipStreamWaitEvent(c->s, c->ev_p[q], 0), "wait");
+        if (n_cons[q] > 0)
+            HIPCK(launch_finish(c->d_sds, reinterpret_cast<const PairTask*>(dd + c->off_cons), n_cons[q], ctiles[q],
+                                nullptr, nullptr, c->d_part + (size_t)q * C * c->pair_tiles, nullptr, c->dp, nullptr,
+                                nullptr, (n_cons[q] + 3) / 4, 0, c->s),
                   "finish launch");
-        }
-        vsa_status st = clip_decide(c, d_steps + C);
+        st = clip_decide(c, d_steps + C);
         if (st != VSA_OK) return st;
+        // the next chunk's ingest beside this chunk's rounds: the previous
+        // chunk's rounds (the last readers of the slots and buffers it
+        // reuses) have completed
+        if (ch + 1 < n_chunks) {
+            st = clip_ingest(c, in, ch + 1, &n_cons[q ^ 1], &ctiles[q ^ 1]);
+            if (st != VSA_OK) return st;
+        }
         // each round commits at least one iteration of the pass
-        const int limit = 4 * (n + sd.rs) + 64;
+        const int limit = 4 * (C + sd.rs) + 64;
         int rounds = 0, batch = c->est_rounds;
         for (;;) {
             for (int r = 0; r < batch; ++r, ++rounds) {
@@ -2009,18 +2067,26 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
             HIPCK(hipStreamSynchronize(c->s), "clip chunk");
             c->counters[2] += 1;
             if (!clip_pending(c)) break;
-            if (rounds > limit) return fail(VSA_E_DEVICE, "decision pass did not settle");
+            if (rounds > limit) {
+                (void)hipStreamSynchronize(c->sp);
+                return fail(VSA_E_DEVICE, "decision pass did not settle");
+            }
             batch = 4;
         }
         c->est_rounds = std::min(rounds, 32);
         c->counters[0] += 1;
         // records of this chunk (mapped memory, complete after the wait)
         const PubSnap ps = c->h_snap[(c->dec_no - 1) & 1];
-        if (ps.frames_written - frames_read > c->out_cap || ps.shots_written - shots_read > c->out_cap)
+        if (ps.frames_written - frames_read > c->out_cap || ps.shots_written - shots_read > c->out_cap) {
+            (void)hipStreamSynchronize(c->sp);
             return fail(VSA_E_DEVICE, "clip record ring overflow");
+        }
         for (uint64_t i = frames_read; i < ps.frames_written; ++i) {
             const OutFrame& o = c->h_out_frames[i % c->out_cap];
-            if (o.r.frame != (int64_t)i || i >= (uint64_t)T) return fail(VSA_E_DEVICE, "clip records out of order");
+            if (o.r.frame != (int64_t)i || i >= (uint64_t)T) {
+                (void)hipStreamSynchronize(c->sp);
+                return fail(VSA_E_DEVICE, "clip records out of order");
+            }
             out_frames[i] = o.r;
         }
         for (uint64_t i = shots_read; i < ps.shots_written; ++i)
@@ -2029,6 +2095,7 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
         shots_read = ps.shots_written;
         run_tasks = ps.sparse_run;
     }
+    HIPCK(hipStreamSynchronize(c->sp), "clip ingest");
     c->counters[3] += run_tasks;
     if (frames_read != (uint64_t)T) return fail(VSA_E_DEVICE, "clip ended with frames missing");
     if (n_shots) *n_shots = (int32_t)shots_read;

@@ -280,6 +280,24 @@ def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, **engi
     return dt, kt, c0, c1, frames_out
 
 
+def run_clip_leg(vsa, dev_frames, params, chunk, runs, torch):
+    """The whole resident clip analysed alone by the offline form, `runs`
+    times after one untimed run; frames/s of each run."""
+    F, H, W = dev_frames.shape
+    out = []
+    with vsa.Clip(W, H, chunk=chunk, params=params) as c:
+        c.run_tensor(dev_frames)
+        c0 = c.counters()
+        for _ in range(runs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = c.run_tensor(dev_frames)
+            out.append(F / (time.perf_counter() - t0))
+        c1 = c.counters()
+    per_run = {k: (c1[k] - c0[k]) / runs for k in c0}
+    return out, per_run, len(res["shots"])
+
+
 def cpu_baseline(frames, params, budget_s):
     import oracle
     if not os.path.exists(oracle.LIB_PATH):
@@ -322,6 +340,11 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--no-clip", action="store_true", help="skip the offline single-clip run")
+    ap.add_argument("--clip-chunk", type=int, default=256, help="frames per chunk of the offline single-clip run")
+    ap.add_argument("--clip-runs", type=int, default=5)
+    ap.add_argument("--clip-only", action="store_true",
+                    help="only the offline single-clip run (one JSON line of its own; for kernel traces)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -345,6 +368,24 @@ def main():
     print(f"[bench] rendered {frames.shape} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     dev = torch.from_numpy(frames).to("cuda:0")
     torch.cuda.synchronize()
+
+    def clip_leg():
+        cf, per, nshots = run_clip_leg(vsa, dev, params, args.clip_chunk, args.clip_runs, torch)
+        med = float(np.median(cf))
+        print(f"[bench] single clip, chunks of {args.clip_chunk}: {med:.0f} frames/s "
+              f"(runs {[round(x) for x in cf]})", file=sys.stderr, flush=True)
+        return {"workload": f"one {args.frames}-frame 2048x1080 8-bit clip resident in HBM analysed alone by "
+                            f"the offline form (vsa_clip_run), chunks of {args.clip_chunk} frames, k_max 8, "
+                            "sparse schedule; median of the runs",
+                "fps": round(med, 1), "x_realtime": round(med / RT_FPS, 1), "runs_fps": [round(x, 1) for x in cf],
+                "ms_per_clip": round(1e3 * args.frames / med, 3), "chunk": args.clip_chunk, "shots": nshots,
+                "per_clip": per}
+
+    if args.clip_only:
+        if args.gpu_warm_steps > 0:
+            run_engine(vsa, dev, params, args.streams, args.gpu_warm_steps, 0, 0, torch)
+        print(json.dumps({"single_clip": clip_leg()}))
+        return
 
     if args.gpu_warm_steps > 0:
         # the GPU sat idle while the frames were rendered on the host: a run
@@ -375,6 +416,10 @@ def main():
         pdt, _, _, _, _ = run_engine(vsa, dev, params, 1, args.plain_steps, 20, 0, torch)
         plain_fps = args.plain_steps / pdt
         print(f"[bench] plain 1 stream: {plain_fps:.0f} frames/s", file=sys.stderr, flush=True)
+    if not args.no_clip:
+        extra["single_clip"] = clip_leg()
+        if plain_fps:
+            extra["single_clip"]["vs_plain_stream"] = round(extra["single_clip"]["fps"] / plain_fps, 2)
     kt_all = None
     if not args.no_diag:
         # untimed diagnostic: every kernel timed, for the per-kernel breakdown

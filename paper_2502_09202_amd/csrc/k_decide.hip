@@ -14,7 +14,13 @@
 // needs sparse measures (fields of an analysed frame, deep-check pairs after
 // the fast check fired) is planned in one step and committed in the next one,
 // after the step's motion-search launch has computed the requested pairs;
-// iterations that need nothing more are committed at once.  The planned
+// iterations that need nothing more are committed at once.  In the offline
+// clip form (a field cache is given), an iteration that asks for the fields
+// of its frame also asks for those of up to kMaxSpec later non-static frames
+// already ingested, as many as the analysis window may still take; they are
+// filed per ring slot under their frame, and a later iteration that wants a
+// cached frame's fields commits without a new request.  The cached values are
+// the same measures, so the records do not change.  The planned
 // tasks of all streams are compacted into one dense list: each workgroup sums
 // its streams' task and tile counts, reserves its slice of the list and of the
 // tile range with one packed 64-bit atomic, hands each stream its offsets (a
@@ -243,8 +249,8 @@ __device__ __forceinline__ int p_rep(const StreamDesc& sd, int K, int d) {
 
 // Sparse tasks of the planned iteration, in a fixed order: v0, v1, v2, then
 // F_K for K = 2..Kn, then the distinct P_K for K = 1..Kn (when t > shot start).
-__device__ __forceinline__ int plan_task_count(const StreamDesc& sd, const DecideState& st) {
-    if (!st.plan) return 0;
+// Speculative field tasks (three per frame of st.spec_mask) follow them.
+__device__ __forceinline__ int plan_regular_count(const StreamDesc& sd, const DecideState& st) {
     int n = st.plan_nf ? 3 : 0;
     if (st.plan_deep) {
         n += st.plan_kn - 1;
@@ -255,6 +261,25 @@ __device__ __forceinline__ int plan_task_count(const StreamDesc& sd, const Decid
     return n;
 }
 
+template <bool kSpec>
+__device__ __forceinline__ int plan_task_count(const StreamDesc& sd, const DecideState& st) {
+    if (!st.plan) return 0;
+    return plan_regular_count(sd, st) + (kSpec ? 3 * st.plan_spec : 0);
+}
+
+// The three field pairs of frame u (Sec. III.C): v0 = (U_u, D_u),
+// v1 = (U_u, D_u+1), v2 = (D_u, U_u+1).
+__device__ __forceinline__ void field_task(const StreamDesc& sd, int u, int i, PairTask& k) {
+    k.kind = MK_FIELD;
+    k.ref = u;
+    k.ref_field = (i == 2) ? PL_LOWER : PL_UPPER;
+    k.oth = (i == 0) ? u : u + 1;
+    k.oth_field = (i == 2) ? PL_UPPER : PL_LOWER;
+    k.level = sd.Lf;
+    k.tiles = me_tiles(sd.wf, sd.hf);
+}
+
+template <bool kSpec>
 __device__ PairTask plan_task(const StreamDesc& sd, const DecideState& st, int sid, int i) {
     PairTask k;
     k.sid = sid;
@@ -262,16 +287,21 @@ __device__ PairTask plan_task(const StreamDesc& sd, const DecideState& st, int s
     k.epoch = sd.epoch;
     k.tile_prefix = 0;
     const int t = st.t;
+    if (kSpec && st.plan_spec > 0) {
+        const int reg = plan_regular_count(sd, st);
+        if (i >= reg) {
+            const int j = (i - reg) / 3, c = (i - reg) % 3;
+            uint32_t m = st.spec_mask;
+            for (int q = 0; q < j; ++q) m &= m - 1;       // drop the j lowest frames
+            field_task(sd, t + 1 + __builtin_ctz(m), c, k);
+            k.result = kResSpec + c;
+            return k;
+        }
+    }
     if (st.plan_nf) {
         if (i < 3) {
-            k.kind = MK_FIELD;
-            k.ref = t;
-            k.ref_field = (i == 2) ? PL_LOWER : PL_UPPER;
-            k.oth = (i == 0) ? t : t + 1;
-            k.oth_field = (i == 2) ? PL_UPPER : PL_LOWER;
-            k.level = sd.Lf;
+            field_task(sd, t, i, k);
             k.result = kResFields + i;
-            k.tiles = me_tiles(sd.wf, sd.hf);
             return k;
         }
         i -= 3;
@@ -313,14 +343,28 @@ __device__ __forceinline__ PlaneDims plane_dims(const StreamDesc& sd, const Pair
     return PlaneDims{sd.wl[d], sd.hl[d]};
 }
 
-// Advance one stream as far as the ingested frames allow.
-__device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, const PairResult* res,
+// Cached speculative fields of frame u into the result slots of an
+// iteration's own field measures; false if u's are not cached.
+__device__ __forceinline__ bool spec_fetch(const StreamDesc& sd, int u, PairResult* res, const DecideParams& dp) {
+    const double* cv = dp.spec + (int64_t)(u % sd.rs) * 4;
+    if (!(cv[3] == (double)u)) return false;
+    for (int i = 0; i < 3; ++i) { res[kResFields + i].act = cv[i]; res[kResFields + i].swr = 0.0; }
+    return true;
+}
+
+// Advance one stream as far as the ingested frames allow (kSpec: with the
+// speculative field measures when dp.spec is given).
+template <bool kSpec>
+__device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, PairResult* res,
                         const DecideParams& dp, int has_frame, int frame, int ended_T) {
     st.n_closed = 0;
     if (st.done) { st.plan = 0; return; }
     if (has_frame) st.n = frame;
     if (ended_T >= 0) st.T_end = ended_T;
+    const bool spec_on = kSpec && dp.spec != nullptr && !dp.dense;
     if (st.plan) {
+        // fields wanted but not requested: they were in the cache when planned
+        if (spec_on && st.plan_want && !st.plan_nf) spec_fetch(sd, st.t, res, dp);
         commit(sd, st, closed, res, dp, st.plan_want, st.plan_fire, st.plan_deep, st.plan_kn);
         st.plan = 0;
     }
@@ -349,13 +393,31 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
             else if (t + sd.k_max + 1 <= st.n) Kn = sd.k_max + 1;
             else break;                           // wait for the look-ahead frames
         }
+        const bool cached = spec_on && want && spec_fetch(sd, t, res, dp);
         st.plan_want = want;
         st.plan_fire = fire;
         st.plan_deep = need_deep;
-        st.plan_nf = need_fields;
+        st.plan_nf = need_fields && !cached;
         st.plan_kn = Kn;
+        st.plan_spec = 0;
+        st.spec_mask = 0;
         st.plan = 1;
-        if (plan_task_count(sd, st) > 0) break;       // measures requested; commit next step
+        if (spec_on && st.plan_nf && !need_deep) {
+            // the fields of the next non-static frames already ingested, as
+            // many as the analysis window may still take: computed with t's
+            int quota = dp.n_ss - st.ss.n - 1;
+            for (int k = 0; k < 32 && t + 1 + k + 1 <= st.n && quota > 0 && st.plan_spec < kMaxSpec; ++k) {
+                const int u = t + 1 + k;
+                if (info_of(sd, u).flags & VSA_F_STATIC) continue;
+                --quota;
+                const double* cu = dp.spec + (int64_t)(u % sd.rs) * 4;
+                if (!(cu[3] == (double)u)) {
+                    st.spec_mask |= 1u << k;
+                    st.plan_spec += 1;
+                }
+            }
+        }
+        if (plan_task_count<kSpec>(sd, st) > 0) break;       // measures requested; commit next step
         st.plan = 0;
         commit(sd, st, closed, res, dp, want, fire, need_deep, Kn);
     }
@@ -405,6 +467,7 @@ __device__ __forceinline__ int64_t wsum64(int64_t v) {
 //     and of the output rings, and writes its tasks;
 //  4. the wave copies the finished frame and shot records out in parallel.
 // Streams never share a wave, so their control paths do not serialise.
+template <bool kSpec>
 __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     const StreamDesc* __restrict__ sds, DecideState* __restrict__ states, const StepStream* __restrict__ steps,
     int32_t n_steps, DecideParams dp, const TilePartial* __restrict__ cpart, const TilePartial* __restrict__ spart,
@@ -497,24 +560,35 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
             const int64_t B = (int64_t)(w / kBlock) * (h / kBlock), n = 64 * B;
             double f[4];
             finish_pair(a[0], a[1], a[2], a[3], a[4], n, a[5], B, dp.a0, f);
-            res[wave][mine.result].act = f[3];
-            res[wave][mine.result].swr = f[1];
+            if (kSpec && mine.result >= kResSpec) {   // a speculative field measure: into the cache
+                double* cv = dp.spec + (int64_t)(mine.ref % sd.rs) * 4;
+                cv[mine.result - kResSpec] = f[3];
+                cv[3] = (double)mine.ref;
+            } else {
+                res[wave][mine.result].act = f[3];
+                res[wave][mine.result].swr = f[1];
+            }
         }
     }
     __syncthreads();
-    // 3. decisions (lane 0 of each wave), counts of what the stream produces
-    StreamDesc sd;
+    // 3. decisions (lane 0 of each wave), counts of what the stream produces.
+    //    With speculation (one long sequential pass per launch) the
+    //    descriptor is read in place, which keeps the pass's state in
+    //    registers; otherwise it is copied (fewer registers, and the many
+    //    streams' short passes are placed beside the motion-search grids).
+    StreamDesc sd_copy;
+    const StreamDesc& sd = kSpec ? sds[active ? sid : 0] : sd_copy;
     DecideState st;
     if (active && lane == 0) {
-        sd = sds[sid];
+        if (!kSpec) sd_copy = sds[sid];
         st = states[sid];
         vsa_shot_result* closed = closed_buf + (int64_t)sid * kMaxClosed;
         const int e0 = st.emitted;
-        advance(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T);
-        const int nt = plan_task_count(sd, st);
+        advance<kSpec>(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T);
+        const int nt = plan_task_count<kSpec>(sd, st);
         int tiles = 0, blocks = 0;
         for (int q = 0; q < nt; ++q) {
-            const PairTask pt = plan_task(sd, st, sid, q);
+            const PairTask pt = plan_task<kSpec>(sd, st, sid, q);
             tiles += pt.tiles;
             const PlaneDims pd = plane_dims(sd, pt);
             blocks += (pd.w / kBlock) * (pd.h / kBlock);
@@ -554,7 +628,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         int32_t* slog = log ? log + (int64_t)sid * log_cap * 6 : nullptr;
         int tile = b.tile;
         for (int q = 0; q < b.ntasks; ++q) {
-            PairTask t = plan_task(sd, st, sid, q);
+            PairTask t = plan_task<kSpec>(sd, st, sid, q);
             t.tile_prefix = tile;
             tile += t.tiles;
             sparse_next[b.task + q] = t;
@@ -649,14 +723,14 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
             }
         }
         const int e0 = st.emitted;
-        advance(sd, st, closed, res, dp, has, step, step >= T - 1 ? T : -1);
+        advance<false>(sd, st, closed, res, dp, has, step, step >= T - 1 ? T : -1);
         for (int f = e0; f < st.t; ++f) fill_record(recs[f], info_of(sd, f));
         st.emitted = st.t;
         for (int k = 0; k < st.n_closed; ++k)
             if (ns < shots_cap) shots[ns++] = closed[k];
-        const int nt = plan_task_count(sd, st);
+        const int nt = plan_task_count<false>(sd, st);
         for (int k = 0; k < nt; ++k) {
-            const PairTask t = plan_task(sd, st, 0, k);
+            const PairTask t = plan_task<false>(sd, st, 0, k);
             if (log && nl < log_cap) {
                 int32_t* e = log + 6 * nl;
                 e[0] = t.kind; e[1] = t.ref; e[2] = t.oth; e[3] = t.ref_field; e[4] = t.oth_field;
@@ -689,14 +763,21 @@ hipError_t launch_finish_decide(const StreamDesc* sds, DecideState* states, cons
                                 LaunchTiming tm) {
     if (n_steps <= 0) return hipSuccess;
     const dim3 g((n_steps + kDecideWaves - 1) / kDecideWaves), b(64 * kDecideWaves);
-    if (tm.any())
-        hipExtLaunchKernelGGL(k_finish_decide, g, b, 0, s, tm.start, tm.stop, 0, sds, states, steps, n_steps, dp,
-                              cpart, spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,
-                              shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);
-    else
-        hipLaunchKernelGGL(k_finish_decide, g, b, 0, s, sds, states, steps, n_steps, dp, cpart, spart, sparse_prev,
-                           sparse_next, cur, out_frames, frames_cap, out_shots, shots_cap, log, log_cap, closed_buf,
-                           par, snap, sjobs_next, smap_next);
+#define VSA_K6(SPEC)                                                                                            \
+    do {                                                                                                        \
+        if (tm.any())                                                                                           \
+            hipExtLaunchKernelGGL(k_finish_decide<SPEC>, g, b, 0, s, tm.start, tm.stop, 0, sds, states, steps,  \
+                                  n_steps, dp, cpart, spart, sparse_prev, sparse_next, cur, out_frames,         \
+                                  frames_cap, out_shots, shots_cap, log, log_cap, closed_buf, par, snap,        \
+                                  sjobs_next, smap_next);                                                       \
+        else                                                                                                    \
+            hipLaunchKernelGGL(k_finish_decide<SPEC>, g, b, 0, s, sds, states, steps, n_steps, dp, cpart,       \
+                               spart, sparse_prev, sparse_next, cur, out_frames, frames_cap, out_shots,         \
+                               shots_cap, log, log_cap, closed_buf, par, snap, sjobs_next, smap_next);          \
+    } while (0)
+    if (dp.spec) VSA_K6(true);
+    else VSA_K6(false);
+#undef VSA_K6
     return hipGetLastError();
 }
 

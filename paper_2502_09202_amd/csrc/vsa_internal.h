@@ -92,6 +92,13 @@ constexpr int kResFields = 0;
 constexpr int kResF = 3;
 constexpr int kResP = kResF + kMaxKmax + 2;
 constexpr int kResSlots = kResP + kMaxKmax + 2;
+// Speculative field measures (offline clip form only): when an iteration
+// asks for the fields of its frame, those of up to kMaxSpec later frames the
+// analysis may still want are computed with them and cached per ring slot.
+// Their tasks carry result = kResSpec + component.
+constexpr int kMaxSpec = 10;
+constexpr int kResSpec = kResSlots;
+static_assert(3 + 3 * kMaxSpec <= 3 + 2 * (kMaxKmax + 1), "speculative tasks exceed the per-stream task limit");
 
 // Sampling-structure analysis of the open shot.
 struct Analysis {
@@ -116,6 +123,8 @@ struct DecideState {
     // iteration planned in the previous step (its sparse measures are computed
     // by this step's motion-search launch)
     int32_t plan, plan_want, plan_fire, plan_deep, plan_nf, plan_kn;
+    int32_t plan_spec;                   // speculative field frames planned with it:
+    uint32_t spec_mask;                  // bit k = frame t + 1 + k
     int32_t done;               // end of stream fully processed
     int32_t n_closed;           // shots closed by the last advance
     int32_t sp_base, sp_count;  // where the planned tasks sit in that step's sparse list
@@ -130,6 +139,9 @@ constexpr int kMaxClosed = 4;
 struct DecideParams {
     int32_t w_hist, n_ss, dense, a_static_fx;
     double a0, rho_f, theta_f, theta_f0, rho_d, theta_d, gamma, tau_c, eps, tau_p, theta_kf;
+    // field cache of the speculative field measures: per ring slot v0, v1, v2
+    // and the frame they belong to (NaN: none); null disables speculation
+    double* spec;
 };
 
 // Per-step view of one stream (host -> device each step).

@@ -169,6 +169,7 @@ DecideParams decide_params(const vsa_params& p, int dense) {
     d.w_hist = p.w_hist; d.n_ss = p.n_ss; d.dense = dense; d.a_static_fx = p.a_static_fx;
     d.a0 = p.a0; d.rho_f = p.rho_f; d.theta_f = p.theta_f; d.theta_f0 = p.theta_f0; d.rho_d = p.rho_d; d.theta_d = p.theta_d;
     d.gamma = p.gamma; d.tau_c = p.tau_c; d.eps = p.eps; d.tau_p = p.tau_p; d.theta_kf = p.theta_kf;
+    d.spec = nullptr;
     return d;
 }
 
@@ -1732,6 +1733,7 @@ struct vsa_clip {
     uint64_t out_cap = 0;
     PubSnap* h_snap = nullptr;     // [2], by decision-launch parity
     PubSnap* d_snap = nullptr;
+    double* d_spec = nullptr;      // speculative field cache: rs x (v0, v1, v2, frame)
     uint8_t* d_stage = nullptr;    // host-sourced frames of two chunks
     int64_t stage_pitch = 0, stage_bytes = 0;
     int64_t dec_no = 0;            // decision launches in the current run
@@ -1887,7 +1889,7 @@ void vsa_clip_destroy(vsa_clip* c) {
     if (c->sp) (void)hipStreamSynchronize(c->sp);
     if (c->s) (void)hipStreamSynchronize(c->s);
     void* dev[] = {c->mem, c->d_sds, c->d_state, c->d_cur, c->d_closed, c->d_desc, c->d_cjobs, c->d_cmap,
-                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage};
+                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage, c->d_spec};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_desc, c->h_init, c->h_out_frames, c->h_out_shots, c->h_snap};
@@ -1936,7 +1938,9 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     c->C = C;
     c->pyr_tiles = pyramid_tiles(sd);
     c->pair_tiles = me_tiles(sd.wl[0], sd.hl[0]);
-    c->sparse_tiles = max_sparse_tiles(sd);
+    // one round's sparse pairs: a deep check, or the fields of an analysed
+    // frame and of up to kMaxSpec frames after it
+    c->sparse_tiles = std::max(max_sparse_tiles(sd), 3 * (1 + kMaxSpec) * me_tiles(sd.wf, sd.hf));
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
     auto grid = [&](int64_t tiles, int w) {
@@ -1967,8 +1971,12 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
               dalloc((void**)&c->d_part, sizeof(TilePartial) * (2 * cpt + c->sparse_tiles)) &&
               dalloc((void**)&c->d_sparse, 2 * sizeof(PairTask) * tc) &&
               dalloc((void**)&c->d_sjobs, 2 * sizeof(TileJob) * tc) &&
-              dalloc((void**)&c->d_smap, 2 * sizeof(int32_t) * c->sparse_tiles);
+              dalloc((void**)&c->d_smap, 2 * sizeof(int32_t) * c->sparse_tiles) &&
+              dalloc((void**)&c->d_spec, sizeof(double) * 4 * sd.rs);
     if (!ok) return fail(VSA_E_NOMEM, "clip device buffers");
+    // speculative field measures: the sparse schedule only (the dense one
+    // computes every frame's fields anyway)
+    if (cfg->schedule == VSA_SCHEDULE_SPARSE) c->dp.spec = c->d_spec;
     // records out: a chunk emits at most its frames plus the backlog the pass
     // held (< rs); shots never outnumber frames + 3
     c->out_cap = (uint64_t)(2 * (C + sd.rs) + 64);
@@ -2027,6 +2035,7 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
     HIPCK(hipMemcpyAsync(c->d_state, c->h_init, sizeof(DecideState), hipMemcpyHostToDevice, c->s), "state reset");
     HIPCK(hipMemsetAsync(c->d_cur, 0, sizeof(DeviceCursors), c->s), "cursor reset");
     HIPCK(hipMemsetAsync(sd.info, 0, sizeof(FrameInfo) * sd.rs, c->s), "record reset");
+    HIPCK(hipMemsetAsync(c->d_spec, 0xff, sizeof(double) * 4 * sd.rs, c->s), "field cache reset");   // NaN tags
     HIPCK(hipStreamSynchronize(c->s), "reset");
     std::memset(c->h_snap, 0, 2 * sizeof(PubSnap));
     c->dec_no = 0;

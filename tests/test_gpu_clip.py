@@ -3,6 +3,8 @@
 A clip taken `chunk` frames per launch must give the records and shots of the
 oracle's sequential pass over the same frames: integers and labels exact,
 doubles bitwise (the engine's kernels and finishing arithmetic are the same).
+The sparse schedule computes some field measures speculatively (ahead of the
+pass asking for them); records must still show exactly the ones it asked for.
 Chunk sizes cover one frame, sizes that do not divide the clip (a ragged last
 chunk), a chunk larger than the clip and the bench's 256; both schedules,
 both sample widths, host and device sources, clips of 0-3 frames, and
@@ -55,7 +57,8 @@ def test_chunks_equal_oracle(vsa, params, c1, c1_ref, chunk):
     _same(got, c1_ref, f"chunk {chunk}")
     assert got["frames"]["pts"].tolist() == list(range(len(c1)))
     assert cnt["chunks"] == -(-len(c1) // chunk)
-    assert cnt["sparse_tasks"] == np.count_nonzero(c1_ref["keys"]["kind"] != 0)
+    # every measure the sequential pass asks for, plus the speculative fields
+    assert cnt["sparse_tasks"] >= np.count_nonzero(c1_ref["keys"]["kind"] != 0)
 
 
 def test_device_source_and_repeated_runs(vsa, orc, params, c1, c1_ref):

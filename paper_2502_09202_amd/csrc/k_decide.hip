@@ -183,11 +183,11 @@ __device__ int deep_check(const StreamDesc& sd, const DecideState& st, int t, in
 }
 
 // Commit iteration t = st.t with the flags it was planned with.
+// a is the consecutive activity of t (the frame record's act).
 __device__ void commit(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, const PairResult* res,
-                       const DecideParams& dp, bool want_fields, bool fire, bool need_deep, int Kn) {
+                       const DecideParams& dp, bool want_fields, bool fire, bool need_deep, int Kn, double a) {
     const int t = st.t;
     FrameInfo& fi = info_of(sd, t);
-    const double a = fi.act;
     if (want_fields) {
         const double v0 = res[kResFields + 0].act, v1 = res[kResFields + 1].act, v2 = res[kResFields + 2].act;
         fi.v[0] = v0; fi.v[1] = v1; fi.v[2] = v2;
@@ -352,11 +352,32 @@ __device__ __forceinline__ bool spec_fetch(const StreamDesc& sd, int u, PairResu
     return true;
 }
 
+// Consecutive activity and static bit of frames base .. base+n-1, staged in
+// LDS by the whole wave before a long sequential pass (both are final before
+// the pass runs, which only reads them); act == nullptr: none staged.
+struct Staged {
+    const double* act;
+    const uint8_t* stat;
+    int base, n;
+};
+
+__device__ __forceinline__ double act_at(const StreamDesc& sd, const Staged& pf, int f) {
+    const int k = f - pf.base;
+    if (pf.act && k >= 0 && k < pf.n) return pf.act[k];
+    return info_of(sd, f).act;
+}
+
+__device__ __forceinline__ bool static_at(const StreamDesc& sd, const Staged& pf, int f) {
+    const int k = f - pf.base;
+    if (pf.act && k >= 0 && k < pf.n) return pf.stat[k] != 0;
+    return (info_of(sd, f).flags & VSA_F_STATIC) != 0;
+}
+
 // Advance one stream as far as the ingested frames allow (kSpec: with the
 // speculative field measures when dp.spec is given).
 template <bool kSpec>
 __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, PairResult* res,
-                        const DecideParams& dp, int has_frame, int frame, int ended_T) {
+                        const DecideParams& dp, int has_frame, int frame, int ended_T, const Staged& pf) {
     st.n_closed = 0;
     if (st.done) { st.plan = 0; return; }
     if (has_frame) st.n = frame;
@@ -365,7 +386,7 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
     if (st.plan) {
         // fields wanted but not requested: they were in the cache when planned
         if (spec_on && st.plan_want && !st.plan_nf) spec_fetch(sd, st.t, res, dp);
-        commit(sd, st, closed, res, dp, st.plan_want, st.plan_fire, st.plan_deep, st.plan_kn);
+        commit(sd, st, closed, res, dp, st.plan_want, st.plan_fire, st.plan_deep, st.plan_kn, act_at(sd, pf, st.t));
         st.plan = 0;
     }
     for (;;) {
@@ -380,9 +401,8 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
             break;
         }
         if (t + 1 > st.n) break;                  // pair t -> t+1 not finished yet
-        const FrameInfo& fi = info_of(sd, t);
-        const double a = fi.act;
-        const bool stat = (fi.flags & VSA_F_STATIC) != 0;
+        const double a = act_at(sd, pf, t);
+        const bool stat = static_at(sd, pf, t);
         const bool want = st.ss.open && !stat;    // static frames carry no information
         const bool fire = fast_check(st, a, dp);
         const bool need_fields = want || dp.dense;
@@ -408,7 +428,7 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
             int quota = dp.n_ss - st.ss.n - 1;
             for (int k = 0; k < 32 && t + 1 + k + 1 <= st.n && quota > 0 && st.plan_spec < kMaxSpec; ++k) {
                 const int u = t + 1 + k;
-                if (info_of(sd, u).flags & VSA_F_STATIC) continue;
+                if (static_at(sd, pf, u)) continue;
                 --quota;
                 const double* cu = dp.spec + (int64_t)(u % sd.rs) * 4;
                 if (!(cu[3] == (double)u)) {
@@ -419,7 +439,7 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
         }
         if (plan_task_count<kSpec>(sd, st) > 0) break;       // measures requested; commit next step
         st.plan = 0;
-        commit(sd, st, closed, res, dp, want, fire, need_deep, Kn);
+        commit(sd, st, closed, res, dp, want, fire, need_deep, Kn, a);
     }
 }
 
@@ -571,6 +591,26 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         }
     }
     __syncthreads();
+    // With speculation (the offline clip form: one stream, whose pass may
+    // run over a whole chunk in this launch), the wave stages the activity
+    // and static bit of the frames the pass can reach into LDS, so that its
+    // lane-0 loop does not wait on a global load per frame.
+    constexpr int kPf = kSpec ? 512 : 1;
+    __shared__ double pf_act[kDecideWaves][kPf];
+    __shared__ uint8_t pf_stat[kDecideWaves][kPf];
+    int pf_base = 0, pf_n = 0;
+    if (kSpec && active) {
+        const StreamDesc& sg = sds[sid];
+        pf_base = states[sid].t;
+        const int newest = ss.has_frame ? ss.frame : states[sid].n;
+        pf_n = max(0, min(kPf, newest + 1 - pf_base));
+        for (int k = lane; k < pf_n; k += 64) {
+            const FrameInfo& fi = sg.info[(pf_base + k) % sg.rs];
+            pf_act[wave][k] = fi.act;
+            pf_stat[wave][k] = (fi.flags & VSA_F_STATIC) ? 1 : 0;
+        }
+    }
+    __syncthreads();
     // 3. decisions (lane 0 of each wave), counts of what the stream produces.
     //    With speculation (one long sequential pass per launch) the
     //    descriptor is read in place, which keeps the pass's state in
@@ -584,7 +624,8 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         st = states[sid];
         vsa_shot_result* closed = closed_buf + (int64_t)sid * kMaxClosed;
         const int e0 = st.emitted;
-        advance<kSpec>(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T);
+        const Staged pf{kSpec ? pf_act[wave] : nullptr, kSpec ? pf_stat[wave] : nullptr, pf_base, pf_n};
+        advance<kSpec>(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T, pf);
         const int nt = plan_task_count<kSpec>(sd, st);
         int tiles = 0, blocks = 0;
         for (int q = 0; q < nt; ++q) {
@@ -723,7 +764,7 @@ __global__ void k_decide_replay(StreamDesc sd, DecideState* st_, PairResult* res
             }
         }
         const int e0 = st.emitted;
-        advance<false>(sd, st, closed, res, dp, has, step, step >= T - 1 ? T : -1);
+        advance<false>(sd, st, closed, res, dp, has, step, step >= T - 1 ? T : -1, Staged{nullptr, nullptr, 0, 0});
         for (int f = e0; f < st.t; ++f) fill_record(recs[f], info_of(sd, f));
         st.emitted = st.t;
         for (int k = 0; k < st.n_closed; ++k)

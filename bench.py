@@ -36,8 +36,28 @@ HBM_PEAK_GBS = 8000.0
 # differences into one full-rate lane-op (v_qsad_pk_u16_u8: 16 at quarter rate)
 AD_PEAK_T = 256 * 64 * 2.4e9 * 4 / 1e12
 RT_FPS = 25.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pyramid_2k_b256_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pyramid_k_me_2k_b256_traffic.txt")
 K1_SOURCE = os.path.join(ROOT, "paper_2502_09202_amd", "csrc", "k_pyramid.hip")
+ME_SOURCE = os.path.join(ROOT, "paper_2502_09202_amd", "csrc", "k_me.hip")
+
+
+def me_traffic(streams):
+    """HBM bytes per motion-search launch (mean of the consecutive and the
+    sparse launch) from the same counter summary, or None if k_me.hip has
+    changed since the counters were taken or they were taken at another
+    batch size."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(ME_SOURCE, "rb").read()).hexdigest()
+        if kv.get("k_me.hip sha256") != sha or int(kv.get("streams", -1)) != streams:
+            return None
+        return float(kv["k_me hbm bytes per launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def k1_traffic(streams):
@@ -454,7 +474,8 @@ def main():
                               "achieved": round(nb * 289 * 64 / (ms * 1e-3) / 1e12, 2) if ms > 0 else 0.0}
         alu = {"bound": "alu", "kernel": "k_me<uint8_t>",
                "achieved": round(me_tads, 2), "peak": round(AD_PEAK_T, 1),
-               "unit": "T absdiff/s", "frac": round(me_tads / AD_PEAK_T, 4), "traffic": None,
+               "unit": "T absdiff/s", "frac": round(me_tads / AD_PEAK_T, 4),
+               "traffic": None if me_traffic(args.streams) is None else int(me_traffic(args.streams)),
                "avg_launch_us": round(me_ms / max(me_n, 1) * 1e3, 3), "ad_per_launch": ad / max(me_n, 1),
                "launches": launches}
         roof, other = (hbm, alu) if k1_ms >= me_ms else (alu, hbm)

@@ -554,22 +554,38 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
             for (int k = 0; k < 6; ++k) acc[wave][lane][k] = 0;
         }
         if (spc > 0) {
+            // each lane takes one contiguous run of the tile range: its loads
+            // are independent (many in flight), it sums each task's part of
+            // the run in registers and adds it to the task's accumulators
+            // once (a run spans few tasks, so the LDS atomics rarely collide)
             const int t0 = __shfl(mine.tile_prefix, 0, 64);
             const int t_last = __shfl(mine.tile_prefix + mine.tiles, spc - 1, 64);
-            for (int q = t0 + lane; q < t_last; q += 64) {
-                int lo = 0, hi = spc - 1;       // last task whose first tile is <= q
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (tpre[wave][mid] <= q) lo = mid; else hi = mid - 1;
+            const int per = (t_last - t0 + 63) / 64;
+            int q = t0 + lane * per;
+            const int q_end = min(t_last, q + per);
+            if (q < q_end) {
+                int j = 0, hi = spc - 1;        // last task whose first tile is <= q
+                while (j < hi) {
+                    const int mid = (j + hi + 1) >> 1;
+                    if (tpre[wave][mid] <= q) j = mid; else hi = mid - 1;
                 }
-                const TilePartial& p = spart[q];
-                unsigned long long* acc_t = reinterpret_cast<unsigned long long*>(acc[wave][lo]);
-                atomicAdd(acc_t + 0, (unsigned long long)p.sx);
-                atomicAdd(acc_t + 1, (unsigned long long)p.sy);
-                atomicAdd(acc_t + 2, (unsigned long long)p.sxx);
-                atomicAdd(acc_t + 3, (unsigned long long)p.syy);
-                atomicAdd(acc_t + 4, (unsigned long long)p.sxy);
-                atomicAdd(acc_t + 5, (unsigned long long)p.a);
+                while (q < q_end) {
+                    const int seg_end = min(q_end, j + 1 < spc ? tpre[wave][j + 1] : t_last);
+                    int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+#pragma unroll 8
+                    for (; q < seg_end; ++q) {
+                        const TilePartial& p = spart[q];
+                        s0 += p.sx; s1 += p.sy; s2 += p.sxx; s3 += p.syy; s4 += p.sxy; s5 += p.a;
+                    }
+                    unsigned long long* acc_t = reinterpret_cast<unsigned long long*>(acc[wave][j]);
+                    atomicAdd(acc_t + 0, (unsigned long long)s0);
+                    atomicAdd(acc_t + 1, (unsigned long long)s1);
+                    atomicAdd(acc_t + 2, (unsigned long long)s2);
+                    atomicAdd(acc_t + 3, (unsigned long long)s3);
+                    atomicAdd(acc_t + 4, (unsigned long long)s4);
+                    atomicAdd(acc_t + 5, (unsigned long long)s5);
+                    ++j;
+                }
             }
         }
         if (lane < spc && mine.epoch == sd.epoch && mine.result >= 0) {

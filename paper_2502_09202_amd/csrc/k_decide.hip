@@ -426,15 +426,16 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
             // the fields of the next non-static frames already ingested, as
             // many as the analysis window may still take: computed with t's
             int quota = dp.n_ss - st.ss.n - 1;
+            // (frames below spec_next were planned before, or skipped as
+            // static: the cache check in the pass covers them either way)
             for (int k = 0; k < 32 && t + 1 + k + 1 <= st.n && quota > 0 && st.plan_spec < kMaxSpec; ++k) {
                 const int u = t + 1 + k;
                 if (static_at(sd, pf, u)) continue;
                 --quota;
-                const double* cu = dp.spec + (int64_t)(u % sd.rs) * 4;
-                if (!(cu[3] == (double)u)) {
-                    st.spec_mask |= 1u << k;
-                    st.plan_spec += 1;
-                }
+                if (u < st.spec_next) continue;
+                st.spec_mask |= 1u << k;
+                st.plan_spec += 1;
+                st.spec_next = u + 1;
             }
         }
         if (plan_task_count<kSpec>(sd, st) > 0) break;       // measures requested; commit next step

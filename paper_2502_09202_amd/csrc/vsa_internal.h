@@ -125,6 +125,7 @@ struct DecideState {
     int32_t plan, plan_want, plan_fire, plan_deep, plan_nf, plan_kn;
     int32_t plan_spec;                   // speculative field frames planned with it:
     uint32_t spec_mask;                  // bit k = frame t + 1 + k
+    int32_t spec_next, spec_pad;         // frames below spec_next were considered for speculation
     int32_t done;               // end of stream fully processed
     int32_t n_closed;           // shots closed by the last advance
     int32_t sp_base, sp_count;  // where the planned tasks sit in that step's sparse list

@@ -2004,23 +2004,13 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     return VSA_OK;
 }
 
-vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_bytes, int64_t pitch_bytes,
-                        int32_t n_frames, int32_t src, vsa_frame_result* out_frames, vsa_shot_result* out_shots,
-                        int32_t shots_cap, int32_t* n_shots) {
-    if (!c) return fail(VSA_E_INVAL, "NULL clip");
-    if (n_frames < 0) return fail(VSA_E_INVAL, "negative frame count");
-    if (n_frames > 0 && (!frames || !out_frames)) return fail(VSA_E_INVAL, "NULL frames or records");
-    if (shots_cap < 0 || (shots_cap > 0 && !out_shots)) return fail(VSA_E_INVAL, "bad shot array");
-    if (src != VSA_SRC_HOST && src != VSA_SRC_DEVICE_BORROW) return fail(VSA_E_INVAL, "src must be host or device");
-    if (n_shots) *n_shots = 0;
-    if (n_frames == 0) return VSA_OK;
-    std::lock_guard<std::mutex> lk(c->mu);
+// The body of vsa_clip_run, after the argument checks and with the
+// analyser's lock held; on failure the caller waits for both streams.
+static vsa_status clip_run_body(vsa_clip* c, const void* frames, int64_t frame_stride_bytes, int64_t pitch_bytes,
+                                int32_t n_frames, int32_t src, vsa_frame_result* out_frames,
+                                vsa_shot_result* out_shots, int32_t shots_cap, int32_t* n_shots) {
     const StreamDesc& sd = c->sd;
     const int64_t row = (int64_t)sd.W * (sd.bits == 8 ? 1 : 2);
-    if (pitch_bytes < row) return fail(VSA_E_INVAL, "pitch smaller than a row");
-    if (n_frames > 1 && frame_stride_bytes < pitch_bytes * (sd.H - 1) + row)
-        return fail(VSA_E_INVAL, "frame stride smaller than a frame");
-    HIPCK(hipSetDevice(c->device), "hipSetDevice");
     const int C = c->C, T = n_frames;
     if (src == VSA_SRC_HOST && !c->d_stage) {
         c->stage_pitch = round_up(row, 256);
@@ -2076,26 +2066,18 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
             HIPCK(hipStreamSynchronize(c->s), "clip chunk");
             c->counters[2] += 1;
             if (!clip_pending(c)) break;
-            if (rounds > limit) {
-                (void)hipStreamSynchronize(c->sp);
-                return fail(VSA_E_DEVICE, "decision pass did not settle");
-            }
+            if (rounds > limit) return fail(VSA_E_DEVICE, "decision pass did not settle");
             batch = 4;
         }
         c->est_rounds = std::min(rounds, 32);
         c->counters[0] += 1;
         // records of this chunk (mapped memory, complete after the wait)
         const PubSnap ps = c->h_snap[(c->dec_no - 1) & 1];
-        if (ps.frames_written - frames_read > c->out_cap || ps.shots_written - shots_read > c->out_cap) {
-            (void)hipStreamSynchronize(c->sp);
+        if (ps.frames_written - frames_read > c->out_cap || ps.shots_written - shots_read > c->out_cap)
             return fail(VSA_E_DEVICE, "clip record ring overflow");
-        }
         for (uint64_t i = frames_read; i < ps.frames_written; ++i) {
             const OutFrame& o = c->h_out_frames[i % c->out_cap];
-            if (o.r.frame != (int64_t)i || i >= (uint64_t)T) {
-                (void)hipStreamSynchronize(c->sp);
-                return fail(VSA_E_DEVICE, "clip records out of order");
-            }
+            if (o.r.frame != (int64_t)i || i >= (uint64_t)T) return fail(VSA_E_DEVICE, "clip records out of order");
             out_frames[i] = o.r;
         }
         for (uint64_t i = shots_read; i < ps.shots_written; ++i)
@@ -2109,6 +2091,33 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
     if (frames_read != (uint64_t)T) return fail(VSA_E_DEVICE, "clip ended with frames missing");
     if (n_shots) *n_shots = (int32_t)shots_read;
     return VSA_OK;
+}
+
+vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_bytes, int64_t pitch_bytes,
+                        int32_t n_frames, int32_t src, vsa_frame_result* out_frames, vsa_shot_result* out_shots,
+                        int32_t shots_cap, int32_t* n_shots) {
+    if (!c) return fail(VSA_E_INVAL, "NULL clip");
+    if (n_frames < 0) return fail(VSA_E_INVAL, "negative frame count");
+    if (n_frames > 0 && (!frames || !out_frames)) return fail(VSA_E_INVAL, "NULL frames or records");
+    if (shots_cap < 0 || (shots_cap > 0 && !out_shots)) return fail(VSA_E_INVAL, "bad shot array");
+    if (src != VSA_SRC_HOST && src != VSA_SRC_DEVICE_BORROW) return fail(VSA_E_INVAL, "src must be host or device");
+    if (n_shots) *n_shots = 0;
+    if (n_frames == 0) return VSA_OK;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const StreamDesc& sd = c->sd;
+    const int64_t row = (int64_t)sd.W * (sd.bits == 8 ? 1 : 2);
+    if (pitch_bytes < row) return fail(VSA_E_INVAL, "pitch smaller than a row");
+    if (n_frames > 1 && frame_stride_bytes < pitch_bytes * (sd.H - 1) + row)
+        return fail(VSA_E_INVAL, "frame stride smaller than a frame");
+    HIPCK(hipSetDevice(c->device), "hipSetDevice");
+    const vsa_status st = clip_run_body(c, frames, frame_stride_bytes, pitch_bytes, n_frames, src, out_frames,
+                                        out_shots, shots_cap, n_shots);
+    if (st != VSA_OK) {
+        // nothing queued may still read the caller's frames once the call returns
+        (void)hipStreamSynchronize(c->sp);
+        (void)hipStreamSynchronize(c->s);
+    }
+    return st;
 }
 
 vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n) {

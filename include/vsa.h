@@ -25,6 +25,9 @@
  * records.  Records come out in frame order, a bounded number of frames after
  * the frame was pushed (the deep check looks ahead up to k_max+1 frames); a
  * shot record is final only once the next boundary (or the end) is known.
+ * For one clip whose frames are all at hand, the offline form (vsa_clip_*)
+ * gives the same records for the whole clip in one call, taking it a chunk
+ * of frames per launch.
  *
  * Conventions
  *   - Every call that can fail returns a vsa_status (0 = VSA_OK, < 0 error);

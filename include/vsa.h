@@ -322,8 +322,10 @@ typedef struct {
     int32_t width, height;     /* full-resolution luma size of every frame                  */
     int32_t bit_depth;         /* 8 or 10                                                   */
     int32_t k_max;             /* 0 = params default, else 1..15                            */
-    int32_t chunk;             /* frames per chunk, 1..4096; 0 = 256.  Device memory grows
-                                  with it (a ring of chunk + 2 k_max + 8 frame slots)        */
+    int32_t chunk;             /* frames per chunk, 1..4096; 0 = 256 (the first chunk takes
+                                  min(chunk, max(16, chunk / 4)) frames, so that decisions
+                                  start early).  Device memory grows with it (a ring of
+                                  2 chunk + 2 k_max + 8 frame slots)                        */
     int32_t schedule;          /* VSA_SCHEDULE_SPARSE (the paper's) or VSA_SCHEDULE_DENSE   */
     int32_t no_intensity;      /* 1: skip H(t) (h_mean/h_std/h_mad are NaN)                 */
     int32_t me_wgs_per_cu;     /* persistent motion-search workgroups per CU, 0 = default   */

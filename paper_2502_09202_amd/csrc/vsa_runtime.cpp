@@ -1789,13 +1789,19 @@ struct ClipSource {
     int32_t T, src;
 };
 
+// Chunks of a clip: the first takes min(C, max(16, C / 4)) frames, so that
+// the decisions start before a whole chunk has been ingested; the others C.
+int clip_head(int C) { return std::min(C, std::max(16, C / 4)); }
+int clip_chunk_start(int C, int ch) { return ch == 0 ? 0 : clip_head(C) + (ch - 1) * C; }
+int clip_chunks(int C, int T) { return T <= clip_head(C) ? 1 : 1 + (T - clip_head(C) + C - 1) / C; }
+
 // Fill the descriptors of chunk ch (parity ch & 1) and enqueue its ingest on
 // P: host-sourced planes, descriptor upload, K1 (+ intensity), consecutive
 // K2; then record ev_p of its parity.  *n_cons receives its consecutive pairs.
 vsa_status clip_ingest(vsa_clip* c, const ClipSource& in, int ch, int* n_cons_out, int* ctiles_out) {
     const StreamDesc& sd = c->sd;
     const int C = c->C, q = ch & 1;
-    const int f0 = ch * C, n = std::min(C, in.T - f0);
+    const int f0 = clip_chunk_start(C, ch), n = std::min(ch == 0 ? clip_head(C) : C, in.T - f0);
     const bool last = f0 + n == in.T;
     const int64_t row = (int64_t)sd.W * (sd.bits == 8 ? 1 : 2);
     uint8_t* h = c->h_desc + (size_t)q * c->desc_bytes;
@@ -2030,7 +2036,7 @@ static vsa_status clip_run_body(vsa_clip* c, const void* frames, int64_t frame_s
     std::memset(c->h_snap, 0, 2 * sizeof(PubSnap));
     c->dec_no = 0;
     const ClipSource in{static_cast<const uint8_t*>(frames), frame_stride_bytes, pitch_bytes, T, src};
-    const int n_chunks = (T + C - 1) / C;
+    const int n_chunks = clip_chunks(C, T);
     int n_cons[2] = {0, 0}, ctiles[2] = {0, 0};
     vsa_status st = clip_ingest(c, in, 0, &n_cons[0], &ctiles[0]);
     if (st != VSA_OK) return st;

@@ -1672,7 +1672,8 @@ vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, 
 //
 // The streaming engine advances each stream by one frame per step, so a lone
 // stream pays a step's launches and host work for every frame.  Here all
-// frames of the clip are at hand and are taken `chunk` at a time:
+// frames of the clip are at hand and are taken `chunk` at a time (the first
+// chunk shorter, so that the decisions start early):
 //   ingest stream (P), per chunk:
 //     K1  pyramid, fields and intensity measure of every frame of the chunk
 //         (one launch);
@@ -1696,7 +1697,10 @@ vsa_status vsa_debug_decide(const vsa_params* pp, int32_t k_max, int32_t dense, 
 // frame that the pass can still read.  The host learns whether another round
 // is needed from the cursor snapshot each decision launch writes into mapped
 // memory: it enqueues as many rounds as the previous chunk took before it
-// first waits, then four at a time.
+// first waits, then four at a time.  K6 runs as k_finish_decide<true>, which
+// also computes the fields of later frames ahead of the pass (speculative
+// field measures, cached per ring slot), so that an analysis window costs a
+// few rounds rather than one per analysed frame.
 struct vsa_clip {
     std::mutex mu;
     int device = 0;

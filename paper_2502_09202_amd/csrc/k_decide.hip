@@ -629,19 +629,15 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     }
     __syncthreads();
     // 3. decisions (lane 0 of each wave), counts of what the stream produces.
-    //    With speculation (one long sequential pass per launch) the
-    //    descriptor is copied to LDS: a private copy, indexed by pyramid
+    //    The descriptor is copied to LDS: a private copy, indexed by pyramid
     //    level at run time, would live in scratch, and reads in place would
     //    be repeated after every store of a planned task (the compiler cannot
-    //    tell them apart); otherwise it is copied to private memory (the
-    //    many streams' short passes, placed beside the motion-search grids).
-    StreamDesc sd_copy;
-    __shared__ StreamDesc sd_lds[kSpec ? kDecideWaves : 1];
-    const StreamDesc& sd = kSpec ? sd_lds[kSpec ? wave : 0] : sd_copy;
+    //    tell them apart).
+    __shared__ StreamDesc sd_lds[kDecideWaves];
+    const StreamDesc& sd = sd_lds[wave];
     DecideState st;
     if (active && lane == 0) {
-        if (kSpec) sd_lds[wave] = sds[sid];
-        else sd_copy = sds[sid];
+        sd_lds[wave] = sds[sid];
         st = states[sid];
         vsa_shot_result* closed = closed_buf + (int64_t)sid * kMaxClosed;
         const int e0 = st.emitted;

@@ -635,6 +635,11 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
     //    tell them apart).
     __shared__ StreamDesc sd_lds[kDecideWaves];
     const StreamDesc& sd = sd_lds[wave];
+    // with speculation (up to 3 + 3 kMaxSpec tasks a launch) the planned
+    // tasks are sized and written one lane per task from an LDS copy of the
+    // decision state; otherwise lane 0 does it
+    __shared__ DecideState st_lds[kSpec ? kDecideWaves : 1];
+    __shared__ int32_t ptile[kSpec ? kDecideWaves : 1][kMaxT], pblk[kSpec ? kDecideWaves : 1][kMaxT];
     DecideState st;
     if (active && lane == 0) {
         sd_lds[wave] = sds[sid];
@@ -645,11 +650,15 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         advance<kSpec>(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T, pf);
         const int nt = plan_task_count<kSpec>(sd, st);
         int tiles = 0, blocks = 0;
-        for (int q = 0; q < nt; ++q) {
-            const PairTask pt = plan_task<kSpec>(sd, st, sid, q);
-            tiles += pt.tiles;
-            const PlaneDims pd = plane_dims(sd, pt);
-            blocks += (pd.w / kBlock) * (pd.h / kBlock);
+        if (kSpec) {
+            st_lds[wave] = st;
+        } else {
+            for (int q = 0; q < nt; ++q) {
+                const PairTask pt = plan_task<kSpec>(sd, st, sid, q);
+                tiles += pt.tiles;
+                const PlaneDims pd = plane_dims(sd, pt);
+                blocks += (pd.w / kBlock) * (pd.h / kBlock);
+            }
         }
         Bcast& b = bc[wave];
         b.info = sd.info; b.rs = sd.rs; b.sid = sid; b.epoch = sd.epoch; b.e0 = e0; b.nframes = st.t - e0; b.nshots = st.n_closed;
@@ -659,6 +668,23 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         b.nframes = 0; b.nshots = 0; b.ntasks = 0; b.tiles = 0; b.blocks = 0;
     }
     __syncthreads();
+    if (kSpec) {
+        // tiles and blocks of the planned tasks, one lane per task
+        if (active && lane < bc[wave].ntasks) {
+            const PairTask pt = plan_task<kSpec>(sd, st_lds[wave], sid, lane);
+            const PlaneDims pd = plane_dims(sd, pt);
+            ptile[wave][lane] = pt.tiles;
+            pblk[wave][lane] = (pd.w / kBlock) * (pd.h / kBlock);
+        }
+        __syncthreads();
+        if (active && lane == 0) {
+            int tiles = 0, blocks = 0;
+            for (int q = 0; q < bc[wave].ntasks; ++q) { tiles += ptile[wave][q]; blocks += pblk[wave][q]; }
+            bc[wave].tiles = tiles;
+            bc[wave].blocks = blocks;
+        }
+        __syncthreads();
+    }
     // one reservation per counter for the whole workgroup
     if (threadIdx.x == 0) {
         int nt = 0, ti = 0, nf = 0, ns = 0, bl = 0;
@@ -681,7 +707,32 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         }
     }
     __syncthreads();
-    if (active && lane == 0) {
+    if (kSpec && active && lane < bc[wave].ntasks) {
+        // task `lane`: its first tile follows the tiles of the tasks before it
+        const Bcast& b = bc[wave];
+        int pre = b.tile;
+        for (int r = 0; r < lane; ++r) pre += ptile[wave][r];
+        PairTask t = plan_task<kSpec>(sd, st_lds[wave], sid, lane);
+        t.tile_prefix = pre;
+        sparse_next[b.task + lane] = t;
+        sjobs_next[b.task + lane] = make_tile_job(sd, t, nullptr);
+        npre[wave][lane] = pre;
+    }
+    if (kSpec && active && lane == 0) {
+        const Bcast& b = bc[wave];
+        int32_t* slog = log ? log + (int64_t)sid * log_cap * 6 : nullptr;
+        int end = b.tile;
+        for (int q = 0; q < b.ntasks; ++q) {
+            end += ptile[wave][q];
+            if (slog) log_task(slog, log_cap, st, plan_task<kSpec>(sd, st, sid, q));
+        }
+        npre[wave][b.ntasks] = end;
+        st.sp_base = b.task;
+        st.sp_count = b.ntasks;
+        st.emitted = st.t;
+        states[sid] = st;
+    }
+    if (!kSpec && active && lane == 0) {
         const Bcast& b = bc[wave];
         int32_t* slog = log ? log + (int64_t)sid * log_cap * 6 : nullptr;
         int tile = b.tile;

@@ -382,6 +382,13 @@ vsa_status vsa_debug_pair(const vsa_params* p, const uint16_t* I, const uint16_t
                           int32_t h, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
                           int32_t* sad, int64_t* ints, double* dbl);
 
+/* How vsa_clip_run splits an n_frames clip at this chunk size (0 = 256):
+ * chunk i covers frames starts[i] .. starts[i] + counts[i] - 1, for the first
+ * min(count, cap) chunks (arrays of cap entries, the caller's; NULL with cap
+ * 0 to count).  Host arithmetic only.  Returns the chunk count, or
+ * VSA_E_INVAL. */
+int32_t vsa_debug_clip_chunks(int32_t chunk, int32_t n_frames, int32_t* starts, int32_t* counts, int32_t cap);
+
 /* The finishing arithmetic of Sec. III.A on n integer tuples
  * (Sx, Sy, Sxx, Syy, Sxy, N, A, B) -> n x (NCC, SWR, AMM, ACT), computed by the
  * device (ints: n x 8 int64; out: n x 4 double; both the caller's). */

@@ -2130,6 +2130,19 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
     return st;
 }
 
+int32_t vsa_debug_clip_chunks(int32_t chunk, int32_t n_frames, int32_t* starts, int32_t* counts, int32_t cap) {
+    const int C = chunk ? chunk : 256;
+    if (C < 1 || C > 4096 || n_frames < 0 || cap < 0 || (cap > 0 && (!starts || !counts)))
+        return fail(VSA_E_INVAL, "bad argument");
+    if (n_frames == 0) return 0;
+    const int n = clip_chunks(C, n_frames);
+    for (int ch = 0; ch < n && ch < cap; ++ch) {
+        starts[ch] = clip_chunk_start(C, ch);
+        counts[ch] = std::min(ch == 0 ? clip_head(C) : C, n_frames - starts[ch]);
+    }
+    return n;
+}
+
 vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n) {
     if (!c || !out || n < 0) return fail(VSA_E_INVAL, "bad argument");
     std::lock_guard<std::mutex> lk(c->mu);

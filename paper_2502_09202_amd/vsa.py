@@ -88,6 +88,7 @@ SYMBOLS = [
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
     "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters",
+    "vsa_debug_clip_chunks",
 ]
 
 _lib = None
@@ -145,6 +146,7 @@ def lib():
         "vsa_clip_destroy": (None, [P]),
         "vsa_clip_run": (i32, [P, P, i64, i64, i32, i32, P, P, i32, C.POINTER(i32)]),
         "vsa_clip_counters": (i32, [P, P, i32]),
+        "vsa_debug_clip_chunks": (i32, [i32, i32, P, P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -454,6 +456,14 @@ def run_clip(frames: np.ndarray, params: Optional[dict] = None, bit_depth: int =
 
 
 # -- test hooks ---------------------------------------------------------------
+
+def debug_clip_chunks(chunk: int, n_frames: int):
+    """(starts, counts) of the chunks vsa_clip_run takes an n_frames clip in."""
+    n = _check(lib().vsa_debug_clip_chunks(chunk, n_frames, None, None, 0), "debug_clip_chunks")
+    starts, counts = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    _check(lib().vsa_debug_clip_chunks(chunk, n_frames, _ptr(starts), _ptr(counts), n), "debug_clip_chunks")
+    return starts, counts
+
 
 def debug_levels(plane: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8) -> np.ndarray:
     a = np.ascontiguousarray(plane)

@@ -92,3 +92,13 @@ def test_clip_config_checks(vsa):
     lib.vsa_clip_destroy(None)   # no-op
     assert lib.vsa_clip_run(None, None, 0, 0, 0, 0, None, None, 0, None) == vsa.E_INVAL
     assert lib.vsa_clip_counters(None, None, 0) == vsa.E_INVAL
+
+
+def test_clip_without_device(vsa):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(vsa.VsaError) as ei:
+        vsa.Clip(64, 32)
+    assert ei.value.code == vsa.E_DEVICE
+    assert vsa.last_error()

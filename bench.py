@@ -129,6 +129,8 @@ def render_frames(kind, n, W, H, workers, bits=8):
         jobs = [(kind, n, int(a), int(b), shm.name) for a, b in zip(chunks[:-1], chunks[1:]) if b > a]
         with mp.get_context("spawn").Pool(workers) as pool:
             done = sum(pool.map(_render_range, jobs))
+            pool.close()          # workers exit on their own; the with-exit then terminates nothing
+            pool.join()
         assert done == n
         frames = np.ndarray((n, H, W), dt, buffer=shm.buf).copy()
     finally:
@@ -236,6 +238,20 @@ def serve_requests(serve, pools, n, rate, seed, lengths=(200, 3000)):
     return reqs
 
 
+def geometry(W, H, params):
+    """Pyramid geometry of a W x H stream (the engine's level rule): level
+    sizes halve with the odd row / column dropped; the working level L is the
+    first no wider than wmax, the field level Lf = max(0, L - lf_offset), and
+    Lcap the coarsest level still holding 2 x 2 blocks of 8 x 8."""
+    dims = [(W, H)]
+    while dims[-1][0] > 1 and dims[-1][1] > 1:
+        dims.append((dims[-1][0] // 2, dims[-1][1] // 2))
+    L = next(i for i, (w, _) in enumerate(dims) if w <= params["wmax"])
+    Lcap = max(i for i, (w, h) in enumerate(dims) if i >= L and w // 8 >= 2 and h // 8 >= 2)
+    Lf = max(0, L - params["lf_offset"])
+    return {"L": L, "Lcap": Lcap, "Lf": Lf, "dims": dims, "field": (W >> Lf, (H // 2) >> Lf)}
+
+
 def k1_tiles(g):
     """Pyramid tiles of one frame (64 x 16 working-level pixels up to L = 2,
     32 x 16 at L = 3, 16 x 16 beyond; the grid also covers the fields)."""
@@ -263,11 +279,35 @@ def k1_bytes_per_frame(g, W, H, k_max, intensity=True):
     return b + 2 * wf * hf + (k1_tiles(g) * 256 * 2 if intensity else 0)
 
 
-def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, **engine_kw):
+# Untimed steps before any timed window.  Every stream opens a shot at its
+# first frame, so for the first n_ss + k_max + a few steps all streams analyse
+# their first shot's fields at once (about 4x the sparse work of the steady
+# state); the timed steps start after that transient whatever --warmup says.
+PREROLL_STEPS = 96
+MARKER = "spin_kernel"     # torch.cuda._sleep's kernel: brackets the timed steps in a kernel trace
+
+
+def mark(torch):
+    """A tiny, uniquely named kernel on the device (torch.cuda._sleep), with
+    the device idle before and after it: the boundaries of the headline's
+    timed steps in a rocprofv3 trace or counter run of this command."""
+    torch.cuda.synchronize()
+    torch.cuda._sleep(1000)
+    torch.cuda.synchronize()
+
+
+def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, preroll=PREROLL_STEPS, markers=False,
+               src=None, **engine_kw):
+    """B streams of the resident clip (stream i starts at frame i*F/B), `preroll
+    + warmup` untimed steps, then `steps` timed ones.  src: None reads the
+    frames in place from device memory; a pinned host tensor of the same clip
+    makes every step upload its planes from host memory (end-to-end rate)."""
     F, H, W = dev_frames.shape
     e = vsa.Engine(device=0, max_streams=max(B, 1), params=params, profile=int(profile), **engine_kw)
     sids = np.array([e.stream_open(W, H, 8) for _ in range(B)], np.int32)
-    base = dev_frames.data_ptr()
+    host = src is not None
+    base = (src if host else dev_frames).data_ptr()
+    mode = vsa.SRC_HOST_BORROW if host else vsa.SRC_DEVICE_BORROW
     fbytes = H * W
     offs = (np.arange(B) * (F // B)) % F
     pitches = np.full(B, W, np.int64)
@@ -275,24 +315,28 @@ def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, **engi
     def do_step(s):
         idx = (offs + s) % F
         ptrs = (base + idx.astype(np.uint64) * fbytes).astype(np.uint64)
-        rc = e.stream_push_batch(sids, ptrs, pitches, vsa.SRC_DEVICE_BORROW, None)
+        rc = e.stream_push_batch(sids, ptrs, pitches, mode, None)
         if rc != 0:
             raise RuntimeError(vsa.last_error())
         e.step()
 
-    for s in range(warmup):
+    for s in range(preroll + warmup):
         do_step(s)
     e.sync()
     torch.cuda.synchronize()
     if profile:
         e.kernel_times(reset=True)
     c0 = e.counters()
+    if markers:
+        mark(torch)
     t0 = time.perf_counter()
-    for s in range(warmup, warmup + steps):
+    for s in range(preroll + warmup, preroll + warmup + steps):
         do_step(s)
     e.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if markers:
+        mark(torch)
     c1 = e.counters()
     kt = e.kernel_times() if profile else None
     frames_out = sum(len(e.poll_frames(int(sid), 1 << 20)) for sid in sids)
@@ -318,7 +362,29 @@ def run_clip_leg(vsa, dev_frames, params, chunk, runs, torch):
     return out, per_run, len(res["shots"])
 
 
-def cpu_baseline(frames, params, budget_s):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_sample(args):
+    frames, params = args
+    import oracle
+    t0 = time.perf_counter()
+    oracle.run_clip(frames, params)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(frames, params, budget_s, copies_max=8):
+    """The oracle as it stands (plain scalar C++, one thread per clip) on the
+    first frames of the same 2K clip: one process, then min(nproc, 8)
+    processes each analysing that sample at once (independent clips are the
+    only parallelism the oracle has).  value = the parallel aggregate."""
     import oracle
     if not os.path.exists(oracle.LIB_PATH):
         oracle.build()
@@ -327,11 +393,57 @@ def cpu_baseline(frames, params, budget_s):
     oracle.run_clip(frames[:n], params)
     per = (time.perf_counter() - t0) / n
     n = int(max(8, min(len(frames), budget_s / max(per, 1e-6))))
+    sample = np.ascontiguousarray(frames[:n])
+    dt1 = _oracle_sample((sample, params))
+    nproc = os.cpu_count() or 1
+    copies = max(1, min(nproc, copies_max))
     t0 = time.perf_counter()
-    oracle.run_clip(frames[:n], params)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} frames of the 2048x1080 clip, one process, sparse schedule"}
+    with mp.get_context("spawn").Pool(copies) as pool:
+        times = pool.map(_oracle_sample, [(sample, params)] * copies)
+        pool.close()
+        pool.join()
+    wall = time.perf_counter() - t0
+    agg = copies * n / max(times)
+    return {"value": round(agg, 3), "unit": "frames/s", "cores": copies, "kind": "oracle",
+            "sample": f"first {n} frames of the 2048x1080 clip (k_max 8, sparse schedule), analysed by "
+                      f"{copies} oracle processes at once (one thread each); value = {copies} x {n} frames / "
+                      f"slowest process",
+            "single_process_fps": round(n / dt1, 3), "per_core_fps": round(agg / copies, 3),
+            "x_realtime_single": round(n / dt1 / RT_FPS, 3), "wall_s_parallel": round(wall, 2),
+            "nproc": nproc, "cpu_model": _cpu_model()}
+
+
+def summarize_trace(path):
+    """Per-kernel statistics of a rocprofv3 CSV (kernel trace or counter
+    collection) restricted to the dispatches between the two marker kernels
+    that bracket the headline's timed steps (dispatch ids strictly between)."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    if not rows:
+        raise SystemExit(f"{path}: no rows")
+    key = "Dispatch_Id" if "Dispatch_Id" in rows[0] else "Correlation_Id"
+    marks = sorted({int(r[key]) for r in rows if MARKER in r["Kernel_Name"]})
+    if len(marks) < 2:
+        raise SystemExit(f"{path}: {len(marks)} marker dispatches (need 2)")
+    lo, hi = marks[0], marks[1]
+    win = [r for r in rows if lo < int(r[key]) < hi]
+    out = {}
+    if "Counter_Name" in rows[0]:
+        for r in win:
+            d = out.setdefault((r["Kernel_Name"], r["Counter_Name"]), {})
+            d[int(r[key])] = d.get(int(r[key]), 0.0) + float(r["Counter_Value"])
+        print(f"# {path}: dispatches {lo + 1}..{hi - 1} (between the markers)")
+        print(f"# {'kernel':<44} {'counter':<12} {'dispatches':>10} {'mean per dispatch':>18}")
+        for (k, c), d in sorted(out.items()):
+            print(f"  {k[:44]:<44} {c:<12} {len(d):>10} {sum(d.values()) / len(d):>18.1f}")
+        return
+    for r in win:
+        d = out.setdefault(r["Kernel_Name"], [])
+        d.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print(f"# {path}: dispatches {lo + 1}..{hi - 1} (between the markers)")
+    print(f"# {'kernel':<44} {'calls':>6} {'total ms':>9} {'avg us':>9} {'min us':>9} {'max us':>9}")
+    for k, d in sorted(out.items(), key=lambda kv: -sum(kv[1])):
+        print(f"  {k[:44]:<44} {len(d):>6} {sum(d) / 1e3:>9.3f} {sum(d) / len(d):>9.2f} {min(d):>9.2f} {max(d):>9.2f}")
 
 
 def main():
@@ -347,7 +459,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--gpu-warm-steps", type=int, default=1000,
+    ap.add_argument("--gpu-warm-steps", type=int, default=500,
                     help="untimed steps of a separate engine before the timed run (clocks, code objects)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-stream comparison run")
     ap.add_argument("--no-diag", action="store_true", help="skip the all-kernel timing run")
@@ -366,7 +478,17 @@ def main():
     ap.add_argument("--clip-only", action="store_true",
                     help="only the offline single-clip run (one JSON line of its own; for kernel traces)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--preroll", type=int, default=PREROLL_STEPS,
+                    help="untimed steps before the warm-up steps of every batched run (first-shot transient)")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end run from pinned host memory")
+    ap.add_argument("--e2e-steps", type=int, default=40)
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print per-kernel figures of a rocprofv3 kernel-trace or counter CSV of this command "
+                         "over the headline's timed steps (between the marker kernels) and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); streams shard across "
               "GPUs with no exchange, so run one process per GPU", file=sys.stderr)
@@ -377,7 +499,6 @@ def main():
         return
 
     import torch
-    import oracle  # noqa: F401  (cpu baseline only)
     from paper_2502_09202_amd import vsa
 
     W, H = 2048, 1080
@@ -410,30 +531,57 @@ def main():
     if args.gpu_warm_steps > 0:
         # the GPU sat idle while the frames were rendered on the host: a run
         # straight after that is slower by up to a third until the clocks rise
-        run_engine(vsa, dev, params, args.streams, args.gpu_warm_steps, 0, 0, torch)
+        run_engine(vsa, dev, params, args.streams, args.gpu_warm_steps, 0, 0, torch, preroll=0)
+    # the headline: kernel launches timed by events their own dispatch stamps
+    # (no extra commands on the streams), the timed steps bracketed by marker
+    # kernels for the trace and counter runs of this same command
     dt, kt, c0, c1, nout = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup,
-                                      0 if args.no_profile else 1, torch)
+                                      0 if args.no_profile else 1, torch, preroll=args.preroll, markers=True)
     fps = args.streams * args.steps / dt
     print(f"[bench] batched B={args.streams}: {fps:.0f} frames/s, {1e3 * dt / args.steps:.3f} ms/step, "
           f"{nout} records", file=sys.stderr, flush=True)
     extra = {}
+    if not args.no_profile:
+        # the same run with the engine's timing events off: what they cost
+        odt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,
+                                     preroll=args.preroll)
+        extra["events_off"] = {"fps": round(args.streams * args.steps / odt, 1),
+                               "ms_per_step": round(1e3 * odt / args.steps, 4)}
+        print(f"[bench] batched B={args.streams}, timing events off: {args.streams * args.steps / odt:.0f} "
+              "frames/s", file=sys.stderr, flush=True)
     if args.also_streams > 0:
-        adt, _, _, _, _ = run_engine(vsa, dev, params, args.also_streams, args.steps, args.warmup, 0, torch)
-        extra[f"batched_{args.also_streams}_streams"] = {"fps": round(args.also_streams * args.steps / adt, 1),
+        adt, _, _, _, _ = run_engine(vsa, dev, params, args.also_streams, args.steps, args.warmup, 0, torch,
+                                     preroll=args.preroll)
+        afps = args.also_streams * args.steps / adt
+        extra[f"batched_{args.also_streams}_streams"] = {"fps": round(afps, 1),
+                                                         "x_realtime_per_stream": round(afps / args.also_streams / RT_FPS, 1),
                                                          "ms_per_step": round(1e3 * adt / args.steps, 4)}
-        print(f"[bench] batched B={args.also_streams}: {args.also_streams * args.steps / adt:.0f} frames/s",
-              file=sys.stderr, flush=True)
+        print(f"[bench] batched B={args.also_streams}: {afps:.0f} frames/s", file=sys.stderr, flush=True)
     if not args.no_intensity_leg:
         # the same batched run without the unary intensity measure (no decision uses it)
         ndt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,
-                                     no_intensity=1)
+                                     preroll=args.preroll, no_intensity=1)
         extra["batched_no_intensity"] = {"fps": round(args.streams * args.steps / ndt, 1),
                                          "ms_per_step": round(1e3 * ndt / args.steps, 4)}
         print(f"[bench] batched B={args.streams} without the intensity measure: "
               f"{args.streams * args.steps / ndt:.0f} frames/s", file=sys.stderr, flush=True)
+    if not args.no_e2e and args.e2e_steps > 0:
+        # end to end: every step uploads its planes from pinned host memory
+        # (VSA_SRC_HOST_BORROW, one DMA per plane, no host-side copy)
+        pinned = torch.from_numpy(frames).pin_memory()
+        edt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.e2e_steps, 5, 0, torch,
+                                     preroll=args.preroll // 4, src=pinned)
+        efps = args.streams * args.e2e_steps / edt
+        extra["end_to_end_pinned_host"] = {
+            "workload": f"the headline's {args.streams} streams with every plane uploaded from pinned host "
+                        "memory by the step (Y plane only, one host-to-device copy each)",
+            "fps": round(efps, 1), "x_realtime": round(efps / RT_FPS, 1),
+            "upload_GBps": round(efps * W * H / 1e9, 2), "steps": args.e2e_steps}
+        print(f"[bench] end to end from pinned host memory: {efps:.0f} frames/s", file=sys.stderr, flush=True)
+        del pinned
     plain_fps = None
     if not args.no_plain and args.plain_steps > 0:
-        pdt, _, _, _, _ = run_engine(vsa, dev, params, 1, args.plain_steps, 20, 0, torch)
+        pdt, _, _, _, _ = run_engine(vsa, dev, params, 1, args.plain_steps, 20, 0, torch, preroll=0)
         plain_fps = args.plain_steps / pdt
         print(f"[bench] plain 1 stream: {plain_fps:.0f} frames/s", file=sys.stderr, flush=True)
     if not args.no_clip:
@@ -443,9 +591,10 @@ def main():
     kt_all = None
     if not args.no_diag:
         # untimed diagnostic: every kernel timed, for the per-kernel breakdown
-        _, kt_all, _, _, _ = run_engine(vsa, dev, params, args.streams, min(args.steps, 200), 20, 2, torch)
+        _, kt_all, _, _, _ = run_engine(vsa, dev, params, args.streams, min(args.steps, 200), 20, 2, torch,
+                                        preroll=args.preroll)
 
-    g = oracle.geometry(W, H, params)
+    g = geometry(W, H, params)
     k1b = k1_bytes_per_frame(g, W, H, params["k_max"])
     roof = None
     if kt:
@@ -551,6 +700,10 @@ def main():
                                f"{args.frames}-frame seeded clip resident in HBM, k_max 8, sparse schedule",
                    "streams": args.streams, "width": W, "height": H, "bit_depth": 8},
         "x_realtime": round(fps / RT_FPS, 1),
+        "x_realtime_per_stream": round(fps / args.streams / RT_FPS, 1),
+        "untimed_steps": {"preroll": args.preroll, "warmup": args.warmup,
+                          "why": "every stream opens a shot at its first frame; the preroll takes all of them "
+                                 "past that shot's analysis window, so the timed steps are the steady state"},
         "plain_fps": None if plain_fps is None else round(plain_fps, 1),
         "plain_x_realtime": None if plain_fps is None else round(plain_fps / RT_FPS, 1),
         "roofline": roof,

@@ -120,9 +120,13 @@ enum {
                                   call returns; the caller may reuse the buffer at once          */
     VSA_SRC_DEVICE_COPY = 1,   /* device memory; copied into engine-owned device memory before
                                   the call returns                                               */
-    VSA_SRC_DEVICE_BORROW = 2  /* device memory read in place by the next vsa_step; the caller
+    VSA_SRC_DEVICE_BORROW = 2, /* device memory read in place by the next vsa_step; the caller
                                   keeps it valid and unmodified until that step has completed:
                                   vsa_sync has returned, or vsa_collect counts it as published  */
+    VSA_SRC_HOST_BORROW = 3    /* host memory (pinned by the caller, e.g. hipHostMalloc, for a
+                                  direct DMA) uploaded by the next vsa_step without a host-side
+                                  copy; kept valid and unmodified until that step has completed,
+                                  as for VSA_SRC_DEVICE_BORROW                                   */
 };
 
 /* Per-frame record.  The pair measures describe (frame -> frame+1) at the

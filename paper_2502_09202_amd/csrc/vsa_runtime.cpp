@@ -873,7 +873,7 @@ vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t
         HIPCK(hipStreamSynchronize(e->stream_b), "device copy");
         s->pend_src = s->staging_dev[slot];
         s->pend_pitch = s->staging_pitch;
-    } else if (src == VSA_SRC_DEVICE_BORROW) {
+    } else if (src == VSA_SRC_DEVICE_BORROW || src == VSA_SRC_HOST_BORROW) {
         s->pend_src = luma;
         s->pend_pitch = pitch;
     } else {
@@ -1051,10 +1051,18 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
                                      hipMemcpyHostToDevice, Bs), "plane upload");
                 HIPCK(hipEventRecord(e->stage_ev[2 * sid + slot], Bs), "event");
                 ss.src = s.staging_dev[slot];
+                ss.src_pitch = s.pend_pitch;
+            } else if (s.pend_mode == VSA_SRC_HOST_BORROW) {
+                // the caller's (pinned) plane straight into the device staging slot
+                const int64_t row = (int64_t)s.sd.W * (s.sd.bits == 8 ? 1 : 2);
+                HIPCK(hipMemcpy2DAsync(s.staging_dev[slot], s.staging_pitch, s.pend_src, s.pend_pitch, row,
+                                       s.sd.H, hipMemcpyHostToDevice, Bs), "plane upload");
+                ss.src = s.staging_dev[slot];
+                ss.src_pitch = s.staging_pitch;
             } else {
                 ss.src = s.pend_src;
+                ss.src_pitch = s.pend_pitch;
             }
-            ss.src_pitch = s.pend_pitch;
             ss.k1_tiles = pyramid_tiles(s.sd);
             k1[n_k1++] = n_steps;
             if (s.next_frame >= 1) {

@@ -135,12 +135,15 @@ class Server:
         self.engine.close()
 
     def run(self, requests: List[ClipRequest], clock: Callable[[], float] = time.perf_counter,
-            keep_records: bool = True) -> ServeReport:
+            keep_records: bool = True, poll_cap: int = 0) -> ServeReport:
+        """Serve `requests` to completion.  poll_cap bounds the records taken
+        from the engine per step (0: max(4096, 8 x active clips)); whatever a
+        finished clip still has queued is drained before its slot is freed."""
         e = self.engine
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         waiting: deque = deque()
         active: Dict[int, _Clip] = {}
-        push_time: List[float] = []          # per step: when its pushes returned
+        push_time = np.zeros(1024)           # per step: when its pushes returned
         lat: List[np.ndarray] = []
         results: Dict[int, ClipResult] = {}
         qwait: List[float] = []
@@ -149,6 +152,13 @@ class Server:
         frames_total = 0
         t0 = clock()
         step = 0
+
+        def take(c: _Clip, r: np.ndarray, t_poll: float) -> int:
+            lat.append(t_poll - push_time[c.admit_step + r["frame"].astype(np.int64)])
+            if keep_records:
+                c.frames.append(r)
+            return len(r)
+
         while pending or waiting or active:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
@@ -182,24 +192,27 @@ class Server:
                 if c.pushed == c.req.length and not c.ended:
                     e.stream_end(c.sid)
                     c.ended = True
-            push_time.append(clock() - t0)
+            if step == len(push_time):
+                push_time = np.concatenate([push_time, np.zeros_like(push_time)])
+            push_time[step] = clock() - t0
             e.step()
             step += 1
             e.collect()
-            sids, recs = e.poll_frames_all(max(4096, 8 * len(active)))
+            sids, recs = e.poll_frames_all(poll_cap if poll_cap > 0 else max(4096, 8 * len(active)))
             t_poll = clock() - t0
-            if len(recs):
-                frames_total += len(recs)
-                pt = np.asarray(push_time)
-                for sid in np.unique(sids):
-                    c = active[int(sid)]
-                    r = recs[sids == sid]
-                    lat.append(t_poll - pt[c.admit_step + r["frame"].astype(np.int64)])
-                    if keep_records:
-                        c.frames.append(r)
+            for sid in np.unique(sids):
+                frames_total += take(active[int(sid)], recs[sids == sid], t_poll)
             for sid in [s for s, c in active.items() if c.ended]:
                 c = active[sid]
                 if e.stream_done(sid):
+                    # every record is published; some may still wait in the
+                    # stream's queue (the per-step poll is capped): take them
+                    # all before the slot (and its queue) is freed
+                    while True:
+                        r = e.poll_frames(sid, 4096)
+                        if not len(r):
+                            break
+                        frames_total += take(c, r, clock() - t0)
                     shots = e.poll_shots(sid)
                     c.shots.append(shots)
                     done = clock() - t0
@@ -301,6 +314,14 @@ class PlainServer:
                     if keep_records:
                         c.frames.append(recs)
                 if c.ended and e.stream_done(sid):
+                    while True:               # drain what the capped poll left
+                        r = e.poll_frames(sid, 4096)
+                        if not len(r):
+                            break
+                        frames_total += len(r)
+                        lat.append(clock() - t0 - np.asarray(pts)[r["frame"].astype(np.int64)])
+                        if keep_records:
+                            c.frames.append(r)
                     c.shots.append(e.poll_shots(sid))
                     finished.append(cid)
             for cid in finished:

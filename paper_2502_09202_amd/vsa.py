@@ -21,7 +21,7 @@ DEFAULT_PARAMS_JSON = os.path.join(HERE, "params", "default.json")
 
 OK, E_INVAL, E_NOMEM, E_ADMIT, E_STATE, E_DEVICE, E_AGAIN, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 SCHEDULE_SPARSE, SCHEDULE_DENSE = 0, 1
-SRC_HOST, SRC_DEVICE_COPY, SRC_DEVICE_BORROW = 0, 1, 2
+SRC_HOST, SRC_DEVICE_COPY, SRC_DEVICE_BORROW, SRC_HOST_BORROW = 0, 1, 2, 3
 F_HAS_PAIR, F_STATIC, F_FAST_FIRED, F_IN_TRANSITION = 1, 2, 4, 8
 F_KEYFRAME, F_SHOT_START, F_ANALYZED = 16, 32, 64
 SAMPLING_NAMES = {0: "undetermined", 1: "progressive", 2: "tff", 3: "bff", 4: "pulldown32"}

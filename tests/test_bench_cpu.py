@@ -45,10 +45,42 @@ def _expected_k1_bytes(W, H, k_max, wmax=512):
     return W * H + levels + fields + tiles * 256 * 2
 
 
-def test_pyramid_bytes_per_frame(orc, params):
+def test_pyramid_bytes_per_frame(params):
     sys.path.insert(0, ROOT)
     import bench
     p = dict(params, k_max=8)
-    g = orc.geometry(2048, 1080, p)
+    g = bench.geometry(2048, 1080, p)
     got = bench.k1_bytes_per_frame(g, 2048, 1080, 8)
     assert got == _expected_k1_bytes(2048, 1080, 8) == 3018432
+
+
+def test_bench_geometry_matches_the_level_rule(orc, params):
+    """bench.py sizes its bytes with its own geometry (not the oracle's); the
+    two agree on every format of the workloads and some odd sizes."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for W, H in ((320, 180), (720, 576), (1280, 720), (1920, 1080), (2048, 1080), (3840, 2160), (4099, 2051),
+                 (64, 32), (1001, 77)):
+        a, b = bench.geometry(W, H, params), orc.geometry(W, H, params)
+        assert (a["L"], a["Lf"], a["Lcap"], a["field"]) == (b["L"], b["Lf"], b["Lcap"], b["field"]), (W, H)
+        assert a["dims"][:b["Lcap"] + 1] == b["dims"][:b["Lcap"] + 1], (W, H)
+
+
+def test_trace_summary_between_markers(tmp_path):
+    """The kernel-trace summary takes only the dispatches between the two
+    marker kernels (the headline's timed steps)."""
+    rows = ["Kind,Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp",
+            "K,1,vsa::k_me<unsigned char>,0,500000",
+            "K,2,at::cuda::spin_kernel(long),600000,601000",
+            "K,3,vsa::k_me<unsigned char>,700000,710000",
+            "K,4,vsa::k_me<unsigned char>,710000,730000",
+            "K,5,\"vsa::k_pyramid<unsigned char, 2>\",710000,711000",
+            "K,6,at::cuda::spin_kernel(long),800000,801000",
+            "K,7,vsa::k_me<unsigned char>,900000,990000"]
+    f = tmp_path / "kernel_trace.csv"
+    f.write_text("\n".join(rows) + "\n")
+    r = subprocess.run([sys.executable, BENCH, "--summarize-trace", str(f)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    line = next(l for l in r.stdout.splitlines() if "k_me" in l)
+    assert line.split()[-5:] == ["2", "0.030", "15.00", "10.00", "20.00"]

@@ -365,6 +365,29 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
  * [3] sparse pair tasks computed, summed over the analyser's runs. */
 vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the pair measure of
+ * vsa_debug_pair (motion field, exact moments, NCC, SWR, AMM, ACT; Sec. III.A)
+ * on two w x h planes already in device memory, with nothing allocated.  Every
+ * intermediate lives in one fixed device array of the library (about 4 MiB,
+ * held on each GPU the library runs on until the process ends); the call only
+ * enqueues kernels on hip_stream (nullable: the null stream) on the calling
+ * thread's current device and returns without waiting.
+ *   I, J          planes of uint8 (bit_depth 8) or uint16 samples <= 1023 (bit_depth
+ *                 10, 2-byte aligned), rows pitch_bytes apart; read, not kept
+ *   w, h          8..1024 each (larger: VSA_E_INVAL, the array's limit)
+ *   mv            device, (w/8)*(h/8) x 2 int8 (dx, dy per block), or NULL
+ *   ints          device, 9 int64: Sx, Sy, Sxx, Syy, Sxy, N, A, B, STATIC; or NULL
+ *   dbl           device, 4 doubles: NCC, SWR, AMM, ACT; or NULL
+ * The outputs are the caller's and are written when the stream reaches the
+ * work.  All calls on one GPU share the array: calls that may overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Errors: VSA_E_INVAL (NULL plane, size, pitch, alignment, bit depth),
+ * VSA_E_UNSUPPORTED (block or radius other than 8), VSA_E_DEVICE. */
+vsa_status vsa_pair_noalloc(const vsa_params* p, const void* I, const void* J, int32_t w, int32_t h,
+                            int64_t pitch_bytes, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
+                            int64_t* ints, double* dbl, void* hip_stream);
+
 /* Thread-local description of the last error; valid until the next call. */
 const char* vsa_last_error(void);
 

@@ -82,6 +82,16 @@ vsa_status hip_fail(hipError_t e, const char* what) {
     return VSA_E_DEVICE;
 }
 
+}  // namespace
+
+namespace vsa {
+// error reporting for the library's other translation units
+vsa_status report_error(vsa_status code, const char* msg) { return fail(code, msg); }
+vsa_status report_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace vsa
+
+namespace {
+
 #define HIPCK(x, what)                                  \
     do {                                                \
         hipError_t e_ = (x);                            \

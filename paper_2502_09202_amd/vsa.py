@@ -88,7 +88,7 @@ SYMBOLS = [
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
     "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters",
-    "vsa_debug_clip_chunks",
+    "vsa_debug_clip_chunks", "vsa_pair_noalloc",
 ]
 
 _lib = None
@@ -147,6 +147,7 @@ def lib():
         "vsa_clip_run": (i32, [P, P, i64, i64, i32, i32, P, P, i32, C.POINTER(i32)]),
         "vsa_clip_counters": (i32, [P, P, i32]),
         "vsa_debug_clip_chunks": (i32, [i32, i32, P, P, i32]),
+        "vsa_pair_noalloc": (i32, [C.POINTER(Params), P, P, i32, i32, i64, i32, i32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

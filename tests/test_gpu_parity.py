@@ -211,6 +211,23 @@ def test_decide_injected(vsa, orc, params, seed, dense):
     assert np.array_equal(np.sort(got["keys"]), np.sort(rk))
 
 
+def test_decide_pinned_branches(vsa, orc, params):
+    """The hand-built sequences that pin the pass's rarer branches on the
+    oracle (look-back truncated at the shot start, the clip end's missing
+    V_{K+1}, the interlace vote's middle band, the field-order tie, a flash
+    before a dissolve) give the same records, shots and measure requests on
+    the device decision kernel."""
+    import test_oracle_decide as tod
+    for name, seq, kw in tod.branch_cases():
+        p = dict(params, **kw)
+        ref = orc.decide_injected(seq, p)
+        got = vsa.debug_decide(seq, p, k_max=p["k_max"])
+        _cmp_records(got["frames"], ref["frames"], check_pair=False)
+        _cmp_shots(got["shots"], ref["shots"])
+        rk = ref["keys"][ref["keys"]["kind"] != 0]
+        assert np.array_equal(np.sort(got["keys"]), np.sort(rk)), name
+
+
 # ------------------------------------------------------------- full engine
 
 def _engine_vs_oracle(vsa, orc, params, frames, bits=8, dense=False, k_max=0):

@@ -282,9 +282,14 @@ def k1_bytes_per_frame(g, W, H, k_max, intensity=True):
 # Untimed steps before any timed window.  Every stream opens a shot at its
 # first frame, so for the first n_ss + k_max + a few steps all streams analyse
 # their first shot's fields at once (about 4x the sparse work of the steady
-# state); the timed steps start after that transient whatever --warmup says.
-PREROLL_STEPS = 96
+# state), and the engine's launch tuner times its candidates from step 64 to
+# about step 160; the timed steps start after both, whatever --warmup says.
+PREROLL_STEPS = 200
 MARKER = "spin_kernel"     # torch.cuda._sleep's kernel: brackets the timed steps in a kernel trace
+# The headline times the pyramid and motion-search launches of one step in
+# this many (timing events stamped by a dispatch cost it device time; every
+# step timed costs the headline several percent).
+PROFILE_EVERY = 1
 
 
 def mark(torch):
@@ -340,6 +345,8 @@ def run_engine(vsa, dev_frames, params, B, steps, warmup, profile, torch, prerol
     c1 = e.counters()
     kt = e.kernel_times() if profile else None
     frames_out = sum(len(e.poll_frames(int(sid), 1 << 20)) for sid in sids)
+    c1["tuning"] = {b: (v["best"], v["candidates"][v["best"]]["wgs"] if v["best"] >= 0 else None)
+                    for b, v in e.tuning().items()} if not engine_kw.get("me_wgs_per_cu") else "fixed"
     e.close()
     return dt, kt, c0, c1, frames_out
 
@@ -480,6 +487,8 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--preroll", type=int, default=PREROLL_STEPS,
                     help="untimed steps before the warm-up steps of every batched run (first-shot transient)")
+    ap.add_argument("--me-wgs", type=int, default=0,
+                    help="persistent motion-search workgroups per CU for every batched run (0: the engine's tuner)")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end run from pinned host memory")
     ap.add_argument("--e2e-steps", type=int, default=40)
     ap.add_argument("--summarize-trace", metavar="CSV",
@@ -536,15 +545,17 @@ def main():
     # (no extra commands on the streams), the timed steps bracketed by marker
     # kernels for the trace and counter runs of this same command
     dt, kt, c0, c1, nout = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup,
-                                      0 if args.no_profile else 1, torch, preroll=args.preroll, markers=True)
+                                      0 if args.no_profile else 1, torch, preroll=args.preroll, markers=True,
+                                      profile_every=PROFILE_EVERY, me_wgs_per_cu=args.me_wgs)
     fps = args.streams * args.steps / dt
     print(f"[bench] batched B={args.streams}: {fps:.0f} frames/s, {1e3 * dt / args.steps:.3f} ms/step, "
           f"{nout} records", file=sys.stderr, flush=True)
     extra = {}
     if not args.no_profile:
-        # the same run with the engine's timing events off: what they cost
+        # the same run with the engine's timing events off: what the sampled
+        # events cost
         odt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,
-                                     preroll=args.preroll)
+                                     preroll=args.preroll, me_wgs_per_cu=args.me_wgs)
         extra["events_off"] = {"fps": round(args.streams * args.steps / odt, 1),
                                "ms_per_step": round(1e3 * odt / args.steps, 4)}
         print(f"[bench] batched B={args.streams}, timing events off: {args.streams * args.steps / odt:.0f} "
@@ -608,8 +619,12 @@ def main():
         k1_gbs = args.streams * k1b / (k1_avg * 1e-3) / 1e9
         cblocks = c1["consecutive_blocks"] - c0["consecutive_blocks"]
         sblocks = c1["sparse_blocks"] - c0["sparse_blocks"]
+        # absolute differences per launch: every timed step runs one launch of
+        # each kind; the durations come from the sampled (timed) steps
         ad = (cblocks + sblocks) * 289 * 64
-        me_tads = ad / (me_ms * 1e-3) / 1e12 if me_ms > 0 else 0.0
+        ad_launch = ad / (2 * args.steps)
+        me_avg_ms = me_ms / max(me_n, 1)
+        me_tads = ad_launch / (me_avg_ms * 1e-3) / 1e12 if me_ms > 0 else 0.0
         traffic = k1_traffic(args.streams)
         hbm = {"bound": "hbm", "kernel": "k_pyramid", "achieved": round(k1_gbs, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(k1_gbs / HBM_PEAK_GBS, 4),
@@ -618,15 +633,16 @@ def main():
         launches = {}
         for name, key, nb in (("consecutive", "me8", cblocks), ("sparse", "me_sparse", sblocks)):
             ms, n = kt[key]
-            launches[name] = {"avg_launch_us": round(ms / max(n, 1) * 1e3, 3),
-                              "ad_per_launch": nb * 289 * 64 / max(n, 1),
-                              "achieved": round(nb * 289 * 64 / (ms * 1e-3) / 1e12, 2) if ms > 0 else 0.0}
+            avg = ms / max(n, 1)
+            adl = nb * 289 * 64 / args.steps
+            launches[name] = {"avg_launch_us": round(avg * 1e3, 3), "timed_launches": n, "ad_per_launch": adl,
+                              "achieved": round(adl / (avg * 1e-3) / 1e12, 2) if ms > 0 else 0.0}
         alu = {"bound": "alu", "kernel": "k_me<uint8_t>",
                "achieved": round(me_tads, 2), "peak": round(AD_PEAK_T, 1),
                "unit": "T absdiff/s", "frac": round(me_tads / AD_PEAK_T, 4),
                "traffic": None if me_traffic(args.streams) is None else int(me_traffic(args.streams)),
-               "avg_launch_us": round(me_ms / max(me_n, 1) * 1e3, 3), "ad_per_launch": ad / max(me_n, 1),
-               "launches": launches}
+               "avg_launch_us": round(me_avg_ms * 1e3, 3), "ad_per_launch": ad_launch,
+               "timed_launches": me_n, "launches": launches}
         roof, other = (hbm, alu) if k1_ms >= me_ms else (alu, hbm)
         extra["roofline_other"] = other
         if kt_all:
@@ -701,6 +717,7 @@ def main():
                    "streams": args.streams, "width": W, "height": H, "bit_depth": 8},
         "x_realtime": round(fps / RT_FPS, 1),
         "x_realtime_per_stream": round(fps / args.streams / RT_FPS, 1),
+        "me_launch": c1.get("tuning"),
         "untimed_steps": {"preroll": args.preroll, "warmup": args.warmup,
                           "why": "every stream opens a shot at its first frame; the preroll takes all of them "
                                  "past that shot's analysis window, so the timed steps are the steady state"},

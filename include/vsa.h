@@ -38,7 +38,12 @@
  *   - Calls on one engine are serialised by an internal mutex; distinct
  *     engines are independent.
  *   - Pixel formats: 8-bit luma in uint8, or 10-bit luma in uint16 (values
- *     <= 1023, little endian).  Only the Y plane is read.
+ *     <= 1023, little endian).  Only the Y plane is read.  A 10-bit plane the
+ *     library reads from host memory with a copy (VSA_SRC_HOST) is checked
+ *     and refused with VSA_E_INVAL if a sample exceeds 1023; planes read in
+ *     place (device memory, VSA_SRC_HOST_BORROW) are not checked, and such
+ *     samples give unspecified measures (never an access outside the
+ *     library's buffers).
  */
 #ifndef VSA_H
 #define VSA_H
@@ -48,7 +53,7 @@
 extern "C" {
 #endif
 
-#define VSA_ABI_VERSION 1
+#define VSA_ABI_VERSION 2
 
 typedef int32_t vsa_status;
 enum {
@@ -103,6 +108,8 @@ typedef struct {
     int32_t no_intensity;      /* 1: skip the unary intensity measure H(t) (Sec. III.A; no
                                   decision uses it): h_mean/h_std/h_mad are NaN and
                                   vsa_get_histogram fails with VSA_E_STATE; 0: computed      */
+    int32_t profile_every;     /* with profile: time the launches of one step in this many
+                                  (0 or 1: every step); timing events cost device time      */
 } vsa_engine_config;
 
 enum { VSA_SCHEDULE_SPARSE = 0, VSA_SCHEDULE_DENSE = 1 };

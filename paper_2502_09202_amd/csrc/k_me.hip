@@ -9,19 +9,22 @@
 // ACT = sqrt((AMM + a0) SWR).
 //
 // K2 layout: one 256-thread workgroup per tile of 8 x 8 blocks (64 x 64
-// pixels of I).  The tile of I and its (64+16) x (64+16) search window of J
-// are staged in LDS once (clamped at the plane edges), so every candidate is
-// read from LDS.  Four lanes share a block: lane q searches dy in
-// [-8+4q, -5+4q] over all dx and one quarter of the dy = +8 row.
-// 8-bit: v_qsad_pk_u16_u8 gives the SADs of four consecutive dx from one
-// aligned 8-byte window (dx groups -8, -4, 0, +4), v_sad_u8 covers dx = +8, so
-// no byte alignment is ever needed in the search loop; each J row a lane needs
-// is read from LDS once and used for all four of its dy.  10-bit: v_sad_u16 on
-// pairs of samples with a 2-byte realignment for odd dx.  Each candidate's key
-// is (SAD << 16) + code(dx, dy), where the code is strictly increasing in the
-// candidate order (|d|^2, dy, dx) and below 2^16, so the minimum key is the
-// unique argmin; the code is arithmetic, no table is read.  The epilogue reads the warped block from the same
-// LDS window and forms int32 moments per lane, reduced per tile to int64.
+// pixels of I); a persistent grid walks the tile list.  The tile of I and its
+// (64+16) x (64+16) search window of J are staged in LDS once (clamped at the
+// plane edges), so every candidate is read from LDS.  Four lanes share a
+// block: lane q searches dy in [-8+4q, -5+4q] over all dx and one quarter of
+// the dy = +8 row.  8-bit: v_qsad_pk_u16_u8 gives the SADs of four
+// consecutive dx from one aligned 8-byte window (dx groups -8, -4, 0, +4),
+// v_sad_u8 covers dx = +8, so no byte alignment is ever needed in the search
+// loop; each J row a lane needs is read from LDS once for two of its dy.  The
+// 8-bit walk double-buffers the tiles in LDS: each thread loads its share of
+// the next tile into registers while the current one is searched, with one
+// barrier per tile.  10-bit: v_sad_u16 on pairs of samples with a 2-byte
+// realignment for odd dx.  Each candidate's key is (SAD << 16) + code(dx, dy),
+// where the code is strictly increasing in the candidate order (|d|^2, dy, dx)
+// and below 2^16, so the minimum key is the unique argmin; the code is
+// arithmetic, no table is read.  The epilogue reads the warped block from the
+// same LDS window and forms int32 moments per lane, reduced per tile to int64.
 // K3 sums the tile partials of each pair and forms the doubles in a fixed
 // order with no contraction.
 #include "vsa_internal.h"
@@ -151,11 +154,23 @@ __device__ __forceinline__ uint64_t pk64(uint32_t lo, uint32_t hi) {
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// Key of the candidate whose 16-bit SAD sits in the low (SEL_LO) or high
+// (SEL_HI) half of a packed accumulator: the SAD in the key's upper half, the
+// tie-break code in its lower half, one byte permute (v_perm_b32) each.
+constexpr uint32_t kSelLo = 0x05040100u;
+constexpr uint32_t kSelHi = 0x07060100u;
+__device__ __forceinline__ uint32_t key_of(uint32_t acc, uint32_t code, uint32_t sel) {
+    return __builtin_amdgcn_perm(acc, code, sel);
+}
+
 // 8-bit search for one lane: returns the best key (SAD << 16) + code(dx, dy).
-// The lane's four dy rows are visited one at a time (eight J rows each, read
-// from LDS), which keeps only five accumulators live; register pressure, not
-// LDS bandwidth, is what limits this kernel's occupancy.
-__device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
+// two passes of two dy each, every J row of a pass read from LDS once and
+// used for both dy; keys formed once per candidate with a byte permute and
+// reduced with three-input minima.  Row u+1 of a pass is read before row u is
+// searched; an empty asm after each row takes the row's sums and the row
+// offset as in-out operands, so the compiler can neither defer the row's work
+// past it nor hoist the loads of row u+2 above it (two J rows live at most).
+__device__ __forceinline__ uint32_t search8p(const uint8_t* sI, const uint8_t* sJ, int bx, int by, int q) {
     uint32_t r0[8], r1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -164,8 +179,6 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
         r1[j] = v.y;
     }
     uint32_t best = 0xffffffffu;
-    // Two passes of two dy each (dy = -8+4q+i0+i, i = 0, 1): the nine J rows
-    // of a pass are each read from LDS once and used for both of its dy.
 #pragma unroll 1
     for (int i0 = 0; i0 < 4; i0 += 2) {
         // acc[i][g]: four packed SADs of dx = -8+4g .. -5+4g; a8[i]: dx = +8
@@ -173,15 +186,18 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
         uint32_t a8[2] = {0, 0};
         const uint8_t* jb = sJ + (8 * by + 4 * q + i0) * kJW8 + 8 * bx;
         uint32_t off = 0;
+        uint2 na = *reinterpret_cast<const uint2*>(jb);
+        uint2 nb = *reinterpret_cast<const uint2*>(jb + 8);
+        uint2 nc = *reinterpret_cast<const uint2*>(jb + 16);
 #pragma unroll
         for (int u = 0; u < 9; ++u) {      // J row u pairs with block row j = u - i
-            // the row's address passes through an empty asm that reads the
-            // previous row's sum, so later rows are not hoisted into registers
-            if (u > 0) asm volatile("" : "+v"(off) : "v"(a8[0]));
-            const uint2 a = *reinterpret_cast<const uint2*>(jb + off);
-            const uint2 b = *reinterpret_cast<const uint2*>(jb + off + 8);
-            const uint2 c = *reinterpret_cast<const uint2*>(jb + off + 16);
+            const uint2 a = na, b = nb, c = nc;
             off += kJW8;
+            if (u < 8) {
+                na = *reinterpret_cast<const uint2*>(jb + off);
+                nb = *reinterpret_cast<const uint2*>(jb + off + 8);
+                nc = *reinterpret_cast<const uint2*>(jb + off + 16);
+            }
             const uint64_t w01 = pk64(a.x, a.y), w12 = pk64(a.y, b.x), w23 = pk64(b.x, b.y);
             const uint64_t w34 = pk64(b.y, c.x), w45 = pk64(c.x, c.y);
 #pragma unroll
@@ -198,18 +214,18 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
                 acc[i][3] = __builtin_amdgcn_qsad_pk_u16_u8(w45, r1[j], acc[i][3]);
                 a8[i] = __builtin_amdgcn_sad_u8(c.x, r0[j], a8[i]);
                 a8[i] = __builtin_amdgcn_sad_u8(c.y, r1[j], a8[i]);
+                asm volatile("" : "+v"(acc[i][0]), "+v"(acc[i][1]), "+v"(acc[i][2]), "+v"(acc[i][3]),
+                             "+v"(a8[i]), "+v"(off));
             }
         }
-        // keys: the dx part of the code is a constant per candidate, the dy
-        // part is added once per row (adding a constant keeps the row's argmin)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            uint32_t rb = (a8[i] << 16) + code_dx(8);
+            uint32_t rb = key_of(a8[i], code_dx(8), kSelLo);
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const uint32_t lo = (uint32_t)acc[i][g], hi = (uint32_t)(acc[i][g] >> 32);
-                rb = min(rb, min((lo << 16) + code_dx(-8 + 4 * g), (lo & 0xffff0000u) + code_dx(-7 + 4 * g)));
-                rb = min(rb, min((hi << 16) + code_dx(-6 + 4 * g), (hi & 0xffff0000u) + code_dx(-5 + 4 * g)));
+                rb = min(rb, min(key_of(lo, code_dx(-8 + 4 * g), kSelLo), key_of(lo, code_dx(-7 + 4 * g), kSelHi)));
+                rb = min(rb, min(key_of(hi, code_dx(-6 + 4 * g), kSelLo), key_of(hi, code_dx(-5 + 4 * g), kSelHi)));
             }
             best = min(best, rb + code_dy(-8 + 4 * q + i0 + i));
         }
@@ -231,9 +247,9 @@ __device__ __forceinline__ uint32_t search8(const uint8_t* sI, const uint8_t* sJ
         }
         const int dx0 = -8 + 4 * q;
         const uint32_t lo = (uint32_t)a4, hi = (uint32_t)(a4 >> 32);
-        uint32_t rb = min((lo << 16) + code_dx(dx0), (lo & 0xffff0000u) + code_dx(dx0 + 1));
-        rb = min(rb, min((hi << 16) + code_dx(dx0 + 2), (hi & 0xffff0000u) + code_dx(dx0 + 3)));
-        if (q == 3) rb = min(rb, (e8 << 16) + code_dx(8));
+        uint32_t rb = min(key_of(lo, code_dx(dx0), kSelLo), key_of(lo, code_dx(dx0 + 1), kSelHi));
+        rb = min(rb, min(key_of(hi, code_dx(dx0 + 2), kSelLo), key_of(hi, code_dx(dx0 + 3), kSelHi)));
+        if (q == 3) rb = min(rb, key_of(e8, code_dx(8), kSelLo));
         best = min(best, rb + code_dy(8));
     }
     return best;
@@ -376,7 +392,7 @@ __device__ void me_tile(const TileJob& jb, int local, TilePartial* part_out, int
     if (!(jb.flags & TF_ZERO_MV)) {
         uint32_t key = 0xffffffffu;
         if (valid) {
-            if constexpr (sizeof(T) == 1) key = search8(sI, sJ, bx, by, q);
+            if constexpr (sizeof(T) == 1) key = search8p(sI, sJ, bx, by, q);
             else key = search16(sI, sJ, bx, by, q);
         }
         key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
@@ -426,6 +442,291 @@ __device__ void me_tile(const TileJob& jb, int local, TilePartial* part_out, int
     __syncthreads();   // LDS is reused by the next tile
 }
 
+// ---- 8-bit tiles: prefetched into registers, double-buffered in LDS -------
+
+// One tile of 8 x 8 blocks, resolved from its job (uniform across the
+// workgroup).
+struct Tile8 {
+    const uint8_t* I;
+    const uint8_t* J;
+    int8_t* mv;
+    int w, h, pitch, cos_I, cos_J;
+    int bx0, by0, flags;
+};
+
+// A thread's share of staging one tile: its 16-byte chunk of the I tile and
+// up to four 8-byte chunks of the 80 x 80 J window (and, for a co-sited
+// lower field, the same chunks one row higher).  Thread t holds J chunks
+// i = t + 256 k (i < 800): window row i / 10, byte column 8 (i % 10), LDS
+// offset 8 i; and I chunk t: row t / 4, byte column 16 (t % 4), LDS offset
+// 16 t.
+struct Stage8 {
+    uint4 i0, i1;
+    uint2 j0[4], j1[4];
+};
+
+constexpr int kJChunks8 = kJRows * (kJW8 / 8);   // 800
+
+// Loads and stores through global-address-space pointers: the planes' and
+// tiles' addresses come out of the jobs as generic pointers, and generic
+// (flat) accesses count against the LDS wait counter too, so the search's
+// first wait for an LDS read would also wait for the prefetched tile.
+template <typename V>
+__device__ __forceinline__ V gload(const uint8_t* p) {
+    return *(const __attribute__((address_space(1))) V*)p;
+}
+template <typename V>
+__device__ __forceinline__ void gstore(void* p, V v) {
+    *(__attribute__((address_space(1))) V*)p = v;
+}
+__device__ __forceinline__ void store_partial(TilePartial* dst, const TilePartial& p) {
+    int64_t* d = reinterpret_cast<int64_t*>(dst);
+    gstore<int64_t>(d + 0, p.sx); gstore<int64_t>(d + 1, p.sy); gstore<int64_t>(d + 2, p.sxx);
+    gstore<int64_t>(d + 3, p.syy); gstore<int64_t>(d + 4, p.sxy); gstore<int64_t>(d + 5, p.a);
+}
+__device__ __forceinline__ uint2 gload2(const uint8_t* p) {
+    const uint64_t v = gload<uint64_t>(p);
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+__device__ __forceinline__ uint4 gload4(const uint8_t* p) {
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2 v = gload<u64x2>(p);
+    return make_uint4((uint32_t)v.x, (uint32_t)(v.x >> 32), (uint32_t)v.y, (uint32_t)(v.y >> 32));
+}
+
+// How a J chunk (8 bytes from byte column gx of the window row) is staged:
+// whole within the plane, entirely left or right of it (every byte is the
+// edge sample, one byte is loaded), or across the edge of a plane whose width
+// is not a multiple of 8 (bytes loaded one by one when stored).
+enum : int { JC_IN = 0, JC_LEFT = 1, JC_RIGHT = 2, JC_PART = 3 };
+__device__ __forceinline__ int jclass(int gx, int w) {
+    if (gx >= 0 && gx + 8 <= w) return JC_IN;
+    if (gx + 8 <= 0) return JC_LEFT;
+    if (gx >= w) return JC_RIGHT;
+    return JC_PART;
+}
+
+__device__ __forceinline__ bool resolve8(const StreamDesc* __restrict__ sds, const TileJob* __restrict__ jobs,
+                                         int n_jobs, int idx, int tile, bool sparse, int8_t* dbg_mv, Tile8& T) {
+    if (idx < 0 || idx >= n_jobs) return false;   // never expected; keeps reads in bounds
+    const TileJob& jb = jobs[idx];
+    if (jb.bits != 8) return false;
+    if (sparse) {
+        const StreamDesc& sd = sds[jb.sid];
+        if (!sd.active || sd.epoch != jb.epoch) return false;   // stream closed since planning
+    }
+    const int local = tile - jb.tile_prefix;
+    T.I = jb.I; T.J = jb.J;
+    T.w = jb.w; T.h = jb.h; T.pitch = jb.pitch;
+    T.cos_I = jb.cos_I; T.cos_J = jb.cos_J;
+    T.bx0 = (local % jb.tiles_x) * kTBX;
+    T.by0 = (local / jb.tiles_x) * kTBY;
+    T.flags = jb.flags;
+    T.mv = (jb.flags & TF_DEBUG) ? dbg_mv : jb.mv;
+    return true;
+}
+
+// Global loads of a thread's chunks (no wait: they land while the previous
+// tile is searched).  Window rows past the plane are clamped; the column
+// class of a chunk is uniform over most tiles (inner columns all whole).
+__device__ __forceinline__ void stage8_load(const Tile8& T, Stage8& S) {
+    const int tid = threadIdx.x;
+    {
+        const int gy = min(8 * T.by0 + (tid >> 2), T.h - 1);
+        const uint32_t o = (uint32_t)gy * (uint32_t)T.pitch + 8 * T.bx0 + 16 * (tid & 3);
+        S.i0 = gload4(T.I + o);
+        if (T.cos_I) S.i1 = gload4(T.I + (o - (gy > 0 ? T.pitch : 0)));
+    }
+    const int x0 = 8 * T.bx0 - 8, y0 = 8 * T.by0 - 8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = tid + kMEThreads * k;
+        if (k == 3 && i >= kJChunks8) break;
+        const int r = i / (kJW8 / 8);
+        const int gx = x0 + 8 * (i - r * (kJW8 / 8));
+        const int gy = clampi(y0 + r, 0, T.h - 1);
+        const uint32_t ro = (uint32_t)gy * (uint32_t)T.pitch;
+        const uint32_t rp = gy > 0 ? ro - T.pitch : ro;
+        const int cls = jclass(gx, T.w);
+        if (cls == JC_IN) {
+            S.j0[k] = gload2(T.J + ro + gx);
+            if (T.cos_J) S.j1[k] = gload2(T.J + rp + gx);
+        } else if (cls != JC_PART) {
+            const uint32_t e = cls == JC_LEFT ? 0u : (uint32_t)(T.w - 1);
+            S.j0[k].x = gload<uint8_t>(T.J + ro + e);
+            if (T.cos_J) S.j1[k].x = gload<uint8_t>(T.J + rp + e);
+        }
+    }
+}
+
+__device__ __forceinline__ void stage8_store(const Tile8& T, const Stage8& S, uint8_t* sI, uint8_t* sJ) {
+    const int tid = threadIdx.x;
+    {
+        uint4 v = S.i0;
+        if (T.cos_I) v = cosite_vec<uint8_t, uint4>(v, S.i1, T.cos_I);
+        reinterpret_cast<uint4*>(sI)[tid] = v;
+    }
+    const int x0 = 8 * T.bx0 - 8, y0 = 8 * T.by0 - 8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = tid + kMEThreads * k;
+        if (k == 3 && i >= kJChunks8) break;
+        const int r = i / (kJW8 / 8);
+        const int gx = x0 + 8 * (i - r * (kJW8 / 8));
+        const int cls = jclass(gx, T.w);
+        uint2 v = S.j0[k], w = S.j1[k];
+        if (cls == JC_LEFT || cls == JC_RIGHT) {
+            v.x = v.y = (v.x & 0xffu) * 0x01010101u;
+            w.x = w.y = (w.x & 0xffu) * 0x01010101u;
+        } else if (cls == JC_PART) {
+            const int gy = clampi(y0 + r, 0, T.h - 1);
+            const uint8_t* row = T.J + (uint32_t)gy * (uint32_t)T.pitch;
+            const uint8_t* prv = T.J + (uint32_t)(gy > 0 ? gy - 1 : 0) * (uint32_t)T.pitch;
+            union { uint8_t t[8]; uint2 u; } a, b;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int x = clampi(gx + e, 0, T.w - 1);
+                a.t[e] = gload<uint8_t>(row + x);
+                b.t[e] = T.cos_J ? gload<uint8_t>(prv + x) : (uint8_t)0;
+            }
+            v = a.u;
+            w = b.u;
+        }
+        if (T.cos_J) v = cosite_vec<uint8_t, uint2>(v, w, T.cos_J);
+        reinterpret_cast<uint2*>(sJ)[i] = v;
+    }
+}
+
+// The persistent walk over tiles lo..hi-1 (first, first+stride, ...) of one
+// 8-bit launch.  Tile k+1's chunks are loaded into registers while tile k is
+// searched and are written to the other LDS buffer at the top of the next
+// iteration, so one barrier per tile separates the writes of a buffer from
+// its reads (a buffer is rewritten two tiles later, after every thread has
+// passed the barrier in between).  The four waves' moment sums of a tile go
+// to a double-buffered LDS slot and are added by thread 0 after that barrier.
+__device__ void me_walk8(const StreamDesc* __restrict__ sds, const TileJob* __restrict__ jobs, int n_jobs,
+                         const int32_t* __restrict__ map, int hi, int first, int stride, bool sparse,
+                         TilePartial* __restrict__ partials, int8_t* dbg_mv, int32_t* dbg_sad) {
+    __shared__ __attribute__((aligned(16))) uint8_t sI[2][64 * 64];
+    __shared__ __attribute__((aligned(16))) uint8_t sJ[2][kJRows * kJW8];
+    __shared__ int32_t red[2][4 * 6];
+    const int tid = threadIdx.x;
+    const int b = tid >> 2, q = tid & 3;
+    const int bx = b & (kTBX - 1), by = b >> 3;
+    const int wave = tid >> 6;
+    Stage8 S;
+    // the job index of the tile whose chunks sit in S (re-resolved from the
+    // job, which the scalar cache still holds, when they are stored), and the
+    // map entry of the tile after it
+    int idx_cur = first < hi ? map[first] : -1;
+    int idx_nn = (first + stride < hi) ? map[first + stride] : -1;
+    if (first < hi) {
+        Tile8 t0;
+        if (resolve8(sds, jobs, n_jobs, idx_cur, first, sparse, dbg_mv, t0)) stage8_load(t0, S);
+    }
+    int buf = 0;
+    int pending = -1;           // tile whose wave sums wait in red[buf ^ 1]
+    // Its motion vector (lane q = 0 of a valid block), stored after the next
+    // barrier rather than at the end of the tile: a store still in flight at
+    // the top of the next iteration would hold up the wait for that tile's
+    // prefetched loads.
+    int8_t* mv_dst = nullptr;
+    int mv_blk = 0;
+    uint32_t mv_val = 0;
+    for (int tile = first; tile < hi; tile += stride) {
+        Tile8 cur;
+        const bool cur_ok = resolve8(sds, jobs, n_jobs, idx_cur, tile, sparse, dbg_mv, cur);
+        if (cur_ok) stage8_store(cur, S, sI[buf], sJ[buf]);
+        __syncthreads();
+        // the next tile's loads go out first; the previous tile's results
+        // are stored after them (neither waits for the other)
+        const int nt = tile + stride;
+        if (nt < hi) {
+            idx_cur = idx_nn;
+            idx_nn = (nt + stride < hi) ? map[nt + stride] : -1;
+            Tile8 n;
+            if (resolve8(sds, jobs, n_jobs, idx_cur, nt, sparse, dbg_mv, n)) stage8_load(n, S);
+        }
+        if (pending >= 0 && tid == 0) {
+            const int32_t* rd = red[buf ^ 1];
+            TilePartial p;
+            p.sx = (int64_t)rd[0] + rd[6] + rd[12] + rd[18];
+            p.sy = (int64_t)rd[1] + rd[7] + rd[13] + rd[19];
+            p.sxx = (int64_t)rd[2] + rd[8] + rd[14] + rd[20];
+            p.syy = (int64_t)rd[3] + rd[9] + rd[15] + rd[21];
+            p.sxy = (int64_t)rd[4] + rd[10] + rd[16] + rd[22];
+            p.a = (int64_t)rd[5] + rd[11] + rd[17] + rd[23];
+            store_partial(partials + pending, p);
+        }
+        if (mv_dst) {
+            gstore<uint8_t>(mv_dst + 2 * mv_blk, (uint8_t)(mv_val & 0xffu));
+            gstore<uint8_t>(mv_dst + 2 * mv_blk + 1, (uint8_t)(mv_val >> 8));
+        }
+        mv_dst = nullptr;
+        pending = -1;
+        if (cur_ok) {
+            const uint8_t* cI = sI[buf];
+            const uint8_t* cJ = sJ[buf];
+            const int nbx = cur.w / kBlock, nby = cur.h / kBlock;
+            const bool valid = (cur.bx0 + bx < nbx) && (cur.by0 + by < nby);
+            int dx = 0, dy = 0;
+            if (!(cur.flags & TF_ZERO_MV)) {
+                uint32_t key = valid ? search8p(cI, cJ, bx, by, q) : 0xffffffffu;
+                key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
+                key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
+                if (valid) {
+                    const uint32_t cell = (key & 0xffffu) % (uint32_t)(kCand * kCand);   // (dy+8)*17 + dx+8
+                    dx = (int)(cell % kCand) - kRadius;
+                    dy = (int)(cell / kCand) - kRadius;
+                }
+            }
+            int32_t m[5] = {0, 0, 0, 0, 0};
+            int32_t a = 0;
+            if (valid) {
+                moments<uint8_t>(cI, cJ, bx, by, q, dx, dy, m);
+                if (q == 0) a = amm_fx(dx * dx + dy * dy);
+            }
+            const int blk = (cur.by0 + by) * nbx + (cur.bx0 + bx);
+            if ((cur.flags & TF_DEBUG) && dbg_sad) {
+                int32_t sd_ = valid ? rows_sad<uint8_t>(cI, cJ, bx, by, q, dx, dy) : 0;
+                sd_ += __shfl_xor(sd_, 1, 64);
+                sd_ += __shfl_xor(sd_, 2, 64);
+                if (valid && q == 0) dbg_sad[blk] = sd_;
+            }
+            if (cur.mv && valid && q == 0) {
+                mv_dst = cur.mv;
+                mv_blk = blk;
+                mv_val = (uint32_t)(dx & 0xff) | ((uint32_t)(dy & 0xff) << 8);
+            }
+            // per-wave int32 sums are exact for 8-bit samples (16 blocks per wave)
+            const int32_t w0 = wave_sum(m[0]), w1 = wave_sum(m[1]), w2 = wave_sum(m[2]);
+            const int32_t w3 = wave_sum(m[3]), w4 = wave_sum(m[4]), w5 = wave_sum(a);
+            if ((tid & 63) == 0) {
+                int32_t* rd = red[buf] + wave * 6;
+                rd[0] = w0; rd[1] = w1; rd[2] = w2; rd[3] = w3; rd[4] = w4; rd[5] = w5;
+            }
+            pending = tile;
+        }
+        buf ^= 1;
+    }
+    __syncthreads();
+    if (mv_dst) {
+        gstore<uint8_t>(mv_dst + 2 * mv_blk, (uint8_t)(mv_val & 0xffu));
+        gstore<uint8_t>(mv_dst + 2 * mv_blk + 1, (uint8_t)(mv_val >> 8));
+    }
+    if (pending >= 0 && tid == 0) {
+        const int32_t* rd = red[buf ^ 1];
+        TilePartial p;
+        p.sx = (int64_t)rd[0] + rd[6] + rd[12] + rd[18];
+        p.sy = (int64_t)rd[1] + rd[7] + rd[13] + rd[19];
+        p.sxx = (int64_t)rd[2] + rd[8] + rd[14] + rd[20];
+        p.syy = (int64_t)rd[3] + rd[9] + rd[15] + rd[21];
+        p.sxy = (int64_t)rd[4] + rd[10] + rd[16] + rd[22];
+        p.a = (int64_t)rd[5] + rd[11] + rd[17] + rd[23];
+        store_partial(partials + pending, p);
+    }
+}
+
 }  // namespace
 
 // Persistent grid over the tiles of the consecutive-pair list (host-built) and
@@ -443,9 +744,6 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
                                                    int32_t* dbg_sad, unsigned long long* __restrict__ clear_tt) {
     // clear this step's planning counter before the decision kernel adds to it
     if (clear_tt && blockIdx.x == 0 && threadIdx.x == 0) *clear_tt = 0ull;
-    __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
-    __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
-    __shared__ int64_t red[4 * 6];
     const bool sparse = cur != nullptr;
     // the sparse pairs precede the step's decisions on the critical path;
     // their waves issue before those of the next step's consecutive pairs
@@ -466,25 +764,33 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
         first = lo + j;
         stride = groups;
     }
-    // A tile's job: map entry, then the job (the next tile's map entry is
-    // loaded one iteration ahead).  The consecutive pairs' jobs are built by
-    // this step's pyramid kernel, the sparse pairs' by the previous step's
-    // decision kernel.
-    int idx_next = first < hi ? map[first] : 0;
-    for (int tile = first; tile < hi; tile += stride) {
-        const int idx = idx_next;
-        const int nt = tile + stride;
-        if (nt < hi) idx_next = map[nt];
-        if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
-        const TileJob& jb = jobs[idx];
-        const int local = tile - jb.tile_prefix;
-        if (jb.bits != (sizeof(T) == 1 ? 8 : 10)) continue;
-        if (sparse) {
-            const StreamDesc& sd = sds[jb.sid];
-            if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
+    // A tile's job: map entry, then the job.  The consecutive pairs' jobs are
+    // built by this step's pyramid kernel, the sparse pairs' by the previous
+    // step's decision kernel.
+    if constexpr (sizeof(T) == 1) {
+        me_walk8(sds, jobs, n_jobs, map, hi, first, stride, sparse, partials, dbg_mv, dbg_sad);
+    } else {
+        // 10-bit: one LDS buffer; the next tile's map entry is loaded one
+        // iteration ahead
+        __shared__ __attribute__((aligned(16))) uint8_t sI[64 * 64 * sizeof(T)];
+        __shared__ __attribute__((aligned(16))) uint8_t sJ[kJRows * kJW8 * sizeof(T)];
+        __shared__ int64_t red[4 * 6];
+        int idx_next = first < hi ? map[first] : 0;
+        for (int tile = first; tile < hi; tile += stride) {
+            const int idx = idx_next;
+            const int nt = tile + stride;
+            if (nt < hi) idx_next = map[nt];
+            if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
+            const TileJob& jb = jobs[idx];
+            const int local = tile - jb.tile_prefix;
+            if (jb.bits != 10) continue;
+            if (sparse) {
+                const StreamDesc& sd = sds[jb.sid];
+                if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
+            }
+            const bool dbg = (jb.flags & TF_DEBUG) != 0;
+            me_tile<T>(jb, local, partials + tile, dbg ? dbg_mv : jb.mv, dbg ? dbg_sad : nullptr, sI, sJ, red);
         }
-        const bool dbg = (jb.flags & TF_DEBUG) != 0;
-        me_tile<T>(jb, local, partials + tile, dbg ? dbg_mv : jb.mv, dbg ? dbg_sad : nullptr, sI, sJ, red);
     }
 }
 
@@ -552,6 +858,22 @@ __global__ void k_finish_debug(const int64_t* __restrict__ ints, int64_t n, doub
     double f[4];
     finish_pair(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], a0, f);
     out[4 * i] = f[0]; out[4 * i + 1] = f[1]; out[4 * i + 2] = f[2]; out[4 * i + 3] = f[3];
+}
+
+// Workgroups of the motion-search kernel one compute unit holds at once (its
+// registers and LDS decide); persistent grids are sized within it, since a
+// workgroup that waits for room would start its share of tiles late.
+int me_max_wgs_per_cu(int bits) {
+    static int cached[2] = {0, 0};
+    int& c = cached[bits == 8 ? 0 : 1];
+    if (c == 0) {
+        int n = 0;
+        const hipError_t e = bits == 8
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_me<uint8_t>, kMEThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_me<uint16_t>, kMEThreads, 0);
+        c = (e == hipSuccess && n > 0) ? n : 2;
+    }
+    return c;
 }
 
 hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* jobs, int32_t n_jobs, const int32_t* map,

@@ -337,7 +337,10 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
         store_row<T, CW>(slot + sd.off[0] + (int64_t)YL * sd.pl[0] * (int64_t)sizeof(T), X, wL, fl);
         if (hist && X < wL) {
             // a run of equal adjacent values is one atomic (fewer lanes of a
-            // wave on one LDS address in smooth regions)
+            // wave on one LDS address in smooth regions); a bin index is kept
+            // below 2^bits even for samples outside the 10-bit range (which the
+            // host refuses for planes it copies; a device plane is read as is)
+            constexpr int kMaxBin = sizeof(T) == 1 ? 255 : 1023;
             int cur = fl.v[0];
             uint32_t cnt = 1;
 #pragma unroll
@@ -346,12 +349,12 @@ __device__ void pyramid_tile(const StreamDesc& sd, const StepStream& ss, int til
                 if (fl.v[i] == cur) {
                     ++cnt;
                 } else {
-                    atomicAdd(&hist[cur], cnt);
+                    atomicAdd(&hist[min(cur, kMaxBin)], cnt);
                     cur = fl.v[i];
                     cnt = 1;
                 }
             }
-            atomicAdd(&hist[cur], cnt);
+            atomicAdd(&hist[min(cur, kMaxBin)], cnt);
         }
     } else {
 #pragma unroll

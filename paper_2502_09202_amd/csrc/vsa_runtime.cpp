@@ -48,6 +48,7 @@ hipError_t launch_pyramid(int bits, int L, const StreamDesc*, const StepStream*,
                           TileJob*, int32_t*, hipStream_t, LaunchTiming = {});
 int pyramid_tiles(const StreamDesc& sd);
 hipError_t launch_intensity(const StreamDesc*, const StepStream*, const int32_t*, int32_t, hipStream_t);
+int me_max_wgs_per_cu(int bits);
 hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
                      const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                      LaunchTiming = {});
@@ -113,7 +114,7 @@ constexpr int kSnap = 64;
 // of the consecutive pairs and of the sparse pairs.
 struct TuneCand { int consec, sparse; };
 constexpr int kTuneN = 4;
-constexpr TuneCand kTuneCands[kTuneN] = {{1, 4}, {2, 3}, {2, 4}, {4, 4}};
+constexpr TuneCand kTuneCands[kTuneN] = {{2, 2}, {3, 3}, {2, 3}, {3, 2}};
 constexpr int kTuneSamples = 3;
 constexpr int kTuneWindow = 8;     // steps per timing window
 // Windows start only after this many steps of an engine: the first steps
@@ -223,6 +224,16 @@ vsa_status check_exact_sums(const StreamDesc& sd) {
     if (npx * npx * (double)(maxv * maxv) >= 9.2e18)
         return fail(VSA_E_UNSUPPORTED, "frame too large for exact 64-bit intensity sums");
     return VSA_OK;
+}
+
+// Every sample of a 10-bit plane (uint16, rows pitch bytes apart) is <= 1023.
+bool samples_10bit_ok(const uint8_t* plane, int64_t pitch, int W, int H) {
+    uint16_t any = 0;
+    for (int y = 0; y < H; ++y) {
+        const uint16_t* r = reinterpret_cast<const uint16_t*>(plane + y * pitch);
+        for (int x = 0; x < W; ++x) any |= r[x];
+    }
+    return (any & 0xFC00u) == 0;
 }
 
 int max_sparse_tiles(const StreamDesc& sd) {
@@ -339,6 +350,7 @@ struct vsa_engine {
     hipEvent_t prof_ev[kProfRing][kProfKinds][2] = {};
     int prof_used[kProfRing][kProfKinds] = {};
     int64_t prof_step = 0;
+    int profile_every = 1;             // steps per timed step
     double prof_ms[kProfKinds] = {0};
     uint64_t prof_n[kProfKinds] = {0};
     int has8 = 0, has10 = 0;           // an open stream of that sample width (its launches run)
@@ -678,6 +690,7 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
              hipMemset(e->d_results, 0, sizeof(PairResult) * M * kResSlots) == hipSuccess;
     }
     e->profile = cfg->profile < 0 ? 0 : (cfg->profile > 2 ? 2 : cfg->profile);
+    e->profile_every = cfg->profile_every > 1 ? cfg->profile_every : 1;
     for (int i = 0; ok && e->profile && i < kProfRing; ++i)
         for (int k = 0; ok && k < kProfKinds; ++k)
             for (int j = 0; ok && j < 2; ++j)
@@ -875,6 +888,8 @@ vsa_status vsa_stream_push(vsa_engine* e, int32_t sid, const void* luma, int64_t
         }
         const uint8_t* p = static_cast<const uint8_t*>(luma);
         for (int y = 0; y < s->sd.H; ++y) std::memcpy(e->h_stage[k] + y * s->staging_pitch, p + y * pitch, row);
+        if (s->sd.bits == 10 && !samples_10bit_ok(e->h_stage[k], s->staging_pitch, s->sd.W, s->sd.H))
+            return fail(VSA_E_INVAL, "10-bit plane holds a sample above 1023");
         s->pend_src = e->h_stage[k];
         s->pend_pitch = s->staging_pitch;
     } else if (src == VSA_SRC_DEVICE_COPY) {
@@ -1011,7 +1026,8 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     // Kernels are timed by events stamped from their own dispatch (the first
     // launch of a kind starts the pair, the last one stops it); the whole step
     // by recorded events.
-    auto profiled = [&](int k) { return e->profile && !(e->profile == 1 && k > 3); };
+    const bool prof_now = e->profile && (e->step_no % e->profile_every) == 0;
+    auto profiled = [&](int k) { return prof_now && !(e->profile == 1 && k > 3); };
     auto timing = [&](int k, bool first, bool last) {
         LaunchTiming t;
         if (!profiled(k)) return t;
@@ -1198,7 +1214,9 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         }
         wgs = kTuneCands[cand];
     }
+    const int me_cap = std::min(e->has8 ? me_max_wgs_per_cu(8) : 64, e->has10 ? me_max_wgs_per_cu(10) : 64);
     auto me_grid = [&](int64_t tiles, int w) {
+        w = std::max(1, std::min(w, me_cap));
         int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)w * e->cus);
         if (g >= 8) g -= g % 8;   // whole groups of one workgroup per XCD
         return g;
@@ -1971,7 +1989,9 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     c->sparse_tiles = std::max(max_sparse_tiles(sd), 3 * (1 + kMaxSpec) * me_tiles(sd.wf, sd.hf));
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    const int me_cap = me_max_wgs_per_cu(sd.bits);
     auto grid = [&](int64_t tiles, int w) {
+        w = std::max(1, std::min(w, me_cap));
         int gsz = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)w * cus);
         if (gsz >= 8) gsz -= gsz % 8;   // whole groups of one workgroup per XCD
         return gsz;
@@ -2137,6 +2157,11 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
     if (pitch_bytes < row) return fail(VSA_E_INVAL, "pitch smaller than a row");
     if (n_frames > 1 && frame_stride_bytes < pitch_bytes * (sd.H - 1) + row)
         return fail(VSA_E_INVAL, "frame stride smaller than a frame");
+    if (src == VSA_SRC_HOST && sd.bits == 10)
+        for (int32_t i = 0; i < n_frames; ++i)
+            if (!samples_10bit_ok(static_cast<const uint8_t*>(frames) + (int64_t)i * frame_stride_bytes, pitch_bytes,
+                                  sd.W, sd.H))
+                return fail(VSA_E_INVAL, "10-bit frame holds a sample above 1023");
     HIPCK(hipSetDevice(c->device), "hipSetDevice");
     const vsa_status st = clip_run_body(c, frames, frame_stride_bytes, pitch_bytes, n_frames, src, out_frames,
                                         out_shots, shots_cap, n_shots);

@@ -50,7 +50,7 @@ class EngineConfig(C.Structure):
         ("device", C.c_int32), ("max_streams", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
         ("schedule", C.c_int32), ("use_graph", C.c_int32), ("params", C.POINTER(Params)),
         ("debug_log", C.c_int32), ("me_wgs_per_cu", C.c_int32), ("profile", C.c_int32),
-        ("no_intensity", C.c_int32),
+        ("no_intensity", C.c_int32), ("profile_every", C.c_int32),
     ]
 
 
@@ -199,12 +199,13 @@ class Engine:
 
     def __init__(self, device: int = 0, max_streams: int = 64, hbm_budget_bytes: int = 0,
                  schedule: int = SCHEDULE_SPARSE, use_graph: int = 0, params: Optional[dict] = None,
-                 debug_log: int = 0, profile: int = 0, me_wgs_per_cu: int = 0, no_intensity: int = 0):
+                 debug_log: int = 0, profile: int = 0, me_wgs_per_cu: int = 0, no_intensity: int = 0,
+                 profile_every: int = 0):
         self._params = make_params(params)
         cfg = EngineConfig(device=device, max_streams=max_streams, hbm_budget_bytes=hbm_budget_bytes,
                            schedule=schedule, use_graph=use_graph,
                            params=C.pointer(self._params), debug_log=debug_log, me_wgs_per_cu=me_wgs_per_cu,
-                           profile=profile, no_intensity=no_intensity)
+                           profile=profile, no_intensity=no_intensity, profile_every=profile_every)
         h = C.c_void_p()
         _check(lib().vsa_engine_create(C.byref(cfg), C.byref(h)), "engine_create")
         self.h = h

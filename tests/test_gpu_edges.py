@@ -120,3 +120,43 @@ def test_stream_without_frames(vsa, params):
     assert len(e.poll_frames(sid, 10)) == 0
     assert len(e.poll_shots(sid, 10)) == 0
     e.close()
+
+
+def test_10bit_samples_above_1023(vsa, params):
+    """A 10-bit plane with a sample above 1023 is refused when the library
+    copies it from host memory (stream push and clip run); read in place from
+    device memory it is analysed without a fault (the working-level histogram
+    keeps its bins below 1024) and the stream still ends normally."""
+    import torch
+    W, H = 640, 360
+    ok = np.full((H, W), 500, np.uint16)
+    bad = ok.copy()
+    bad[100, 200] = 1024
+    e = vsa.Engine(max_streams=2, params=params)
+    sid = e.stream_open(W, H, 10)
+    assert e.stream_push(sid, ok, pts=0) == 0
+    e.step()
+    assert e.stream_push(sid, bad, pts=1) == vsa.E_INVAL
+    assert "1023" in vsa.last_error()
+    # in place from device memory: values far outside the range, run to the end
+    big = torch.from_numpy(np.full((H, W), 4000, np.int16)).to("cuda:0")
+    sid2 = e.stream_open(W, H, 10)
+    for t in range(4):
+        assert e.stream_push_tensor(sid2, big, pts=t) == 0
+        if t == 3:
+            e.stream_end(sid2)
+        e.step()
+        e.sync()
+    for _ in range(20):
+        if e.stream_done(sid2):
+            break
+        e.step()
+        e.sync()
+    assert e.stream_done(sid2)
+    assert len(e.poll_frames(sid2, 16)) == 4
+    e.close()
+    with vsa.Clip(W, H, bit_depth=10, chunk=4, params=params) as c:
+        with pytest.raises(vsa.VsaError) as ei:
+            c.run(np.stack([ok, bad]))
+        assert ei.value.code == vsa.E_INVAL
+        assert len(c.run(np.stack([ok, ok]))["frames"]) == 2

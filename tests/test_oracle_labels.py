@@ -60,3 +60,25 @@ def test_2k_cut_dissolve_flashes_sampling(orc, params):
         assert int(s["sampling"]) == t["sampling"]
         if t["sampling"] == 4:
             assert int(s["pulldown_phase"]) == t["pulldown_phase"]
+
+
+@pytest.mark.slow
+def test_8frame_dissolve_is_not_cut(orc, params):
+    """Sec. III.B targets short dissolves (up to 4 frames); the 2K workload's
+    8-frame linear dissolves are longer.  What the method does with one is
+    pinned here: no boundary of either kind inside it or next to it (the fast
+    check fires on three of its frames, and the deep check finds no K <= 8
+    whose forward activity clearly exceeds the backward one), so the two shots
+    are reported as one rather than cut in the middle.  Seed 3's dissolve,
+    frames 558 -> 566, in a 68-frame window."""
+    spec = synth.make_c2(seed=3, T=1500, W=2048, H=1080, k_dis=8)
+    assert (558, 566, 8) in spec.truth()["boundaries"]
+    a, b = 528, 596
+    rd = synth.Renderer(spec)
+    frames = np.stack([rd.frame(t) for t in range(a, b)])
+    r = orc.run_clip(frames, dict(params, k_max=8))
+    f = r["frames"]
+    assert np.count_nonzero(f["boundary"]) == 0
+    fired = (np.nonzero(f["flags"] & 4)[0] + a).tolist()
+    assert any(558 <= t < 566 for t in fired)          # the deep check ran inside the dissolve
+    assert len(r["shots"]) == 1

@@ -341,6 +341,8 @@ typedef struct {
     int32_t no_intensity;      /* 1: skip H(t) (h_mean/h_std/h_mad are NaN)                 */
     int32_t me_wgs_per_cu;     /* persistent motion-search workgroups per CU, 0 = default   */
     const vsa_params* params;  /* NULL = built-in defaults                                  */
+    int32_t debug_log;         /* 1: keep a log of the sparse measures the sequential pass
+                                  requests (vsa_clip_debug_log)                              */
 } vsa_clip_config;
 
 /* Create a clip analyser on cfg->device and allocate its device memory (sized
@@ -369,8 +371,19 @@ vsa_status vsa_clip_run(vsa_clip* c, const void* frames, int64_t frame_stride_by
 
 /* Instrumentation (not in the paper): the first n of [0] chunks processed,
  * [1] decision launches (one per chunk plus one per round), [2] host waits,
- * [3] sparse pair tasks computed, summed over the analyser's runs. */
+ * [3] sparse pair tasks computed, [4] of those, speculative field measures
+ * (computed ahead of the pass; some may never be asked for), [5] sparse
+ * measures the sequential pass requested (Sec. III.A's selective schedule:
+ * field measures served from the speculative cache count as requested),
+ * summed over the analyser's runs. */
 vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n);
+
+/* Test hook: the sparse measures the sequential pass requested in the last
+ * run of an analyser created with debug_log, up to cap x 6 int32 (kind, ref,
+ * oth, ref_field, oth_field, level; the caller's array), the same set the
+ * oracle logs in the sparse schedule.  Returns the count, VSA_E_STATE without
+ * debug_log, VSA_E_INVAL for bad arguments. */
+int32_t vsa_clip_debug_log(vsa_clip* c, int32_t* keys, int32_t cap);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): the pair measure of

@@ -373,11 +373,16 @@ __device__ __forceinline__ bool static_at(const StreamDesc& sd, const Staged& pf
     return (info_of(sd, f).flags & VSA_F_STATIC) != 0;
 }
 
+__device__ __forceinline__ void log_task(int32_t* log, int64_t cap, DecideState& st, const PairTask& k);
+
 // Advance one stream as far as the ingested frames allow (kSpec: with the
-// speculative field measures when dp.spec is given).
+// speculative field measures when dp.spec is given).  A frame whose fields
+// the pass takes from the speculative cache counts (and is logged, with
+// slog) as the three field measures it requested.
 template <bool kSpec>
 __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* closed, PairResult* res,
-                        const DecideParams& dp, int has_frame, int frame, int ended_T, const Staged& pf) {
+                        const DecideParams& dp, int has_frame, int frame, int ended_T, const Staged& pf,
+                        int32_t* slog = nullptr, int64_t log_cap = 0) {
     st.n_closed = 0;
     if (st.done) { st.plan = 0; return; }
     if (has_frame) st.n = frame;
@@ -414,6 +419,12 @@ __device__ void advance(const StreamDesc& sd, DecideState& st, vsa_shot_result* 
             else break;                           // wait for the look-ahead frames
         }
         const bool cached = spec_on && want && spec_fetch(sd, t, res, dp);
+        if (cached)
+            for (int i = 0; i < 3; ++i) {
+                PairTask k;
+                field_task(sd, t, i, k);
+                log_task(slog, log_cap, st, k);
+            }
         st.plan_want = want;
         st.plan_fire = fire;
         st.plan_deep = need_deep;
@@ -647,7 +658,8 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         vsa_shot_result* closed = closed_buf + (int64_t)sid * kMaxClosed;
         const int e0 = st.emitted;
         const Staged pf{kSpec ? pf_act[wave] : nullptr, kSpec ? pf_stat[wave] : nullptr, pf_base, pf_n};
-        advance<kSpec>(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T, pf);
+        advance<kSpec>(sd, st, closed, res[wave], dp, ss.has_frame, ss.frame, ss.ended_T, pf,
+                       kSpec && log ? log + (int64_t)sid * log_cap * 6 : nullptr, log_cap);
         const int nt = plan_task_count<kSpec>(sd, st);
         int tiles = 0, blocks = 0;
         if (kSpec) {
@@ -722,10 +734,13 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         const Bcast& b = bc[wave];
         int32_t* slog = log ? log + (int64_t)sid * log_cap * 6 : nullptr;
         int end = b.tile;
+        const int regular = b.ntasks > 0 ? plan_regular_count(sd, st) : 0;
         for (int q = 0; q < b.ntasks; ++q) {
             end += ptile[wave][q];
-            if (slog) log_task(slog, log_cap, st, plan_task<kSpec>(sd, st, sid, q));
+            // the measures the pass asked for; speculative ones are only counted
+            if (q < regular) log_task(slog, log_cap, st, plan_task<kSpec>(sd, st, sid, q));
         }
+        st.spec_count += b.ntasks - regular;
         npre[wave][b.ntasks] = end;
         st.sp_base = b.task;
         st.sp_count = b.ntasks;

@@ -129,7 +129,8 @@ struct DecideState {
     int32_t done;               // end of stream fully processed
     int32_t n_closed;           // shots closed by the last advance
     int32_t sp_base, sp_count;  // where the planned tasks sit in that step's sparse list
-    int64_t log_count;          // sparse measures logged
+    int64_t log_count;          // sparse measures requested by the pass (logged when a log is kept)
+    int64_t spec_count;         // speculative field tasks planned (offline clip form)
 };
 
 // Shots closed by one advance of a stream: at most 3 (a planned boundary, one

@@ -1778,7 +1778,10 @@ struct vsa_clip {
     int64_t stage_pitch = 0, stage_bytes = 0;
     int64_t dec_no = 0;            // decision launches in the current run
     int est_rounds = 8;            // rounds enqueued before the first wait of a chunk
-    uint64_t counters[4] = {0};    // chunks, decision launches, host waits, sparse tasks
+    uint64_t counters[6] = {0};    // chunks, decision launches, host waits, sparse tasks, speculative
+                                   // field tasks among them, measures requested by the pass
+    int32_t* d_log = nullptr;      // with debug_log: the measures the pass requested (6 int32 each)
+    int64_t log_cap = 0, log_n = 0;  // capacity, and the count of the last run
 };
 
 namespace {
@@ -1806,7 +1809,7 @@ vsa_status clip_decide(vsa_clip* c, const StepStream* d_entry) {
                     nullptr, c->grid_s, c->s),
           "motion search launch");
     HIPCK(launch_finish_decide(c->d_sds, c->d_state, d_entry, 1, c->dp, c->d_part, spart, sp_prev, sp_next, c->d_cur,
-                               c->d_out_frames, c->out_cap, c->d_out_shots, c->out_cap, nullptr, 0, c->d_closed, par,
+                               c->d_out_frames, c->out_cap, c->d_out_shots, c->out_cap, c->d_log, c->log_cap, c->d_closed, par,
                                c->d_snap + par, sj_next, sm_next, c->s),
           "decide launch");
     c->dec_no += 1;
@@ -1935,7 +1938,7 @@ void vsa_clip_destroy(vsa_clip* c) {
     if (c->sp) (void)hipStreamSynchronize(c->sp);
     if (c->s) (void)hipStreamSynchronize(c->s);
     void* dev[] = {c->mem, c->d_sds, c->d_state, c->d_cur, c->d_closed, c->d_desc, c->d_cjobs, c->d_cmap,
-                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage, c->d_spec};
+                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage, c->d_spec, c->d_log};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_desc, c->h_init, c->h_out_frames, c->h_out_shots, c->h_snap};
@@ -2021,6 +2024,10 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
               dalloc((void**)&c->d_sjobs, 2 * sizeof(TileJob) * tc) &&
               dalloc((void**)&c->d_smap, 2 * sizeof(int32_t) * c->sparse_tiles) &&
               dalloc((void**)&c->d_spec, sizeof(double) * 4 * sd.rs);
+    if (ok && cfg->debug_log) {
+        c->log_cap = kLogCapPerStream;
+        ok = dalloc((void**)&c->d_log, sizeof(int32_t) * 6 * (size_t)c->log_cap);
+    }
     if (!ok) return fail(VSA_E_NOMEM, "clip device buffers");
     // speculative field measures: the sparse schedule only (the dense one
     // computes every frame's fields anyway)
@@ -2136,6 +2143,11 @@ static vsa_status clip_run_body(vsa_clip* c, const void* frames, int64_t frame_s
     }
     HIPCK(hipStreamSynchronize(c->sp), "clip ingest");
     c->counters[3] += run_tasks;
+    DecideState fin;
+    HIPCK(hipMemcpy(&fin, c->d_state, sizeof fin, hipMemcpyDeviceToHost), "decision state");
+    c->counters[4] += (uint64_t)fin.spec_count;
+    c->counters[5] += (uint64_t)fin.log_count;
+    c->log_n = fin.log_count;
     if (frames_read != (uint64_t)T) return fail(VSA_E_DEVICE, "clip ended with frames missing");
     if (n_shots) *n_shots = (int32_t)shots_read;
     return VSA_OK;
@@ -2189,8 +2201,18 @@ int32_t vsa_debug_clip_chunks(int32_t chunk, int32_t n_frames, int32_t* starts, 
 vsa_status vsa_clip_counters(vsa_clip* c, uint64_t* out, int32_t n) {
     if (!c || !out || n < 0) return fail(VSA_E_INVAL, "bad argument");
     std::lock_guard<std::mutex> lk(c->mu);
-    for (int i = 0; i < n && i < 4; ++i) out[i] = c->counters[i];
+    for (int i = 0; i < n && i < 6; ++i) out[i] = c->counters[i];
     return VSA_OK;
+}
+
+int32_t vsa_clip_debug_log(vsa_clip* c, int32_t* keys, int32_t cap) {
+    if (!c || cap < 0 || (cap > 0 && !keys)) return fail(VSA_E_INVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->d_log) return fail(VSA_E_STATE, "clip analyser created without debug_log");
+    const int64_t n = std::min(c->log_n, c->log_cap);
+    const int64_t k = std::min<int64_t>(n, cap);
+    if (k > 0) HIPCK(hipMemcpy(keys, c->d_log, sizeof(int32_t) * 6 * k, hipMemcpyDeviceToHost), "clip log");
+    return (int32_t)n;
 }
 
 }  // extern "C"

@@ -57,7 +57,7 @@ class EngineConfig(C.Structure):
 class ClipConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("bit_depth", C.c_int32),
                 ("k_max", C.c_int32), ("chunk", C.c_int32), ("schedule", C.c_int32), ("no_intensity", C.c_int32),
-                ("me_wgs_per_cu", C.c_int32), ("params", C.POINTER(Params))]
+                ("me_wgs_per_cu", C.c_int32), ("params", C.POINTER(Params)), ("debug_log", C.c_int32)]
 
 
 class StreamDesc(C.Structure):
@@ -87,7 +87,7 @@ SYMBOLS = [
     "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_get_histogram", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
-    "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters",
+    "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters", "vsa_clip_debug_log",
     "vsa_debug_clip_chunks", "vsa_pair_noalloc",
 ]
 
@@ -146,6 +146,7 @@ def lib():
         "vsa_clip_destroy": (None, [P]),
         "vsa_clip_run": (i32, [P, P, i64, i64, i32, i32, P, P, i32, C.POINTER(i32)]),
         "vsa_clip_counters": (i32, [P, P, i32]),
+        "vsa_clip_debug_log": (i32, [P, P, i32]),
         "vsa_debug_clip_chunks": (i32, [i32, i32, P, P, i32]),
         "vsa_pair_noalloc": (i32, [C.POINTER(Params), P, P, i32, i32, i64, i32, i32, P, P, P, P]),
     }
@@ -367,11 +368,11 @@ class Clip:
 
     def __init__(self, width: int, height: int, bit_depth: int = 8, k_max: int = 0, chunk: int = 0,
                  dense: bool = False, params: Optional[dict] = None, no_intensity: int = 0,
-                 me_wgs_per_cu: int = 0, device: int = 0):
+                 me_wgs_per_cu: int = 0, device: int = 0, debug_log: bool = False):
         self._params = make_params(params)
         cfg = ClipConfig(device=device, width=width, height=height, bit_depth=bit_depth, k_max=k_max, chunk=chunk,
                          schedule=SCHEDULE_DENSE if dense else SCHEDULE_SPARSE, no_intensity=no_intensity,
-                         me_wgs_per_cu=me_wgs_per_cu, params=C.pointer(self._params))
+                         me_wgs_per_cu=me_wgs_per_cu, params=C.pointer(self._params), debug_log=int(debug_log))
         h = C.c_void_p()
         _check(lib().vsa_clip_create(C.byref(cfg), C.byref(h)), "clip_create")
         self.h = h
@@ -418,9 +419,18 @@ class Clip:
                          SRC_DEVICE_BORROW)
 
     def counters(self) -> dict:
-        out = np.zeros(4, np.uint64)
-        _check(lib().vsa_clip_counters(self.h, _ptr(out), 4), "clip_counters")
-        return dict(zip(("chunks", "decision_launches", "waits", "sparse_tasks"), (int(x) for x in out)))
+        out = np.zeros(6, np.uint64)
+        _check(lib().vsa_clip_counters(self.h, _ptr(out), 6), "clip_counters")
+        return dict(zip(("chunks", "decision_launches", "waits", "sparse_tasks", "speculative_tasks",
+                         "requested_measures"), (int(x) for x in out)))
+
+    def measure_log(self) -> np.ndarray:
+        """[n, 6] int32 (kind, ref, oth, ref_field, oth_field, level) of the sparse
+        measures the sequential pass requested in the last run (debug_log)."""
+        n = _check(lib().vsa_clip_debug_log(self.h, None, 0), "clip_debug_log")
+        out = np.zeros((max(n, 1), 6), np.int32)
+        _check(lib().vsa_clip_debug_log(self.h, _ptr(out), n), "clip_debug_log")
+        return out[:n].copy()
 
 
 def run_clip(frames: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8, dense: bool = False,

@@ -38,6 +38,26 @@ def _same(got, ref, what=""):
         assert np.array_equal(gs[name], rs[name]), f"{what} shot {name}"
 
 
+def _same_requests(c, ref, what="", base=None):
+    """The sparse measures the clip's sequential pass requested in its last
+    run are the oracle's, as a set, and the counters (less `base`, the
+    counters before that run) agree with them: every request was computed,
+    as a regular task or speculatively ahead of the pass."""
+    rk = ref["keys"][ref["keys"]["kind"] != 0]
+    got = c.measure_log()
+    keys = np.zeros(len(got), rk.dtype)
+    for i, name in enumerate(("kind", "ref", "oth", "ref_field", "oth_field", "level")):
+        keys[name] = got[:, i]
+    assert np.array_equal(np.sort(keys), np.sort(rk)), f"{what} requested measures"
+    cnt = c.counters()
+    if base:
+        cnt = {k: v - base[k] for k, v in cnt.items()}
+    assert cnt["requested_measures"] == len(rk), what
+    assert cnt["sparse_tasks"] >= cnt["requested_measures"], what
+    # speculative tasks cover the field requests not computed as regular tasks
+    assert cnt["speculative_tasks"] >= cnt["sparse_tasks"] - cnt["requested_measures"], what
+
+
 def _n_chunks(T, C):
     """Chunks of a T-frame clip: a first one of min(C, max(16, C // 4)) frames, then C each."""
     head = min(C, max(16, C // 4))
@@ -57,14 +77,13 @@ def c1_ref(orc, params, c1):
 @pytest.mark.parametrize("chunk", [1, 7, 16, 64, 256])
 def test_chunks_equal_oracle(vsa, params, c1, c1_ref, chunk):
     print(f"clip 320x180 chunk={chunk}", flush=True)
-    with vsa.Clip(320, 180, chunk=chunk, params=params) as c:
+    with vsa.Clip(320, 180, chunk=chunk, params=params, debug_log=True) as c:
         got = c.run(c1)
         cnt = c.counters()
+        _same_requests(c, c1_ref, f"chunk {chunk}")
     _same(got, c1_ref, f"chunk {chunk}")
     assert got["frames"]["pts"].tolist() == list(range(len(c1)))
     assert cnt["chunks"] == _n_chunks(len(c1), chunk)
-    # every measure the sequential pass asks for, plus the speculative fields
-    assert cnt["sparse_tasks"] >= np.count_nonzero(c1_ref["keys"]["kind"] != 0)
 
 
 def test_device_source_and_repeated_runs(vsa, orc, params, c1, c1_ref):
@@ -113,8 +132,14 @@ def test_interlaced_mix_clip(vsa, orc, params):
     p["k_max"] = 8
     frames = synth.render(synth.make_mix_clip(0, seed=3, T=300), range(120))
     ref = orc.run_clip(frames, p)
-    with vsa.Clip(720, 576, chunk=40, params=p) as c:
+    with vsa.Clip(720, 576, chunk=40, params=p, debug_log=True) as c:
         got = c.run(frames)
+        _same_requests(c, ref, "720x576")
+        # a second, shorter run logs only its own requests
+        ref40 = orc.run_clip(frames[:40], p)
+        base = c.counters()
+        c.run(frames[:40])
+        _same_requests(c, ref40, "720x576, 40 frames", base)
     _same(got, ref, "720x576")
 
 

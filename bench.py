@@ -94,14 +94,8 @@ def copy_only(nbytes, reps):
 
 def _spec(kind):
     import synth
-    if kind[0] == "c2":
-        _, seed, T, W, H = kind
-        return synth.make_c2(seed=seed, T=T, W=W, H=H, k_dis=8)
-    if kind[0] == "c5":
-        _, seed, T, W, H = kind
-        return synth.make_c5(seed=seed, T=T, W=W, H=H)
-    _, i, seed, T = kind                      # clip i of the uneven mix
-    return synth.make_mix_clip(i, seed=seed, T=T)
+    _, seed, T, W, H = kind                   # the 2K clip
+    return synth.make_c2(seed=seed, T=T, W=W, H=H, k_dis=8)
 
 
 def _render_range(args):
@@ -143,99 +137,134 @@ def render_clip(seed, T, W, H, workers):
     return render_frames(("c2", seed, T, W, H), T, W, H, workers)
 
 
-def mix_pools(n, workers, torch):
-    """The first n frames of one clip per format of the uneven mix, on the device."""
+def mix_clips(n, frames_needed, torch, seed=3, first=0):
+    """Clips first..first+n-1 of the uneven mix, each rendered on the device
+    from its own spec (format i mod 6, length U{200..3000}): its first
+    min(length, frames_needed) frames, or all of them (frames_needed None)."""
     import synth
-    pools = []
-    for i, (W, H, _, _) in enumerate(synth.MIX_FORMATS):
-        fr = render_frames(("mix", i, 3, 3000), n, W, H, workers)
-        pools.append(torch.from_numpy(fr).to("cuda:0"))
+    from synth.device import DeviceRenderer
+    clips = []
+    for i in range(first, first + n):
+        spec = synth.make_mix_clip(i, seed=seed)
+        m = spec.T if frames_needed is None else min(spec.T, frames_needed)
+        clips.append(DeviceRenderer(spec, "cuda:0").frames(0, m))
     torch.cuda.synchronize()
-    return pools
+    return clips
 
 
-def run_mix(vsa, pools, params, B, steps, warmup, torch):
-    """B clips of the uneven mix in one engine (clip i: format i mod 6), every
-    clip stepping together; returns frames/s and the per-kernel times."""
+def run_mix(vsa, clips, params, steps, warmup, torch):
+    """The clips of the uneven mix in one engine, one stream each, every
+    stream stepping together from its clip's first frame; a clip shorter than
+    the run ends there (its stream is ended after its last frame and pushes no
+    more).  Returns frames/s (frames pushed in the timed steps) and the
+    per-kernel times."""
+    B = len(clips)
     e = vsa.Engine(device=0, max_streams=B, params=params, profile=2)
     sids, bases, pitches, planes, nsrc = [], [], [], [], []
-    for i in range(B):
-        src = pools[i % len(pools)]
+    for src in clips:
         F, H, W = src.shape
         sids.append(e.stream_open(W, H, 8))
         bases.append(src.data_ptr()); pitches.append(W); planes.append(H * W); nsrc.append(F)
     sids = np.array(sids, np.int32)
     bases = np.array(bases, np.uint64); pitches = np.array(pitches, np.int64)
     planes = np.array(planes, np.uint64); nsrc = np.array(nsrc, np.int64)
-    offs = np.arange(B) * 7
 
     def do_step(s):
-        ptrs = bases + ((offs + s) % nsrc).astype(np.uint64) * planes
-        if e.stream_push_batch(sids, ptrs, pitches, vsa.SRC_DEVICE_BORROW, None) != 0:
+        live = s < nsrc
+        if not live.any():
+            e.step()
+            return 0
+        ptrs = bases[live] + np.uint64(s) * planes[live]
+        if e.stream_push_batch(sids[live], ptrs, pitches[live], vsa.SRC_DEVICE_BORROW, None) != 0:
             raise RuntimeError(vsa.last_error())
+        for sid in sids[s == nsrc - 1]:
+            e.stream_end(int(sid))
         e.step()
+        return int(live.sum())
 
     for s in range(warmup):
         do_step(s)
     e.sync()
     e.kernel_times(reset=True)
+    pushed = 0
     t0 = time.perf_counter()
     for s in range(warmup, warmup + steps):
-        do_step(s)
+        pushed += do_step(s)
     e.sync()
     dt = time.perf_counter() - t0
     kt = e.kernel_times()
     e.close()
-    return B * steps / dt, {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}
+    return pushed / dt, pushed, {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}
 
 
-def run_stress(vsa, frames, params, B, steps, warmup, dense, torch):
-    """B streams of 3840x2160 10-bit (uint16) in one engine, sparse or dense
-    schedule; returns frames/s, AD per frame and the per-kernel times."""
-    F, H, W = frames.shape
-    e = vsa.Engine(device=0, max_streams=B, params=params, profile=2,
-                   schedule=vsa.SCHEDULE_DENSE if dense else vsa.SCHEDULE_SPARSE)
-    sids = np.array([e.stream_open(W, H, 10) for _ in range(B)], np.int32)
-    base = frames.data_ptr()
-    plane = H * W * 2
-    offs = (np.arange(B) * (F // B)) % F
+def run_stress(vsa, params, B, frames_per_stream, seg, torch):
+    """The 4K 10-bit 50i clip (its full length) cut into B consecutive pieces,
+    piece s read by stream s in order, in two engines at once (sparse and dense
+    schedule).  Each segment of `seg` steps is rendered on the device first,
+    untimed; each engine's steps over it are timed between device
+    synchronisations.  Returns, per schedule, frames/s, AD per frame and the
+    per-kernel times, and the render time."""
+    import synth
+    from synth.device import DeviceRenderer
+    T = B * frames_per_stream
+    spec = synth.make_c5(seed=5, T=T)
+    H, W = spec.H, spec.W
+    rends = [DeviceRenderer(spec, "cuda:0") for _ in range(B)]
+    buf = torch.empty((B, seg, H, W), dtype=torch.int16, device="cuda:0")
+    engines = {}
+    for dense in (False, True):
+        e = vsa.Engine(device=0, max_streams=B, params=params, profile=2,
+                       schedule=vsa.SCHEDULE_DENSE if dense else vsa.SCHEDULE_SPARSE)
+        engines[dense] = (e, np.array([e.stream_open(W, H, 10) for _ in range(B)], np.int32))
     pitches = np.full(B, W * 2, np.int64)
+    plane = H * W * 2
+    base = np.array([buf[b].data_ptr() for b in range(B)], np.uint64)
+    c0 = {d: e.counters() for d, (e, _) in engines.items()}
+    for e, _ in engines.values():
+        e.kernel_times(reset=True)
+    busy = {False: 0.0, True: 0.0}
+    render_s = 0.0
+    done = 0
+    while done < frames_per_stream:
+        n = min(seg, frames_per_stream - done)
+        t1 = time.perf_counter()
+        for b in range(B):
+            rends[b].render_into(buf[b, :n], b * frames_per_stream + done)
+        torch.cuda.synchronize()
+        render_s += time.perf_counter() - t1
+        for dense, (e, sids) in engines.items():
+            e.sync()
+            t1 = time.perf_counter()
+            for j in range(n):
+                if e.stream_push_batch(sids, base + np.uint64(j * plane), pitches, vsa.SRC_DEVICE_BORROW,
+                                       None) != 0:
+                    raise RuntimeError(vsa.last_error())
+                if done + j == frames_per_stream - 1:
+                    for sid in sids:
+                        e.stream_end(int(sid))
+                e.step()
+            e.sync()
+            busy[dense] += time.perf_counter() - t1
+        done += n
+    out = {}
+    for dense, (e, sids) in engines.items():
+        c1 = e.counters()
+        kt = e.kernel_times()
+        blocks = (c1["consecutive_blocks"] - c0[dense]["consecutive_blocks"]) + \
+                 (c1["sparse_blocks"] - c0[dense]["sparse_blocks"])
+        out[dense] = (B * frames_per_stream / busy[dense], blocks * 289 * 64 / (B * frames_per_stream),
+                      {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]})
+        e.close()
+    return out, render_s
 
-    def do_step(s):
-        ptrs = (base + ((offs + s) % F).astype(np.uint64) * plane).astype(np.uint64)
-        if e.stream_push_batch(sids, ptrs, pitches, vsa.SRC_DEVICE_BORROW, None) != 0:
-            raise RuntimeError(vsa.last_error())
-        e.step()
 
-    for s in range(warmup):
-        do_step(s)
-    e.sync()
-    e.kernel_times(reset=True)
-    c0 = e.counters()
-    t0 = time.perf_counter()
-    for s in range(warmup, warmup + steps):
-        do_step(s)
-    e.sync()
-    dt = time.perf_counter() - t0
-    c1 = e.counters()
-    kt = e.kernel_times()
-    e.close()
-    blocks = (c1["consecutive_blocks"] - c0["consecutive_blocks"]) + (c1["sparse_blocks"] - c0["sparse_blocks"])
-    return (B * steps / dt, blocks * 289 * 64 / (B * steps),
-            {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]})
-
-
-def serve_requests(serve, pools, n, rate, seed, lengths=(200, 3000)):
-    """Clips of the uneven mix arriving as a Poisson process: format uniform,
-    length U{lengths}, each reading its format's frame pool from a random start."""
-    rng = np.random.default_rng(seed)
-    arr = serve.poisson_arrivals(rate, n, seed) if rate > 0 else np.zeros(n)
-    reqs = []
-    for cid in range(n):
-        src = pools[int(rng.integers(0, len(pools)))]
-        reqs.append(serve.ClipRequest(cid, float(arr[cid]), src, int(rng.integers(0, src.shape[0])),
-                                      int(rng.integers(lengths[0], lengths[1] + 1)), 8))
-    return reqs
+def serve_requests(serve, clips, rate, seed):
+    """One request per rendered clip, arriving as a Poisson process at `rate`
+    per second (all at once for rate 0), each reading its own clip from its
+    first frame to its last."""
+    arr = serve.poisson_arrivals(rate, len(clips), seed) if rate > 0 else np.zeros(len(clips))
+    return [serve.ClipRequest(cid, float(arr[cid]), src, 0, int(src.shape[0]), 8)
+            for cid, src in enumerate(clips)]
 
 
 def geometry(W, H, params):
@@ -477,6 +506,10 @@ def main():
     ap.add_argument("--serve-clips", type=int, default=32)
     ap.add_argument("--no-stress", action="store_true", help="skip the 4K 10-bit sparse/dense runs")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-rates", default="0.5,1,2,5,10,20",
+                    help="comma-separated Poisson rates of the served sweep ('' for none)")
+    ap.add_argument("--stress-frames", type=int, default=45000,
+                    help="frames of the 4K 10-bit stress clip (the clip's stated length by default)")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--no-clip", action="store_true", help="skip the offline single-clip run")
@@ -648,53 +681,87 @@ def main():
         if kt_all:
             extra["kernel_ms_per_step"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in kt_all.items() if v[1]}
         extra["step_hbm_frac"] = round(args.streams * k1b / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
-    pools = None
-    if not (args.no_mix and args.no_serve):
-        t1 = time.perf_counter()
-        pools = mix_pools(64, args.workers, torch)
-        print(f"[bench] mix frame pools rendered in {time.perf_counter() - t1:.1f}s", file=sys.stderr, flush=True)
     if not args.no_mix:
-        mfps, mkt = run_mix(vsa, pools, dict(params, k_max=8), 64, 300, 30, torch)
-        extra["mix"] = {"workload": "64 clips of the uneven mix in one engine (720x576i, 1280x720p, "
-                                    "1920x1080p, 1920x1080i, 2048x1080p, 3840x2160p; 8-bit), one frame "
-                                    "each per step", "fps": round(mfps, 1), "kernel_ms_per_step": mkt}
+        t1 = time.perf_counter()
+        mix_steps, mix_warm = 300, 30
+        clips = mix_clips(64, mix_steps + mix_warm, torch)
+        rs = time.perf_counter() - t1
+        print(f"[bench] mix: 64 clips rendered in {rs:.1f}s", file=sys.stderr, flush=True)
+        mfps, mframes, mkt = run_mix(vsa, clips, dict(params, k_max=8), mix_steps, mix_warm, torch)
+        extra["mix"] = {"workload": "clips 0..63 of the uneven mix (720x576i, 1280x720p, 1920x1080p, "
+                                    "1920x1080i, 2048x1080p, 3840x2160p; 8-bit; lengths U{200..3000}), each "
+                                    "rendered from its own spec, one stream each in one engine, all stepping "
+                                    "together from their first frame; a clip that ends stops pushing",
+                        "fps": round(mfps, 1), "frames": mframes, "steps": mix_steps,
+                        "kernel_ms_per_step": mkt, "render_s": round(rs, 1)}
+        del clips
+        torch.cuda.empty_cache()
         print(f"[bench] mix 64 clips: {mfps:.0f} frames/s", file=sys.stderr, flush=True)
     if not args.no_serve:
         from paper_2502_09202_amd import serve
+        t1 = time.perf_counter()
+        clips = mix_clips(args.serve_clips, None, torch, seed=4)
+        rs = time.perf_counter() - t1
+        nfr = sum(int(c.shape[0]) for c in clips)
+        print(f"[bench] serve: {len(clips)} clips ({nfr} frames) rendered in {rs:.1f}s", file=sys.stderr,
+              flush=True)
         sv = {}
         p8 = dict(params, k_max=8)
-        for name, rate in (("poisson", args.serve_rate), ("archive", 0.0)):
+
+        def serve_once(reqs, path):
+            S = serve.Server if path == "batched" else serve.PlainServer
+            srv = S(max_streams=256, params=p8)
+            try:
+                return srv.run(reqs, keep_records=False).summary()
+            finally:
+                srv.close()
+
+        rates = [float(x) for x in args.serve_rates.split(",") if x] if args.serve_rates else []
+        if args.serve_rate not in rates:
+            rates.append(args.serve_rate)
+        sweep = {}
+        for rate in sorted(rates):
+            # enough clips for a few seconds of arrivals (all of them at the higher rates)
+            n = min(len(clips), max(6, int(round(4 * rate))))
+            row = {"clips": n}
             for path in ("batched", "plain"):
-                reqs = serve_requests(serve, pools, args.serve_clips, rate, 4)
-                S = serve.Server if path == "batched" else serve.PlainServer
-                srv = S(max_streams=256, params=p8)
-                try:
-                    rep_ = srv.run(reqs, keep_records=False)
-                finally:
-                    srv.close()
-                sv[f"{name}_{path}"] = rep_.summary()
-                print(f"[bench] serve {name} {path}: {rep_.fps:.0f} frames/s, frame p50/p99 "
-                      f"{sv[f'{name}_{path}']['frame_latency_ms_p50']:.2f}/"
-                      f"{sv[f'{name}_{path}']['frame_latency_ms_p99']:.2f} ms", file=sys.stderr, flush=True)
-        extra["serve"] = {"workload": f"{args.serve_clips} clips of the uneven mix, length U{{200..3000}}, "
-                                      f"Poisson arrivals at {args.serve_rate}/s (poisson) or all at once "
-                                      "(archive); budget 90% of free HBM, 256 slots", **sv}
+                sm = serve_once(serve_requests(serve, clips[:n], rate, 4), path)
+                row[path] = sm
+                print(f"[bench] serve rate {rate}/s {path}: {sm['fps']:.0f} frames/s, frame p50/p99 "
+                      f"{sm['frame_latency_ms_p50']:.2f}/{sm['frame_latency_ms_p99']:.2f} ms", file=sys.stderr,
+                      flush=True)
+            sweep[f"{rate:g}"] = row
+            if rate == args.serve_rate:
+                sv["poisson_batched"], sv["poisson_plain"] = row["batched"], row["plain"]
+        for path in ("batched", "plain"):
+            sv[f"archive_{path}"] = serve_once(serve_requests(serve, clips, 0.0, 4), path)
+            print(f"[bench] serve archive {path}: {sv[f'archive_{path}']['fps']:.0f} frames/s", file=sys.stderr,
+                  flush=True)
+        extra["serve"] = {"workload": f"{len(clips)} clips of the uneven mix at their own lengths "
+                                      f"(U{{200..3000}}, {nfr} frames), each rendered from its own spec; "
+                                      f"Poisson arrivals at {args.serve_rate}/s (poisson), or all at once "
+                                      "(archive); budget 90% of free HBM, 256 slots", "render_s": round(rs, 1),
+                          **sv,
+                          "rate_sweep": {"note": "per rate, the first max(6, 4 x rate) clips (at most all) "
+                                                 "arriving at that Poisson rate, batched and plain per-stream",
+                                         **sweep}}
+        del clips
+        torch.cuda.empty_cache()
     if not args.no_stress:
-        t1 = time.perf_counter()
-        c5 = torch.from_numpy(render_frames(("c5", 5, 600, 3840, 2160), 32, 3840, 2160, args.workers,
-                                            bits=10).astype(np.int16)).to("cuda:0")
-        torch.cuda.synchronize()
-        print(f"[bench] 4K 10-bit frames rendered in {time.perf_counter() - t1:.1f}s", file=sys.stderr, flush=True)
-        st = {"workload": "8 streams of 3840x2160 10-bit (uint16) 50i, low contrast, pans up to 64 px/frame, "
-                          "noise sigma 12, flashes every ~25 frames, k_max 4"}
-        for dense in (False, True):
-            sfps, adpf, skt = run_stress(vsa, c5, dict(params, k_max=4), 8, 200, 20, dense, torch)
+        B = 8
+        per = args.stress_frames // B
+        res, rs = run_stress(vsa, dict(params, k_max=4), B, per, 64, torch)
+        st = {"workload": f"the 3840x2160 10-bit (uint16) 50i stress clip, {B * per} frames, cut into {B} "
+                          f"consecutive pieces read by {B} streams; low contrast 64..192, pans up to 64 px/frame, "
+                          "noise sigma 12, flashes p 1/25, k_max 4; rendered on the device 64 steps at a time, "
+                          "untimed", "render_s": round(rs, 1)}
+        for dense, (sfps, adpf, skt) in res.items():
             st["dense" if dense else "sparse"] = {"fps": round(sfps, 1), "x_realtime": round(sfps / RT_FPS, 1),
                                                   "absdiff_per_frame": round(adpf), "kernel_ms_per_step": skt}
             print(f"[bench] 4K 10-bit {'dense' if dense else 'sparse'}: {sfps:.0f} frames/s, "
                   f"{adpf / 1e6:.1f} M AD/frame", file=sys.stderr, flush=True)
         extra["stress_10bit"] = st
-        del c5
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(frames, params, args.cpu_seconds)

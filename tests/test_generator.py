@@ -55,3 +55,39 @@ def test_interlaced_fields_half_interval():
         assert np.array_equal(fr[0::2], early[0::2]) and np.array_equal(fr[1::2], late[1::2])
     else:
         assert np.array_equal(fr[1::2], early[1::2]) and np.array_equal(fr[0::2], late[0::2])
+
+
+def _device_frames(spec, t0, n):
+    from synth.device import DeviceRenderer
+    r = DeviceRenderer(spec, device="cpu", host_noise=True)
+    return r.frames(t0, n).numpy().astype(np.int32)
+
+
+def _close(a, b):
+    d = np.abs(a.astype(np.int32) - b.astype(np.int32))
+    # the two FFTs may round a texture value to the other integer
+    return d.max() <= 1 and np.count_nonzero(d) <= max(8, d.size // 2000)
+
+
+def test_device_renderer_follows_the_recipe():
+    """The torch renderer (run here on the CPU, with the numpy noise streams)
+    gives the numpy renderer's frames on a 2K-shaped clip with interlaced,
+    pulldown and progressive shots, rectangles, dissolves, flashes and
+    flicker, and on the 320x180 clip with its per-frame pans."""
+    spec = synth.make_c2(seed=3, T=420, W=256, H=136, k_dis=8)
+    kinds = {s.sampling for s in spec.shots}
+    assert kinds >= {1, 2, 3, 4} or len(spec.shots) >= 2
+    ref = synth.render(spec)
+    got = _device_frames(spec, 0, spec.T)
+    for t in range(spec.T):
+        assert _close(got[t], ref[t]), t
+    c1 = synth.make_c1(seed=4, T=40)
+    assert _close(_device_frames(c1, 5, 30), synth.render(c1, range(5, 35)))
+
+
+def test_device_renderer_10bit_and_offsets():
+    spec = synth.make_c5(seed=6, T=60, W=320, H=176)
+    ref = synth.render(spec, range(20, 44))
+    got = _device_frames(spec, 20, 24)
+    assert ref.dtype == np.uint16
+    assert _close(got, ref)

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define VSA_ABI_VERSION 2
+#define VSA_ABI_VERSION 3
 
 typedef int32_t vsa_status;
 enum {
@@ -88,6 +88,11 @@ typedef struct {
     double tau_p;         /* 3:2 pulldown if the mean v0 at two neighbouring positions of the
                              5-frame unit exceeds tau_p times the mean at each other one     */
     double theta_kf;      /* keyframe when accumulated ACT exceeds theta_kf                  */
+    int32_t search;       /* motion field of frame pairs (Sec. III.A): 0 full search over
+                             [-R, R]^2; 1 coarse-to-fine: full search on the 2x2-box image one
+                             level coarser, then +-refine around twice that vector (reach
+                             2R + refine).  Field pairs always take the full search.          */
+    int32_t refine;       /* refinement radius of the coarse-to-fine search; must be 1       */
 } vsa_params;
 
 typedef struct {

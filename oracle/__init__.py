@@ -43,7 +43,7 @@ class Params(C.Structure):
         ("a0", C.c_double), ("rho_f", C.c_double), ("theta_f", C.c_double), ("theta_f0", C.c_double),
         ("rho_d", C.c_double), ("theta_d", C.c_double), ("gamma", C.c_double),
         ("tau_c", C.c_double), ("eps", C.c_double), ("tau_p", C.c_double),
-        ("theta_kf", C.c_double),
+        ("theta_kf", C.c_double), ("search", C.c_int32), ("refine", C.c_int32),
     ]
 
 

@@ -215,18 +215,52 @@ bool finish(int64_t sx, int64_t sy, int64_t sxx, int64_t syy, int64_t sxy, int64
     return true;
 }
 
-// The pair measure M(I -> J): for every whole 8 x 8 block of I, the
-// displacement d in [-R, R]^2 minimising the SAD against J (J read with
-// clamp-to-edge), ties broken by the candidate order; J warped block-wise by
-// those vectors; the exact moments of I against warped J over the covered
-// pixels; A = sum over blocks of floor(256 |d|).
-void pair_measure(const Plane& I, const Plane& J, const orc_params& p, bool zero_mv, PairOut& o) {
+// The best displacement of the 8 x 8 block of I at (x0, y0) among the
+// candidates (cx, cy) + e, e in [-R, R]^2, against J read with clamp-to-edge:
+// the smallest SAD, ties broken by the order of e (squared length, then ey,
+// then ex).  With zero_mv only e = (0, 0) is a candidate.
+void block_search(const Plane& I, const Plane& J, int x0, int y0, int cx, int cy, int R,
+                  const std::vector<int>& rank, bool zero_mv, int& bdx, int& bdy, int& best_sad) {
+    const int nc = 2 * R + 1;
+    auto cJ = [&](int x, int y) {
+        x = std::min(std::max(x, 0), J.w - 1);
+        y = std::min(std::max(y, 0), J.h - 1);
+        return J.at(x, y);
+    };
+    int best_rank = 0;
+    best_sad = -1; bdx = cx; bdy = cy;
+    for (int ey = -R; ey <= R; ++ey)
+        for (int ex = -R; ex <= R; ++ex) {
+            if (zero_mv && (ex != 0 || ey != 0)) continue;
+            const int dx = cx + ex, dy = cy + ey;
+            int s = 0;
+            for (int j = 0; j < 8; ++j)
+                for (int i = 0; i < 8; ++i)
+                    s += std::abs(I.at(x0 + i, y0 + j) - cJ(x0 + i + dx, y0 + j + dy));
+            const int r = rank[(size_t)(ey + R) * nc + (ex + R)];
+            if (best_sad < 0 || s < best_sad || (s == best_sad && r < best_rank)) {
+                best_sad = s; best_rank = r; bdx = dx; bdy = dy;
+            }
+        }
+}
+
+// The pair measure M(I -> J): for every whole 8 x 8 block of I a
+// displacement d, J warped block-wise by those vectors, the exact moments of
+// I against warped J over the covered pixels, and A = sum over blocks of
+// floor(256 |d|).  The motion field (Sec. III.A) is
+//  - full search: d in [-R, R]^2 minimising the SAD against J (clamp-to-edge),
+//    ties broken by the candidate order; or, with hier,
+//  - coarse-to-fine: I and J are box-downscaled once (the pyramid's own step),
+//    each whole block of the coarse I gets its full-search vector d_c against
+//    the coarse J; a block (bx, by) of I whose coarse block (bx/2, by/2) is
+//    whole is predicted by 2 d_c, any other block by (0, 0); d is the best of
+//    prediction + e, e in [-r, r]^2 against J, ties by the order of e.
+//    Its reach is 2R + r per axis.
+void pair_measure(const Plane& I, const Plane& J, const orc_params& p, bool zero_mv, bool hier, PairOut& o) {
     const int w = I.w, h = I.h, R = p.radius;
     o = PairOut();
     o.nbx = w / 8; o.nby = h / 8; o.B = (int64_t)o.nbx * o.nby;
-    if (o.B <= 0 || J.w != w || J.h != h || R < 0) { o.ok = false; return; }
-    const std::vector<int> rank = candidate_ranks(R);
-    const int nc = 2 * R + 1;
+    if (o.B <= 0 || J.w != w || J.h != h || R < 0 || (hier && p.refine < 0)) { o.ok = false; return; }
     auto cJ = [&](int x, int y) {
         x = std::min(std::max(x, 0), w - 1);
         y = std::min(std::max(y, 0), h - 1);
@@ -234,23 +268,29 @@ void pair_measure(const Plane& I, const Plane& J, const orc_params& p, bool zero
     };
     o.mv.assign((size_t)o.B * 2, 0);
     o.sad.assign((size_t)o.B, 0);
+    // predictions: (0, 0), or twice the coarse full-search vector
+    std::vector<int> pred((size_t)o.B * 2, 0);
+    if (hier && !zero_mv) {
+        const Plane Ic = downscale(I), Jc = downscale(J);
+        const int nbxc = Ic.w / 8, nbyc = Ic.h / 8;
+        const std::vector<int> rankR = candidate_ranks(R);
+        for (int by = 0; by < o.nby; ++by)
+            for (int bx = 0; bx < o.nbx; ++bx) {
+                if (bx / 2 >= nbxc || by / 2 >= nbyc) continue;
+                int cdx, cdy, cs;
+                block_search(Ic, Jc, 8 * (bx / 2), 8 * (by / 2), 0, 0, R, rankR, false, cdx, cdy, cs);
+                const size_t b = (size_t)by * o.nbx + bx;
+                pred[2 * b] = 2 * cdx; pred[2 * b + 1] = 2 * cdy;
+            }
+    }
+    const int Rs = hier ? p.refine : R;
+    const std::vector<int> rank = candidate_ranks(Rs);
     for (int by = 0; by < o.nby; ++by)
         for (int bx = 0; bx < o.nbx; ++bx) {
             const int x0 = 8 * bx, y0 = 8 * by;
-            int best_sad = -1, best_rank = 0, bdx = 0, bdy = 0;
-            for (int dy = -R; dy <= R; ++dy)
-                for (int dx = -R; dx <= R; ++dx) {
-                    if (zero_mv && (dx != 0 || dy != 0)) continue;
-                    int s = 0;
-                    for (int j = 0; j < 8; ++j)
-                        for (int i = 0; i < 8; ++i)
-                            s += std::abs(I.at(x0 + i, y0 + j) - cJ(x0 + i + dx, y0 + j + dy));
-                    const int r = rank[(size_t)(dy + R) * nc + (dx + R)];
-                    if (best_sad < 0 || s < best_sad || (s == best_sad && r < best_rank)) {
-                        best_sad = s; best_rank = r; bdx = dx; bdy = dy;
-                    }
-                }
             const size_t b = (size_t)by * o.nbx + bx;
+            int bdx, bdy, best_sad;
+            block_search(I, J, x0, y0, pred[2 * b], pred[2 * b + 1], Rs, rank, zero_mv, bdx, bdy, best_sad);
             o.mv[2 * b] = (int8_t)bdx; o.mv[2 * b + 1] = (int8_t)bdy;
             o.sad[b] = best_sad;
             for (int j = 0; j < 8; ++j)
@@ -568,7 +608,8 @@ struct FrameProvider : Provider {
         const FrameLevels* b = get(oth);
         if (!a || !b) return false;
         PairOut o;
-        pair_measure(plane(*a, rf, level), plane(*b, of, level), p, false, o);
+        // field pairs keep the full search; frame pairs follow p.search
+        pair_measure(plane(*a, rf, level), plane(*b, of, level), p, false, p.search == 1 && kind != 1, o);
         if (!o.ok) return false;
         m.act = o.act; m.swr = o.swr;
         if (it == cache.end()) {
@@ -643,7 +684,8 @@ struct InjectedProvider : Provider {
 
 bool params_ok(const orc_params* p) {
     return p && p->block == 8 && p->radius >= 0 && p->radius <= 16 && p->k_max >= 1 &&
-           p->k_max <= 64 && p->w_hist >= 1 && p->n_ss >= 1 && p->lf_offset >= 0 && p->tau_p >= 1.0;
+           p->k_max <= 64 && p->w_hist >= 1 && p->n_ss >= 1 && p->lf_offset >= 0 && p->tau_p >= 1.0 &&
+           (p->search == 0 || p->search == 1) && p->refine >= 0 && 2 * p->radius + p->refine <= 127;
 }
 
 int export_results(const std::vector<orc_frame_rec>& recs, const std::vector<orc_shot_rec>& shots,
@@ -724,7 +766,7 @@ int32_t orc_pair(const uint16_t* I, const uint16_t* J, int32_t w, int32_t h, con
     a.px.assign(I, I + (size_t)w * h);
     b.px.assign(J, J + (size_t)w * h);
     PairOut o;
-    pair_measure(a, b, *p, force_zero_mv != 0, o);
+    pair_measure(a, b, *p, force_zero_mv != 0, p->search == 1, o);
     if (!o.ok) return -1;
     if (mv) std::memcpy(mv, o.mv.data(), o.mv.size());
     if (sad) std::memcpy(sad, o.sad.data(), o.sad.size() * sizeof(int32_t));

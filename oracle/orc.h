@@ -41,6 +41,10 @@ typedef struct {
     double eps;           /* class fraction margin                             */
     double tau_p;         /* pulldown: combed positions' mean v0 ratio          */
     double theta_kf;      /* keyframe threshold on accumulated ACT             */
+    int32_t search;       /* frame-pair motion field: 0 full search over [-R, R]^2;
+                             1 coarse-to-fine: full search on the 2x2-box image one
+                             level coarser, then +-refine around twice that vector */
+    int32_t refine;       /* refinement radius r of the coarse-to-fine search   */
 } orc_params;
 
 /* Per-frame record. */
@@ -102,7 +106,8 @@ int32_t orc_downscale(const uint16_t* src, int32_t w, int32_t h, uint16_t* dst);
 int32_t orc_levels(const void* Y, int32_t W, int32_t H, int64_t pitch_bytes, int32_t bits,
                    const orc_params* p, uint16_t* out, int64_t cap, int64_t* n_out);
 
-/* Pair measure M(I -> J) at one level (I, J: w x h uint16, densely packed).
+/* Pair measure M(I -> J) at one level (I, J: w x h uint16, densely packed),
+ * with the motion field of p->search (the plane pair is taken as a frame pair).
  * mv: B x 2 int8 (dx, dy); sad: B int32 (nullable);
  * ints: Sx, Sy, Sxx, Syy, Sxy, N, A, B, STATIC;  dbl: NCC, SWR, AMM, ACT.
  * force_zero_mv = 1 skips the search and uses d = (0, 0) for every block. */

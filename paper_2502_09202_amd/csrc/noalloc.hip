@@ -120,6 +120,7 @@ extern "C" vsa_status vsa_pair_noalloc(const vsa_params* pp, const void* I, cons
     vsa_params p;
     if (pp) p = *pp; else vsa_default_params(&p);
     if (p.block != 8 || p.radius != 8) return report_error(VSA_E_UNSUPPORTED, "block must be 8 and radius 8");
+    if (p.search != 0) return report_error(VSA_E_UNSUPPORTED, "the no-alloc pair measure takes the full search");
     uint8_t* base = nullptr;
     vsa_status st = scratch_ptr(&base);
     if (st != VSA_OK) return st;

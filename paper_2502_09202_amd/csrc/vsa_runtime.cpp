@@ -172,6 +172,8 @@ vsa_status check_params(const vsa_params& p) {
     if (p.w_hist < 1 || p.w_hist > kMaxHist) return fail(VSA_E_INVAL, "w_hist must be in 1..16");
     if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
     if (!(p.tau_p >= 1.0)) return fail(VSA_E_INVAL, "tau_p must be >= 1");
+    if (p.search != 0 && p.search != 1) return fail(VSA_E_INVAL, "search must be 0 or 1");
+    if (p.search == 1) return fail(VSA_E_UNSUPPORTED, "coarse-to-fine search not built yet");
     return VSA_OK;
 }
 
@@ -600,6 +602,7 @@ void vsa_default_params(vsa_params* p) {
     p->a_static_fx = 64; p->w_hist = 8; p->n_ss = 20;
     p->a0 = 1.0; p->rho_f = 1.5; p->theta_f = 0.05; p->theta_f0 = 1.0; p->rho_d = 1.3; p->theta_d = 0.4;
     p->gamma = 0.5; p->tau_c = 0.65; p->eps = 0.2; p->tau_p = 2.0; p->theta_kf = 3.0;
+    p->search = 0; p->refine = 1;
 }
 
 vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {

@@ -32,7 +32,7 @@ def test_library_exports_every_symbol(vsa):
 
 
 def test_abi_version(vsa):
-    assert vsa.abi_version() == 2
+    assert vsa.abi_version() == 3
 
 
 def test_defaults_match_parameter_file(vsa, params):

@@ -331,7 +331,7 @@ __device__ PairTask plan_task(const StreamDesc& sd, const DecideState& st, int s
         k.result = kResP + K;
     }
     const int dl = k.level - sd.L;
-    k.tiles = me_tiles(sd.wl[dl], sd.hl[dl]);
+    k.tiles = frame_pair_tiles(sd.search, sd.wl[dl], sd.hl[dl]);
     return k;
 }
 

@@ -510,7 +510,7 @@ __device__ __forceinline__ bool resolve8(const StreamDesc* __restrict__ sds, con
                                          int n_jobs, int idx, int tile, bool sparse, int8_t* dbg_mv, Tile8& T) {
     if (idx < 0 || idx >= n_jobs) return false;   // never expected; keeps reads in bounds
     const TileJob& jb = jobs[idx];
-    if (jb.bits != 8) return false;
+    if (jb.bits != 8 || (jb.flags & TF_HIER)) return false;
     if (sparse) {
         const StreamDesc& sd = sds[jb.sid];
         if (!sd.active || sd.epoch != jb.epoch) return false;   // stream closed since planning
@@ -727,6 +727,331 @@ __device__ void me_walk8(const StreamDesc* __restrict__ sds, const TileJob* __re
     }
 }
 
+
+// ---- coarse-to-fine motion field (frame pairs of streams with search = 1) --
+//
+// A tile is 16 x 16 blocks (128 x 128 samples) of I.  Its fine I and a fine
+// J window (rows fy0-17 .., columns fx0-24 .., clamped to the plane) are
+// staged in LDS; the coarse I tile (64 x 64, 8 x 8 coarse blocks) and the
+// coarse J window (80 x 80 around it, clamped to the coarse plane) are box
+// averages of those staged samples, laid out as the full search stages its
+// tiles, so the coarse vectors come from the full search's own lane code.
+// Then every lane takes one fine block: prediction = twice its coarse
+// block's vector (when that coarse block is whole), the best of prediction
+// + e, e in [-1, 1]^2, and the warped moments of the block.
+constexpr int kHT = kHTB * kBlock;       // 128 samples per tile side
+constexpr int kHOX = 24;                 // window column of fine column fx0
+constexpr int kHOY = 17;                 // window row of fine row fy0
+constexpr int kHJW = 176;                // window row length (samples)
+constexpr int kHJH = 162;                // window rows
+static_assert(kHOX % 8 == 0 && kHJW % 8 == 0, "window chunks are 8 samples");
+// refine reads up to column 8*15 + kHOX + 16 + 11 and row 8*15 + 7 + 17 + kHOY
+static_assert(8 * 15 + kHOX + 16 + 11 < kHJW && 8 * 15 + 7 + 17 + kHOY < kHJH, "window too small");
+// the coarse window's fine sources: columns fx0-16 .. fx0+143, rows fy0-16 .. fy0+143
+static_assert(kHOX - 16 >= 0 && kHOX + 143 < kHJW && kHOY - 16 >= 0 && kHOY + 143 < kHJH, "window too small");
+
+template <typename T>
+struct HierLds {
+    uint8_t fI[kHT * kHT * sizeof(T)];
+    uint8_t fJ[kHJH * kHJW * sizeof(T)];
+    uint8_t cI[64 * 64 * sizeof(T)];
+    uint8_t cJ[kJRows * kJW8 * sizeof(T)];
+    int32_t cmv[64];                      // coarse vector per coarse block: dx & 0xff | (dy & 0xff) << 8
+    int64_t red[4 * 6];
+};
+
+template <typename T>
+__device__ __forceinline__ T lds_at(const uint8_t* base, int idx) {
+    return reinterpret_cast<const T*>(base)[idx];
+}
+
+template <typename T>
+__device__ void hier_stage(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) {
+    constexpr int B = (int)sizeof(T);
+    const int tid = threadIdx.x;
+    // fine I: 128 rows of 128 samples in 16-byte chunks; a chunk past the row
+    // pitch is not read (its blocks are not whole), rows past the plane are
+    // clamped
+    constexpr int ICH = kHT * B / 16;
+    for (int i = tid; i < kHT * ICH; i += kMEThreads) {
+        const int r = i / ICH, c = i - (i / ICH) * ICH;
+        const int gy = min(fy0 + r, jb.h - 1);
+        const int gx = fx0 + c * (16 / B);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gx < jb.pitch) v = gload4(jb.I + ((int64_t)gy * jb.pitch + gx) * B);
+        reinterpret_cast<uint4*>(S.fI)[i] = v;
+    }
+    // fine J window in 8-sample chunks, clamped to the plane
+    constexpr int JCH = kHJW / 8;
+    const int x0 = fx0 - kHOX, y0 = fy0 - kHOY;
+    for (int i = tid; i < kHJH * JCH; i += kMEThreads) {
+        const int r = i / JCH, c = i - (i / JCH) * JCH;
+        const int gy = clampi(y0 + r, 0, jb.h - 1);
+        const int gx = x0 + 8 * c;
+        const uint8_t* row = jb.J + (int64_t)gy * jb.pitch * B;
+        T* dst = reinterpret_cast<T*>(S.fJ) + r * kHJW + 8 * c;
+        if (gx >= 0 && gx + 8 <= jb.w) {
+            if constexpr (B == 1) {
+                *reinterpret_cast<uint2*>(dst) = gload2(row + gx);
+            } else {
+                *reinterpret_cast<uint4*>(dst) = gload4(row + 2 * gx);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dst[k] = gload<T>(row + clampi(gx + k, 0, jb.w - 1) * B);
+        }
+    }
+}
+
+// Coarse tile and window from the staged fine samples (2 x 2 box, rounding
+// half up: the pyramid's own step, so they equal the next level's planes).
+template <typename T>
+__device__ void hier_coarse(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) {
+    const int tid = threadIdx.x;
+    const T* fI = reinterpret_cast<const T*>(S.fI);
+    const T* fJ = reinterpret_cast<const T*>(S.fJ);
+    T* cI = reinterpret_cast<T*>(S.cI);
+    T* cJ = reinterpret_cast<T*>(S.cJ);
+    for (int i = tid; i < 64 * 64; i += kMEThreads) {
+        const int y = i >> 6, x = i & 63;
+        const T* a = fI + (2 * y) * kHT + 2 * x;
+        cI[i] = (T)(((int)a[0] + a[1] + a[kHT] + a[kHT + 1] + 2) >> 2);
+    }
+    const int wc = jb.w / 2, hc = jb.h / 2;
+    const int cx0 = fx0 / 2 - 8, cy0 = fy0 / 2 - 8;
+    for (int i = tid; i < kJRows * kJW8; i += kMEThreads) {
+        const int r = i / kJW8, c = i - (i / kJW8) * kJW8;
+        const int cx = clampi(cx0 + c, 0, wc - 1), cy = clampi(cy0 + r, 0, hc - 1);
+        const T* a = fJ + (2 * cy - fy0 + kHOY) * kHJW + (2 * cx - fx0 + kHOX);
+        cJ[i] = (T)(((int)a[0] + a[1] + a[kHJW] + a[kHJW + 1] + 2) >> 2);
+    }
+}
+
+// Key of refinement candidate e: SAD << 16 | code, the code increasing in
+// (|e|^2, ey, ex).
+__device__ __forceinline__ uint32_t hier_key(uint32_t sad, int ex, int ey) {
+    return (sad << 16) | (uint32_t)(((ex * ex + ey * ey) * 3 + ey + 1) * 3 + ex + 1);
+}
+
+// 8-bit refinement of fine block (bx, by) around prediction (px, py), px
+// and py even: v_qsad_pk_u16_u8 over the two dx groups q-4 .. q-1 and
+// q .. q+3 with q = px rounded down to a multiple of 4, which hold the three
+// candidates px-1 .. px+1; each J row is read once for the three ey.
+__device__ __forceinline__ uint32_t hier_refine8(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int px,
+                                                 int py) {
+    uint32_t r0[8], r1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint2 v = *reinterpret_cast<const uint2*>(fI + (8 * by + j) * kHT + 8 * bx);
+        r0[j] = v.x;
+        r1[j] = v.y;
+    }
+    const int q4 = px & ~3;
+    const uint8_t* jb = fJ + (8 * by + py + kHOY - 1) * kHJW + (8 * bx + kHOX + q4 - 4);
+    uint64_t acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+    for (int u = 0; u < 10; ++u) {           // J row u holds block row j = u - 1 - ey for ey = -1, 0, 1
+        const uint32_t* wp = reinterpret_cast<const uint32_t*>(jb + u * kHJW);
+        const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
+        const uint64_t w01 = pk64(w0, w1), w12 = pk64(w1, w2), w23 = pk64(w2, w3);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int j = u - e;
+            if (j < 0 || j > 7) continue;
+            acc[e][0] = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], acc[e][0]);
+            acc[e][0] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], acc[e][0]);
+            acc[e][1] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], acc[e][1]);
+            acc[e][1] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], acc[e][1]);
+        }
+    }
+    const bool h2 = (px - q4) != 0;          // px = q4 or q4 + 2
+    uint32_t best = 0xffffffffu;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const uint64_t a0 = acc[e][0], a1 = acc[e][1];
+        const uint32_t sm = h2 ? (uint32_t)(a1 >> 16) & 0xffffu : (uint32_t)(a0 >> 48);
+        const uint32_t s0 = h2 ? (uint32_t)(a1 >> 32) & 0xffffu : (uint32_t)a1 & 0xffffu;
+        const uint32_t sp = h2 ? (uint32_t)(a1 >> 48) : (uint32_t)(a1 >> 16) & 0xffffu;
+        best = min(best, min(hier_key(sm, -1, e - 1), min(hier_key(s0, 0, e - 1), hier_key(sp, 1, e - 1))));
+    }
+    return best;
+}
+
+// 10-bit refinement: the ten J rows' ten samples each, absolute differences
+// in registers.
+__device__ __forceinline__ uint32_t hier_refine16(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int px,
+                                                  int py) {
+    const uint16_t* I = reinterpret_cast<const uint16_t*>(fI) + (8 * by) * kHT + 8 * bx;
+    const uint16_t* J = reinterpret_cast<const uint16_t*>(fJ) + (8 * by + py + kHOY - 1) * kHJW + (8 * bx + px + kHOX - 1);
+    uint32_t sad[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int u = 0; u < 10; ++u) {
+        int jr[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) jr[k] = J[u * kHJW + k];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int j = u - e;
+            if (j < 0 || j > 7) continue;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int x = I[j * kHT + i];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) sad[e][f] += (uint32_t)abs(x - jr[i + f]);
+            }
+        }
+    }
+    uint32_t best = 0xffffffffu;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) best = min(best, hier_key(sad[e][f], f - 1, e - 1));
+    return best;
+}
+
+// Moments of fine block (bx, by) against J warped by (dx, dy).
+template <typename T>
+__device__ __forceinline__ void hier_moments(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int dx, int dy,
+                                             int64_t m[5]) {
+    int32_t s[5] = {0, 0, 0, 0, 0};
+    if constexpr (sizeof(T) == 1) {
+        const int col = 8 * bx + kHOX + dx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint2 xv = *reinterpret_cast<const uint2*>(fI + (8 * by + j) * kHT + 8 * bx);
+            const uint8_t* jr = fJ + (8 * by + j + dy + kHOY) * kHJW + (col & ~3);
+            const uint32_t w0 = *reinterpret_cast<const uint32_t*>(jr);
+            const uint32_t w1 = *reinterpret_cast<const uint32_t*>(jr + 4);
+            const uint32_t w2 = *reinterpret_cast<const uint32_t*>(jr + 8);
+            const int sh = col & 3;
+            const uint32_t y0 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            const uint32_t y1 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+            s[0] += (int32_t)(__builtin_amdgcn_sad_u8(xv.x, 0u, 0u) + __builtin_amdgcn_sad_u8(xv.y, 0u, 0u));
+            s[1] += (int32_t)(__builtin_amdgcn_sad_u8(y0, 0u, 0u) + __builtin_amdgcn_sad_u8(y1, 0u, 0u));
+            s[2] += (int32_t)__builtin_amdgcn_udot4(xv.y, xv.y, __builtin_amdgcn_udot4(xv.x, xv.x, 0u, false), false);
+            s[3] += (int32_t)__builtin_amdgcn_udot4(y1, y1, __builtin_amdgcn_udot4(y0, y0, 0u, false), false);
+            s[4] += (int32_t)__builtin_amdgcn_udot4(xv.y, y1, __builtin_amdgcn_udot4(xv.x, y0, 0u, false), false);
+        }
+    } else {
+        const uint16_t* I = reinterpret_cast<const uint16_t*>(fI) + (8 * by) * kHT + 8 * bx;
+        const uint16_t* J = reinterpret_cast<const uint16_t*>(fJ) + (8 * by + dy + kHOY) * kHJW + (8 * bx + dx + kHOX);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int32_t x = I[j * kHT + i], y = J[j * kHJW + i];
+                s[0] += x; s[1] += y; s[2] += x * x; s[3] += y * y; s[4] += x * y;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) m[k] = s[k];
+}
+
+// One coarse-to-fine tile: the vectors of its fine blocks, their moments and
+// A, one partial per tile.
+template <typename T>
+__device__ void me_tile_hier(const TileJob& jb, int local, TilePartial* part_out, int8_t* mv_out, int32_t* sad_out,
+                             HierLds<T>& S) {
+    const int tid = threadIdx.x;
+    const int tx = local % jb.tiles_x, ty = local / jb.tiles_x;
+    const int fx0 = tx * kHT, fy0 = ty * kHT;
+    const int nbx = jb.w / kBlock, nby = jb.h / kBlock;
+    const int nbxc = (jb.w / 2) / kBlock, nbyc = (jb.h / 2) / kBlock;
+    const bool zero = (jb.flags & TF_ZERO_MV) != 0;
+    // the coarse stage runs when the coarse plane has a whole block (else every
+    // prediction is (0, 0))
+    const bool coarse = !zero && nbxc > 0 && nbyc > 0;
+    hier_stage<T>(jb, fx0, fy0, S);
+    __syncthreads();
+    if (coarse) {
+        hier_coarse<T>(jb, fx0, fy0, S);
+        __syncthreads();
+        // coarse full search: four lanes per coarse block, as in a full-search tile
+        const int b = tid >> 2, q = tid & 3;
+        const int cbx = b & 7, cby = b >> 3;
+        const bool cvalid = (8 * tx + cbx < nbxc) && (8 * ty + cby < nbyc);
+        uint32_t key = 0xffffffffu;
+        if (cvalid) {
+            if constexpr (sizeof(T) == 1) key = search8p(S.cI, S.cJ, cbx, cby, q);
+            else key = search16(S.cI, S.cJ, cbx, cby, q);
+        }
+        key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
+        key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
+        if (q == 0) {
+            int v = 0;
+            if (cvalid) {
+                const uint32_t cell = (key & 0xffffu) % (uint32_t)(kCand * kCand);   // (dy+8)*17 + dx+8
+                const int dx = (int)(cell % kCand) - kRadius, dy = (int)(cell / kCand) - kRadius;
+                v = (dx & 0xff) | ((dy & 0xff) << 8);
+            }
+            S.cmv[b] = cvalid ? v : 0;
+        }
+        __syncthreads();
+    }
+    // refinement and moments: one lane per fine block
+    const int bx = tid & (kHTB - 1), by = tid / kHTB;
+    const bool valid = (kHTB * tx + bx < nbx) && (kHTB * ty + by < nby);
+    int dx = 0, dy = 0;
+    uint32_t best = 0;
+    if (valid && !zero) {
+        int px = 0, py = 0;
+        if (coarse && kHTB / 2 * tx + (bx >> 1) < nbxc && kHTB / 2 * ty + (by >> 1) < nbyc) {
+            const int v = S.cmv[(by >> 1) * 8 + (bx >> 1)];
+            px = 2 * (int)(int8_t)(v & 0xff);
+            py = 2 * (int)(int8_t)((v >> 8) & 0xff);
+        }
+        if constexpr (sizeof(T) == 1) best = hier_refine8(S.fI, S.fJ, bx, by, px, py);
+        else best = hier_refine16(S.fI, S.fJ, bx, by, px, py);
+        const int code = (int)(best & 0xffffu) % 9;      // (ey+1)*3 + ex+1
+        dx = px + code % 3 - 1;
+        dy = py + code / 3 - 1;
+    }
+    int64_t m[5] = {0, 0, 0, 0, 0};
+    int32_t a = 0;
+    if (valid) {
+        hier_moments<T>(S.fI, S.fJ, bx, by, dx, dy, m);
+        a = amm_fx(dx * dx + dy * dy);
+    }
+    const int blk = (kHTB * ty + by) * nbx + (kHTB * tx + bx);
+    if (valid && mv_out) {
+        mv_out[2 * blk] = (int8_t)dx;
+        mv_out[2 * blk + 1] = (int8_t)dy;
+    }
+    if (valid && sad_out) {
+        if (zero) {
+            int32_t s0 = 0;
+            const T* I = reinterpret_cast<const T*>(S.fI) + (8 * by) * kHT + 8 * bx;
+            const T* J = reinterpret_cast<const T*>(S.fJ) + (8 * by + kHOY) * kHJW + (8 * bx + kHOX);
+            for (int j = 0; j < 8; ++j)
+                for (int i = 0; i < 8; ++i) s0 += abs((int)I[j * kHT + i] - (int)J[j * kHJW + i]);
+            sad_out[blk] = s0;
+        } else {
+            sad_out[blk] = (int32_t)(best >> 16);
+        }
+    }
+    // one lane per block: 64 blocks per wave, so the sums take 64 bits
+    const int wave = tid >> 6;
+    int64_t w[6];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = wave_sum64(m[k]);
+    w[5] = wave_sum64((int64_t)a);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) S.red[wave * 6 + k] = w[k];
+    __syncthreads();
+    if (tid == 0) {
+        TilePartial p;
+        p.sx = S.red[0] + S.red[6] + S.red[12] + S.red[18];
+        p.sy = S.red[1] + S.red[7] + S.red[13] + S.red[19];
+        p.sxx = S.red[2] + S.red[8] + S.red[14] + S.red[20];
+        p.syy = S.red[3] + S.red[9] + S.red[15] + S.red[21];
+        p.sxy = S.red[4] + S.red[10] + S.red[16] + S.red[22];
+        p.a = S.red[5] + S.red[11] + S.red[17] + S.red[23];
+        store_partial(part_out, p);
+    }
+    __syncthreads();   // LDS is reused by the next tile
+}
+
 }  // namespace
 
 // Persistent grid over the tiles of the consecutive-pair list (host-built) and
@@ -783,7 +1108,7 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
             if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
             const TileJob& jb = jobs[idx];
             const int local = tile - jb.tile_prefix;
-            if (jb.bits != 10) continue;
+            if (jb.bits != 10 || (jb.flags & TF_HIER)) continue;
             if (sparse) {
                 const StreamDesc& sd = sds[jb.sid];
                 if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
@@ -791,6 +1116,47 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
             const bool dbg = (jb.flags & TF_DEBUG) != 0;
             me_tile<T>(jb, local, partials + tile, dbg ? dbg_mv : jb.mv, dbg ? dbg_sad : nullptr, sI, sJ, red);
         }
+    }
+}
+
+// Persistent grid over the coarse-to-fine tiles of a tile list (the same
+// lists, maps and jobs as k_me; tiles of full-search pairs and of the other
+// sample width are skipped).  One workgroup of 256 lanes per 16 x 16-block
+// tile, the XCD slicing of k_me.
+template <typename T>
+__global__ void __launch_bounds__(kMEThreads) k_me_hier(const StreamDesc* __restrict__ sds,
+                                                        const TileJob* __restrict__ jobs, int32_t n_jobs,
+                                                        const int32_t* __restrict__ map, int32_t n_tiles,
+                                                        const DeviceCursors* __restrict__ cur, int32_t par_prev,
+                                                        TilePartial* __restrict__ partials, int8_t* dbg_mv,
+                                                        int32_t* dbg_sad) {
+    __shared__ __attribute__((aligned(16))) HierLds<T> S;
+    const bool sparse = cur != nullptr;
+    if (sparse) __builtin_amdgcn_s_setprio(2);
+    const int total = sparse ? tt_tiles(cur->sparse_tt[par_prev].v) : n_tiles;
+    int lo = 0, hi = total, first = blockIdx.x, stride = gridDim.x;
+    if (gridDim.x >= kXcd) {
+        const int groups = gridDim.x / kXcd;
+        const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+        if (j >= groups) return;
+        const int per = (total + kXcd - 1) / kXcd;
+        lo = x * per;
+        hi = min(total, lo + per);
+        first = lo + j;
+        stride = groups;
+    }
+    for (int tile = first; tile < hi; tile += stride) {
+        const int idx = map[tile];
+        if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
+        const TileJob& jb = jobs[idx];
+        if (jb.bits != (sizeof(T) == 1 ? 8 : 10) || !(jb.flags & TF_HIER)) continue;
+        if (sparse) {
+            const StreamDesc& sd = sds[jb.sid];
+            if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
+        }
+        const bool dbg = (jb.flags & TF_DEBUG) != 0;
+        me_tile_hier<T>(jb, tile - jb.tile_prefix, partials + tile, dbg ? dbg_mv : jb.mv, dbg ? dbg_sad : nullptr,
+                        S);
     }
 }
 
@@ -898,6 +1264,41 @@ hipError_t launch_me(int bits, const StreamDesc* sds, const TileJob* jobs, int32
         else
             hipLaunchKernelGGL(k_me<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map, n_tiles,
                                cur, par_prev, partials, dbg_mv, dbg_sad, clear_tt);
+    }
+    return hipGetLastError();
+}
+
+int me_hier_max_wgs_per_cu(int bits) {
+    static int cached[2] = {0, 0};
+    int& c = cached[bits == 8 ? 0 : 1];
+    if (c == 0) {
+        int n = 0;
+        const hipError_t e = bits == 8
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_me_hier<uint8_t>, kMEThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_me_hier<uint16_t>, kMEThreads, 0);
+        c = (e == hipSuccess && n > 0) ? n : 1;
+    }
+    return c;
+}
+
+hipError_t launch_me_hier(int bits, const StreamDesc* sds, const TileJob* jobs, int32_t n_jobs, const int32_t* map,
+                          int32_t n_tiles, const DeviceCursors* cur, int32_t par_prev, TilePartial* partials,
+                          int8_t* dbg_mv, int32_t* dbg_sad, int grid, hipStream_t s, LaunchTiming tm) {
+    if (grid <= 0) return hipSuccess;
+    if (bits == 8) {
+        if (tm.any())
+            hipExtLaunchKernelGGL(k_me_hier<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds,
+                                  jobs, n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad);
+        else
+            hipLaunchKernelGGL(k_me_hier<uint8_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map,
+                               n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad);
+    } else {
+        if (tm.any())
+            hipExtLaunchKernelGGL(k_me_hier<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, tm.start, tm.stop, 0, sds,
+                                  jobs, n_jobs, map, n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad);
+        else
+            hipLaunchKernelGGL(k_me_hier<uint16_t>, dim3(grid), dim3(kMEThreads), 0, s, sds, jobs, n_jobs, map,
+                               n_tiles, cur, par_prev, partials, dbg_mv, dbg_sad);
     }
     return hipGetLastError();
 }

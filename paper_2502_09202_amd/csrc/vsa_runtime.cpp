@@ -52,6 +52,10 @@ int me_max_wgs_per_cu(int bits);
 hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
                      const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                      LaunchTiming = {});
+int me_hier_max_wgs_per_cu(int bits);
+hipError_t launch_me_hier(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
+                          const DeviceCursors*, int32_t, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
+                          LaunchTiming = {});
 hipError_t launch_finish(const StreamDesc*, const PairTask*, int32_t, int32_t, const PairTask*,
                          DeviceCursors*, const TilePartial*, PairResult*, const DecideParams&, int64_t*,
                          double*, int grid, int32_t par_prev, hipStream_t);
@@ -173,7 +177,7 @@ vsa_status check_params(const vsa_params& p) {
     if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
     if (!(p.tau_p >= 1.0)) return fail(VSA_E_INVAL, "tau_p must be >= 1");
     if (p.search != 0 && p.search != 1) return fail(VSA_E_INVAL, "search must be 0 or 1");
-    if (p.search == 1) return fail(VSA_E_UNSUPPORTED, "coarse-to-fine search not built yet");
+    if (p.search == 1 && p.refine != 1) return fail(VSA_E_UNSUPPORTED, "the coarse-to-fine search refines by 1");
     return VSA_OK;
 }
 
@@ -243,7 +247,7 @@ int max_sparse_tiles(const StreamDesc& sd) {
     for (int K = 1; K <= sd.k_max + 1; ++K) {
         const int l = std::min(sd.L + ceil_log2(K), sd.Lcap);
         const int d = l - sd.L;
-        n += (K >= 2 ? 2 : 1) * me_tiles(sd.wl[d], sd.hl[d]);
+        n += (K >= 2 ? 2 : 1) * frame_pair_tiles(sd.search, sd.wl[d], sd.hl[d]);
     }
     return n;
 }
@@ -765,6 +769,7 @@ static vsa_status prepare_stream(const vsa_engine* e, const vsa_stream_desc* d, 
     vsa_status st = make_geo(d->width, d->height, e->params, kmax, g);
     if (st != VSA_OK) return st;
     layout(g, d->width, d->height, d->bit_depth, kmax, sd);
+    sd.search = e->params.search;
     st = check_exact_sums(sd);
     if (st != VSA_OK) return st;
     staging_pitch = round_up((int64_t)d->width * (d->bit_depth == 8 ? 1 : 2), 256);
@@ -779,7 +784,7 @@ uint64_t vsa_stream_footprint(const vsa_engine* e, const vsa_stream_desc* d) {
     int64_t sp;
     uint64_t bytes;
     if (prepare_stream(e, d, sd, g, sp, bytes) != VSA_OK) return 0;
-    return bytes + (uint64_t)(me_tiles(sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
+    return bytes + (uint64_t)(frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
 }
 
 vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid) {
@@ -795,7 +800,7 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     int slot = -1;
     for (int i = 0; i < e->max_streams; ++i)
         if (!e->streams[i].open) { slot = i; break; }
-    const uint64_t part = (uint64_t)(me_tiles(sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
+    const uint64_t part = (uint64_t)(frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
     if (slot < 0 || e->used + bytes + part > e->budget) {
         e->counters[3] += 1;
         return fail(VSA_E_ADMIT, slot < 0 ? "no free stream slot" : "HBM budget exhausted");
@@ -828,7 +833,7 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     s.staging_pitch = sp;
     s.staging_dev[0] = mem + off;
     s.staging_dev[1] = mem + off + round_up(sp * sd.H, 256);
-    s.consec_tiles = me_tiles(sd.wl[0], sd.hl[0]);
+    s.consec_tiles = frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]);
     s.sparse_tiles_max = max_sparse_tiles(sd);
     s.epoch = epoch;
     e->used += s.bytes;
@@ -1225,6 +1230,17 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         return g;
     };
     const int grid_c = me_grid(consec_tiles, wgs.consec), grid_s = me_grid(sparse_max, wgs.sparse);
+    // coarse-to-fine frame pairs: their own kernel, within its occupancy
+    const bool hier = e->params.search != 0;
+    const int mh_cap = std::min(e->has8 ? me_hier_max_wgs_per_cu(8) : 64, e->has10 ? me_hier_max_wgs_per_cu(10) : 64);
+    auto mh_grid = [&](int64_t tiles, int w) {
+        w = std::max(1, std::min(w, mh_cap));
+        int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)w * e->cus);
+        if (g >= 8) g -= g % 8;
+        return g;
+    };
+    const int grid_hc = hier ? mh_grid(consec_tiles, wgs.consec) : 0;
+    const int grid_hs = hier ? mh_grid(sparse_max, wgs.sparse) : 0;
     // consecutive partials alternate by step parity; sparse task lists, jobs
     // and maps too (read the previous step's, write the next)
     TilePartial* cpart = e->d_partials + (size_t)par * e->partials_cap;
@@ -1237,13 +1253,21 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
     int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
     // one launch per sample width that an open stream has
-    if (consec_tiles > 0) {
+    if (consec_tiles > 0 && !hier) {
         if (e->has8)
             HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
                             grid_c, Cs, timing(1, true, true)), "motion search launch");
         if (e->has10)
             HIPCK(launch_me(10, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
                             grid_c, Cs, timing(2, true, true)), "motion search launch");
+    } else if (consec_tiles > 0) {
+        // every consecutive pair is a frame pair: the coarse-to-fine kernel alone
+        if (e->has8)
+            HIPCK(launch_me_hier(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, cpart, nullptr, nullptr,
+                                 grid_hc, Cs, timing(1, true, true)), "motion search launch");
+        if (e->has10)
+            HIPCK(launch_me_hier(10, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, cpart, nullptr, nullptr,
+                                 grid_hc, Cs, timing(2, true, true)), "motion search launch");
     }
     HIPCK(hipEventRecord(e->ev_c[slot_s], Cs), "event");
     // the first sparse launch also clears the counter this step's decisions
@@ -1251,10 +1275,19 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     const bool sparse8 = e->has8 || !e->has10;
     if (sparse8)
         HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart,
-                        nullptr, nullptr, grid_s, A, timing(3, true, !e->has10)), "motion search launch");
+                        nullptr, nullptr, grid_s, A, timing(3, true, !e->has10 && !hier)), "motion search launch");
     if (e->has10)
         HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, !sparse8, spart,
-                        nullptr, nullptr, grid_s, A, timing(3, !sparse8, true)), "motion search launch");
+                        nullptr, nullptr, grid_s, A, timing(3, !sparse8, !hier)), "motion search launch");
+    if (hier) {
+        // the planned deep-check pairs are frame pairs (the fields keep the full search)
+        if (sparse8)
+            HIPCK(launch_me_hier(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, spart,
+                                 nullptr, nullptr, grid_hs, A, timing(3, false, !e->has10)), "motion search launch");
+        if (e->has10)
+            HIPCK(launch_me_hier(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, spart,
+                                 nullptr, nullptr, grid_hs, A, timing(3, false, true)), "motion search launch");
+    }
     HIPCK(hipStreamWaitEvent(A, e->ev_c[slot_s], 0), "wait");
     if (!e->no_intensity) HIPCK(hipStreamWaitEvent(A, e->ev_h[slot_s], 0), "wait");
     const int sn = (int)(e->step_no % kSnap);
@@ -1543,6 +1576,7 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     sd.wf = w; sd.hf = h; sd.pf = sd.pl[0]; sd.offU = sd.offD = 0;
     sd.slot_bytes = round_up((int64_t)sd.pl[0] * h * b, 256);
     sd.B_L = (w / 8) * (h / 8);
+    sd.search = p.search;
     std::vector<uint8_t> host(2 * sd.slot_bytes, 0);
     for (int s = 0; s < 2; ++s) {
         const uint16_t* src = s == 0 ? I : J;
@@ -1556,7 +1590,7 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     PairTask t;
     std::memset(&t, 0, sizeof t);
     t.sid = 0; t.kind = MK_CONSEC; t.ref = 0; t.oth = 1; t.level = 0; t.result = -1;
-    t.tiles = me_tiles(w, h); t.tile_prefix = 0;
+    t.tiles = frame_pair_tiles(p.search, w, h); t.tile_prefix = 0;
     t.flags = TF_DEBUG | (force_zero_mv ? TF_ZERO_MV : 0);
     uint8_t *ring = nullptr, *dsd = nullptr, *dt = nullptr, *djob = nullptr;
     int32_t* dmap = nullptr;
@@ -1587,9 +1621,12 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     const TileJob job = make_tile_job(sd, t, nullptr);
     if (err == hipSuccess) err = hipMemcpy(djob, &job, sizeof job, hipMemcpyHostToDevice);
     const DecideParams dp = decide_params(p, 0);
-    if (err == hipSuccess)
+    if (err == hipSuccess && !p.search)
         err = launch_me(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<TileJob*>(djob), 1, dmap, t.tiles,
                         nullptr, 0, false, part, dmv, dsad, std::min(t.tiles, 1024), nullptr);
+    if (err == hipSuccess && p.search)
+        err = launch_me_hier(bits, reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<TileJob*>(djob), 1, dmap,
+                             t.tiles, nullptr, 0, part, dmv, dsad, std::min(t.tiles, 1024), nullptr);
     if (err == hipSuccess)
         err = launch_finish(reinterpret_cast<StreamDesc*>(dsd), reinterpret_cast<PairTask*>(dt), 1, t.tiles,
                             nullptr, nullptr, part, nullptr, dp, dints, ddbl, 1, 0, nullptr);
@@ -1751,6 +1788,7 @@ struct vsa_clip {
     int pair_tiles = 0;            // motion-search tiles of a consecutive pair
     int sparse_tiles = 0;          // most tiles one round's sparse pairs can have
     int grid_c = 0, grid_s = 0;    // persistent motion-search grids
+    int grid_hc = 0, grid_hs = 0;  // and those of the coarse-to-fine kernel (search = 1)
     hipStream_t s = nullptr;       // decisions (D)
     hipStream_t sp = nullptr;      // ingest (P)
     hipEvent_t ev_p[2] = {};       // P has finished the chunk of that parity
@@ -1811,6 +1849,10 @@ vsa_status clip_decide(vsa_clip* c, const StepStream* d_entry) {
     HIPCK(launch_me(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, spart, nullptr,
                     nullptr, c->grid_s, c->s),
           "motion search launch");
+    if (c->sd.search)   // the deep-check pairs among them (frame pairs) take the coarse-to-fine kernel
+        HIPCK(launch_me_hier(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, spart,
+                             nullptr, nullptr, c->grid_hs, c->s),
+              "motion search launch");
     HIPCK(launch_finish_decide(c->d_sds, c->d_state, d_entry, 1, c->dp, c->d_part, spart, sp_prev, sp_next, c->d_cur,
                                c->d_out_frames, c->out_cap, c->d_out_shots, c->out_cap, c->d_log, c->log_cap, c->d_closed, par,
                                c->d_snap + par, sj_next, sm_next, c->s),
@@ -1919,11 +1961,16 @@ vsa_status clip_ingest(vsa_clip* c, const ClipSource& in, int ch, int* n_cons_ou
           "pyramid launch");
     if (!c->no_intensity) HIPCK(launch_intensity(c->d_sds, d_steps, d_k1, n, c->sp), "intensity launch");
     if (ctiles > 0) {
-        int gc = std::min(c->grid_c, ctiles);
+        int gc = std::min(sd.search ? c->grid_hc : c->grid_c, ctiles);
         if (gc >= 8) gc -= gc % 8;
-        HIPCK(launch_me(sd.bits, c->d_sds, cjobs, C, cmap, ctiles, nullptr, 0, false, cpart, nullptr, nullptr, gc,
-                        c->sp),
-              "motion search launch");
+        if (sd.search)
+            HIPCK(launch_me_hier(sd.bits, c->d_sds, cjobs, C, cmap, ctiles, nullptr, 0, cpart, nullptr, nullptr, gc,
+                                 c->sp),
+                  "motion search launch");
+        else
+            HIPCK(launch_me(sd.bits, c->d_sds, cjobs, C, cmap, ctiles, nullptr, 0, false, cpart, nullptr, nullptr, gc,
+                            c->sp),
+                  "motion search launch");
     }
     HIPCK(hipEventRecord(c->ev_p[q], c->sp), "event");
     *n_cons_out = n_cons;
@@ -1975,6 +2022,7 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     if (st != VSA_OK) return st;
     StreamDesc sd;
     layout(g, cfg->width, cfg->height, cfg->bit_depth, kmax, sd);
+    sd.search = p.search;
     st = check_exact_sums(sd);
     if (st != VSA_OK) return st;
     // the chunk being decided, the chunk being ingested beside it, the deep
@@ -1989,7 +2037,7 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     c->no_intensity = cfg->no_intensity != 0;
     c->C = C;
     c->pyr_tiles = pyramid_tiles(sd);
-    c->pair_tiles = me_tiles(sd.wl[0], sd.hl[0]);
+    c->pair_tiles = frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]);
     // one round's sparse pairs: a deep check, or the fields of an analysed
     // frame and of up to kMaxSpec frames after it
     c->sparse_tiles = std::max(max_sparse_tiles(sd), 3 * (1 + kMaxSpec) * me_tiles(sd.wf, sd.hf));
@@ -2004,6 +2052,17 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     };
     c->grid_c = grid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2);
     c->grid_s = grid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
+    if (sd.search) {
+        const int mh_cap = me_hier_max_wgs_per_cu(sd.bits);
+        auto hgrid = [&](int64_t tiles, int w) {
+            w = std::max(1, std::min(w, mh_cap));
+            int gsz = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)w * cus);
+            if (gsz >= 8) gsz -= gsz % 8;
+            return gsz;
+        };
+        c->grid_hc = hgrid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2);
+        c->grid_hs = hgrid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
+    }
     HIPCK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking), "hipStreamCreate");
     HIPCK(hipStreamCreateWithFlags(&c->sp, hipStreamNonBlocking), "hipStreamCreate");
     for (hipEvent_t& ev : c->ev_p) HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");

@@ -197,13 +197,16 @@ def run_mix(vsa, clips, params, steps, warmup, torch):
     return pushed / dt, pushed, {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}
 
 
-def run_stress(vsa, params, B, frames_per_stream, seg, torch):
+def run_stress(vsa, params, B, frames_per_stream, seg, torch,
+               configs=(("sparse", False, 0), ("dense", True, 0))):
     """The 4K 10-bit 50i clip (its full length) cut into B consecutive pieces,
     piece s read by stream s in order, in two engines at once (sparse and dense
     schedule).  Each segment of `seg` steps is rendered on the device first,
     untimed; each engine's steps over it are timed between device
     synchronisations.  Returns, per schedule, frames/s, AD per frame and the
-    per-kernel times, and the render time."""
+    per-kernel times, and the render time.  Each config is (name, dense,
+    search); per config the result is frames/s, 8 x 8 blocks searched per
+    frame and the per-kernel times."""
     import synth
     from synth.device import DeviceRenderer
     T = B * frames_per_stream
@@ -212,17 +215,17 @@ def run_stress(vsa, params, B, frames_per_stream, seg, torch):
     rends = [DeviceRenderer(spec, "cuda:0") for _ in range(B)]
     buf = torch.empty((B, seg, H, W), dtype=torch.int16, device="cuda:0")
     engines = {}
-    for dense in (False, True):
-        e = vsa.Engine(device=0, max_streams=B, params=params, profile=2,
+    for name, dense, search in configs:
+        e = vsa.Engine(device=0, max_streams=B, params=dict(params, search=search), profile=2,
                        schedule=vsa.SCHEDULE_DENSE if dense else vsa.SCHEDULE_SPARSE)
-        engines[dense] = (e, np.array([e.stream_open(W, H, 10) for _ in range(B)], np.int32))
+        engines[name] = (e, np.array([e.stream_open(W, H, 10) for _ in range(B)], np.int32))
     pitches = np.full(B, W * 2, np.int64)
     plane = H * W * 2
     base = np.array([buf[b].data_ptr() for b in range(B)], np.uint64)
     c0 = {d: e.counters() for d, (e, _) in engines.items()}
     for e, _ in engines.values():
         e.kernel_times(reset=True)
-    busy = {False: 0.0, True: 0.0}
+    busy = {name: 0.0 for name in engines}
     render_s = 0.0
     done = 0
     while done < frames_per_stream:
@@ -232,7 +235,7 @@ def run_stress(vsa, params, B, frames_per_stream, seg, torch):
             rends[b].render_into(buf[b, :n], b * frames_per_stream + done)
         torch.cuda.synchronize()
         render_s += time.perf_counter() - t1
-        for dense, (e, sids) in engines.items():
+        for name, (e, sids) in engines.items():
             e.sync()
             t1 = time.perf_counter()
             for j in range(n):
@@ -244,16 +247,16 @@ def run_stress(vsa, params, B, frames_per_stream, seg, torch):
                         e.stream_end(int(sid))
                 e.step()
             e.sync()
-            busy[dense] += time.perf_counter() - t1
+            busy[name] += time.perf_counter() - t1
         done += n
     out = {}
-    for dense, (e, sids) in engines.items():
+    for name, (e, sids) in engines.items():
         c1 = e.counters()
         kt = e.kernel_times()
-        blocks = (c1["consecutive_blocks"] - c0[dense]["consecutive_blocks"]) + \
-                 (c1["sparse_blocks"] - c0[dense]["sparse_blocks"])
-        out[dense] = (B * frames_per_stream / busy[dense], blocks * 289 * 64 / (B * frames_per_stream),
-                      {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]})
+        blocks = (c1["consecutive_blocks"] - c0[name]["consecutive_blocks"]) + \
+                 (c1["sparse_blocks"] - c0[name]["sparse_blocks"])
+        out[name] = (B * frames_per_stream / busy[name], blocks / (B * frames_per_stream),
+                     {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]})
         e.close()
     return out, render_s
 
@@ -523,6 +526,7 @@ def main():
     ap.add_argument("--me-wgs", type=int, default=0,
                     help="persistent motion-search workgroups per CU for every batched run (0: the engine's tuner)")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end run from pinned host memory")
+    ap.add_argument("--no-hier", action="store_true", help="skip the coarse-to-fine (search = 1) batched run")
     ap.add_argument("--e2e-steps", type=int, default=40)
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-kernel figures of a rocprofv3 kernel-trace or counter CSV of this command "
@@ -601,6 +605,29 @@ def main():
                                                          "x_realtime_per_stream": round(afps / args.also_streams / RT_FPS, 1),
                                                          "ms_per_step": round(1e3 * adt / args.steps, 4)}
         print(f"[bench] batched B={args.also_streams}: {afps:.0f} frames/s", file=sys.stderr, flush=True)
+    if not args.no_hier:
+        # the coarse-to-fine motion field (search = 1) on the headline's streams
+        hp = dict(params, search=1, refine=1)
+        hdt, hkt, _, _, _ = run_engine(vsa, dev, hp, args.streams, args.steps, args.warmup, 1, torch,
+                                       preroll=args.preroll)
+        gh = geometry(W, H, params)
+        wl, hl = gh["dims"][gh["L"]]
+        ad_pair = ((wl // 2) // 8) * ((hl // 2) // 8) * 289 * 64 + (wl // 8) * (hl // 8) * 9 * 64
+        ad_full = (wl // 8) * (hl // 8) * 289 * 64
+        ms, n = hkt["me8"]
+        avg = ms / max(n, 1)
+        adl = args.streams * ad_pair
+        extra["coarse_to_fine"] = {
+            "workload": f"the headline's {args.streams} streams with search = 1: frame pairs take the full search "
+                        "on the box-downscaled pair, then +-1 around twice that vector (reach 17 working pixels, "
+                        "68 px at 2K, against 8 for the full search); field pairs keep the full search",
+            "fps": round(args.streams * args.steps / hdt, 1), "ms_per_step": round(1e3 * hdt / args.steps, 4),
+            "consecutive_launch": {"kernel": "k_me_hier<uint8_t>", "avg_launch_us": round(avg * 1e3, 3),
+                                   "ad_per_launch": adl, "achieved": round(adl / (avg * 1e-3) / 1e12, 2),
+                                   "frac": round(adl / (avg * 1e-3) / 1e12 / AD_PEAK_T, 4)},
+            "ad_per_pair": ad_pair, "ad_per_pair_full_search": ad_full}
+        print(f"[bench] coarse-to-fine B={args.streams}: {args.streams * args.steps / hdt:.0f} frames/s, "
+              f"consecutive launch {avg * 1e3:.1f} us", file=sys.stderr, flush=True)
     if not args.no_intensity_leg:
         # the same batched run without the unary intensity measure (no decision uses it)
         ndt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,
@@ -750,16 +777,21 @@ def main():
     if not args.no_stress:
         B = 8
         per = args.stress_frames // B
-        res, rs = run_stress(vsa, dict(params, k_max=4), B, per, 64, torch)
+        res, rs = run_stress(vsa, dict(params, k_max=4), B, per, 64, torch,
+                             configs=(("sparse", False, 0), ("dense", True, 0),
+                                      ("sparse_coarse_to_fine", False, 1)))
         st = {"workload": f"the 3840x2160 10-bit (uint16) 50i stress clip, {B * per} frames, cut into {B} "
                           f"consecutive pieces read by {B} streams; low contrast 64..192, pans up to 64 px/frame, "
                           "noise sigma 12, flashes p 1/25, k_max 4; rendered on the device 64 steps at a time, "
                           "untimed", "render_s": round(rs, 1)}
-        for dense, (sfps, adpf, skt) in res.items():
-            st["dense" if dense else "sparse"] = {"fps": round(sfps, 1), "x_realtime": round(sfps / RT_FPS, 1),
-                                                  "absdiff_per_frame": round(adpf), "kernel_ms_per_step": skt}
-            print(f"[bench] 4K 10-bit {'dense' if dense else 'sparse'}: {sfps:.0f} frames/s, "
-                  f"{adpf / 1e6:.1f} M AD/frame", file=sys.stderr, flush=True)
+        for name, (sfps, bpf, skt) in res.items():
+            row = {"fps": round(sfps, 1), "x_realtime": round(sfps / RT_FPS, 1),
+                   "blocks_per_frame": round(bpf, 1), "kernel_ms_per_step": skt}
+            if "coarse_to_fine" not in name:            # full search: 289 candidates of 64 samples per block
+                row["absdiff_per_frame"] = round(bpf * 289 * 64)
+            st[name] = row
+            print(f"[bench] 4K 10-bit {name}: {sfps:.0f} frames/s, {bpf:.0f} blocks/frame", file=sys.stderr,
+                  flush=True)
         extra["stress_10bit"] = st
         torch.cuda.empty_cache()
     cpu = None

@@ -730,60 +730,130 @@ __device__ void me_walk8(const StreamDesc* __restrict__ sds, const TileJob* __re
 
 // ---- coarse-to-fine motion field (frame pairs of streams with search = 1) --
 //
-// A tile is 16 x 16 blocks (128 x 128 samples) of I.  Its fine I and a fine
-// J window (rows fy0-17 .., columns fx0-24 .., clamped to the plane) are
-// staged in LDS; the coarse I tile (64 x 64, 8 x 8 coarse blocks) and the
-// coarse J window (80 x 80 around it, clamped to the coarse plane) are box
-// averages of those staged samples, laid out as the full search stages its
-// tiles, so the coarse vectors come from the full search's own lane code.
-// Then every lane takes one fine block: prediction = twice its coarse
-// block's vector (when that coarse block is whole), the best of prediction
-// + e, e in [-1, 1]^2, and the warped moments of the block.
+// A tile is 16 x 16 blocks (128 x 128 samples) of I.  First the coarse I tile
+// (64 x 64, 8 x 8 coarse blocks) and the coarse J window (80 x 80 around it,
+// clamped to the coarse plane) are formed in LDS straight from the fine
+// planes in memory (2 x 2 box averages, the pyramid's own step), laid out as
+// the full search stages its tiles, so the coarse vectors come from the full
+// search's lane code.  Then, for each half of the tile (8 block rows), the
+// fine I rows and a fine J window (rows -17 .., columns fx0-24 .., clamped to
+// the plane) are staged and two lanes take each fine block: prediction =
+// twice its coarse block's vector (when that coarse block is whole), the best
+// of prediction + e, e in [-1, 1]^2, and the warped moments, each lane over
+// four of the block's rows.
 constexpr int kHT = kHTB * kBlock;       // 128 samples per tile side
+constexpr int kHHR = kHT / 2;            // fine rows per half tile
 constexpr int kHOX = 24;                 // window column of fine column fx0
-constexpr int kHOY = 17;                 // window row of fine row fy0
+constexpr int kHOY = 17;                 // window row of the half's first fine row
 constexpr int kHJW = 176;                // window row length (samples)
-constexpr int kHJH = 162;                // window rows
+constexpr int kHJH = kHHR + 2 * kHOY;    // 98 window rows per half
 static_assert(kHOX % 8 == 0 && kHJW % 8 == 0, "window chunks are 8 samples");
-// refine reads up to column 8*15 + kHOX + 16 + 11 and row 8*15 + 7 + 17 + kHOY
-static_assert(8 * 15 + kHOX + 16 + 11 < kHJW && 8 * 15 + 7 + 17 + kHOY < kHJH, "window too small");
-// the coarse window's fine sources: columns fx0-16 .. fx0+143, rows fy0-16 .. fy0+143
-static_assert(kHOX - 16 >= 0 && kHOX + 143 < kHJW && kHOY - 16 >= 0 && kHOY + 143 < kHJH, "window too small");
+// a refinement or moment reads up to column 8*15 + kHOX + 17 + 11 and row
+// 8*7 + 7 + 17 + kHOY of the half's window
+static_assert(8 * 15 + kHOX + 16 + 11 < kHJW && 8 * 7 + 7 + 17 + kHOY < kHJH, "window too small");
 
 template <typename T>
 struct HierLds {
-    uint8_t fI[kHT * kHT * sizeof(T)];
-    uint8_t fJ[kHJH * kHJW * sizeof(T)];
     uint8_t cI[64 * 64 * sizeof(T)];
     uint8_t cJ[kJRows * kJW8 * sizeof(T)];
+    uint8_t fI[kHHR * kHT * sizeof(T)];
+    uint8_t fJ[kHJH * kHJW * sizeof(T)];
     int32_t cmv[64];                      // coarse vector per coarse block: dx & 0xff | (dy & 0xff) << 8
     int64_t red[4 * 6];
 };
 
+// 2 x 2 box averages (rounding half up) of four coarse samples from two fine
+// rows of eight samples (8 bytes, or 16 bytes of 16-bit samples):
+// v_dot4_u32_u8 / v_dot2_u32_u16 against a mask add the two samples of a
+// column pair of each row onto the rounding constant; the four results are
+// packed into the coarse row's four samples.
+typedef unsigned short hpk_us2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t box_pair8(uint32_t a, uint32_t b, uint32_t m) {
+    return __builtin_amdgcn_udot4(a, m, __builtin_amdgcn_udot4(b, m, 2u, false), false) >> 2;
+}
+__device__ __forceinline__ uint32_t box_pair16(uint32_t a, uint32_t b) {
+    const hpk_us2 one = {1, 1};
+    return __builtin_amdgcn_udot2(__builtin_bit_cast(hpk_us2, a), one,
+                                  __builtin_amdgcn_udot2(__builtin_bit_cast(hpk_us2, b), one, 2u, false), false) >> 2;
+}
 template <typename T>
-__device__ __forceinline__ T lds_at(const uint8_t* base, int idx) {
-    return reinterpret_cast<const T*>(base)[idx];
+__device__ __forceinline__ void box4_global(const uint8_t* r0, const uint8_t* r1, T* dst) {
+    if constexpr (sizeof(T) == 1) {
+        const uint2 a = gload2(r0), b = gload2(r1);
+        const uint32_t s0 = box_pair8(a.x, b.x, 0x00000101u), s1 = box_pair8(a.x, b.x, 0x01010000u);
+        const uint32_t s2 = box_pair8(a.y, b.y, 0x00000101u), s3 = box_pair8(a.y, b.y, 0x01010000u);
+        *reinterpret_cast<uint32_t*>(dst) = s0 | (s1 << 8) | (s2 << 16) | (s3 << 24);
+    } else {
+        const uint4 a = gload4(r0), b = gload4(r1);
+        const uint32_t s0 = box_pair16(a.x, b.x), s1 = box_pair16(a.y, b.y);
+        const uint32_t s2 = box_pair16(a.z, b.z), s3 = box_pair16(a.w, b.w);
+        *reinterpret_cast<uint2*>(dst) = make_uint2(s0 | (s1 << 16), s2 | (s3 << 16));
+    }
 }
 
+// The coarse tile and window, from the fine planes in memory.  Coarse I
+// items past the row pitch are not read (their blocks are not whole); coarse
+// rows past the plane read its last fine rows.  Window items whose columns
+// reach past the coarse plane's edge clamp each column on its own.
 template <typename T>
-__device__ void hier_stage(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) {
+__device__ void hier_coarse(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) {
     constexpr int B = (int)sizeof(T);
     const int tid = threadIdx.x;
-    // fine I: 128 rows of 128 samples in 16-byte chunks; a chunk past the row
-    // pitch is not read (its blocks are not whole), rows past the plane are
-    // clamped
+    T* cI = reinterpret_cast<T*>(S.cI);
+    T* cJ = reinterpret_cast<T*>(S.cJ);
+    for (int i = tid; i < 64 * 16; i += kMEThreads) {
+        const int y = i >> 4, x = 4 * (i & 15);
+        const int gx = fx0 + 2 * x;
+        if (gx >= jb.pitch) {
+            if constexpr (B == 1) *reinterpret_cast<uint32_t*>(cI + y * 64 + x) = 0u;
+            else *reinterpret_cast<uint2*>(cI + y * 64 + x) = make_uint2(0u, 0u);
+            continue;
+        }
+        const int g0 = min(fy0 + 2 * y, jb.h - 1), g1 = min(fy0 + 2 * y + 1, jb.h - 1);
+        box4_global<T>(jb.I + ((int64_t)g0 * jb.pitch + gx) * B, jb.I + ((int64_t)g1 * jb.pitch + gx) * B,
+                       cI + y * 64 + x);
+    }
+    const int wc = jb.w / 2, hc = jb.h / 2;
+    const int cx0 = fx0 / 2 - 8, cy0 = fy0 / 2 - 8;
+    constexpr int G = kJW8 / 4;                      // items per window row
+    for (int i = tid; i < kJRows * G; i += kMEThreads) {
+        const int r = i / G, c = 4 * (i - (i / G) * G);
+        const int cy = clampi(cy0 + r, 0, hc - 1);
+        const uint8_t* r0 = jb.J + (int64_t)(2 * cy) * jb.pitch * B;
+        const uint8_t* r1 = r0 + (int64_t)jb.pitch * B;
+        T* dst = cJ + r * kJW8 + c;
+        if (cx0 + c >= 0 && cx0 + c + 3 <= wc - 1) {
+            box4_global<T>(r0 + 2 * (cx0 + c) * B, r1 + 2 * (cx0 + c) * B, dst);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int f = 2 * clampi(cx0 + c + k, 0, wc - 1);
+                dst[k] = (T)(((int)gload<T>(r0 + f * B) + gload<T>(r0 + (f + 1) * B) + gload<T>(r1 + f * B) +
+                              gload<T>(r1 + (f + 1) * B) + 2) >> 2);
+            }
+        }
+    }
+}
+
+// Fine I rows fy0 + 64 hh .. +64 and the half's J window (rows from
+// fy0 + 64 hh - kHOY, columns from fx0 - kHOX), clamped to the plane; I
+// chunks past the row pitch are not read.
+template <typename T>
+__device__ void hier_stage_half(const TileJob& jb, int fx0, int fy0, int hh, HierLds<T>& S) {
+    constexpr int B = (int)sizeof(T);
+    const int tid = threadIdx.x;
+    const int ry = fy0 + kHHR * hh;
     constexpr int ICH = kHT * B / 16;
-    for (int i = tid; i < kHT * ICH; i += kMEThreads) {
+    for (int i = tid; i < kHHR * ICH; i += kMEThreads) {
         const int r = i / ICH, c = i - (i / ICH) * ICH;
-        const int gy = min(fy0 + r, jb.h - 1);
+        const int gy = min(ry + r, jb.h - 1);
         const int gx = fx0 + c * (16 / B);
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (gx < jb.pitch) v = gload4(jb.I + ((int64_t)gy * jb.pitch + gx) * B);
         reinterpret_cast<uint4*>(S.fI)[i] = v;
     }
-    // fine J window in 8-sample chunks, clamped to the plane
     constexpr int JCH = kHJW / 8;
-    const int x0 = fx0 - kHOX, y0 = fy0 - kHOY;
+    const int x0 = fx0 - kHOX, y0 = ry - kHOY;
     for (int i = tid; i < kHJH * JCH; i += kMEThreads) {
         const int r = i / JCH, c = i - (i / JCH) * JCH;
         const int gy = clampi(y0 + r, 0, jb.h - 1);
@@ -791,39 +861,12 @@ __device__ void hier_stage(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) {
         const uint8_t* row = jb.J + (int64_t)gy * jb.pitch * B;
         T* dst = reinterpret_cast<T*>(S.fJ) + r * kHJW + 8 * c;
         if (gx >= 0 && gx + 8 <= jb.w) {
-            if constexpr (B == 1) {
-                *reinterpret_cast<uint2*>(dst) = gload2(row + gx);
-            } else {
-                *reinterpret_cast<uint4*>(dst) = gload4(row + 2 * gx);
-            }
+            if constexpr (B == 1) *reinterpret_cast<uint2*>(dst) = gload2(row + gx);
+            else *reinterpret_cast<uint4*>(dst) = gload4(row + 2 * gx);
         } else {
 #pragma unroll
             for (int k = 0; k < 8; ++k) dst[k] = gload<T>(row + clampi(gx + k, 0, jb.w - 1) * B);
         }
-    }
-}
-
-// Coarse tile and window from the staged fine samples (2 x 2 box, rounding
-// half up: the pyramid's own step, so they equal the next level's planes).
-template <typename T>
-__device__ void hier_coarse(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) {
-    const int tid = threadIdx.x;
-    const T* fI = reinterpret_cast<const T*>(S.fI);
-    const T* fJ = reinterpret_cast<const T*>(S.fJ);
-    T* cI = reinterpret_cast<T*>(S.cI);
-    T* cJ = reinterpret_cast<T*>(S.cJ);
-    for (int i = tid; i < 64 * 64; i += kMEThreads) {
-        const int y = i >> 6, x = i & 63;
-        const T* a = fI + (2 * y) * kHT + 2 * x;
-        cI[i] = (T)(((int)a[0] + a[1] + a[kHT] + a[kHT + 1] + 2) >> 2);
-    }
-    const int wc = jb.w / 2, hc = jb.h / 2;
-    const int cx0 = fx0 / 2 - 8, cy0 = fy0 / 2 - 8;
-    for (int i = tid; i < kJRows * kJW8; i += kMEThreads) {
-        const int r = i / kJW8, c = i - (i / kJW8) * kJW8;
-        const int cx = clampi(cx0 + c, 0, wc - 1), cy = clampi(cy0 + r, 0, hc - 1);
-        const T* a = fJ + (2 * cy - fy0 + kHOY) * kHJW + (2 * cx - fx0 + kHOX);
-        cJ[i] = (T)(((int)a[0] + a[1] + a[kHJW] + a[kHJW + 1] + 2) >> 2);
     }
 }
 
@@ -833,38 +876,44 @@ __device__ __forceinline__ uint32_t hier_key(uint32_t sad, int ex, int ey) {
     return (sad << 16) | (uint32_t)(((ex * ex + ey * ey) * 3 + ey + 1) * 3 + ex + 1);
 }
 
-// 8-bit refinement of fine block (bx, by) around prediction (px, py), px
-// and py even: v_qsad_pk_u16_u8 over the two dx groups q-4 .. q-1 and
-// q .. q+3 with q = px rounded down to a multiple of 4, which hold the three
-// candidates px-1 .. px+1; each J row is read once for the three ey.
-__device__ __forceinline__ uint32_t hier_refine8(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int px,
-                                                 int py) {
-    uint32_t r0[8], r1[8];
+// 8-bit partial refinement of half-tile block (bx, by) over its rows j0 ..
+// j0+3, around prediction (px, py) (both even): v_qsad_pk_u16_u8 over the
+// two dx groups q-4 .. q-1 and q .. q+3, q = px rounded down to a multiple
+// of 4, which hold the candidates px-1 .. px+1; each J row is read once for
+// the three ey.  acc[ey+1][group]: four packed 16-bit partial SADs.
+__device__ __forceinline__ void hier_refine8(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int j0, int px,
+                                             int py, uint64_t (&acc)[3][2]) {
+    uint32_t r0[4], r1[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint2 v = *reinterpret_cast<const uint2*>(fI + (8 * by + j) * kHT + 8 * bx);
+    for (int j = 0; j < 4; ++j) {
+        const uint2 v = *reinterpret_cast<const uint2*>(fI + (8 * by + j0 + j) * kHT + 8 * bx);
         r0[j] = v.x;
         r1[j] = v.y;
     }
     const int q4 = px & ~3;
-    const uint8_t* jb = fJ + (8 * by + py + kHOY - 1) * kHJW + (8 * bx + kHOX + q4 - 4);
-    uint64_t acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    const uint8_t* jb = fJ + (8 * by + j0 + py + kHOY - 1) * kHJW + (8 * bx + kHOX + q4 - 4);
 #pragma unroll
-    for (int u = 0; u < 10; ++u) {           // J row u holds block row j = u - 1 - ey for ey = -1, 0, 1
+    for (int e = 0; e < 3; ++e) acc[e][0] = acc[e][1] = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {            // J row u holds row j = u - 1 - ey of the lane's four
         const uint32_t* wp = reinterpret_cast<const uint32_t*>(jb + u * kHJW);
         const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
         const uint64_t w01 = pk64(w0, w1), w12 = pk64(w1, w2), w23 = pk64(w2, w3);
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             const int j = u - e;
-            if (j < 0 || j > 7) continue;
+            if (j < 0 || j > 3) continue;
             acc[e][0] = __builtin_amdgcn_qsad_pk_u16_u8(w01, r0[j], acc[e][0]);
             acc[e][0] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r1[j], acc[e][0]);
             acc[e][1] = __builtin_amdgcn_qsad_pk_u16_u8(w12, r0[j], acc[e][1]);
             acc[e][1] = __builtin_amdgcn_qsad_pk_u16_u8(w23, r1[j], acc[e][1]);
         }
     }
-    const bool h2 = (px - q4) != 0;          // px = q4 or q4 + 2
+}
+
+// The key of the best candidate from the summed packed SADs.
+__device__ __forceinline__ uint32_t hier_best8(const uint64_t (&acc)[3][2], int px) {
+    const bool h2 = (px & 3) != 0;           // px = q4 or q4 + 2
     uint32_t best = 0xffffffffu;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
@@ -877,22 +926,25 @@ __device__ __forceinline__ uint32_t hier_refine8(const uint8_t* fI, const uint8_
     return best;
 }
 
-// 10-bit refinement: the ten J rows' ten samples each, absolute differences
-// in registers.
-__device__ __forceinline__ uint32_t hier_refine16(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int px,
-                                                  int py) {
-    const uint16_t* I = reinterpret_cast<const uint16_t*>(fI) + (8 * by) * kHT + 8 * bx;
-    const uint16_t* J = reinterpret_cast<const uint16_t*>(fJ) + (8 * by + py + kHOY - 1) * kHJW + (8 * bx + px + kHOX - 1);
-    uint32_t sad[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+// 10-bit partial refinement over rows j0 .. j0+3: sad[ey+1][ex+1].
+__device__ __forceinline__ void hier_refine16(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int j0, int px,
+                                              int py, uint32_t (&sad)[3][3]) {
+    const uint16_t* I = reinterpret_cast<const uint16_t*>(fI) + (8 * by + j0) * kHT + 8 * bx;
+    const uint16_t* J =
+        reinterpret_cast<const uint16_t*>(fJ) + (8 * by + j0 + py + kHOY - 1) * kHJW + (8 * bx + px + kHOX - 1);
 #pragma unroll
-    for (int u = 0; u < 10; ++u) {
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) sad[e][f] = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
         int jr[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) jr[k] = J[u * kHJW + k];
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             const int j = u - e;
-            if (j < 0 || j > 7) continue;
+            if (j < 0 || j > 3) continue;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int x = I[j * kHT + i];
@@ -901,23 +953,16 @@ __device__ __forceinline__ uint32_t hier_refine16(const uint8_t* fI, const uint8
             }
         }
     }
-    uint32_t best = 0xffffffffu;
-#pragma unroll
-    for (int e = 0; e < 3; ++e)
-#pragma unroll
-        for (int f = 0; f < 3; ++f) best = min(best, hier_key(sad[e][f], f - 1, e - 1));
-    return best;
 }
 
-// Moments of fine block (bx, by) against J warped by (dx, dy).
+// Moments of rows j0 .. j0+3 of half-tile block (bx, by) against J warped by (dx, dy).
 template <typename T>
-__device__ __forceinline__ void hier_moments(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int dx, int dy,
-                                             int64_t m[5]) {
-    int32_t s[5] = {0, 0, 0, 0, 0};
+__device__ __forceinline__ void hier_moments(const uint8_t* fI, const uint8_t* fJ, int bx, int by, int j0, int dx,
+                                             int dy, int32_t s[5]) {
     if constexpr (sizeof(T) == 1) {
         const int col = 8 * bx + kHOX + dx;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = j0; j < j0 + 4; ++j) {
             const uint2 xv = *reinterpret_cast<const uint2*>(fI + (8 * by + j) * kHT + 8 * bx);
             const uint8_t* jr = fJ + (8 * by + j + dy + kHOY) * kHJW + (col & ~3);
             const uint32_t w0 = *reinterpret_cast<const uint32_t*>(jr);
@@ -933,111 +978,174 @@ __device__ __forceinline__ void hier_moments(const uint8_t* fI, const uint8_t* f
             s[4] += (int32_t)__builtin_amdgcn_udot4(xv.y, y1, __builtin_amdgcn_udot4(xv.x, y0, 0u, false), false);
         }
     } else {
-        const uint16_t* I = reinterpret_cast<const uint16_t*>(fI) + (8 * by) * kHT + 8 * bx;
-        const uint16_t* J = reinterpret_cast<const uint16_t*>(fJ) + (8 * by + dy + kHOY) * kHJW + (8 * bx + dx + kHOX);
+        const uint16_t* I = reinterpret_cast<const uint16_t*>(fI) + (8 * by + j0) * kHT + 8 * bx;
+        const uint16_t* J =
+            reinterpret_cast<const uint16_t*>(fJ) + (8 * by + j0 + dy + kHOY) * kHJW + (8 * bx + dx + kHOX);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int32_t x = I[j * kHT + i], y = J[j * kHJW + i];
                 s[0] += x; s[1] += y; s[2] += x * x; s[3] += y * y; s[4] += x * y;
             }
     }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[k] = s[k];
 }
 
-// One coarse-to-fine tile: the vectors of its fine blocks, their moments and
-// A, one partial per tile.
+// The fine blocks of half hh of a staged tile: two lanes per block (lane pair
+// 2 k, 2 k + 1: rows 0-3 and 4-7), refinement around the coarse prediction,
+// the vector and SAD out, moments and A into the lane's sums.
 template <typename T>
-__device__ void me_tile_hier(const TileJob& jb, int local, TilePartial* part_out, int8_t* mv_out, int32_t* sad_out,
-                             HierLds<T>& S) {
+__device__ __forceinline__ void hier_half(const TileJob& jb, HierLds<T>& S, int tx, int ty, int hh, bool coarse,
+                                          bool zero, int8_t* mv_out, int32_t* sad_out, int32_t s[5], int32_t& a) {
     const int tid = threadIdx.x;
-    const int tx = local % jb.tiles_x, ty = local / jb.tiles_x;
-    const int fx0 = tx * kHT, fy0 = ty * kHT;
     const int nbx = jb.w / kBlock, nby = jb.h / kBlock;
     const int nbxc = (jb.w / 2) / kBlock, nbyc = (jb.h / 2) / kBlock;
-    const bool zero = (jb.flags & TF_ZERO_MV) != 0;
-    // the coarse stage runs when the coarse plane has a whole block (else every
-    // prediction is (0, 0))
-    const bool coarse = !zero && nbxc > 0 && nbyc > 0;
-    hier_stage<T>(jb, fx0, fy0, S);
-    __syncthreads();
-    if (coarse) {
-        hier_coarse<T>(jb, fx0, fy0, S);
-        __syncthreads();
-        // coarse full search: four lanes per coarse block, as in a full-search tile
-        const int b = tid >> 2, q = tid & 3;
-        const int cbx = b & 7, cby = b >> 3;
-        const bool cvalid = (8 * tx + cbx < nbxc) && (8 * ty + cby < nbyc);
-        uint32_t key = 0xffffffffu;
-        if (cvalid) {
-            if constexpr (sizeof(T) == 1) key = search8p(S.cI, S.cJ, cbx, cby, q);
-            else key = search16(S.cI, S.cJ, cbx, cby, q);
-        }
-        key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
-        key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
-        if (q == 0) {
-            int v = 0;
-            if (cvalid) {
-                const uint32_t cell = (key & 0xffffu) % (uint32_t)(kCand * kCand);   // (dy+8)*17 + dx+8
-                const int dx = (int)(cell % kCand) - kRadius, dy = (int)(cell / kCand) - kRadius;
-                v = (dx & 0xff) | ((dy & 0xff) << 8);
-            }
-            S.cmv[b] = cvalid ? v : 0;
-        }
-        __syncthreads();
-    }
-    // refinement and moments: one lane per fine block
-    const int bx = tid & (kHTB - 1), by = tid / kHTB;
+    const int hl = tid & 1, k = tid >> 1;
+    const int bx = k & (kHTB - 1), byh = k / kHTB;    // block column, block row within the half
+    const int by = kHTB / 2 * hh + byh;               // block row within the tile
     const bool valid = (kHTB * tx + bx < nbx) && (kHTB * ty + by < nby);
     int dx = 0, dy = 0;
     uint32_t best = 0;
-    if (valid && !zero) {
+    if (!zero) {
         int px = 0, py = 0;
         if (coarse && kHTB / 2 * tx + (bx >> 1) < nbxc && kHTB / 2 * ty + (by >> 1) < nbyc) {
             const int v = S.cmv[(by >> 1) * 8 + (bx >> 1)];
             px = 2 * (int)(int8_t)(v & 0xff);
             py = 2 * (int)(int8_t)((v >> 8) & 0xff);
         }
-        if constexpr (sizeof(T) == 1) best = hier_refine8(S.fI, S.fJ, bx, by, px, py);
-        else best = hier_refine16(S.fI, S.fJ, bx, by, px, py);
+        // both lanes of a pair run the same code; an invalid block's lanes
+        // read inside the window and their result is not used
+        if constexpr (sizeof(T) == 1) {
+            uint64_t acc[3][2];
+            hier_refine8(S.fI, S.fJ, bx, byh, 4 * hl, px, py, acc);
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const uint64_t o = (uint64_t)__shfl_xor((long long)acc[e][g], 1, 64);
+                    acc[e][g] += o;   // 16-bit lanes: each sum stays below 64 * 255
+                }
+            best = hier_best8(acc, px);
+        } else {
+            uint32_t sd[3][3];
+            hier_refine16(S.fI, S.fJ, bx, byh, 4 * hl, px, py, sd);
+            best = 0xffffffffu;
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const uint32_t t = sd[e][f] + (uint32_t)__shfl_xor((int)sd[e][f], 1, 64);
+                    best = min(best, hier_key(t, f - 1, e - 1));
+                }
+        }
         const int code = (int)(best & 0xffffu) % 9;      // (ey+1)*3 + ex+1
         dx = px + code % 3 - 1;
         dy = py + code / 3 - 1;
     }
-    int64_t m[5] = {0, 0, 0, 0, 0};
-    int32_t a = 0;
     if (valid) {
-        hier_moments<T>(S.fI, S.fJ, bx, by, dx, dy, m);
-        a = amm_fx(dx * dx + dy * dy);
+        hier_moments<T>(S.fI, S.fJ, bx, byh, 4 * hl, dx, dy, s);
+        if (hl == 0) a += amm_fx(dx * dx + dy * dy);
     }
     const int blk = (kHTB * ty + by) * nbx + (kHTB * tx + bx);
-    if (valid && mv_out) {
+    if (valid && hl == 0 && mv_out) {
         mv_out[2 * blk] = (int8_t)dx;
         mv_out[2 * blk + 1] = (int8_t)dy;
     }
-    if (valid && sad_out) {
+    if (sad_out) {
+        int32_t sv = 0;
         if (zero) {
-            int32_t s0 = 0;
-            const T* I = reinterpret_cast<const T*>(S.fI) + (8 * by) * kHT + 8 * bx;
-            const T* J = reinterpret_cast<const T*>(S.fJ) + (8 * by + kHOY) * kHJW + (8 * bx + kHOX);
-            for (int j = 0; j < 8; ++j)
-                for (int i = 0; i < 8; ++i) s0 += abs((int)I[j * kHT + i] - (int)J[j * kHJW + i]);
-            sad_out[blk] = s0;
+            const T* I = reinterpret_cast<const T*>(S.fI) + (8 * byh + 4 * hl) * kHT + 8 * bx;
+            const T* J = reinterpret_cast<const T*>(S.fJ) + (8 * byh + 4 * hl + kHOY) * kHJW + (8 * bx + kHOX);
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 8; ++i) sv += abs((int)I[j * kHT + i] - (int)J[j * kHJW + i]);
+            sv += __shfl_xor(sv, 1, 64);
         } else {
-            sad_out[blk] = (int32_t)(best >> 16);
+            sv = (int32_t)(best >> 16);
         }
+        if (valid && hl == 0) sad_out[blk] = sv;
     }
-    // one lane per block: 64 blocks per wave, so the sums take 64 bits
+}
+
+// Coarse vectors of the tile's coarse blocks (four lanes per coarse block, as
+// in a full-search tile) into S.cmv.
+template <typename T>
+__device__ __forceinline__ void hier_coarse_search(const TileJob& jb, HierLds<T>& S, int tx, int ty) {
+    const int tid = threadIdx.x;
+    const int nbxc = (jb.w / 2) / kBlock, nbyc = (jb.h / 2) / kBlock;
+    const int b = tid >> 2, q = tid & 3;
+    const int cbx = b & 7, cby = b >> 3;
+    const bool cvalid = (8 * tx + cbx < nbxc) && (8 * ty + cby < nbyc);
+    uint32_t key = 0xffffffffu;
+    if (cvalid) {
+        if constexpr (sizeof(T) == 1) key = search8p(S.cI, S.cJ, cbx, cby, q);
+        else key = search16(S.cI, S.cJ, cbx, cby, q);
+    }
+    key = min(key, (uint32_t)__shfl_xor((int)key, 1, 64));
+    key = min(key, (uint32_t)__shfl_xor((int)key, 2, 64));
+    if (q == 0) {
+        int v = 0;
+        if (cvalid) {
+            const uint32_t cell = (key & 0xffffu) % (uint32_t)(kCand * kCand);   // (dy+8)*17 + dx+8
+            const int dx = (int)(cell % kCand) - kRadius, dy = (int)(cell / kCand) - kRadius;
+            v = (dx & 0xff) | ((dy & 0xff) << 8);
+        }
+        S.cmv[b] = v;
+    }
+}
+
+// One coarse-to-fine tile: the vectors of its fine blocks, their moments and
+// A, one partial per tile.
+__device__ __forceinline__ const uint8_t* uniform_ptr(const uint8_t* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<const uint8_t*>(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ void me_tile_hier(const TileJob& job, int local, TilePartial* part_out, int8_t* mv_out, int32_t* sad_out,
+                             HierLds<T>& S) {
+    // the job is the same for the whole workgroup: its fields in scalar
+    // registers, so that the staging addresses are a scalar base plus a
+    // 32-bit lane offset
+    TileJob jb = job;
+    jb.I = uniform_ptr(job.I);
+    jb.J = uniform_ptr(job.J);
+    jb.w = __builtin_amdgcn_readfirstlane(job.w);
+    jb.h = __builtin_amdgcn_readfirstlane(job.h);
+    jb.pitch = __builtin_amdgcn_readfirstlane(job.pitch);
+    jb.tiles_x = __builtin_amdgcn_readfirstlane(job.tiles_x);
+    jb.flags = __builtin_amdgcn_readfirstlane(job.flags);
+    const int tid = threadIdx.x;
+    const int tx = local % jb.tiles_x, ty = local / jb.tiles_x;
+    const int fx0 = tx * kHT, fy0 = ty * kHT;
+    const int nbxc = (jb.w / 2) / kBlock, nbyc = (jb.h / 2) / kBlock;
+    const bool zero = (jb.flags & TF_ZERO_MV) != 0;
+    // the coarse stage runs when the coarse plane has a whole block (else every
+    // prediction is (0, 0))
+    const bool coarse = !zero && nbxc > 0 && nbyc > 0;
+    int32_t s[5] = {0, 0, 0, 0, 0};
+    int32_t a = 0;
+    if (coarse) {
+        hier_coarse<T>(jb, fx0, fy0, S);
+        __syncthreads();
+        hier_coarse_search<T>(jb, S, tx, ty);
+    }
+    for (int hh = 0; hh < 2; ++hh) {
+        __syncthreads();                               // the previous half's (or the coarse stage's) reads are done
+        hier_stage_half<T>(jb, fx0, fy0, hh, S);
+        __syncthreads();
+        hier_half<T>(jb, S, tx, ty, hh, coarse, zero, mv_out, sad_out, s, a);
+    }
+    // per lane: half of each of two blocks; int64 wave sums (10-bit squares)
     const int wave = tid >> 6;
     int64_t w[6];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) w[k] = wave_sum64(m[k]);
+    for (int q = 0; q < 5; ++q) w[q] = wave_sum64((int64_t)s[q]);
     w[5] = wave_sum64((int64_t)a);
     if ((tid & 63) == 0)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) S.red[wave * 6 + k] = w[k];
+        for (int q = 0; q < 6; ++q) S.red[wave * 6 + q] = w[q];
     __syncthreads();
     if (tid == 0) {
         TilePartial p;

@@ -1239,8 +1239,10 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         if (g >= 8) g -= g % 8;
         return g;
     };
-    const int grid_hc = hier ? mh_grid(consec_tiles, wgs.consec) : 0;
-    const int grid_hs = hier ? mh_grid(sparse_max, wgs.sparse) : 0;
+    // its waves spend most of their time waiting for their tile's loads, so its
+    // grids take every workgroup a CU holds
+    const int grid_hc = hier ? mh_grid(consec_tiles, mh_cap) : 0;
+    const int grid_hs = hier ? mh_grid(sparse_max, mh_cap) : 0;
     // consecutive partials alternate by step parity; sparse task lists, jobs
     // and maps too (read the previous step's, write the next)
     TilePartial* cpart = e->d_partials + (size_t)par * e->partials_cap;
@@ -2060,8 +2062,8 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
             if (gsz >= 8) gsz -= gsz % 8;
             return gsz;
         };
-        c->grid_hc = hgrid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2);
-        c->grid_hs = hgrid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
+        c->grid_hc = hgrid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : mh_cap);
+        c->grid_hs = hgrid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : mh_cap);
     }
     HIPCK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking), "hipStreamCreate");
     HIPCK(hipStreamCreateWithFlags(&c->sp, hipStreamNonBlocking), "hipStreamCreate");

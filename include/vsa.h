@@ -91,7 +91,9 @@ typedef struct {
     int32_t search;       /* motion field of frame pairs (Sec. III.A): 0 full search over
                              [-R, R]^2; 1 coarse-to-fine: full search on the 2x2-box image one
                              level coarser, then +-refine around twice that vector (reach
-                             2R + refine).  Field pairs always take the full search.          */
+                             2R + refine).  Field pairs always take the full search.
+                             2 (dense inverse search flow) is taken by vsa_debug_flow_pair
+                             only; the engine and the clip analyser refuse it.               */
     int32_t refine;       /* refinement radius of the coarse-to-fine search; must be 1       */
 } vsa_params;
 

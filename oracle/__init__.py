@@ -78,6 +78,7 @@ def lib():
         L.orc_pair.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(Params), C.c_int32,
                                P, P, P, P]
         L.orc_finish.argtypes = [P, C.c_double, P]
+        L.orc_flow_pair.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(Params), P, P, P]
         L.orc_intensity.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.orc_run_clip.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
                                    C.c_int32, C.c_int32, C.POINTER(Params), P, P, C.c_int32,
@@ -86,7 +87,7 @@ def lib():
                                           C.POINTER(Params), P, P, C.c_int32,
                                           C.POINTER(C.c_int32), P, C.c_int32,
                                           C.POINTER(C.c_int32)]
-        for f in ("orc_geometry", "orc_downscale", "orc_levels", "orc_pair", "orc_finish",
+        for f in ("orc_geometry", "orc_downscale", "orc_levels", "orc_pair", "orc_finish", "orc_flow_pair",
                   "orc_intensity", "orc_run_clip", "orc_decide_injected"):
             getattr(L, f).restype = C.c_int32
         _lib = L
@@ -170,6 +171,21 @@ def pair(I, J, params, force_zero_mv=False):
     out["mv"] = mv[:B].reshape(h // 8, w // 8, 2)
     out["sad"] = sad[:B].reshape(h // 8, w // 8)
     return out
+
+
+def flow_pair(I, J, params):
+    """Pair measure with the dense inverse search flow (search = 2):
+    {"flow": [h, w, 2] (dx, dy), "ncc", "swr", "amm", "act", "static"}."""
+    I = np.ascontiguousarray(I, dtype=np.uint16)
+    J = np.ascontiguousarray(J, dtype=np.uint16)
+    h, w = I.shape
+    flow = np.zeros((h, w, 2), np.float64)
+    dbl = np.zeros(4, np.float64)
+    st = C.c_int32(0)
+    _check(lib().orc_flow_pair(_ptr(I), _ptr(J), w, h, make_params(params), _ptr(flow), _ptr(dbl), C.byref(st)),
+           "orc_flow_pair")
+    return {"flow": flow, "ncc": float(dbl[0]), "swr": float(dbl[1]), "amm": float(dbl[2]), "act": float(dbl[3]),
+            "static": int(st.value)}
 
 
 def intensity(plane, bits=8):

@@ -308,6 +308,184 @@ void pair_measure(const Plane& I, const Plane& J, const orc_params& p, bool zero
     o.ncc = f[0]; o.swr = f[1]; o.amm = f[2]; o.act = f[3];
 }
 
+
+// ---- Dense inverse search (search = 2): the paper's own kind of motion
+// field (Sec. III.A names the dense inverse search optical flow of its
+// reference [8]); this is a plain reading of that method on the same
+// pyramid, with fixed work so that its result is exactly reproducible.
+//
+//  - Scales: the pair's two planes, then up to kDisScales box-downscaled
+//    copies (the pyramid's own step), coarsest first; a copy narrower or
+//    lower than one patch ends the list.
+//  - Patches: kDisP x kDisP, origins every kDisS samples from 0, plus one
+//    flush with the right (bottom) edge when the grid does not reach it.
+//  - Per patch, inverse-compositional search: template T = the reference
+//    patch, gradients by central differences over the whole plane (edge
+//    samples repeated); H = sum g g^T + lambda I; kDisIters steps of
+//    u <- u - H^-1 sum g (J(x + u) - T(x)), J sampled bilinearly with
+//    clamp-to-edge coordinates; each component clamped to +-kDisUmax.
+//    Start: 0 at the coarsest scale, else twice the coarser dense flow at
+//    the patch centre halved (integer division, clamped).
+//  - Densification: the flow at a pixel is the average of the vectors of the
+//    patches covering it, weighted by 1 / max(1, |J(x + u) - I(x)|).
+//  - Sums run in a fixed order: within a patch row by row, left to right;
+//    over a plane, each row left to right, then the rows top to bottom.
+constexpr int kDisP = 8;
+constexpr int kDisS = 4;
+constexpr int kDisScales = 2;
+constexpr int kDisIters = 8;
+constexpr double kDisLambda = 64.0;
+constexpr double kDisUmax = 32.0;
+
+// Bilinear sample of J at (X, Y), coordinates clamped to the plane.
+double bilin(const Plane& J, double X, double Y) {
+    const double xc = std::min(std::max(X, 0.0), (double)(J.w - 1));
+    const double yc = std::min(std::max(Y, 0.0), (double)(J.h - 1));
+    const int x0 = (int)std::floor(xc), y0 = (int)std::floor(yc);
+    const int x1 = std::min(x0 + 1, J.w - 1), y1 = std::min(y0 + 1, J.h - 1);
+    const double fx = xc - x0, fy = yc - y0;
+    const double a = J.at(x0, y0), b = J.at(x1, y0), c = J.at(x0, y1), d = J.at(x1, y1);
+    const double top = a + fx * (b - a);
+    const double bot = c + fx * (d - c);
+    return top + fy * (bot - top);
+}
+
+std::vector<int> patch_origins(int n) {
+    std::vector<int> o;
+    for (int x = 0; x + kDisP <= n; x += kDisS) o.push_back(x);
+    if (!o.empty() && o.back() + kDisP < n) o.push_back(n - kDisP);
+    return o;
+}
+
+// Dense flow of I -> J (fx, fy per pixel of I, in the plane's pixels).
+void dis_flow(const Plane& I0, const Plane& J0, std::vector<double>& fx, std::vector<double>& fy) {
+    std::vector<Plane> Is{I0}, Js{J0};
+    for (int k = 0; k < kDisScales; ++k) {
+        Plane a = downscale(Is.back()), b = downscale(Js.back());
+        if (a.w < kDisP || a.h < kDisP) break;
+        Is.push_back(a);
+        Js.push_back(b);
+    }
+    std::vector<double> cfx, cfy;        // the coarser scale's dense flow
+    int cw = 0, ch = 0;
+    for (int k = (int)Is.size() - 1; k >= 0; --k) {
+        const Plane& I = Is[(size_t)k];
+        const Plane& J = Js[(size_t)k];
+        const int w = I.w, h = I.h;
+        const std::vector<int> ox = patch_origins(w), oy = patch_origins(h);
+        std::vector<double> ux(ox.size() * oy.size()), uy(ox.size() * oy.size());
+        for (size_t j = 0; j < oy.size(); ++j)
+            for (size_t i = 0; i < ox.size(); ++i) {
+                const int px = ox[i], py = oy[j];
+                double u0 = 0.0, u1 = 0.0;
+                if (!cfx.empty()) {
+                    const int cx = std::min((px + kDisP / 2) / 2, cw - 1);
+                    const int cy = std::min((py + kDisP / 2) / 2, ch - 1);
+                    u0 = 2.0 * cfx[(size_t)cy * cw + cx];
+                    u1 = 2.0 * cfy[(size_t)cy * cw + cx];
+                }
+                double gx[kDisP][kDisP], gy[kDisP][kDisP];
+                double h00 = kDisLambda, h01 = 0.0, h11 = kDisLambda;
+                for (int y = 0; y < kDisP; ++y)
+                    for (int x = 0; x < kDisP; ++x) {
+                        const int X = px + x, Y = py + y;
+                        gx[y][x] = (I.at(std::min(X + 1, w - 1), Y) - I.at(std::max(X - 1, 0), Y)) / 2.0;
+                        gy[y][x] = (I.at(X, std::min(Y + 1, h - 1)) - I.at(X, std::max(Y - 1, 0))) / 2.0;
+                        h00 += gx[y][x] * gx[y][x];
+                        h01 += gx[y][x] * gy[y][x];
+                        h11 += gy[y][x] * gy[y][x];
+                    }
+                const double det = h00 * h11 - h01 * h01;
+                for (int it = 0; it < kDisIters; ++it) {
+                    double b0 = 0.0, b1 = 0.0;
+                    for (int y = 0; y < kDisP; ++y)
+                        for (int x = 0; x < kDisP; ++x) {
+                            const int X = px + x, Y = py + y;
+                            const double e = bilin(J, X + u0, Y + u1) - I.at(X, Y);
+                            b0 += gx[y][x] * e;
+                            b1 += gy[y][x] * e;
+                        }
+                    const double d0 = (h11 * b0 - h01 * b1) / det;
+                    const double d1 = (h00 * b1 - h01 * b0) / det;
+                    u0 = std::min(std::max(u0 - d0, -kDisUmax), kDisUmax);
+                    u1 = std::min(std::max(u1 - d1, -kDisUmax), kDisUmax);
+                }
+                ux[j * ox.size() + i] = u0;
+                uy[j * ox.size() + i] = u1;
+            }
+        // densification
+        std::vector<double> nfx((size_t)w * h), nfy((size_t)w * h);
+        for (int Y = 0; Y < h; ++Y)
+            for (int X = 0; X < w; ++X) {
+                double n0 = 0.0, n1 = 0.0, den = 0.0;
+                for (size_t j = 0; j < oy.size(); ++j) {
+                    if (oy[j] > Y || oy[j] + kDisP <= Y) continue;
+                    for (size_t i = 0; i < ox.size(); ++i) {
+                        if (ox[i] > X || ox[i] + kDisP <= X) continue;
+                        const double u0 = ux[j * ox.size() + i], u1 = uy[j * ox.size() + i];
+                        const double e = bilin(J, X + u0, Y + u1) - I.at(X, Y);
+                        const double wgt = 1.0 / std::max(1.0, std::fabs(e));
+                        n0 += wgt * u0;
+                        n1 += wgt * u1;
+                        den += wgt;
+                    }
+                }
+                nfx[(size_t)Y * w + X] = n0 / den;
+                nfy[(size_t)Y * w + X] = n1 / den;
+            }
+        cfx.swap(nfx);
+        cfy.swap(nfy);
+        cw = w;
+        ch = h;
+    }
+    fx.swap(cfx);
+    fy.swap(cfy);
+}
+
+// The pair measure with the dense flow: NCC of I against J warped by the
+// flow (bilinear), over every pixel, AMM = mean flow magnitude, SWR, ACT;
+// static if 256 AMM < a_static_fx (the block reading's threshold).
+void flow_measure(const Plane& I, const Plane& J, const orc_params& p, PairOut& o, std::vector<double>* flow) {
+    o = PairOut();
+    const int w = I.w, h = I.h;
+    if (w < kDisP || h < kDisP || J.w != w || J.h != h) { o.ok = false; return; }
+    std::vector<double> fx, fy;
+    dis_flow(I, J, fx, fy);
+    double sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0, sm = 0;
+    for (int Y = 0; Y < h; ++Y) {
+        double rx = 0, ry = 0, rxx = 0, ryy = 0, rxy = 0, rm = 0;
+        for (int X = 0; X < w; ++X) {
+            const double u0 = fx[(size_t)Y * w + X], u1 = fy[(size_t)Y * w + X];
+            const double x = I.at(X, Y);
+            const double y = bilin(J, X + u0, Y + u1);
+            rx += x; ry += y; rxx += x * x; ryy += y * y; rxy += x * y;
+            rm += std::sqrt(u0 * u0 + u1 * u1);
+        }
+        sx += rx; sy += ry; sxx += rxx; syy += ryy; sxy += rxy; sm += rm;
+    }
+    const double n = (double)w * h;
+    const double cov = n * sxy - sx * sy;
+    const double vx = n * sxx - sx * sx;
+    const double vy = n * syy - sy * sy;
+    double ncc;
+    if (vx <= 0.0 && vy <= 0.0) ncc = 1.0;
+    else if (vx <= 0.0 || vy <= 0.0) ncc = 0.0;
+    else {
+        const double c = cov / std::sqrt(vx * vy);
+        ncc = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    }
+    o.ncc = ncc;
+    o.swr = 1.0 - ncc;
+    o.amm = sm / n;
+    o.act = std::sqrt((o.amm + p.a0) * o.swr);
+    o.is_static = 256.0 * o.amm < (double)p.a_static_fx;
+    o.n = (int64_t)w * h;
+    if (flow) {
+        flow->resize((size_t)2 * w * h);
+        for (size_t i = 0; i < (size_t)w * h; ++i) { (*flow)[2 * i] = fx[i]; (*flow)[2 * i + 1] = fy[i]; }
+    }
+}
+
 struct Meas { double act = 0, swr = 0; };
 
 // Source of the pair measures used by the sequential pass.
@@ -608,8 +786,10 @@ struct FrameProvider : Provider {
         const FrameLevels* b = get(oth);
         if (!a || !b) return false;
         PairOut o;
-        // field pairs keep the full search; frame pairs follow p.search
-        pair_measure(plane(*a, rf, level), plane(*b, of, level), p, false, p.search == 1 && kind != 1, o);
+        // search 2: the dense flow for every pair; else field pairs keep the
+        // full search and frame pairs follow p.search
+        if (p.search == 2) flow_measure(plane(*a, rf, level), plane(*b, of, level), p, o, nullptr);
+        else pair_measure(plane(*a, rf, level), plane(*b, of, level), p, false, p.search == 1 && kind != 1, o);
         if (!o.ok) return false;
         m.act = o.act; m.swr = o.swr;
         if (it == cache.end()) {
@@ -624,7 +804,7 @@ struct FrameProvider : Provider {
         Meas m;
         if (!measure(0, t, 0, t + 1, 0, g.L, m, &o)) return false;
         fill_pair_record(r, o);
-        if (mv_out) std::memcpy(mv_out + (size_t)t * o.mv.size(), o.mv.data(), o.mv.size());
+        if (mv_out && !o.mv.empty()) std::memcpy(mv_out + (size_t)t * o.mv.size(), o.mv.data(), o.mv.size());
         return true;
     }
     bool field(int t, int which, Meas& m) override {
@@ -685,7 +865,7 @@ struct InjectedProvider : Provider {
 bool params_ok(const orc_params* p) {
     return p && p->block == 8 && p->radius >= 0 && p->radius <= 16 && p->k_max >= 1 &&
            p->k_max <= 64 && p->w_hist >= 1 && p->n_ss >= 1 && p->lf_offset >= 0 && p->tau_p >= 1.0 &&
-           (p->search == 0 || p->search == 1) && p->refine >= 0 && 2 * p->radius + p->refine <= 127;
+           p->search >= 0 && p->search <= 2 && p->refine >= 0 && 2 * p->radius + p->refine <= 127;
 }
 
 int export_results(const std::vector<orc_frame_rec>& recs, const std::vector<orc_shot_rec>& shots,
@@ -775,6 +955,23 @@ int32_t orc_pair(const uint16_t* I, const uint16_t* J, int32_t w, int32_t h, con
         std::memcpy(ints, v, sizeof v);
     }
     if (dbl) { dbl[0] = o.ncc; dbl[1] = o.swr; dbl[2] = o.amm; dbl[3] = o.act; }
+    return 0;
+}
+
+int32_t orc_flow_pair(const uint16_t* I, const uint16_t* J, int32_t w, int32_t h, const orc_params* p,
+                      double* flow, double* dbl, int32_t* is_static) {
+    if (!I || !J || !params_ok(p) || w < kDisP || h < kDisP) return -1;
+    Plane a, b;
+    a.w = b.w = w; a.h = b.h = h;
+    a.px.assign(I, I + (size_t)w * h);
+    b.px.assign(J, J + (size_t)w * h);
+    PairOut o;
+    std::vector<double> f;
+    flow_measure(a, b, *p, o, flow ? &f : nullptr);
+    if (!o.ok) return -1;
+    if (flow) std::memcpy(flow, f.data(), f.size() * sizeof(double));
+    if (dbl) { dbl[0] = o.ncc; dbl[1] = o.swr; dbl[2] = o.amm; dbl[3] = o.act; }
+    if (is_static) *is_static = o.is_static ? 1 : 0;
     return 0;
 }
 

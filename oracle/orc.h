@@ -41,9 +41,11 @@ typedef struct {
     double eps;           /* class fraction margin                             */
     double tau_p;         /* pulldown: combed positions' mean v0 ratio          */
     double theta_kf;      /* keyframe threshold on accumulated ACT             */
-    int32_t search;       /* frame-pair motion field: 0 full search over [-R, R]^2;
-                             1 coarse-to-fine: full search on the 2x2-box image one
-                             level coarser, then +-refine around twice that vector */
+    int32_t search;       /* motion field: 0 full search over [-R, R]^2 (every pair);
+                             1 coarse-to-fine for frame pairs: full search on the 2x2-box
+                             image one level coarser, then +-refine around twice that
+                             vector (field pairs: full search);
+                             2 dense inverse search flow for every pair (orc_flow_pair) */
     int32_t refine;       /* refinement radius r of the coarse-to-fine search   */
 } orc_params;
 
@@ -116,6 +118,12 @@ int32_t orc_pair(const uint16_t* I, const uint16_t* J, int32_t w, int32_t h,
                  int8_t* mv, int32_t* sad, int64_t* ints, double* dbl);
 
 /* NCC, SWR, AMM, ACT from the exact integers (Sx, Sy, Sxx, Syy, Sxy, N, A, B). */
+/* Pair measure with the dense inverse search flow (search = 2): flow (w x h
+ * x 2 doubles: dx, dy per pixel; nullable), dbl: NCC, SWR, AMM, ACT,
+ * *is_static (nullable).  Planes at least 8 x 8. */
+int32_t orc_flow_pair(const uint16_t* I, const uint16_t* J, int32_t w, int32_t h, const orc_params* p,
+                      double* flow, double* dbl, int32_t* is_static);
+
 int32_t orc_finish(const int64_t* ints8, double a0, double* out4);
 
 /* The offline sequential pass over a whole clip.  frames: T planes of

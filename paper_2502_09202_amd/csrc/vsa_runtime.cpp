@@ -176,7 +176,8 @@ vsa_status check_params(const vsa_params& p) {
     if (p.w_hist < 1 || p.w_hist > kMaxHist) return fail(VSA_E_INVAL, "w_hist must be in 1..16");
     if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
     if (!(p.tau_p >= 1.0)) return fail(VSA_E_INVAL, "tau_p must be >= 1");
-    if (p.search != 0 && p.search != 1) return fail(VSA_E_INVAL, "search must be 0 or 1");
+    if (p.search < 0 || p.search > 2) return fail(VSA_E_INVAL, "search must be 0, 1 or 2");
+    if (p.search == 2) return fail(VSA_E_UNSUPPORTED, "the dense flow (search 2) runs only as a single pair measure");
     if (p.search == 1 && p.refine != 1) return fail(VSA_E_UNSUPPORTED, "the coarse-to-fine search refines by 1");
     return VSA_OK;
 }

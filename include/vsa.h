@@ -436,6 +436,40 @@ vsa_status vsa_debug_pair(const vsa_params* p, const uint16_t* I, const uint16_t
                           int32_t h, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
                           int32_t* sad, int64_t* ints, double* dbl);
 
+/* Dense inverse search flow pair measure (Sec. III.A: the paper's motion
+ * field is dense inverse search optical flow, its reference [8]), with fixed
+ * work so that it is exactly reproducible: the pair's planes and up to two
+ * 2x2-box-downscaled copies, coarsest first; 8 x 8 patches every 4 samples
+ * (plus one flush with the right and bottom edges); per patch eight
+ * inverse-compositional steps u <- u - H^-1 sum g (J(x + u) - T(x)),
+ * H = sum g g^T + 64 I, central-difference gradients, J sampled bilinearly
+ * with clamped coordinates, components clamped to +-32; the flow at a pixel
+ * is the mean of the covering patches' vectors weighted by
+ * 1 / max(1, |J(x + u) - I(x)|).  Measures: NCC of I against J warped by the
+ * flow over every pixel, SWR = 1 - NCC, AMM = mean flow length (pixels of
+ * the plane), ACT = sqrt((AMM + a0) SWR); static if 256 AMM < a_static_fx.
+ * IEEE double, sums in a fixed order: the results are bitwise those of the
+ * sequential definition.
+ *
+ * vsa_flow_scratch_bytes: device bytes the measure of a w x h pair needs
+ * (w, h >= 8), or VSA_E_INVAL.
+ * vsa_flow_pair: I, J device planes of w x h samples (bits 8: bytes, 10:
+ * uint16 words, 2-byte aligned) with a row pitch in bytes; scratch: device
+ * memory of at least vsa_flow_scratch_bytes (the caller's, not kept);
+ * flow: device w x h x 2 doubles (dx, dy interleaved, pixels of the plane) or
+ * NULL; results: device 5 doubles (NCC, SWR, AMM, ACT, static 0/1).  Only
+ * a0 and a_static_fx of p are read (NULL = defaults).  Enqueued on
+ * hip_stream (NULL = the null stream); no allocation, no synchronisation.
+ * vsa_debug_flow_pair: the same from host planes of uint16 samples (w x h,
+ * dense), synchronous; flow (w x h x 2, nullable), dbl (NCC, SWR, AMM, ACT),
+ * is_static (nullable) are host arrays. */
+int64_t vsa_flow_scratch_bytes(int32_t w, int32_t h);
+vsa_status vsa_flow_pair(const vsa_params* p, const void* I, const void* J, int32_t w, int32_t h,
+                         int64_t pitch_bytes, int32_t bits, void* scratch, int64_t scratch_bytes,
+                         double* flow, double* results, void* hip_stream);
+vsa_status vsa_debug_flow_pair(const vsa_params* p, const uint16_t* I, const uint16_t* J, int32_t w,
+                               int32_t h, int32_t bits, double* flow, double* dbl, int32_t* is_static);
+
 /* How vsa_clip_run splits an n_frames clip at this chunk size (0 = 256):
  * chunk i covers frames starts[i] .. starts[i] + counts[i] - 1, for the first
  * min(count, cap) chunks (arrays of cap entries, the caller's; NULL with cap

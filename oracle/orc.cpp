@@ -418,10 +418,10 @@ void dis_flow(const Plane& I0, const Plane& J0, std::vector<double>& fx, std::ve
         for (int Y = 0; Y < h; ++Y)
             for (int X = 0; X < w; ++X) {
                 double n0 = 0.0, n1 = 0.0, den = 0.0;
-                for (size_t j = 0; j < oy.size(); ++j) {
-                    if (oy[j] > Y || oy[j] + kDisP <= Y) continue;
-                    for (size_t i = 0; i < ox.size(); ++i) {
-                        if (ox[i] > X || ox[i] + kDisP <= X) continue;
+                for (size_t j = 0; j < oy.size() && oy[j] <= Y; ++j) {      // origins ascend
+                    if (oy[j] + kDisP <= Y) continue;
+                    for (size_t i = 0; i < ox.size() && ox[i] <= X; ++i) {
+                        if (ox[i] + kDisP <= X) continue;
                         const double u0 = ux[j * ox.size() + i], u1 = uy[j * ox.size() + i];
                         const double e = bilin(J, X + u0, Y + u1) - I.at(X, Y);
                         const double wgt = 1.0 / std::max(1.0, std::fabs(e));

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvsa.so")
-SOURCES = ["k_pyramid.hip", "k_me.hip", "k_decide.hip", "noalloc.hip", "vsa_runtime.cpp"]
+SOURCES = ["k_pyramid.hip", "k_me.hip", "k_decide.hip", "k_flow.hip", "noalloc.hip", "vsa_runtime.cpp"]
 ARCH = os.environ.get("VSA_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: the finishing arithmetic and every decision threshold

@@ -53,6 +53,9 @@ hipError_t launch_me(int bits, const StreamDesc*, const TileJob*, int32_t, const
                      const DeviceCursors*, int32_t, bool, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                      LaunchTiming = {});
 int me_hier_max_wgs_per_cu(int bits);
+int64_t flow_scratch_bytes(int w, int h);
+hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, int64_t pitch, int bits, double a0,
+                            int a_static_fx, uint8_t* scratch, double* flow_out, double* res_out, hipStream_t s);
 hipError_t launch_me_hier(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
                           const DeviceCursors*, int32_t, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                           LaunchTiming = {});
@@ -1556,6 +1559,64 @@ vsa_status vsa_debug_levels(const vsa_params* pp, const void* luma, int32_t W, i
     for (int d = 0; d < sd.nlev; ++d) put(sd.off[d], sd.wl[d], sd.hl[d], sd.pl[d]);
     put(sd.offU, sd.wf, sd.hf, sd.pf);
     put(sd.offD, sd.wf, sd.hf, sd.pf);
+    return VSA_OK;
+}
+
+int64_t vsa_flow_scratch_bytes(int32_t w, int32_t h) {
+    if (w < 8 || h < 8) return fail(VSA_E_INVAL, "plane smaller than one 8 x 8 patch");
+    return flow_scratch_bytes(w, h);
+}
+
+vsa_status vsa_flow_pair(const vsa_params* pp, const void* I, const void* J, int32_t w, int32_t h, int64_t pitch_bytes,
+                         int32_t bits, void* scratch, int64_t scratch_bytes, double* flow, double* results,
+                         void* hip_stream) {
+    if (!I || !J || !scratch || !results || (bits != 8 && bits != 10)) return fail(VSA_E_INVAL, "bad argument");
+    if (w < 8 || h < 8) return fail(VSA_E_INVAL, "plane smaller than one 8 x 8 patch");
+    if (pitch_bytes < (int64_t)w * (bits == 8 ? 1 : 2)) return fail(VSA_E_INVAL, "pitch smaller than a row");
+    if (bits == 10 && ((pitch_bytes & 1) || (reinterpret_cast<uintptr_t>(I) & 1) || (reinterpret_cast<uintptr_t>(J) & 1)))
+        return fail(VSA_E_INVAL, "10-bit planes and pitch must be 2-byte aligned");
+    if (scratch_bytes < flow_scratch_bytes(w, h)) return fail(VSA_E_INVAL, "scratch smaller than vsa_flow_scratch_bytes");
+    vsa_params p;
+    if (pp) p = *pp; else vsa_default_params(&p);
+    HIPCK(launch_flow_pair(static_cast<const uint8_t*>(I), static_cast<const uint8_t*>(J), w, h, pitch_bytes, bits,
+                           p.a0, p.a_static_fx, static_cast<uint8_t*>(scratch), flow, results,
+                           static_cast<hipStream_t>(hip_stream)),
+          "flow pair launch");
+    return VSA_OK;
+}
+
+vsa_status vsa_debug_flow_pair(const vsa_params* pp, const uint16_t* I, const uint16_t* J, int32_t w, int32_t h,
+                               int32_t bits, double* flow, double* dbl, int32_t* is_static) {
+    if (!I || !J || (bits != 8 && bits != 10) || w < 8 || h < 8) return fail(VSA_E_INVAL, "bad argument");
+    const int maxv = bits == 8 ? 255 : 1023;
+    for (int64_t i = 0; i < (int64_t)w * h; ++i)
+        if (I[i] > maxv || J[i] > maxv) return fail(VSA_E_INVAL, "sample out of range");
+    const int64_t n = (int64_t)w * h;
+    const int64_t sb = flow_scratch_bytes(w, h);
+    uint8_t *dI = nullptr, *dJ = nullptr, *scr = nullptr;
+    double *dflow = nullptr, *dres = nullptr;
+    hipError_t err = hipMalloc(&dI, 2 * n);
+    if (err == hipSuccess) err = hipMalloc(&dJ, 2 * n);
+    if (err == hipSuccess) err = hipMalloc(&scr, sb);
+    if (err == hipSuccess && flow) err = hipMalloc(&dflow, sizeof(double) * 2 * n);
+    if (err == hipSuccess) err = hipMalloc(&dres, sizeof(double) * 5);
+    if (err == hipSuccess) err = hipMemcpy(dI, I, 2 * n, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(dJ, J, 2 * n, hipMemcpyHostToDevice);
+    vsa_status st = VSA_OK;
+    if (err == hipSuccess) {
+        // the samples go in as 16-bit words whatever their width
+        st = vsa_flow_pair(pp, dI, dJ, w, h, 2 * (int64_t)w, 10, scr, sb, dflow, dres, nullptr);
+        if (st == VSA_OK) err = hipDeviceSynchronize();
+    }
+    double res[5] = {0, 0, 0, 0, 0};
+    if (err == hipSuccess && st == VSA_OK) err = hipMemcpy(res, dres, sizeof res, hipMemcpyDeviceToHost);
+    if (err == hipSuccess && st == VSA_OK && flow) err = hipMemcpy(flow, dflow, sizeof(double) * 2 * n, hipMemcpyDeviceToHost);
+    for (void* q : {(void*)dI, (void*)dJ, (void*)scr, (void*)dflow, (void*)dres})
+        if (q) (void)hipFree(q);
+    if (st != VSA_OK) return st;
+    if (err != hipSuccess) return fail(VSA_E_DEVICE, hipGetErrorString(err));
+    if (dbl) { dbl[0] = res[0]; dbl[1] = res[1]; dbl[2] = res[2]; dbl[3] = res[3]; }
+    if (is_static) *is_static = res[4] != 0.0 ? 1 : 0;
     return VSA_OK;
 }
 

@@ -86,6 +86,7 @@ SYMBOLS = [
     "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
     "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_get_histogram", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
+    "vsa_flow_scratch_bytes", "vsa_flow_pair", "vsa_debug_flow_pair",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
     "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters", "vsa_clip_debug_log",
     "vsa_debug_clip_chunks", "vsa_pair_noalloc",
@@ -134,6 +135,9 @@ def lib():
         "vsa_last_error": (C.c_char_p, []),
         "vsa_debug_levels": (i32, [C.POINTER(Params), P, i32, i32, i64, i32, P, i64, C.POINTER(i64)]),
         "vsa_debug_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i32, i32, P, P, P, P]),
+        "vsa_flow_scratch_bytes": (i64, [i32, i32]),
+        "vsa_flow_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i64, i32, P, i64, P, P, P]),
+        "vsa_debug_flow_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i32, P, P, P]),
         "vsa_debug_finish": (i32, [P, i64, C.c_double, P]),
         "vsa_debug_decide": (i32, [C.POINTER(Params), i32, i32, i32, P, P, P, P, P, P, P, P, P, i32,
                                    C.POINTER(i32), P, i32, C.POINTER(i32)]),
@@ -509,6 +513,41 @@ def debug_pair(I: np.ndarray, J: np.ndarray, params: Optional[dict] = None, bit_
     out["mv"] = mv[:B].reshape(h // 8, w // 8, 2)
     out["sad"] = sad[:B].reshape(h // 8, w // 8)
     return out
+
+
+def debug_flow_pair(I: np.ndarray, J: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8) -> dict:
+    """Dense inverse search flow pair measure of two host planes (see
+    vsa_debug_flow_pair): {"flow": [h, w, 2], "ncc", "swr", "amm", "act", "static"}."""
+    I = np.ascontiguousarray(I, dtype=np.uint16)
+    J = np.ascontiguousarray(J, dtype=np.uint16)
+    h, w = I.shape
+    flow = np.zeros((h, w, 2), np.float64)
+    dbl = np.zeros(4, np.float64)
+    st = C.c_int32(0)
+    p = make_params(params)
+    _check(lib().vsa_debug_flow_pair(C.byref(p), _ptr(I), _ptr(J), w, h, bit_depth, _ptr(flow), _ptr(dbl),
+                                     C.byref(st)), "debug_flow_pair")
+    return {"flow": flow, "ncc": float(dbl[0]), "swr": float(dbl[1]), "amm": float(dbl[2]), "act": float(dbl[3]),
+            "static": int(st.value)}
+
+
+def flow_scratch_bytes(w: int, h: int) -> int:
+    return _check(lib().vsa_flow_scratch_bytes(w, h), "flow_scratch_bytes")
+
+
+def flow_pair(I, J, scratch, results, params: Optional[dict] = None, flow=None, stream: Optional[int] = None):
+    """Enqueue the flow pair measure of two CUDA tensors [h, w] (uint8, or
+    int16/uint16 holding 10-bit samples) into `results` (CUDA float64 [5]),
+    using `scratch` (CUDA uint8, at least flow_scratch_bytes) and, if given,
+    `flow` (CUDA float64 [h, w, 2])."""
+    h, w = I.shape
+    bits = 8 if I.element_size() == 1 else 10
+    p = make_params(params)
+    _check(lib().vsa_flow_pair(C.byref(p), C.c_void_p(I.data_ptr()), C.c_void_p(J.data_ptr()), w, h,
+                               I.stride(0) * I.element_size(), bits, C.c_void_p(scratch.data_ptr()),
+                               scratch.numel(), None if flow is None else C.c_void_p(flow.data_ptr()),
+                               C.c_void_p(results.data_ptr()), None if stream is None else C.c_void_p(stream)),
+           "flow_pair")
 
 
 def debug_finish(ints: np.ndarray, a0: float) -> np.ndarray:

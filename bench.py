@@ -197,6 +197,77 @@ def run_mix(vsa, clips, params, steps, warmup, torch):
     return pushed / dt, pushed, {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}
 
 
+def flow_ops(w, h):
+    """Double-precision operations of one dense-flow pair measure of a w x h
+    pair (the kernels' arithmetic, counted per operation: add, sub, mul, div,
+    sqrt, min, max, floor, abs): a bilinear sample is 17; an inverse-
+    compositional step is 26 per patch pixel plus 16 for the 2 x 2 solve; a
+    patch's Hessian 8 per pixel; densification 28 per covering patch of a
+    pixel plus 2; the measure sums 32 per pixel.  Scales: the pair's and up to
+    two box-downscaled copies at least 8 x 8."""
+    def origins(n):
+        if n < 8:
+            return 0
+        k = (n - 8) // 4 + 1
+        return k + (1 if (k - 1) * 4 + 8 < n else 0)
+
+    def cover(n):
+        k = (n - 8) // 4 + 1
+        extra = origins(n) > k
+        tot = 0
+        for x in range(n):
+            lo = (x - 4) // 4 if x >= 8 else 0
+            hi = min(k - 1, x // 4)
+            tot += max(0, hi - lo + 1) + (1 if extra and x >= n - 8 else 0)
+        return tot
+
+    ops = 0
+    cw, ch = w, h
+    for k in range(3):
+        if k > 0:
+            cw, ch = cw // 2, ch // 2
+            if cw < 8 or ch < 8:
+                break
+        npatch = origins(cw) * origins(ch)
+        ops += npatch * (64 * 8 + 8 * (64 * 26 + 16) + 2)
+        ops += cover(cw) * cover(ch) * 28 + 2 * cw * ch
+    return ops + 32 * w * h
+
+
+def run_flow(vsa, dev_frames, params, torch, pairs=64, warmup=8):
+    """Dense-flow pair measures (search = 2) of consecutive 2K frames at the
+    working level (512 x 270, two box steps of the frames, formed on the device
+    before timing), one after another on one HIP stream; returns pairs/s, ms
+    per pair and the double-precision operation rate."""
+    x = dev_frames[: pairs + warmup + 1].to(torch.int32)
+    for _ in range(2):
+        x = (x[:, 0::2, 0::2][:, : x.shape[1] // 2, : x.shape[2] // 2] + x[:, 1::2, 0::2][:, : x.shape[1] // 2, : x.shape[2] // 2]
+             + x[:, 0::2, 1::2][:, : x.shape[1] // 2, : x.shape[2] // 2] + x[:, 1::2, 1::2][:, : x.shape[1] // 2, : x.shape[2] // 2]
+             + 2) >> 2
+    lv = x.to(torch.uint8).contiguous()
+    n, h, w = lv.shape
+    p = dict(params, search=2)
+    scratch = torch.empty(vsa.flow_scratch_bytes(w, h), dtype=torch.uint8, device="cuda:0")
+    res = torch.zeros((n, 5), dtype=torch.float64, device="cuda:0")
+    st = torch.cuda.Stream()
+    for t in range(warmup):
+        vsa.flow_pair(lv[t], lv[t + 1], scratch, res[t], p, stream=st.cuda_stream)
+    st.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for t in range(warmup, warmup + pairs):
+        vsa.flow_pair(lv[t], lv[t + 1], scratch, res[t], p, stream=st.cuda_stream)
+    e1.record(st)
+    st.synchronize()
+    ms = e0.elapsed_time(e1) / pairs
+    ops = flow_ops(w, h)
+    return {"workload": f"dense inverse search flow pair measure (search = 2) of consecutive frames of the 2K clip "
+                        f"at the working level ({w} x {h}, 8-bit), one pair after another on one HIP stream",
+            "pairs_per_s": round(1e3 / ms, 1), "ms_per_pair": round(ms, 4),
+            "fp64_ops_per_pair": ops, "fp64_gops": round(ops / (ms * 1e-3) / 1e9, 2),
+            "fp64_peak_gops": 78600.0, "frac": round(ops / (ms * 1e-3) / 1e9 / 78600.0, 5)}
+
+
 def run_stress(vsa, params, B, frames_per_stream, seg, torch,
                configs=(("sparse", False, 0), ("dense", True, 0))):
     """The 4K 10-bit 50i clip (its full length) cut into B consecutive pieces,
@@ -527,6 +598,7 @@ def main():
                     help="persistent motion-search workgroups per CU for every batched run (0: the engine's tuner)")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end run from pinned host memory")
     ap.add_argument("--no-hier", action="store_true", help="skip the coarse-to-fine (search = 1) batched run")
+    ap.add_argument("--no-flow", action="store_true", help="skip the dense-flow pair measure timing")
     ap.add_argument("--e2e-steps", type=int, default=40)
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-kernel figures of a rocprofv3 kernel-trace or counter CSV of this command "
@@ -628,6 +700,10 @@ def main():
             "ad_per_pair": ad_pair, "ad_per_pair_full_search": ad_full}
         print(f"[bench] coarse-to-fine B={args.streams}: {args.streams * args.steps / hdt:.0f} frames/s, "
               f"consecutive launch {avg * 1e3:.1f} us", file=sys.stderr, flush=True)
+    if not args.no_flow:
+        extra["dense_flow_pair"] = run_flow(vsa, dev, params, torch)
+        print(f"[bench] dense flow pair: {extra['dense_flow_pair']['ms_per_pair']:.3f} ms per 512x270 pair",
+              file=sys.stderr, flush=True)
     if not args.no_intensity_leg:
         # the same batched run without the unary intensity measure (no decision uses it)
         ndt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,

@@ -117,6 +117,12 @@ typedef struct {
                                   vsa_get_histogram fails with VSA_E_STATE; 0: computed      */
     int32_t profile_every;     /* with profile: time the launches of one step in this many
                                   (0 or 1: every step); timing events cost device time      */
+    const char* params_json;   /* non-NULL: the parameters as a JSON object of the fields of
+                                  vsa_params (vsa_params_from_json), used instead of params  */
+    const char* autotune_cache;/* non-NULL: a text file of the launch tuner's choices, one per
+                                  (compute units, search, step size bucket); read at create
+                                  (a bucket found there is not tuned again) and appended as
+                                  buckets settle.  Missing or unreadable: tuned as without   */
 } vsa_engine_config;
 
 enum { VSA_SCHEDULE_SPARSE = 0, VSA_SCHEDULE_DENSE = 1 };
@@ -186,6 +192,13 @@ int32_t vsa_abi_version(void);
 
 /* Fill *out with the built-in parameter defaults. */
 void vsa_default_params(vsa_params* out);
+
+/* The parameters from a JSON object whose keys are vsa_params' field names
+ * (integers for the int32 fields, numbers for the doubles); fields it does
+ * not name keep their defaults.  VSA_E_INVAL (out unchanged) for a syntax
+ * error, an unknown key, a non-integer int32 field or a value out of int32
+ * range.  The package's params/default.json is such an object. */
+vsa_status vsa_params_from_json(const char* json, vsa_params* out);
 
 /* Create an engine on cfg->device; allocates the engine-wide device buffers.
  * Errors: VSA_E_INVAL (NULL, bad sizes), VSA_E_UNSUPPORTED (params the kernels

@@ -380,6 +380,7 @@ struct vsa_engine {
     bool no_intensity = false;         // skip the unary intensity measure
     struct TuneBucket { double ms[kTuneN] = {}; int n[kTuneN] = {}; int best = -1; };   // ms: shortest window
     TuneBucket tune[32];
+    std::string tune_cache;            // the tuner's choices on disk (empty: none)
     struct TunePending { hipEvent_t ev0 = nullptr, ev1 = nullptr; int bucket = -1, cand = -1; };
     TunePending tune_ring[kTuneRing];
     int tune_head = 0;
@@ -613,6 +614,65 @@ void vsa_default_params(vsa_params* p) {
     p->search = 0; p->refine = 1;
 }
 
+static void tune_cache_load(vsa_engine* e);
+
+vsa_status vsa_params_from_json(const char* json, vsa_params* out) {
+    if (!json || !out) return fail(VSA_E_INVAL, "NULL argument");
+    vsa_params p;
+    vsa_default_params(&p);
+    struct IntField { const char* name; int32_t* v; };
+    struct DblField { const char* name; double* v; };
+    const IntField ints[] = {{"block", &p.block}, {"radius", &p.radius}, {"wmax", &p.wmax},
+                             {"lf_offset", &p.lf_offset}, {"k_max", &p.k_max}, {"a_static_fx", &p.a_static_fx},
+                             {"w_hist", &p.w_hist}, {"n_ss", &p.n_ss}, {"search", &p.search}, {"refine", &p.refine}};
+    const DblField dbls[] = {{"a0", &p.a0}, {"rho_f", &p.rho_f}, {"theta_f", &p.theta_f},
+                             {"theta_f0", &p.theta_f0}, {"rho_d", &p.rho_d}, {"theta_d", &p.theta_d},
+                             {"gamma", &p.gamma}, {"tau_c", &p.tau_c}, {"eps", &p.eps}, {"tau_p", &p.tau_p},
+                             {"theta_kf", &p.theta_kf}};
+    const char* c = json;
+    auto ws = [&]() { while (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r') ++c; };
+    ws();
+    if (*c++ != '{') return fail(VSA_E_INVAL, "params JSON: expected '{'");
+    ws();
+    if (*c == '}') { ++c; ws(); if (*c) return fail(VSA_E_INVAL, "params JSON: text after the object"); *out = p; return VSA_OK; }
+    for (;;) {
+        ws();
+        if (*c++ != '"') return fail(VSA_E_INVAL, "params JSON: expected a key");
+        const char* k0 = c;
+        while (*c && *c != '"') ++c;
+        if (!*c) return fail(VSA_E_INVAL, "params JSON: unterminated key");
+        const std::string key(k0, c - k0);
+        ++c;
+        ws();
+        if (*c++ != ':') return fail(VSA_E_INVAL, "params JSON: expected ':'");
+        ws();
+        char* end = nullptr;
+        const double v = std::strtod(c, &end);
+        if (end == c) return fail(VSA_E_INVAL, "params JSON: expected a number");
+        const std::string lit(c, end - c);
+        c = end;
+        bool found = false;
+        for (const IntField& f : ints)
+            if (key == f.name) {
+                if (lit.find_first_of(".eE") != std::string::npos || v < -2147483648.0 || v > 2147483647.0)
+                    return fail(VSA_E_INVAL, "params JSON: " + key + " must be an int32");
+                *f.v = (int32_t)v;
+                found = true;
+            }
+        for (const DblField& f : dbls)
+            if (key == f.name) { *f.v = v; found = true; }
+        if (!found) return fail(VSA_E_INVAL, "params JSON: unknown key " + key);
+        ws();
+        if (*c == ',') { ++c; continue; }
+        if (*c == '}') { ++c; break; }
+        return fail(VSA_E_INVAL, "params JSON: expected ',' or '}'");
+    }
+    ws();
+    if (*c) return fail(VSA_E_INVAL, "params JSON: text after the object");
+    *out = p;
+    return VSA_OK;
+}
+
 vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     if (!cfg || !out) return fail(VSA_E_INVAL, "NULL argument");
     *out = nullptr;
@@ -626,7 +686,14 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     if (cfg->me_wgs_per_cu < 0 || cfg->me_wgs_per_cu > 8)
         return fail(VSA_E_INVAL, "me_wgs_per_cu must be in 0..8");
     vsa_params p;
-    if (cfg->params) p = *cfg->params; else vsa_default_params(&p);
+    if (cfg->params_json) {
+        const vsa_status sj = vsa_params_from_json(cfg->params_json, &p);
+        if (sj != VSA_OK) return sj;
+    } else if (cfg->params) {
+        p = *cfg->params;
+    } else {
+        vsa_default_params(&p);
+    }
     vsa_status st = check_params(p);
     if (st != VSA_OK) return st;
     int ndev = 0;
@@ -651,6 +718,10 @@ vsa_status vsa_engine_create(const vsa_engine_config* cfg, vsa_engine** out) {
     e->me_grid = cus * 8;
     e->me_fixed = cfg->me_wgs_per_cu;
     e->no_intensity = cfg->no_intensity != 0;
+    if (cfg->autotune_cache) {
+        e->tune_cache = cfg->autotune_cache;
+        tune_cache_load(e);
+    }
     const int M = cfg->max_streams;
     auto dalloc = [&](void** p_, size_t n) { return hipMalloc(p_, n) == hipSuccess; };
     bool ok = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess;
@@ -971,6 +1042,35 @@ static inline uint64_t now_ns() {
                std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// The tuner's cache file: one line per settled bucket, "cus S search S bucket
+// B consec C sparse P" (workgroups per CU of the two grids).  A line counts
+// only for this device's CU count and search mode, and only if its pair is
+// one of the candidates; later lines win.
+static void tune_cache_load(vsa_engine* e) {
+    FILE* f = std::fopen(e->tune_cache.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        int cus = 0, search = 0, bucket = -1, consec = 0, sparse = 0;
+        if (std::sscanf(line, "cus %d search %d bucket %d consec %d sparse %d", &cus, &search, &bucket, &consec,
+                        &sparse) != 5)
+            continue;
+        if (cus != e->cus || search != e->params.search || bucket < 0 || bucket >= 32) continue;
+        for (int c = 0; c < kTuneN; ++c)
+            if (kTuneCands[c].consec == consec && kTuneCands[c].sparse == sparse) e->tune[bucket].best = c;
+    }
+    std::fclose(f);
+}
+
+static void tune_cache_store(vsa_engine* e, int bucket, int cand) {
+    if (e->tune_cache.empty()) return;
+    FILE* f = std::fopen(e->tune_cache.c_str(), "a");
+    if (!f) return;   // the cache only saves tuning time
+    std::fprintf(f, "cus %d search %d bucket %d consec %d sparse %d\n", e->cus, e->params.search, bucket,
+                 kTuneCands[cand].consec, kTuneCands[cand].sparse);
+    std::fclose(f);
+}
+
 // Add a finished window to its bucket; once every candidate has kTuneSamples
 // windows the bucket keeps the fastest.  With wait, block for the timing.
 void tune_harvest(vsa_engine* e, vsa_engine::TunePending& t, bool wait) {
@@ -990,6 +1090,7 @@ void tune_harvest(vsa_engine* e, vsa_engine::TunePending& t, bool wait) {
                 for (int c = 1; c < kTuneN; ++c)
                     if (b.ms[c] < b.ms[best]) best = c;
                 b.best = best;
+                tune_cache_store(e, t.bucket, best);
             }
         }
     }

@@ -50,7 +50,8 @@ class EngineConfig(C.Structure):
         ("device", C.c_int32), ("max_streams", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
         ("schedule", C.c_int32), ("use_graph", C.c_int32), ("params", C.POINTER(Params)),
         ("debug_log", C.c_int32), ("me_wgs_per_cu", C.c_int32), ("profile", C.c_int32),
-        ("no_intensity", C.c_int32), ("profile_every", C.c_int32),
+        ("no_intensity", C.c_int32), ("profile_every", C.c_int32), ("params_json", C.c_char_p),
+        ("autotune_cache", C.c_char_p),
     ]
 
 
@@ -86,7 +87,7 @@ SYMBOLS = [
     "vsa_stream_done", "vsa_step", "vsa_sync", "vsa_poll_frames", "vsa_poll_shots",
     "vsa_get_motion", "vsa_stream_close", "vsa_engine_counters", "vsa_engine_tuning", "vsa_get_histogram", "vsa_last_error",
     "vsa_debug_levels", "vsa_debug_pair", "vsa_debug_finish", "vsa_debug_decide",
-    "vsa_flow_scratch_bytes", "vsa_flow_pair", "vsa_debug_flow_pair",
+    "vsa_flow_scratch_bytes", "vsa_flow_pair", "vsa_debug_flow_pair", "vsa_params_from_json",
     "vsa_debug_measure_log", "vsa_stream_push_batch", "vsa_engine_kernel_times", "vsa_collect",
     "vsa_poll_frames_all", "vsa_clip_create", "vsa_clip_destroy", "vsa_clip_run", "vsa_clip_counters", "vsa_clip_debug_log",
     "vsa_debug_clip_chunks", "vsa_pair_noalloc",
@@ -136,6 +137,7 @@ def lib():
         "vsa_debug_levels": (i32, [C.POINTER(Params), P, i32, i32, i64, i32, P, i64, C.POINTER(i64)]),
         "vsa_debug_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i32, i32, P, P, P, P]),
         "vsa_flow_scratch_bytes": (i64, [i32, i32]),
+        "vsa_params_from_json": (i32, [C.c_char_p, C.POINTER(Params)]),
         "vsa_flow_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i64, i32, P, i64, P, P, P]),
         "vsa_debug_flow_pair": (i32, [C.POINTER(Params), P, P, i32, i32, i32, P, P, P]),
         "vsa_debug_finish": (i32, [P, i64, C.c_double, P]),
@@ -205,12 +207,16 @@ class Engine:
     def __init__(self, device: int = 0, max_streams: int = 64, hbm_budget_bytes: int = 0,
                  schedule: int = SCHEDULE_SPARSE, use_graph: int = 0, params: Optional[dict] = None,
                  debug_log: int = 0, profile: int = 0, me_wgs_per_cu: int = 0, no_intensity: int = 0,
-                 profile_every: int = 0):
+                 profile_every: int = 0, params_json: Optional[str] = None,
+                 autotune_cache: Optional[str] = None):
         self._params = make_params(params)
+        self._json = None if params_json is None else params_json.encode()
+        self._cache = None if autotune_cache is None else os.fsencode(autotune_cache)
         cfg = EngineConfig(device=device, max_streams=max_streams, hbm_budget_bytes=hbm_budget_bytes,
                            schedule=schedule, use_graph=use_graph,
                            params=C.pointer(self._params), debug_log=debug_log, me_wgs_per_cu=me_wgs_per_cu,
-                           profile=profile, no_intensity=no_intensity, profile_every=profile_every)
+                           profile=profile, no_intensity=no_intensity, profile_every=profile_every,
+                           params_json=self._json, autotune_cache=self._cache)
         h = C.c_void_p()
         _check(lib().vsa_engine_create(C.byref(cfg), C.byref(h)), "engine_create")
         self.h = h
@@ -438,11 +444,11 @@ class Clip:
 
 
 def run_clip(frames: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8, dense: bool = False,
-             k_max: int = 0, device: int = 0, debug_log: bool = False, want_mv: bool = False):
+             k_max: int = 0, device: int = 0, debug_log: bool = False, want_mv: bool = False, **engine_kw):
     """Push a whole host clip [T, H, W] through one stream; returns records and shots."""
     T, H, W = frames.shape
     with Engine(device=device, max_streams=1, params=params,
-                schedule=SCHEDULE_DENSE if dense else SCHEDULE_SPARSE, debug_log=int(debug_log)) as e:
+                schedule=SCHEDULE_DENSE if dense else SCHEDULE_SPARSE, debug_log=int(debug_log), **engine_kw) as e:
         sid = e.stream_open(W, H, bit_depth, k_max)
         recs, shots, mvs = [], [], []
         for t in range(T):
@@ -513,6 +519,13 @@ def debug_pair(I: np.ndarray, J: np.ndarray, params: Optional[dict] = None, bit_
     out["mv"] = mv[:B].reshape(h // 8, w // 8, 2)
     out["sad"] = sad[:B].reshape(h // 8, w // 8)
     return out
+
+
+def params_from_json(text: str) -> dict:
+    """The library's reading of a JSON parameter object (vsa_params_from_json)."""
+    p = Params()
+    _check(lib().vsa_params_from_json(text.encode(), C.byref(p)), "params_from_json")
+    return {name: getattr(p, name) for name, _ in Params._fields_}
 
 
 def debug_flow_pair(I: np.ndarray, J: np.ndarray, params: Optional[dict] = None, bit_depth: int = 8) -> dict:

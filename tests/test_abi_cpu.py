@@ -102,3 +102,24 @@ def test_clip_without_device(vsa):
         vsa.Clip(64, 32)
     assert ei.value.code == vsa.E_DEVICE
     assert vsa.last_error()
+
+
+def test_params_from_json(vsa, params):
+    """The library reads the package's parameter file as its own defaults,
+    a partial object over the defaults, and refuses malformed objects."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(vsa.__file__), "params", "default.json")
+    got = vsa.params_from_json(open(here).read())
+    ref = vsa.params_from_json("{}")
+    assert got == ref
+    assert got == {k: params[k] for k in got}
+    part = vsa.params_from_json('{"k_max": 8, "theta_kf": 2.5e0, "search": 1}')
+    assert part["k_max"] == 8 and part["theta_kf"] == 2.5 and part["search"] == 1
+    assert {k: v for k, v in part.items() if k not in ("k_max", "theta_kf", "search")} == \
+        {k: v for k, v in ref.items() if k not in ("k_max", "theta_kf", "search")}
+    assert vsa.params_from_json(json.dumps({"rho_f": 2})) ["rho_f"] == 2.0
+    for bad in ('{"k_max": 8.5}', '{"nope": 1}', '{"k_max" 8}', '{"k_max": 8,}', '[1]', '{"k_max": 8} x',
+                '{"k_max": 3000000000}', '{"a0": }', ''):
+        with pytest.raises(vsa.VsaError):
+            vsa.params_from_json(bad)

@@ -328,14 +328,39 @@ void pair_measure(const Plane& I, const Plane& J, const orc_params& p, bool zero
 //    the patch centre halved (integer division, clamped).
 //  - Densification: the flow at a pixel is the average of the vectors of the
 //    patches covering it, weighted by 1 / max(1, |J(x + u) - I(x)|).
-//  - Sums run in a fixed order: within a patch row by row, left to right;
-//    over a plane, each row left to right, then the rows top to bottom.
+//  - Sums run in a fixed order (tree_sum): a patch's 64 terms in row-major
+//    order are added as a balanced binary tree (pairs, then pairs of pairs);
+//    a longer list (a row's pixels, then the rows' sums) is cut into runs of
+//    64 (the last one filled with zeros), each run added as that tree and
+//    the runs' sums added in order.
 constexpr int kDisP = 8;
 constexpr int kDisS = 4;
 constexpr int kDisScales = 2;
 constexpr int kDisIters = 8;
 constexpr double kDisLambda = 64.0;
 constexpr double kDisUmax = 32.0;
+
+// Balanced binary tree sum of 64 terms: adjacent pairs, then adjacent pairs
+// of those, and so on.
+double tree64(const double* v) {
+    double t[64];
+    for (int i = 0; i < 64; ++i) t[i] = v[i];
+    for (int step = 1; step < 64; step *= 2)
+        for (int i = 0; i < 64; i += 2 * step) t[i] = t[i] + t[i + step];
+    return t[0];
+}
+
+// Sum of n terms: runs of 64 (the last one filled with zeros) each added as a
+// tree, the runs' sums added in order.
+double tree_sum(const std::vector<double>& v) {
+    double acc = 0.0;
+    for (size_t c = 0; c < v.size(); c += 64) {
+        double run[64];
+        for (size_t i = 0; i < 64; ++i) run[i] = c + i < v.size() ? v[c + i] : 0.0;
+        acc = acc + tree64(run);
+    }
+    return acc;
+}
 
 // Bilinear sample of J at (X, Y), coordinates clamped to the plane.
 double bilin(const Plane& J, double X, double Y) {
@@ -384,27 +409,28 @@ void dis_flow(const Plane& I0, const Plane& J0, std::vector<double>& fx, std::ve
                     u0 = 2.0 * cfx[(size_t)cy * cw + cx];
                     u1 = 2.0 * cfy[(size_t)cy * cw + cx];
                 }
-                double gx[kDisP][kDisP], gy[kDisP][kDisP];
-                double h00 = kDisLambda, h01 = 0.0, h11 = kDisLambda;
+                double gx[kDisP * kDisP], gy[kDisP * kDisP], t0[kDisP * kDisP], t1[kDisP * kDisP],
+                    t2[kDisP * kDisP];
                 for (int y = 0; y < kDisP; ++y)
                     for (int x = 0; x < kDisP; ++x) {
-                        const int X = px + x, Y = py + y;
-                        gx[y][x] = (I.at(std::min(X + 1, w - 1), Y) - I.at(std::max(X - 1, 0), Y)) / 2.0;
-                        gy[y][x] = (I.at(X, std::min(Y + 1, h - 1)) - I.at(X, std::max(Y - 1, 0))) / 2.0;
-                        h00 += gx[y][x] * gx[y][x];
-                        h01 += gx[y][x] * gy[y][x];
-                        h11 += gy[y][x] * gy[y][x];
+                        const int X = px + x, Y = py + y, q = y * kDisP + x;
+                        gx[q] = (I.at(std::min(X + 1, w - 1), Y) - I.at(std::max(X - 1, 0), Y)) / 2.0;
+                        gy[q] = (I.at(X, std::min(Y + 1, h - 1)) - I.at(X, std::max(Y - 1, 0))) / 2.0;
+                        t0[q] = gx[q] * gx[q];
+                        t1[q] = gx[q] * gy[q];
+                        t2[q] = gy[q] * gy[q];
                     }
+                const double h00 = tree64(t0) + kDisLambda, h01 = tree64(t1), h11 = tree64(t2) + kDisLambda;
                 const double det = h00 * h11 - h01 * h01;
                 for (int it = 0; it < kDisIters; ++it) {
-                    double b0 = 0.0, b1 = 0.0;
                     for (int y = 0; y < kDisP; ++y)
                         for (int x = 0; x < kDisP; ++x) {
-                            const int X = px + x, Y = py + y;
+                            const int X = px + x, Y = py + y, q = y * kDisP + x;
                             const double e = bilin(J, X + u0, Y + u1) - I.at(X, Y);
-                            b0 += gx[y][x] * e;
-                            b1 += gy[y][x] * e;
+                            t0[q] = gx[q] * e;
+                            t1[q] = gy[q] * e;
                         }
+                    const double b0 = tree64(t0), b1 = tree64(t1);
                     const double d0 = (h11 * b0 - h01 * b1) / det;
                     const double d1 = (h00 * b1 - h01 * b0) / det;
                     u0 = std::min(std::max(u0 - d0, -kDisUmax), kDisUmax);
@@ -451,18 +477,21 @@ void flow_measure(const Plane& I, const Plane& J, const orc_params& p, PairOut& 
     if (w < kDisP || h < kDisP || J.w != w || J.h != h) { o.ok = false; return; }
     std::vector<double> fx, fy;
     dis_flow(I, J, fx, fy);
-    double sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0, sm = 0;
+    // per row the six sums over its pixels, then the same over the rows
+    std::vector<double> rows[6];
     for (int Y = 0; Y < h; ++Y) {
-        double rx = 0, ry = 0, rxx = 0, ryy = 0, rxy = 0, rm = 0;
+        std::vector<double> v[6];
         for (int X = 0; X < w; ++X) {
             const double u0 = fx[(size_t)Y * w + X], u1 = fy[(size_t)Y * w + X];
             const double x = I.at(X, Y);
             const double y = bilin(J, X + u0, Y + u1);
-            rx += x; ry += y; rxx += x * x; ryy += y * y; rxy += x * y;
-            rm += std::sqrt(u0 * u0 + u1 * u1);
+            v[0].push_back(x); v[1].push_back(y); v[2].push_back(x * x); v[3].push_back(y * y);
+            v[4].push_back(x * y); v[5].push_back(std::sqrt(u0 * u0 + u1 * u1));
         }
-        sx += rx; sy += ry; sxx += rxx; syy += ryy; sxy += rxy; sm += rm;
+        for (int k = 0; k < 6; ++k) rows[k].push_back(tree_sum(v[k]));
     }
+    const double sx = tree_sum(rows[0]), sy = tree_sum(rows[1]), sxx = tree_sum(rows[2]);
+    const double syy = tree_sum(rows[3]), sxy = tree_sum(rows[4]), sm = tree_sum(rows[5]);
     const double n = (double)w * h;
     const double cov = n * sxy - sx * sy;
     const double vx = n * sxx - sx * sx;

@@ -11,12 +11,13 @@
 // covering patches' vectors weighted by 1 / max(1, |J(x + u) - I(x)|).  The
 // measures: NCC of I against J warped by the flow, AMM = mean flow length.
 //
-// Everything is IEEE double with no contraction, every sum in a fixed order
-// (within a patch row by row; a plane row by row, then the rows in order),
-// so the results are bitwise those of a sequential evaluation.  One lane per
-// patch for the search, one per pixel for densification, one per row for
-// the measure sums.  The work is small (a 2K working level is 8 500 patches
-// per scale), so the kernels favour that exact order over bandwidth.
+// Everything is IEEE double with no contraction, every sum in a fixed order:
+// a patch's 64 terms (row-major) as a balanced binary tree, which is exactly
+// what a wavefront's butterfly of xor shuffles forms in every lane; a longer
+// list (a row's pixels, then the rows) in runs of 64 lanes (zeros past the
+// end), each run a tree, the runs' sums added in order.  One wavefront per
+// patch for the search, one lane per pixel for densification, one wavefront
+// per row for the measure sums and one for the rows.
 #include "vsa_internal.h"
 
 namespace vsa {
@@ -47,6 +48,13 @@ __device__ __forceinline__ double fbilin(const FPlane& J, double X, double Y) {
     const double top = a + fx * (b - a);
     const double bot = c + fx * (d - c);
     return top + fy * (bot - top);
+}
+
+// Balanced binary tree sum of the 64 lanes' values (lane order), in every lane.
+__device__ __forceinline__ double wave_tree(double v) {
+#pragma unroll
+    for (int step = 1; step < 64; step *= 2) v = v + __shfl_xor(v, step, 64);
+    return v;
 }
 
 // Patch origins along an axis of n samples: k * kFS while the patch fits,
@@ -81,13 +89,15 @@ __global__ void k_flow_down(const uint16_t* src, int w, int h, uint16_t* dst) {
     dst[i] = (uint16_t)(((int)r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
 }
 
-// One lane per patch: the inverse-compositional search.  cfx / cfy: the
+// One wavefront per patch (four per workgroup), lane y * 8 + x on pixel
+// (x, y) of the patch: the inverse-compositional search.  cfx / cfy: the
 // coarser scale's dense flow (cw x ch), null at the coarsest scale.
-__global__ void k_flow_patch(FPlane I, FPlane J, const double* cfx, const double* cfy, int cw, int ch,
-                             double* ux, double* uy) {
+__global__ void __launch_bounds__(256) k_flow_patch(FPlane I, FPlane J, const double* cfx, const double* cfy, int cw,
+                                                    int ch, double* ux, double* uy) {
     const int nx = forigins(I.w), ny = forigins(I.h);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nx * ny) return;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nx * ny) return;                     // the whole wavefront
+    const int lane = threadIdx.x & 63;
     const int j = p / nx, i = p - (p / nx) * nx;
     const int px = forigin(I.w, i), py = forigin(I.h, j);
     double u0 = 0.0, u1 = 0.0;
@@ -97,40 +107,25 @@ __global__ void k_flow_patch(FPlane I, FPlane J, const double* cfx, const double
         u0 = 2.0 * cfx[(int64_t)cy * cw + cx];
         u1 = 2.0 * cfy[(int64_t)cy * cw + cx];
     }
-    // central-difference gradients (exact halves of integer differences),
-    // formed again in each step rather than held per lane
-    auto grad = [&](int X, int Y, double& a, double& b) {
-        a = (fat(I, min(X + 1, I.w - 1), Y) - fat(I, max(X - 1, 0), Y)) / 2.0;
-        b = (fat(I, X, min(Y + 1, I.h - 1)) - fat(I, X, max(Y - 1, 0))) / 2.0;
-    };
-    double h00 = kFLambda, h01 = 0.0, h11 = kFLambda;
-    for (int y = 0; y < kFP; ++y)
-        for (int x = 0; x < kFP; ++x) {
-            double a, b;
-            grad(px + x, py + y, a, b);
-            h00 += a * a;
-            h01 += a * b;
-            h11 += b * b;
-        }
+    const int X = px + (lane & 7), Y = py + (lane >> 3);
+    // central-difference gradients (exact halves of integer differences)
+    const double a = (fat(I, min(X + 1, I.w - 1), Y) - fat(I, max(X - 1, 0), Y)) / 2.0;
+    const double b = (fat(I, X, min(Y + 1, I.h - 1)) - fat(I, X, max(Y - 1, 0))) / 2.0;
+    const double iv = fat(I, X, Y);
+    const double h00 = wave_tree(a * a) + kFLambda, h01 = wave_tree(a * b), h11 = wave_tree(b * b) + kFLambda;
     const double det = h00 * h11 - h01 * h01;
     for (int it = 0; it < kFIters; ++it) {
-        double b0 = 0.0, b1 = 0.0;
-        for (int y = 0; y < kFP; ++y)
-            for (int x = 0; x < kFP; ++x) {
-                const int X = px + x, Y = py + y;
-                double a, b;
-                grad(X, Y, a, b);
-                const double e = fbilin(J, X + u0, Y + u1) - fat(I, X, Y);
-                b0 += a * e;
-                b1 += b * e;
-            }
+        const double e = fbilin(J, X + u0, Y + u1) - iv;
+        const double b0 = wave_tree(a * e), b1 = wave_tree(b * e);
         const double d0 = (h11 * b0 - h01 * b1) / det;
         const double d1 = (h00 * b1 - h01 * b0) / det;
         u0 = fmin(fmax(u0 - d0, -kFUmax), kFUmax);
         u1 = fmin(fmax(u1 - d1, -kFUmax), kFUmax);
     }
-    ux[p] = u0;
-    uy[p] = u1;
+    if (lane == 0) {
+        ux[p] = u0;
+        uy[p] = u1;
+    }
 }
 
 // Patch indices covering sample X along an axis of n samples, ascending:
@@ -173,31 +168,49 @@ __global__ void k_flow_densify(FPlane I, FPlane J, const double* ux, const doubl
     fy[q] = n1 / den;
 }
 
-// One lane per row: the row's measure sums, left to right.
-__global__ void k_flow_rows(FPlane I, FPlane J, const double* fx, const double* fy, double* rows) {
-    const int Y = blockIdx.x * blockDim.x + threadIdx.x;
-    if (Y >= I.h) return;
-    double rx = 0, ry = 0, rxx = 0, ryy = 0, rxy = 0, rm = 0;
-    for (int X = 0; X < I.w; ++X) {
-        const int64_t q = (int64_t)Y * I.w + X;
-        const double u0 = fx[q], u1 = fy[q];
-        const double x = fat(I, X, Y);
-        const double y = fbilin(J, X + u0, Y + u1);
-        rx += x; ry += y; rxx += x * x; ryy += y * y; rxy += x * y;
-        rm += sqrt(u0 * u0 + u1 * u1);
+// One wavefront per row (four per workgroup): the row's six measure sums,
+// runs of 64 pixels each a tree, the runs added in order.
+__global__ void __launch_bounds__(256) k_flow_rows(FPlane I, FPlane J, const double* fx, const double* fy,
+                                                   double* rows) {
+    const int Y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (Y >= I.h) return;                         // the whole wavefront
+    const int lane = threadIdx.x & 63;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < I.w; c += 64) {
+        const int X = c + lane;
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (X < I.w) {
+            const int64_t q = (int64_t)Y * I.w + X;
+            const double u0 = fx[q], u1 = fy[q];
+            const double x = fat(I, X, Y);
+            const double y = fbilin(J, X + u0, Y + u1);
+            v[0] = x; v[1] = y; v[2] = x * x; v[3] = y * y; v[4] = x * y;
+            v[5] = sqrt(u0 * u0 + u1 * u1);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] = acc[k] + wave_tree(v[k]);
     }
-    double* r = rows + 6 * (int64_t)Y;
-    r[0] = rx; r[1] = ry; r[2] = rxx; r[3] = ryy; r[4] = rxy; r[5] = rm;
+    if (lane == 0) {
+        double* r = rows + 6 * (int64_t)Y;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r[k] = acc[k];
+    }
 }
 
-// One lane: the rows in order, then NCC, SWR, AMM, ACT and the static test.
-__global__ void k_flow_total(const double* rows, int w, int h, double a0, int a_static_fx, double* out) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0, sm = 0;
-    for (int Y = 0; Y < h; ++Y) {
-        const double* r = rows + 6 * (int64_t)Y;
-        sx += r[0]; sy += r[1]; sxx += r[2]; syy += r[3]; sxy += r[4]; sm += r[5];
+// One wavefront: the rows' sums the same way, then NCC, SWR, AMM, ACT and
+// the static test.
+__global__ void __launch_bounds__(64) k_flow_total(const double* rows, int w, int h, double a0, int a_static_fx,
+                                                   double* out) {
+    if (blockIdx.x != 0) return;
+    const int lane = threadIdx.x & 63;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < h; c += 64) {
+        const int Y = c + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] = acc[k] + wave_tree(Y < h ? rows[6 * (int64_t)Y + k] : 0.0);
     }
+    if (lane != 0) return;
+    const double sx = acc[0], sy = acc[1], sxx = acc[2], syy = acc[3], sxy = acc[4], sm = acc[5];
     const double n = (double)w * h;
     const double cov = n * sxy - sx * sy;
     const double vx = n * sxx - sx * sx;
@@ -291,12 +304,12 @@ hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, in
         const double* cfx = k + 1 < ns ? sc[k + 1].fx : nullptr;
         const double* cfy = k + 1 < ns ? sc[k + 1].fy : nullptr;
         const int cw = k + 1 < ns ? sc[k + 1].w : 0, ch = k + 1 < ns ? sc[k + 1].h : 0;
-        hipLaunchKernelGGL(k_flow_patch, dim3(fgrid(np, 64)), dim3(64), 0, s, PI, PJ, cfx, cfy, cw, ch, c.ux, c.uy);
+        hipLaunchKernelGGL(k_flow_patch, dim3(fgrid(np, 4)), dim3(256), 0, s, PI, PJ, cfx, cfy, cw, ch, c.ux, c.uy);
         hipLaunchKernelGGL(k_flow_densify, dim3(fgrid((int64_t)c.w * c.h, 256)), dim3(256), 0, s, PI, PJ, c.ux, c.uy,
                            c.fx, c.fy);
     }
     const FPlane PI{sc[0].I, w, h}, PJ{sc[0].J, w, h};
-    hipLaunchKernelGGL(k_flow_rows, dim3(fgrid(h, 64)), dim3(64), 0, s, PI, PJ, sc[0].fx, sc[0].fy, rows);
+    hipLaunchKernelGGL(k_flow_rows, dim3(fgrid(h, 4)), dim3(256), 0, s, PI, PJ, sc[0].fx, sc[0].fy, rows);
     hipLaunchKernelGGL(k_flow_total, dim3(1), dim3(64), 0, s, rows, w, h, a0, a_static_fx, res_out);
     if (flow_out) {
         // interleave dx, dy

@@ -523,26 +523,32 @@ def cpu_baseline(frames, params, budget_s, copies_max=8):
             "nproc": nproc, "cpu_model": _cpu_model()}
 
 
-def summarize_trace(path):
+def summarize_trace(path, match=None):
     """Per-kernel statistics of a rocprofv3 CSV (kernel trace or counter
     collection) restricted to the dispatches between the two marker kernels
-    that bracket the headline's timed steps (dispatch ids strictly between)."""
+    that bracket the headline's timed steps (dispatch ids strictly between);
+    with match, every dispatch of the kernels whose name contains it."""
     import csv
     rows = list(csv.DictReader(open(path)))
     if not rows:
         raise SystemExit(f"{path}: no rows")
     key = "Dispatch_Id" if "Dispatch_Id" in rows[0] else "Correlation_Id"
-    marks = sorted({int(r[key]) for r in rows if MARKER in r["Kernel_Name"]})
-    if len(marks) < 2:
-        raise SystemExit(f"{path}: {len(marks)} marker dispatches (need 2)")
-    lo, hi = marks[0], marks[1]
+    if match:
+        rows = [r for r in rows if match in r["Kernel_Name"]]
+        lo, hi = -1, 1 << 62
+    else:
+        marks = sorted({int(r[key]) for r in rows if MARKER in r["Kernel_Name"]})
+        if len(marks) < 2:
+            raise SystemExit(f"{path}: {len(marks)} marker dispatches (need 2)")
+        lo, hi = marks[0], marks[1]
     win = [r for r in rows if lo < int(r[key]) < hi]
     out = {}
     if "Counter_Name" in rows[0]:
         for r in win:
             d = out.setdefault((r["Kernel_Name"], r["Counter_Name"]), {})
             d[int(r[key])] = d.get(int(r[key]), 0.0) + float(r["Counter_Value"])
-        print(f"# {path}: dispatches {lo + 1}..{hi - 1} (between the markers)")
+        print(f"# {path}: " + (f"every dispatch of kernels matching {match!r}" if match else
+                                   f"dispatches {lo + 1}..{hi - 1} (between the markers)"))
         print(f"# {'kernel':<44} {'counter':<12} {'dispatches':>10} {'mean per dispatch':>18}")
         for (k, c), d in sorted(out.items()):
             print(f"  {k[:44]:<44} {c:<12} {len(d):>10} {sum(d.values()) / len(d):>18.1f}")
@@ -550,7 +556,8 @@ def summarize_trace(path):
     for r in win:
         d = out.setdefault(r["Kernel_Name"], [])
         d.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    print(f"# {path}: dispatches {lo + 1}..{hi - 1} (between the markers)")
+    print(f"# {path}: " + (f"every dispatch of kernels matching {match!r}" if match else
+                               f"dispatches {lo + 1}..{hi - 1} (between the markers)"))
     print(f"# {'kernel':<44} {'calls':>6} {'total ms':>9} {'avg us':>9} {'min us':>9} {'max us':>9}")
     for k, d in sorted(out.items(), key=lambda kv: -sum(kv[1])):
         print(f"  {k[:44]:<44} {len(d):>6} {sum(d) / 1e3:>9.3f} {sum(d) / len(d):>9.2f} {min(d):>9.2f} {max(d):>9.2f}")
@@ -603,9 +610,11 @@ def main():
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-kernel figures of a rocprofv3 kernel-trace or counter CSV of this command "
                          "over the headline's timed steps (between the marker kernels) and exit")
+    ap.add_argument("--trace-match", metavar="NAME",
+                    help="with --summarize-trace: every dispatch of the kernels whose name contains NAME instead")
     args = ap.parse_args()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace)
+        summarize_trace(args.summarize_trace, args.trace_match)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); streams shard across "

@@ -651,6 +651,9 @@ vsa_status vsa_params_from_json(const char* json, vsa_params* out) {
         if (end == c) return fail(VSA_E_INVAL, "params JSON: expected a number");
         const std::string lit(c, end - c);
         c = end;
+        // JSON numbers only: no infinities, NaN or hexadecimal forms
+        if (!std::isfinite(v) || lit.find_first_of("xXnNiI") != std::string::npos)
+            return fail(VSA_E_INVAL, "params JSON: " + key + " is not a finite JSON number");
         bool found = false;
         for (const IntField& f : ints)
             if (key == f.name) {

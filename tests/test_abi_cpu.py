@@ -120,6 +120,7 @@ def test_params_from_json(vsa, params):
         {k: v for k, v in ref.items() if k not in ("k_max", "theta_kf", "search")}
     assert vsa.params_from_json(json.dumps({"rho_f": 2})) ["rho_f"] == 2.0
     for bad in ('{"k_max": 8.5}', '{"nope": 1}', '{"k_max" 8}', '{"k_max": 8,}', '[1]', '{"k_max": 8} x',
-                '{"k_max": 3000000000}', '{"a0": }', ''):
+                '{"k_max": 3000000000}', '{"a0": }', '', '{"k_max": nan}', '{"a0": inf}', '{"a0": 0x10}',
+                '{"k_max": -infinity}'):
         with pytest.raises(vsa.VsaError):
             vsa.params_from_json(bad)

@@ -92,8 +92,10 @@ typedef struct {
                              [-R, R]^2; 1 coarse-to-fine: full search on the 2x2-box image one
                              level coarser, then +-refine around twice that vector (reach
                              2R + refine).  Field pairs always take the full search.
-                             2 (dense inverse search flow) is taken by vsa_debug_flow_pair
-                             only; the engine and the clip analyser refuse it.               */
+                             2 dense inverse search flow for every pair, frame and field
+                             pairs alike (the measure of vsa_flow_pair); the frame records
+                             then carry n_pix = the plane's pixels and zero moments,
+                             amm_num and n_blocks, and vsa_get_motion has no block field.   */
     int32_t refine;       /* refinement radius of the coarse-to-fine search; must be 1       */
 } vsa_params;
 
@@ -286,7 +288,8 @@ int32_t vsa_poll_frames_all(vsa_engine* e, int32_t* sids, vsa_frame_result* out,
  * (frame -> frame+1) of stream sid at the working level, as nby x nbx pairs
  * (dx, dy) of int8 written to mv_xy (cap_blocks pairs, the caller's array;
  * NULL to query nbx, nby), if that frame is still held on the device (the
- * last 2 k_max + 7 frames).  Synchronises the engine.  VSA_E_INVAL otherwise. */
+ * last 2 k_max + 7 frames).  Synchronises the engine.  VSA_E_INVAL otherwise;
+ * VSA_E_UNSUPPORTED for an engine with the dense flow (search 2). */
 vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv_xy,
                           int32_t cap_blocks, int32_t* nbx, int32_t* nby);
 
@@ -444,7 +447,8 @@ vsa_status vsa_debug_levels(const vsa_params* p, const void* luma, int32_t width
 /* Pair measure (Sec. III.A) of two w x h planes (uint16 samples, densely packed):
  * mv (B x 2 int8), sad (B int32, nullable), ints (Sx, Sy, Sxx, Syy, Sxy, N, A,
  * B, STATIC), dbl (NCC, SWR, AMM, ACT).  bit_depth selects the 8-bit or
- * 10-bit kernel; force_zero_mv uses d = (0, 0) for every block. */
+ * 10-bit kernel; force_zero_mv uses d = (0, 0) for every block.  The block
+ * searches only (search 0 or 1; 2 is VSA_E_UNSUPPORTED: vsa_debug_flow_pair). */
 vsa_status vsa_debug_pair(const vsa_params* p, const uint16_t* I, const uint16_t* J, int32_t w,
                           int32_t h, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
                           int32_t* sad, int64_t* ints, double* dbl);

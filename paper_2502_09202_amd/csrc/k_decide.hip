@@ -276,7 +276,7 @@ __device__ __forceinline__ void field_task(const StreamDesc& sd, int u, int i, P
     k.oth = (i == 0) ? u : u + 1;
     k.oth_field = (i == 2) ? PL_UPPER : PL_LOWER;
     k.level = sd.Lf;
-    k.tiles = me_tiles(sd.wf, sd.hf);
+    k.tiles = field_pair_tiles(sd.search, sd.wf, sd.hf);
 }
 
 template <bool kSpec>
@@ -532,7 +532,20 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
         sid = ss.sid;
         const StreamDesc& sd = sds[sid];
         // 1. consecutive pair (frame-1 -> frame) of this step: lanes stride over its tiles
-        if (ss.has_frame && ss.consec_tiles > 0) {
+        if (ss.has_frame && ss.consec_tiles > 0 && sd.search == 2) {
+            // the dense flow: the pair's tiles hold its row sums
+            const FlowFinish f = flow_finish(reinterpret_cast<const FlowRow*>(cpart + ss.consec_prefix), sd.wl[0],
+                                             sd.hl[0], dp.a0, dp.a_static_fx);
+            if (lane == 0) {
+                FrameInfo& fi = sd.info[(ss.frame - 1) % sd.rs];
+                fi.ncc = f.ncc; fi.swr = f.swr; fi.amm = f.amm; fi.act = f.act;
+                for (int k = 0; k < 5; ++k) fi.mom[k] = 0;
+                fi.n_pix = (int64_t)sd.wl[0] * sd.hl[0];
+                fi.amm_num = 0;
+                fi.n_blocks = 0;
+                fi.flags |= VSA_F_HAS_PAIR | (f.is_static ? VSA_F_STATIC : 0);
+            }
+        } else if (ss.has_frame && ss.consec_tiles > 0) {
             int64_t a[6] = {0, 0, 0, 0, 0, 0};
             for (int q = lane; q < ss.consec_tiles; q += 64) {
                 const TilePartial& p = cpart[ss.consec_prefix + q];
@@ -565,7 +578,25 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
             tpre[wave][lane] = mine.tile_prefix;
             for (int k = 0; k < 6; ++k) acc[wave][lane][k] = 0;
         }
-        if (spc > 0) {
+        if (spc > 0 && sd.search == 2) {
+            // the dense flow: task by task, the whole wave adds up its row sums
+            for (int j = 0; j < spc; ++j) {
+                const PairTask tk = sparse_prev[spb + j];
+                if (tk.epoch != sd.epoch || tk.result < 0) continue;
+                const PlaneDims pd = plane_dims(sd, tk);
+                const FlowFinish f = flow_finish(reinterpret_cast<const FlowRow*>(spart + tk.tile_prefix), pd.w, pd.h,
+                                                 dp.a0, dp.a_static_fx);
+                if (lane != 0) continue;
+                if (kSpec && tk.result >= kResSpec) {
+                    double* cv = dp.spec + (int64_t)(tk.ref % sd.rs) * 4;
+                    cv[tk.result - kResSpec] = f.act;
+                    cv[3] = (double)tk.ref;
+                } else {
+                    res[wave][tk.result].act = f.act;
+                    res[wave][tk.result].swr = f.swr;
+                }
+            }
+        } else if (spc > 0) {
             // each lane takes one contiguous run of the tile range: its loads
             // are independent (many in flight), it sums each task's part of
             // the run in registers and adds it to the task's accumulators
@@ -600,7 +631,7 @@ __global__ void __launch_bounds__(64 * kDecideWaves) k_finish_decide(
                 }
             }
         }
-        if (lane < spc && mine.epoch == sd.epoch && mine.result >= 0) {
+        if (lane < spc && mine.epoch == sd.epoch && mine.result >= 0 && sd.search != 2) {
             const int64_t* a = acc[wave][lane];
             int w, h;
             if (mine.ref_field != PL_FRAME) { w = sd.wf; h = sd.hf; }

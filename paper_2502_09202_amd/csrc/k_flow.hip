@@ -18,7 +18,9 @@
 // end), each run a tree, the runs' sums added in order.  One wavefront per
 // patch for the search, one lane per pixel for densification, one wavefront
 // per row for the measure sums and one for the rows.
-#include "vsa_internal.h"
+#include "pair_finish.h"
+
+#include <algorithm>
 
 namespace vsa {
 
@@ -48,13 +50,6 @@ __device__ __forceinline__ double fbilin(const FPlane& J, double X, double Y) {
     const double top = a + fx * (b - a);
     const double bot = c + fx * (d - c);
     return top + fy * (bot - top);
-}
-
-// Balanced binary tree sum of the 64 lanes' values (lane order), in every lane.
-__device__ __forceinline__ double wave_tree(double v) {
-#pragma unroll
-    for (int step = 1; step < 64; step *= 2) v = v + __shfl_xor(v, step, 64);
-    return v;
 }
 
 // Patch origins along an axis of n samples: k * kFS while the patch fits,
@@ -89,17 +84,12 @@ __global__ void k_flow_down(const uint16_t* src, int w, int h, uint16_t* dst) {
     dst[i] = (uint16_t)(((int)r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
 }
 
-// One wavefront per patch (four per workgroup), lane y * 8 + x on pixel
-// (x, y) of the patch: the inverse-compositional search.  cfx / cfy: the
-// coarser scale's dense flow (cw x ch), null at the coarsest scale.
-__global__ void __launch_bounds__(256) k_flow_patch(FPlane I, FPlane J, const double* cfx, const double* cfy, int cw,
-                                                    int ch, double* ux, double* uy) {
-    const int nx = forigins(I.w), ny = forigins(I.h);
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (p >= nx * ny) return;                     // the whole wavefront
-    const int lane = threadIdx.x & 63;
-    const int j = p / nx, i = p - (p / nx) * nx;
-    const int px = forigin(I.w, i), py = forigin(I.h, j);
+// The inverse-compositional search of the patch at (px, py), by one
+// wavefront, lane y * 8 + x on pixel (x, y) of the patch; (u0, u1) start from
+// the coarser scale's dense flow cfx / cfy (cw x ch) at the patch centre, or
+// from zero without one.  Every lane returns the patch's vector.
+__device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, const double* cfx, const double* cfy,
+                                             int cw, int ch, int px, int py, int lane, double& ru0, double& ru1) {
     double u0 = 0.0, u1 = 0.0;
     if (cfx) {
         const int cx = min((px + kFP / 2) / 2, cw - 1);
@@ -122,6 +112,21 @@ __global__ void __launch_bounds__(256) k_flow_patch(FPlane I, FPlane J, const do
         u0 = fmin(fmax(u0 - d0, -kFUmax), kFUmax);
         u1 = fmin(fmax(u1 - d1, -kFUmax), kFUmax);
     }
+    ru0 = u0;
+    ru1 = u1;
+}
+
+// One wavefront per patch (four per workgroup).  cfx / cfy: the coarser
+// scale's dense flow (cw x ch), null at the coarsest scale.
+__global__ void __launch_bounds__(256) k_flow_patch(FPlane I, FPlane J, const double* cfx, const double* cfy, int cw,
+                                                    int ch, double* ux, double* uy) {
+    const int nx = forigins(I.w), ny = forigins(I.h);
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nx * ny) return;                     // the whole wavefront
+    const int lane = threadIdx.x & 63;
+    const int j = p / nx, i = p - (p / nx) * nx;
+    double u0, u1;
+    patch_search(I, J, cfx, cfy, cw, ch, forigin(I.w, i), forigin(I.h, j), lane, u0, u1);
     if (lane == 0) {
         ux[p] = u0;
         uy[p] = u1;
@@ -138,12 +143,12 @@ __device__ __forceinline__ void fcover(int n, int X, int& lo, int& hi, bool& flu
     flush = forigins(n) > k && X >= n - kFP;
 }
 
-// One lane per pixel: the weighted average of the covering patches' vectors.
-__global__ void k_flow_densify(FPlane I, FPlane J, const double* ux, const double* uy, double* fx, double* fy) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (int64_t)I.w * I.h) return;
-    const int Y = (int)(q / I.w), X = (int)(q - (int64_t)Y * I.w);
-    const int nx = forigins(I.w), ny = forigins(I.h);
+// The flow at pixel (X, Y): the average of the covering patches' vectors
+// (ux, uy: nx per row of patches), each weighted by 1 / max(1, |J(X + u) - I(X)|),
+// the patches taken row by row, ascending, the flush ones last.
+__device__ __forceinline__ void densify_at(const FPlane& I, const FPlane& J, const double* ux, const double* uy, int X,
+                                           int Y, double& f0, double& f1) {
+    const int nx = forigins(I.w);
     const double iv = fat(I, X, Y);
     int jlo, jhi, ilo, ihi;
     bool jf, iff;
@@ -163,9 +168,26 @@ __global__ void k_flow_densify(FPlane I, FPlane J, const double* ux, const doubl
             den += wgt;
         }
     }
-    (void)ny;
-    fx[q] = n0 / den;
-    fy[q] = n1 / den;
+    f0 = n0 / den;
+    f1 = n1 / den;
+}
+
+// One lane per pixel: the dense flow of a scale.
+__global__ void k_flow_densify(FPlane I, FPlane J, const double* ux, const double* uy, double* fx, double* fy) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)I.w * I.h) return;
+    const int Y = (int)(q / I.w), X = (int)(q - (int64_t)Y * I.w);
+    densify_at(I, J, ux, uy, X, Y, fx[q], fy[q]);
+}
+
+// The six measure terms of pixel (X, Y) under flow (u0, u1): x = I, y = J
+// warped bilinearly, x^2, y^2, xy and the flow length.
+__device__ __forceinline__ void pixel_terms(const FPlane& I, const FPlane& J, int X, int Y, double u0, double u1,
+                                            double v[6]) {
+    const double x = fat(I, X, Y);
+    const double y = fbilin(J, X + u0, Y + u1);
+    v[0] = x; v[1] = y; v[2] = x * x; v[3] = y * y; v[4] = x * y;
+    v[5] = sqrt(u0 * u0 + u1 * u1);
 }
 
 // One wavefront per row (four per workgroup): the row's six measure sums,
@@ -181,11 +203,7 @@ __global__ void __launch_bounds__(256) k_flow_rows(FPlane I, FPlane J, const dou
         double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (X < I.w) {
             const int64_t q = (int64_t)Y * I.w + X;
-            const double u0 = fx[q], u1 = fy[q];
-            const double x = fat(I, X, Y);
-            const double y = fbilin(J, X + u0, Y + u1);
-            v[0] = x; v[1] = y; v[2] = x * x; v[3] = y * y; v[4] = x * y;
-            v[5] = sqrt(u0 * u0 + u1 * u1);
+            pixel_terms(I, J, X, Y, fx[q], fy[q], v);
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) acc[k] = acc[k] + wave_tree(v[k]);
@@ -197,38 +215,232 @@ __global__ void __launch_bounds__(256) k_flow_rows(FPlane I, FPlane J, const dou
     }
 }
 
-// One wavefront: the rows' sums the same way, then NCC, SWR, AMM, ACT and
-// the static test.
-__global__ void __launch_bounds__(64) k_flow_total(const double* rows, int w, int h, double a0, int a_static_fx,
+// One wavefront: the rows' sums, then NCC, SWR, AMM, ACT and the static test.
+__global__ void __launch_bounds__(64) k_flow_total(const FlowRow* rows, int w, int h, double a0, int a_static_fx,
                                                    double* out) {
     if (blockIdx.x != 0) return;
-    const int lane = threadIdx.x & 63;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c = 0; c < h; c += 64) {
-        const int Y = c + lane;
+    const FlowFinish f = flow_finish(rows, w, h, a0, a_static_fx);
+    if ((threadIdx.x & 63) != 0) return;
+    out[0] = f.ncc;
+    out[1] = f.swr;
+    out[2] = f.amm;
+    out[3] = f.act;
+    out[4] = f.is_static ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Pair lists: the engine's and the clip form's pairs with the dense flow.
+//
+// A pair of a list is cut into one unit per row of its plane: its tiles (in
+// the list's tile map) are its rows, and the slot of tile r receives the six
+// measure sums of row r, which the finishing kernels add up.  Its scratch
+// starts at tile_prefix * unit bytes of the list's scratch (unit: at least
+// flow_pair_bytes / rows of every pair the list can hold).  Each phase is one
+// launch over the whole list (a persistent grid walking the tiles); a tile
+// does the phase's work for its row, or nothing where the phase has fewer
+// rows than the pair.
+
+constexpr int kXcdF = 8;          // accelerator complex dies, one L2 each
+
+// Scratch of one pair of a list: per scale (finest first) its I and J
+// samples and patch vectors, and for the coarser scales their dense flow
+// (the finest scale's flow is consumed where it is made).  Byte offsets from
+// the pair's base, each array on a 256-byte boundary.
+struct FlowGeo {
+    int ns;
+    int w[kFScales + 1], h[kFScales + 1];
+    int64_t oI[kFScales + 1], oJ[kFScales + 1], oux[kFScales + 1], ouy[kFScales + 1];
+    int64_t ofx[kFScales + 1], ofy[kFScales + 1];
+    int64_t bytes;
+};
+
+__host__ __device__ inline int64_t ftake(int64_t& at, int64_t n) {
+    const int64_t o = at;
+    at += (n + 255) / 256 * 256;
+    return o;
+}
+
+__host__ __device__ inline FlowGeo flow_geo(int w, int h) {
+    FlowGeo g;
+    int64_t at = 0;
+    g.ns = 0;
+    int cw = w, ch = h;
+    for (int k = 0; k <= kFScales; ++k) {
+        if (k > 0) {
+            cw /= 2;
+            ch /= 2;
+            if (cw < kFP || ch < kFP) break;
+        }
+        const int64_t px = (int64_t)cw * ch;
+        const int64_t pt = (int64_t)forigins(cw) * forigins(ch);
+        g.w[k] = cw;
+        g.h[k] = ch;
+        g.oI[k] = ftake(at, 2 * px);
+        g.oJ[k] = ftake(at, 2 * px);
+        g.oux[k] = ftake(at, 8 * pt);
+        g.ouy[k] = ftake(at, 8 * pt);
+        g.ofx[k] = k > 0 ? ftake(at, 8 * px) : 0;
+        g.ofy[k] = k > 0 ? ftake(at, 8 * px) : 0;
+        g.ns = k + 1;
+    }
+    g.bytes = at;
+    return g;
+}
+
+// Sample (x, y) of a job's plane (8 or 10 bits, row pitch in samples); with
+// cs = Lf + 1 the lower field on the upper field's rows.
+__device__ __forceinline__ int job_sample(const uint8_t* P, int pitch, int bits, int cs, int x, int y) {
+    const int64_t o = (int64_t)y * pitch + x, op = (int64_t)(y > 0 ? y - 1 : 0) * pitch + x;
+    int a, b = 0;
+    if (bits == 8) {
+        a = P[o];
+        if (cs) b = P[op];
+    } else {
+        const uint16_t* Q = reinterpret_cast<const uint16_t*>(P);
+        a = Q[o];
+        if (cs) b = Q[op];
+    }
+    if (!cs) return a;
+    const int m = 1 << cs;
+    return ((m - 1) * a + b + (m >> 1)) >> cs;
+}
+
+enum : int { FL_LOAD = 0, FL_DOWN = 1, FL_PATCH = 2, FL_DENSE = 3, FL_ROWS = 4 };
+
+// One phase over a pair list.  n_tiles: the list's tiles (consecutive
+// pairs), or with cur set the sparse pairs planned by the previous step's
+// decisions (their count read from cur->sparse_tt[par_prev]).  k: the scale.
+template <int PH>
+__global__ void __launch_bounds__(256) k_flow_list(const StreamDesc* __restrict__ sds,
+                                                   const TileJob* __restrict__ jobs, int32_t n_jobs,
+                                                   const int32_t* __restrict__ map, int32_t n_tiles,
+                                                   const DeviceCursors* __restrict__ cur, int32_t par_prev,
+                                                   uint8_t* __restrict__ scratch, int64_t unit,
+                                                   FlowRow* __restrict__ rows, int k,
+                                                   unsigned long long* __restrict__ clear_tt) {
+    // the sparse list's first phase clears the counter the step's decisions plan into
+    if (clear_tt && blockIdx.x == 0 && threadIdx.x == 0) *clear_tt = 0ull;
+    const bool sparse = cur != nullptr;
+    if (sparse) __builtin_amdgcn_s_setprio(2);
+    const int total = sparse ? tt_tiles(cur->sparse_tt[par_prev].v) : n_tiles;
+    // one contiguous slice of the tiles per XCD: a pair's neighbouring rows
+    // share lines of its planes in that XCD's L2
+    int hi = total, first = blockIdx.x, stride = gridDim.x;
+    if (gridDim.x >= kXcdF) {
+        const int groups = gridDim.x / kXcdF;     // the host launches a multiple of kXcdF
+        const int x = blockIdx.x % kXcdF, j = blockIdx.x / kXcdF;
+        if (j >= groups) return;
+        const int per = (total + kXcdF - 1) / kXcdF;
+        const int lo = x * per;
+        hi = min(total, lo + per);
+        first = lo + j;
+        stride = groups;
+    }
+    __shared__ double red[4][6];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int tile = first; tile < hi; tile += stride) {
+        const int idx = map[tile];
+        if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
+        const TileJob& jb = jobs[idx];
+        if (!(jb.flags & TF_FLOW)) continue;
+        if (sparse) {
+            const StreamDesc& sd = sds[jb.sid];
+            if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
+        }
+        const int r = tile - jb.tile_prefix;
+        if (r < 0 || r >= jb.h) continue;
+        const FlowGeo g = flow_geo(jb.w, jb.h);
+        uint8_t* base = scratch + (int64_t)jb.tile_prefix * unit;
+        if constexpr (PH == FL_LOAD) {
+            uint16_t* dI = reinterpret_cast<uint16_t*>(base + g.oI[0]) + (int64_t)r * jb.w;
+            uint16_t* dJ = reinterpret_cast<uint16_t*>(base + g.oJ[0]) + (int64_t)r * jb.w;
+            for (int x = threadIdx.x; x < jb.w; x += 256) {
+                dI[x] = (uint16_t)job_sample(jb.I, jb.pitch, jb.bits, jb.cos_I, x, r);
+                dJ[x] = (uint16_t)job_sample(jb.J, jb.pitch, jb.bits, jb.cos_J, x, r);
+            }
+        } else if constexpr (PH == FL_DOWN) {
+            if (k < 1 || k >= g.ns || r >= g.h[k]) continue;
+            const int sw = g.w[k - 1], dw = g.w[k];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc[k] = acc[k] + wave_tree(Y < h ? rows[6 * (int64_t)Y + k] : 0.0);
+            for (int side = 0; side < 2; ++side) {
+                const uint16_t* src = reinterpret_cast<const uint16_t*>(base + (side ? g.oJ[k - 1] : g.oI[k - 1]));
+                uint16_t* dst = reinterpret_cast<uint16_t*>(base + (side ? g.oJ[k] : g.oI[k])) + (int64_t)r * dw;
+                for (int x = threadIdx.x; x < dw; x += 256) {
+                    const uint16_t* r0 = src + (int64_t)(2 * r) * sw + 2 * x;
+                    const uint16_t* r1 = r0 + sw;
+                    dst[x] = (uint16_t)(((int)r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
+                }
+            }
+        } else if constexpr (PH == FL_PATCH) {
+            if (k >= g.ns || r >= forigins(g.h[k])) continue;
+            const FPlane PI{reinterpret_cast<const uint16_t*>(base + g.oI[k]), g.w[k], g.h[k]};
+            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + g.oJ[k]), g.w[k], g.h[k]};
+            const bool coarse = k + 1 < g.ns;
+            const double* cfx = coarse ? reinterpret_cast<const double*>(base + g.ofx[k + 1]) : nullptr;
+            const double* cfy = coarse ? reinterpret_cast<const double*>(base + g.ofy[k + 1]) : nullptr;
+            const int cw = coarse ? g.w[k + 1] : 0, ch = coarse ? g.h[k + 1] : 0;
+            double* ux = reinterpret_cast<double*>(base + g.oux[k]);
+            double* uy = reinterpret_cast<double*>(base + g.ouy[k]);
+            const int nx = forigins(g.w[k]);
+            const int py = forigin(g.h[k], r);
+            for (int i = wave; i < nx; i += 4) {
+                double u0, u1;
+                patch_search(PI, PJ, cfx, cfy, cw, ch, forigin(g.w[k], i), py, lane, u0, u1);
+                if (lane == 0) {
+                    ux[(int64_t)r * nx + i] = u0;
+                    uy[(int64_t)r * nx + i] = u1;
+                }
+            }
+        } else if constexpr (PH == FL_DENSE) {
+            if (k < 1 || k >= g.ns || r >= g.h[k]) continue;
+            const FPlane PI{reinterpret_cast<const uint16_t*>(base + g.oI[k]), g.w[k], g.h[k]};
+            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + g.oJ[k]), g.w[k], g.h[k]};
+            const double* ux = reinterpret_cast<const double*>(base + g.oux[k]);
+            const double* uy = reinterpret_cast<const double*>(base + g.ouy[k]);
+            double* fx = reinterpret_cast<double*>(base + g.ofx[k]) + (int64_t)r * g.w[k];
+            double* fy = reinterpret_cast<double*>(base + g.ofy[k]) + (int64_t)r * g.w[k];
+            for (int X = threadIdx.x; X < g.w[k]; X += 256) densify_at(PI, PJ, ux, uy, X, r, fx[X], fy[X]);
+        } else {
+            // the finest scale: each pixel's flow, its measure terms, the
+            // row's sums in runs of 64 pixels (one run per wavefront), the
+            // runs added in order
+            const FPlane PI{reinterpret_cast<const uint16_t*>(base + g.oI[0]), jb.w, jb.h};
+            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + g.oJ[0]), jb.w, jb.h};
+            const double* ux = reinterpret_cast<const double*>(base + g.oux[0]);
+            const double* uy = reinterpret_cast<const double*>(base + g.ouy[0]);
+            double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int c0 = 0; c0 < jb.w; c0 += 256) {
+                const int c = c0 + 64 * wave;
+                if (c < jb.w) {
+                    const int X = c + lane;
+                    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    if (X < jb.w) {
+                        double u0, u1;
+                        densify_at(PI, PJ, ux, uy, X, r, u0, u1);
+                        pixel_terms(PI, PJ, X, r, u0, u1, v);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) v[q] = wave_tree(v[q]);
+                    if (lane == 0) {
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) red[wave][q] = v[q];
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    for (int wv = 0; wv < 4 && c0 + 64 * wv < jb.w; ++wv) {
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) acc[q] = acc[q] + red[wv][q];
+                    }
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) rows[tile].s[q] = acc[q];
+            }
+        }
     }
-    if (lane != 0) return;
-    const double sx = acc[0], sy = acc[1], sxx = acc[2], syy = acc[3], sxy = acc[4], sm = acc[5];
-    const double n = (double)w * h;
-    const double cov = n * sxy - sx * sy;
-    const double vx = n * sxx - sx * sx;
-    const double vy = n * syy - sy * sy;
-    double ncc;
-    if (vx <= 0.0 && vy <= 0.0) ncc = 1.0;
-    else if (vx <= 0.0 || vy <= 0.0) ncc = 0.0;
-    else {
-        const double c = cov / sqrt(vx * vy);
-        ncc = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-    }
-    const double swr = 1.0 - ncc;
-    const double amm = sm / n;
-    out[0] = ncc;
-    out[1] = swr;
-    out[2] = amm;
-    out[3] = sqrt((amm + a0) * swr);
-    out[4] = 256.0 * amm < (double)a_static_fx ? 1.0 : 0.0;
 }
 
 inline unsigned fgrid(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -310,7 +522,8 @@ hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, in
     }
     const FPlane PI{sc[0].I, w, h}, PJ{sc[0].J, w, h};
     hipLaunchKernelGGL(k_flow_rows, dim3(fgrid(h, 4)), dim3(256), 0, s, PI, PJ, sc[0].fx, sc[0].fy, rows);
-    hipLaunchKernelGGL(k_flow_total, dim3(1), dim3(64), 0, s, rows, w, h, a0, a_static_fx, res_out);
+    hipLaunchKernelGGL(k_flow_total, dim3(1), dim3(64), 0, s, reinterpret_cast<const FlowRow*>(rows), w, h, a0,
+                       a_static_fx, res_out);
     if (flow_out) {
         // interleave dx, dy
         hipError_t e = hipMemcpy2DAsync(flow_out, 2 * sizeof(double), sc[0].fx, sizeof(double), sizeof(double), n0,
@@ -320,6 +533,60 @@ hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, in
                                  hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
+    return hipGetLastError();
+}
+
+// Scratch bytes of one pair of a pair list with a w x h plane.
+int64_t flow_pair_bytes(int w, int h) { return flow_geo(w, h).bytes; }
+
+// Workgroups of the pair-list phases one compute unit holds at once (the
+// fullest of them decides).
+int flow_list_max_wgs_per_cu() {
+    static int cached = 0;
+    if (cached == 0) {
+        int lo = 64;
+        const void* fns[] = {reinterpret_cast<const void*>(k_flow_list<FL_LOAD>),
+                             reinterpret_cast<const void*>(k_flow_list<FL_DOWN>),
+                             reinterpret_cast<const void*>(k_flow_list<FL_PATCH>),
+                             reinterpret_cast<const void*>(k_flow_list<FL_DENSE>),
+                             reinterpret_cast<const void*>(k_flow_list<FL_ROWS>)};
+        for (const void* f : fns) {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess || n < 1) n = 1;
+            lo = std::min(lo, n);
+        }
+        cached = lo;
+    }
+    return cached;
+}
+
+// Every phase of the dense flow over a pair list (jobs, map as for the
+// motion search), in order on stream s: the samples, the coarser scales,
+// then coarsest first the patch search and (coarser scales) the dense flow,
+// and last the finest scale's row sums into rows (one per tile).  With clear
+// set (sparse lists), the first phase clears the counter of the other parity.
+hipError_t launch_flow_list(const StreamDesc* sds, const TileJob* jobs, int32_t n_jobs, const int32_t* map,
+                            int32_t n_tiles, const DeviceCursors* cur, int32_t par_prev, bool clear, uint8_t* scratch,
+                            int64_t unit, TilePartial* rows, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    unsigned long long* clear_tt =
+        (cur && clear) ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
+    FlowRow* fr = reinterpret_cast<FlowRow*>(rows);
+    const dim3 g(grid), b(256);
+    hipLaunchKernelGGL(k_flow_list<FL_LOAD>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch, unit,
+                       fr, 0, clear_tt);
+    for (int k = 1; k <= kFScales; ++k)
+        hipLaunchKernelGGL(k_flow_list<FL_DOWN>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch,
+                           unit, fr, k, nullptr);
+    for (int k = kFScales; k >= 0; --k) {
+        hipLaunchKernelGGL(k_flow_list<FL_PATCH>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch,
+                           unit, fr, k, nullptr);
+        if (k > 0)
+            hipLaunchKernelGGL(k_flow_list<FL_DENSE>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev,
+                               scratch, unit, fr, k, nullptr);
+    }
+    hipLaunchKernelGGL(k_flow_list<FL_ROWS>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch, unit,
+                       fr, 0, nullptr);
     return hipGetLastError();
 }
 

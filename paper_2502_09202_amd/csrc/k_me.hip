@@ -510,7 +510,7 @@ __device__ __forceinline__ bool resolve8(const StreamDesc* __restrict__ sds, con
                                          int n_jobs, int idx, int tile, bool sparse, int8_t* dbg_mv, Tile8& T) {
     if (idx < 0 || idx >= n_jobs) return false;   // never expected; keeps reads in bounds
     const TileJob& jb = jobs[idx];
-    if (jb.bits != 8 || (jb.flags & TF_HIER)) return false;
+    if (jb.bits != 8 || (jb.flags & (TF_HIER | TF_FLOW))) return false;
     if (sparse) {
         const StreamDesc& sd = sds[jb.sid];
         if (!sd.active || sd.epoch != jb.epoch) return false;   // stream closed since planning
@@ -1216,7 +1216,7 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
             if (idx < 0 || idx >= n_jobs) continue;   // never expected; keeps reads in bounds
             const TileJob& jb = jobs[idx];
             const int local = tile - jb.tile_prefix;
-            if (jb.bits != 10 || (jb.flags & TF_HIER)) continue;
+            if (jb.bits != 10 || (jb.flags & (TF_HIER | TF_FLOW))) continue;
             if (sparse) {
                 const StreamDesc& sd = sds[jb.sid];
                 if (!sd.active || sd.epoch != jb.epoch) continue;   // stream closed since planning
@@ -1286,6 +1286,37 @@ __global__ void __launch_bounds__(256) k_finish(const StreamDesc* __restrict__ s
         const PairTask& tk = is_consec ? consec[t] : sparse[t - n_consec];
         if (!sds[tk.sid].active || sds[tk.sid].epoch != tk.epoch) continue;
         const int base = (is_consec ? 0 : consec_tiles) + tk.tile_prefix;
+        if (sds[tk.sid].search == 2) {
+            // the dense flow: the pair's tiles hold its row sums
+            const StreamDesc& sd = sds[tk.sid];
+            const PlaneRef P = plane_of(sd, tk.ref, tk.ref_field, tk.level);
+            const FlowFinish f =
+                flow_finish(reinterpret_cast<const FlowRow*>(partials + base), P.w, P.h, dp.a0, dp.a_static_fx);
+            if (lane != 0) continue;
+            const int64_t n = (int64_t)P.w * P.h;
+            if (tk.flags & TF_DEBUG) {
+                if (dbg_ints) {
+                    for (int k = 0; k < 9; ++k) dbg_ints[k] = 0;
+                    dbg_ints[5] = n;
+                    dbg_ints[8] = f.is_static ? 1 : 0;
+                }
+                if (dbg_dbl) { dbg_dbl[0] = f.ncc; dbg_dbl[1] = f.swr; dbg_dbl[2] = f.amm; dbg_dbl[3] = f.act; }
+            }
+            if (is_consec) {
+                FrameInfo& fi = sd.info[tk.ref % sd.rs];
+                fi.ncc = f.ncc; fi.swr = f.swr; fi.amm = f.amm; fi.act = f.act;
+                for (int k = 0; k < 5; ++k) fi.mom[k] = 0;
+                fi.n_pix = n;
+                fi.amm_num = 0;
+                fi.n_blocks = 0;
+                fi.flags |= VSA_F_HAS_PAIR | (f.is_static ? VSA_F_STATIC : 0);
+            } else if (tk.result >= 0) {
+                PairResult& r = results[(int64_t)tk.sid * kResSlots + tk.result];
+                r.act = f.act;
+                r.swr = f.swr;
+            }
+            continue;
+        }
         int64_t s[6] = {0, 0, 0, 0, 0, 0};
         for (int i = lane; i < tk.tiles; i += 64) {
             const TilePartial& p = partials[base + i];

@@ -26,4 +26,59 @@ __device__ __forceinline__ void finish_pair(int64_t sx, int64_t sy, int64_t sxx,
     out[0] = ncc; out[1] = swr; out[2] = amm; out[3] = act;
 }
 
+// Balanced binary tree sum of the 64 lanes' values (lane order), in every
+// lane: the butterfly of xor shuffles adds lane pairs, then pairs of pairs.
+__device__ __forceinline__ double wave_tree(double v) {
+#pragma unroll
+    for (int step = 1; step < 64; step *= 2) v = v + __shfl_xor(v, step, 64);
+    return v;
+}
+
+// A dense flow pair's per-row sums (one per row of its plane, in the slot of
+// the row's tile): sum x, sum y, sum x^2, sum y^2, sum xy over the row's
+// pixels (x = I, y = J warped by the flow) and the sum of the flow lengths.
+struct FlowRow {
+    double s[6];
+};
+static_assert(sizeof(FlowRow) == sizeof(TilePartial), "a flow row sum takes the slot of a tile partial");
+
+struct FlowFinish {
+    double ncc, swr, amm, act;
+    bool is_static;
+};
+
+// The dense flow pair measure from its h row sums (Sec. III.A with the flow
+// in place of the block field): the rows' sums in runs of 64 rows, each run a
+// tree, the runs added in order; then NCC of I against the warped J, SWR,
+// AMM = mean flow length, ACT, and static if 256 AMM < a_static_fx.  Called
+// by a whole wavefront; every lane gets the result.
+__device__ __forceinline__ FlowFinish flow_finish(const FlowRow* rows, int w, int h, double a0, int a_static_fx) {
+    const int lane = threadIdx.x & 63;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < h; c += 64) {
+        const int Y = c + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] = acc[k] + wave_tree(Y < h ? rows[Y].s[k] : 0.0);
+    }
+    const double sx = acc[0], sy = acc[1], sxx = acc[2], syy = acc[3], sxy = acc[4], sm = acc[5];
+    const double n = (double)w * h;
+    const double cov = n * sxy - sx * sy;
+    const double vx = n * sxx - sx * sx;
+    const double vy = n * syy - sy * sy;
+    double ncc;
+    if (vx <= 0.0 && vy <= 0.0) ncc = 1.0;
+    else if (vx <= 0.0 || vy <= 0.0) ncc = 0.0;
+    else {
+        const double c = cov / __builtin_sqrt(vx * vy);
+        ncc = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    }
+    FlowFinish f;
+    f.ncc = ncc;
+    f.swr = 1.0 - ncc;
+    f.amm = sm / n;
+    f.act = __builtin_sqrt((f.amm + a0) * f.swr);
+    f.is_static = 256.0 * f.amm < (double)a_static_fx;
+    return f;
+}
+
 }  // namespace vsa

@@ -46,7 +46,7 @@ struct StreamDesc {
     uint16_t* tileh;                  // per pyramid tile: its working-level histogram (2^bits counts)
     int32_t B_L;                      // blocks at the working level
     int32_t epoch;                    // bumped each time the slot is (re)opened
-    int32_t search;                   // frame pairs: 0 full search, 1 coarse-to-fine
+    int32_t search;                   // 0 full search, 1 coarse-to-fine (frame pairs), 2 dense flow
 };
 
 // Per-frame record under construction (one per ring slot).
@@ -80,8 +80,10 @@ enum : int32_t {
     TF_MV_RING = 1,    // store the motion field in the stream's MV ring (consecutive pairs)
     TF_DEBUG = 2,      // store motion field, SADs and integers in the debug buffers
     TF_ZERO_MV = 4,    // use d = (0, 0) for every block (no search)
-    TF_HIER = 8        // coarse-to-fine motion field, 16 x 16-block tiles (frame pairs of a
+    TF_HIER = 8,       // coarse-to-fine motion field, 16 x 16-block tiles (frame pairs of a
                        // stream whose parameters ask for it)
+    TF_FLOW = 16       // dense flow pair measure, one tile per row of the plane (every pair
+                       // of a stream whose parameters ask for it)
 };
 
 // Result of a sparse pair measure.
@@ -228,9 +230,14 @@ constexpr int kHTB = 16;
 inline __host__ __device__ int me_tiles_hier(int w, int h) {
     return div_up(w / kBlock, kHTB) * div_up(h / kBlock, kHTB);
 }
-// Tiles of a frame pair (field pairs always take me_tiles).
+// Tiles of a frame pair and of a field pair.  The dense flow's tiles are
+// the plane's rows; the coarse-to-fine search leaves field pairs to the full
+// search.
 inline __host__ __device__ int frame_pair_tiles(int search, int w, int h) {
-    return search ? me_tiles_hier(w, h) : me_tiles(w, h);
+    return search == 2 ? h : (search ? me_tiles_hier(w, h) : me_tiles(w, h));
+}
+inline __host__ __device__ int field_pair_tiles(int search, int w, int h) {
+    return search == 2 ? h : me_tiles(w, h);
 }
 
 // Everything a motion-search tile needs from its pair, resolved once per pair
@@ -270,11 +277,12 @@ inline __host__ __device__ TileJob make_tile_job(const StreamDesc& sd, const Pai
         j.w = sd.wl[d]; j.h = sd.hl[d]; j.pitch = sd.pl[d];
         j.cos_I = j.cos_J = 0;
     }
-    const bool hier = sd.search && t.ref_field == PL_FRAME;
-    j.mv = mv;
+    const bool hier = sd.search == 1 && t.ref_field == PL_FRAME;
+    const bool flow = sd.search == 2;
+    j.mv = flow ? nullptr : mv;
     j.tiles_x = div_up(j.w / kBlock, hier ? kHTB : kTBX);
     j.tile_prefix = t.tile_prefix;
-    j.flags = t.flags | (hier ? TF_HIER : 0);
+    j.flags = (flow ? (t.flags & ~TF_MV_RING) : t.flags) | (hier ? TF_HIER : 0) | (flow ? TF_FLOW : 0);
     j.sid = t.sid;
     j.epoch = t.epoch;
     j.bits = sd.bits;

@@ -56,6 +56,10 @@ int me_hier_max_wgs_per_cu(int bits);
 int64_t flow_scratch_bytes(int w, int h);
 hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, int64_t pitch, int bits, double a0,
                             int a_static_fx, uint8_t* scratch, double* flow_out, double* res_out, hipStream_t s);
+int64_t flow_pair_bytes(int w, int h);
+int flow_list_max_wgs_per_cu();
+hipError_t launch_flow_list(const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t, const DeviceCursors*,
+                            int32_t, bool, uint8_t*, int64_t, TilePartial*, int grid, hipStream_t);
 hipError_t launch_me_hier(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
                           const DeviceCursors*, int32_t, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                           LaunchTiming = {});
@@ -180,7 +184,6 @@ vsa_status check_params(const vsa_params& p) {
     if (p.n_ss < 1) return fail(VSA_E_INVAL, "n_ss must be >= 1");
     if (!(p.tau_p >= 1.0)) return fail(VSA_E_INVAL, "tau_p must be >= 1");
     if (p.search < 0 || p.search > 2) return fail(VSA_E_INVAL, "search must be 0, 1 or 2");
-    if (p.search == 2) return fail(VSA_E_UNSUPPORTED, "the dense flow (search 2) runs only as a single pair measure");
     if (p.search == 1 && p.refine != 1) return fail(VSA_E_UNSUPPORTED, "the coarse-to-fine search refines by 1");
     return VSA_OK;
 }
@@ -247,13 +250,32 @@ bool samples_10bit_ok(const uint8_t* plane, int64_t pitch, int W, int H) {
 }
 
 int max_sparse_tiles(const StreamDesc& sd) {
-    int n = 3 * me_tiles(sd.wf, sd.hf);
+    int n = 3 * field_pair_tiles(sd.search, sd.wf, sd.hf);
     for (int K = 1; K <= sd.k_max + 1; ++K) {
         const int l = std::min(sd.L + ceil_log2(K), sd.Lcap);
         const int d = l - sd.L;
         n += (K >= 2 ? 2 : 1) * frame_pair_tiles(sd.search, sd.wl[d], sd.hl[d]);
     }
     return n;
+}
+
+// Scratch bytes per tile of a stream's dense flow pairs (search 2): each of
+// its pair planes (the stored frame levels and the field level) fits in its
+// rows' share.  0 for the block searches.
+int64_t flow_unit(const StreamDesc& sd) {
+    if (sd.search != 2) return 0;
+    int64_t u = 0;
+    auto one = [&](int w, int h) { u = std::max(u, ((flow_pair_bytes(w, h) + h - 1) / h + 255) / 256 * 256); };
+    for (int d = 0; d < sd.nlev; ++d) one(sd.wl[d], sd.hl[d]);
+    one(sd.wf, sd.hf);
+    return u;
+}
+
+// Device bytes a stream adds to the engine's per-tile buffers: its tile
+// partials and, with the dense flow, its share of the flow scratch.
+uint64_t stream_tile_bytes(const StreamDesc& sd) {
+    const uint64_t tiles = (uint64_t)(frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd));
+    return tiles * (sizeof(TilePartial) + (uint64_t)flow_unit(sd));
 }
 
 struct HostStream {
@@ -314,6 +336,11 @@ struct vsa_engine {
     OutShot* d_out_shots = nullptr;
     TilePartial* d_partials = nullptr;
     int64_t partials_cap = 0;
+    // dense flow scratch (search 2): the consecutive pairs' and the sparse
+    // pairs' lists, flow_unit bytes per tile (grown, never shrunk)
+    uint8_t* d_flow_c = nullptr;
+    uint8_t* d_flow_s = nullptr;
+    int64_t flow_unit = 0, flow_tiles_c = 0, flow_tiles_s = 0;
     // motion-search jobs and tile maps: the consecutive pairs' per step slot
     // (written by the pyramid kernel), the sparse pairs' per step parity
     // (written by the decision kernel); maps hold partials_cap entries each
@@ -428,6 +455,42 @@ vsa_status ensure_partials(vsa_engine* e) {
         return fail(VSA_E_NOMEM, "tile partial buffer");
     }
     e->partials_cap = cap;
+    return VSA_OK;
+}
+
+// The dense flow's scratch for every open stream's pairs: a pair's starts at
+// its tile prefix times the unit, in the list of its kind (consecutive or
+// sparse); the unit is the largest any open stream needs.
+vsa_status ensure_flow(vsa_engine* e) {
+    if (e->params.search != 2) return VSA_OK;
+    int64_t unit = 0, need_c = 0, need_s = 0;
+    for (const HostStream& s : e->streams)
+        if (s.open) {
+            unit = std::max(unit, flow_unit(s.sd));
+            need_c += s.consec_tiles;
+            need_s += s.sparse_tiles_max;
+        }
+    if (unit <= e->flow_unit && need_c <= e->flow_tiles_c && need_s <= e->flow_tiles_s) return VSA_OK;
+    HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
+    HIPCK(hipStreamSynchronize(e->stream_c), "hipStreamSynchronize");
+    HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    if (e->d_flow_c) HIPCK(hipFree(e->d_flow_c), "hipFree");
+    if (e->d_flow_s) HIPCK(hipFree(e->d_flow_s), "hipFree");
+    e->d_flow_c = e->d_flow_s = nullptr;
+    unit = std::max(unit, e->flow_unit);
+    const int64_t tc = std::max(e->flow_tiles_c, need_c + need_c / 2);
+    const int64_t ts = std::max(e->flow_tiles_s, need_s + need_s / 2);
+    const bool ok = hipMalloc(&e->d_flow_c, (size_t)(unit * tc)) == hipSuccess &&
+                    hipMalloc(&e->d_flow_s, (size_t)(unit * ts)) == hipSuccess;
+    if (!ok) {
+        if (e->d_flow_c) (void)hipFree(e->d_flow_c);
+        e->d_flow_c = e->d_flow_s = nullptr;
+        e->flow_unit = e->flow_tiles_c = e->flow_tiles_s = 0;
+        return fail(VSA_E_NOMEM, "dense flow scratch");
+    }
+    e->flow_unit = unit;
+    e->flow_tiles_c = tc;
+    e->flow_tiles_s = ts;
     return VSA_OK;
 }
 
@@ -814,7 +877,8 @@ void vsa_engine_destroy(vsa_engine* e) {
     for (uint8_t* h : e->h_stage) if (h) (void)hipHostFree(h);
     for (hipEvent_t ev : e->stage_ev) if (ev) (void)hipEventDestroy(ev);
     void* dev[] = {e->d_sds, e->d_states, e->d_closed, e->d_results, e->d_sparse, e->d_cur,
-                   e->d_partials, e->d_log, e->d_desc, e->d_sjobs, e->d_cjobs, e->d_cmap, e->d_smap};
+                   e->d_partials, e->d_log, e->d_desc, e->d_sjobs, e->d_cjobs, e->d_cmap, e->d_smap,
+                   e->d_flow_c, e->d_flow_s};
     for (void* p : dev) if (p) (void)hipFree(p);
     for (int i = 0; i < kDescRing; ++i) {
         if (e->h_desc[i]) (void)hipHostFree(e->h_desc[i]);
@@ -862,7 +926,7 @@ uint64_t vsa_stream_footprint(const vsa_engine* e, const vsa_stream_desc* d) {
     int64_t sp;
     uint64_t bytes;
     if (prepare_stream(e, d, sd, g, sp, bytes) != VSA_OK) return 0;
-    return bytes + (uint64_t)(frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
+    return bytes + stream_tile_bytes(sd);
 }
 
 vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid) {
@@ -878,7 +942,7 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     int slot = -1;
     for (int i = 0; i < e->max_streams; ++i)
         if (!e->streams[i].open) { slot = i; break; }
-    const uint64_t part = (uint64_t)(frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]) + max_sparse_tiles(sd)) * sizeof(TilePartial);
+    const uint64_t part = stream_tile_bytes(sd);
     if (slot < 0 || e->used + bytes + part > e->budget) {
         e->counters[3] += 1;
         return fail(VSA_E_ADMIT, slot < 0 ? "no free stream slot" : "HBM budget exhausted");
@@ -935,6 +999,7 @@ vsa_status vsa_stream_open(vsa_engine* e, const vsa_stream_desc* d, int32_t* sid
     if (err == hipSuccess) err = hipStreamWaitEvent(e->stream_b, e->init_ev[slot], 0);
     if (err != hipSuccess) { free_stream(e, slot); return hip_fail(err, "stream init"); }
     st = ensure_partials(e);
+    if (st == VSA_OK) st = ensure_flow(e);
     if (st != VSA_OK) { free_stream(e, slot); return st; }
     if (sd.bits == 10) e->has10 = 1;
     else e->has8 = 1;
@@ -1305,8 +1370,9 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     for (const HostStream& s : e->streams) if (s.open && !s.done) sparse_max += s.sparse_tiles_max;
     int bucket = 0;
     while (bucket < 31 && (int64_t(1) << (bucket + 1)) <= consec_tiles) ++bucket;
+    const bool flow = e->params.search == 2;
     TuneCand wgs{e->me_fixed, e->me_fixed};
-    if (!e->me_fixed) {
+    if (!e->me_fixed && !flow) {
         if (e->tune_win && e->tune_win->bucket != bucket) {   // the bucket changed: drop the window
             e->tune_win->bucket = -1;
             e->tune_win = nullptr;
@@ -1339,7 +1405,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     };
     const int grid_c = me_grid(consec_tiles, wgs.consec), grid_s = me_grid(sparse_max, wgs.sparse);
     // coarse-to-fine frame pairs: their own kernel, within its occupancy
-    const bool hier = e->params.search != 0;
+    const bool hier = e->params.search == 1;
     const int mh_cap = std::min(e->has8 ? me_hier_max_wgs_per_cu(8) : 64, e->has10 ? me_hier_max_wgs_per_cu(10) : 64);
     auto mh_grid = [&](int64_t tiles, int w) {
         w = std::max(1, std::min(w, mh_cap));
@@ -1362,8 +1428,21 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     TileJob* sjobs_next = e->d_sjobs + (size_t)par * sp_cap;
     int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
     int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
+    // the dense flow (search 2): every phase over the list, persistent grids
+    // within the phases' occupancy
+    const int fl_cap = flow ? flow_list_max_wgs_per_cu() : 0;
+    auto fl_grid = [&](int64_t tiles) {
+        int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)fl_cap * e->cus);
+        if (g >= 8) g -= g % 8;
+        return g;
+    };
     // one launch per sample width that an open stream has
-    if (consec_tiles > 0 && !hier) {
+    if (flow) {
+        if (consec_tiles > 0)
+            HIPCK(launch_flow_list(e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, e->d_flow_c,
+                                   e->flow_unit, cpart, fl_grid(consec_tiles), Cs),
+                  "dense flow launch");
+    } else if (consec_tiles > 0 && !hier) {
         if (e->has8)
             HIPCK(launch_me(8, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, cpart, nullptr, nullptr,
                             grid_c, Cs, timing(1, true, true)), "motion search launch");
@@ -1383,10 +1462,14 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     // the first sparse launch also clears the counter this step's decisions
     // plan into: the 8-bit one runs unless only 10-bit streams are open
     const bool sparse8 = e->has8 || !e->has10;
-    if (sparse8)
+    if (flow)
+        HIPCK(launch_flow_list(e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true,
+                               e->d_flow_s, e->flow_unit, spart, fl_grid(sparse_max), A),
+              "dense flow launch");
+    if (sparse8 && !flow)
         HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart,
                         nullptr, nullptr, grid_s, A, timing(3, true, !e->has10 && !hier)), "motion search launch");
-    if (e->has10)
+    if (e->has10 && !flow)
         HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, !sparse8, spart,
                         nullptr, nullptr, grid_s, A, timing(3, !sparse8, !hier)), "motion search launch");
     if (hier) {
@@ -1496,6 +1579,7 @@ vsa_status vsa_get_motion(vsa_engine* e, int32_t sid, int64_t frame, int8_t* mv,
     if (nbx) *nbx = bx;
     if (nby) *nby = by;
     if (!mv) return VSA_OK;
+    if (s->sd.search == 2) return fail(VSA_E_UNSUPPORTED, "the dense flow (search 2) keeps no block motion field");
     if (cap_blocks < bx * by) return fail(VSA_E_INVAL, "output too small");
     // pair (frame -> frame+1) exists once frame+1 has been stepped and is still in the ring
     if (frame < 0 || frame + 1 >= s->next_frame || frame < s->next_frame - s->sd.rs)
@@ -1732,6 +1816,7 @@ vsa_status vsa_debug_pair(const vsa_params* pp, const uint16_t* I, const uint16_
     if (pp) p = *pp; else vsa_default_params(&p);
     vsa_status st = check_params(p);
     if (st != VSA_OK) return st;
+    if (p.search == 2) return fail(VSA_E_UNSUPPORTED, "the dense flow pair measure is vsa_debug_flow_pair");
     const int b = bits == 8 ? 1 : 2;
     const int maxv = bits == 8 ? 255 : 1023;
     for (int64_t i = 0; i < (int64_t)w * h; ++i)
@@ -1957,6 +2042,10 @@ struct vsa_clip {
     int sparse_tiles = 0;          // most tiles one round's sparse pairs can have
     int grid_c = 0, grid_s = 0;    // persistent motion-search grids
     int grid_hc = 0, grid_hs = 0;  // and those of the coarse-to-fine kernel (search = 1)
+    int grid_fc = 0, grid_fs = 0;  // and those of the dense flow's phases (search = 2)
+    int64_t flow_unit = 0;         // dense flow scratch bytes per tile
+    uint8_t* d_flow_c = nullptr;   // C x pair_tiles units (the consecutive pairs of a chunk)
+    uint8_t* d_flow_s = nullptr;   // sparse_tiles units
     hipStream_t s = nullptr;       // decisions (D)
     hipStream_t sp = nullptr;      // ingest (P)
     hipEvent_t ev_p[2] = {};       // P has finished the chunk of that parity
@@ -2014,10 +2103,15 @@ vsa_status clip_decide(vsa_clip* c, const StepStream* d_entry) {
     int32_t* sm_prev = c->d_smap + (size_t)(par ^ 1) * c->sparse_tiles;
     int32_t* sm_next = c->d_smap + (size_t)par * c->sparse_tiles;
     TilePartial* spart = c->d_part + (size_t)2 * c->C * c->pair_tiles;
-    HIPCK(launch_me(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, spart, nullptr,
-                    nullptr, c->grid_s, c->s),
-          "motion search launch");
-    if (c->sd.search)   // the deep-check pairs among them (frame pairs) take the coarse-to-fine kernel
+    if (c->sd.search == 2)
+        HIPCK(launch_flow_list(c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, c->d_flow_s,
+                               c->flow_unit, spart, c->grid_fs, c->s),
+              "dense flow launch");
+    else
+        HIPCK(launch_me(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, spart,
+                        nullptr, nullptr, c->grid_s, c->s),
+              "motion search launch");
+    if (c->sd.search == 1)   // the deep-check pairs among them (frame pairs) take the coarse-to-fine kernel
         HIPCK(launch_me_hier(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, spart,
                              nullptr, nullptr, c->grid_hs, c->s),
               "motion search launch");
@@ -2128,7 +2222,13 @@ vsa_status clip_ingest(vsa_clip* c, const ClipSource& in, int ch, int* n_cons_ou
     HIPCK(launch_pyramid(sd.bits, sd.L, c->d_sds, d_steps, d_k1, n, n * c->pyr_tiles, cjobs, cmap, c->sp),
           "pyramid launch");
     if (!c->no_intensity) HIPCK(launch_intensity(c->d_sds, d_steps, d_k1, n, c->sp), "intensity launch");
-    if (ctiles > 0) {
+    if (ctiles > 0 && sd.search == 2) {
+        int gc = std::min(c->grid_fc, ctiles);
+        if (gc >= 8) gc -= gc % 8;
+        HIPCK(launch_flow_list(c->d_sds, cjobs, C, cmap, ctiles, nullptr, 0, false, c->d_flow_c, c->flow_unit, cpart,
+                               gc, c->sp),
+              "dense flow launch");
+    } else if (ctiles > 0) {
         int gc = std::min(sd.search ? c->grid_hc : c->grid_c, ctiles);
         if (gc >= 8) gc -= gc % 8;
         if (sd.search)
@@ -2156,7 +2256,8 @@ void vsa_clip_destroy(vsa_clip* c) {
     if (c->sp) (void)hipStreamSynchronize(c->sp);
     if (c->s) (void)hipStreamSynchronize(c->s);
     void* dev[] = {c->mem, c->d_sds, c->d_state, c->d_cur, c->d_closed, c->d_desc, c->d_cjobs, c->d_cmap,
-                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage, c->d_spec, c->d_log};
+                   c->d_part, c->d_sparse, c->d_sjobs, c->d_smap, c->d_stage, c->d_spec, c->d_log,
+                   c->d_flow_c, c->d_flow_s};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {c->h_desc, c->h_init, c->h_out_frames, c->h_out_shots, c->h_snap};
@@ -2208,7 +2309,7 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     c->pair_tiles = frame_pair_tiles(sd.search, sd.wl[0], sd.hl[0]);
     // one round's sparse pairs: a deep check, or the fields of an analysed
     // frame and of up to kMaxSpec frames after it
-    c->sparse_tiles = std::max(max_sparse_tiles(sd), 3 * (1 + kMaxSpec) * me_tiles(sd.wf, sd.hf));
+    c->sparse_tiles = std::max(max_sparse_tiles(sd), 3 * (1 + kMaxSpec) * field_pair_tiles(sd.search, sd.wf, sd.hf));
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
     const int me_cap = me_max_wgs_per_cu(sd.bits);
@@ -2220,7 +2321,17 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     };
     c->grid_c = grid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2);
     c->grid_s = grid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
-    if (sd.search) {
+    if (sd.search == 2) {
+        const int fl_cap = flow_list_max_wgs_per_cu();
+        auto fgrid = [&](int64_t tiles) {
+            int gsz = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)fl_cap * cus);
+            if (gsz >= 8) gsz -= gsz % 8;
+            return gsz;
+        };
+        c->grid_fc = fgrid((int64_t)C * c->pair_tiles);
+        c->grid_fs = fgrid(c->sparse_tiles);
+        c->flow_unit = flow_unit(sd);
+    } else if (sd.search) {
         const int mh_cap = me_hier_max_wgs_per_cu(sd.bits);
         auto hgrid = [&](int64_t tiles, int w) {
             w = std::max(1, std::min(w, mh_cap));
@@ -2254,6 +2365,9 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
               dalloc((void**)&c->d_sjobs, 2 * sizeof(TileJob) * tc) &&
               dalloc((void**)&c->d_smap, 2 * sizeof(int32_t) * c->sparse_tiles) &&
               dalloc((void**)&c->d_spec, sizeof(double) * 4 * sd.rs);
+    if (ok && sd.search == 2)
+        ok = dalloc((void**)&c->d_flow_c, (size_t)(c->flow_unit * (int64_t)cpt)) &&
+             dalloc((void**)&c->d_flow_s, (size_t)(c->flow_unit * (int64_t)c->sparse_tiles));
     if (ok && cfg->debug_log) {
         c->log_cap = kLogCapPerStream;
         ok = dalloc((void**)&c->d_log, sizeof(int32_t) * 6 * (size_t)c->log_cap);

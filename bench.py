@@ -523,6 +523,22 @@ def cpu_baseline(frames, params, budget_s, copies_max=8):
             "nproc": nproc, "cpu_model": _cpu_model()}
 
 
+def short_kernel_name(name):
+    """A kernel's name without the return type, namespaces and parameter list
+    (template arguments kept)."""
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("vsa::(anonymous namespace)::", "").replace("vsa::", "")
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
+
+
 def summarize_trace(path, match=None):
     """Per-kernel statistics of a rocprofv3 CSV (kernel trace or counter
     collection) restricted to the dispatches between the two marker kernels
@@ -554,7 +570,7 @@ def summarize_trace(path, match=None):
             print(f"  {k[:44]:<44} {c:<12} {len(d):>10} {sum(d.values()) / len(d):>18.1f}")
         return
     for r in win:
-        d = out.setdefault(r["Kernel_Name"], [])
+        d = out.setdefault(short_kernel_name(r["Kernel_Name"]), [])
         d.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     print(f"# {path}: " + (f"every dispatch of kernels matching {match!r}" if match else
                                f"dispatches {lo + 1}..{hi - 1} (between the markers)"))
@@ -606,6 +622,11 @@ def main():
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end run from pinned host memory")
     ap.add_argument("--no-hier", action="store_true", help="skip the coarse-to-fine (search = 1) batched run")
     ap.add_argument("--no-flow", action="store_true", help="skip the dense-flow pair measure timing")
+    ap.add_argument("--no-flow-engine", action="store_true",
+                    help="skip the batched run with the dense flow for every pair (search = 2)")
+    ap.add_argument("--flow-steps", type=int, default=20, help="timed steps of the dense-flow batched run")
+    ap.add_argument("--flow-engine-only", action="store_true",
+                    help="only the dense-flow batched run (one JSON line with it)")
     ap.add_argument("--e2e-steps", type=int, default=40)
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-kernel figures of a rocprofv3 kernel-trace or counter CSV of this command "
@@ -648,6 +669,30 @@ def main():
                 "fps": round(med, 1), "x_realtime": round(med / RT_FPS, 1), "runs_fps": [round(x, 1) for x in cf],
                 "ms_per_clip": round(1e3 * args.frames / med, 3), "chunk": args.clip_chunk, "shots": nshots,
                 "per_clip": per}
+
+    def flow_engine_leg():
+        # the dense flow for every pair the pass measures, on the headline's streams
+        fsteps = max(1, args.flow_steps)
+        fdt, _, fc0, fc1, _ = run_engine(vsa, dev, dict(params, search=2), args.streams, fsteps, 4, 0, torch,
+                                         preroll=16, markers=args.flow_engine_only)
+        gf = geometry(W, H, params)
+        wl, hl = gf["dims"][gf["L"]]
+        ops = args.streams * flow_ops(wl, hl) * fsteps
+        sparse = fc1["sparse_tasks"] - fc0["sparse_tasks"]
+        print(f"[bench] dense flow B={args.streams}: {args.streams * fsteps / fdt:.0f} frames/s, "
+              f"{1e3 * fdt / fsteps:.2f} ms/step", file=sys.stderr, flush=True)
+        return {"workload": f"the headline's {args.streams} streams with search = 2: every pair the pass measures "
+                            f"(consecutive {wl} x {hl} pairs, field and deep-check pairs) takes the dense inverse "
+                            "search flow measure, as pair lists cut into plane rows, one launch per phase and list",
+                "fps": round(args.streams * fsteps / fdt, 1), "ms_per_step": round(1e3 * fdt / fsteps, 4),
+                "steps": fsteps, "sparse_pairs_per_step": round(sparse / fsteps, 2),
+                "fp64_gops_consecutive_only": round(ops / fdt / 1e9, 1),
+                "note": "fp64_gops_consecutive_only counts the consecutive pairs' operations alone (a lower "
+                        "bound on the step's rate); peak 78600 fp64 GOP/s"}
+
+    if args.flow_engine_only:
+        print(json.dumps({"dense_flow_engine": flow_engine_leg()}))
+        return
 
     if args.clip_only:
         if args.gpu_warm_steps > 0:
@@ -713,6 +758,8 @@ def main():
         extra["dense_flow_pair"] = run_flow(vsa, dev, params, torch)
         print(f"[bench] dense flow pair: {extra['dense_flow_pair']['ms_per_pair']:.3f} ms per 512x270 pair",
               file=sys.stderr, flush=True)
+    if not args.no_flow_engine:
+        extra["dense_flow_engine"] = flow_engine_leg()
     if not args.no_intensity_leg:
         # the same batched run without the unary intensity measure (no decision uses it)
         ndt, _, _, _, _ = run_engine(vsa, dev, params, args.streams, args.steps, args.warmup, 0, torch,

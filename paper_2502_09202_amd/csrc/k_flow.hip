@@ -12,12 +12,15 @@
 // measures: NCC of I against J warped by the flow, AMM = mean flow length.
 //
 // Everything is IEEE double with no contraction, every sum in a fixed order:
-// a patch's 64 terms (row-major) as a balanced binary tree, which is exactly
-// what a wavefront's butterfly of xor shuffles forms in every lane; a longer
+// a patch's 64 terms (row-major) as a balanced binary tree, which a group of
+// 16 lanes forms exactly (four terms of one column per lane: the levels over
+// a row's columns by lane permutes, the next two in the lane, the last by a
+// row mirror); a longer
 // list (a row's pixels, then the rows) in runs of 64 lanes (zeros past the
-// end), each run a tree, the runs' sums added in order.  One wavefront per
-// patch for the search, one lane per pixel for densification, one wavefront
-// per row for the measure sums and one for the rows.
+// end), each run a tree (a wavefront's butterfly), the runs' sums added in
+// order.  Sixteen lanes per patch for the search, one lane per pixel for
+// densification, one wavefront per run of a row for the measure sums and one
+// for the rows.
 #include "pair_finish.h"
 
 #include <algorithm>
@@ -84,12 +87,48 @@ __global__ void k_flow_down(const uint16_t* src, int w, int h, uint16_t* dst) {
     dst[i] = (uint16_t)(((int)r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
 }
 
-// The inverse-compositional search of the patch at (px, py), by one
-// wavefront, lane y * 8 + x on pixel (x, y) of the patch; (u0, u1) start from
-// the coarser scale's dense flow cfx / cfy (cw x ch) at the patch centre, or
-// from zero without one.  Every lane returns the patch's vector.
+// A double from another lane of the same 16-lane row by a DPP move of each
+// half (CTRL: the DPP lane pattern).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 8 lanes of a half-row (lane-xor 1, 2, 4; the halves of the
+// 16-lane DPP rows), in every lane of it: lane-xor 1 and 2 by quad permutes;
+// after them the four lanes of a quad hold the same sum, so the third level
+// takes any lane of the other quad (the half-row mirror).  Each level adds
+// the same two values as a balanced tree, in either order.
+__device__ __forceinline__ double half_row_tree(double v) {
+    v = v + dpp_f64<0xB1>(v);     // quad_perm [1, 0, 3, 2]: lane ^ 1
+    v = v + dpp_f64<0x4E>(v);     // quad_perm [2, 3, 0, 1]: lane ^ 2
+    v = v + dpp_f64<0x141>(v);    // row_half_mirror: the other quad of the half-row
+    return v;
+}
+
+// The 64-term balanced tree of a patch (terms in row-major order) held by a
+// 16-lane group, lane `sub` holding rows 4 (sub >> 3) + k, k = 0..3, of
+// column sub & 7: levels 1-3 (the columns of a row) across the half-row,
+// levels 4-5 (the rows 4 (sub >> 3) .. + 3) inside the lane, level 6 (the
+// two halves of the patch) across the row (the row mirror).  Every lane of
+// the group gets the sum.
+__device__ __forceinline__ double patch_tree(double v0, double v1, double v2, double v3) {
+    const double r0 = half_row_tree(v0), r1 = half_row_tree(v1), r2 = half_row_tree(v2), r3 = half_row_tree(v3);
+    const double h = (r0 + r1) + (r2 + r3);
+    return h + dpp_f64<0x140>(h);   // row_mirror: the other half of the row
+}
+
+// The inverse-compositional search of the patch at (px, py) by a group of 16
+// lanes (a DPP row): lane `sub` holds the patch's pixels in column sub & 7,
+// rows 4 (sub >> 3) .. + 3, so that the lanes of one load read two rows of
+// the patch.  (u0, u1) start from the coarser scale's dense flow cfx / cfy
+// (cw x ch) at the patch centre, or from zero without one.  Every lane of
+// the group returns the patch's vector.
 __device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, const double* cfx, const double* cfy,
-                                             int cw, int ch, int px, int py, int lane, double& ru0, double& ru1) {
+                                             int cw, int ch, int px, int py, int sub, double& ru0, double& ru1) {
     double u0 = 0.0, u1 = 0.0;
     if (cfx) {
         const int cx = min((px + kFP / 2) / 2, cw - 1);
@@ -97,16 +136,26 @@ __device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, c
         u0 = 2.0 * cfx[(int64_t)cy * cw + cx];
         u1 = 2.0 * cfy[(int64_t)cy * cw + cx];
     }
-    const int X = px + (lane & 7), Y = py + (lane >> 3);
+    const int X = px + (sub & 7), Y0 = py + 4 * (sub >> 3);
     // central-difference gradients (exact halves of integer differences)
-    const double a = (fat(I, min(X + 1, I.w - 1), Y) - fat(I, max(X - 1, 0), Y)) / 2.0;
-    const double b = (fat(I, X, min(Y + 1, I.h - 1)) - fat(I, X, max(Y - 1, 0))) / 2.0;
-    const double iv = fat(I, X, Y);
-    const double h00 = wave_tree(a * a) + kFLambda, h01 = wave_tree(a * b), h11 = wave_tree(b * b) + kFLambda;
+    double a[4], b[4], iv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int Y = Y0 + k;
+        a[k] = (fat(I, min(X + 1, I.w - 1), Y) - fat(I, max(X - 1, 0), Y)) / 2.0;
+        b[k] = (fat(I, X, min(Y + 1, I.h - 1)) - fat(I, X, max(Y - 1, 0))) / 2.0;
+        iv[k] = fat(I, X, Y);
+    }
+    const double h00 = patch_tree(a[0] * a[0], a[1] * a[1], a[2] * a[2], a[3] * a[3]) + kFLambda;
+    const double h01 = patch_tree(a[0] * b[0], a[1] * b[1], a[2] * b[2], a[3] * b[3]);
+    const double h11 = patch_tree(b[0] * b[0], b[1] * b[1], b[2] * b[2], b[3] * b[3]) + kFLambda;
     const double det = h00 * h11 - h01 * h01;
     for (int it = 0; it < kFIters; ++it) {
-        const double e = fbilin(J, X + u0, Y + u1) - iv;
-        const double b0 = wave_tree(a * e), b1 = wave_tree(b * e);
+        double e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = fbilin(J, X + u0, Y0 + k + u1) - iv[k];
+        const double b0 = patch_tree(a[0] * e[0], a[1] * e[1], a[2] * e[2], a[3] * e[3]);
+        const double b1 = patch_tree(b[0] * e[0], b[1] * e[1], b[2] * e[2], b[3] * e[3]);
         const double d0 = (h11 * b0 - h01 * b1) / det;
         const double d1 = (h00 * b1 - h01 * b0) / det;
         u0 = fmin(fmax(u0 - d0, -kFUmax), kFUmax);
@@ -116,18 +165,18 @@ __device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, c
     ru1 = u1;
 }
 
-// One wavefront per patch (four per workgroup).  cfx / cfy: the coarser
-// scale's dense flow (cw x ch), null at the coarsest scale.
+// Sixteen patches per 256-lane workgroup, one 16-lane group each.  cfx /
+// cfy: the coarser scale's dense flow (cw x ch), null at the coarsest scale.
 __global__ void __launch_bounds__(256) k_flow_patch(FPlane I, FPlane J, const double* cfx, const double* cfy, int cw,
                                                     int ch, double* ux, double* uy) {
     const int nx = forigins(I.w), ny = forigins(I.h);
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (p >= nx * ny) return;                     // the whole wavefront
-    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (p >= nx * ny) return;                     // the whole group
+    const int sub = threadIdx.x & 15;
     const int j = p / nx, i = p - (p / nx) * nx;
     double u0, u1;
-    patch_search(I, J, cfx, cfy, cw, ch, forigin(I.w, i), forigin(I.h, j), lane, u0, u1);
-    if (lane == 0) {
+    patch_search(I, J, cfx, cfy, cw, ch, forigin(I.w, i), forigin(I.h, j), sub, u0, u1);
+    if (sub == 0) {
         ux[p] = u0;
         uy[p] = u1;
     }
@@ -245,13 +294,13 @@ constexpr int kXcdF = 8;          // accelerator complex dies, one L2 each
 // Scratch of one pair of a list: per scale (finest first) its I and J
 // samples and patch vectors, and for the coarser scales their dense flow
 // (the finest scale's flow is consumed where it is made).  Byte offsets from
-// the pair's base, each array on a 256-byte boundary.
-struct FlowGeo {
-    int ns;
-    int w[kFScales + 1], h[kFScales + 1];
-    int64_t oI[kFScales + 1], oJ[kFScales + 1], oux[kFScales + 1], ouy[kFScales + 1];
-    int64_t ofx[kFScales + 1], ofy[kFScales + 1];
-    int64_t bytes;
+// the pair's base, each array on a 256-byte boundary.  flow_scale gives one
+// scale's entry (w = 0: the pair has no such scale); its loop over the
+// scales is unrolled, so a scale chosen at run time is picked by selects
+// rather than read from an indexed array (which would live in scratch).
+struct FlowScale {
+    int w, h;
+    int64_t oI, oJ, oux, ouy, ofx, ofy;
 };
 
 __host__ __device__ inline int64_t ftake(int64_t& at, int64_t n) {
@@ -260,31 +309,32 @@ __host__ __device__ inline int64_t ftake(int64_t& at, int64_t n) {
     return o;
 }
 
-__host__ __device__ inline FlowGeo flow_geo(int w, int h) {
-    FlowGeo g;
+__host__ __device__ inline FlowScale flow_scale(int w, int h, int k, int64_t* bytes = nullptr) {
+    FlowScale r{0, 0, 0, 0, 0, 0, 0, 0};
     int64_t at = 0;
-    g.ns = 0;
     int cw = w, ch = h;
-    for (int k = 0; k <= kFScales; ++k) {
-        if (k > 0) {
+#pragma unroll
+    for (int s = 0; s <= kFScales; ++s) {
+        if (s > 0) {
             cw /= 2;
             ch /= 2;
             if (cw < kFP || ch < kFP) break;
         }
         const int64_t px = (int64_t)cw * ch;
         const int64_t pt = (int64_t)forigins(cw) * forigins(ch);
-        g.w[k] = cw;
-        g.h[k] = ch;
-        g.oI[k] = ftake(at, 2 * px);
-        g.oJ[k] = ftake(at, 2 * px);
-        g.oux[k] = ftake(at, 8 * pt);
-        g.ouy[k] = ftake(at, 8 * pt);
-        g.ofx[k] = k > 0 ? ftake(at, 8 * px) : 0;
-        g.ofy[k] = k > 0 ? ftake(at, 8 * px) : 0;
-        g.ns = k + 1;
+        FlowScale c;
+        c.w = cw;
+        c.h = ch;
+        c.oI = ftake(at, 2 * px);
+        c.oJ = ftake(at, 2 * px);
+        c.oux = ftake(at, 8 * pt);
+        c.ouy = ftake(at, 8 * pt);
+        c.ofx = s > 0 ? ftake(at, 8 * px) : 0;
+        c.ofy = s > 0 ? ftake(at, 8 * px) : 0;
+        if (s == k) r = c;
     }
-    g.bytes = at;
-    return g;
+    if (bytes) *bytes = at;
+    return r;
 }
 
 // Sample (x, y) of a job's plane (8 or 10 bits, row pitch in samples); with
@@ -311,7 +361,7 @@ enum : int { FL_LOAD = 0, FL_DOWN = 1, FL_PATCH = 2, FL_DENSE = 3, FL_ROWS = 4 }
 // pairs), or with cur set the sparse pairs planned by the previous step's
 // decisions (their count read from cur->sparse_tt[par_prev]).  k: the scale.
 template <int PH>
-__global__ void __launch_bounds__(256) k_flow_list(const StreamDesc* __restrict__ sds,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_flow_list(const StreamDesc* __restrict__ sds,
                                                    const TileJob* __restrict__ jobs, int32_t n_jobs,
                                                    const int32_t* __restrict__ map, int32_t n_tiles,
                                                    const DeviceCursors* __restrict__ cur, int32_t par_prev,
@@ -349,22 +399,23 @@ __global__ void __launch_bounds__(256) k_flow_list(const StreamDesc* __restrict_
         }
         const int r = tile - jb.tile_prefix;
         if (r < 0 || r >= jb.h) continue;
-        const FlowGeo g = flow_geo(jb.w, jb.h);
         uint8_t* base = scratch + (int64_t)jb.tile_prefix * unit;
         if constexpr (PH == FL_LOAD) {
-            uint16_t* dI = reinterpret_cast<uint16_t*>(base + g.oI[0]) + (int64_t)r * jb.w;
-            uint16_t* dJ = reinterpret_cast<uint16_t*>(base + g.oJ[0]) + (int64_t)r * jb.w;
+            const FlowScale S = flow_scale(jb.w, jb.h, 0);
+            uint16_t* dI = reinterpret_cast<uint16_t*>(base + S.oI) + (int64_t)r * jb.w;
+            uint16_t* dJ = reinterpret_cast<uint16_t*>(base + S.oJ) + (int64_t)r * jb.w;
             for (int x = threadIdx.x; x < jb.w; x += 256) {
                 dI[x] = (uint16_t)job_sample(jb.I, jb.pitch, jb.bits, jb.cos_I, x, r);
                 dJ[x] = (uint16_t)job_sample(jb.J, jb.pitch, jb.bits, jb.cos_J, x, r);
             }
         } else if constexpr (PH == FL_DOWN) {
-            if (k < 1 || k >= g.ns || r >= g.h[k]) continue;
-            const int sw = g.w[k - 1], dw = g.w[k];
+            const FlowScale S = flow_scale(jb.w, jb.h, k), F = flow_scale(jb.w, jb.h, k - 1);
+            if (k < 1 || S.w == 0 || r >= S.h) continue;
+            const int sw = F.w, dw = S.w;
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                const uint16_t* src = reinterpret_cast<const uint16_t*>(base + (side ? g.oJ[k - 1] : g.oI[k - 1]));
-                uint16_t* dst = reinterpret_cast<uint16_t*>(base + (side ? g.oJ[k] : g.oI[k])) + (int64_t)r * dw;
+                const uint16_t* src = reinterpret_cast<const uint16_t*>(base + (side ? F.oJ : F.oI));
+                uint16_t* dst = reinterpret_cast<uint16_t*>(base + (side ? S.oJ : S.oI)) + (int64_t)r * dw;
                 for (int x = threadIdx.x; x < dw; x += 256) {
                     const uint16_t* r0 = src + (int64_t)(2 * r) * sw + 2 * x;
                     const uint16_t* r1 = r0 + sw;
@@ -372,42 +423,49 @@ __global__ void __launch_bounds__(256) k_flow_list(const StreamDesc* __restrict_
                 }
             }
         } else if constexpr (PH == FL_PATCH) {
-            if (k >= g.ns || r >= forigins(g.h[k])) continue;
-            const FPlane PI{reinterpret_cast<const uint16_t*>(base + g.oI[k]), g.w[k], g.h[k]};
-            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + g.oJ[k]), g.w[k], g.h[k]};
-            const bool coarse = k + 1 < g.ns;
-            const double* cfx = coarse ? reinterpret_cast<const double*>(base + g.ofx[k + 1]) : nullptr;
-            const double* cfy = coarse ? reinterpret_cast<const double*>(base + g.ofy[k + 1]) : nullptr;
-            const int cw = coarse ? g.w[k + 1] : 0, ch = coarse ? g.h[k + 1] : 0;
-            double* ux = reinterpret_cast<double*>(base + g.oux[k]);
-            double* uy = reinterpret_cast<double*>(base + g.ouy[k]);
-            const int nx = forigins(g.w[k]);
-            const int py = forigin(g.h[k], r);
-            for (int i = wave; i < nx; i += 4) {
-                double u0, u1;
-                patch_search(PI, PJ, cfx, cfy, cw, ch, forigin(g.w[k], i), py, lane, u0, u1);
-                if (lane == 0) {
-                    ux[(int64_t)r * nx + i] = u0;
-                    uy[(int64_t)r * nx + i] = u1;
+            const FlowScale S = flow_scale(jb.w, jb.h, k), Q = flow_scale(jb.w, jb.h, k + 1);
+            if (S.w == 0 || r >= forigins(S.h)) continue;
+            const FPlane PI{reinterpret_cast<const uint16_t*>(base + S.oI), S.w, S.h};
+            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + S.oJ), S.w, S.h};
+            const bool coarse = Q.w != 0;
+            const double* cfx = coarse ? reinterpret_cast<const double*>(base + Q.ofx) : nullptr;
+            const double* cfy = coarse ? reinterpret_cast<const double*>(base + Q.ofy) : nullptr;
+            const int cw = Q.w, ch = Q.h;
+            double* ux = reinterpret_cast<double*>(base + S.oux);
+            double* uy = reinterpret_cast<double*>(base + S.ouy);
+            const int nx = forigins(S.w);
+            const int py = forigin(S.h, r);
+            const int grp = threadIdx.x >> 4, sub = threadIdx.x & 15;
+            for (int i0 = 0; i0 < nx; i0 += 16) {        // the groups of a wavefront stay together
+                const int i = i0 + grp;
+                if (i < nx) {
+                    double u0, u1;
+                    patch_search(PI, PJ, cfx, cfy, cw, ch, forigin(S.w, i), py, sub, u0, u1);
+                    if (sub == 0) {
+                        ux[(int64_t)r * nx + i] = u0;
+                        uy[(int64_t)r * nx + i] = u1;
+                    }
                 }
             }
         } else if constexpr (PH == FL_DENSE) {
-            if (k < 1 || k >= g.ns || r >= g.h[k]) continue;
-            const FPlane PI{reinterpret_cast<const uint16_t*>(base + g.oI[k]), g.w[k], g.h[k]};
-            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + g.oJ[k]), g.w[k], g.h[k]};
-            const double* ux = reinterpret_cast<const double*>(base + g.oux[k]);
-            const double* uy = reinterpret_cast<const double*>(base + g.ouy[k]);
-            double* fx = reinterpret_cast<double*>(base + g.ofx[k]) + (int64_t)r * g.w[k];
-            double* fy = reinterpret_cast<double*>(base + g.ofy[k]) + (int64_t)r * g.w[k];
-            for (int X = threadIdx.x; X < g.w[k]; X += 256) densify_at(PI, PJ, ux, uy, X, r, fx[X], fy[X]);
+            const FlowScale S = flow_scale(jb.w, jb.h, k);
+            if (k < 1 || S.w == 0 || r >= S.h) continue;
+            const FPlane PI{reinterpret_cast<const uint16_t*>(base + S.oI), S.w, S.h};
+            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + S.oJ), S.w, S.h};
+            const double* ux = reinterpret_cast<const double*>(base + S.oux);
+            const double* uy = reinterpret_cast<const double*>(base + S.ouy);
+            double* fx = reinterpret_cast<double*>(base + S.ofx) + (int64_t)r * S.w;
+            double* fy = reinterpret_cast<double*>(base + S.ofy) + (int64_t)r * S.w;
+            for (int X = threadIdx.x; X < S.w; X += 256) densify_at(PI, PJ, ux, uy, X, r, fx[X], fy[X]);
         } else {
             // the finest scale: each pixel's flow, its measure terms, the
             // row's sums in runs of 64 pixels (one run per wavefront), the
             // runs added in order
-            const FPlane PI{reinterpret_cast<const uint16_t*>(base + g.oI[0]), jb.w, jb.h};
-            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + g.oJ[0]), jb.w, jb.h};
-            const double* ux = reinterpret_cast<const double*>(base + g.oux[0]);
-            const double* uy = reinterpret_cast<const double*>(base + g.ouy[0]);
+            const FlowScale S = flow_scale(jb.w, jb.h, 0);
+            const FPlane PI{reinterpret_cast<const uint16_t*>(base + S.oI), jb.w, jb.h};
+            const FPlane PJ{reinterpret_cast<const uint16_t*>(base + S.oJ), jb.w, jb.h};
+            const double* ux = reinterpret_cast<const double*>(base + S.oux);
+            const double* uy = reinterpret_cast<const double*>(base + S.ouy);
             double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             for (int c0 = 0; c0 < jb.w; c0 += 256) {
                 const int c = c0 + 64 * wave;
@@ -516,7 +574,7 @@ hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, in
         const double* cfx = k + 1 < ns ? sc[k + 1].fx : nullptr;
         const double* cfy = k + 1 < ns ? sc[k + 1].fy : nullptr;
         const int cw = k + 1 < ns ? sc[k + 1].w : 0, ch = k + 1 < ns ? sc[k + 1].h : 0;
-        hipLaunchKernelGGL(k_flow_patch, dim3(fgrid(np, 4)), dim3(256), 0, s, PI, PJ, cfx, cfy, cw, ch, c.ux, c.uy);
+        hipLaunchKernelGGL(k_flow_patch, dim3(fgrid(np, 16)), dim3(256), 0, s, PI, PJ, cfx, cfy, cw, ch, c.ux, c.uy);
         hipLaunchKernelGGL(k_flow_densify, dim3(fgrid((int64_t)c.w * c.h, 256)), dim3(256), 0, s, PI, PJ, c.ux, c.uy,
                            c.fx, c.fy);
     }
@@ -537,7 +595,11 @@ hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, in
 }
 
 // Scratch bytes of one pair of a pair list with a w x h plane.
-int64_t flow_pair_bytes(int w, int h) { return flow_geo(w, h).bytes; }
+int64_t flow_pair_bytes(int w, int h) {
+    int64_t b = 0;
+    (void)flow_scale(w, h, 0, &b);
+    return b;
+}
 
 // Workgroups of the pair-list phases one compute unit holds at once (the
 // fullest of them decides).

@@ -469,7 +469,7 @@ vsa_status vsa_debug_pair(const vsa_params* p, const uint16_t* I, const uint16_t
  * sequential definition.
  *
  * vsa_flow_scratch_bytes: device bytes the measure of a w x h pair needs
- * (w, h >= 8), or VSA_E_INVAL.
+ * (w, h >= 8, fewer than 2^31 samples), or VSA_E_INVAL.
  * vsa_flow_pair: I, J device planes of w x h samples (bits 8: bytes, 10:
  * uint16 words, 2-byte aligned) with a row pitch in bytes; scratch: device
  * memory of at least vsa_flow_scratch_bytes (the caller's, not kept);

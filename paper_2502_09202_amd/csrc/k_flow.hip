@@ -41,7 +41,13 @@ struct FPlane {
     int w, h;
 };
 
-__device__ __forceinline__ int fat(const FPlane& P, int x, int y) { return (int)P.px[(int64_t)y * P.w + x]; }
+// A plane has fewer than 2^31 samples and sides below 2^24 (the entries
+// refuse larger ones), so a 24-bit row product and a 32-bit byte offset from
+// the plane's base reach every sample.
+__device__ __forceinline__ int fat(const FPlane& P, int x, int y) {
+    const uint32_t off = 2u * (__umul24((uint32_t)y, (uint32_t)P.w) + (uint32_t)x);
+    return (int)*reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(P.px) + off);
+}
 
 __device__ __forceinline__ double fbilin(const FPlane& J, double X, double Y) {
     const double xc = fmin(fmax(X, 0.0), (double)(J.w - 1));
@@ -92,8 +98,8 @@ __global__ void k_flow_down(const uint16_t* src, int w, int h, uint16_t* dst) {
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 

@@ -912,6 +912,8 @@ static vsa_status prepare_stream(const vsa_engine* e, const vsa_stream_desc* d, 
     if (st != VSA_OK) return st;
     layout(g, d->width, d->height, d->bit_depth, kmax, sd);
     sd.search = e->params.search;
+    if (sd.search == 2 && (int64_t)d->width * d->height >= (1ll << 31))
+        return fail(VSA_E_UNSUPPORTED, "frames of 2^31 samples or more with the dense flow");
     st = check_exact_sums(sd);
     if (st != VSA_OK) return st;
     staging_pitch = round_up((int64_t)d->width * (d->bit_depth == 8 ? 1 : 2), 256);
@@ -1750,8 +1752,13 @@ vsa_status vsa_debug_levels(const vsa_params* pp, const void* luma, int32_t W, i
     return VSA_OK;
 }
 
+// The flow kernels address a plane with 24-bit row products and 32-bit byte
+// offsets: sides below 2^24 and fewer than 2^31 samples.
+static bool flow_plane_fits(int64_t w, int64_t h) { return w < (1 << 24) && h < (1 << 24) && w * h < (1ll << 31); }
+
 int64_t vsa_flow_scratch_bytes(int32_t w, int32_t h) {
     if (w < 8 || h < 8) return fail(VSA_E_INVAL, "plane smaller than one 8 x 8 patch");
+    if (!flow_plane_fits(w, h)) return fail(VSA_E_INVAL, "plane of 2^31 samples or more");
     return flow_scratch_bytes(w, h);
 }
 
@@ -1760,6 +1767,7 @@ vsa_status vsa_flow_pair(const vsa_params* pp, const void* I, const void* J, int
                          void* hip_stream) {
     if (!I || !J || !scratch || !results || (bits != 8 && bits != 10)) return fail(VSA_E_INVAL, "bad argument");
     if (w < 8 || h < 8) return fail(VSA_E_INVAL, "plane smaller than one 8 x 8 patch");
+    if (!flow_plane_fits(w, h)) return fail(VSA_E_INVAL, "plane of 2^31 samples or more");
     if (pitch_bytes < (int64_t)w * (bits == 8 ? 1 : 2)) return fail(VSA_E_INVAL, "pitch smaller than a row");
     if (bits == 10 && ((pitch_bytes & 1) || (reinterpret_cast<uintptr_t>(I) & 1) || (reinterpret_cast<uintptr_t>(J) & 1)))
         return fail(VSA_E_INVAL, "10-bit planes and pitch must be 2-byte aligned");
@@ -1776,6 +1784,7 @@ vsa_status vsa_flow_pair(const vsa_params* pp, const void* I, const void* J, int
 vsa_status vsa_debug_flow_pair(const vsa_params* pp, const uint16_t* I, const uint16_t* J, int32_t w, int32_t h,
                                int32_t bits, double* flow, double* dbl, int32_t* is_static) {
     if (!I || !J || (bits != 8 && bits != 10) || w < 8 || h < 8) return fail(VSA_E_INVAL, "bad argument");
+    if (!flow_plane_fits(w, h)) return fail(VSA_E_INVAL, "plane of 2^31 samples or more");
     const int maxv = bits == 8 ? 255 : 1023;
     for (int64_t i = 0; i < (int64_t)w * h; ++i)
         if (I[i] > maxv || J[i] > maxv) return fail(VSA_E_INVAL, "sample out of range");
@@ -2292,6 +2301,8 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     StreamDesc sd;
     layout(g, cfg->width, cfg->height, cfg->bit_depth, kmax, sd);
     sd.search = p.search;
+    if (sd.search == 2 && (int64_t)cfg->width * cfg->height >= (1ll << 31))
+        return fail(VSA_E_UNSUPPORTED, "frames of 2^31 samples or more with the dense flow");
     st = check_exact_sums(sd);
     if (st != VSA_OK) return st;
     // the chunk being decided, the chunk being ingested beside it, the deep

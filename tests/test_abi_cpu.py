@@ -124,3 +124,17 @@ def test_params_from_json(vsa, params):
                 '{"k_max": -infinity}'):
         with pytest.raises(vsa.VsaError):
             vsa.params_from_json(bad)
+
+
+def test_flow_scratch_sizes(vsa):
+    """The flow pair's scratch size is host arithmetic: monotone in the plane,
+    refused below one patch and at 2^31 samples or more (the kernels address
+    a plane with 32-bit offsets)."""
+    a = vsa.flow_scratch_bytes(512, 270)
+    assert a > 0 and a % 256 == 0
+    assert vsa.flow_scratch_bytes(1024, 270) > a > vsa.flow_scratch_bytes(256, 135)
+    assert vsa.flow_scratch_bytes(8, 8) > 0
+    for w, h in ((7, 8), (8, 7), (1 << 16, 1 << 15), (1 << 24, 8)):
+        with pytest.raises(vsa.VsaError):
+            vsa.flow_scratch_bytes(w, h)
+    assert vsa.flow_scratch_bytes((1 << 16) - 1, 1 << 15) > 0

@@ -93,16 +93,6 @@ __global__ void k_flow_down(const uint16_t* src, int w, int h, uint16_t* dst) {
     dst[i] = (uint16_t)(((int)r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
 }
 
-// A double from another lane of the same 16-lane row by a DPP move of each
-// half (CTRL: the DPP lane pattern).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 // Sum over the 8 lanes of a half-row (lane-xor 1, 2, 4; the halves of the
 // 16-lane DPP rows), in every lane of it: lane-xor 1 and 2 by quad permutes;
 // after them the four lanes of a quad hold the same sum, so the third level

@@ -26,11 +26,30 @@ __device__ __forceinline__ void finish_pair(int64_t sx, int64_t sy, int64_t sxx,
     out[0] = ncc; out[1] = swr; out[2] = amm; out[3] = act;
 }
 
+// A double from another lane of the same 16-lane row by a DPP move of each
+// half (CTRL: the DPP lane pattern).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Balanced binary tree sum of the 64 lanes' values (lane order), in every
-// lane: the butterfly of xor shuffles adds lane pairs, then pairs of pairs.
+// lane: a butterfly that adds lane pairs, then pairs of pairs.  Levels 1-2
+// (lane ^ 1, lane ^ 2) by DPP quad permutes; after them the lanes of a quad
+// hold equal values, so level 3 takes any lane of the other quad of the
+// half-row (the half-row mirror) and, likewise, level 4 any lane of the other
+// half of the row (the row mirror); levels 5-6 (lane ^ 16, lane ^ 32) by
+// shuffles.  Every level adds the tree's two values, in either order.
 __device__ __forceinline__ double wave_tree(double v) {
-#pragma unroll
-    for (int step = 1; step < 64; step *= 2) v = v + __shfl_xor(v, step, 64);
+    v = v + dpp_f64<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+    v = v + dpp_f64<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+    v = v + dpp_f64<0x141>(v);    // row_half_mirror
+    v = v + dpp_f64<0x140>(v);    // row_mirror
+    v = v + __shfl_xor(v, 16, 64);
+    v = v + __shfl_xor(v, 32, 64);
     return v;
 }
 

@@ -431,29 +431,33 @@ vsa_status ensure_partials(vsa_engine* e) {
     HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream_c), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    // the new buffers first: if they do not fit, the old ones stay in place
+    // and the open streams keep running
+    const int64_t old_cap = e->partials_cap;
+    const int64_t cap = std::max<int64_t>(need * 2, 4096);
+    TilePartial* np = nullptr;
+    int32_t *ncmap = nullptr, *nsmap = nullptr;
+    // partials: consecutive pairs of even and odd steps, then the sparse pairs
+    bool ok = hipMalloc(&np, sizeof(TilePartial) * cap * 3) == hipSuccess &&
+              hipMalloc(&ncmap, sizeof(int32_t) * cap * (kAhead + 1)) == hipSuccess &&
+              hipMalloc(&nsmap, sizeof(int32_t) * cap * 2) == hipSuccess;
     // the sparse tile maps planned by the last decision kernel are still to be
     // read by the next motion search: they move to the new allocation
-    const int64_t old_cap = e->partials_cap;
-    int32_t* old_smap = e->d_smap;
-    if (e->d_partials) HIPCK(hipFree(e->d_partials), "hipFree");
-    if (e->d_cmap) HIPCK(hipFree(e->d_cmap), "hipFree");
-    e->d_partials = nullptr;
-    e->d_cmap = e->d_smap = nullptr;
-    const int64_t cap = std::max<int64_t>(need * 2, 4096);
-    // partials: consecutive pairs of even and odd steps, then the sparse pairs
-    bool ok = hipMalloc(&e->d_partials, sizeof(TilePartial) * cap * 3) == hipSuccess &&
-              hipMalloc(&e->d_cmap, sizeof(int32_t) * cap * (kAhead + 1)) == hipSuccess &&
-              hipMalloc(&e->d_smap, sizeof(int32_t) * cap * 2) == hipSuccess;
-    if (ok && old_smap) {
+    if (ok && e->d_smap) {
         for (int par = 0; ok && par < 2; ++par)
-            ok = hipMemcpy(e->d_smap + par * cap, old_smap + par * old_cap, sizeof(int32_t) * old_cap,
+            ok = hipMemcpy(nsmap + par * cap, e->d_smap + par * old_cap, sizeof(int32_t) * old_cap,
                            hipMemcpyDeviceToDevice) == hipSuccess;
     }
-    if (old_smap) (void)hipFree(old_smap);
     if (!ok) {
-        e->partials_cap = 0;
+        for (void* q : {(void*)np, (void*)ncmap, (void*)nsmap})
+            if (q) (void)hipFree(q);
         return fail(VSA_E_NOMEM, "tile partial buffer");
     }
+    for (void* q : {(void*)e->d_partials, (void*)e->d_cmap, (void*)e->d_smap})
+        if (q) (void)hipFree(q);
+    e->d_partials = np;
+    e->d_cmap = ncmap;
+    e->d_smap = nsmap;
     e->partials_cap = cap;
     return VSA_OK;
 }
@@ -474,20 +478,21 @@ vsa_status ensure_flow(vsa_engine* e) {
     HIPCK(hipStreamSynchronize(e->stream_b), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream_c), "hipStreamSynchronize");
     HIPCK(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-    if (e->d_flow_c) HIPCK(hipFree(e->d_flow_c), "hipFree");
-    if (e->d_flow_s) HIPCK(hipFree(e->d_flow_s), "hipFree");
-    e->d_flow_c = e->d_flow_s = nullptr;
     unit = std::max(unit, e->flow_unit);
     const int64_t tc = std::max(e->flow_tiles_c, need_c + need_c / 2);
     const int64_t ts = std::max(e->flow_tiles_s, need_s + need_s / 2);
-    const bool ok = hipMalloc(&e->d_flow_c, (size_t)(unit * tc)) == hipSuccess &&
-                    hipMalloc(&e->d_flow_s, (size_t)(unit * ts)) == hipSuccess;
+    // the new buffers first: if they do not fit, the old ones stay in place
+    uint8_t *nc = nullptr, *ns = nullptr;
+    const bool ok = hipMalloc(&nc, (size_t)(unit * tc)) == hipSuccess &&
+                    hipMalloc(&ns, (size_t)(unit * ts)) == hipSuccess;
     if (!ok) {
-        if (e->d_flow_c) (void)hipFree(e->d_flow_c);
-        e->d_flow_c = e->d_flow_s = nullptr;
-        e->flow_unit = e->flow_tiles_c = e->flow_tiles_s = 0;
+        if (nc) (void)hipFree(nc);
         return fail(VSA_E_NOMEM, "dense flow scratch");
     }
+    if (e->d_flow_c) (void)hipFree(e->d_flow_c);
+    if (e->d_flow_s) (void)hipFree(e->d_flow_s);
+    e->d_flow_c = nc;
+    e->d_flow_s = ns;
     e->flow_unit = unit;
     e->flow_tiles_c = tc;
     e->flow_tiles_s = ts;
@@ -1438,6 +1443,8 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         if (g >= 8) g -= g % 8;
         return g;
     };
+    if (flow && (consec_tiles > 0 || sparse_max > 0) && (!e->d_flow_c || !e->d_flow_s))
+        return fail(VSA_E_STATE, "dense flow scratch missing");
     // one launch per sample width that an open stream has
     if (flow) {
         if (consec_tiles > 0)

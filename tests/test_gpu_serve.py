@@ -110,3 +110,38 @@ def test_served_small_poll_cap_keeps_every_record(vsa, orc, params):
     for r in reqs:
         frames = np.ascontiguousarray(host[(r.start + np.arange(r.length)) % host.shape[0]])
         _compare(rep.results[r.cid], orc.run_clip(frames, params), f"{r.cid} vs oracle")
+
+
+def test_served_dense_flow_mix(vsa, orc, params):
+    """The served form with the dense flow (search = 2): clips of four formats
+    queue for three slots, finished clips release slots that later clips of
+    other shapes reuse (sparse flow pairs planned for a closed stream are
+    skipped, the flow scratch grows between steps), and every clip's records
+    equal the oracle's, the measures bit for bit."""
+    import torch
+    from paper_2502_09202_amd import serve
+    src = _sources(torch)
+    rng = np.random.default_rng(23)
+    reqs = []
+    for cid in range(8):
+        dev, host, bits = src[cid % len(src)]
+        length = int(rng.integers(10, 24))
+        start = int(rng.integers(0, dev.shape[0]))
+        reqs.append((serve.ClipRequest(cid, 0.0 if cid < 6 else 0.01, dev, start, length, bits), host))
+    p = dict(params, search=2)
+    srv = serve.Server(max_streams=3, params=p)
+    try:
+        rep = srv.run([r for r, _ in reqs])
+    finally:
+        srv.close()
+    assert len(rep.results) == len(reqs)
+    assert rep.max_concurrent <= 3
+    for r, host in reqs:
+        frames = np.ascontiguousarray(host[(r.start + np.arange(r.length)) % host.shape[0]])
+        ref = orc.run_clip(frames, p, bits=r.bit_depth)
+        got = rep.results[r.cid]
+        _compare(got, ref, f"{r.cid} vs oracle")
+        for name in ("ncc", "swr", "amm", "act"):
+            a, b = got.frames[name], ref["frames"][name]
+            ok = ~np.isnan(b)
+            assert np.array_equal(a[ok].view(np.uint64), b[ok].view(np.uint64)), f"clip {r.cid}: {name}"

@@ -105,26 +105,44 @@ __device__ __forceinline__ double half_row_tree(double v) {
     return v;
 }
 
+// Lanes per patch in the patch search, PL = 8 or 16: each lane holds
+// 64 / PL pixels of one column of its patch (rows (64 / PL) (sub >> 3) ..
+// + 64 / PL - 1 of column sub & 7), so that the lanes of one load read few
+// rows.  Eight lanes (a whole column each) issue fewer instructions per patch
+// and suit the pair lists, which have patches to spare; sixteen give a single
+// pair twice the groups in flight.
+constexpr int kPLList = 8;
+constexpr int kPLPair = 16;
+
 // The 64-term balanced tree of a patch (terms in row-major order) held by a
-// 16-lane group, lane `sub` holding rows 4 (sub >> 3) + k, k = 0..3, of
-// column sub & 7: levels 1-3 (the columns of a row) across the half-row,
-// levels 4-5 (the rows 4 (sub >> 3) .. + 3) inside the lane, level 6 (the
-// two halves of the patch) across the row (the row mirror).  Every lane of
-// the group gets the sum.
-__device__ __forceinline__ double patch_tree(double v0, double v1, double v2, double v3) {
-    const double r0 = half_row_tree(v0), r1 = half_row_tree(v1), r2 = half_row_tree(v2), r3 = half_row_tree(v3);
-    const double h = (r0 + r1) + (r2 + r3);
-    return h + dpp_f64<0x140>(h);   // row_mirror: the other half of the row
+// group of PL lanes (the layout above): levels 1-3 (the columns of a row)
+// across the half-row, the next log2(64 / PL) levels (the lane's rows) inside
+// the lane, and with 16 lanes the last (the two halves of the patch) across
+// the row (the row mirror).  Every lane of the group gets the sum.
+template <int PL>
+__device__ __forceinline__ double patch_tree(double v[64 / PL]) {
+    static_assert(PL == 8 || PL == 16, "a patch group is a half-row or a row of the DPP lanes");
+    constexpr int kPR = 64 / PL;
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) v[k] = half_row_tree(v[k]);
+#pragma unroll
+    for (int step = 1; step < kPR; step *= 2) {
+#pragma unroll
+        for (int k = 0; k < kPR; k += 2 * step) v[k] = v[k] + v[k + step];
+    }
+    if constexpr (PL == 16) return v[0] + dpp_f64<0x140>(v[0]);   // row_mirror: the other half of the row
+    return v[0];
 }
 
-// The inverse-compositional search of the patch at (px, py) by a group of 16
-// lanes (a DPP row): lane `sub` holds the patch's pixels in column sub & 7,
-// rows 4 (sub >> 3) .. + 3, so that the lanes of one load read two rows of
-// the patch.  (u0, u1) start from the coarser scale's dense flow cfx / cfy
-// (cw x ch) at the patch centre, or from zero without one.  Every lane of
-// the group returns the patch's vector.
+// The inverse-compositional search of the patch at (px, py) by a group of
+// PL lanes holding 64 / PL pixels of one column each (lane `sub`).  (u0, u1)
+// start from the coarser scale's dense flow cfx / cfy (cw x ch) at the patch
+// centre, or from zero without one.  Every lane of the group returns the
+// patch's vector.
+template <int PL>
 __device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, const double* cfx, const double* cfy,
                                              int cw, int ch, int px, int py, int sub, double& ru0, double& ru1) {
+    constexpr int kPR = 64 / PL;
     double u0 = 0.0, u1 = 0.0;
     if (cfx) {
         const int cx = min((px + kFP / 2) / 2, cw - 1);
@@ -132,26 +150,36 @@ __device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, c
         u0 = 2.0 * cfx[(int64_t)cy * cw + cx];
         u1 = 2.0 * cfy[(int64_t)cy * cw + cx];
     }
-    const int X = px + (sub & 7), Y0 = py + 4 * (sub >> 3);
+    const int X = px + (sub & 7), Y0 = py + kPR * (sub >> 3);
     // central-difference gradients (exact halves of integer differences)
-    double a[4], b[4], iv[4];
+    double a[kPR], b[kPR], iv[kPR], t[kPR];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kPR; ++k) {
         const int Y = Y0 + k;
         a[k] = (fat(I, min(X + 1, I.w - 1), Y) - fat(I, max(X - 1, 0), Y)) / 2.0;
         b[k] = (fat(I, X, min(Y + 1, I.h - 1)) - fat(I, X, max(Y - 1, 0))) / 2.0;
         iv[k] = fat(I, X, Y);
     }
-    const double h00 = patch_tree(a[0] * a[0], a[1] * a[1], a[2] * a[2], a[3] * a[3]) + kFLambda;
-    const double h01 = patch_tree(a[0] * b[0], a[1] * b[1], a[2] * b[2], a[3] * b[3]);
-    const double h11 = patch_tree(b[0] * b[0], b[1] * b[1], b[2] * b[2], b[3] * b[3]) + kFLambda;
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) t[k] = a[k] * a[k];
+    const double h00 = patch_tree<PL>(t) + kFLambda;
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) t[k] = a[k] * b[k];
+    const double h01 = patch_tree<PL>(t);
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) t[k] = b[k] * b[k];
+    const double h11 = patch_tree<PL>(t) + kFLambda;
     const double det = h00 * h11 - h01 * h01;
     for (int it = 0; it < kFIters; ++it) {
-        double e[4];
+        double e[kPR];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = fbilin(J, X + u0, Y0 + k + u1) - iv[k];
-        const double b0 = patch_tree(a[0] * e[0], a[1] * e[1], a[2] * e[2], a[3] * e[3]);
-        const double b1 = patch_tree(b[0] * e[0], b[1] * e[1], b[2] * e[2], b[3] * e[3]);
+        for (int k = 0; k < kPR; ++k) e[k] = fbilin(J, X + u0, Y0 + k + u1) - iv[k];
+#pragma unroll
+        for (int k = 0; k < kPR; ++k) t[k] = a[k] * e[k];
+        const double b0 = patch_tree<PL>(t);
+#pragma unroll
+        for (int k = 0; k < kPR; ++k) t[k] = b[k] * e[k];
+        const double b1 = patch_tree<PL>(t);
         const double d0 = (h11 * b0 - h01 * b1) / det;
         const double d1 = (h00 * b1 - h01 * b0) / det;
         u0 = fmin(fmax(u0 - d0, -kFUmax), kFUmax);
@@ -161,17 +189,19 @@ __device__ __forceinline__ void patch_search(const FPlane& I, const FPlane& J, c
     ru1 = u1;
 }
 
-// Sixteen patches per 256-lane workgroup, one 16-lane group each.  cfx /
-// cfy: the coarser scale's dense flow (cw x ch), null at the coarsest scale.
+// 256 / kPLPair patches per 256-lane workgroup, one group of kPLPair lanes
+// each.
+// cfx / cfy: the coarser scale's dense flow (cw x ch), null at the coarsest
+// scale.
 __global__ void __launch_bounds__(256) k_flow_patch(FPlane I, FPlane J, const double* cfx, const double* cfy, int cw,
                                                     int ch, double* ux, double* uy) {
     const int nx = forigins(I.w), ny = forigins(I.h);
-    const int p = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int p = blockIdx.x * (256 / kPLPair) + threadIdx.x / kPLPair;
     if (p >= nx * ny) return;                     // the whole group
-    const int sub = threadIdx.x & 15;
+    const int sub = threadIdx.x % kPLPair;
     const int j = p / nx, i = p - (p / nx) * nx;
     double u0, u1;
-    patch_search(I, J, cfx, cfy, cw, ch, forigin(I.w, i), forigin(I.h, j), sub, u0, u1);
+    patch_search<kPLPair>(I, J, cfx, cfy, cw, ch, forigin(I.w, i), forigin(I.h, j), sub, u0, u1);
     if (sub == 0) {
         ux[p] = u0;
         uy[p] = u1;
@@ -431,12 +461,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             double* uy = reinterpret_cast<double*>(base + S.ouy);
             const int nx = forigins(S.w);
             const int py = forigin(S.h, r);
-            const int grp = threadIdx.x >> 4, sub = threadIdx.x & 15;
-            for (int i0 = 0; i0 < nx; i0 += 16) {        // the groups of a wavefront stay together
+            const int grp = threadIdx.x / kPLList, sub = threadIdx.x % kPLList;
+            for (int i0 = 0; i0 < nx; i0 += 256 / kPLList) {   // the groups of a wavefront stay together
                 const int i = i0 + grp;
                 if (i < nx) {
                     double u0, u1;
-                    patch_search(PI, PJ, cfx, cfy, cw, ch, forigin(S.w, i), py, sub, u0, u1);
+                    patch_search<kPLList>(PI, PJ, cfx, cfy, cw, ch, forigin(S.w, i), py, sub, u0, u1);
                     if (sub == 0) {
                         ux[(int64_t)r * nx + i] = u0;
                         uy[(int64_t)r * nx + i] = u1;
@@ -570,7 +600,8 @@ hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, in
         const double* cfx = k + 1 < ns ? sc[k + 1].fx : nullptr;
         const double* cfy = k + 1 < ns ? sc[k + 1].fy : nullptr;
         const int cw = k + 1 < ns ? sc[k + 1].w : 0, ch = k + 1 < ns ? sc[k + 1].h : 0;
-        hipLaunchKernelGGL(k_flow_patch, dim3(fgrid(np, 16)), dim3(256), 0, s, PI, PJ, cfx, cfy, cw, ch, c.ux, c.uy);
+        hipLaunchKernelGGL(k_flow_patch, dim3(fgrid(np, 256 / kPLPair)), dim3(256), 0, s, PI, PJ, cfx, cfy, cw, ch,
+                           c.ux, c.uy);
         hipLaunchKernelGGL(k_flow_densify, dim3(fgrid((int64_t)c.w * c.h, 256)), dim3(256), 0, s, PI, PJ, c.ux, c.uy,
                            c.fx, c.fy);
     }

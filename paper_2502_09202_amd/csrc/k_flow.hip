@@ -628,25 +628,20 @@ int64_t flow_pair_bytes(int w, int h) {
     return b;
 }
 
-// Workgroups of the pair-list phases one compute unit holds at once (the
-// fullest of them decides).
-int flow_list_max_wgs_per_cu() {
-    static int cached = 0;
-    if (cached == 0) {
-        int lo = 64;
+// Workgroups of pair-list phase `ph` one compute unit holds at once.
+static int flow_phase_wgs_per_cu(int ph) {
+    static int cached[5] = {0, 0, 0, 0, 0};
+    if (cached[ph] == 0) {
         const void* fns[] = {reinterpret_cast<const void*>(k_flow_list<FL_LOAD>),
                              reinterpret_cast<const void*>(k_flow_list<FL_DOWN>),
                              reinterpret_cast<const void*>(k_flow_list<FL_PATCH>),
                              reinterpret_cast<const void*>(k_flow_list<FL_DENSE>),
                              reinterpret_cast<const void*>(k_flow_list<FL_ROWS>)};
-        for (const void* f : fns) {
-            int n = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess || n < 1) n = 1;
-            lo = std::min(lo, n);
-        }
-        cached = lo;
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fns[ph], 256, 0) != hipSuccess || n < 1) n = 1;
+        cached[ph] = n;
     }
-    return cached;
+    return cached[ph];
 }
 
 // Every phase of the dense flow over a pair list (jobs, map as for the
@@ -654,28 +649,36 @@ int flow_list_max_wgs_per_cu() {
 // then coarsest first the patch search and (coarser scales) the dense flow,
 // and last the finest scale's row sums into rows (one per tile).  With clear
 // set (sparse lists), the first phase clears the counter of the other parity.
+// Each phase's persistent grid takes as many workgroups as the compute units
+// hold of it (cus of them), at most tiles_bound (the list's largest tile
+// count), in whole groups of one workgroup per XCD.
 hipError_t launch_flow_list(const StreamDesc* sds, const TileJob* jobs, int32_t n_jobs, const int32_t* map,
                             int32_t n_tiles, const DeviceCursors* cur, int32_t par_prev, bool clear, uint8_t* scratch,
-                            int64_t unit, TilePartial* rows, int grid, hipStream_t s) {
-    if (grid <= 0) return hipSuccess;
+                            int64_t unit, TilePartial* rows, int64_t tiles_bound, int cus, hipStream_t s) {
+    if (tiles_bound <= 0) return hipSuccess;
     unsigned long long* clear_tt =
         (cur && clear) ? const_cast<unsigned long long*>(&cur->sparse_tt[par_prev ^ 1].v) : nullptr;
     FlowRow* fr = reinterpret_cast<FlowRow*>(rows);
-    const dim3 g(grid), b(256);
-    hipLaunchKernelGGL(k_flow_list<FL_LOAD>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch, unit,
-                       fr, 0, clear_tt);
+    auto grid = [&](int ph) {
+        int g = (int)std::min<int64_t>(tiles_bound, (int64_t)flow_phase_wgs_per_cu(ph) * std::max(cus, 1));
+        if (g >= kXcdF) g -= g % kXcdF;
+        return dim3(std::max(g, 1));
+    };
+    const dim3 b(256);
+    hipLaunchKernelGGL(k_flow_list<FL_LOAD>, grid(FL_LOAD), b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev,
+                       scratch, unit, fr, 0, clear_tt);
     for (int k = 1; k <= kFScales; ++k)
-        hipLaunchKernelGGL(k_flow_list<FL_DOWN>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch,
-                           unit, fr, k, nullptr);
+        hipLaunchKernelGGL(k_flow_list<FL_DOWN>, grid(FL_DOWN), b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
+                           par_prev, scratch, unit, fr, k, nullptr);
     for (int k = kFScales; k >= 0; --k) {
-        hipLaunchKernelGGL(k_flow_list<FL_PATCH>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch,
-                           unit, fr, k, nullptr);
+        hipLaunchKernelGGL(k_flow_list<FL_PATCH>, grid(FL_PATCH), b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
+                           par_prev, scratch, unit, fr, k, nullptr);
         if (k > 0)
-            hipLaunchKernelGGL(k_flow_list<FL_DENSE>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev,
-                               scratch, unit, fr, k, nullptr);
+            hipLaunchKernelGGL(k_flow_list<FL_DENSE>, grid(FL_DENSE), b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur,
+                               par_prev, scratch, unit, fr, k, nullptr);
     }
-    hipLaunchKernelGGL(k_flow_list<FL_ROWS>, g, b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev, scratch, unit,
-                       fr, 0, nullptr);
+    hipLaunchKernelGGL(k_flow_list<FL_ROWS>, grid(FL_ROWS), b, 0, s, sds, jobs, n_jobs, map, n_tiles, cur, par_prev,
+                       scratch, unit, fr, 0, nullptr);
     return hipGetLastError();
 }
 

@@ -57,9 +57,8 @@ int64_t flow_scratch_bytes(int w, int h);
 hipError_t launch_flow_pair(const uint8_t* I, const uint8_t* J, int w, int h, int64_t pitch, int bits, double a0,
                             int a_static_fx, uint8_t* scratch, double* flow_out, double* res_out, hipStream_t s);
 int64_t flow_pair_bytes(int w, int h);
-int flow_list_max_wgs_per_cu();
 hipError_t launch_flow_list(const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t, const DeviceCursors*,
-                            int32_t, bool, uint8_t*, int64_t, TilePartial*, int grid, hipStream_t);
+                            int32_t, bool, uint8_t*, int64_t, TilePartial*, int64_t tiles_bound, int cus, hipStream_t);
 hipError_t launch_me_hier(int bits, const StreamDesc*, const TileJob*, int32_t, const int32_t*, int32_t,
                           const DeviceCursors*, int32_t, TilePartial*, int8_t*, int32_t*, int grid, hipStream_t,
                           LaunchTiming = {});
@@ -1435,21 +1434,13 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     TileJob* sjobs_next = e->d_sjobs + (size_t)par * sp_cap;
     int32_t* smap_prev = e->d_smap + (size_t)(par ^ 1) * e->partials_cap;
     int32_t* smap_next = e->d_smap + (size_t)par * e->partials_cap;
-    // the dense flow (search 2): every phase over the list, persistent grids
-    // within the phases' occupancy
-    const int fl_cap = flow ? flow_list_max_wgs_per_cu() : 0;
-    auto fl_grid = [&](int64_t tiles) {
-        int g = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)fl_cap * e->cus);
-        if (g >= 8) g -= g % 8;
-        return g;
-    };
     if (flow && (consec_tiles > 0 || sparse_max > 0) && (!e->d_flow_c || !e->d_flow_s))
         return fail(VSA_E_STATE, "dense flow scratch missing");
     // one launch per sample width that an open stream has
     if (flow) {
         if (consec_tiles > 0)
             HIPCK(launch_flow_list(e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, false, e->d_flow_c,
-                                   e->flow_unit, cpart, fl_grid(consec_tiles), Cs),
+                                   e->flow_unit, cpart, consec_tiles, e->cus, Cs),
                   "dense flow launch");
     } else if (consec_tiles > 0 && !hier) {
         if (e->has8)
@@ -1473,7 +1464,7 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
     const bool sparse8 = e->has8 || !e->has10;
     if (flow)
         HIPCK(launch_flow_list(e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true,
-                               e->d_flow_s, e->flow_unit, spart, fl_grid(sparse_max), A),
+                               e->d_flow_s, e->flow_unit, spart, std::max<int64_t>(sparse_max, 1), e->cus, A),
               "dense flow launch");
     if (sparse8 && !flow)
         HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart,
@@ -2058,7 +2049,7 @@ struct vsa_clip {
     int sparse_tiles = 0;          // most tiles one round's sparse pairs can have
     int grid_c = 0, grid_s = 0;    // persistent motion-search grids
     int grid_hc = 0, grid_hs = 0;  // and those of the coarse-to-fine kernel (search = 1)
-    int grid_fc = 0, grid_fs = 0;  // and those of the dense flow's phases (search = 2)
+    int cus = 0;                   // compute units (the dense flow's phase grids, search = 2)
     int64_t flow_unit = 0;         // dense flow scratch bytes per tile
     uint8_t* d_flow_c = nullptr;   // C x pair_tiles units (the consecutive pairs of a chunk)
     uint8_t* d_flow_s = nullptr;   // sparse_tiles units
@@ -2121,7 +2112,7 @@ vsa_status clip_decide(vsa_clip* c, const StepStream* d_entry) {
     TilePartial* spart = c->d_part + (size_t)2 * c->C * c->pair_tiles;
     if (c->sd.search == 2)
         HIPCK(launch_flow_list(c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, c->d_flow_s,
-                               c->flow_unit, spart, c->grid_fs, c->s),
+                               c->flow_unit, spart, c->sparse_tiles, c->cus, c->s),
               "dense flow launch");
     else
         HIPCK(launch_me(c->sd.bits, c->d_sds, sj_prev, (int32_t)tc, sm_prev, 0, c->d_cur, par ^ 1, true, spart,
@@ -2239,10 +2230,8 @@ vsa_status clip_ingest(vsa_clip* c, const ClipSource& in, int ch, int* n_cons_ou
           "pyramid launch");
     if (!c->no_intensity) HIPCK(launch_intensity(c->d_sds, d_steps, d_k1, n, c->sp), "intensity launch");
     if (ctiles > 0 && sd.search == 2) {
-        int gc = std::min(c->grid_fc, ctiles);
-        if (gc >= 8) gc -= gc % 8;
         HIPCK(launch_flow_list(c->d_sds, cjobs, C, cmap, ctiles, nullptr, 0, false, c->d_flow_c, c->flow_unit, cpart,
-                               gc, c->sp),
+                               ctiles, c->cus, c->sp),
               "dense flow launch");
     } else if (ctiles > 0) {
         int gc = std::min(sd.search ? c->grid_hc : c->grid_c, ctiles);
@@ -2340,14 +2329,7 @@ vsa_status vsa_clip_create(const vsa_clip_config* cfg, vsa_clip** out) {
     c->grid_c = grid((int64_t)C * c->pair_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 2);
     c->grid_s = grid(c->sparse_tiles, cfg->me_wgs_per_cu ? cfg->me_wgs_per_cu : 4);
     if (sd.search == 2) {
-        const int fl_cap = flow_list_max_wgs_per_cu();
-        auto fgrid = [&](int64_t tiles) {
-            int gsz = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)fl_cap * cus);
-            if (gsz >= 8) gsz -= gsz % 8;
-            return gsz;
-        };
-        c->grid_fc = fgrid((int64_t)C * c->pair_tiles);
-        c->grid_fs = fgrid(c->sparse_tiles);
+        c->cus = cus;
         c->flow_unit = flow_unit(sd);
     } else if (sd.search) {
         const int mh_cap = me_hier_max_wgs_per_cu(sd.bits);

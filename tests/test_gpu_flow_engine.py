@@ -81,6 +81,17 @@ def test_flow_engine_2k(vsa, orc, params):
     _flow_vs_oracle(vsa, orc, fp(params, k_max=8), frames)
 
 
+def test_flow_engine_4k_10bit(vsa, orc, params):
+    """3840 x 2160 10-bit 50i, 12 frames: working level 3 (480 x 270), field
+    pairs at level 2 (960 x 540, the lower field read on the upper field's
+    rows, weights 7 and 1 of the row and the row above, s = 3)."""
+    spec = synth.make_c5(seed=7, T=60, W=3840, H=2160)
+    frames = synth.render(spec, range(12))
+    print("dense flow engine 4K 10-bit, 12 frames", flush=True)
+    got, ref = _flow_vs_oracle(vsa, orc, fp(params), frames, bits=10)
+    assert np.any(ref["keys"]["kind"] == 1)
+
+
 def test_flow_engine_batched_mixed(vsa, orc, params):
     """Streams of uneven shapes in one engine (the scratch unit is the widest
     stream's); each equals its oracle run."""

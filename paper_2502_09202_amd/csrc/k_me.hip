@@ -801,6 +801,43 @@ __device__ void hier_coarse(const TileJob& jb, int fx0, int fy0, HierLds<T>& S) 
     const int tid = threadIdx.x;
     T* cI = reinterpret_cast<T*>(S.cI);
     T* cJ = reinterpret_cast<T*>(S.cJ);
+    if (jb.cI) {
+        // the coarse tile and window straight from the stored coarser level
+        // (a quarter of the bytes).  Coarse I items past its row pitch or its
+        // rows belong to no whole coarse block and are not read; window rows
+        // and columns clamp to the coarse plane (w / 2 x h / 2) as above.
+        const int wc = jb.w / 2, hc = jb.h / 2;
+        const int ccx = fx0 / 2, ccy = fy0 / 2;
+        for (int i = tid; i < 64 * 16; i += kMEThreads) {
+            const int y = i >> 4, x = 4 * (i & 15);
+            const int cx = ccx + x, cy = ccy + y;
+            T* dst = cI + y * 64 + x;
+            if (cx >= jb.cpitch || cy >= hc) {
+                if constexpr (B == 1) *reinterpret_cast<uint32_t*>(dst) = 0u;
+                else *reinterpret_cast<uint2*>(dst) = make_uint2(0u, 0u);
+                continue;
+            }
+            const uint8_t* src = jb.cI + ((int64_t)cy * jb.cpitch + cx) * B;
+            if constexpr (B == 1) *reinterpret_cast<uint32_t*>(dst) = gload<uint32_t>(src);
+            else *reinterpret_cast<uint2*>(dst) = gload2(src);
+        }
+        const int cx0 = ccx - 8, cy0 = ccy - 8;
+        constexpr int G = kJW8 / 4;
+        for (int i = tid; i < kJRows * G; i += kMEThreads) {
+            const int r = i / G, c = 4 * (i - (i / G) * G);
+            const int cy = clampi(cy0 + r, 0, hc - 1);
+            const uint8_t* row = jb.cJ + (int64_t)cy * jb.cpitch * B;
+            T* dst = cJ + r * kJW8 + c;
+            if (cx0 + c >= 0 && cx0 + c + 3 <= wc - 1) {
+                if constexpr (B == 1) *reinterpret_cast<uint32_t*>(dst) = gload<uint32_t>(row + (cx0 + c));
+                else *reinterpret_cast<uint2*>(dst) = gload2(row + 2 * (cx0 + c));
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dst[k] = gload<T>(row + clampi(cx0 + c + k, 0, wc - 1) * B);
+            }
+        }
+        return;
+    }
     for (int i = tid; i < 64 * 16; i += kMEThreads) {
         const int y = i >> 4, x = 4 * (i & 15);
         const int gx = fx0 + 2 * x;
@@ -1111,6 +1148,9 @@ __device__ void me_tile_hier(const TileJob& job, int local, TilePartial* part_ou
     TileJob jb = job;
     jb.I = uniform_ptr(job.I);
     jb.J = uniform_ptr(job.J);
+    jb.cI = uniform_ptr(job.cI);
+    jb.cJ = uniform_ptr(job.cJ);
+    jb.cpitch = __builtin_amdgcn_readfirstlane(job.cpitch);
     jb.w = __builtin_amdgcn_readfirstlane(job.w);
     jb.h = __builtin_amdgcn_readfirstlane(job.h);
     jb.pitch = __builtin_amdgcn_readfirstlane(job.pitch);

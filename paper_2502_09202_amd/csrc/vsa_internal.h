@@ -255,6 +255,12 @@ struct TileJob {
     int32_t flags;                    // TF_*
     int32_t sid, epoch;               // stream and its epoch when planned
     int32_t bits;                     // 8 or 10
+    // coarse-to-fine frame pairs: the pair's planes one level coarser when
+    // the ring holds that level (the stored pyramid level is exactly the
+    // 2 x 2 box image of the pair's level), else null
+    const uint8_t* cI;
+    const uint8_t* cJ;
+    int32_t cpitch;                   // its row pitch (samples)
 };
 
 // Job of pair t of stream sd (mv: the motion-field destination).
@@ -279,6 +285,14 @@ inline __host__ __device__ TileJob make_tile_job(const StreamDesc& sd, const Pai
     }
     const bool hier = sd.search == 1 && t.ref_field == PL_FRAME;
     const bool flow = sd.search == 2;
+    j.cI = j.cJ = nullptr;
+    j.cpitch = 0;
+    if (hier && t.level - sd.L + 1 < sd.nlev) {
+        const int dc = t.level - sd.L + 1;
+        j.cI = sd.ring + sref + sd.off[dc];
+        j.cJ = sd.ring + soth + sd.off[dc];
+        j.cpitch = sd.pl[dc];
+    }
     j.mv = flow ? nullptr : mv;
     j.tiles_x = div_up(j.w / kBlock, hier ? kHTB : kTBX);
     j.tile_prefix = t.tile_prefix;

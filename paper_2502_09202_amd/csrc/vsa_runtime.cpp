@@ -1458,6 +1458,20 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
             HIPCK(launch_me_hier(10, e->d_sds, cjobs, M, cmap, consec_tiles, nullptr, 0, cpart, nullptr, nullptr,
                                  grid_hc, Cs, timing(2, true, true)), "motion search launch");
     }
+    if (hier && e->step_no >= 1) {
+        // the planned deep-check pairs (frame pairs, coarse-to-fine) on this
+        // stream, once the previous step's decisions that planned them are
+        // done, beside the field pairs' full search on the main stream.  The
+        // decisions of this step wait for ev_c, so the planning counter and
+        // the job list they read are not reused before they have run.
+        HIPCK(hipStreamWaitEvent(Cs, e->pub_ev[(e->step_no - 1) % kSnap], 0), "wait");
+        if (e->has8 || !e->has10)
+            HIPCK(launch_me_hier(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, spart,
+                                 nullptr, nullptr, grid_hs, Cs), "motion search launch");
+        if (e->has10)
+            HIPCK(launch_me_hier(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, spart,
+                                 nullptr, nullptr, grid_hs, Cs), "motion search launch");
+    }
     HIPCK(hipEventRecord(e->ev_c[slot_s], Cs), "event");
     // the first sparse launch also clears the counter this step's decisions
     // plan into: the 8-bit one runs unless only 10-bit streams are open
@@ -1466,21 +1480,14 @@ vsa_status vsa_step(vsa_engine* e, void* hip_stream) {
         HIPCK(launch_flow_list(e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true,
                                e->d_flow_s, e->flow_unit, spart, std::max<int64_t>(sparse_max, 1), e->cus, A),
               "dense flow launch");
+    // (with the coarse-to-fine search these are the field pairs' launches; the
+    // deep-check pairs went to the search stream above)
     if (sparse8 && !flow)
         HIPCK(launch_me(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, true, spart,
-                        nullptr, nullptr, grid_s, A, timing(3, true, !e->has10 && !hier)), "motion search launch");
+                        nullptr, nullptr, grid_s, A, timing(3, true, !e->has10)), "motion search launch");
     if (e->has10 && !flow)
         HIPCK(launch_me(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, !sparse8, spart,
-                        nullptr, nullptr, grid_s, A, timing(3, !sparse8, !hier)), "motion search launch");
-    if (hier) {
-        // the planned deep-check pairs are frame pairs (the fields keep the full search)
-        if (sparse8)
-            HIPCK(launch_me_hier(8, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, spart,
-                                 nullptr, nullptr, grid_hs, A, timing(3, false, !e->has10)), "motion search launch");
-        if (e->has10)
-            HIPCK(launch_me_hier(10, e->d_sds, sjobs_prev, (int32_t)sp_cap, smap_prev, 0, e->d_cur, par ^ 1, spart,
-                                 nullptr, nullptr, grid_hs, A, timing(3, false, true)), "motion search launch");
-    }
+                        nullptr, nullptr, grid_s, A, timing(3, !sparse8, true)), "motion search launch");
     HIPCK(hipStreamWaitEvent(A, e->ev_c[slot_s], 0), "wait");
     if (!e->no_intensity) HIPCK(hipStreamWaitEvent(A, e->ev_h[slot_s], 0), "wait");
     const int sn = (int)(e->step_no % kSnap);

@@ -426,7 +426,8 @@ int32_t vsa_clip_debug_log(vsa_clip* c, int32_t* keys, int32_t cap);
  * work.  All calls on one GPU share the array: calls that may overlap on one
  * GPU (other streams, other threads) race and must be serialised by the
  * caller.  Errors: VSA_E_INVAL (NULL plane, size, pitch, alignment, bit depth),
- * VSA_E_UNSUPPORTED (block or radius other than 8), VSA_E_DEVICE. */
+ * VSA_E_UNSUPPORTED (block or radius other than 8, or search other than 0:
+ * the full search only), VSA_E_DEVICE. */
 vsa_status vsa_pair_noalloc(const vsa_params* p, const void* I, const void* J, int32_t w, int32_t h,
                             int64_t pitch_bytes, int32_t bit_depth, int32_t force_zero_mv, int8_t* mv,
                             int64_t* ints, double* dbl, void* hip_stream);

@@ -1219,8 +1219,10 @@ __global__ void __launch_bounds__(kMEThreads, 2) k_me(const StreamDesc* __restri
     if (clear_tt && blockIdx.x == 0 && threadIdx.x == 0) *clear_tt = 0ull;
     const bool sparse = cur != nullptr;
     // the sparse pairs precede the step's decisions on the critical path;
-    // their waves issue before those of the next step's consecutive pairs
+    // their waves issue before those of the next step's consecutive pairs,
+    // which in turn issue before the pyramid's (HBM-bound, it has slack)
     if (sparse) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(1);
     const int total = sparse ? tt_tiles(cur->sparse_tt[par_prev].v) : n_tiles;
     // Workgroups are dispatched round-robin over the XCDs, each with its own
     // L2: workgroup b runs on XCD b % kXcd.  Each XCD walks one contiguous

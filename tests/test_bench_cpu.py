@@ -84,3 +84,17 @@ def test_trace_summary_between_markers(tmp_path):
     assert r.returncode == 0, r.stderr
     line = next(l for l in r.stdout.splitlines() if "k_me" in l)
     assert line.split()[-5:] == ["2", "0.030", "15.00", "10.00", "20.00"]
+
+
+def test_short_kernel_names():
+    """Trace summaries name kernels without return type, namespaces and
+    parameters, template arguments kept (so the phases of one template stay
+    apart)."""
+    sys.path.insert(0, os.path.dirname(BENCH))
+    import bench
+    assert bench.short_kernel_name(
+        "void vsa::(anonymous namespace)::k_flow_list<2>(vsa::StreamDesc const*, int)") == "k_flow_list<2>"
+    assert bench.short_kernel_name("void vsa::k_pyramid<unsigned char, 2>(vsa::StreamDesc const*)") == \
+        "k_pyramid<unsigned char, 2>"
+    assert bench.short_kernel_name("vsa::k_copy16(HIP_vector_type<unsigned int, 4u>*, long)") == "k_copy16"
+    assert bench.short_kernel_name("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
